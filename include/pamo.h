@@ -1,0 +1,179 @@
+/*
+ * pamo.h -- C ABI of the MI355X (gfx950) implementation of parallel,
+ * intersection-free QEM edge-collapse mesh simplification, the simplification
+ * stage of PaMO (Oh, Yuan, Wei, Shi, Xiang, Liu, Su; Pacific Graphics 2025):
+ * Sec. 5, the "Parallel Intersection-Free Mesh Simplification" algorithm,
+ * Eq. 1, Sec. 5.2 and Appendix 3 (self-intersection test), Sec. 5.3 (undo,
+ * invalid flags, tolerance).
+ *
+ * Conventions for every entry point
+ *   - Mesh arrays are DEVICE pointers on the context's device, allocated and
+ *     owned by the caller: V is float64 [nv][3], F is int32 [nf][3] with the
+ *     corners counter-clockwise seen from outside.  The input must be a closed
+ *     (watertight) edge- and vertex-manifold mesh without exactly degenerate
+ *     triangles, every vertex used by some face, and free of
+ *     self-intersections -- the output of the paper's remeshing stage (Sec. 3
+ *     and 4).  Coordinates are expected in [0,1]^3 (Sec. 3 normalises the
+ *     input there; the default weights of Eq. 1 assume that scale).
+ *   - Half-edge h = 3 f + c runs from F[f][c] to F[f][(c+1)%3].  An edge is
+ *     named by its smaller half-edge id.
+ *   - All work is enqueued on the context's stream.  Functions that return
+ *     host-visible counts synchronise that stream before returning; the others
+ *     are asynchronous and write their counts to device memory.
+ *   - Return value: 0 success, 1 PAMO_TARGET_UNREACHED (warning), < 0 error;
+ *     pamo_last_error() then describes it.  No C++ exception crosses this
+ *     boundary.  After an error the outputs are unspecified; inputs are never
+ *     modified unless the entry point says so.
+ *   - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef PAMO_H
+#define PAMO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pamo_ctx pamo_ctx;
+typedef int32_t pamo_status;
+
+#define PAMO_OK 0
+#define PAMO_TARGET_UNREACHED 1   /* stopped after `tolerance` rounds without a collapse (Sec. 5.3) */
+#define PAMO_ERR_ARG (-1)         /* bad argument (null pointer, size, index out of range) */
+#define PAMO_ERR_NONMANIFOLD (-2) /* open, non-manifold, inconsistently oriented or with unused vertices */
+#define PAMO_ERR_SELF_INTERSECTING (-3) /* input has a self-intersection (only when validating) */
+#define PAMO_ERR_DEGENERATE (-4)  /* a face repeats a vertex */
+#define PAMO_ERR_HIP (-6)         /* HIP runtime error */
+#define PAMO_ERR_CAPACITY (-7)    /* an internal bound was exceeded (traversal stack, deferred pairs) */
+
+typedef struct {
+  double w_e;          /* edge-length weight of Eq. 1 (paper default 0.001) */
+  double w_s;          /* skinny-triangle weight of Eq. 1 (paper default 0.005) */
+  int32_t tolerance;   /* zero-collapse rounds before giving up (paper default 4, Sec. 5.3) */
+  int32_t max_rounds;  /* stop after this many rounds (< 0: no limit) */
+  int32_t validate_input; /* 1: check manifoldness and self-intersections of the input first */
+  int32_t reserved[5];
+} pamo_options;
+
+typedef struct {
+  int64_t rounds;       /* rounds run */
+  int64_t faces_out, verts_out;
+  int64_t candidates;   /* independent-region edges selected, summed over rounds */
+  int64_t commits;      /* collapses kept */
+  int64_t rej_link;     /* rejected by the link condition */
+  int64_t rej_flip;     /* rejected: a generated triangle degenerate or flipped */
+  int64_t rej_isect;    /* undone because of a self-intersection */
+  int64_t capped;       /* passed but not needed to reach the exact target */
+  int64_t undo_hist[5]; /* rounds needing 0, 1, 2, 3, >3 undo iterations (cf. Table 7) */
+  int64_t deferred_pairs; /* pairs settled by the exact (expansion) predicate */
+  int64_t status;       /* as the return value */
+} pamo_stats;
+
+/* Fill *opt with the paper's defaults (w_e 0.001, w_s 0.005, tolerance 4). */
+void pamo_default_options(pamo_options* opt);
+
+/* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  `opt` may be NULL (defaults).  The context owns
+ * its device workspace, which grows to fit the largest mesh seen. */
+pamo_status pamo_create(pamo_ctx** out, int device, void* hip_stream, const pamo_options* opt);
+void pamo_destroy(pamo_ctx* ctx);
+pamo_status pamo_set_options(pamo_ctx* ctx, const pamo_options* opt);
+/* Message of the last error on this context (valid until the next call). */
+const char* pamo_last_error(const pamo_ctx* ctx);
+/* Bytes of device workspace the context currently holds. */
+int64_t pamo_workspace_bytes(const pamo_ctx* ctx);
+
+/* ---- round-level steps (stateless: the caller owns everything between calls) ---- */
+
+/* Per-vertex quadric error metric (Garland-Heckbert, named for the Q_ab term of
+ * Eq. 1): Q[v] = sum over the faces around v, in ascending face slot, of the
+ * plane quadric of the face (unit normal n, offset d = -n.p0), stored as the
+ * 10 entries xx xy xz xw yy yz yw zz zw ww.  Q: device float64 [nv][10]. */
+pamo_status pamo_quadrics(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf, double* Q);
+
+/* Edge costs (Eq. 1 with the QEM placement), 64-bit keys and the independent
+ * edges of one round (cost propagation and region selection of Sec. 5.1).
+ *   flags  device uint8 [3 nf] invalid-edge flags, or NULL
+ *   demote device uint8 [3 nf] edges to leave out this round, or NULL
+ *   keys   device uint64 [3 nf] output (key of the edge on both half-edges;
+ *          UINT64_MAX for flagged edges), or NULL
+ *   cand   device int32, capacity 3 nf: chosen edges (smaller half-edge id), ascending
+ *   ncand  device int32 [1]: their number
+ * Asynchronous. */
+pamo_status pamo_select(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                        const uint8_t* flags, const uint8_t* demote, uint64_t* keys, int32_t* cand,
+                        int32_t* ncand);
+
+/* Check the chosen edges of one round: link condition (Sec. 5.1), exact
+ * degeneracy and normal flip of the generated triangles, the exact face
+ * target (keep the smallest keys when more pass than needed to reach
+ * target_faces), then apply them together to an internal copy and run the
+ * intersection check / undo loop (Sec. 5.2, 5.3) to its fixed point.
+ *   cand, ncand  as produced by pamo_select for the same V, F, flags
+ *   vbar   device float64 [ncand][3] output: new vertex position
+ *   reason device uint8 [ncand] output: 0 collapse, 1 link condition,
+ *          2 degenerate or flipped triangle, 3 self-intersection, 4 not needed
+ * V and F are not modified.  Synchronises the stream. */
+pamo_status pamo_check(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                       const uint8_t* flags, int64_t target_faces, const int32_t* cand, const int32_t* ncand,
+                       double* vbar, uint8_t* reason, int64_t* undo_iterations);
+
+/* Commit the collapses with reason 0 and compact the mesh IN PLACE (stable:
+ * surviving vertices and faces keep their relative order).  Also writes the
+ * invalid-edge flags for the next round into flags_io (device uint8 [3 nf] in,
+ * [3 nf_out] out, may be NULL): the edges rejected with reason 1-3, plus the
+ * previous flags when nothing was committed (Sec. 5.3).  *nv and *nf (host)
+ * are updated.  Synchronises the stream. */
+pamo_status pamo_collapse(pamo_ctx* ctx, double* V, int64_t* nv, int32_t* F, int64_t* nf, const int32_t* cand,
+                          const int32_t* ncand, const double* vbar, const uint8_t* reason, uint8_t* flags_io);
+
+/* ---- the whole method ---- */
+
+/* Simplify until exactly target_faces - (target_faces mod 2) faces remain, or
+ * `tolerance` rounds in a row collapse nothing (returns PAMO_TARGET_UNREACHED
+ * with the mesh reached), or max_rounds.  V_out / F_out: device buffers of at
+ * least nv / nf rows; *nv_out, *nf_out host.  stats (host) may be NULL.
+ * Synchronises the stream. */
+pamo_status pamo_simplify(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                          int64_t target_faces, double* V_out, int64_t* nv_out, int32_t* F_out, int64_t* nf_out,
+                          pamo_stats* stats);
+
+/* ---- utilities ---- */
+
+/* All pairs (t < u) of faces that intersect under the test of Sec. 5.2 /
+ * Appendix 3 with exact signs.  pairs: device int32 [cap][2]; *npairs (host)
+ * gets the total, which may exceed cap (then only cap pairs are written, in
+ * no particular order).  Also fails with PAMO_ERR_NONMANIFOLD on an invalid mesh.
+ * Synchronises the stream. */
+pamo_status pamo_self_intersections(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                                    int32_t* pairs, int64_t cap, int64_t* npairs);
+
+/* Evaluate the pair test on n explicit triangle pairs: P, Q device float64
+ * [n][9] (corner positions), ip, iq device int32 [n][3] (vertex ids, which
+ * decide the shared-vertex case), out device uint8 [n] (1 = intersect).
+ * Asynchronous. */
+pamo_status pamo_tri_pairs(pamo_ctx* ctx, const double* P, const int32_t* ip, const double* Q, const int32_t* iq,
+                           int64_t n, uint8_t* out);
+
+/* ---- measurement ---- */
+
+/* Time phases of the round driver with HIP events on the context stream.
+ * Bit i of phase_mask enables phase i (0 disables all).  Each timed launch
+ * also adds its algorithmic byte count: the bytes the phase must move at
+ * minimum for the mesh size it ran on (every input read once, every output
+ * written once).  Host-only bookkeeping; no effect on results. */
+pamo_status pamo_profile_enable(pamo_ctx* ctx, uint32_t phase_mask);
+/* Number of phases and the name of phase i ("" when out of range). */
+int32_t pamo_profile_phases(void);
+const char* pamo_profile_name(int32_t phase);
+/* Totals since the last reset: launches, milliseconds (HIP event elapsed
+ * time), algorithmic bytes.  Synchronises the stream. */
+pamo_status pamo_profile_read(pamo_ctx* ctx, int32_t phase, int64_t* launches, double* ms, double* bytes);
+pamo_status pamo_profile_reset(pamo_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAMO_H */

@@ -1,0 +1,788 @@
+// Host side of the library: contexts, the round driver of
+// ParallelSimplification (PaMO Sec. 5) and the C ABI of include/pamo.h.
+//
+// One round on the device (all kernels on the context stream):
+//   quadrics -> cost/keys -> vertex minima -> selection + compaction      [read ncand]
+//   local checks -> reason histogram                                      [read passing]
+//   (exact-target cap) -> face boxes -> tentative apply -> LBVH build
+//   changed-face list -> query -> exact resolve of deferred pairs         [read undone]
+//   { undo -> restored-face list -> query -> resolve }*                   [read undone]
+//   commit -> flags -> stable compaction                                  [read nf, nv]
+// The host reads back a handful of counters per round to size launches and
+// to decide the loop; everything else stays on the GPU.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.hpp"
+#include "round.hpp"
+#include "exact_dev.hpp"
+
+using namespace pamo;
+
+// Phases timed on request with HIP events on the context stream.  Each
+// carries its algorithmic byte count: the bytes the phase must move at
+// minimum (every input element read once, every output written once).
+enum Phase {
+  PH_QUADRICS, PH_COST, PH_SELECT, PH_LOCAL, PH_CAP, PH_BOXES, PH_APPLY, PH_BVH, PH_FACELIST, PH_QUERY,
+  PH_PAIRS, PH_RESOLVE, PH_UNDO, PH_COMMIT, PH_FLAGS, PH_COMPACT, PH_COUNT
+};
+static const char* const PH_NAME[PH_COUNT] = {
+    "quadrics", "cost_keys", "select", "local_check", "cap", "face_boxes", "apply", "bvh_build",
+    "face_list", "query", "pairs", "resolve", "undo", "commit", "flags", "compact"};
+
+struct Prof {
+  uint32_t mask = 0;
+  struct Acc {
+    int64_t launches = 0;
+    double ms = 0, bytes = 0;
+  } acc[PH_COUNT];
+  struct Pending {
+    int ph;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+};
+
+struct pamo_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  pamo_options opt{};
+  std::string err;
+  Workspace ws;
+  int* hcnt = nullptr;  // pinned mirror of the device counters
+  int* dcnt = nullptr;
+  Prof prof;
+};
+
+namespace {
+
+enum {
+  C_NCAND = 0,
+  C_NQ = 1,
+  C_NUNDO = 2,
+  C_NDEFER = 3,
+  C_NF = 4,
+  C_NV = 5,
+  C_ERR = 6,
+  C_NPAIRS = 7,
+  C_NCANDP = 24,  // candidate pairs collected by one query pass
+  C_HIST = 8,   // 8 entries: reason histogram after the local checks
+  C_HIST2 = 16, // 8 entries: final reason histogram
+  C_COUNT = 32
+};
+
+struct Fail {
+  pamo_status code;
+  std::string msg;
+};
+
+void fail(pamo_status code, const std::string& msg) { throw Fail{code, msg}; }
+
+hipEvent_t ev_get(pamo_ctx* c) {
+  if (!c->prof.pool.empty()) {
+    hipEvent_t e = c->prof.pool.back();
+    c->prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  PAMO_HIP(hipEventCreate(&e));
+  return e;
+}
+
+// fold finished timings into the accumulators (the stream is synchronised)
+void prof_resolve(pamo_ctx* c) {
+  for (auto& p : c->prof.pending) {
+    float ms = 0;
+    PAMO_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    auto& a = c->prof.acc[p.ph];
+    a.launches++;
+    a.ms += ms;
+    a.bytes += p.bytes;
+    c->prof.pool.push_back(p.a);
+    c->prof.pool.push_back(p.b);
+  }
+  c->prof.pending.clear();
+}
+
+struct Scope {
+  pamo_ctx* c;
+  int ph;
+  double bytes;
+  hipEvent_t a = nullptr;
+  Scope(pamo_ctx* c_, int ph_, double bytes_) : c(c_), ph(ph_), bytes(bytes_) {
+    if (c->prof.mask & (1u << ph)) {
+      a = ev_get(c);
+      PAMO_HIP(hipEventRecord(a, c->stream));
+    }
+  }
+  ~Scope() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, c->stream) == hipSuccess)
+      c->prof.pending.push_back({ph, a, b, bytes});
+  }
+};
+#define PAMO_CAT2(a, b) a##b
+#define PAMO_CAT(a, b) PAMO_CAT2(a, b)
+#define TIMED(ph, bytes) Scope PAMO_CAT(scope_, __LINE__)(c, ph, (double)(bytes))
+
+const int* readback(pamo_ctx* c) {
+  PAMO_HIP(hipMemcpyAsync(c->hcnt, c->dcnt, C_COUNT * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  PAMO_HIP(hipStreamSynchronize(c->stream));
+  if (!c->prof.pending.empty()) prof_resolve(c);
+  return c->hcnt;
+}
+
+void check_err_bits(int e) {
+  if (!e) return;
+  if (e & PAMO_EBIT_INDEX) fail(PAMO_ERR_ARG, "a face refers to a vertex index outside [0, nv)");
+  if (e & PAMO_EBIT_DEGENERATE) fail(PAMO_ERR_DEGENERATE, "a face repeats a vertex");
+  if (e & PAMO_EBIT_EDGE) fail(PAMO_ERR_NONMANIFOLD, "an edge does not have exactly two faces (open or non-manifold mesh)");
+  if (e & PAMO_EBIT_ORIENT) fail(PAMO_ERR_NONMANIFOLD, "the two faces of an edge are inconsistently oriented");
+  if (e & PAMO_EBIT_VERTEX) fail(PAMO_ERR_NONMANIFOLD, "an unused vertex or a non-manifold vertex");
+  if (e & PAMO_EBIT_RING) fail(PAMO_ERR_NONMANIFOLD, "a vertex star is corrupt or too long");
+  if (e & PAMO_EBIT_STACK) fail(PAMO_ERR_CAPACITY, "BVH traversal stack overflow");
+  if (e & PAMO_EBIT_DEFER) fail(PAMO_ERR_CAPACITY, "too many pairs for the exact predicate");
+  fail(PAMO_ERR_HIP, "unknown device error");
+}
+
+MeshView mesh_bufs(pamo_ctx* c, const char* tag, int64_t nv, int64_t nf) {
+  std::string t(tag);
+  MeshView m;
+  m.V = c->ws.get<double>(t + ".V", 3 * nv);
+  m.F = c->ws.get<int>(t + ".F", 3 * nf);
+  m.twin = c->ws.get<int>(t + ".twin", 3 * nf);
+  m.vh = c->ws.get<int>(t + ".vh", nv);
+  m.flags = c->ws.get<uint8_t>(t + ".flags", 3 * nf);
+  m.nv = (int)nv;
+  m.nf = (int)nf;
+  return m;
+}
+
+void check_sizes(int64_t nv, int64_t nf) {
+  if (nv < 4 || nf < 4) fail(PAMO_ERR_ARG, "a closed mesh needs at least 4 vertices and 4 faces");
+  if (nf > (int64_t)(INT32_MAX / 3) - 1 || nv > INT32_MAX - 1) fail(PAMO_ERR_ARG, "mesh too large for int32 ids");
+}
+
+// copy the caller's mesh into `m`, build twins / leaving half-edges, validate
+void load_mesh(pamo_ctx* c, MeshView m, const double* V, const int32_t* F, const uint8_t* flags) {
+  hipStream_t s = c->stream;
+  PAMO_HIP(hipMemcpyAsync(m.V, V, 3 * (size_t)m.nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  PAMO_HIP(hipMemcpyAsync(m.F, F, 3 * (size_t)m.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+  if (flags)
+    PAMO_HIP(hipMemcpyAsync(m.flags, flags, 3 * (size_t)m.nf, hipMemcpyDeviceToDevice, s));
+  else
+    fill_u8(s, m.flags, 3 * (int64_t)m.nf, 0);
+  fill_i32(s, c->dcnt, C_COUNT, 0);
+  launch_adjacency(c->ws, s, m, c->dcnt + C_ERR);
+  const int* h = readback(c);
+  check_err_bits(h[C_ERR]);
+  launch_check_vertices(c->ws, s, m, c->dcnt + C_ERR);
+  h = readback(c);
+  check_err_bits(h[C_ERR]);
+}
+
+struct RoundBufs {
+  double* Q;
+  uint64_t* key;
+  uint64_t* vmin;
+  int* cand;
+  uint8_t* reason;
+  double* vbar;
+  double* oldpos;
+  uint64_t* ckey;
+  int* owner;
+  int* undone;
+  uint8_t* falive;
+  uint8_t* valive;
+  float* box;
+  int* qlist;
+  int2* defer;
+  int defer_cap;
+};
+
+// one query pass (traversal + pair predicate + exact resolve); grows the
+// candidate-pair buffer and repeats when it overflowed (marks are idempotent)
+const int* query_pass(pamo_ctx* c, const Bvh& bvh, QueryMode mode, const int* qlist, int* nq_dev, int bound,
+                      QueryArgs& qa, double bytes) {
+  hipStream_t s = c->stream;
+  for (;;) {
+    fill_i32(s, c->dcnt + C_NCANDP, 1, 0);
+    fill_i32(s, c->dcnt + C_NDEFER, 1, 0);
+    if (mode == QUERY_ALL_PAIRS) fill_i32(s, c->dcnt + C_NPAIRS, 1, 0);
+    {
+      TIMED(PH_QUERY, bytes);
+      launch_query(s, bvh, mode, qlist, nq_dev, bound, qa);
+    }
+    {
+      TIMED(PH_PAIRS, 0);
+      launch_pairs(s, mode, qa);
+    }
+    {
+      TIMED(PH_RESOLVE, 0);
+      launch_resolve(s, mode, qa);
+    }
+    const int* h = readback(c);
+    check_err_bits(h[C_ERR]);
+    if (h[C_NCANDP] <= qa.cand_cap) return h;
+    int64_t cap = (int64_t)h[C_NCANDP] + h[C_NCANDP] / 4 + 1024;
+    if (cap > INT32_MAX / 2) fail(PAMO_ERR_CAPACITY, "too many candidate pairs");
+    qa.cand = c->ws.get<int2>("q.pairs", cap);
+    qa.cand_cap = (int)cap;
+  }
+}
+
+void init_pair_buffer(pamo_ctx* c, QueryArgs& qa, int64_t nf) {
+  int64_t cap = std::max<int64_t>(1 << 20, 16 * nf);
+  qa.cand = c->ws.get<int2>("q.pairs", cap);
+  qa.cand_cap = (int)std::min<int64_t>(cap, INT32_MAX / 2);
+  qa.ncand = c->dcnt + C_NCANDP;
+}
+
+RoundBufs round_bufs(pamo_ctx* c, int64_t nv, int64_t nf) {
+  RoundBufs b;
+  Workspace& w = c->ws;
+  int64_t nh = 3 * nf;
+  b.Q = w.get<double>("r.Q", 10 * nv);
+  b.key = w.get<uint64_t>("r.key", nh);
+  b.vmin = w.get<uint64_t>("r.vmin", nv);
+  b.cand = w.get<int>("r.cand", nh);
+  b.reason = w.get<uint8_t>("r.reason", nh);
+  b.vbar = w.get<double>("r.vbar", 3 * nh);
+  b.oldpos = w.get<double>("r.oldpos", 3 * nh);
+  b.ckey = w.get<uint64_t>("r.ckey", nh);
+  b.owner = w.get<int>("r.owner", nf);
+  b.undone = w.get<int>("r.undone", nh);
+  b.falive = w.get<uint8_t>("r.falive", nf);
+  b.valive = w.get<uint8_t>("r.valive", nv);
+  b.box = w.get<float>("r.box", 6 * nf);
+  b.qlist = w.get<int>("r.qlist", nf);
+  b.defer_cap = (int)std::max<int64_t>(1 << 16, nf);
+  b.defer = w.get<int2>("r.defer", b.defer_cap);
+  return b;
+}
+
+struct RoundResult {
+  int ncand = 0, npass = 0, chosen = 0, undone = 0, commits = 0, iters = 0, deferred = 0;
+  int hist[8] = {0};
+};
+
+// Local checks, cap, tentative apply and the check/undo fixed point on `m`
+// (modified: tentative state restored for undone collapses, applied ones
+// left applied).  reason/vbar are per candidate; undone[c] != 0 marks
+// collapses undone by the loop (reason not yet set to 3).
+void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand, const int* ncand_dev, int ncand,
+                    int64_t teff, uint8_t* reason, double* vbar, RoundResult& R) {
+  hipStream_t s = c->stream;
+  int* cnt = c->dcnt;
+  {
+    TIMED(PH_LOCAL, 780.0 * ncand);
+    launch_local_check(s, m, b.Q, c->opt.w_e, c->opt.w_s, cand, ncand_dev, ncand, b.key, reason, vbar, b.ckey,
+                       cnt + C_ERR);
+  }
+  fill_i32(s, cnt + C_HIST, 8, 0);
+  launch_reason_hist(s, ncand_dev, ncand, reason, cnt + C_HIST);
+  const int* h = readback(c);
+  check_err_bits(h[C_ERR]);
+  R.npass = h[C_HIST + 0];
+  int64_t need = (m.nf - teff) / 2;
+  R.chosen = R.npass;
+  if (R.npass > need) {
+    TIMED(PH_CAP, 8 * 16.0 * ncand);
+    launch_cap(c->ws, s, ncand_dev, ncand, b.ckey, reason, need);
+    R.chosen = (int)need;
+  }
+  fill_u8(s, b.falive, m.nf, 1);
+  fill_i32(s, b.owner, m.nf, -1);
+  fill_i32(s, b.undone, ncand, 0);
+  if (R.chosen == 0) return;
+  const double nf = m.nf, nv = m.nv;
+  {
+    TIMED(PH_BOXES, 36 * nf + 24 * nv);
+    launch_face_boxes(s, m, b.box);
+  }
+  {
+    TIMED(PH_APPLY, 900.0 * R.chosen);
+    launch_apply(s, m, cand, ncand_dev, ncand, reason, vbar, b.oldpos, b.owner, b.falive, b.box);
+  }
+  Bvh bvh;
+  {
+    TIMED(PH_BVH, 216 * nf);
+    bvh = build_bvh(c->ws, s, b.box, m.nf);
+  }
+  {
+    TIMED(PH_FACELIST, 8 * nf);
+    launch_face_list(c->ws, s, m.nf, b.owner, b.falive, b.undone, 0, bvh.sorted, b.qlist, cnt + C_NQ);
+  }
+  QueryArgs qa{};
+  qa.V = m.V;
+  qa.F = m.F;
+  qa.falive = b.falive;
+  qa.owner = b.owner;
+  qa.undone = b.undone;
+  qa.iter = 1;
+  qa.nundo = cnt + C_NUNDO;
+  qa.defer = b.defer;
+  qa.ndefer = cnt + C_NDEFER;
+  qa.defer_cap = b.defer_cap;
+  qa.err = cnt + C_ERR;
+  init_pair_buffer(c, qa, m.nf);
+  fill_i32(s, cnt + C_NUNDO, 2, 0);
+  const double qbytes = 64 * (nf - 1) + 17 * nf + 24 * nv;  // tree + faces + alive/owner + vertices
+  h = query_pass(c, bvh, QUERY_CHANGED, b.qlist, cnt + C_NQ, m.nf, qa, qbytes);
+  int newly = h[C_NUNDO];
+  R.deferred += h[C_NDEFER];
+  while (newly > 0) {
+    R.undone += newly;
+    R.iters++;
+    {
+      TIMED(PH_UNDO, 200.0 * newly);
+      launch_undo(s, m, cand, ncand_dev, ncand, b.undone, R.iters, b.oldpos, b.falive);
+    }
+    {
+      TIMED(PH_FACELIST, 8 * nf);
+      launch_face_list(c->ws, s, m.nf, b.owner, b.falive, b.undone, R.iters, bvh.sorted, b.qlist, cnt + C_NQ);
+    }
+    fill_i32(s, cnt + C_NUNDO, 2, 0);
+    qa.iter = R.iters + 1;
+    h = query_pass(c, bvh, QUERY_RESTORED, b.qlist, cnt + C_NQ, m.nf, qa, qbytes);
+    newly = h[C_NUNDO];
+    R.deferred += h[C_NDEFER];
+  }
+  R.commits = R.chosen - R.undone;
+}
+
+void add_stats(pamo_stats* st, const RoundResult& R) {
+  st->rounds++;
+  st->candidates += R.ncand;
+  st->commits += R.commits;
+  st->rej_link += R.hist[1];
+  st->rej_flip += R.hist[2];
+  st->rej_isect += R.hist[3];
+  st->capped += R.hist[4];
+  st->undo_hist[std::min(R.iters, 4)]++;
+  st->deferred_pairs += R.deferred;
+}
+
+// One full round on `cur`.  When collapses are committed, the compacted mesh
+// lands in `alt` and the two views are swapped.
+RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, int64_t teff) {
+  hipStream_t s = c->stream;
+  int* cnt = c->dcnt;
+  RoundResult R;
+  fill_i32(s, cnt, C_COUNT, 0);
+  const double nf = cur.nf, nv = cur.nv;
+  {
+    TIMED(PH_QUADRICS, 108 * nv + 24 * nf);
+    launch_quadrics(s, cur, b.Q, cnt + C_ERR);
+  }
+  {
+    TIMED(PH_COST, 104 * nv + 51 * nf);
+    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, b.key, cnt + C_ERR);
+  }
+  {
+    TIMED(PH_SELECT, 20 * nv + 93 * nf);
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
+  }
+  const int* h = readback(c);
+  check_err_bits(h[C_ERR]);
+  R.ncand = h[C_NCAND];
+  if (R.ncand == 0) return R;  // nothing selectable: a round without collapses
+  check_and_undo(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, teff, b.reason, b.vbar, R);
+  fill_u8(s, b.valive, cur.nv, 1);
+  if (R.chosen > 0) {
+    TIMED(PH_COMMIT, 100.0 * R.chosen);
+    launch_commit(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.undone, b.valive);
+  }
+  fill_i32(s, cnt + C_HIST2, 8, 0);
+  launch_reason_hist(s, cnt + C_NCAND, R.ncand, b.reason, cnt + C_HIST2);
+  // invalid flags for the next round: this round's rejections, plus the old
+  // flags when nothing was collapsed (Sec. 5.3)
+  {
+    TIMED(PH_FLAGS, 3 * nf + 10.0 * R.ncand);
+    if (R.commits > 0) fill_u8(s, cur.flags, 3 * (int64_t)cur.nf, 0);
+    launch_flags(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason);
+  }
+  if (R.commits > 0) {
+    TIMED(PH_COMPACT, 72 * nf + 66 * nv);
+    launch_compact(c->ws, s, cur, alt, b.falive, b.valive, cnt + C_NF, cnt + C_NV, cnt + C_ERR);
+  }
+  h = readback(c);
+  check_err_bits(h[C_ERR]);
+  for (int i = 0; i < 8; i++) R.hist[i] = h[C_HIST2 + i];
+  if (R.commits > 0) {
+    alt.nf = h[C_NF];
+    alt.nv = h[C_NV];
+    std::swap(cur, alt);
+  }
+  return R;
+}
+
+__global__ void k_iota(int* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+
+__global__ void k_check_index(const int* F, int64_t n3, int nv, int* err) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n3 && (F[i] < 0 || F[i] >= nv)) atomicOr(err, PAMO_EBIT_INDEX);
+}
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
+
+// all intersecting pairs of the mesh m; returns their number
+int64_t whole_mesh_pairs(pamo_ctx* c, MeshView m, int2* pairs, int64_t cap) {
+  hipStream_t s = c->stream;
+  int* cnt = c->dcnt;
+  float* box = c->ws.get<float>("w.box", 6 * (int64_t)m.nf);
+
+  int defer_cap = (int)std::max<int64_t>(1 << 16, m.nf);
+  int2* defer = c->ws.get<int2>("w.defer", defer_cap);
+  fill_i32(s, cnt, C_COUNT, 0);
+  fill_i32(s, cnt + C_NQ, 1, m.nf);
+  launch_face_boxes(s, m, box);
+  Bvh bvh = build_bvh(c->ws, s, box, m.nf);
+  const int* ql = bvh.sorted;  // every face, in Morton order
+  QueryArgs qa{};
+  qa.V = m.V;
+  qa.F = m.F;
+  qa.defer = defer;
+  qa.ndefer = cnt + C_NDEFER;
+  qa.defer_cap = defer_cap;
+  qa.pairs = pairs;
+  qa.npairs = cnt + C_NPAIRS;
+  qa.pairs_cap = cap;
+  qa.err = cnt + C_ERR;
+  init_pair_buffer(c, qa, m.nf);
+  const int* h = query_pass(c, bvh, QUERY_ALL_PAIRS, ql, cnt + C_NQ, m.nf, qa, 0);
+  return h[C_NPAIRS];
+}
+
+__global__ void k_tri_pairs(const double* P, const int* ip, const double* Q, const int* iq, int64_t n, uint8_t* out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  P3 a[3], b[3];
+  int ia[3], ib[3];
+  for (int k = 0; k < 3; k++) {
+    a[k] = P3{P[9 * i + 3 * k], P[9 * i + 3 * k + 1], P[9 * i + 3 * k + 2]};
+    b[k] = P3{Q[9 * i + 3 * k], Q[9 * i + 3 * k + 1], Q[9 * i + 3 * k + 2]};
+    ia[k] = ip[3 * i + k];
+    ib[k] = iq[3 * i + k];
+  }
+  out[i] = (uint8_t)tri_pair<true>(a, ia, b, ib);
+}
+
+template <class Fn>
+pamo_status guarded(pamo_ctx* c, Fn&& fn) {
+  if (!c) return PAMO_ERR_ARG;
+  try {
+    PAMO_HIP(hipSetDevice(c->device));
+    c->err.clear();
+    return fn();
+  } catch (const Fail& f) {
+    c->err = f.msg;
+    return f.code;
+  } catch (const HipError& e) {
+    c->err = e.what();
+    return PAMO_ERR_HIP;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return PAMO_ERR_HIP;
+  } catch (...) {
+    c->err = "unknown failure";
+    return PAMO_ERR_HIP;
+  }
+}
+
+int32_t read_count(pamo_ctx* c, const int32_t* dev) {
+  int32_t v = 0;
+  PAMO_HIP(hipMemcpyAsync(&v, dev, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+  PAMO_HIP(hipStreamSynchronize(c->stream));
+  return v;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+extern "C" {
+
+void pamo_default_options(pamo_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->w_e = 0.001;
+  o->w_s = 0.005;
+  o->tolerance = 4;
+  o->max_rounds = -1;
+  o->validate_input = 0;
+}
+
+pamo_status pamo_create(pamo_ctx** out, int device, void* hip_stream, const pamo_options* opt) {
+  if (!out) return PAMO_ERR_ARG;
+  *out = nullptr;
+  pamo_ctx* c = new (std::nothrow) pamo_ctx();
+  if (!c) return PAMO_ERR_ARG;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  pamo_default_options(&c->opt);
+  if (opt) c->opt = *opt;
+  if (hipSetDevice(device) != hipSuccess || hipHostMalloc((void**)&c->hcnt, C_COUNT * sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&c->dcnt, C_COUNT * sizeof(int)) != hipSuccess) {
+    if (c->hcnt) (void)hipHostFree(c->hcnt);
+    delete c;
+    return PAMO_ERR_HIP;
+  }
+  *out = c;
+  return PAMO_OK;
+}
+
+void pamo_destroy(pamo_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& p : c->prof.pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : c->prof.pool) (void)hipEventDestroy(e);
+  c->ws.release();
+  if (c->dcnt) (void)hipFree(c->dcnt);
+  if (c->hcnt) (void)hipHostFree(c->hcnt);
+  delete c;
+}
+
+pamo_status pamo_set_options(pamo_ctx* c, const pamo_options* opt) {
+  if (!c || !opt) return PAMO_ERR_ARG;
+  if (opt->tolerance < 1) return PAMO_ERR_ARG;
+  c->opt = *opt;
+  return PAMO_OK;
+}
+
+const char* pamo_last_error(const pamo_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int64_t pamo_workspace_bytes(const pamo_ctx* c) { return c ? (int64_t)c->ws.total : 0; }
+
+pamo_status pamo_quadrics(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F, int64_t nf, double* Q) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!V || !F || !Q) fail(PAMO_ERR_ARG, "null pointer");
+    check_sizes(nv, nf);
+    MeshView A = mesh_bufs(c, "mA", nv, nf);
+    load_mesh(c, A, V, F, nullptr);
+    launch_quadrics(c->stream, A, Q, c->dcnt + C_ERR);
+    check_err_bits(readback(c)[C_ERR]);
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_select(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                        const uint8_t* flags, const uint8_t* demote, uint64_t* keys, int32_t* cand, int32_t* ncand) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!V || !F || !cand || !ncand) fail(PAMO_ERR_ARG, "null pointer");
+    check_sizes(nv, nf);
+    MeshView A = mesh_bufs(c, "mA", nv, nf);
+    load_mesh(c, A, V, F, flags);
+    RoundBufs b = round_bufs(c, nv, nf);
+    uint64_t* key = keys ? keys : b.key;
+    launch_quadrics(c->stream, A, b.Q, c->dcnt + C_ERR);
+    launch_cost_keys(c->stream, A, b.Q, c->opt.w_e, c->opt.w_s, demote, key, c->dcnt + C_ERR);
+    launch_select(c->ws, c->stream, A, key, b.vmin, cand, ncand);
+    check_err_bits(readback(c)[C_ERR]);
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_check(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                       const uint8_t* flags, int64_t target_faces, const int32_t* cand, const int32_t* ncand,
+                       double* vbar, uint8_t* reason, int64_t* undo_iterations) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!V || !F || !cand || !ncand || !vbar || !reason) fail(PAMO_ERR_ARG, "null pointer");
+    check_sizes(nv, nf);
+    if (target_faces < 0) fail(PAMO_ERR_ARG, "negative target");
+    MeshView A = mesh_bufs(c, "mA", nv, nf);
+    load_mesh(c, A, V, F, flags);
+    RoundBufs b = round_bufs(c, nv, nf);
+    int nc = read_count(c, ncand);
+    if (nc < 0 || nc > 3 * nf) fail(PAMO_ERR_ARG, "bad candidate count");
+    if (undo_iterations) *undo_iterations = 0;
+    if (nc == 0) return PAMO_OK;
+    hipStream_t s = c->stream;
+    fill_i32(s, c->dcnt, C_COUNT, 0);
+    launch_quadrics(s, A, b.Q, c->dcnt + C_ERR);
+    launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, b.key, c->dcnt + C_ERR);
+    int64_t teff = target_faces - target_faces % 2;
+    if (A.nf <= teff) fail(PAMO_ERR_ARG, "the mesh is already at or below the target");
+    RoundResult R;
+    R.ncand = nc;
+    check_and_undo(c, A, b, cand, ncand, nc, teff, reason, vbar, R);
+    fill_u8(s, b.valive, A.nv, 1);
+    if (R.chosen > 0) launch_commit(s, A, cand, ncand, nc, reason, b.undone, b.valive);
+    check_err_bits(readback(c)[C_ERR]);
+    if (undo_iterations) *undo_iterations = R.iters;
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_collapse(pamo_ctx* c, double* V, int64_t* nv, int32_t* F, int64_t* nf, const int32_t* cand,
+                          const int32_t* ncand, const double* vbar, const uint8_t* reason, uint8_t* flags_io) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!V || !nv || !F || !nf || !cand || !ncand || !vbar || !reason) fail(PAMO_ERR_ARG, "null pointer");
+    check_sizes(*nv, *nf);
+    hipStream_t s = c->stream;
+    MeshView A = mesh_bufs(c, "mA", *nv, *nf);
+    MeshView B = mesh_bufs(c, "mB", *nv, *nf);
+    load_mesh(c, A, V, F, flags_io);
+    RoundBufs b = round_bufs(c, *nv, *nf);
+    int nc = read_count(c, ncand);
+    if (nc < 0 || nc > 3 * *nf) fail(PAMO_ERR_ARG, "bad candidate count");
+    int* cnt = c->dcnt;
+    fill_i32(s, cnt, C_COUNT, 0);
+    int commits = 0;
+    if (nc > 0) {
+      PAMO_HIP(hipMemcpyAsync(b.reason, reason, nc, hipMemcpyDeviceToDevice, s));
+      fill_u8(s, b.falive, A.nf, 1);
+      fill_u8(s, b.valive, A.nv, 1);
+      fill_i32(s, b.owner, A.nf, -1);
+      fill_i32(s, b.undone, nc, 0);
+      launch_face_boxes(s, A, b.box);
+      launch_apply(s, A, cand, ncand, nc, b.reason, vbar, b.oldpos, b.owner, b.falive, b.box);
+      launch_commit(s, A, cand, ncand, nc, b.reason, b.undone, b.valive);
+      launch_reason_hist(s, ncand, nc, b.reason, cnt + C_HIST2);
+      commits = readback(c)[C_HIST2];
+      if (commits > 0) fill_u8(s, A.flags, 3 * (int64_t)A.nf, 0);
+      launch_flags(s, A, cand, ncand, nc, b.reason);
+    }
+    if (commits > 0) {
+      launch_compact(c->ws, s, A, B, b.falive, b.valive, cnt + C_NF, cnt + C_NV, cnt + C_ERR);
+      const int* h = readback(c);
+      check_err_bits(h[C_ERR]);
+      B.nf = h[C_NF];
+      B.nv = h[C_NV];
+      PAMO_HIP(hipMemcpyAsync(V, B.V, 3 * (size_t)B.nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+      PAMO_HIP(hipMemcpyAsync(F, B.F, 3 * (size_t)B.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+      if (flags_io) PAMO_HIP(hipMemcpyAsync(flags_io, B.flags, 3 * (size_t)B.nf, hipMemcpyDeviceToDevice, s));
+      *nv = B.nv;
+      *nf = B.nf;
+    } else if (flags_io) {
+      PAMO_HIP(hipMemcpyAsync(flags_io, A.flags, 3 * (size_t)A.nf, hipMemcpyDeviceToDevice, s));
+    }
+    PAMO_HIP(hipStreamSynchronize(s));
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_simplify(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                          int64_t target_faces, double* V_out, int64_t* nv_out, int32_t* F_out, int64_t* nf_out,
+                          pamo_stats* stats) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!V || !F || !V_out || !F_out || !nv_out || !nf_out) fail(PAMO_ERR_ARG, "null pointer");
+    check_sizes(nv, nf);
+    if (target_faces < 0) fail(PAMO_ERR_ARG, "negative target");
+    hipStream_t s = c->stream;
+    MeshView cur = mesh_bufs(c, "mA", nv, nf);
+    MeshView alt = mesh_bufs(c, "mB", nv, nf);
+    load_mesh(c, cur, V, F, nullptr);
+    if (c->opt.validate_input) {
+      int2* dummy = c->ws.get<int2>("w.pairs", 1);
+      if (whole_mesh_pairs(c, cur, dummy, 0) > 0) fail(PAMO_ERR_SELF_INTERSECTING, "the input intersects itself");
+    }
+    RoundBufs b = round_bufs(c, nv, nf);
+    pamo_stats st;
+    memset(&st, 0, sizeof(st));
+    int64_t teff = target_faces - target_faces % 2;
+    int streak = 0;
+    pamo_status status = PAMO_OK;
+    for (;;) {
+      if (cur.nf <= teff) break;
+      if (streak >= c->opt.tolerance) {
+        status = PAMO_TARGET_UNREACHED;
+        break;
+      }
+      if (c->opt.max_rounds >= 0 && st.rounds >= c->opt.max_rounds) break;
+      RoundResult R = run_round(c, cur, alt, b, teff);
+      add_stats(&st, R);
+      streak = R.commits == 0 ? streak + 1 : 0;
+    }
+    PAMO_HIP(hipMemcpyAsync(V_out, cur.V, 3 * (size_t)cur.nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+    PAMO_HIP(hipMemcpyAsync(F_out, cur.F, 3 * (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+    PAMO_HIP(hipStreamSynchronize(s));
+    *nv_out = cur.nv;
+    *nf_out = cur.nf;
+    st.faces_out = cur.nf;
+    st.verts_out = cur.nv;
+    st.status = status;
+    if (stats) *stats = st;
+    return status;
+  });
+}
+
+pamo_status pamo_self_intersections(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                                    int32_t* pairs, int64_t cap, int64_t* npairs) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!V || !F || !npairs || (cap > 0 && !pairs)) fail(PAMO_ERR_ARG, "null pointer");
+    if (nv < 1 || nf < 1 || nf > (int64_t)(INT32_MAX / 3) - 1) fail(PAMO_ERR_ARG, "bad sizes");
+    MeshView m;
+    m.V = const_cast<double*>(V);
+    m.F = const_cast<int*>(F);
+    m.twin = nullptr;
+    m.vh = nullptr;
+    m.flags = nullptr;
+    m.nv = (int)nv;
+    m.nf = (int)nf;
+    fill_i32(c->stream, c->dcnt, C_COUNT, 0);
+    hipLaunchKernelGGL(k_check_index, dim3(nblk(3 * nf)), dim3(256), 0, c->stream, F, 3 * nf, (int)nv,
+                       c->dcnt + C_ERR);
+    check_err_bits(readback(c)[C_ERR]);
+    int2* out = pairs ? (int2*)pairs : c->ws.get<int2>("w.pairs", 1);
+    *npairs = whole_mesh_pairs(c, m, out, pairs ? cap : 0);
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_tri_pairs(pamo_ctx* c, const double* P, const int32_t* ip, const double* Q, const int32_t* iq,
+                           int64_t n, uint8_t* out) {
+  return guarded(c, [&]() -> pamo_status {
+    if (n < 0 || (n > 0 && (!P || !ip || !Q || !iq || !out))) fail(PAMO_ERR_ARG, "bad arguments");
+    if (n == 0) return PAMO_OK;
+    hipLaunchKernelGGL(k_tri_pairs, dim3(nblk(n, 64)), dim3(64), 0, c->stream, P, ip, Q, iq, n, out);
+    PAMO_HIP(hipGetLastError());
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_profile_enable(pamo_ctx* c, uint32_t phase_mask) {
+  if (!c) return PAMO_ERR_ARG;
+  c->prof.mask = phase_mask;
+  return PAMO_OK;
+}
+
+int32_t pamo_profile_phases(void) { return PH_COUNT; }
+
+const char* pamo_profile_name(int32_t phase) { return phase >= 0 && phase < PH_COUNT ? PH_NAME[phase] : ""; }
+
+pamo_status pamo_profile_read(pamo_ctx* c, int32_t phase, int64_t* launches, double* ms, double* bytes) {
+  if (!c || phase < 0 || phase >= PH_COUNT) return PAMO_ERR_ARG;
+  return guarded(c, [&]() -> pamo_status {
+    PAMO_HIP(hipStreamSynchronize(c->stream));
+    prof_resolve(c);
+    const auto& a = c->prof.acc[phase];
+    if (launches) *launches = a.launches;
+    if (ms) *ms = a.ms;
+    if (bytes) *bytes = a.bytes;
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_profile_reset(pamo_ctx* c) {
+  if (!c) return PAMO_ERR_ARG;
+  return guarded(c, [&]() -> pamo_status {
+    PAMO_HIP(hipStreamSynchronize(c->stream));
+    prof_resolve(c);
+    for (auto& a : c->prof.acc) a = Prof::Acc();
+    return PAMO_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Device-side helpers for the half-edge mesh and the per-edge arithmetic of
+// the simplification round (PaMO Sec. 5.1, Eq. 1).
+//
+// Mesh layout in HBM (all arrays indexed by slot, compacted every round):
+//   V     double[nv][3]    vertex positions
+//   F     int32 [nf][3]    triangle corners, counter-clockwise seen from outside
+//   twin  int32 [3 nf]     opposite half-edge; half-edge h = 3f + c runs from
+//                          F[f][c] to F[f][(c+1)%3]
+//   vh    int32 [nv]       one half-edge leaving each vertex
+//   flags uint8 [3 nf]     invalid-edge flags (an edge is flagged when either of
+//                          its half-edges is)
+// An edge is represented by its smaller half-edge id, which is also its
+// unique id inside the 64-bit key.
+//
+// Floating-point contract: every expression below is evaluated in float64 in
+// exactly the order written (the library is built with contraction off), and
+// sums over faces run in ascending face slot, so the results do not depend on
+// the thread that computes them.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// usable from host code too (unit tests of the arithmetic)
+#define PAMO_HD __host__ __device__
+
+#define PAMO_KEY_MAX 0xFFFFFFFFFFFFFFFFull
+#define PAMO_SKINNY_K 3.4641016151377544  // 2 sqrt(3): 4 sqrt(3) A = (2 sqrt(3)) |n|
+
+namespace pamo {
+
+PAMO_HD __forceinline__ int he_next(int h) { return h - h % 3 + (h % 3 == 2 ? 0 : h % 3 + 1); }
+PAMO_HD __forceinline__ int he_prev(int h) { return h - h % 3 + (h % 3 == 0 ? 2 : h % 3 - 1); }
+
+// rotate to the next half-edge leaving the same vertex
+PAMO_HD __forceinline__ int he_rot(const int* __restrict__ twin, int h) { return twin[he_prev(h)]; }
+
+struct P3 {
+  double x, y, z;
+};
+
+PAMO_HD __forceinline__ P3 ld3(const double* __restrict__ V, int v) {
+  return P3{V[3 * (int64_t)v], V[3 * (int64_t)v + 1], V[3 * (int64_t)v + 2]};
+}
+
+// Unit-normal plane quadric of triangle p0 p1 p2, 10 upper-triangle entries
+// (xx xy xz xw yy yz yw zz zw ww).
+PAMO_HD __forceinline__ void face_quadric(P3 p0, P3 p1, P3 p2, double* K) {
+  double e1x = p1.x - p0.x, e1y = p1.y - p0.y, e1z = p1.z - p0.z;
+  double e2x = p2.x - p0.x, e2y = p2.y - p0.y, e2z = p2.z - p0.z;
+  double nx = e1y * e2z - e1z * e2y;
+  double ny = e1z * e2x - e1x * e2z;
+  double nz = e1x * e2y - e1y * e2x;
+  double len = sqrt(nx * nx + ny * ny + nz * nz);
+  nx = nx / len;
+  ny = ny / len;
+  nz = nz / len;
+  double d = -(nx * p0.x + ny * p0.y + nz * p0.z);
+  K[0] = nx * nx; K[1] = nx * ny; K[2] = nx * nz; K[3] = nx * d;
+  K[4] = ny * ny; K[5] = ny * nz; K[6] = ny * d;
+  K[7] = nz * nz; K[8] = nz * d;
+  K[9] = d * d;
+}
+
+// v^T Q v for v = (x, y, z, 1)
+PAMO_HD __forceinline__ double quadric_eval(const double* q, P3 v) {
+  double qx = q[0] * v.x + q[1] * v.y + q[2] * v.z + q[3];
+  double qy = q[1] * v.x + q[4] * v.y + q[5] * v.z + q[6];
+  double qz = q[2] * v.x + q[5] * v.y + q[7] * v.z + q[8];
+  double qw = q[3] * v.x + q[6] * v.y + q[8] * v.z + q[9];
+  return qx * v.x + qy * v.y + qz * v.z + qw;
+}
+
+// 1 - C_ijk of Eq. 1: C_ijk = 4 sqrt(3) A / (l01^2 + l12^2 + l20^2)
+PAMO_HD __forceinline__ double skinny_term(P3 p0, P3 p1, P3 p2) {
+  double e1x = p1.x - p0.x, e1y = p1.y - p0.y, e1z = p1.z - p0.z;
+  double e2x = p2.x - p0.x, e2y = p2.y - p0.y, e2z = p2.z - p0.z;
+  double e3x = p2.x - p1.x, e3y = p2.y - p1.y, e3z = p2.z - p1.z;
+  double nx = e1y * e2z - e1z * e2y;
+  double ny = e1z * e2x - e1x * e2z;
+  double nz = e1x * e2y - e1y * e2x;
+  double nn = sqrt(nx * nx + ny * ny + nz * nz);
+  double l01 = e1x * e1x + e1y * e1y + e1z * e1z;
+  double l12 = e3x * e3x + e3y * e3y + e3z * e3z;
+  double l20 = e2x * e2x + e2y * e2y + e2z * e2z;
+  double lsum = l01 + l12 + l20;
+  return 1.0 - (PAMO_SKINNY_K * nn) / lsum;
+}
+
+// Order-preserving 64-bit key: float32 (round to nearest even) cost in the
+// high half, unique edge id in the low half (Sec. 5.1, cost propagation).
+PAMO_HD __forceinline__ uint64_t make_key(double cost, uint32_t edge_id) {
+  if (cost != cost) return PAMO_KEY_MAX;
+  float c = (float)cost;
+  uint32_t u;
+  __builtin_memcpy(&u, &c, 4);
+  uint32_t o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((uint64_t)o << 32) | (uint64_t)edge_id;
+}
+
+// Sorted insertion of x into a[0..CAP) kept ascending with INT_MAX padding.
+// Fully unrolled so the list stays in registers.
+template <int CAP>
+PAMO_HD __forceinline__ void sorted_insert(int* a, int x) {
+#pragma unroll
+  for (int i = CAP - 1; i >= 0; --i) {
+    int lo = i > 0 ? a[i - 1] : INT32_MIN;
+    int m = lo > x ? lo : x;
+    a[i] = a[i] < m ? a[i] : m;
+  }
+}
+
+}  // namespace pamo

@@ -1,0 +1,295 @@
+// Device-wide primitives: prefix sums, stream compaction and a stable LSD
+// radix sort, written for 64-lane wavefronts (ballot / popcount ranking).
+#include "internal.hpp"
+
+namespace pamo {
+
+namespace {
+
+constexpr int T = 256;       // threads per block (4 waves)
+constexpr int ITEMS = 16;    // items per thread in scans
+constexpr int TILE = T * ITEMS;
+constexpr int TOP_T = 1024;  // single-block scan of tile sums
+constexpr int TOP_ITEMS = 16;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+// exclusive scan over the block; *total gets the block sum (all threads)
+template <int NT>
+__device__ __forceinline__ int block_excl_scan(int x, int& total) {
+  constexpr int NW = NT / 64;
+  __shared__ int wsum[NW + 1];
+  int lane = lane_id(), w = threadIdx.x >> 6;
+  int inc = wave_incl_scan(x);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    int v = lane < NW ? wsum[lane] : 0;
+    int vi = wave_incl_scan(v);
+    if (lane < NW) wsum[lane] = vi - v;
+    if (lane == NW - 1) wsum[NW] = vi;
+  }
+  __syncthreads();
+  int r = wsum[w] + inc - x;
+  total = wsum[NW];
+  __syncthreads();
+  return r;
+}
+
+template <int NT>
+__device__ __forceinline__ int block_sum(int x) {
+  int t;
+  block_excl_scan<NT>(x, t);
+  return t;
+}
+
+struct FlagLoad {
+  const uint8_t* f;
+  __device__ int load(int64_t i) const { return f[i] != 0; }
+};
+struct IntLoad {
+  const int32_t* a;
+  __device__ int load(int64_t i) const { return a[i]; }
+};
+
+template <class Op>
+__global__ __launch_bounds__(T) void k_tile_reduce(Op op, int64_t n, int32_t* tile_sum) {
+  int64_t base = (int64_t)blockIdx.x * TILE;
+  int s = 0;
+  for (int i = threadIdx.x; i < TILE; i += T) {
+    int64_t g = base + i;
+    if (g < n) s += op.load(g);
+  }
+  s = block_sum<T>(s);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = s;
+}
+
+// exclusive scan of a[0..n) in place (n <= TOP_T*TOP_ITEMS); total -> *total
+__global__ __launch_bounds__(TOP_T) void k_top_scan(int32_t* a, int n, int32_t* total) {
+  int base = threadIdx.x * TOP_ITEMS;
+  int v[TOP_ITEMS];
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < TOP_ITEMS; i++) {
+    v[i] = base + i < n ? a[base + i] : 0;
+    s += v[i];
+  }
+  int tot;
+  int ex = block_excl_scan<TOP_T>(s, tot);
+#pragma unroll
+  for (int i = 0; i < TOP_ITEMS; i++) {
+    if (base + i < n) a[base + i] = ex;
+    ex += v[i];
+  }
+  if (threadIdx.x == 0 && total) *total = tot;
+}
+
+struct CompactStore {
+  int32_t* out;
+  __device__ void store(int64_t i, int prefix, int v) const {
+    if (v) out[prefix] = (int32_t)i;
+  }
+};
+struct CompactMapStore {
+  int32_t* out;
+  const int32_t* map;
+  __device__ void store(int64_t i, int prefix, int v) const {
+    if (v) out[prefix] = map[i];
+  }
+};
+struct RankStore {
+  int32_t* map;
+  __device__ void store(int64_t i, int prefix, int v) const { map[i] = v ? prefix : -1; }
+};
+struct ScanStore {
+  int32_t* out;
+  __device__ void store(int64_t i, int prefix, int) const { out[i] = prefix; }
+};
+
+template <class Op, class St>
+__global__ __launch_bounds__(T) void k_tile_scan(Op op, St st, int64_t n, const int32_t* tile_off) {
+  int64_t base = (int64_t)blockIdx.x * TILE + (int64_t)threadIdx.x * ITEMS;
+  int v[ITEMS];
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    v[i] = base + i < n ? op.load(base + i) : 0;
+    s += v[i];
+  }
+  int tot;
+  int ex = block_excl_scan<T>(s, tot) + tile_off[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    if (base + i < n) st.store(base + i, ex, v[i]);
+    ex += v[i];
+  }
+}
+
+template <class Op, class St>
+void run_scan(Workspace& ws, hipStream_t s, Op op, St st, int64_t n, int32_t* total) {
+  int64_t ntiles = (n + TILE - 1) / TILE;
+  if (ntiles > (int64_t)TOP_T * TOP_ITEMS) throw std::runtime_error("scan: input too large");
+  if (ntiles == 0) {
+    if (total) fill_i32(s, total, 1, 0);
+    return;
+  }
+  int32_t* tiles = ws.get<int32_t>("prim.tiles", ntiles);
+  hipLaunchKernelGGL(k_tile_reduce<Op>, dim3((unsigned)ntiles), dim3(T), 0, s, op, n, tiles);
+  hipLaunchKernelGGL(k_top_scan, dim3(1), dim3(TOP_T), 0, s, tiles, (int)ntiles, total);
+  hipLaunchKernelGGL((k_tile_scan<Op, St>), dim3((unsigned)ntiles), dim3(T), 0, s, op, st, n,
+                     (const int32_t*)tiles);
+  PAMO_HIP(hipGetLastError());
+}
+
+__global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+unsigned grid_for(int64_t n, int t = 256) {
+  int64_t b = (n + t - 1) / t;
+  if (b < 1) b = 1;
+  if (b > 65536) b = 65536;
+  return (unsigned)b;
+}
+
+// ------------------------------------------------------------ radix sort
+constexpr int RS_T = 256;
+constexpr int RS_CHUNKS = 16;
+constexpr int RS_TILE = RS_T * RS_CHUNKS;
+
+template <class K>
+__global__ __launch_bounds__(RS_T) void k_radix_hist(const K* keys, int64_t n, int shift, int32_t* ghist,
+                                                      int nblocks) {
+  __shared__ int hist[256];
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int i = threadIdx.x; i < RS_TILE; i += RS_T) {
+    int64_t g = base + i;
+    if (g < n) atomicAdd(&hist[(int)((keys[g] >> shift) & 0xFF)], 1);
+  }
+  __syncthreads();
+  ghist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
+}
+
+template <class K>
+__global__ __launch_bounds__(RS_T) void k_radix_scatter(const K* kin, const int32_t* vin, K* kout, int32_t* vout,
+                                                         int64_t n, int shift, const int32_t* ghist,
+                                                         int nblocks) {
+  __shared__ int running[256];
+  __shared__ int wcount[RS_T / 64][256];
+  int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+  running[tid] = ghist[(int64_t)tid * nblocks + blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < RS_T / 64; k++) wcount[k][tid] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int c = 0; c < RS_CHUNKS; c++) {
+    int64_t g = base + (int64_t)c * RS_T + tid;
+    bool valid = g < n;
+    K key = valid ? kin[g] : (K)0;
+    int32_t val = valid ? vin[g] : 0;
+    int d = (int)((key >> shift) & 0xFF);
+    unsigned long long mask = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+      unsigned long long bb = __ballot((d >> b) & 1);
+      mask &= ((d >> b) & 1) ? bb : ~bb;
+    }
+    unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int rank = __popcll(mask & lt);
+    if (valid && rank == 0) wcount[w][d] = __popcll(mask);
+    __syncthreads();
+    if (valid) {
+      int off = running[d] + rank;
+      for (int k = 0; k < w; k++) off += wcount[k][d];
+      kout[off] = key;
+      vout[off] = val;
+    }
+    __syncthreads();
+    int add = 0;
+#pragma unroll
+    for (int k = 0; k < RS_T / 64; k++) {
+      add += wcount[k][tid];
+      wcount[k][tid] = 0;
+    }
+    running[tid] += add;
+    __syncthreads();
+  }
+}
+
+template <class K>
+void radix_sort_impl(Workspace& ws, hipStream_t s, K* keys, int32_t* vals, int64_t n, int bits, const char* tag) {
+  if (n <= 1) return;
+  int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
+  int passes = (bits + 7) / 8;
+  std::string t(tag);
+  K* k2 = ws.get<K>(t + ".k2", n);
+  int32_t* v2 = ws.get<int32_t>(t + ".v2", n);
+  int32_t* hist = ws.get<int32_t>(t + ".hist", (size_t)256 * nblocks);
+  K *ki = keys, *ko = k2;
+  int32_t *vi = vals, *vo = v2;
+  for (int p = 0; p < passes; p++) {
+    int shift = 8 * p;
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3(nblocks), dim3(RS_T), 0, s, (const K*)ki, n, shift, hist, nblocks);
+    scan_exclusive(ws, s, hist, hist, (int64_t)256 * nblocks, nullptr);
+    hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nblocks), dim3(RS_T), 0, s, (const K*)ki, (const int32_t*)vi, ko, vo,
+                       n, shift, (const int32_t*)hist, nblocks);
+    PAMO_HIP(hipGetLastError());
+    K* tk = ki; ki = ko; ko = tk;
+    int32_t* tv = vi; vi = vo; vo = tv;
+  }
+  if (ki != keys) {
+    PAMO_HIP(hipMemcpyAsync(keys, ki, n * sizeof(K), hipMemcpyDeviceToDevice, s));
+    PAMO_HIP(hipMemcpyAsync(vals, vi, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  }
+}
+
+}  // namespace
+
+void fill_u8(hipStream_t s, uint8_t* p, int64_t n, uint8_t v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+}
+void fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+}
+
+void compact_flags(Workspace& ws, hipStream_t s, const uint8_t* flags, int64_t n, int32_t* out, int32_t* count) {
+  run_scan(ws, s, FlagLoad{flags}, CompactStore{out}, n, count);
+}
+void compact_flags_map(Workspace& ws, hipStream_t s, const uint8_t* flags, int64_t n, const int32_t* map,
+                       int32_t* out, int32_t* count) {
+  run_scan(ws, s, FlagLoad{flags}, CompactMapStore{out, map}, n, count);
+}
+void rank_flags(Workspace& ws, hipStream_t s, const uint8_t* flags, int64_t n, int32_t* map, int32_t* count) {
+  run_scan(ws, s, FlagLoad{flags}, RankStore{map}, n, count);
+}
+void scan_exclusive(Workspace& ws, hipStream_t s, const int32_t* in, int32_t* out, int64_t n, int32_t* total) {
+  // the tile pass reads all of a tile before writing it, so in == out is fine
+  run_scan(ws, s, IntLoad{in}, ScanStore{out}, n, total);
+}
+void radix_sort_u32(Workspace& ws, hipStream_t s, uint32_t* keys, int32_t* vals, int64_t n, int bits) {
+  radix_sort_impl<uint32_t>(ws, s, keys, vals, n, bits, "rs32");
+}
+void radix_sort_u64(Workspace& ws, hipStream_t s, uint64_t* keys, int32_t* vals, int64_t n, int bits) {
+  radix_sort_impl<uint64_t>(ws, s, keys, vals, n, bits, "rs64");
+}
+
+}  // namespace pamo

@@ -1,0 +1,780 @@
+// Per-round kernels of parallel intersection-free QEM simplification
+// (PaMO Sec. 5.1 and 5.3), one thread per vertex, edge or candidate.
+//
+// Every per-element result is a pure function of the pre-round mesh, so the
+// kernels need no atomics except the idempotent marks of the check/undo loop:
+//   quadrics      vertex:    Q_v = sum of plane quadrics of its faces, ascending face slot
+//   cost_keys     edge:      placement + Eq. 1 cost + 64-bit key (both half-edges)
+//   vertex_min    vertex:    m_v = min key of its edges (pull form of the paper's AtomicMin)
+//   select        edge:      key_e = min of m_w over the closed neighbourhood of e
+//   local_check   candidate: link condition, exact degeneracy, normal flip
+//   apply/undo    candidate: tentative collapse and its exact reversal
+//   commit        candidate: twin rewiring of the two removed faces
+//   compaction    face/vertex: stable, order-preserving
+#include "internal.hpp"
+#include "exact_dev.hpp"
+#include "round.hpp"
+
+namespace pamo {
+
+namespace {
+
+constexpr int RING_GUARD = 1 << 15;  // a vertex star longer than this is treated as corrupt
+
+__device__ __forceinline__ void set_err(int* err, int bit) { atomicOr(err, bit); }
+
+// visit the outgoing half-edges of the vertex at the origin of h0
+template <class Fn>
+__device__ __forceinline__ bool walk_star(const int* __restrict__ twin, int h0, Fn&& fn) {
+  if (h0 < 0) return false;
+  int h = h0, guard = 0;
+  do {
+    fn(h);
+    h = twin[he_prev(h)];
+    if (++guard > RING_GUARD || h < 0) return false;
+  } while (h != h0);
+  return true;
+}
+
+__device__ __forceinline__ int dest(const int* __restrict__ F, int h) { return F[he_next(h)]; }
+
+// pop the smallest entry of an ascending register list
+template <int CAP>
+__device__ __forceinline__ int pop_front(int* a) {
+  int f = a[0];
+#pragma unroll
+  for (int i = 0; i < CAP - 1; i++) a[i] = a[i + 1];
+  a[CAP - 1] = INT32_MAX;
+  return f;
+}
+
+// ------------------------------------------------------------ adjacency
+__global__ void k_he_keys(const int* __restrict__ F, int nf, int nv, int bits, uint64_t* keys, int* vals, int* err) {
+  int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= 3 * nf) return;
+  int a = F[h], b = F[he_next(h)];
+  if (a < 0 || a >= nv || b < 0 || b >= nv) {
+    set_err(err, PAMO_EBIT_INDEX);
+    a = b = 0;
+  }
+  if (a == b) set_err(err, PAMO_EBIT_DEGENERATE);
+  uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+  keys[h] = ((uint64_t)lo << bits) | hi;
+  vals[h] = h;
+}
+
+__global__ void k_pair_twins(const uint64_t* __restrict__ keys, const int* __restrict__ vals, int n,
+                             const int* __restrict__ F, int* twin, int* err) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t k = keys[i];
+  if (i > 0 && keys[i - 1] == k) return;  // not the first of its group
+  int len = 1;
+  while (i + len < n && keys[i + len] == k && len < 3) len++;
+  if (len != 2) {
+    set_err(err, PAMO_EBIT_EDGE);
+    twin[vals[i]] = -1;
+    return;
+  }
+  int h1 = vals[i], h2 = vals[i + 1];
+  // opposite directions: h1 = a->b, h2 = b->a
+  if (F[h1] != F[he_next(h2)] || F[he_next(h1)] != F[h2]) {
+    set_err(err, PAMO_EBIT_ORIENT);
+    return;
+  }
+  twin[h1] = h2;
+  twin[h2] = h1;
+}
+
+__global__ void k_vertex_he(const int* __restrict__ F, int nf, int* vh, int* deg) {
+  int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= 3 * nf) return;
+  int v = F[h];
+  vh[v] = h;  // any leaving half-edge will do
+  atomicAdd(&deg[v], 1);
+}
+
+// every vertex must be used and its star must be one fan around it
+__global__ void k_check_vertices(const int* __restrict__ twin, const int* __restrict__ vh,
+                                 const int* __restrict__ deg, int nv, int* err) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  int d = deg[v];
+  if (d == 0) {
+    set_err(err, PAMO_EBIT_VERTEX);
+    return;
+  }
+  int h0 = vh[v], h = h0, cnt = 0;
+  do {
+    int p = twin[he_prev(h)];
+    cnt++;
+    if (p < 0 || cnt > d) break;
+    h = p;
+  } while (h != h0);
+  if (cnt != d || h != h0) set_err(err, PAMO_EBIT_VERTEX);
+}
+
+// ------------------------------------------------------------ quadrics
+__global__ __launch_bounds__(256) void k_quadrics(MeshView m, double* __restrict__ Q, int* err) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= m.nv) return;
+  constexpr int CAP = 16;
+  int fl[CAP];
+#pragma unroll
+  for (int i = 0; i < CAP; i++) fl[i] = INT32_MAX;
+  int n = 0;
+  bool ok = walk_star(m.twin, m.vh[v], [&](int h) {
+    if (n < CAP) sorted_insert<CAP>(fl, h / 3);
+    n++;
+  });
+  if (!ok) {
+    set_err(err, PAMO_EBIT_RING);
+    return;
+  }
+  double q[10];
+#pragma unroll
+  for (int i = 0; i < 10; i++) q[i] = 0.0;
+  int last = -1;
+  for (int k = 0; k < n; k++) {
+    int f;
+    if (n <= CAP) {
+      f = pop_front<CAP>(fl);
+    } else {
+      int best = INT32_MAX;
+      walk_star(m.twin, m.vh[v], [&](int h) {
+        int g = h / 3;
+        if (g > last && g < best) best = g;
+      });
+      f = best;
+    }
+    last = f;
+    double K[10];
+    face_quadric(ld3(m.V, m.F[3 * f]), ld3(m.V, m.F[3 * f + 1]), ld3(m.V, m.F[3 * f + 2]), K);
+#pragma unroll
+    for (int i = 0; i < 10; i++) q[i] = q[i] + K[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 10; i++) Q[10 * (int64_t)v + i] = q[i];
+}
+
+// ------------------------------------------------------------ edge evaluation
+struct EdgeRing {
+  static constexpr int CAP = 32;
+  int fl[CAP];  // faces of star(a) u star(b) without the two edge faces, ascending
+  int n;
+  P3 lo, hi;  // box of the closed 1-rings
+};
+
+// ring faces of edge h (a = F[h], b = F[next h]), ascending, and the box of
+// every vertex of star(a) u star(b)
+__device__ __forceinline__ bool edge_ring(const MeshView& m, int h, EdgeRing& R) {
+  int f1 = h / 3, f2 = m.twin[h] / 3;
+#pragma unroll
+  for (int i = 0; i < EdgeRing::CAP; i++) R.fl[i] = INT32_MAX;
+  R.n = 0;
+  R.lo = P3{INFINITY, INFINITY, INFINITY};
+  R.hi = P3{-INFINITY, -INFINITY, -INFINITY};
+  auto visit = [&](int g) {
+    int f = g / 3;
+    P3 p = ld3(m.V, dest(m.F, g));
+    R.lo.x = fmin(R.lo.x, p.x); R.lo.y = fmin(R.lo.y, p.y); R.lo.z = fmin(R.lo.z, p.z);
+    R.hi.x = fmax(R.hi.x, p.x); R.hi.y = fmax(R.hi.y, p.y); R.hi.z = fmax(R.hi.z, p.z);
+    if (f == f1 || f == f2) return;
+    if (R.n < EdgeRing::CAP) sorted_insert<EdgeRing::CAP>(R.fl, f);
+    R.n++;
+  };
+  bool ok = walk_star(m.twin, h, visit);
+  ok = ok && walk_star(m.twin, m.twin[h], visit);
+  return ok;
+}
+
+// k-th step of an ascending walk over the ring faces: fast path pops the
+// register list, slow path (ring longer than the list) rescans the stars
+__device__ __forceinline__ int ring_next(const MeshView& m, int h, EdgeRing& R, int last) {
+  if (R.n <= EdgeRing::CAP) return pop_front<EdgeRing::CAP>(R.fl);
+  int f1 = h / 3, f2 = m.twin[h] / 3;
+  int best = INT32_MAX;
+  auto scan = [&](int g) {
+    int f = g / 3;
+    if (f != f1 && f != f2 && f > last && f < best) best = f;
+  };
+  walk_star(m.twin, h, scan);
+  walk_star(m.twin, m.twin[h], scan);
+  return best;
+}
+
+// placement of the merged vertex (quadric minimiser by Cramer's rule when the
+// system is well conditioned and the minimiser is inside the ring box, else
+// the best of midpoint, p_s, p_r)
+__device__ __forceinline__ P3 placement(const double* q, P3 ps, P3 pr, P3 lo, P3 hi) {
+  double a00 = q[0], a01 = q[1], a02 = q[2], a11 = q[4], a12 = q[5], a22 = q[7];
+  double r0 = -q[3], r1 = -q[6], r2 = -q[8];
+  double c00 = a11 * a22 - a12 * a12;
+  double c01 = a01 * a22 - a12 * a02;
+  double c02 = a01 * a12 - a11 * a02;
+  double det = a00 * c00 - a01 * c01 + a02 * c02;
+  double tr3 = (a00 + a11 + a22) / 3.0;
+  double thr = 1e-10 * (tr3 * tr3 * tr3);
+  if (fabs(det) > thr) {
+    double dx = r0 * c00 - a01 * (r1 * a22 - a12 * r2) + a02 * (r1 * a12 - a11 * r2);
+    double dy = a00 * (r1 * a22 - a12 * r2) - r0 * c01 + a02 * (a01 * r2 - r1 * a02);
+    double dz = a00 * (a11 * r2 - r1 * a12) - a01 * (a01 * r2 - r1 * a02) + r0 * c02;
+    P3 v{dx / det, dy / det, dz / det};
+    if (v.x >= lo.x && v.x <= hi.x && v.y >= lo.y && v.y <= hi.y && v.z >= lo.z && v.z <= hi.z) return v;
+  }
+  P3 mid{(ps.x + pr.x) * 0.5, (ps.y + pr.y) * 0.5, (ps.z + pr.z) * 0.5};
+  P3 best = mid;
+  double qb = quadric_eval(q, mid);
+  double qs = quadric_eval(q, ps);
+  if (qs < qb) {
+    best = ps;
+    qb = qs;
+  }
+  double qr = quadric_eval(q, pr);
+  if (qr < qb) best = pr;
+  return best;
+}
+
+__device__ __forceinline__ P3 corner_after(const MeshView& m, int f, int c, int s, int r, P3 vbar) {
+  int v = m.F[3 * f + c];
+  return (v == s || v == r) ? vbar : ld3(m.V, v);
+}
+
+// cost (Eq. 1) and placement of edge h; R is consumed
+__device__ __forceinline__ double edge_cost(const MeshView& m, const double* __restrict__ Q, int h, EdgeRing& R,
+                                            double w_e, double w_s, P3& vbar) {
+  int a = m.F[h], b = m.F[he_next(h)];
+  int s = a < b ? a : b, r = a < b ? b : a;
+  double q[10];
+#pragma unroll
+  for (int i = 0; i < 10; i++) q[i] = Q[10 * (int64_t)s + i] + Q[10 * (int64_t)r + i];
+  P3 ps = ld3(m.V, s), pr = ld3(m.V, r);
+  vbar = placement(q, ps, pr, R.lo, R.hi);
+  double dx = ps.x - pr.x, dy = ps.y - pr.y, dz = ps.z - pr.z;
+  double lab = sqrt(dx * dx + dy * dy + dz * dz);
+  double S = 0.0;
+  int last = -1;
+  for (int k = 0; k < R.n; k++) {
+    int f = ring_next(m, h, R, last);
+    last = f;
+    S = S + skinny_term(corner_after(m, f, 0, s, r, vbar), corner_after(m, f, 1, s, r, vbar),
+                        corner_after(m, f, 2, s, r, vbar));
+  }
+  return quadric_eval(q, vbar) + w_e * lab + w_s * S;
+}
+
+// ------------------------------------------------------------ cost + keys
+__global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
+                                                   const uint8_t* __restrict__ demote, uint64_t* __restrict__ key,
+                                                   int* err) {
+  int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= 3 * m.nf) return;
+  int t = m.twin[h];
+  if (t < h) return;  // the smaller half-edge represents the edge
+  uint64_t k = PAMO_KEY_MAX;
+  bool skip = m.flags[h] || m.flags[t] || (demote && (demote[h] || demote[t]));
+  if (!skip) {
+    EdgeRing R;
+    if (!edge_ring(m, h, R)) {
+      set_err(err, PAMO_EBIT_RING);
+    } else {
+      P3 vbar;
+      double cost = edge_cost(m, Q, h, R, w_e, w_s, vbar);
+      k = make_key(cost, (uint32_t)h);
+    }
+  }
+  key[h] = k;
+  key[t] = k;
+}
+
+// ------------------------------------------------------------ selection
+__global__ __launch_bounds__(256) void k_vertex_min(MeshView m, const uint64_t* __restrict__ key,
+                                                    uint64_t* __restrict__ vmin) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= m.nv) return;
+  uint64_t best = PAMO_KEY_MAX;
+  walk_star(m.twin, m.vh[v], [&](int h) {
+    uint64_t k = key[h];
+    best = k < best ? k : best;
+  });
+  vmin[v] = best;
+}
+
+// e = (a, b) is chosen iff its key is the minimum over the vertex minima of
+// {a, b} u N(a) u N(b), i.e. no edge sharing a ring triangle has a smaller key
+__global__ __launch_bounds__(256) void k_select(MeshView m, const uint64_t* __restrict__ key,
+                                                const uint64_t* __restrict__ vmin, uint8_t* __restrict__ sel) {
+  int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= 3 * m.nf) return;
+  uint8_t ok = 0;
+  uint64_t k = key[h];
+  if (k != PAMO_KEY_MAX && h < m.twin[h]) {
+    int a = m.F[h], b = m.F[he_next(h)];
+    if (vmin[a] == k && vmin[b] == k) {
+      bool local_min = true;
+      auto nb = [&](int g) {
+        if (vmin[dest(m.F, g)] < k) local_min = false;
+      };
+      walk_star(m.twin, h, nb);
+      if (local_min) walk_star(m.twin, m.twin[h], nb);
+      ok = local_min;
+    }
+  }
+  sel[h] = ok;
+}
+
+// ------------------------------------------------------------ local checks
+__device__ __forceinline__ bool degenerate(P3 a, P3 b, P3 c) {
+  // certain nonzero in some projection -> not degenerate
+  for (int k = 0; k < 3; k++) {
+    int s = orient2d_filter(pu(a, k), pv(a, k), pu(b, k), pv(b, k), pu(c, k), pv(c, k));
+    if (s != UNK) return false;
+  }
+  return degenerate_exact(a, b, c);
+}
+
+// link condition Lk(a) n Lk(b) = Lk(ab) on a closed manifold: the only
+// common neighbours are the two apexes, and the edge is not inside a
+// tetrahedron component (both endpoints of valence 3)
+__device__ __forceinline__ bool link_ok(const MeshView& m, int h) {
+  constexpr int CAP = 16;
+  int na[CAP];
+#pragma unroll
+  for (int i = 0; i < CAP; i++) na[i] = -1;
+  int vala = 0;
+  walk_star(m.twin, h, [&](int g) {
+    int w = dest(m.F, g);
+#pragma unroll
+    for (int i = 0; i < CAP; i++)
+      if (i == vala) na[i] = w;
+    vala++;
+  });
+  int valb = 0, common = 0;
+  walk_star(m.twin, m.twin[h], [&](int g) {
+    int w = dest(m.F, g);
+    valb++;
+    bool in = false;
+    if (vala <= CAP) {
+#pragma unroll
+      for (int i = 0; i < CAP; i++) in |= na[i] == w;
+    } else {
+      walk_star(m.twin, h, [&](int g2) { in |= dest(m.F, g2) == w; });
+    }
+    common += in;
+  });
+  return common == 2 && !(vala == 3 && valb == 3);
+}
+
+__global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* __restrict__ Q, double w_e,
+                                                     double w_s, const int* __restrict__ cand,
+                                                     const int* __restrict__ ncand, const uint64_t* __restrict__ key,
+                                                     uint8_t* __restrict__ reason, double* __restrict__ vbar_out,
+                                                     uint64_t* __restrict__ ckey, int* err) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= *ncand) return;
+  int h = cand[c];
+  ckey[c] = key[h];
+  uint8_t rs = 0;
+  P3 vbar{0, 0, 0};
+  if (!link_ok(m, h)) {
+    rs = 1;
+  } else {
+    EdgeRing R;
+    if (!edge_ring(m, h, R)) set_err(err, PAMO_EBIT_RING);
+    int nring = R.n;
+    (void)edge_cost(m, Q, h, R, w_e, w_s, vbar);
+    // the ring list was consumed; walk the stars again for the checks
+    int a = m.F[h], b = m.F[he_next(h)];
+    int s = a < b ? a : b, r = a < b ? b : a;
+    int f1 = h / 3, f2 = m.twin[h] / 3;
+    bool bad = false;
+    auto chk = [&](int g) {
+      int f = g / 3;
+      if (f == f1 || f == f2 || bad) return;
+      P3 o0 = ld3(m.V, m.F[3 * f]), o1 = ld3(m.V, m.F[3 * f + 1]), o2 = ld3(m.V, m.F[3 * f + 2]);
+      P3 p0 = corner_after(m, f, 0, s, r, vbar), p1 = corner_after(m, f, 1, s, r, vbar),
+         p2 = corner_after(m, f, 2, s, r, vbar);
+      if (degenerate(p0, p1, p2)) {
+        bad = true;
+        return;
+      }
+      double ax = o1.x - o0.x, ay = o1.y - o0.y, az = o1.z - o0.z;
+      double bx = o2.x - o0.x, by = o2.y - o0.y, bz = o2.z - o0.z;
+      double nox = ay * bz - az * by, noy = az * bx - ax * bz, noz = ax * by - ay * bx;
+      double cx = p1.x - p0.x, cy = p1.y - p0.y, cz = p1.z - p0.z;
+      double dx = p2.x - p0.x, dy = p2.y - p0.y, dz = p2.z - p0.z;
+      double nnx = cy * dz - cz * dy, nny = cz * dx - cx * dz, nnz = cx * dy - cy * dx;
+      double dot = nox * nnx + noy * nny + noz * nnz;
+      if (!(dot > 0.0)) bad = true;
+    };
+    (void)nring;
+    walk_star(m.twin, h, chk);
+    walk_star(m.twin, m.twin[h], chk);
+    if (bad) rs = 2;
+  }
+  reason[c] = rs;
+  vbar_out[3 * (int64_t)c] = vbar.x;
+  vbar_out[3 * (int64_t)c + 1] = vbar.y;
+  vbar_out[3 * (int64_t)c + 2] = vbar.z;
+}
+
+// candidates passing the local checks whose key exceeds the threshold are
+// capped (exact face target)
+__global__ void k_cap(const int* __restrict__ ncand, const uint64_t* __restrict__ ckey, const uint64_t* __restrict__ thr,
+                      uint8_t* __restrict__ reason) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= *ncand) return;
+  if (reason[c] == 0 && ckey[c] > *thr) reason[c] = 4;
+}
+
+__global__ void k_pass_keys(const int* __restrict__ ncand, const uint64_t* __restrict__ ckey,
+                            const uint8_t* __restrict__ reason, uint64_t* __restrict__ out, int* __restrict__ idx) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= *ncand) return;
+  out[c] = reason[c] == 0 ? ckey[c] : PAMO_KEY_MAX;
+  idx[c] = c;
+}
+
+__global__ void k_pick(const uint64_t* __restrict__ sorted, int64_t k, uint64_t* __restrict__ thr) { *thr = sorted[k]; }
+
+// ------------------------------------------------------------ boxes
+__device__ __forceinline__ float f_down(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = nextafterf(f, -INFINITY);
+  return f;
+}
+__device__ __forceinline__ float f_up(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = nextafterf(f, INFINITY);
+  return f;
+}
+
+__device__ __forceinline__ void face_box_f32(const MeshView& m, int f, float* b) {
+  P3 p0 = ld3(m.V, m.F[3 * f]), p1 = ld3(m.V, m.F[3 * f + 1]), p2 = ld3(m.V, m.F[3 * f + 2]);
+  b[0] = f_down(fmin(fmin(p0.x, p1.x), p2.x));
+  b[1] = f_down(fmin(fmin(p0.y, p1.y), p2.y));
+  b[2] = f_down(fmin(fmin(p0.z, p1.z), p2.z));
+  b[3] = f_up(fmax(fmax(p0.x, p1.x), p2.x));
+  b[4] = f_up(fmax(fmax(p0.y, p1.y), p2.y));
+  b[5] = f_up(fmax(fmax(p0.z, p1.z), p2.z));
+}
+
+__global__ __launch_bounds__(256) void k_face_boxes(MeshView m, float* __restrict__ box) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= m.nf) return;
+  float b[6];
+  face_box_f32(m, f, b);
+#pragma unroll
+  for (int i = 0; i < 6; i++) box[6 * (int64_t)f + i] = b[i];
+}
+
+// ------------------------------------------------------------ apply / undo
+// Tentatively collapse every candidate with reason 0: the merged vertex keeps
+// the smaller id s and moves to vbar, corners of the larger id r are
+// relabelled s, the two faces of the edge die.  Faces of star(a) u star(b)
+// get owner = candidate; their boxes grow to cover the new geometry too.
+__global__ __launch_bounds__(256) void k_apply(MeshView m, const int* __restrict__ cand, const int* __restrict__ ncand,
+                                               const uint8_t* __restrict__ reason, const double* __restrict__ vbar,
+                                               double* __restrict__ oldpos, int* __restrict__ owner,
+                                               uint8_t* __restrict__ falive, float* __restrict__ box) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= *ncand || reason[c] != 0) return;
+  int h = cand[c];
+  int t = m.twin[h];
+  int a = m.F[h], b = m.F[he_next(h)];
+  int s = a < b ? a : b, r = a < b ? b : a;
+  int hr = a == r ? h : t;  // leaves r
+  int f1 = h / 3, f2 = t / 3;
+  auto own = [&](int g) { owner[g / 3] = c; };
+  walk_star(m.twin, h, own);
+  walk_star(m.twin, t, own);
+  walk_star(m.twin, hr, [&](int g) {
+    int f = g / 3;
+    if (f != f1 && f != f2) m.F[g] = s;  // corner g % 3 of face f held r
+  });
+  for (int k = 0; k < 3; k++) oldpos[3 * (int64_t)c + k] = m.V[3 * (int64_t)s + k];
+  for (int k = 0; k < 3; k++) m.V[3 * (int64_t)s + k] = vbar[3 * (int64_t)c + k];
+  falive[f1] = 0;
+  falive[f2] = 0;
+  // union boxes of the faces around s (now the merged vertex)
+  int hs = a == s ? h : t;
+  auto grow = [&](int g) {
+    int f = g / 3;
+    if (f == f1 || f == f2) return;
+    float nb[6];
+    face_box_f32(m, f, nb);
+    float* bx = box + 6 * (int64_t)f;
+    bx[0] = fminf(bx[0], nb[0]); bx[1] = fminf(bx[1], nb[1]); bx[2] = fminf(bx[2], nb[2]);
+    bx[3] = fmaxf(bx[3], nb[3]); bx[4] = fmaxf(bx[4], nb[4]); bx[5] = fmaxf(bx[5], nb[5]);
+  };
+  walk_star(m.twin, hs, grow);
+  walk_star(m.twin, hr, grow);
+}
+
+// undo the collapses marked in check iteration `iter`
+__global__ __launch_bounds__(256) void k_undo(MeshView m, const int* __restrict__ cand, const int* __restrict__ ncand,
+                                              const int* __restrict__ undone, int iter,
+                                              const double* __restrict__ oldpos, uint8_t* __restrict__ falive) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= *ncand || undone[c] != iter) return;
+  int h = cand[c];
+  int t = m.twin[h];
+  int a = m.F[h], b = m.F[he_next(h)];
+  // corners of f1 = h/3 and f2 = t/3 were never relabelled, so a, b are the
+  // original endpoints
+  int s = a < b ? a : b, r = a < b ? b : a;
+  int hr = a == r ? h : t;
+  int f1 = h / 3, f2 = t / 3;
+  walk_star(m.twin, hr, [&](int g) {
+    int f = g / 3;
+    if (f != f1 && f != f2) m.F[g] = r;
+  });
+  for (int k = 0; k < 3; k++) m.V[3 * (int64_t)s + k] = oldpos[3 * (int64_t)c + k];
+  falive[f1] = 1;
+  falive[f2] = 1;
+}
+
+__global__ void k_changed_faces(int nf, const int* __restrict__ owner, const uint8_t* __restrict__ falive,
+                                const int* __restrict__ undone, int iter, const int* __restrict__ order,
+                                uint8_t* __restrict__ pred) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nf) return;
+  int f = order ? order[j] : j;
+  int o = owner[f];
+  uint8_t p = 0;
+  if (o >= 0) {
+    if (iter == 0)
+      p = falive[f];  // faces changed by an applied collapse
+    else
+      p = undone[o] == iter;  // faces restored by the undo of iteration iter
+  }
+  pred[j] = p;
+}
+
+// ------------------------------------------------------------ commit
+// Make the surviving collapses permanent: rewire the twins across the two
+// removed faces, fix the leaving half-edges of the merged vertex and the two
+// apexes, retire r.  Undone candidates get reason 3.
+__global__ __launch_bounds__(256) void k_commit(MeshView m, const int* __restrict__ cand, const int* __restrict__ ncand,
+                                                uint8_t* __restrict__ reason, const int* __restrict__ undone,
+                                                uint8_t* __restrict__ valive) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= *ncand || reason[c] != 0) return;
+  if (undone[c]) {
+    reason[c] = 3;
+    return;
+  }
+  int h1 = cand[c];
+  int h2 = m.twin[h1];
+  int a = m.F[h1], b = m.F[he_next(h1)];
+  int r = a < b ? b : a;
+  int o1 = m.twin[he_next(h1)];  // x -> b
+  int o2 = m.twin[he_prev(h1)];  // a -> x
+  int o3 = m.twin[he_next(h2)];  // y -> a
+  int o4 = m.twin[he_prev(h2)];  // b -> y
+  m.twin[o1] = o2;
+  m.twin[o2] = o1;
+  m.twin[o3] = o4;
+  m.twin[o4] = o3;
+  int s = a < b ? a : b;
+  m.vh[s] = o2;            // leaves the merged vertex
+  m.vh[m.F[o1]] = o1;      // leaves x
+  m.vh[m.F[o3]] = o3;      // leaves y
+  valive[r] = 0;
+}
+
+__global__ void k_flags(MeshView m, const int* __restrict__ cand, const int* __restrict__ ncand,
+                        const uint8_t* __restrict__ reason) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= *ncand) return;
+  uint8_t rs = reason[c];
+  if (rs >= 1 && rs <= 3) {
+    int h = cand[c];
+    m.flags[h] = 1;
+    m.flags[m.twin[h]] = 1;
+  }
+}
+
+__global__ void k_reason_hist(const int* __restrict__ ncand, const uint8_t* __restrict__ reason, int* __restrict__ hist) {
+  __shared__ int local[8];
+  if (threadIdx.x < 8) local[threadIdx.x] = 0;
+  __syncthreads();
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < *ncand) atomicAdd(&local[reason[c] & 7], 1);
+  __syncthreads();
+  if (threadIdx.x < 8 && local[threadIdx.x]) atomicAdd(&hist[threadIdx.x], local[threadIdx.x]);
+}
+
+// ------------------------------------------------------------ compaction
+__global__ void k_compact_faces(MeshView src, MeshView dst, const uint8_t* __restrict__ falive,
+                                const int* __restrict__ fmap, const int* __restrict__ vmap, int* err) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= src.nf || !falive[f]) return;
+  int g = fmap[f];
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    int h = 3 * f + k;
+    int v = vmap[src.F[h]];
+    int t = src.twin[h];
+    int tf = t >= 0 ? fmap[t / 3] : -1;
+    if (v < 0 || tf < 0) {  // a live face pointing at a removed vertex or face
+      atomicOr(err, PAMO_EBIT_RING);
+      v = 0;
+      tf = g;
+    }
+    dst.F[3 * g + k] = v;
+    dst.twin[3 * g + k] = 3 * tf + (t >= 0 ? t % 3 : k);
+    dst.flags[3 * g + k] = src.flags[h];
+  }
+}
+
+__global__ void k_compact_verts(MeshView src, MeshView dst, const uint8_t* __restrict__ valive,
+                                const int* __restrict__ vmap, const int* __restrict__ fmap) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= src.nv || !valive[v]) return;
+  int w = vmap[v];
+  for (int k = 0; k < 3; k++) dst.V[3 * (int64_t)w + k] = src.V[3 * (int64_t)v + k];
+  int h = src.vh[v];
+  dst.vh[w] = 3 * fmap[h / 3] + h % 3;
+}
+
+__global__ void k_flags_or(uint8_t* __restrict__ dst, const uint8_t* __restrict__ src, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] |= src[i];
+}
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
+
+}  // namespace
+
+// ============================================================ host wrappers
+void launch_adjacency(Workspace& ws, hipStream_t s, MeshView m, int* err) {
+  int64_t nh = 3 * (int64_t)m.nf;
+  uint64_t* keys = ws.get<uint64_t>("adj.keys", nh);
+  int* vals = ws.get<int>("adj.vals", nh);
+  int* deg = ws.get<int>("adj.deg", m.nv);
+  int bits = 1;
+  while ((1ll << bits) < m.nv) bits++;
+  hipLaunchKernelGGL(k_he_keys, dim3(nblk(nh)), dim3(256), 0, s, (const int*)m.F, m.nf, m.nv, bits, keys, vals, err);
+  radix_sort_u64(ws, s, keys, vals, nh, 2 * bits);
+  fill_i32(s, m.twin, nh, -1);
+  hipLaunchKernelGGL(k_pair_twins, dim3(nblk(nh)), dim3(256), 0, s, (const uint64_t*)keys, (const int*)vals, (int)nh,
+                     (const int*)m.F, m.twin, err);
+  fill_i32(s, deg, m.nv, 0);
+  hipLaunchKernelGGL(k_vertex_he, dim3(nblk(nh)), dim3(256), 0, s, (const int*)m.F, m.nf, m.vh, deg);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_check_vertices(Workspace& ws, hipStream_t s, MeshView m, int* err) {
+  int* deg = ws.get<int>("adj.deg", m.nv);
+  hipLaunchKernelGGL(k_check_vertices, dim3(nblk(m.nv)), dim3(256), 0, s, (const int*)m.twin, (const int*)m.vh,
+                     (const int*)deg, m.nv, err);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err) {
+  hipLaunchKernelGGL(k_quadrics, dim3(nblk(m.nv)), dim3(256), 0, s, m, Q, err);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
+                      uint64_t* key, int* err) {
+  hipLaunchKernelGGL(k_cost_keys, dim3(nblk(3 * (int64_t)m.nf)), dim3(256), 0, s, m, Q, w_e, w_s, demote, key, err);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, int* cand,
+                   int* ncand) {
+  int64_t nh = 3 * (int64_t)m.nf;
+  uint8_t* sel = ws.get<uint8_t>("sel", nh);
+  hipLaunchKernelGGL(k_vertex_min, dim3(nblk(m.nv)), dim3(256), 0, s, m, key, vmin);
+  hipLaunchKernelGGL(k_select, dim3(nblk(nh)), dim3(256), 0, s, m, key, (const uint64_t*)vmin, sel);
+  compact_flags(ws, s, sel, nh, cand, ncand);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_local_check(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const int* cand,
+                        const int* ncand, int cand_bound, const uint64_t* key, uint8_t* reason, double* vbar,
+                        uint64_t* ckey, int* err) {
+  hipLaunchKernelGGL(k_local_check, dim3(nblk(cand_bound)), dim3(256), 0, s, m, Q, w_e, w_s, cand, ncand, key, reason,
+                     vbar, ckey, err);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_cap(Workspace& ws, hipStream_t s, const int* ncand, int nc_host, const uint64_t* ckey, uint8_t* reason,
+                int64_t need) {
+  uint64_t* k = ws.get<uint64_t>("cap.keys", nc_host);
+  int* idx = ws.get<int>("cap.idx", nc_host);
+  uint64_t* thr = ws.get<uint64_t>("cap.thr", 1);
+  hipLaunchKernelGGL(k_pass_keys, dim3(nblk(nc_host)), dim3(256), 0, s, ncand, ckey, (const uint8_t*)reason, k, idx);
+  radix_sort_u64(ws, s, k, idx, nc_host, 64);
+  hipLaunchKernelGGL(k_pick, dim3(1), dim3(1), 0, s, (const uint64_t*)k, need - 1, thr);
+  hipLaunchKernelGGL(k_cap, dim3(nblk(nc_host)), dim3(256), 0, s, ncand, ckey, (const uint64_t*)thr, reason);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_face_boxes(hipStream_t s, MeshView m, float* box) {
+  hipLaunchKernelGGL(k_face_boxes, dim3(nblk(m.nf)), dim3(256), 0, s, m, box);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_apply(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const uint8_t* reason,
+                  const double* vbar, double* oldpos, int* owner, uint8_t* falive, float* box) {
+  hipLaunchKernelGGL(k_apply, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, vbar, oldpos, owner,
+                     falive, box);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_undo(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const int* undone,
+                 int iter, const double* oldpos, uint8_t* falive) {
+  hipLaunchKernelGGL(k_undo, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, undone, iter, oldpos, falive);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_face_list(Workspace& ws, hipStream_t s, int nf, const int* owner, const uint8_t* falive,
+                      const int* undone, int iter, const int* order, int* list, int* count) {
+  uint8_t* pred = ws.get<uint8_t>("qpred", nf);
+  hipLaunchKernelGGL(k_changed_faces, dim3(nblk(nf)), dim3(256), 0, s, nf, owner, falive, undone, iter, order, pred);
+  if (order)
+    compact_flags_map(ws, s, pred, nf, order, list, count);
+  else
+    compact_flags(ws, s, pred, nf, list, count);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_commit(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, uint8_t* reason,
+                   const int* undone, uint8_t* valive) {
+  hipLaunchKernelGGL(k_commit, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, undone, valive);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_flags(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound,
+                  const uint8_t* reason) {
+  hipLaunchKernelGGL(k_flags, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_reason_hist(hipStream_t s, const int* ncand, int cand_bound, const uint8_t* reason, int* hist) {
+  hipLaunchKernelGGL(k_reason_hist, dim3(nblk(cand_bound)), dim3(256), 0, s, ncand, reason, hist);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_compact(Workspace& ws, hipStream_t s, MeshView src, MeshView dst, const uint8_t* falive,
+                    const uint8_t* valive, int* nf_new, int* nv_new, int* err) {
+  int* fmap = ws.get<int>("cmp.fmap", src.nf);
+  int* vmap = ws.get<int>("cmp.vmap", src.nv);
+  rank_flags(ws, s, falive, src.nf, fmap, nf_new);
+  rank_flags(ws, s, valive, src.nv, vmap, nv_new);
+  hipLaunchKernelGGL(k_compact_faces, dim3(nblk(src.nf)), dim3(256), 0, s, src, dst, falive, (const int*)fmap,
+                     (const int*)vmap, err);
+  hipLaunchKernelGGL(k_compact_verts, dim3(nblk(src.nv)), dim3(256), 0, s, src, dst, valive, (const int*)vmap,
+                     (const int*)fmap);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_flags_or(hipStream_t s, uint8_t* dst, const uint8_t* src, int64_t n) {
+  hipLaunchKernelGGL(k_flags_or, dim3(nblk(n)), dim3(256), 0, s, dst, src, n);
+  PAMO_HIP(hipGetLastError());
+}
+
+}  // namespace pamo

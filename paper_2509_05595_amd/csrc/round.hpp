@@ -1,0 +1,106 @@
+// Launch wrappers of the round kernels and the LBVH (internal).
+#pragma once
+#include "internal.hpp"
+
+// error bits raised by kernels into one device int
+#define PAMO_EBIT_INDEX 1        // vertex index out of range
+#define PAMO_EBIT_DEGENERATE 2   // a face repeats a vertex
+#define PAMO_EBIT_EDGE 4         // an edge without exactly two faces
+#define PAMO_EBIT_ORIENT 8       // the two faces of an edge run the same way
+#define PAMO_EBIT_VERTEX 16      // unused vertex, or a vertex star that is not one fan
+#define PAMO_EBIT_RING 32        // a vertex star longer than the walk guard
+#define PAMO_EBIT_STACK 64       // BVH traversal stack overflow
+#define PAMO_EBIT_DEFER 128      // deferred exact-pair list overflow
+
+namespace pamo {
+
+struct MeshView {
+  double* V;
+  int* F;
+  int* twin;
+  int* vh;
+  uint8_t* flags;
+  int nv, nf;
+};
+
+void launch_adjacency(Workspace& ws, hipStream_t s, MeshView m, int* err);
+void launch_check_vertices(Workspace& ws, hipStream_t s, MeshView m, int* err);
+void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err);
+void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
+                      uint64_t* key, int* err);
+void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, int* cand,
+                   int* ncand);
+void launch_local_check(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const int* cand,
+                        const int* ncand, int cand_bound, const uint64_t* key, uint8_t* reason, double* vbar,
+                        uint64_t* ckey, int* err);
+void launch_cap(Workspace& ws, hipStream_t s, const int* ncand, int nc_host, const uint64_t* ckey, uint8_t* reason,
+                int64_t need);
+void launch_face_boxes(hipStream_t s, MeshView m, float* box);
+void launch_apply(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const uint8_t* reason,
+                  const double* vbar, double* oldpos, int* owner, uint8_t* falive, float* box);
+void launch_undo(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const int* undone,
+                 int iter, const double* oldpos, uint8_t* falive);
+// faces changed by an applied collapse (iter = 0) or restored by the undo of
+// check iteration iter (iter >= 1), ascending
+// (in the order of `order` when given: a permutation of the faces)
+void launch_face_list(Workspace& ws, hipStream_t s, int nf, const int* owner, const uint8_t* falive,
+                      const int* undone, int iter, const int* order, int* list, int* count);
+void launch_commit(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, uint8_t* reason,
+                   const int* undone, uint8_t* valive);
+void launch_flags(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const uint8_t* reason);
+void launch_flags_or(hipStream_t s, uint8_t* dst, const uint8_t* src, int64_t n);
+void launch_reason_hist(hipStream_t s, const int* ncand, int cand_bound, const uint8_t* reason, int* hist);
+void launch_compact(Workspace& ws, hipStream_t s, MeshView src, MeshView dst, const uint8_t* falive,
+                    const uint8_t* valive, int* nf_new, int* nv_new, int* err);
+
+// ------------------------------------------------------------ LBVH
+struct __align__(16) BvhNode {
+  float4 a, b, c;  // left box (a.xyz, a.w b.xy) and right box (b.zw c.x, c.yzw): lo xyz, hi xyz
+  int4 d;          // when the children are leaves: their face ids (-1 = padding leaf)
+};
+
+// balanced implicit tree over 2^H Morton-sorted leaves: internal node k
+// (0 <= k < 2^H - 1) has children 2k+1 and 2k+2; heap index 2^H - 1 + j is leaf j
+struct Bvh {
+  BvhNode* nodes;
+  const int* sorted;  // faces in Morton order (leaf j holds sorted[j])
+  int n;              // faces
+  int H;              // depth
+};
+
+// build over the face boxes box[f] (6 floats, lo then hi), all nf faces
+Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf);
+
+enum QueryMode { QUERY_CHANGED = 0, QUERY_RESTORED = 1, QUERY_ALL_PAIRS = 2 };
+
+struct QueryArgs {
+  const double* V;
+  const int* F;
+  const uint8_t* falive;  // may be null: all alive
+  const int* owner;       // QUERY_CHANGED / QUERY_RESTORED
+  int* undone;            // marks, CAS 0 -> iter
+  int iter;
+  int* nundo;             // newly undone collapses
+  int2* defer;            // pairs the float filter could not decide
+  int* ndefer;
+  int defer_cap;
+  int2* pairs;            // QUERY_ALL_PAIRS output (t < u)
+  int* npairs;
+  int64_t pairs_cap;
+  int2* cand;             // candidate pairs collected by the traversal
+  int* ncand;
+  int cand_cap;
+  int* err;
+};
+
+// queries: qlist[0..*nq) (device count), nq_bound >= *nq for the grid size.
+// Traversal collects candidate pairs into a.cand (count a.ncand, which may
+// exceed a.cand_cap: then the caller grows the buffer and repeats).
+void launch_query(hipStream_t s, const Bvh& bvh, QueryMode mode, const int* qlist, const int* nq, int nq_bound,
+                  const QueryArgs& a);
+// the pair predicate on the collected pairs
+void launch_pairs(hipStream_t s, QueryMode mode, const QueryArgs& a);
+// settle the deferred pairs exactly
+void launch_resolve(hipStream_t s, QueryMode mode, const QueryArgs& a);
+
+}  // namespace pamo

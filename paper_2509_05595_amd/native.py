@@ -1,0 +1,241 @@
+"""Thin Python binding of libpamo.so (include/pamo.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch provides device memory and the current stream.  Importing this module
+raises if the built library is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpamo.so")
+
+PAMO_OK = 0
+PAMO_TARGET_UNREACHED = 1
+ERRORS = {-1: "ARG", -2: "NONMANIFOLD", -3: "SELF_INTERSECTING", -4: "DEGENERATE", -6: "HIP", -7: "CAPACITY"}
+
+EXPORTS = ["pamo_default_options", "pamo_create", "pamo_destroy", "pamo_set_options", "pamo_last_error",
+           "pamo_workspace_bytes", "pamo_quadrics", "pamo_select", "pamo_check", "pamo_collapse",
+           "pamo_simplify", "pamo_self_intersections", "pamo_tri_pairs", "pamo_profile_enable",
+           "pamo_profile_phases", "pamo_profile_name", "pamo_profile_read", "pamo_profile_reset"]
+
+
+class Options(C.Structure):
+    _fields_ = [("w_e", C.c_double), ("w_s", C.c_double), ("tolerance", C.c_int32),
+                ("max_rounds", C.c_int32), ("validate_input", C.c_int32), ("reserved", C.c_int32 * 5)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("rounds", C.c_int64), ("faces_out", C.c_int64), ("verts_out", C.c_int64),
+                ("candidates", C.c_int64), ("commits", C.c_int64), ("rej_link", C.c_int64),
+                ("rej_flip", C.c_int64), ("rej_isect", C.c_int64), ("capped", C.c_int64),
+                ("undo_hist", C.c_int64 * 5), ("deferred_pairs", C.c_int64), ("status", C.c_int64)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "undo_hist"}
+        d["undo_hist"] = list(self.undo_hist)
+        return d
+
+
+class PamoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pamo error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                              "python paper_2509_05595_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P, I64, I32 = C.c_void_p, C.c_int64, C.c_int32
+        L.pamo_default_options.argtypes = [C.POINTER(Options)]
+        L.pamo_default_options.restype = None
+        L.pamo_create.argtypes = [C.POINTER(P), C.c_int, P, C.POINTER(Options)]
+        L.pamo_destroy.argtypes = [P]
+        L.pamo_destroy.restype = None
+        L.pamo_set_options.argtypes = [P, C.POINTER(Options)]
+        L.pamo_last_error.argtypes = [P]
+        L.pamo_last_error.restype = C.c_char_p
+        L.pamo_workspace_bytes.argtypes = [P]
+        L.pamo_workspace_bytes.restype = I64
+        L.pamo_quadrics.argtypes = [P, P, I64, P, I64, P]
+        L.pamo_select.argtypes = [P, P, I64, P, I64, P, P, P, P, P]
+        L.pamo_check.argtypes = [P, P, I64, P, I64, P, I64, P, P, P, P, C.POINTER(I64)]
+        L.pamo_collapse.argtypes = [P, P, C.POINTER(I64), P, C.POINTER(I64), P, P, P, P, P]
+        L.pamo_simplify.argtypes = [P, P, I64, P, I64, I64, P, C.POINTER(I64), P, C.POINTER(I64),
+                                    C.POINTER(Stats)]
+        L.pamo_self_intersections.argtypes = [P, P, I64, P, I64, P, I64, C.POINTER(I64)]
+        L.pamo_tri_pairs.argtypes = [P, P, P, P, P, I64, P]
+        L.pamo_profile_enable.argtypes = [P, C.c_uint32]
+        L.pamo_profile_phases.argtypes = []
+        L.pamo_profile_name.argtypes = [I32]
+        L.pamo_profile_name.restype = C.c_char_p
+        L.pamo_profile_read.argtypes = [P, I32, C.POINTER(I64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.pamo_profile_reset.argtypes = [P]
+        for n in EXPORTS:
+            if n not in ("pamo_default_options", "pamo_destroy", "pamo_last_error", "pamo_workspace_bytes",
+                         "pamo_profile_name"):
+                getattr(L, n).restype = I32
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().pamo_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """A library context bound to one device and the current torch stream."""
+
+    def __init__(self, device=None, options: Options | None = None, stream=None):
+        dev = torch.device(device if device is not None else "cuda")
+        self.device = torch.device("cuda", dev.index if dev.index is not None else torch.cuda.current_device())
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = s
+        self._h = C.c_void_p()
+        opt = options if options is not None else default_options()
+        rc = lib().pamo_create(C.byref(self._h), self.device.index, C.c_void_p(s.cuda_stream), C.byref(opt))
+        if rc != 0:
+            raise PamoError(rc, "pamo_create failed")
+
+    def close(self):
+        if self._h:
+            lib().pamo_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=(PAMO_OK,)):
+        if rc not in allow:
+            raise PamoError(rc, lib().pamo_last_error(self._h).decode())
+        return rc
+
+    def set_options(self, options: Options):
+        self._check(lib().pamo_set_options(self._h, C.byref(options)))
+
+    def workspace_bytes(self) -> int:
+        return int(lib().pamo_workspace_bytes(self._h))
+
+    def _mesh(self, V, F):
+        assert V.is_cuda and F.is_cuda and V.device == self.device and F.device == self.device
+        assert V.dtype == torch.float64 and F.dtype == torch.int32
+        assert V.is_contiguous() and F.is_contiguous() and V.shape[-1] == 3 and F.shape[-1] == 3
+        return V, F
+
+    def quadrics(self, V, F):
+        V, F = self._mesh(V, F)
+        Q = torch.empty((V.shape[0], 10), dtype=torch.float64, device=self.device)
+        self._check(lib().pamo_quadrics(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(Q)))
+        return Q
+
+    def select(self, V, F, flags=None, demote=None):
+        """Returns (cand int32 [ncand], keys uint64-as-int64 [3 nf])."""
+        V, F = self._mesh(V, F)
+        nh = 3 * F.shape[0]
+        keys = torch.empty(nh, dtype=torch.int64, device=self.device)
+        cand = torch.empty(nh, dtype=torch.int32, device=self.device)
+        n = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self._check(lib().pamo_select(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(flags),
+                                      _ptr(demote), _ptr(keys), _ptr(cand), _ptr(n)))
+        k = int(n.item())
+        return cand[:k].clone(), keys, n
+
+    def check(self, V, F, target, cand, ncand_dev, flags=None):
+        """Returns (vbar [n,3], reason uint8 [n], undo iterations)."""
+        V, F = self._mesh(V, F)
+        n = max(1, cand.shape[0])
+        vbar = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
+        reason = torch.zeros(n, dtype=torch.uint8, device=self.device)
+        it = C.c_int64(0)
+        self._check(lib().pamo_check(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(flags), int(target),
+                                     _ptr(cand), _ptr(ncand_dev), _ptr(vbar), _ptr(reason), C.byref(it)))
+        k = cand.shape[0]
+        return vbar[:k], reason[:k], it.value
+
+    def collapse(self, V, F, cand, ncand_dev, vbar, reason, flags=None):
+        """Commit reason-0 collapses; returns (V, F, flags) (new tensors)."""
+        V, F = self._mesh(V, F)
+        V = V.clone()
+        F = F.clone()
+        fl = flags.clone() if flags is not None else torch.zeros(3 * F.shape[0], dtype=torch.uint8,
+                                                                   device=self.device)
+        nv = C.c_int64(V.shape[0])
+        nf = C.c_int64(F.shape[0])
+        self._check(lib().pamo_collapse(self._h, _ptr(V), C.byref(nv), _ptr(F), C.byref(nf), _ptr(cand),
+                                        _ptr(ncand_dev), _ptr(vbar), _ptr(reason), _ptr(fl)))
+        return V[: nv.value].clone(), F[: nf.value].clone(), fl[: 3 * nf.value].clone()
+
+    def simplify(self, V, F, target):
+        """Returns (V_out, F_out, stats dict)."""
+        V, F = self._mesh(V, F)
+        Vo = torch.empty_like(V)
+        Fo = torch.empty_like(F)
+        nv, nf, st = C.c_int64(0), C.c_int64(0), Stats()
+        self._check(lib().pamo_simplify(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], int(target), _ptr(Vo),
+                                        C.byref(nv), _ptr(Fo), C.byref(nf), C.byref(st)),
+                    allow=(PAMO_OK, PAMO_TARGET_UNREACHED))
+        return Vo[: nv.value], Fo[: nf.value], st.as_dict()
+
+    def self_intersections(self, V, F, cap=1 << 16):
+        V, F = self._mesh(V, F)
+        pairs = torch.empty((cap, 2), dtype=torch.int32, device=self.device)
+        n = C.c_int64(0)
+        self._check(lib().pamo_self_intersections(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(pairs),
+                                                  cap, C.byref(n)))
+        return pairs[: min(cap, n.value)], n.value
+
+    # ---- measurement
+    @staticmethod
+    def phase_names():
+        L = lib()
+        return [L.pamo_profile_name(i).decode() for i in range(L.pamo_profile_phases())]
+
+    def profile(self, phases=None):
+        """Enable HIP-event timing for the named phases (None: all, []: off)."""
+        names = self.phase_names()
+        if phases is None:
+            mask = (1 << len(names)) - 1
+        else:
+            mask = 0
+            for p in phases:
+                mask |= 1 << names.index(p)
+        self._check(lib().pamo_profile_enable(self._h, mask))
+        self._check(lib().pamo_profile_reset(self._h))
+
+    def profile_read(self):
+        """{phase: (launches, ms, algorithmic bytes)} for phases with launches."""
+        out = {}
+        for i, n in enumerate(self.phase_names()):
+            k, ms, b = C.c_int64(0), C.c_double(0), C.c_double(0)
+            self._check(lib().pamo_profile_read(self._h, i, C.byref(k), C.byref(ms), C.byref(b)))
+            if k.value:
+                out[n] = (k.value, ms.value, b.value)
+        return out
+
+    def tri_pairs(self, P, ip, Q, iq):
+        n = P.shape[0]
+        out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        self._check(lib().pamo_tri_pairs(self._h, _ptr(P), _ptr(ip), _ptr(Q), _ptr(iq), n, _ptr(out)))
+        return out
