@@ -12,7 +12,11 @@ Besides the throughput line the JSON carries
                 timed steps divided by their HIP-event duration, against the
                 8 TB/s HBM peak;
   cpu_baseline  the serial C oracle (the same round rule) on a bounded sample:
-                the same recipe at refinement 7 (327,680 faces) to 1%.
+                the same recipe at refinement 7 (327,680 faces) to 1%;
+  batched       the batched form: 256 meshes (noisy geodesic spheres and
+                bumpy tori, face counts log-uniform in [5k, 200k]) each to 1%
+                in one pamo_simplify_batch call, beside the same meshes run
+                one pamo_simplify call at a time (a 32-mesh sample).
 """
 from __future__ import annotations
 
@@ -41,6 +45,54 @@ def cpu_baseline():
                       f"({len(r['F'])} faces), serial C oracle, {dt:.1f} s"}
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def batched(native, torch, dev, steps, warmup, count, seq_sample):
+    """The batched form on the 256-mesh recipe: spheres and tori of log-uniform
+    face counts in [5k, 200k], each to 1%, all in one pamo_simplify_batch call
+    per step; beside it the same meshes one pamo_simplify call each (a sample)."""
+    from paper_2509_05595_amd import meshgen
+    specs = meshgen.batch_specs(count=count)
+    meshes = [meshgen.make_spec(sp) for sp in specs]
+    log(f"batch generated: {count} meshes")
+    dm = [(torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev)) for V, F in meshes]
+    targets = [len(F) // 100 for _, F in meshes]
+    nf_total = sum(len(F) for _, F in meshes)
+    ctx = native.Context(dev)
+    for _ in range(max(1, warmup)):
+        out = ctx.simplify_batch(dm, targets)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = ctx.simplify_batch(dm, targets)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    log(f"batch timed: {dt * 1e3:.1f} ms per call")
+    rounds = max(o[2]["rounds"] for o in out)
+    # one mesh at a time, on the first seq_sample meshes
+    sub = list(range(min(seq_sample, count)))
+    for i in sub[:2]:
+        ctx.simplify(dm[i][0], dm[i][1], targets[i])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in sub:
+        ctx.simplify(dm[i][0], dm[i][1], targets[i])
+    torch.cuda.synchronize()
+    dts = time.perf_counter() - t0
+    nf_sub = sum(len(meshes[i][1]) for i in sub)
+    ctx.close()
+    return {
+        "value": nf_total / dt, "unit": "input faces/s", "ms_per_step": dt * 1e3, "steps": steps,
+        "workload": f"{count} meshes (spheres and tori, log-uniform 5k-200k faces, {nf_total} faces in total) "
+                    f"-> 1% each, one pamo_simplify_batch call",
+        "rounds": rounds, "faces_out": int(sum(o[1].shape[0] for o in out)),
+        "one_at_a_time": {"value": nf_sub / dts, "unit": "input faces/s", "meshes": len(sub),
+                          "faces": nf_sub, "ms": dts * 1e3},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +101,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--refine", type=int, default=8, help="icosphere refinement level (8: 1,310,720 faces)")
     ap.add_argument("--target-frac", type=float, default=0.01)
+    ap.add_argument("--packet", type=int, default=0, help="BVH query packet size (0: library default)")
+    ap.add_argument("--resort", type=int, default=0, help="re-sort BVH leaves every n rounds (0: library default)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the method shards by mesh "
@@ -59,12 +116,13 @@ def main():
     from paper_2509_05595_amd import meshgen, native
 
     V, F = meshgen.noisy_icosphere(args.refine, 2)
+    log("mesh generated")
     nf0 = len(F)
     target = int(nf0 * args.target_frac)
     dev = torch.device("cuda:0")
     Vd = torch.from_numpy(V).to(dev)
     Fd = torch.from_numpy(F).to(dev)
-    ctx = native.Context(dev)
+    ctx = native.Context(dev, options=native.default_options(query_packet=args.packet, resort_every=args.resort))
 
     # warm-up; the last warm-up step times every phase (diagnostic breakdown)
     for i in range(max(1, args.warmup)):
@@ -85,6 +143,7 @@ def main():
     dt = time.perf_counter() - t0
     prof = ctx.profile_read()
     ctx.profile([])
+    log(f"single mesh timed: {dt / args.steps * 1e3:.2f} ms per step")
     ms_per_step = dt / args.steps * 1e3
     value = nf0 / (ms_per_step / 1e3)
     launches, kms, kbytes = prof[dominant]
@@ -121,8 +180,12 @@ def main():
     out["path_roofline"] = {"algorithmic_bytes_per_step": tot_bytes,
                             "achieved_GBs": tot_bytes / (ms_per_step / 1e3) / 1e9,
                             "frac": tot_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS}
+    if not args.no_batch:
+        ctx.close()
+        out["batched"] = batched(native, torch, dev, args.batch_steps, 1, args.batch_count, 32)
     if not args.no_cpu_baseline and args.gpus == 1:
         out["cpu_baseline"] = cpu_baseline()
+        log("cpu baseline timed")
     print(json.dumps(out), flush=True)
 
 

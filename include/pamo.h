@@ -54,7 +54,9 @@ typedef struct {
   int32_t tolerance;   /* zero-collapse rounds before giving up (paper default 4, Sec. 5.3) */
   int32_t max_rounds;  /* stop after this many rounds (< 0: no limit) */
   int32_t validate_input; /* 1: check manifoldness and self-intersections of the input first */
-  int32_t reserved[5];
+  int32_t query_packet; /* queries walking the BVH together (1,2,4,8,16,32,64; 0 = 8); a tuning knob, no effect on results */
+  int32_t resort_every; /* re-sort the BVH leaves by Morton code every this many rounds (0 = 4); a tuning knob, no effect on results */
+  int32_t reserved[3];
 } pamo_options;
 
 typedef struct {
@@ -139,6 +141,35 @@ pamo_status pamo_collapse(pamo_ctx* ctx, double* V, int64_t* nv, int32_t* F, int
 pamo_status pamo_simplify(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
                           int64_t target_faces, double* V_out, int64_t* nv_out, int32_t* F_out, int64_t* nf_out,
                           pamo_stats* stats);
+
+/* The batched form: simplify nmesh independent meshes together.  The meshes
+ * are concatenated into one set of arrays and every kernel launch of a round
+ * covers all of them, so a batch of small meshes fills the GPU the way one
+ * large mesh does (small meshes alone gain little from the parallel method,
+ * as the paper's Limitations section observes).  Each mesh receives exactly
+ * the result pamo_simplify gives it alone: the same rounds, output and
+ * statistics.
+ *   nmesh        1 .. 4096
+ *   V, F         device, the meshes concatenated: float64 [v_off[nmesh]][3]
+ *                and int32 [f_off[nmesh]][3]; F holds vertex ids local to
+ *                its mesh (0 .. nv of the mesh - 1)
+ *   v_off, f_off host int64 [nmesh + 1]: mesh m owns vertex rows
+ *                v_off[m] .. v_off[m+1]-1 and face rows f_off[m] .. f_off[m+1]-1;
+ *                v_off[0] = f_off[0] = 0; every mesh has >= 4 vertices and faces
+ *   targets      host int64 [nmesh]: face target of each mesh
+ *   V_out, F_out device, at least v_off[nmesh] / f_off[nmesh] rows: the
+ *                simplified meshes concatenated in the same order, local ids
+ *   v_out_off, f_out_off host int64 [nmesh + 1] output: where each output
+ *                mesh lies in V_out / F_out
+ *   stats        host pamo_stats [nmesh], or NULL; deferred_pairs holds the
+ *                batch total in every entry (the exact pass is shared)
+ * Returns PAMO_TARGET_UNREACHED when any mesh stopped early (its stats.status
+ * tells which), else PAMO_OK; errors as pamo_simplify, about any of the meshes.
+ * Coordinates outside [0,1]^3 stay correct but cost speed (the BVH gives each
+ * mesh the cell [0,1]^3 of its own).  Synchronises the stream. */
+pamo_status pamo_simplify_batch(pamo_ctx* ctx, int32_t nmesh, const double* V, const int64_t* v_off,
+                                const int32_t* F, const int64_t* f_off, const int64_t* targets, double* V_out,
+                                int64_t* v_out_off, int32_t* F_out, int64_t* f_out_off, pamo_stats* stats);
 
 /* ---- utilities ---- */
 

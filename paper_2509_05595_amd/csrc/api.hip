@@ -55,6 +55,8 @@ struct pamo_ctx {
   Workspace ws;
   int* hcnt = nullptr;  // pinned mirror of the device counters
   int* dcnt = nullptr;
+  int* hbt = nullptr;   // pinned mirror of the per-mesh tallies of a batch
+  size_t hbt_n = 0;
   Prof prof;
 };
 
@@ -70,6 +72,7 @@ enum {
   C_ERR = 6,
   C_NPAIRS = 7,
   C_NCANDP = 24,  // candidate pairs collected by one query pass
+  C_NORD = 25,    // length of the remapped leaf order
   C_HIST = 8,   // 8 entries: reason histogram after the local checks
   C_HIST2 = 16, // 8 entries: final reason histogram
   C_COUNT = 32
@@ -129,6 +132,11 @@ struct Scope {
 #define PAMO_CAT2(a, b) a##b
 #define PAMO_CAT(a, b) PAMO_CAT2(a, b)
 #define TIMED(ph, bytes) Scope PAMO_CAT(scope_, __LINE__)(c, ph, (double)(bytes))
+
+// add algorithmic bytes to a phase after the fact (counts known only later)
+void prof_bytes(pamo_ctx* c, int ph, double bytes) {
+  if (c->prof.mask & (1u << ph)) c->prof.acc[ph].bytes += bytes;
+}
 
 const int* readback(pamo_ctx* c) {
   PAMO_HIP(hipMemcpyAsync(c->hcnt, c->dcnt, C_COUNT * sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -203,6 +211,7 @@ struct RoundBufs {
   int* qlist;
   int2* defer;
   int defer_cap;
+  int* morder;  // leaf order carried between rounds (see Driver)
 };
 
 // one query pass (traversal + pair predicate + exact resolve); grows the
@@ -216,7 +225,7 @@ const int* query_pass(pamo_ctx* c, const Bvh& bvh, QueryMode mode, const int* ql
     if (mode == QUERY_ALL_PAIRS) fill_i32(s, c->dcnt + C_NPAIRS, 1, 0);
     {
       TIMED(PH_QUERY, bytes);
-      launch_query(s, bvh, mode, qlist, nq_dev, bound, qa);
+      launch_query(s, bvh, mode, qlist, nq_dev, bound, qa, c->opt.query_packet > 0 ? c->opt.query_packet : 8);
     }
     {
       TIMED(PH_PAIRS, 0);
@@ -263,39 +272,63 @@ RoundBufs round_bufs(pamo_ctx* c, int64_t nv, int64_t nf) {
   b.qlist = w.get<int>("r.qlist", nf);
   b.defer_cap = (int)std::max<int64_t>(1 << 16, nf);
   b.defer = w.get<int2>("r.defer", b.defer_cap);
+  b.morder = w.get<int>("r.morder", nf);
   return b;
 }
 
 struct RoundResult {
   int ncand = 0, npass = 0, chosen = 0, undone = 0, commits = 0, iters = 0, deferred = 0;
   int hist[8] = {0};
+  const int* leaf_order = nullptr;  // the BVH leaf order used this round (null: no BVH built)
 };
 
-// Local checks, cap, tentative apply and the check/undo fixed point on `m`
-// (modified: tentative state restored for undone collapses, applied ones
-// left applied).  reason/vbar are per candidate; undone[c] != 0 marks
-// collapses undone by the loop (reason not yet set to 3).
-void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand, const int* ncand_dev, int ncand,
-                    int64_t teff, uint8_t* reason, double* vbar, RoundResult& R) {
+// Leaf order of the BVH carried across rounds: sorting by Morton code every
+// round is replaced by the previous order, stably remapped through the
+// compaction, with a fresh sort every `resort` rounds.  Any order gives a
+// correct tree; this only affects speed.
+struct OrderState {
+  bool valid = false;
+  int age = 0;
+  int resort = 4;
+};
+
+// Local checks of the candidates (link, degeneracy, flip) and the histogram
+// of their outcome.  `bound` >= *ncand_dev sizes the grid (selected edges
+// have disjoint rings of at least two faces, so nf / 2 always bounds them).
+void local_checks(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand, const int* ncand_dev, int bound,
+                  uint8_t* reason, double* vbar) {
   hipStream_t s = c->stream;
   int* cnt = c->dcnt;
   {
-    TIMED(PH_LOCAL, 780.0 * ncand);
-    launch_local_check(s, m, b.Q, c->opt.w_e, c->opt.w_s, cand, ncand_dev, ncand, b.key, reason, vbar, b.ckey,
+    TIMED(PH_LOCAL, 0);  // bytes are added once the candidate count is known
+    launch_local_check(s, m, b.Q, c->opt.w_e, c->opt.w_s, cand, ncand_dev, bound, b.key, reason, vbar, b.ckey,
                        cnt + C_ERR);
   }
   fill_i32(s, cnt + C_HIST, 8, 0);
-  launch_reason_hist(s, ncand_dev, ncand, reason, cnt + C_HIST);
-  const int* h = readback(c);
-  check_err_bits(h[C_ERR]);
-  R.npass = h[C_HIST + 0];
-  int64_t need = (m.nf - teff) / 2;
+  launch_reason_hist(s, ncand_dev, bound, reason, cnt + C_HIST);
+}
+
+// exact face target of a single mesh: keep the `need` smallest keys
+void cap_single(pamo_ctx* c, const RoundBufs& b, const int* ncand_dev, uint8_t* reason, int64_t teff, int nf,
+                RoundResult& R) {
+  int64_t need = (nf - teff) / 2;
   R.chosen = R.npass;
   if (R.npass > need) {
-    TIMED(PH_CAP, 8 * 16.0 * ncand);
-    launch_cap(c->ws, s, ncand_dev, ncand, b.ckey, reason, need);
+    TIMED(PH_CAP, 8 * 16.0 * R.ncand);
+    launch_cap(c->ws, c->stream, ncand_dev, R.ncand, b.ckey, reason, need);
     R.chosen = (int)need;
   }
+}
+
+// Tentative apply of the R.chosen collapses with reason 0 and the check/undo
+// fixed point on `m` (modified: undone collapses restored, applied ones left
+// applied).  undone[c] != 0 marks collapses undone by the loop (reason not yet
+// set to 3).  `order`: BVH leaf order to reuse, or null to sort.
+void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand, const int* ncand_dev, int ncand,
+                    uint8_t* reason, double* vbar, RoundResult& R, const int* order, int nmesh = 1) {
+  hipStream_t s = c->stream;
+  int* cnt = c->dcnt;
+  const int* h;
   fill_u8(s, b.falive, m.nf, 1);
   fill_i32(s, b.owner, m.nf, -1);
   fill_i32(s, b.undone, ncand, 0);
@@ -312,7 +345,7 @@ void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand
   Bvh bvh;
   {
     TIMED(PH_BVH, 216 * nf);
-    bvh = build_bvh(c->ws, s, b.box, m.nf);
+    bvh = build_bvh(c->ws, s, b.box, m.nf, order, m.fmesh, nmesh);
   }
   {
     TIMED(PH_FACELIST, 8 * nf);
@@ -329,6 +362,7 @@ void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand
   qa.defer = b.defer;
   qa.ndefer = cnt + C_NDEFER;
   qa.defer_cap = b.defer_cap;
+  qa.fmesh = m.fmesh;
   qa.err = cnt + C_ERR;
   init_pair_buffer(c, qa, m.nf);
   fill_i32(s, cnt + C_NUNDO, 2, 0);
@@ -354,6 +388,7 @@ void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand
     R.deferred += h[C_NDEFER];
   }
   R.commits = R.chosen - R.undone;
+  R.leaf_order = bvh.sorted;
 }
 
 void add_stats(pamo_stats* st, const RoundResult& R) {
@@ -370,7 +405,7 @@ void add_stats(pamo_stats* st, const RoundResult& R) {
 
 // One full round on `cur`.  When collapses are committed, the compacted mesh
 // lands in `alt` and the two views are swapped.
-RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, int64_t teff) {
+RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, int64_t teff, OrderState& os) {
   hipStream_t s = c->stream;
   int* cnt = c->dcnt;
   RoundResult R;
@@ -382,17 +417,23 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs
   }
   {
     TIMED(PH_COST, 104 * nv + 51 * nf);
-    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, b.key, cnt + C_ERR);
+    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, cnt + C_ERR);
   }
   {
     TIMED(PH_SELECT, 20 * nv + 93 * nf);
     launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
   }
+  local_checks(c, cur, b, b.cand, cnt + C_NCAND, cur.nf / 2 + 1, b.reason, b.vbar);
   const int* h = readback(c);
   check_err_bits(h[C_ERR]);
   R.ncand = h[C_NCAND];
+  R.npass = h[C_HIST + 0];
+  prof_bytes(c, PH_LOCAL, 780.0 * R.ncand);
   if (R.ncand == 0) return R;  // nothing selectable: a round without collapses
-  check_and_undo(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, teff, b.reason, b.vbar, R);
+  const bool reuse = os.valid && os.age < os.resort;
+  cap_single(c, b, cnt + C_NCAND, b.reason, teff, cur.nf, R);
+  check_and_undo(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr);
+  if (R.leaf_order) os.age = reuse ? os.age + 1 : 1;
   fill_u8(s, b.valive, cur.nv, 1);
   if (R.chosen > 0) {
     TIMED(PH_COMMIT, 100.0 * R.chosen);
@@ -410,6 +451,18 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs
   if (R.commits > 0) {
     TIMED(PH_COMPACT, 72 * nf + 66 * nv);
     launch_compact(c->ws, s, cur, alt, b.falive, b.valive, cnt + C_NF, cnt + C_NV, cnt + C_ERR);
+  }
+  if (R.leaf_order) {
+    if (R.commits > 0) {
+      // the order buffer may be the one being remapped: go through a copy
+      int* tmp = c->ws.get<int>("ord.copy", cur.nf);
+      PAMO_HIP(hipMemcpyAsync(tmp, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+      launch_remap_order(c->ws, s, tmp, cur.nf, b.falive, c->ws.get<int>("cmp.fmap", cur.nf), b.morder,
+                         cnt + C_NORD);
+    } else if (R.leaf_order != b.morder) {
+      PAMO_HIP(hipMemcpyAsync(b.morder, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+    }
+    os.valid = true;
   }
   h = readback(c);
   check_err_bits(h[C_ERR]);
@@ -435,7 +488,7 @@ __global__ void k_check_index(const int* F, int64_t n3, int nv, int* err) {
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
 
 // all intersecting pairs of the mesh m; returns their number
-int64_t whole_mesh_pairs(pamo_ctx* c, MeshView m, int2* pairs, int64_t cap) {
+int64_t whole_mesh_pairs(pamo_ctx* c, MeshView m, int2* pairs, int64_t cap, int nmesh = 1) {
   hipStream_t s = c->stream;
   int* cnt = c->dcnt;
   float* box = c->ws.get<float>("w.box", 6 * (int64_t)m.nf);
@@ -445,11 +498,12 @@ int64_t whole_mesh_pairs(pamo_ctx* c, MeshView m, int2* pairs, int64_t cap) {
   fill_i32(s, cnt, C_COUNT, 0);
   fill_i32(s, cnt + C_NQ, 1, m.nf);
   launch_face_boxes(s, m, box);
-  Bvh bvh = build_bvh(c->ws, s, box, m.nf);
+  Bvh bvh = build_bvh(c->ws, s, box, m.nf, nullptr, m.fmesh, nmesh);
   const int* ql = bvh.sorted;  // every face, in Morton order
   QueryArgs qa{};
   qa.V = m.V;
   qa.F = m.F;
+  qa.fmesh = m.fmesh;
   qa.defer = defer;
   qa.ndefer = cnt + C_NDEFER;
   qa.defer_cap = defer_cap;
@@ -505,6 +559,170 @@ int32_t read_count(pamo_ctx* c, const int32_t* dev) {
   return v;
 }
 
+
+// ------------------------------------------------------------------ batches
+// A batch is the disjoint union of its meshes in one set of arrays, with the
+// mesh of every face and vertex (fmesh, vmesh) carried through compaction.
+// Every launch of a round covers all meshes; nothing in a round crosses from
+// one mesh to another (rings are mesh-local, the BVH pair filter compares
+// mesh ids), so each mesh follows exactly the rounds it would follow alone.
+// A mesh that has stopped keeps no candidate (its edges get no key) and
+// therefore stays as it is.  Stable compaction keeps the meshes contiguous and
+// in order, so per-mesh offsets are the only bookkeeping.
+
+// per-mesh tallies on the device, one block so that one copy reads them all
+struct Batch {
+  int n = 0;
+  int* dev = nullptr;      // [T_COUNT]
+  int* need = nullptr;     // [n] collapses still needed (0 for stopped meshes)
+  uint8_t* done = nullptr; // [n]
+  int ncand_m() const { return 0; }
+  int npass_m() const { return n; }
+  int commits_m() const { return 2 * n; }
+  int undo_m() const { return 3 * n; }
+  int hist_m() const { return 4 * n; }
+  int f_off() const { return 12 * n; }
+  int v_off() const { return 13 * n + 1; }
+  int total() const { return 14 * n + 2; }
+  int* d(int o) const { return dev + o; }
+};
+
+Batch batch_bufs(pamo_ctx* c, int n) {
+  Batch B;
+  B.n = n;
+  B.dev = c->ws.get<int>("bt.dev", B.total());
+  B.need = c->ws.get<int>("bt.need", n);
+  B.done = c->ws.get<uint8_t>("bt.done", n);
+  size_t want = (size_t)B.total() + n + (n + 3) / 4;
+  if (c->hbt_n < want) {
+    if (c->hbt) PAMO_HIP(hipHostFree(c->hbt));
+    c->hbt = nullptr;
+    c->hbt_n = 0;
+    PAMO_HIP(hipHostMalloc((void**)&c->hbt, want * sizeof(int)));
+    c->hbt_n = want;
+  }
+  return B;
+}
+
+// host staging of the per-round uploads, behind the tally mirror
+int* host_need(pamo_ctx* c, const Batch& B) { return c->hbt + B.total(); }
+uint8_t* host_done(pamo_ctx* c, const Batch& B) { return (uint8_t*)(c->hbt + B.total() + B.n); }
+
+// counters and tallies in one synchronisation
+const int* readback_batch(pamo_ctx* c, const Batch& B) {
+  PAMO_HIP(hipMemcpyAsync(c->hcnt, c->dcnt, C_COUNT * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  PAMO_HIP(hipMemcpyAsync(c->hbt, B.dev, B.total() * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  PAMO_HIP(hipStreamSynchronize(c->stream));
+  if (!c->prof.pending.empty()) prof_resolve(c);
+  return c->hcnt;
+}
+
+struct MeshRun {
+  int64_t teff = 0;
+  int streak = 0;
+  bool active = false;
+  pamo_stats st{};
+};
+
+// One round over every mesh of the batch (the single-mesh round of run_round
+// with per-mesh targets, tallies, flag clearing and offsets).
+RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, const Batch& B,
+                            std::vector<MeshRun>& mr, OrderState& os) {
+  hipStream_t s = c->stream;
+  int* cnt = c->dcnt;
+  const int n = B.n;
+  RoundResult R;
+  fill_i32(s, cnt, C_COUNT, 0);
+  fill_i32(s, B.dev, B.f_off(), 0);  // tallies; the offsets stay
+  int* hneed = host_need(c, B);
+  uint8_t* hdone = host_done(c, B);
+  for (int m = 0; m < n; m++) {
+    int64_t nfm = c->hbt[B.f_off() + m + 1] - c->hbt[B.f_off() + m];
+    hneed[m] = mr[m].active ? (int)((nfm - mr[m].teff) / 2) : 0;
+    hdone[m] = mr[m].active ? 0 : 1;
+  }
+  PAMO_HIP(hipMemcpyAsync(B.need, hneed, n * sizeof(int), hipMemcpyHostToDevice, s));
+  PAMO_HIP(hipMemcpyAsync(B.done, hdone, n, hipMemcpyHostToDevice, s));
+  const double nf = cur.nf, nv = cur.nv;
+  {
+    TIMED(PH_QUADRICS, 108 * nv + 24 * nf);
+    launch_quadrics(s, cur, b.Q, cnt + C_ERR);
+  }
+  {
+    TIMED(PH_COST, 104 * nv + 51 * nf);
+    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, B.done, b.key, cnt + C_ERR);
+  }
+  {
+    TIMED(PH_SELECT, 20 * nv + 93 * nf);
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
+  }
+  const int bound = cur.nf / 2 + 1;
+  local_checks(c, cur, b, b.cand, cnt + C_NCAND, bound, b.reason, b.vbar);
+  launch_mesh_tally(s, b.cand, cnt + C_NCAND, bound, cur.fmesh, b.reason, nullptr, nullptr, B.d(B.ncand_m()),
+                    B.d(B.npass_m()), nullptr, nullptr, nullptr);
+  const int* h = readback_batch(c, B);
+  check_err_bits(h[C_ERR]);
+  R.ncand = h[C_NCAND];
+  R.npass = h[C_HIST + 0];
+  prof_bytes(c, PH_LOCAL, 780.0 * R.ncand);
+  if (R.ncand == 0) return R;
+  bool capped = false;
+  R.chosen = 0;
+  for (int m = 0; m < n; m++) {
+    int np = c->hbt[B.npass_m() + m];
+    if (np > hneed[m]) capped = true;
+    R.chosen += std::min(np, hneed[m]);
+  }
+  if (capped) {
+    TIMED(PH_CAP, 8 * 16.0 * R.ncand);
+    launch_cap_batch(c->ws, s, cnt + C_NCAND, R.ncand, b.cand, cur.fmesh, b.ckey, b.reason, B.need,
+                     B.d(B.ncand_m()), n);
+  }
+  const bool reuse = os.valid && os.age < os.resort;
+  check_and_undo(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr, n);
+  if (R.leaf_order) os.age = reuse ? os.age + 1 : 1;
+  fill_u8(s, b.valive, cur.nv, 1);
+  if (R.chosen > 0) {
+    TIMED(PH_COMMIT, 100.0 * R.chosen);
+    launch_commit(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.undone, b.valive);
+  }
+  fill_i32(s, cnt + C_HIST2, 8, 0);
+  launch_reason_hist(s, cnt + C_NCAND, R.ncand, b.reason, cnt + C_HIST2);
+  launch_mesh_tally(s, b.cand, cnt + C_NCAND, R.ncand, cur.fmesh, nullptr, b.reason, b.undone, nullptr, nullptr,
+                    B.d(B.commits_m()), B.d(B.hist_m()), B.d(B.undo_m()));
+  {
+    TIMED(PH_FLAGS, 3 * nf + 10.0 * R.ncand);
+    if (R.commits > 0) launch_flags_clear_batch(s, cur, B.d(B.commits_m()));
+    launch_flags(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason);
+  }
+  if (R.commits > 0) {
+    TIMED(PH_COMPACT, 72 * nf + 66 * nv);
+    launch_compact(c->ws, s, cur, alt, b.falive, b.valive, cnt + C_NF, cnt + C_NV, cnt + C_ERR);
+    launch_batch_offsets(c->ws, s, b.falive, cur.nf, B.d(B.f_off()), n);
+    launch_batch_offsets(c->ws, s, b.valive, cur.nv, B.d(B.v_off()), n);
+  }
+  if (R.leaf_order) {
+    if (R.commits > 0) {
+      int* tmp = c->ws.get<int>("ord.copy", cur.nf);
+      PAMO_HIP(hipMemcpyAsync(tmp, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+      launch_remap_order(c->ws, s, tmp, cur.nf, b.falive, c->ws.get<int>("cmp.fmap", cur.nf), b.morder,
+                         cnt + C_NORD);
+    } else if (R.leaf_order != b.morder) {
+      PAMO_HIP(hipMemcpyAsync(b.morder, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+    }
+    os.valid = true;
+  }
+  h = readback_batch(c, B);
+  check_err_bits(h[C_ERR]);
+  for (int i = 0; i < 8; i++) R.hist[i] = h[C_HIST2 + i];
+  if (R.commits > 0) {
+    alt.nf = h[C_NF];
+    alt.nv = h[C_NV];
+    std::swap(cur, alt);
+  }
+  return R;
+}
+
 }  // namespace
 
 // ============================================================== C ABI
@@ -551,12 +769,16 @@ void pamo_destroy(pamo_ctx* c) {
   c->ws.release();
   if (c->dcnt) (void)hipFree(c->dcnt);
   if (c->hcnt) (void)hipHostFree(c->hcnt);
+  if (c->hbt) (void)hipHostFree(c->hbt);
   delete c;
 }
 
 pamo_status pamo_set_options(pamo_ctx* c, const pamo_options* opt) {
   if (!c || !opt) return PAMO_ERR_ARG;
   if (opt->tolerance < 1) return PAMO_ERR_ARG;
+  if (opt->resort_every < 0) return PAMO_ERR_ARG;
+  int qp = opt->query_packet;
+  if (qp != 0 && qp != 1 && qp != 2 && qp != 4 && qp != 8 && qp != 16 && qp != 32 && qp != 64) return PAMO_ERR_ARG;
   c->opt = *opt;
   return PAMO_OK;
 }
@@ -587,7 +809,7 @@ pamo_status pamo_select(pamo_ctx* c, const double* V, int64_t nv, const int32_t*
     RoundBufs b = round_bufs(c, nv, nf);
     uint64_t* key = keys ? keys : b.key;
     launch_quadrics(c->stream, A, b.Q, c->dcnt + C_ERR);
-    launch_cost_keys(c->stream, A, b.Q, c->opt.w_e, c->opt.w_s, demote, key, c->dcnt + C_ERR);
+    launch_cost_keys(c->stream, A, b.Q, c->opt.w_e, c->opt.w_s, demote, nullptr, key, c->dcnt + C_ERR);
     launch_select(c->ws, c->stream, A, key, b.vmin, cand, ncand);
     check_err_bits(readback(c)[C_ERR]);
     return PAMO_OK;
@@ -611,12 +833,18 @@ pamo_status pamo_check(pamo_ctx* c, const double* V, int64_t nv, const int32_t* 
     hipStream_t s = c->stream;
     fill_i32(s, c->dcnt, C_COUNT, 0);
     launch_quadrics(s, A, b.Q, c->dcnt + C_ERR);
-    launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, b.key, c->dcnt + C_ERR);
+    launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR);
     int64_t teff = target_faces - target_faces % 2;
     if (A.nf <= teff) fail(PAMO_ERR_ARG, "the mesh is already at or below the target");
     RoundResult R;
     R.ncand = nc;
-    check_and_undo(c, A, b, cand, ncand, nc, teff, reason, vbar, R);
+    local_checks(c, A, b, cand, ncand, nc, reason, vbar);
+    const int* h = readback(c);
+    check_err_bits(h[C_ERR]);
+    R.npass = h[C_HIST + 0];
+    prof_bytes(c, PH_LOCAL, 780.0 * nc);
+    cap_single(c, b, ncand, reason, teff, A.nf, R);
+    check_and_undo(c, A, b, cand, ncand, nc, reason, vbar, R, nullptr);
     fill_u8(s, b.valive, A.nv, 1);
     if (R.chosen > 0) launch_commit(s, A, cand, ncand, nc, reason, b.undone, b.valive);
     check_err_bits(readback(c)[C_ERR]);
@@ -694,6 +922,8 @@ pamo_status pamo_simplify(pamo_ctx* c, const double* V, int64_t nv, const int32_
     int64_t teff = target_faces - target_faces % 2;
     int streak = 0;
     pamo_status status = PAMO_OK;
+    OrderState os;
+    os.resort = c->opt.resort_every > 0 ? c->opt.resort_every : 4;
     for (;;) {
       if (cur.nf <= teff) break;
       if (streak >= c->opt.tolerance) {
@@ -701,7 +931,7 @@ pamo_status pamo_simplify(pamo_ctx* c, const double* V, int64_t nv, const int32_
         break;
       }
       if (c->opt.max_rounds >= 0 && st.rounds >= c->opt.max_rounds) break;
-      RoundResult R = run_round(c, cur, alt, b, teff);
+      RoundResult R = run_round(c, cur, alt, b, teff, os);
       add_stats(&st, R);
       streak = R.commits == 0 ? streak + 1 : 0;
     }
@@ -715,6 +945,115 @@ pamo_status pamo_simplify(pamo_ctx* c, const double* V, int64_t nv, const int32_
     st.status = status;
     if (stats) *stats = st;
     return status;
+  });
+}
+
+pamo_status pamo_simplify_batch(pamo_ctx* c, int32_t nmesh, const double* V, const int64_t* v_off, const int32_t* F,
+                                const int64_t* f_off, const int64_t* targets, double* V_out, int64_t* v_out_off,
+                                int32_t* F_out, int64_t* f_out_off, pamo_stats* stats) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!V || !v_off || !F || !f_off || !targets || !V_out || !v_out_off || !F_out || !f_out_off)
+      fail(PAMO_ERR_ARG, "null pointer");
+    if (nmesh < 1 || nmesh > PAMO_MAX_MESHES) fail(PAMO_ERR_ARG, "nmesh must be in [1, 4096]");
+    if (v_off[0] != 0 || f_off[0] != 0) fail(PAMO_ERR_ARG, "offsets must start at 0");
+    for (int m = 0; m < nmesh; m++) {
+      if (v_off[m + 1] - v_off[m] < 4 || f_off[m + 1] - f_off[m] < 4)
+        fail(PAMO_ERR_ARG, "mesh " + std::to_string(m) + ": a closed mesh needs at least 4 vertices and 4 faces");
+      if (targets[m] < 0) fail(PAMO_ERR_ARG, "mesh " + std::to_string(m) + ": negative target");
+    }
+    const int64_t nv = v_off[nmesh], nf = f_off[nmesh];
+    check_sizes(nv, nf);
+    hipStream_t s = c->stream;
+    MeshView cur = mesh_bufs(c, "mA", nv, nf);
+    MeshView alt = mesh_bufs(c, "mB", nv, nf);
+    cur.fmesh = c->ws.get<int>("mA.fmesh", nf);
+    cur.vmesh = c->ws.get<int>("mA.vmesh", nv);
+    alt.fmesh = c->ws.get<int>("mB.fmesh", nf);
+    alt.vmesh = c->ws.get<int>("mB.vmesh", nv);
+    Batch B = batch_bufs(c, nmesh);
+    for (int m = 0; m <= nmesh; m++) {
+      c->hbt[B.f_off() + m] = (int)f_off[m];
+      c->hbt[B.v_off() + m] = (int)v_off[m];
+    }
+    PAMO_HIP(hipMemcpyAsync(B.d(B.f_off()), c->hbt + B.f_off(), (size_t)(2 * nmesh + 2) * sizeof(int),
+                            hipMemcpyHostToDevice, s));
+    PAMO_HIP(hipMemcpyAsync(cur.V, V, 3 * (size_t)nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+    PAMO_HIP(hipMemcpyAsync(cur.F, F, 3 * (size_t)nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+    fill_i32(s, c->dcnt, C_COUNT, 0);
+    launch_batch_ids(s, B.d(B.f_off()), B.d(B.v_off()), nmesh, (int)nf, (int)nv, cur.F, cur.fmesh, cur.vmesh,
+                     c->dcnt + C_ERR);
+    fill_u8(s, cur.flags, 3 * nf, 0);
+    launch_adjacency(c->ws, s, cur, c->dcnt + C_ERR);
+    check_err_bits(readback(c)[C_ERR]);
+    launch_check_vertices(c->ws, s, cur, c->dcnt + C_ERR);
+    check_err_bits(readback(c)[C_ERR]);
+    if (c->opt.validate_input) {
+      int2* dummy = c->ws.get<int2>("w.pairs", 1);
+      if (whole_mesh_pairs(c, cur, dummy, 0, nmesh) > 0) fail(PAMO_ERR_SELF_INTERSECTING, "an input mesh intersects itself");
+    }
+    RoundBufs b = round_bufs(c, nv, nf);
+    std::vector<MeshRun> mr(nmesh);
+    for (int m = 0; m < nmesh; m++) mr[m].teff = targets[m] - targets[m] % 2;
+    int64_t deferred = 0;
+    OrderState os;
+    os.resort = c->opt.resort_every > 0 ? c->opt.resort_every : 4;
+    bool any_unreached = false;
+    for (;;) {
+      int nactive = 0;
+      for (int m = 0; m < nmesh; m++) {
+        MeshRun& r = mr[m];
+        r.active = false;
+        if (r.st.status != PAMO_OK) continue;
+        int64_t nfm = c->hbt[B.f_off() + m + 1] - c->hbt[B.f_off() + m];
+        if (nfm <= r.teff) continue;
+        if (r.streak >= c->opt.tolerance) {
+          r.st.status = PAMO_TARGET_UNREACHED;
+          any_unreached = true;
+          continue;
+        }
+        if (c->opt.max_rounds >= 0 && r.st.rounds >= c->opt.max_rounds) continue;
+        r.active = true;
+        nactive++;
+      }
+      if (nactive == 0) break;
+      RoundResult R = run_round_batch(c, cur, alt, b, B, mr, os);
+      deferred += R.deferred;
+      for (int m = 0; m < nmesh; m++) {
+        MeshRun& r = mr[m];
+        if (!r.active) continue;
+        const bool had = R.ncand > 0;  // otherwise the tallies of the round were never filled
+        int ncm = had ? c->hbt[B.ncand_m() + m] : 0;
+        int cm = had ? c->hbt[B.commits_m() + m] : 0;
+        const int* hm = c->hbt + B.hist_m() + 8 * m;
+        r.st.rounds++;
+        r.st.candidates += ncm;
+        r.st.commits += cm;
+        if (had) {
+          r.st.rej_link += hm[1];
+          r.st.rej_flip += hm[2];
+          r.st.rej_isect += hm[3];
+          r.st.capped += hm[4];
+        }
+        r.st.undo_hist[std::min(had ? c->hbt[B.undo_m() + m] : 0, 4)]++;
+        r.streak = cm == 0 ? r.streak + 1 : 0;
+      }
+    }
+    launch_batch_output(s, cur, B.d(B.f_off()), B.d(B.v_off()), B.d(B.f_off()), B.d(B.v_off()), nmesh, V_out, F_out);
+    PAMO_HIP(hipStreamSynchronize(s));
+    for (int m = 0; m <= nmesh; m++) {
+      f_out_off[m] = c->hbt[B.f_off() + m];
+      v_out_off[m] = c->hbt[B.v_off() + m];
+    }
+    if (stats) {
+      for (int m = 0; m < nmesh; m++) {
+        pamo_stats& o = stats[m];
+        o = mr[m].st;
+        o.faces_out = f_out_off[m + 1] - f_out_off[m];
+        o.verts_out = v_out_off[m + 1] - v_out_off[m];
+        o.deferred_pairs = deferred;
+      }
+    }
+    return any_unreached ? PAMO_TARGET_UNREACHED : PAMO_OK;
   });
 }
 

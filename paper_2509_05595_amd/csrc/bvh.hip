@@ -50,6 +50,27 @@ __global__ void k_morton(const float* __restrict__ box, int n, uint32_t* __restr
   id[f] = f;
 }
 
+// batches: key = (mesh, Morton code of the box centre moved back to [0,1]^3)
+__global__ void k_morton_mesh(const float* __restrict__ box, int n, const int* __restrict__ fmesh,
+                              uint64_t* __restrict__ code, int* __restrict__ id) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n) return;
+  const float* b = box + 6 * (int64_t)f;
+  int m = fmesh[f];
+  double o[3];
+  mesh_shift(m, o[0], o[1], o[2]);
+  uint32_t q[3];
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    float c = 0.5f * (b[k] + b[k + 3]) - (float)o[k];
+    c = fminf(fmaxf(c, 0.0f), 1.0f);
+    int x = (int)(c * 1024.0f);
+    q[k] = (uint32_t)(x > 1023 ? 1023 : x);
+  }
+  code[f] = ((uint64_t)m << 30) | (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+  id[f] = f;
+}
+
 struct Box {
   float lo[3], hi[3];
 };
@@ -180,6 +201,7 @@ template <int MODE>
 __device__ __forceinline__ bool leaf_candidate(const QueryArgs& a, int t, int u) {
   if (u == t) return false;
   if (a.falive && !a.falive[u]) return false;
+  if (a.fmesh && a.fmesh[u] != a.fmesh[t]) return false;  // batches: meshes never meet
   if (MODE == QUERY_ALL_PAIRS) return u > t;
   int ou = a.owner[u];
   if (MODE == QUERY_CHANGED) {
@@ -244,17 +266,44 @@ __device__ __forceinline__ float wave_max(float x) {
   return x;
 }
 
-// Wave-cooperative (packet) traversal: each wave takes 64 consecutive
-// queries of a Morton-ordered list, walks the tree once with their union box
-// (node loads are uniform across the wave), and each lane tests its own box
-// at every visited node.  Candidate pairs are staged per wave in LDS.
-template <int MODE>
+__device__ __forceinline__ bool box_hit(const float* tb, float lx, float ly, float lz, float hx, float hy, float hz) {
+  return tb[0] <= hx && lx <= tb[3] && tb[1] <= hy && ly <= tb[4] && tb[2] <= hz && lz <= tb[5];
+}
+
+// min/max over the G lanes of a packet (G a power of two <= 64)
+template <int G>
+__device__ __forceinline__ float group_min(float x) {
+#pragma unroll
+  for (int d = G / 2; d >= 1; d >>= 1) x = fminf(x, __shfl_xor(x, d, 64));
+  return x;
+}
+template <int G>
+__device__ __forceinline__ float group_max(float x) {
+#pragma unroll
+  for (int d = G / 2; d >= 1; d >>= 1) x = fmaxf(x, __shfl_xor(x, d, 64));
+  return x;
+}
+
+// Wave-cooperative traversal in packets of G lanes.  The query list is in
+// Morton order, so the G queries of a packet are neighbours; each packet walks
+// the tree once (its lanes load the same node: one coalesced request), entering
+// a child when any of its lanes' own boxes meets it (the packet's union box is
+// a cheap uniform pre-test).  The 64/G packets of a wave advance in lockstep,
+// each with its own stack in LDS.  At a node whose children are leaves every
+// lane tests its own box; hits are staged per wave in LDS and flushed with one
+// atomic per ~200 pairs.  The traversal does no data-dependent loads besides
+// the nodes: the state filters run in the pair kernel.
+template <int MODE, int G>
 __global__ __launch_bounds__(64 * WPB) void k_collect(const BvhNode* __restrict__ nodes, int H, int n,
                                                       const int* __restrict__ qlist, const int* __restrict__ nq,
                                                       QueryArgs a) {
+  constexpr int NG = 64 / G;
   __shared__ int2 sbuf[WPB][SEG];
-  __shared__ int sstack[WPB][STACK];
+  __shared__ int sstack[WPB][NG][STACK];
   const int w = threadIdx.x >> 6;
+  const int lane = lane_id();
+  const int grp = lane / G;
+  const unsigned long long gmask = (G == 64 ? ~0ull : (((1ull << G) - 1) << (grp * G)));
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int nqv = *nq;
   if (blockIdx.x * blockDim.x + w * 64 >= nqv || n < 2) return;  // whole wave idle
@@ -264,11 +313,14 @@ __global__ __launch_bounds__(64 * WPB) void k_collect(const BvhNode* __restrict_
   if (active) {
     Tri T;
     load_tri(a.V, a.F, t, T);
+    double o[3] = {0, 0, 0};
+    if (a.fmesh) mesh_shift(a.fmesh[t], o[0], o[1], o[2]);
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-      float lo = (float)T.lo[k], hi = (float)T.hi[k];
-      if ((double)lo > T.lo[k]) lo = nextafterf(lo, -INFINITY);
-      if ((double)hi < T.hi[k]) hi = nextafterf(hi, INFINITY);
+      double dl = T.lo[k] + o[k], dh = T.hi[k] + o[k];
+      float lo = (float)dl, hi = (float)dh;
+      if ((double)lo > dl) lo = nextafterf(lo, -INFINITY);
+      if ((double)hi < dh) hi = nextafterf(hi, INFINITY);
       tb[k] = lo;
       tb[k + 3] = hi;
     }
@@ -276,47 +328,51 @@ __global__ __launch_bounds__(64 * WPB) void k_collect(const BvhNode* __restrict_
   float ub[6];
 #pragma unroll
   for (int k = 0; k < 3; k++) {
-    ub[k] = wave_min(tb[k]);
-    ub[k + 3] = wave_max(tb[k + 3]);
+    ub[k] = group_min<G>(tb[k]);
+    ub[k + 3] = group_max<G>(tb[k + 3]);
   }
   Stage st{sbuf[w], 0};
-  int* stk = sstack[w];
-  const int64_t leaf0 = ((int64_t)1 << H) - 1;
+  int* stk = sstack[w][grp];
+  const int64_t leaf0 = ((int64_t)1 << H) - 1;  // heap index of the first leaf
+  // a packet with no active lane has an empty union box: it is done at once
+  bool done = !(ub[0] <= ub[3]);
   int sp = 0;
   int node = 0;
-  while (true) {
-    node = __builtin_amdgcn_readfirstlane(node);
-    const BvhNode nd = nodes[node];
-    // union-box test first (uniform), then the lanes' own boxes
-    bool uL = ub[0] <= nd.a.w && nd.a.x <= ub[3] && ub[1] <= nd.b.x && nd.a.y <= ub[4] && ub[2] <= nd.b.y &&
-              nd.a.z <= ub[5];
-    bool uR = ub[0] <= nd.c.y && nd.b.z <= ub[3] && ub[1] <= nd.c.z && nd.b.w <= ub[4] && ub[2] <= nd.c.w &&
-              nd.c.x <= ub[5];
-    bool oL = uL && tb[0] <= nd.a.w && nd.a.x <= tb[3] && tb[1] <= nd.b.x && nd.a.y <= tb[4] && tb[2] <= nd.b.y &&
-              nd.a.z <= tb[5];
-    bool oR = uR && tb[0] <= nd.c.y && nd.b.z <= tb[3] && tb[1] <= nd.c.z && nd.b.w <= tb[4] && tb[2] <= nd.c.w &&
-              nd.c.x <= tb[5];
-    const int cl = 2 * node + 1;
-    int next = -1;
-    if (cl >= leaf0) {  // both children are leaves
-      if (nd.d.x >= 0)
-        stage_append(st, oL && leaf_candidate<MODE>(a, t, nd.d.x), t, nd.d.x, a.cand, a.ncand, a.cand_cap);
-      if (nd.d.y >= 0)
-        stage_append(st, oR && leaf_candidate<MODE>(a, t, nd.d.y), t, nd.d.y, a.cand, a.ncand, a.cand_cap);
-    } else {
-      const bool anyL = __ballot(oL) != 0, anyR = __ballot(oR) != 0;
-      if (anyL) {
-        next = cl;
-        if (anyR) stk[sp++] = cl + 1;  // depth <= H < STACK
-      } else if (anyR) {
-        next = cl + 1;
+  while (__ballot(!done)) {
+    bool hl = false, hr = false;
+    int lf = 0, rf = 0;
+    if (!done) {
+      const BvhNode nd = nodes[node];
+      const bool uL = box_hit(ub, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y);
+      const bool uR = box_hit(ub, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w);
+      const bool oL = uL && box_hit(tb, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y);
+      const bool oR = uR && box_hit(tb, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w);
+      const int cl = 2 * node + 1;
+      int next = -1;
+      if (cl >= leaf0) {  // both children are leaves
+        lf = nd.d.x;
+        rf = nd.d.y;
+        hl = oL && lf >= 0 && lf != t;
+        hr = oR && rf >= 0 && rf != t;
+      } else {
+        const bool anyL = (__ballot(oL) & gmask) != 0, anyR = (__ballot(oR) & gmask) != 0;
+        if (anyL) {
+          next = cl;
+          if (anyR) stk[sp++] = cl + 1;  // depth <= H < STACK; every lane of the packet writes the same value
+        } else if (anyR) {
+          next = cl + 1;
+        }
       }
+      if (next < 0) {
+        if (sp == 0)
+          done = true;
+        else
+          next = stk[--sp];
+      }
+      node = next;
     }
-    if (next < 0) {
-      if (sp == 0) break;
-      next = stk[--sp];
-    }
-    node = next;
+    stage_append(st, hl, t, lf, a.cand, a.ncand, a.cand_cap);
+    stage_append(st, hr, t, rf, a.cand, a.ncand, a.cand_cap);
   }
   stage_flush(st, a.cand, a.ncand, a.cand_cap);
 }
@@ -329,6 +385,7 @@ __global__ __launch_bounds__(256) void k_pairs(QueryArgs a) {
   if (n > a.cand_cap) n = a.cand_cap;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     int2 pr = a.cand[i];
+    if (!leaf_candidate<MODE>(a, pr.x, pr.y)) continue;
     Tri T, U;
     load_tri(a.V, a.F, pr.x, T);
     load_tri(a.V, a.F, pr.y, U);
@@ -361,7 +418,8 @@ __global__ __launch_bounds__(64) void k_resolve(QueryArgs a) {
 
 }  // namespace
 
-Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf) {
+Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf, const int* order, const int* fmesh,
+              int nmesh) {
   Bvh b;
   b.n = nf;
   int H = 1;
@@ -371,10 +429,22 @@ Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf) {
   b.nodes = ws.get<BvhNode>("bvh.nodes", N0 - 1);
   b.sorted = nullptr;
   if (nf < 2) return b;
-  uint32_t* code = ws.get<uint32_t>("bvh.code", nf);
-  int* id = ws.get<int>("bvh.id", nf);
-  hipLaunchKernelGGL(k_morton, dim3(nblk(nf)), dim3(256), 0, s, box, nf, code, id);
-  radix_sort_u32(ws, s, code, id, nf, 30);
+  const int* id = order;
+  if (!order && !fmesh) {
+    uint32_t* code = ws.get<uint32_t>("bvh.code", nf);
+    int* ids = ws.get<int>("bvh.id", nf);
+    hipLaunchKernelGGL(k_morton, dim3(nblk(nf)), dim3(256), 0, s, box, nf, code, ids);
+    radix_sort_u32(ws, s, code, ids, nf, 30);
+    id = ids;
+  } else if (!order) {
+    uint64_t* code = ws.get<uint64_t>("bvh.code64", nf);
+    int* ids = ws.get<int>("bvh.id", nf);
+    int mbits = 1;
+    while ((1 << mbits) < nmesh) mbits++;
+    hipLaunchKernelGGL(k_morton_mesh, dim3(nblk(nf)), dim3(256), 0, s, box, nf, fmesh, code, ids);
+    radix_sort_u64(ws, s, code, ids, nf, 30 + mbits);
+    id = ids;
+  }
   b.sorted = id;
   Box* ta = ws.get<Box>("bvh.topA", (N0 >> LVL) + 1);
   Box* tb = ws.get<Box>("bvh.topB", (N0 >> LVL) + 1);
@@ -384,7 +454,7 @@ Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf) {
   while (l0 < H) {
     int lv = H - l0 < LVL ? H - l0 : LVL;
     int64_t blocks = N0 >> (l0 + lv);
-    hipLaunchKernelGGL(k_levels, dim3((unsigned)blocks), dim3(LVL_T), 0, s, box, (const int*)id, nf, in, out, l0,
+    hipLaunchKernelGGL(k_levels, dim3((unsigned)blocks), dim3(LVL_T), 0, s, box, id, nf, in, out, l0,
                        lv, H, b.nodes);
     in = out;
     out = out == ta ? tb : ta;
@@ -394,17 +464,32 @@ Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf) {
   return b;
 }
 
-void launch_query(hipStream_t s, const Bvh& bvh, QueryMode mode, const int* qlist, const int* nq, int nq_bound,
-                  const QueryArgs& a) {
-  if (nq_bound <= 0 || bvh.n < 2) return;
-  dim3 g(nblk(nq_bound, 64 * WPB)), t(64 * WPB);
+template <int G>
+void launch_collect_g(hipStream_t s, const Bvh& bvh, QueryMode mode, const int* qlist, const int* nq, dim3 g,
+                      const QueryArgs& a) {
+  dim3 t(64 * WPB);
+  const BvhNode* nodes = bvh.nodes;
   if (mode == QUERY_CHANGED)
-    hipLaunchKernelGGL(k_collect<QUERY_CHANGED>, g, t, 0, s, (const BvhNode*)bvh.nodes, bvh.H, bvh.n, qlist, nq, a);
+    hipLaunchKernelGGL((k_collect<QUERY_CHANGED, G>), g, t, 0, s, nodes, bvh.H, bvh.n, qlist, nq, a);
   else if (mode == QUERY_RESTORED)
-    hipLaunchKernelGGL(k_collect<QUERY_RESTORED>, g, t, 0, s, (const BvhNode*)bvh.nodes, bvh.H, bvh.n, qlist, nq, a);
+    hipLaunchKernelGGL((k_collect<QUERY_RESTORED, G>), g, t, 0, s, nodes, bvh.H, bvh.n, qlist, nq, a);
   else
-    hipLaunchKernelGGL(k_collect<QUERY_ALL_PAIRS>, g, t, 0, s, (const BvhNode*)bvh.nodes, bvh.H, bvh.n, qlist, nq,
-                       a);
+    hipLaunchKernelGGL((k_collect<QUERY_ALL_PAIRS, G>), g, t, 0, s, nodes, bvh.H, bvh.n, qlist, nq, a);
+}
+
+void launch_query(hipStream_t s, const Bvh& bvh, QueryMode mode, const int* qlist, const int* nq, int nq_bound,
+                  const QueryArgs& a, int packet) {
+  if (nq_bound <= 0 || bvh.n < 2) return;
+  dim3 g(nblk(nq_bound, 64 * WPB));
+  switch (packet) {
+    case 1: launch_collect_g<1>(s, bvh, mode, qlist, nq, g, a); break;
+    case 2: launch_collect_g<2>(s, bvh, mode, qlist, nq, g, a); break;
+    case 4: launch_collect_g<4>(s, bvh, mode, qlist, nq, g, a); break;
+    case 16: launch_collect_g<16>(s, bvh, mode, qlist, nq, g, a); break;
+    case 32: launch_collect_g<32>(s, bvh, mode, qlist, nq, g, a); break;
+    case 64: launch_collect_g<64>(s, bvh, mode, qlist, nq, g, a); break;
+    default: launch_collect_g<8>(s, bvh, mode, qlist, nq, g, a); break;
+  }
   PAMO_HIP(hipGetLastError());
 }
 

@@ -65,6 +65,8 @@ void compact_flags_map(Workspace& ws, hipStream_t s, const uint8_t* flags, int64
                        int32_t* out, int32_t* count);
 // map[i] = rank of i among nonzero flags, -1 where zero; *count = total
 void rank_flags(Workspace& ws, hipStream_t s, const uint8_t* flags, int64_t n, int32_t* map, int32_t* count);
+// exclusive prefix count of nonzero flags; *total optional
+void run_flag_scan(Workspace& ws, hipStream_t s, const uint8_t* flags, int64_t n, int32_t* out, int32_t* total);
 // exclusive prefix sum of int32, in place allowed; *total optional
 void scan_exclusive(Workspace& ws, hipStream_t s, const int32_t* in, int32_t* out, int64_t n, int32_t* total);
 // stable LSD radix sort of (key, value) pairs on the low `bits` bits; the

@@ -281,6 +281,9 @@ void compact_flags_map(Workspace& ws, hipStream_t s, const uint8_t* flags, int64
 void rank_flags(Workspace& ws, hipStream_t s, const uint8_t* flags, int64_t n, int32_t* map, int32_t* count) {
   run_scan(ws, s, FlagLoad{flags}, RankStore{map}, n, count);
 }
+void run_flag_scan(Workspace& ws, hipStream_t s, const uint8_t* flags, int64_t n, int32_t* out, int32_t* total) {
+  run_scan(ws, s, FlagLoad{flags}, ScanStore{out}, n, total);
+}
 void scan_exclusive(Workspace& ws, hipStream_t s, const int32_t* in, int32_t* out, int64_t n, int32_t* total) {
   // the tile pass reads all of a tile before writing it, so in == out is fine
   run_scan(ws, s, IntLoad{in}, ScanStore{out}, n, total);

@@ -265,14 +265,16 @@ __device__ __forceinline__ double edge_cost(const MeshView& m, const double* __r
 
 // ------------------------------------------------------------ cost + keys
 __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
-                                                   const uint8_t* __restrict__ demote, uint64_t* __restrict__ key,
+                                                   const uint8_t* __restrict__ demote,
+                                                   const uint8_t* __restrict__ mesh_done, uint64_t* __restrict__ key,
                                                    int* err) {
   int h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= 3 * m.nf) return;
   int t = m.twin[h];
   if (t < h) return;  // the smaller half-edge represents the edge
   uint64_t k = PAMO_KEY_MAX;
-  bool skip = m.flags[h] || m.flags[t] || (demote && (demote[h] || demote[t]));
+  bool skip = m.flags[h] || m.flags[t] || (demote && (demote[h] || demote[t])) ||
+              (mesh_done && mesh_done[m.fmesh[h / 3]]);
   if (!skip) {
     EdgeRing R;
     if (!edge_ring(m, h, R)) {
@@ -449,14 +451,17 @@ __device__ __forceinline__ float f_up(double x) {
   return f;
 }
 
+// float32 box of face f, rounded outward (shifted to its mesh's cell in a batch)
 __device__ __forceinline__ void face_box_f32(const MeshView& m, int f, float* b) {
   P3 p0 = ld3(m.V, m.F[3 * f]), p1 = ld3(m.V, m.F[3 * f + 1]), p2 = ld3(m.V, m.F[3 * f + 2]);
-  b[0] = f_down(fmin(fmin(p0.x, p1.x), p2.x));
-  b[1] = f_down(fmin(fmin(p0.y, p1.y), p2.y));
-  b[2] = f_down(fmin(fmin(p0.z, p1.z), p2.z));
-  b[3] = f_up(fmax(fmax(p0.x, p1.x), p2.x));
-  b[4] = f_up(fmax(fmax(p0.y, p1.y), p2.y));
-  b[5] = f_up(fmax(fmax(p0.z, p1.z), p2.z));
+  double ox = 0, oy = 0, oz = 0;
+  if (m.fmesh) mesh_shift(m.fmesh[f], ox, oy, oz);
+  b[0] = f_down(fmin(fmin(p0.x, p1.x), p2.x) + ox);
+  b[1] = f_down(fmin(fmin(p0.y, p1.y), p2.y) + oy);
+  b[2] = f_down(fmin(fmin(p0.z, p1.z), p2.z) + oz);
+  b[3] = f_up(fmax(fmax(p0.x, p1.x), p2.x) + ox);
+  b[4] = f_up(fmax(fmax(p0.y, p1.y), p2.y) + oy);
+  b[5] = f_up(fmax(fmax(p0.z, p1.z), p2.z) + oz);
 }
 
 __global__ __launch_bounds__(256) void k_face_boxes(MeshView m, float* __restrict__ box) {
@@ -626,6 +631,7 @@ __global__ void k_compact_faces(MeshView src, MeshView dst, const uint8_t* __res
     dst.twin[3 * g + k] = 3 * tf + (t >= 0 ? t % 3 : k);
     dst.flags[3 * g + k] = src.flags[h];
   }
+  if (src.fmesh) dst.fmesh[g] = src.fmesh[f];
 }
 
 __global__ void k_compact_verts(MeshView src, MeshView dst, const uint8_t* __restrict__ valive,
@@ -636,11 +642,124 @@ __global__ void k_compact_verts(MeshView src, MeshView dst, const uint8_t* __res
   for (int k = 0; k < 3; k++) dst.V[3 * (int64_t)w + k] = src.V[3 * (int64_t)v + k];
   int h = src.vh[v];
   dst.vh[w] = 3 * fmap[h / 3] + h % 3;
+  if (src.vmesh) dst.vmesh[w] = src.vmesh[v];
+}
+
+__global__ void k_remap_order(const int* __restrict__ order, int n, const uint8_t* __restrict__ falive,
+                              const int* __restrict__ fmap, int* __restrict__ tmp, uint8_t* __restrict__ pred) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int f = order[j];
+  bool keep = falive[f] != 0;
+  tmp[j] = keep ? fmap[f] : -1;
+  pred[j] = keep;
 }
 
 __global__ void k_flags_or(uint8_t* __restrict__ dst, const uint8_t* __restrict__ src, int64_t n) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) dst[i] |= src[i];
+}
+
+// ------------------------------------------------------------ batches
+__global__ void k_mesh_tally(const int* __restrict__ cand, const int* __restrict__ ncand, const int* __restrict__ fmesh,
+                             const uint8_t* __restrict__ reason_local, const uint8_t* __restrict__ reason_final,
+                             const int* __restrict__ undone, int* ncand_m, int* npass_m, int* commits_m, int* hist_m,
+                             int* undo_m) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= *ncand) return;
+  int m = fmesh[cand[c] / 3];
+  if (ncand_m) atomicAdd(&ncand_m[m], 1);
+  if (reason_local && npass_m && reason_local[c] == 0) atomicAdd(&npass_m[m], 1);
+  if (reason_final) {
+    uint8_t r = reason_final[c];
+    if (commits_m && r == 0) atomicAdd(&commits_m[m], 1);
+    if (hist_m) atomicAdd(&hist_m[8 * m + (r & 7)], 1);
+  }
+  if (undo_m && undone && undone[c]) atomicMax(&undo_m[m], undone[c]);
+}
+
+// candidates sorted by (mesh, key, index): rank inside the mesh's segment
+__global__ void k_cap_batch(const int* __restrict__ ncand, const int* __restrict__ sidx, const int* __restrict__ cand,
+                            const int* __restrict__ fmesh, const int* __restrict__ seg, const int* __restrict__ need_m,
+                            uint8_t* __restrict__ reason) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= *ncand) return;
+  int c = sidx[p];
+  int m = fmesh[cand[c] / 3];
+  if (reason[c] == 0 && p - seg[m] >= need_m[m]) reason[c] = 4;
+}
+
+// sort key of a candidate for the per-mesh cap: (mesh, cost), passing
+// candidates before the others; a stable sort keeps ascending candidate index
+// (= ascending edge id) among equal costs, as the single-mesh key does
+__global__ void k_cap_batch_keys(const int* __restrict__ ncand, const int* __restrict__ cand,
+                                 const int* __restrict__ fmesh, const uint64_t* __restrict__ ckey,
+                                 const uint8_t* __restrict__ reason, uint64_t* __restrict__ out,
+                                 int* __restrict__ idx) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= *ncand) return;
+  uint64_t cost = reason[c] == 0 ? (ckey[c] >> 32) : (1ull << 32);
+  uint64_t m = (uint64_t)fmesh[cand[c] / 3];
+  out[c] = (m << 33) | cost;
+  idx[c] = c;
+}
+
+__global__ void k_flags_clear_batch(MeshView m, const int* __restrict__ commits_m) {
+  int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= 3 * m.nf) return;
+  if (commits_m[m.fmesh[h / 3]] > 0) m.flags[h] = 0;
+}
+
+__device__ __forceinline__ int seg_of(const int* __restrict__ off, int nmesh, int i) {
+  int lo = 0, hi = nmesh - 1;  // largest m with off[m] <= i
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= i)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_batch_ids(const int* __restrict__ f_off, const int* __restrict__ v_off, int nmesh, int nf, int nv,
+                            int* __restrict__ F, int* __restrict__ fmesh, int* __restrict__ vmesh, int* err) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nf) {
+    int m = seg_of(f_off, nmesh, i);
+    fmesh[i] = m;
+    int o = v_off[m], nvm = v_off[m + 1] - o;
+    for (int k = 0; k < 3; k++) {
+      int l = F[3 * i + k];
+      if (l < 0 || l >= nvm) atomicOr(err, PAMO_EBIT_INDEX);
+      F[3 * i + k] = l + o;
+    }
+  }
+  if (i < nv) vmesh[i] = seg_of(v_off, nmesh, i);
+}
+
+__global__ void k_batch_offsets(const int* __restrict__ excl, const int* __restrict__ total, int* __restrict__ off,
+                                int nmesh, int n) {
+  int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m > nmesh) return;
+  int o = off[m];
+  off[m] = o >= n ? *total : excl[o];
+}
+
+__global__ void k_batch_output(MeshView mv, const int* __restrict__ f_off, const int* __restrict__ v_off,
+                               const int* __restrict__ f_out_off, const int* __restrict__ v_out_off, int nmesh,
+                               double* __restrict__ V_out, int* __restrict__ F_out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < mv.nf) {
+    int m = mv.fmesh[i];
+    int lf = i - f_off[m];
+    for (int k = 0; k < 3; k++) F_out[3 * (int64_t)(f_out_off[m] + lf) + k] = mv.F[3 * i + k] - v_off[m];
+  }
+  if (i < mv.nv) {
+    int m = mv.vmesh[i];
+    int lv = i - v_off[m];
+    for (int k = 0; k < 3; k++) V_out[3 * (int64_t)(v_out_off[m] + lv) + k] = mv.V[3 * (int64_t)i + k];
+  }
 }
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
@@ -678,8 +797,9 @@ void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err) {
 }
 
 void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
-                      uint64_t* key, int* err) {
-  hipLaunchKernelGGL(k_cost_keys, dim3(nblk(3 * (int64_t)m.nf)), dim3(256), 0, s, m, Q, w_e, w_s, demote, key, err);
+                      const uint8_t* mesh_done, uint64_t* key, int* err) {
+  hipLaunchKernelGGL(k_cost_keys, dim3(nblk(3 * (int64_t)m.nf)), dim3(256), 0, s, m, Q, w_e, w_s, demote, mesh_done,
+                     key, err);
   PAMO_HIP(hipGetLastError());
 }
 
@@ -769,6 +889,69 @@ void launch_compact(Workspace& ws, hipStream_t s, MeshView src, MeshView dst, co
                      (const int*)vmap, err);
   hipLaunchKernelGGL(k_compact_verts, dim3(nblk(src.nv)), dim3(256), 0, s, src, dst, valive, (const int*)vmap,
                      (const int*)fmap);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_remap_order(Workspace& ws, hipStream_t s, const int* order, int nf_old, const uint8_t* falive,
+                        const int* fmap, int* out, int* count) {
+  int* tmp = ws.get<int>("ord.tmp", nf_old);
+  uint8_t* pred = ws.get<uint8_t>("ord.pred", nf_old);
+  hipLaunchKernelGGL(k_remap_order, dim3(nblk(nf_old)), dim3(256), 0, s, order, nf_old, falive, fmap, tmp, pred);
+  compact_flags_map(ws, s, pred, nf_old, tmp, out, count);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_mesh_tally(hipStream_t s, const int* cand, const int* ncand, int bound, const int* fmesh,
+                       const uint8_t* reason_local, const uint8_t* reason_final, const int* undone, int* ncand_m,
+                       int* npass_m, int* commits_m, int* hist_m, int* undo_m) {
+  hipLaunchKernelGGL(k_mesh_tally, dim3(nblk(bound)), dim3(256), 0, s, cand, ncand, fmesh, reason_local, reason_final,
+                     undone, ncand_m, npass_m, commits_m, hist_m, undo_m);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_cap_batch(Workspace& ws, hipStream_t s, const int* ncand, int nc_host, const int* cand,
+                      const int* fmesh, const uint64_t* ckey, uint8_t* reason, const int* need_m,
+                      const int* ncand_m, int nmesh) {
+  int mbits = 1;
+  while ((1ll << mbits) < nmesh) mbits++;
+  uint64_t* k = ws.get<uint64_t>("capb.keys", nc_host);
+  int* idx = ws.get<int>("capb.idx", nc_host);
+  int* seg = ws.get<int>("capb.seg", nmesh + 1);
+  hipLaunchKernelGGL(k_cap_batch_keys, dim3(nblk(nc_host)), dim3(256), 0, s, ncand, cand, fmesh, ckey,
+                     (const uint8_t*)reason, k, idx);
+  radix_sort_u64(ws, s, k, idx, nc_host, 33 + mbits);
+  scan_exclusive(ws, s, ncand_m, seg, nmesh, nullptr);
+  hipLaunchKernelGGL(k_cap_batch, dim3(nblk(nc_host)), dim3(256), 0, s, ncand, (const int*)idx, cand, fmesh,
+                     (const int*)seg, need_m, reason);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_flags_clear_batch(hipStream_t s, MeshView m, const int* commits_m) {
+  hipLaunchKernelGGL(k_flags_clear_batch, dim3(nblk(3 * (int64_t)m.nf)), dim3(256), 0, s, m, commits_m);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_batch_ids(hipStream_t s, const int* f_off, const int* v_off, int nmesh, int nf, int nv, int* F,
+                      int* fmesh, int* vmesh, int* err) {
+  int n = nf > nv ? nf : nv;
+  hipLaunchKernelGGL(k_batch_ids, dim3(nblk(n)), dim3(256), 0, s, f_off, v_off, nmesh, nf, nv, F, fmesh, vmesh, err);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_batch_offsets(Workspace& ws, hipStream_t s, const uint8_t* alive, int n, int* off, int nmesh) {
+  int* excl = ws.get<int>("bo.excl", n);
+  int* total = ws.get<int>("bo.total", 1);
+  run_flag_scan(ws, s, alive, n, excl, total);
+  hipLaunchKernelGGL(k_batch_offsets, dim3(nblk(nmesh + 1)), dim3(256), 0, s, (const int*)excl, (const int*)total, off,
+                     nmesh, n);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_batch_output(hipStream_t s, MeshView m, const int* f_off, const int* v_off, const int* f_out_off,
+                         const int* v_out_off, int nmesh, double* V_out, int* F_out) {
+  int n = m.nf > m.nv ? m.nf : m.nv;
+  hipLaunchKernelGGL(k_batch_output, dim3(nblk(n)), dim3(256), 0, s, m, f_off, v_off, f_out_off, v_out_off, nmesh,
+                     V_out, F_out);
   PAMO_HIP(hipGetLastError());
 }
 

@@ -21,13 +21,25 @@ struct MeshView {
   int* vh;
   uint8_t* flags;
   int nv, nf;
+  int* fmesh = nullptr;  // batches only: mesh of each face / vertex (kept through compaction)
+  int* vmesh = nullptr;
 };
+
+// Batches keep their meshes apart in the BVH by shifting each mesh's boxes
+// to its own cell of a 16 x 16 x 16 grid of pitch 2 (meshes live in [0,1]^3).
+__host__ __device__ __forceinline__ void mesh_shift(int m, double& ox, double& oy, double& oz) {
+  ox = 2.0 * (m & 15);
+  oy = 2.0 * ((m >> 4) & 15);
+  oz = 2.0 * (m >> 8);
+}
+constexpr int PAMO_MAX_MESHES = 4096;
 
 void launch_adjacency(Workspace& ws, hipStream_t s, MeshView m, int* err);
 void launch_check_vertices(Workspace& ws, hipStream_t s, MeshView m, int* err);
 void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err);
+// mesh_done (batches, may be null): edges of finished meshes get no key
 void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
-                      uint64_t* key, int* err);
+                      const uint8_t* mesh_done, uint64_t* key, int* err);
 void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, int* cand,
                    int* ncand);
 void launch_local_check(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const int* cand,
@@ -68,8 +80,40 @@ struct Bvh {
   int H;              // depth
 };
 
-// build over the face boxes box[f] (6 floats, lo then hi), all nf faces
-Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf);
+// ------------------------------------------------------------ batches
+// per-mesh tallies of one round: candidates, passing candidates, commits,
+// final reasons, deepest undo iteration (arrays of nmesh, cleared by caller)
+void launch_mesh_tally(hipStream_t s, const int* cand, const int* ncand, int bound, const int* fmesh,
+                       const uint8_t* reason_local, const uint8_t* reason_final, const int* undone, int* ncand_m,
+                       int* npass_m, int* commits_m, int* hist_m, int* undo_m);
+// exact-target cap per mesh: keep the need[m] smallest keys among the passing
+// candidates of mesh m
+void launch_cap_batch(Workspace& ws, hipStream_t s, const int* ncand, int nc_host, const int* cand,
+                      const int* fmesh, const uint64_t* ckey, uint8_t* reason, const int* need_m,
+                      const int* ncand_m, int nmesh);
+// clear the flags of meshes that committed a collapse this round
+void launch_flags_clear_batch(hipStream_t s, MeshView m, const int* commits_m);
+// F + v_off[mesh]: local to global vertex ids (local ids outside [0, nv of
+// the mesh) raise PAMO_EBIT_INDEX); fmesh/vmesh from the offsets (nmesh + 1 each)
+void launch_batch_ids(hipStream_t s, const int* f_off, const int* v_off, int nmesh, int nf, int nv, int* F,
+                      int* fmesh, int* vmesh, int* err);
+// new per-mesh offsets after a compaction (rank of the first survivor)
+void launch_batch_offsets(Workspace& ws, hipStream_t s, const uint8_t* alive, int n, int* off, int nmesh);
+// write mesh m's output at out offsets: faces with local vertex ids
+void launch_batch_output(hipStream_t s, MeshView m, const int* f_off, const int* v_off, const int* f_out_off,
+                         const int* v_out_off, int nmesh, double* V_out, int* F_out);
+
+// build over the face boxes box[f] (6 floats, lo then hi), all nf faces.
+// `order` (may be null): a permutation of the faces to use as leaf order
+// instead of sorting by Morton code (any order gives a correct tree; a
+// near-Morton order gives a good one).
+// fmesh (batches, may be null): sort by (mesh, Morton code of the unshifted box)
+Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf, const int* order, const int* fmesh = nullptr,
+              int nmesh = 1);
+// new leaf order after a stable compaction: keep the alive faces of `order`
+// in sequence, renamed by fmap
+void launch_remap_order(Workspace& ws, hipStream_t s, const int* order, int nf_old, const uint8_t* falive,
+                        const int* fmap, int* out, int* count);
 
 enum QueryMode { QUERY_CHANGED = 0, QUERY_RESTORED = 1, QUERY_ALL_PAIRS = 2 };
 
@@ -90,14 +134,16 @@ struct QueryArgs {
   int2* cand;             // candidate pairs collected by the traversal
   int* ncand;
   int cand_cap;
+  const int* fmesh;       // batches: mesh of each face (query boxes are shifted like the tree's)
   int* err;
 };
 
 // queries: qlist[0..*nq) (device count), nq_bound >= *nq for the grid size.
 // Traversal collects candidate pairs into a.cand (count a.ncand, which may
 // exceed a.cand_cap: then the caller grows the buffer and repeats).
+// `packet`: queries per traversal packet (1, 2, 4, 8, 16, 32 or 64)
 void launch_query(hipStream_t s, const Bvh& bvh, QueryMode mode, const int* qlist, const int* nq, int nq_bound,
-                  const QueryArgs& a);
+                  const QueryArgs& a, int packet);
 // the pair predicate on the collected pairs
 void launch_pairs(hipStream_t s, QueryMode mode, const QueryArgs& a);
 // settle the deferred pairs exactly

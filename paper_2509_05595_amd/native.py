@@ -20,13 +20,14 @@ ERRORS = {-1: "ARG", -2: "NONMANIFOLD", -3: "SELF_INTERSECTING", -4: "DEGENERATE
 
 EXPORTS = ["pamo_default_options", "pamo_create", "pamo_destroy", "pamo_set_options", "pamo_last_error",
            "pamo_workspace_bytes", "pamo_quadrics", "pamo_select", "pamo_check", "pamo_collapse",
-           "pamo_simplify", "pamo_self_intersections", "pamo_tri_pairs", "pamo_profile_enable",
+           "pamo_simplify", "pamo_simplify_batch", "pamo_self_intersections", "pamo_tri_pairs", "pamo_profile_enable",
            "pamo_profile_phases", "pamo_profile_name", "pamo_profile_read", "pamo_profile_reset"]
 
 
 class Options(C.Structure):
     _fields_ = [("w_e", C.c_double), ("w_s", C.c_double), ("tolerance", C.c_int32),
-                ("max_rounds", C.c_int32), ("validate_input", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("max_rounds", C.c_int32), ("validate_input", C.c_int32), ("query_packet", C.c_int32),
+                ("resort_every", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Stats(C.Structure):
@@ -74,6 +75,7 @@ def lib():
         L.pamo_collapse.argtypes = [P, P, C.POINTER(I64), P, C.POINTER(I64), P, P, P, P, P]
         L.pamo_simplify.argtypes = [P, P, I64, P, I64, I64, P, C.POINTER(I64), P, C.POINTER(I64),
                                     C.POINTER(Stats)]
+        L.pamo_simplify_batch.argtypes = [P, I32, P, P, P, P, P, P, P, P, P, P]
         L.pamo_self_intersections.argtypes = [P, P, I64, P, I64, P, I64, C.POINTER(I64)]
         L.pamo_tri_pairs.argtypes = [P, P, P, P, P, I64, P]
         L.pamo_profile_enable.argtypes = [P, C.c_uint32]
@@ -197,6 +199,33 @@ class Context:
                                         C.byref(nv), _ptr(Fo), C.byref(nf), C.byref(st)),
                     allow=(PAMO_OK, PAMO_TARGET_UNREACHED))
         return Vo[: nv.value], Fo[: nf.value], st.as_dict()
+
+    def simplify_batch(self, meshes, targets):
+        """Simplify a list of (V, F) device meshes together.
+
+        Returns a list of (V_out, F_out, stats dict), one per mesh."""
+        import numpy as np
+        n = len(meshes)
+        for V, F in meshes:
+            self._mesh(V, F)
+        V = torch.cat([m[0] for m in meshes]).contiguous()
+        F = torch.cat([m[1] for m in meshes]).contiguous()
+        v_off = np.zeros(n + 1, dtype=np.int64)
+        f_off = np.zeros(n + 1, dtype=np.int64)
+        v_off[1:] = np.cumsum([m[0].shape[0] for m in meshes])
+        f_off[1:] = np.cumsum([m[1].shape[0] for m in meshes])
+        tg = np.ascontiguousarray(targets, dtype=np.int64)
+        assert tg.shape == (n,)
+        Vo = torch.empty_like(V)
+        Fo = torch.empty_like(F)
+        vo = np.zeros(n + 1, dtype=np.int64)
+        fo = np.zeros(n + 1, dtype=np.int64)
+        st = (Stats * max(n, 1))()
+        h = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+        self._check(lib().pamo_simplify_batch(self._h, n, _ptr(V), h(v_off), _ptr(F), h(f_off), h(tg), _ptr(Vo),
+                                              h(vo), _ptr(Fo), h(fo), st),
+                    allow=(PAMO_OK, PAMO_TARGET_UNREACHED))
+        return [(Vo[vo[m]:vo[m + 1]], Fo[fo[m]:fo[m + 1]], st[m].as_dict()) for m in range(n)]
 
     def self_intersections(self, V, F, cap=1 << 16):
         V, F = self._mesh(V, F)
