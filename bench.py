@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--target-frac", type=float, default=0.01)
     ap.add_argument("--packet", type=int, default=0, help="BVH query packet size (0: library default)")
     ap.add_argument("--resort", type=int, default=0, help="re-sort BVH leaves every n rounds (0: library default)")
+    ap.add_argument("--coop", type=int, default=0, help="lanes per query when few remain (0: library default, 1: off)")
+    ap.add_argument("--coop-below", type=int, default=0, help="query count below which lanes share a query")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
@@ -122,7 +124,8 @@ def main():
     dev = torch.device("cuda:0")
     Vd = torch.from_numpy(V).to(dev)
     Fd = torch.from_numpy(F).to(dev)
-    ctx = native.Context(dev, options=native.default_options(query_packet=args.packet, resort_every=args.resort))
+    ctx = native.Context(dev, options=native.default_options(query_packet=args.packet, resort_every=args.resort,
+                                                             query_coop=args.coop, coop_below=args.coop_below))
 
     # warm-up; the last warm-up step times every phase (diagnostic breakdown)
     for i in range(max(1, args.warmup)):

@@ -54,9 +54,13 @@ typedef struct {
   int32_t tolerance;   /* zero-collapse rounds before giving up (paper default 4, Sec. 5.3) */
   int32_t max_rounds;  /* stop after this many rounds (< 0: no limit) */
   int32_t validate_input; /* 1: check manifoldness and self-intersections of the input first */
-  int32_t query_packet; /* queries walking the BVH together (1,2,4,8,16,32,64; 0 = 8); a tuning knob, no effect on results */
-  int32_t resort_every; /* re-sort the BVH leaves by Morton code every this many rounds (0 = 4); a tuning knob, no effect on results */
-  int32_t reserved[3];
+  /* tuning knobs: none changes a result; 0 selects the library default */
+  int32_t query_packet; /* queries walking the BVH together, one lane each (1,2,4,8,16,32,64; default 1) */
+  int32_t resort_every; /* re-sort the BVH leaves by Morton code every this many rounds (default: never;
+                           the first round's order is carried through the compactions) */
+  int32_t query_coop;   /* lanes sharing one query when few queries remain (2,4,8,16; 1 = never; default 8) */
+  int32_t coop_below;   /* ... namely when a pass has fewer than about this many queries (default 131072) */
+  int32_t reserved[1];
 } pamo_options;
 
 typedef struct {

@@ -47,6 +47,13 @@ struct Prof {
   std::vector<hipEvent_t> pool;
 };
 
+// defaults of the tuning knobs (chosen by the autotuner on the 1.31M-face
+// workload; none of them changes a result)
+constexpr int PAMO_DEFAULT_PACKET = 1;
+constexpr int PAMO_DEFAULT_COOP = 8;
+constexpr int PAMO_DEFAULT_COOP_BELOW = 131072;
+constexpr int PAMO_DEFAULT_RESORT = 1 << 30;  // never: the first round's Morton order, carried along
+
 struct pamo_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -63,18 +70,18 @@ struct pamo_ctx {
 namespace {
 
 enum {
-  C_NCAND = 0,
-  C_NQ = 1,
-  C_NUNDO = 2,
-  C_NDEFER = 3,
-  C_NF = 4,
-  C_NV = 5,
-  C_ERR = 6,
-  C_NPAIRS = 7,
-  C_NCANDP = 24,  // candidate pairs collected by one query pass
-  C_NORD = 25,    // length of the remapped leaf order
-  C_HIST = 8,   // 8 entries: reason histogram after the local checks
-  C_HIST2 = 16, // 8 entries: final reason histogram
+  C_NCAND = 0,   // candidates selected this round
+  C_NQ = 1,      // queries of the current pass
+  C_NUNDO = 2,   // collapses newly undone by the current check pass
+  C_NDEFER = 3,  // pairs deferred to the exact predicate
+  C_NCANDP = 4,  // candidate pairs collected by one query pass
+  C_NPAIRS = 5,  // intersecting pairs (whole-mesh test)
+  C_NF = 6,      // faces / vertices after compaction
+  C_NV = 7,
+  C_HIST = 8,    // 8 entries: reason histogram after the local checks
+  C_HIST2 = 16,  // 8 entries: final reason histogram
+  C_ERR = 24,    // error bits
+  C_NORD = 25,   // length of the remapped leaf order
   C_COUNT = 32
 };
 
@@ -216,20 +223,30 @@ struct RoundBufs {
 
 // one query pass (traversal + pair predicate + exact resolve); grows the
 // candidate-pair buffer and repeats when it overflowed (marks are idempotent)
+// lanes per query for a pass of about nq_est queries (0: one lane per query)
+int coop_lanes(const pamo_ctx* c, int64_t nq_est) {
+  const int below = c->opt.coop_below > 0 ? c->opt.coop_below : PAMO_DEFAULT_COOP_BELOW;
+  if (c->opt.query_coop == 1 || nq_est >= below) return 0;
+  return c->opt.query_coop > 1 ? c->opt.query_coop : PAMO_DEFAULT_COOP;
+}
+
+// one query pass (traversal + pair predicate + exact resolve); grows the
+// candidate-pair buffer and repeats when it overflowed (marks are idempotent).
+// nq_est: about how many queries the pass has (sizes grids, picks the walk)
 const int* query_pass(pamo_ctx* c, const Bvh& bvh, QueryMode mode, const int* qlist, int* nq_dev, int bound,
-                      QueryArgs& qa, double bytes) {
+                      int64_t nq_est, QueryArgs& qa, double bytes, double vbytes) {
   hipStream_t s = c->stream;
+  const int packet = c->opt.query_packet > 0 ? c->opt.query_packet : PAMO_DEFAULT_PACKET;
+  const int coop = coop_lanes(c, nq_est);
+  fill_i32(s, c->dcnt + C_NUNDO, 4, 0);  // undone, deferred, collected, intersecting
   for (;;) {
-    fill_i32(s, c->dcnt + C_NCANDP, 1, 0);
-    fill_i32(s, c->dcnt + C_NDEFER, 1, 0);
-    if (mode == QUERY_ALL_PAIRS) fill_i32(s, c->dcnt + C_NPAIRS, 1, 0);
     {
       TIMED(PH_QUERY, bytes);
-      launch_query(s, bvh, mode, qlist, nq_dev, bound, qa, c->opt.query_packet > 0 ? c->opt.query_packet : 8);
+      launch_query(s, bvh, mode, qlist, nq_dev, bound, qa, packet, coop);
     }
     {
-      TIMED(PH_PAIRS, 0);
-      launch_pairs(s, mode, qa);
+      TIMED(PH_PAIRS, 0);  // bytes added once the pair count is known
+      launch_pairs(s, mode, qa, 16 * nq_est);
     }
     {
       TIMED(PH_RESOLVE, 0);
@@ -237,11 +254,14 @@ const int* query_pass(pamo_ctx* c, const Bvh& bvh, QueryMode mode, const int* ql
     }
     const int* h = readback(c);
     check_err_bits(h[C_ERR]);
+    const int np = std::min(h[C_NCANDP], qa.cand_cap);
+    prof_bytes(c, PH_PAIRS, 8.0 * np + vbytes);
     if (h[C_NCANDP] <= qa.cand_cap) return h;
     int64_t cap = (int64_t)h[C_NCANDP] + h[C_NCANDP] / 4 + 1024;
     if (cap > INT32_MAX / 2) fail(PAMO_ERR_CAPACITY, "too many candidate pairs");
     qa.cand = c->ws.get<int2>("q.pairs", cap);
     qa.cand_cap = (int)cap;
+    fill_i32(s, c->dcnt + C_NDEFER, 3, 0);  // repeat: marks and the undone count stand
   }
 }
 
@@ -304,8 +324,7 @@ void local_checks(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand, 
     launch_local_check(s, m, b.Q, c->opt.w_e, c->opt.w_s, cand, ncand_dev, bound, b.key, reason, vbar, b.ckey,
                        cnt + C_ERR);
   }
-  fill_i32(s, cnt + C_HIST, 8, 0);
-  launch_reason_hist(s, ncand_dev, bound, reason, cnt + C_HIST);
+  launch_reason_hist(s, ncand_dev, bound, reason, cnt + C_HIST);  // C_HIST zeroed with the round's counters
 }
 
 // exact face target of a single mesh: keep the `need` smallest keys
@@ -329,9 +348,7 @@ void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand
   hipStream_t s = c->stream;
   int* cnt = c->dcnt;
   const int* h;
-  fill_u8(s, b.falive, m.nf, 1);
-  fill_i32(s, b.owner, m.nf, -1);
-  fill_i32(s, b.undone, ncand, 0);
+  launch_check_reset(s, m.nf, b.falive, b.owner, ncand, b.undone);
   if (R.chosen == 0) return;
   const double nf = m.nf, nv = m.nv;
   {
@@ -365,9 +382,9 @@ void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand
   qa.fmesh = m.fmesh;
   qa.err = cnt + C_ERR;
   init_pair_buffer(c, qa, m.nf);
-  fill_i32(s, cnt + C_NUNDO, 2, 0);
   const double qbytes = 64 * (nf - 1) + 17 * nf + 24 * nv;  // tree + faces + alive/owner + vertices
-  h = query_pass(c, bvh, QUERY_CHANGED, b.qlist, cnt + C_NQ, m.nf, qa, qbytes);
+  const double pbytes = 17 * nf + 24 * nv;                   // pairs: faces, alive/owner, vertices (+ 8 per pair)
+  h = query_pass(c, bvh, QUERY_CHANGED, b.qlist, cnt + C_NQ, m.nf, 10ll * R.chosen, qa, qbytes, pbytes);
   int newly = h[C_NUNDO];
   R.deferred += h[C_NDEFER];
   while (newly > 0) {
@@ -381,9 +398,8 @@ void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand
       TIMED(PH_FACELIST, 8 * nf);
       launch_face_list(c->ws, s, m.nf, b.owner, b.falive, b.undone, R.iters, bvh.sorted, b.qlist, cnt + C_NQ);
     }
-    fill_i32(s, cnt + C_NUNDO, 2, 0);
     qa.iter = R.iters + 1;
-    h = query_pass(c, bvh, QUERY_RESTORED, b.qlist, cnt + C_NQ, m.nf, qa, qbytes);
+    h = query_pass(c, bvh, QUERY_RESTORED, b.qlist, cnt + C_NQ, m.nf, 10ll * newly, qa, qbytes, pbytes);
     newly = h[C_NUNDO];
     R.deferred += h[C_NDEFER];
   }
@@ -439,7 +455,6 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs
     TIMED(PH_COMMIT, 100.0 * R.chosen);
     launch_commit(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.undone, b.valive);
   }
-  fill_i32(s, cnt + C_HIST2, 8, 0);
   launch_reason_hist(s, cnt + C_NCAND, R.ncand, b.reason, cnt + C_HIST2);
   // invalid flags for the next round: this round's rejections, plus the old
   // flags when nothing was collapsed (Sec. 5.3)
@@ -512,7 +527,7 @@ int64_t whole_mesh_pairs(pamo_ctx* c, MeshView m, int2* pairs, int64_t cap, int 
   qa.pairs_cap = cap;
   qa.err = cnt + C_ERR;
   init_pair_buffer(c, qa, m.nf);
-  const int* h = query_pass(c, bvh, QUERY_ALL_PAIRS, ql, cnt + C_NQ, m.nf, qa, 0);
+  const int* h = query_pass(c, bvh, QUERY_ALL_PAIRS, ql, cnt + C_NQ, m.nf, m.nf, qa, 0, 0);
   return h[C_NPAIRS];
 }
 
@@ -686,7 +701,6 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const Rou
     TIMED(PH_COMMIT, 100.0 * R.chosen);
     launch_commit(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.undone, b.valive);
   }
-  fill_i32(s, cnt + C_HIST2, 8, 0);
   launch_reason_hist(s, cnt + C_NCAND, R.ncand, b.reason, cnt + C_HIST2);
   launch_mesh_tally(s, b.cand, cnt + C_NCAND, R.ncand, cur.fmesh, nullptr, b.reason, b.undone, nullptr, nullptr,
                     B.d(B.commits_m()), B.d(B.hist_m()), B.d(B.undo_m()));
@@ -779,6 +793,9 @@ pamo_status pamo_set_options(pamo_ctx* c, const pamo_options* opt) {
   if (opt->resort_every < 0) return PAMO_ERR_ARG;
   int qp = opt->query_packet;
   if (qp != 0 && qp != 1 && qp != 2 && qp != 4 && qp != 8 && qp != 16 && qp != 32 && qp != 64) return PAMO_ERR_ARG;
+  int qc = opt->query_coop;
+  if (qc != 0 && qc != 1 && qc != 2 && qc != 4 && qc != 8 && qc != 16) return PAMO_ERR_ARG;
+  if (opt->coop_below < 0) return PAMO_ERR_ARG;
   c->opt = *opt;
   return PAMO_OK;
 }
@@ -923,7 +940,7 @@ pamo_status pamo_simplify(pamo_ctx* c, const double* V, int64_t nv, const int32_
     int streak = 0;
     pamo_status status = PAMO_OK;
     OrderState os;
-    os.resort = c->opt.resort_every > 0 ? c->opt.resort_every : 4;
+    os.resort = c->opt.resort_every > 0 ? c->opt.resort_every : PAMO_DEFAULT_RESORT;
     for (;;) {
       if (cur.nf <= teff) break;
       if (streak >= c->opt.tolerance) {
@@ -996,7 +1013,7 @@ pamo_status pamo_simplify_batch(pamo_ctx* c, int32_t nmesh, const double* V, con
     for (int m = 0; m < nmesh; m++) mr[m].teff = targets[m] - targets[m] % 2;
     int64_t deferred = 0;
     OrderState os;
-    os.resort = c->opt.resort_every > 0 ? c->opt.resort_every : 4;
+    os.resort = c->opt.resort_every > 0 ? c->opt.resort_every : PAMO_DEFAULT_RESORT;
     bool any_unreached = false;
     for (;;) {
       int nactive = 0;

@@ -23,7 +23,7 @@ namespace {
 
 constexpr int LVL = 11;  // levels reduced per launch (2048 boxes in LDS)
 constexpr int LVL_T = 256;
-constexpr int STACK = 40;
+constexpr int STACK = 32;  // >= tree depth - 1; depth <= 30 for int32 face ids
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
 
@@ -284,6 +284,23 @@ __device__ __forceinline__ float group_max(float x) {
   return x;
 }
 
+// float32 box of query face t, rounded outward, in its mesh's cell
+__device__ __forceinline__ void query_box(const QueryArgs& a, int t, float* tb) {
+  Tri T;
+  load_tri(a.V, a.F, t, T);
+  double o[3] = {0, 0, 0};
+  if (a.fmesh) mesh_shift(a.fmesh[t], o[0], o[1], o[2]);
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    double dl = T.lo[k] + o[k], dh = T.hi[k] + o[k];
+    float lo = (float)dl, hi = (float)dh;
+    if ((double)lo > dl) lo = nextafterf(lo, -INFINITY);
+    if ((double)hi < dh) hi = nextafterf(hi, INFINITY);
+    tb[k] = lo;
+    tb[k + 3] = hi;
+  }
+}
+
 // Wave-cooperative traversal in packets of G lanes.  The query list is in
 // Morton order, so the G queries of a packet are neighbours; each packet walks
 // the tree once (its lanes load the same node: one coalesced request), entering
@@ -310,21 +327,7 @@ __global__ __launch_bounds__(64 * WPB) void k_collect(const BvhNode* __restrict_
   const bool active = i < nqv;
   const int t = active ? qlist[i] : -1;
   float tb[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-  if (active) {
-    Tri T;
-    load_tri(a.V, a.F, t, T);
-    double o[3] = {0, 0, 0};
-    if (a.fmesh) mesh_shift(a.fmesh[t], o[0], o[1], o[2]);
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-      double dl = T.lo[k] + o[k], dh = T.hi[k] + o[k];
-      float lo = (float)dl, hi = (float)dh;
-      if ((double)lo > dl) lo = nextafterf(lo, -INFINITY);
-      if ((double)hi < dh) hi = nextafterf(hi, INFINITY);
-      tb[k] = lo;
-      tb[k + 3] = hi;
-    }
-  }
+  if (active) query_box(a, t, tb);
   float ub[6];
 #pragma unroll
   for (int k = 0; k < 3; k++) {
@@ -377,18 +380,99 @@ __global__ __launch_bounds__(64 * WPB) void k_collect(const BvhNode* __restrict_
   stage_flush(st, a.cand, a.ncand, a.cand_cap);
 }
 
+// Cooperative traversal: G lanes share ONE query.  The group keeps a stack of
+// pending nodes in LDS; each step its lanes pop up to G nodes (one each), load
+// them in parallel, test both children against the query box, push the
+// internal children that meet it and stage the leaf hits.  A query costs
+// about max(depth, visited nodes / G) dependent loads instead of one per
+// visited node, which matters when few queries are left (late rounds) and the
+// walk is bound by load latency rather than throughput.  Popping the top G
+// entries leaves at most G entries behind per level descended, so the stack
+// holds at most G (H + 2) entries.
+constexpr int COOP_HMAX = 24;
+
+template <int MODE, int G>
+__global__ __launch_bounds__(64 * WPB) void k_collect_coop(const BvhNode* __restrict__ nodes, int H, int n,
+                                                           const int* __restrict__ qlist, const int* __restrict__ nq,
+                                                           QueryArgs a) {
+  constexpr int NG = 64 / G;
+  constexpr int CST = G * (COOP_HMAX + 2);
+  __shared__ int2 sbuf[WPB][SEG];
+  __shared__ int sstack[WPB][NG][CST];
+  const int w = threadIdx.x >> 6;
+  const int lane = lane_id();
+  const int grp = lane / G, gl = lane % G;
+  const unsigned long long gmask = (G == 64 ? ~0ull : (((1ull << G) - 1) << (grp * G)));
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int wave_q0 = (blockIdx.x * WPB + w) * NG;
+  const int nqv = *nq;
+  if (wave_q0 >= nqv || n < 2) return;  // whole wave idle
+  const int q = wave_q0 + grp;
+  const bool active = q < nqv;
+  const int t = active ? qlist[q] : -1;
+  float tb[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  if (active) query_box(a, t, tb);
+  Stage st{sbuf[w], 0};
+  int* stk = sstack[w][grp];
+  const int64_t leaf0 = ((int64_t)1 << H) - 1;
+  if (active && gl == 0) stk[0] = 0;
+  int sp = active ? 1 : 0;  // uniform over the group
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  while (__ballot(sp > 0)) {
+    const int take = sp < G ? sp : G;
+    const int node = gl < take ? stk[sp - take + gl] : -1;
+    sp -= take;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // pops read before pushes overwrite
+    bool hl = false, hr = false, pl = false, pr = false;
+    int lf = 0, rf = 0;
+    const int cl = 2 * node + 1;
+    if (node >= 0) {
+      const BvhNode nd = nodes[node];
+      const bool oL = box_hit(tb, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y);
+      const bool oR = box_hit(tb, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w);
+      if (cl >= leaf0) {
+        lf = nd.d.x;
+        rf = nd.d.y;
+        hl = oL && lf >= 0 && lf != t;
+        hr = oR && rf >= 0 && rf != t;
+      } else {
+        pl = oL;
+        pr = oR;
+      }
+    }
+    const unsigned long long bl = __ballot(pl) & gmask, br = __ballot(pr) & gmask;
+    int pos = sp + __popcll(bl & below) + __popcll(br & below);
+    if (pl) {
+      if (pos < CST) stk[pos] = cl;
+      pos++;
+    }
+    if (pr && pos < CST) stk[pos] = cl + 1;
+    sp += __popcll(bl) + __popcll(br);
+    if (sp > CST) {  // cannot happen for H <= COOP_HMAX; report instead of losing pairs
+      if (gl == 0) atomicOr(a.err, PAMO_EBIT_STACK);
+      sp = 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    stage_append(st, hl, t, lf, a.cand, a.ncand, a.cand_cap);
+    stage_append(st, hr, t, rf, a.cand, a.ncand, a.cand_cap);
+  }
+  stage_flush(st, a.cand, a.ncand, a.cand_cap);
+}
+
 // evaluate the collected pairs: exact float64 box test, filtered predicate,
 // mark the owners of intersecting pairs, defer the undecided ones
 template <int MODE>
-__global__ __launch_bounds__(256) void k_pairs(QueryArgs a) {
+__global__ __launch_bounds__(256, 5) void k_pairs(QueryArgs a) {
   int n = *a.ncand;
   if (n > a.cand_cap) n = a.cand_cap;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     int2 pr = a.cand[i];
-    if (!leaf_candidate<MODE>(a, pr.x, pr.y)) continue;
+    // the triangles are loaded alongside the state filter rather than after
+    // it: one dependent load fewer on the path of every pair
     Tri T, U;
     load_tri(a.V, a.F, pr.x, T);
     load_tri(a.V, a.F, pr.y, U);
+    if (!leaf_candidate<MODE>(a, pr.x, pr.y)) continue;
     if (!tri_box_overlap(T, U)) continue;
     int r = tri_pair<false>(T.p, T.id, U.p, U.id);
     if (r == 1) {
@@ -477,24 +561,49 @@ void launch_collect_g(hipStream_t s, const Bvh& bvh, QueryMode mode, const int* 
     hipLaunchKernelGGL((k_collect<QUERY_ALL_PAIRS, G>), g, t, 0, s, nodes, bvh.H, bvh.n, qlist, nq, a);
 }
 
+template <int G>
+void launch_coop_g(hipStream_t s, const Bvh& bvh, QueryMode mode, const int* qlist, const int* nq, int nq_bound,
+                   const QueryArgs& a) {
+  dim3 g(nblk((int64_t)nq_bound * G, 64 * WPB)), t(64 * WPB);
+  const BvhNode* nodes = bvh.nodes;
+  if (mode == QUERY_CHANGED)
+    hipLaunchKernelGGL((k_collect_coop<QUERY_CHANGED, G>), g, t, 0, s, nodes, bvh.H, bvh.n, qlist, nq, a);
+  else if (mode == QUERY_RESTORED)
+    hipLaunchKernelGGL((k_collect_coop<QUERY_RESTORED, G>), g, t, 0, s, nodes, bvh.H, bvh.n, qlist, nq, a);
+  else
+    hipLaunchKernelGGL((k_collect_coop<QUERY_ALL_PAIRS, G>), g, t, 0, s, nodes, bvh.H, bvh.n, qlist, nq, a);
+}
+
 void launch_query(hipStream_t s, const Bvh& bvh, QueryMode mode, const int* qlist, const int* nq, int nq_bound,
-                  const QueryArgs& a, int packet) {
+                  const QueryArgs& a, int packet, int coop) {
   if (nq_bound <= 0 || bvh.n < 2) return;
+  if (bvh.H - 1 > STACK) throw std::runtime_error("BVH deeper than the traversal stack");
+  if (coop > 1 && bvh.H <= COOP_HMAX) {
+    switch (coop) {
+      case 2: launch_coop_g<2>(s, bvh, mode, qlist, nq, nq_bound, a); break;
+      case 4: launch_coop_g<4>(s, bvh, mode, qlist, nq, nq_bound, a); break;
+      case 16: launch_coop_g<16>(s, bvh, mode, qlist, nq, nq_bound, a); break;
+      default: launch_coop_g<8>(s, bvh, mode, qlist, nq, nq_bound, a); break;
+    }
+    PAMO_HIP(hipGetLastError());
+    return;
+  }
   dim3 g(nblk(nq_bound, 64 * WPB));
   switch (packet) {
-    case 1: launch_collect_g<1>(s, bvh, mode, qlist, nq, g, a); break;
     case 2: launch_collect_g<2>(s, bvh, mode, qlist, nq, g, a); break;
     case 4: launch_collect_g<4>(s, bvh, mode, qlist, nq, g, a); break;
+    case 8: launch_collect_g<8>(s, bvh, mode, qlist, nq, g, a); break;
     case 16: launch_collect_g<16>(s, bvh, mode, qlist, nq, g, a); break;
     case 32: launch_collect_g<32>(s, bvh, mode, qlist, nq, g, a); break;
     case 64: launch_collect_g<64>(s, bvh, mode, qlist, nq, g, a); break;
-    default: launch_collect_g<8>(s, bvh, mode, qlist, nq, g, a); break;
+    default: launch_collect_g<1>(s, bvh, mode, qlist, nq, g, a); break;
   }
   PAMO_HIP(hipGetLastError());
 }
 
-void launch_pairs(hipStream_t s, QueryMode mode, const QueryArgs& a) {
-  dim3 g(2048), t(256);
+void launch_pairs(hipStream_t s, QueryMode mode, const QueryArgs& a, int64_t pairs_est) {
+  int64_t b = (pairs_est + 255) / 256;
+  dim3 g((unsigned)(b < 64 ? 64 : b > 2048 ? 2048 : b)), t(256);
   if (mode == QUERY_CHANGED)
     hipLaunchKernelGGL(k_pairs<QUERY_CHANGED>, g, t, 0, s, a);
   else if (mode == QUERY_RESTORED)

@@ -279,7 +279,7 @@ PAMO_HD inline bool point_in_tri_2d(P3 x, P3 a, P3 b, P3 c, int k) {
 // closed segment pq against closed triangle abc; op, oq = orientation of p, q
 // against the plane of abc (as o3(a, b, c, .)).  Returns 0, 1 or UNK.
 template <bool EX>
-PAMO_HD __attribute__((noinline)) int seg_tri(P3 p, P3 q, P3 a, P3 b, P3 c, int op, int oq) {
+PAMO_HD __forceinline__ int seg_tri_body(P3 p, P3 q, P3 a, P3 b, P3 c, int op, int oq) {
   if (op == UNK || oq == UNK) {
     // a certain strict same side still decides
     return UNK;
@@ -302,6 +302,25 @@ PAMO_HD __attribute__((noinline)) int seg_tri(P3 p, P3 q, P3 a, P3 b, P3 c, int 
   return 1;
 }
 
+// the exact form is large and rarely reached: one out-of-line copy; the
+// filtered form is small and sits on the hot path: inlined
+template <bool EX>
+PAMO_HD __attribute__((noinline)) int seg_tri_call(P3 p, P3 q, P3 a, P3 b, P3 c, int op, int oq) {
+  return seg_tri_body<EX>(p, q, a, b, c, op, oq);
+}
+template <bool EX>
+PAMO_HD __forceinline__ int seg_tri(P3 p, P3 q, P3 a, P3 b, P3 c, int op, int oq) {
+  if (EX) return seg_tri_call<EX>(p, q, a, b, c, op, oq);
+  return seg_tri_body<EX>(p, q, a, b, c, op, oq);
+}
+
+// element i of a 3-array held in registers, without dynamic indexing
+PAMO_HD __forceinline__ double sel3d(double a, double b, double c, int i) { return i == 0 ? a : (i == 1 ? b : c); }
+PAMO_HD __forceinline__ P3 sel3(const P3* v, int i) {
+  return P3{sel3d(v[0].x, v[1].x, v[2].x, i), sel3d(v[0].y, v[1].y, v[2].y, i), sel3d(v[0].z, v[1].z, v[2].z, i)};
+}
+PAMO_HD __forceinline__ int sel3i(const int* v, int i) { return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]); }
+
 // Self-intersection predicate for two triangles with corner positions P, Q
 // and vertex ids ip, iq.  Returns 0, 1, or (EX = false only) UNK.
 template <bool EX>
@@ -323,24 +342,31 @@ PAMO_HD inline int tri_pair(const P3* P, const int* ip, const P3* Q, const int* 
       if (!pin[i]) pnot = i;
       if (!qin[i]) qnot = i;
     }
-    int o = o3<EX>(P[0], P[1], P[2], Q[qnot]);
+    int o = o3<EX>(P[0], P[1], P[2], sel3(Q, qnot));
     if (o == UNK) return UNK;
     if (o != 0) return 0;
     if (!EX) return UNK;  // unreachable: the filter never certifies a zero
     // coplanar: overlap iff the third corners lie strictly on the same side
     int k = proj_axis_exact(P[0], P[1], P[2]);
-    P3 A = P[(pnot + 1) % 3], B = P[(pnot + 2) % 3];
-    int sc = o2k<true>(A, B, P[pnot], k), sd = o2k<true>(A, B, Q[qnot], k);
+    P3 A = sel3(P, (pnot + 1) % 3), B = sel3(P, (pnot + 2) % 3);
+    int sc = o2k<true>(A, B, sel3(P, pnot), k), sd = o2k<true>(A, B, sel3(Q, qnot), k);
     return sc * sd > 0 ? 1 : 0;
   }
   if (s == 1) {
-    P3 B = P[(pa + 1) % 3], C = P[(pa + 2) % 3];
-    P3 D = Q[(qa + 1) % 3], E = Q[(qa + 2) % 3];
-    int r1 = seg_tri<EX>(B, C, Q[0], Q[1], Q[2], o3<EX>(Q[0], Q[1], Q[2], B), o3<EX>(Q[0], Q[1], Q[2], C));
-    if (r1 == 1) return 1;
-    int r2 = seg_tri<EX>(D, E, P[0], P[1], P[2], o3<EX>(P[0], P[1], P[2], D), o3<EX>(P[0], P[1], P[2], E));
-    if (r2 == 1) return 1;
-    return (r1 == UNK || r2 == UNK) ? UNK : 0;
+    // seg BC of P against Q, then seg DE of Q against P (one loop body, so
+    // one inlined copy of the segment test)
+    const P3 B = sel3(P, (pa + 1) % 3), C = sel3(P, (pa + 2) % 3);
+    const P3 D = sel3(Q, (qa + 1) % 3), E = sel3(Q, (qa + 2) % 3);
+    bool unk = false;
+#pragma unroll 1
+    for (int w = 0; w < 2; w++) {
+      const P3 p = w ? D : B, q = w ? E : C;
+      const P3 a = w ? P[0] : Q[0], b = w ? P[1] : Q[1], c = w ? P[2] : Q[2];
+      int r = seg_tri<EX>(p, q, a, b, c, o3<EX>(a, b, c, p), o3<EX>(a, b, c, q));
+      if (r == 1) return 1;
+      unk |= r == UNK;
+    }
+    return unk ? UNK : 0;
   }
   // s == 0
   int sp[3], sq[3];
@@ -349,13 +375,15 @@ PAMO_HD inline int tri_pair(const P3* P, const int* ip, const P3* Q, const int* 
   for (int j = 0; j < 3; j++) sq[j] = o3<EX>(P[0], P[1], P[2], Q[j]);
   if ((sq[0] == 1 && sq[1] == 1 && sq[2] == 1) || (sq[0] == -1 && sq[1] == -1 && sq[2] == -1)) return 0;
   bool unk = false;
-  for (int i = 0; i < 3; i++) {
-    int r = seg_tri<EX>(P[i], P[(i + 1) % 3], Q[0], Q[1], Q[2], sp[i], sp[(i + 1) % 3]);
-    if (r == 1) return 1;
-    unk |= r == UNK;
-  }
-  for (int j = 0; j < 3; j++) {
-    int r = seg_tri<EX>(Q[j], Q[(j + 1) % 3], P[0], P[1], P[2], sq[j], sq[(j + 1) % 3]);
+  // the three edges of P against Q, then the three edges of Q against P
+#pragma unroll 1
+  for (int e = 0; e < 6; e++) {
+    const bool w = e >= 3;
+    const int i = w ? e - 3 : e, i1 = i == 2 ? 0 : i + 1;
+    const P3 p = w ? sel3(Q, i) : sel3(P, i), q = w ? sel3(Q, i1) : sel3(P, i1);
+    const P3 a = w ? P[0] : Q[0], b = w ? P[1] : Q[1], c = w ? P[2] : Q[2];
+    const int op = w ? sel3i(sq, i) : sel3i(sp, i), oq = w ? sel3i(sq, i1) : sel3i(sp, i1);
+    int r = seg_tri<EX>(p, q, a, b, c, op, oq);
     if (r == 1) return 1;
     unk |= r == UNK;
   }

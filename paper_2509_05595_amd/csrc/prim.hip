@@ -135,8 +135,42 @@ __global__ __launch_bounds__(T) void k_tile_scan(Op op, St st, int64_t n, const 
   }
 }
 
+// Small inputs: the whole scan in one block and one launch (a carry walks the
+// chunks of TOP_T * TOP_ITEMS items in order).  Late rounds run on small
+// meshes, where three launches per scan cost more than the work.
+constexpr int64_t SINGLE_MAX = (int64_t)TOP_T * TOP_ITEMS;
+
+template <class Op, class St>
+__global__ __launch_bounds__(TOP_T) void k_scan_single(Op op, St st, int64_t n, int32_t* total) {
+  int carry = 0;
+  for (int64_t base0 = 0; base0 < n; base0 += (int64_t)TOP_T * TOP_ITEMS) {
+    int64_t base = base0 + (int64_t)threadIdx.x * TOP_ITEMS;
+    int v[TOP_ITEMS];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < TOP_ITEMS; i++) {
+      v[i] = base + i < n ? op.load(base + i) : 0;
+      s += v[i];
+    }
+    int tot;
+    int ex = block_excl_scan<TOP_T>(s, tot) + carry;
+#pragma unroll
+    for (int i = 0; i < TOP_ITEMS; i++) {
+      if (base + i < n) st.store(base + i, ex, v[i]);
+      ex += v[i];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
 template <class Op, class St>
 void run_scan(Workspace& ws, hipStream_t s, Op op, St st, int64_t n, int32_t* total) {
+  if (n > 0 && n <= SINGLE_MAX) {
+    hipLaunchKernelGGL((k_scan_single<Op, St>), dim3(1), dim3(TOP_T), 0, s, op, st, n, total);
+    PAMO_HIP(hipGetLastError());
+    return;
+  }
   int64_t ntiles = (n + TILE - 1) / TILE;
   if (ntiles > (int64_t)TOP_T * TOP_ITEMS) throw std::runtime_error("scan: input too large");
   if (ntiles == 0) {

@@ -660,6 +660,17 @@ __global__ void k_flags_or(uint8_t* __restrict__ dst, const uint8_t* __restrict_
   if (i < n) dst[i] |= src[i];
 }
 
+// state of a check/undo loop: every face alive and unowned, nothing undone
+__global__ void k_check_reset(int nf, uint8_t* __restrict__ falive, int* __restrict__ owner, int ncand,
+                              int* __restrict__ undone) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nf) {
+    falive[i] = 1;
+    owner[i] = -1;
+  }
+  if (i < ncand) undone[i] = 0;
+}
+
 // ------------------------------------------------------------ batches
 __global__ void k_mesh_tally(const int* __restrict__ cand, const int* __restrict__ ncand, const int* __restrict__ fmesh,
                              const uint8_t* __restrict__ reason_local, const uint8_t* __restrict__ reason_final,
@@ -898,6 +909,12 @@ void launch_remap_order(Workspace& ws, hipStream_t s, const int* order, int nf_o
   uint8_t* pred = ws.get<uint8_t>("ord.pred", nf_old);
   hipLaunchKernelGGL(k_remap_order, dim3(nblk(nf_old)), dim3(256), 0, s, order, nf_old, falive, fmap, tmp, pred);
   compact_flags_map(ws, s, pred, nf_old, tmp, out, count);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_check_reset(hipStream_t s, int nf, uint8_t* falive, int* owner, int ncand, int* undone) {
+  int n = nf > ncand ? nf : ncand;
+  hipLaunchKernelGGL(k_check_reset, dim3(nblk(n)), dim3(256), 0, s, nf, falive, owner, ncand, undone);
   PAMO_HIP(hipGetLastError());
 }
 

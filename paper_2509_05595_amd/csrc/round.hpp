@@ -48,6 +48,8 @@ void launch_local_check(hipStream_t s, MeshView m, const double* Q, double w_e, 
 void launch_cap(Workspace& ws, hipStream_t s, const int* ncand, int nc_host, const uint64_t* ckey, uint8_t* reason,
                 int64_t need);
 void launch_face_boxes(hipStream_t s, MeshView m, float* box);
+// falive[0..nf) = 1, owner[0..nf) = -1, undone[0..ncand) = 0
+void launch_check_reset(hipStream_t s, int nf, uint8_t* falive, int* owner, int ncand, int* undone);
 void launch_apply(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const uint8_t* reason,
                   const double* vbar, double* oldpos, int* owner, uint8_t* falive, float* box);
 void launch_undo(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const int* undone,
@@ -141,11 +143,13 @@ struct QueryArgs {
 // queries: qlist[0..*nq) (device count), nq_bound >= *nq for the grid size.
 // Traversal collects candidate pairs into a.cand (count a.ncand, which may
 // exceed a.cand_cap: then the caller grows the buffer and repeats).
-// `packet`: queries per traversal packet (1, 2, 4, 8, 16, 32 or 64)
+// `packet`: queries per traversal packet (1, 2, 4, 8, 16, 32 or 64), or
+// `coop` > 1: lanes sharing one query (2, 4, 8 or 16; trees up to 2^24 leaves)
 void launch_query(hipStream_t s, const Bvh& bvh, QueryMode mode, const int* qlist, const int* nq, int nq_bound,
-                  const QueryArgs& a, int packet);
-// the pair predicate on the collected pairs
-void launch_pairs(hipStream_t s, QueryMode mode, const QueryArgs& a);
+                  const QueryArgs& a, int packet, int coop);
+// the pair predicate on the collected pairs (grid sized for about pairs_est
+// pairs; the kernel strides over the device count)
+void launch_pairs(hipStream_t s, QueryMode mode, const QueryArgs& a, int64_t pairs_est);
 // settle the deferred pairs exactly
 void launch_resolve(hipStream_t s, QueryMode mode, const QueryArgs& a);
 

@@ -27,7 +27,8 @@ EXPORTS = ["pamo_default_options", "pamo_create", "pamo_destroy", "pamo_set_opti
 class Options(C.Structure):
     _fields_ = [("w_e", C.c_double), ("w_s", C.c_double), ("tolerance", C.c_int32),
                 ("max_rounds", C.c_int32), ("validate_input", C.c_int32), ("query_packet", C.c_int32),
-                ("resort_every", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("resort_every", C.c_int32), ("query_coop", C.c_int32), ("coop_below", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 class Stats(C.Structure):
