@@ -60,7 +60,9 @@ def batched(native, torch, dev, steps, warmup, count, seq_sample):
     dm = [(torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev)) for V, F in meshes]
     targets = [len(F) // 100 for _, F in meshes]
     nf_total = sum(len(F) for _, F in meshes)
-    ctx = native.Context(dev)
+    from paper_2509_05595_amd import autotune
+    tuned = autotune.options_for(nf_total, batch=True)
+    ctx = native.Context(dev, options=native.default_options(**tuned))
     for _ in range(max(1, warmup)):
         out = ctx.simplify_batch(dm, targets)
     torch.cuda.synchronize()
@@ -87,7 +89,7 @@ def batched(native, torch, dev, steps, warmup, count, seq_sample):
         "value": nf_total / dt, "unit": "input faces/s", "ms_per_step": dt * 1e3, "steps": steps,
         "workload": f"{count} meshes (spheres and tori, log-uniform 5k-200k faces, {nf_total} faces in total) "
                     f"-> 1% each, one pamo_simplify_batch call",
-        "rounds": rounds, "faces_out": int(sum(o[1].shape[0] for o in out)),
+        "rounds": rounds, "faces_out": int(sum(o[1].shape[0] for o in out)), "tuned_options": tuned,
         "one_at_a_time": {"value": nf_sub / dts, "unit": "input faces/s", "meshes": len(sub),
                           "faces": nf_sub, "ms": dts * 1e3},
     }

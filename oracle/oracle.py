@@ -47,6 +47,32 @@ class Stats(C.Structure):
                 ("capped", C.c_int64), ("undo_hist", C.c_int64 * 5), ("status", C.c_int64)]
 
 
+NFEAT = 32  # features per edge (11 used, the rest zero)
+
+
+class MLP(C.Structure):
+    """The learned proposal's network: 32 -> 64 -> 64 -> 1 (see oracle_mesh.c)."""
+    _fields_ = [("w1", (C.c_float * 32) * 64), ("b1", C.c_float * 64),
+                ("w2", (C.c_float * 64) * 64), ("b2", C.c_float * 64),
+                ("w3", C.c_float * 64), ("b3", C.c_float),
+                ("e1", C.c_int32), ("e2", C.c_int32), ("e3", C.c_int32),
+                ("a1", C.c_int32), ("a2", C.c_int32), ("threshold", C.c_float)]
+
+
+def mlp_struct(model: dict) -> MLP:
+    """model: w1 (64,32), b1 (64), w2 (64,64), b2 (64), w3 (64), b3, a1, a2, threshold."""
+    m = MLP()
+    for k in ("w1", "b1", "w2", "b2", "w3"):
+        a = np.ascontiguousarray(model[k], dtype=np.float32)
+        C.memmove(C.addressof(getattr(m, k)), a.ctypes.data, a.nbytes)
+    m.b3 = float(model["b3"])
+    m.e1, m.e2, m.e3 = (int(model[k]) for k in ("e1", "e2", "e3"))
+    m.a1 = int(model["a1"])
+    m.a2 = int(model["a2"])
+    m.threshold = float(model["threshold"])
+    return m
+
+
 class RoundLog(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "faces", "verts", "edges", "candidates", "passing", "chosen", "changed_faces",
@@ -81,11 +107,16 @@ def lib():
         L.oracle_quadric_eval.argtypes = [P, P]
         L.oracle_quadric_eval.restype = C.c_double
         L.oracle_edge_cost.argtypes = [P, I64, P, I64, C.c_int32, C.c_int32, C.c_double, C.c_double, P, P]
-        for n in ("oracle_sizeof_opts", "oracle_sizeof_stats", "oracle_sizeof_round_log"):
+        L.oracle_run_learned.argtypes = [P, I64, P, I64, I64, P, P, P, P, P, P, P, P]
+        L.oracle_collect.argtypes = [P, I64, P, I64, I64, P, P, P, I64, P, P, P, P, P, P]
+        L.oracle_features.argtypes = [P, I64, P, I64, P, I64, C.c_double, C.c_double, P, P]
+        L.oracle_mlp_logits.argtypes = [P, P, I64, P]
+        for n in ("oracle_sizeof_opts", "oracle_sizeof_stats", "oracle_sizeof_round_log", "oracle_sizeof_mlp"):
             getattr(L, n).restype = C.c_int64
         assert L.oracle_sizeof_opts() == C.sizeof(Opts)
         assert L.oracle_sizeof_stats() == C.sizeof(Stats)
         assert L.oracle_sizeof_round_log() == C.sizeof(RoundLog)
+        assert L.oracle_sizeof_mlp() == C.sizeof(MLP)
         _lib = L
     return _lib
 
@@ -253,3 +284,69 @@ def self_intersections(V, F, cap=1 << 20):
 def validate(V, F) -> int:
     V, F = _mesh(V, F)
     return int(lib().oracle_validate(_p(V), len(V), _p(F), len(F)))
+
+
+def _stats_dict(st):
+    d = {k: getattr(st, k) for k, _ in Stats._fields_ if k != "undo_hist"}
+    d["undo_hist"] = list(st.undo_hist)
+    return d
+
+
+def features(V, F, edges, w_e=W_E, w_s=W_S):
+    """Quantised features (n, 32) of the given edges (half-edge ids) and the
+    per-face overlap counts of the mesh."""
+    V, F = _mesh(V, F)
+    e = np.ascontiguousarray(edges, dtype=np.int32)
+    X = np.zeros((len(e), NFEAT), dtype=np.float32)
+    ovl = np.zeros(len(F), dtype=np.int32)
+    rc = lib().oracle_features(_p(V), len(V), _p(F), len(F), _p(e), len(e), w_e, w_s, _p(X), _p(ovl))
+    if rc:
+        raise ValueError(f"oracle_features: {rc}")
+    return X, ovl
+
+
+def mlp_logits(model, X):
+    X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, NFEAT)
+    out = np.zeros(len(X))
+    m = mlp_struct(model)
+    lib().oracle_mlp_logits(C.byref(m), _p(X), len(X), _p(out))
+    return out
+
+
+def run_learned(V, F, target, model, max_rounds=-1, w_e=W_E, w_s=W_S, tolerance=TOLERANCE):
+    """The method with the learned proposal.  Returns dict with V, F, stats,
+    demoted (candidates set aside) and fallbacks (rounds run again plain)."""
+    V, F = _mesh(V, F)
+    Vo, Fo = np.zeros_like(V), np.zeros_like(F)
+    nvo, nfo = np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64)
+    info = np.zeros(2, dtype=np.int64)
+    st = Stats()
+    opt = Opts(w_e, w_s, tolerance, max_rounds)
+    m = mlp_struct(model)
+    rc = lib().oracle_run_learned(_p(V), len(V), _p(F), len(F), int(target), C.byref(opt), C.byref(m), _p(Vo),
+                                  _p(nvo), _p(Fo), _p(nfo), C.byref(st), _p(info))
+    if rc:
+        raise ValueError(f"oracle_run_learned: {rc}")
+    nv, nf = int(nvo[0]), int(nfo[0])
+    return {"V": Vo[:nv].copy(), "F": Fo[:nf].copy(), "stats": _stats_dict(st), "demoted": int(info[0]),
+            "fallbacks": int(info[1])}
+
+
+def collect(V, F, target, cap=1 << 20, w_e=W_E, w_s=W_S, tolerance=TOLERANCE):
+    """The plain method, logging (features, committed?) of every candidate the
+    checks decided.  Returns (X (n, 32) float32, y (n,) uint8, run dict)."""
+    V, F = _mesh(V, F)
+    X = np.zeros((cap, NFEAT), dtype=np.float32)
+    y = np.zeros(cap, dtype=np.uint8)
+    n = np.zeros(1, dtype=np.int64)
+    Vo, Fo = np.zeros_like(V), np.zeros_like(F)
+    nvo, nfo = np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64)
+    st = Stats()
+    opt = Opts(w_e, w_s, tolerance, -1)
+    rc = lib().oracle_collect(_p(V), len(V), _p(F), len(F), int(target), C.byref(opt), _p(X), _p(y), cap, _p(n),
+                              _p(Vo), _p(nvo), _p(Fo), _p(nfo), C.byref(st))
+    if rc:
+        raise ValueError(f"oracle_collect: {rc}")
+    k = int(n[0])
+    return X[:k].copy(), y[:k].copy(), {"V": Vo[: int(nvo[0])].copy(), "F": Fo[: int(nfo[0])].copy(),
+                                        "stats": _stats_dict(st)}

@@ -601,6 +601,228 @@ static void query_face(const omesh *m, const ogrid *G, int64_t t, int64_t *stamp
 }
 
 /* ------------------------------------------------------------------------ */
+/* learned proposal (an addition to the method; the paper has no network)    */
+/* ------------------------------------------------------------------------ */
+/* A small network scores every selected candidate before its checks.  The
+ * ones it scores below a threshold are set aside for the round (their key
+ * becomes the largest) and the selection is redone, so that a neighbour of a
+ * likely rejection can be collapsed instead.  Every collapse still passes
+ * every check; a round that sets candidates aside and then commits nothing is
+ * run again without the network.
+ *
+ * Per-face state for the overlap feature: ovl[f] counts the alive faces that
+ * share no vertex with f and whose float64 boxes meet f's box (closed).  It is
+ * counted on the whole input, and again for each face a round changes, on the
+ * tentative mesh of that round's first check, kept when the face's collapse
+ * is committed. */
+
+#define NF_USED 11
+#define NFEAT 32
+
+typedef struct {
+    float w1[64][32]; float b1[64];   /* w1[j][k]: input k -> unit j */
+    float w2[64][64]; float b2[64];
+    float w3[64];     float b3;
+    int32_t e1, e2, e3;               /* weight grids 2^-e (checked by the library, unused here) */
+    int32_t a1, a2;                   /* activation shifts */
+    float threshold;                  /* set aside when logit < threshold */
+} oracle_mlp;
+
+/* power-of-two scale of each feature before rounding to an integer in
+ * [-127, 127] */
+static const int FEAT_SHIFT[NF_USED] = {2, 3, 7, 7, 6, 6, 2, 2, 4, 0, 2};
+
+/* piecewise-linear log2: exact at powers of two, linear in between */
+static double plog2(double c) {
+    if (!(c > 0.0)) return -64.0;
+    if (isinf(c)) return 64.0;
+    int e;
+    double mant = frexp(c, &e); /* c = mant 2^e, mant in [0.5, 1) */
+    return (double)(e - 1) + (2.0 * mant - 1.0);
+}
+
+static float quantize_feature(double f, int shift) {
+    double q = rint(ldexp(f, shift));
+    if (q != q) return 0.0f;
+    if (q > 127.0) q = 127.0;
+    if (q < -127.0) q = -127.0;
+    return (float)q;
+}
+
+static double seg_len(const double *p, const double *q) {
+    double dx = q[0] - p[0], dy = q[1] - p[1], dz = q[2] - p[2];
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+/* unnormalised normal (p1 - p0) x (p2 - p0) of face f, corners in slot order */
+static void face_normal(const omesh *m, int64_t f, double *n) {
+    const double *p0 = m->V + 3 * (int64_t)m->F[3 * f];
+    const double *p1 = m->V + 3 * (int64_t)m->F[3 * f + 1];
+    const double *p2 = m->V + 3 * (int64_t)m->F[3 * f + 2];
+    double e1x = p1[0] - p0[0], e1y = p1[1] - p0[1], e1z = p1[2] - p0[2];
+    double e2x = p2[0] - p0[0], e2y = p2[1] - p0[1], e2z = p2[2] - p0[2];
+    n[0] = e1y * e2z - e1z * e2y;
+    n[1] = e1z * e2x - e1x * e2z;
+    n[2] = e1x * e2y - e1y * e2x;
+}
+
+/* cosine of the angle between two normals (1 when either is zero) */
+static double normal_cos(const double *n0, const double *n1) {
+    double d = n0[0] * n1[0] + n0[1] * n1[1] + n0[2] * n1[2];
+    double q = (n0[0] * n0[0] + n0[1] * n0[1] + n0[2] * n0[2]) * (n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2]);
+    if (!(q > 0.0)) return 1.0;
+    return d / sqrt(q);
+}
+
+/* cosine of the angle between the normals of the two faces at the edge of
+ * half-edge h (1 where the surface is flat there) */
+static double edge_cos(const omesh *m, int64_t h) {
+    double n0[3], n1[3];
+    face_normal(m, h / 3, n0);
+    face_normal(m, m->twin[h] / 3, n1);
+    return normal_cos(n0, n1);
+}
+
+/* cost of an edge as its key stores it (float32, widened) */
+static double key_cost(uint64_t key) {
+    uint32_t k = (uint32_t)(key >> 32);
+    uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    float f;
+    memcpy(&f, &u, sizeof f);
+    return (double)f;
+}
+
+/* The features of the edge of half-edge h, quantised (NFEAT values, the
+ * unused ones zero).  S = star(a) u star(b), spokes = edges of S's faces that
+ * contain a or b.
+ *   0 plog2 of the edge cost (Eq. 1)            1 plog2 of the edge length
+ *   2 length / longest spoke                    3 shortest spoke / length
+ *   4 cos of the angle between the normals of the edge's two faces (1: flat)
+ *   5 smallest such cos over the spokes
+ *   6 valence of a   7 valence of b             8 common neighbours of a and b
+ *   9 sum of ovl over S                         10 largest ovl over S */
+static void edge_features(const omesh *m, const int32_t *ovl, int64_t h, float *x) {
+    int32_t a = m->F[h], b = m->F[3 * (h / 3) + (h % 3 + 1) % 3];
+    double f[NF_USED];
+    int32_t ring[RING_CAP];
+    int n = ring_faces(m, a, b, ring, RING_CAP);
+    double le = seg_len(m->V + 3 * (int64_t)a, m->V + 3 * (int64_t)b);
+    double lmax = 0.0, lmin = INFINITY, cmin = INFINITY;
+    int64_t osum = 0, omax = 0;
+    for (int i = 0; i < n; i++) {
+        int64_t g = ring[i];
+        for (int c = 0; c < 3; c++) {
+            int32_t u = m->F[3 * g + c], w = m->F[3 * g + (c + 1) % 3];
+            if (u != a && u != b && w != a && w != b) continue;
+            double l = seg_len(m->V + 3 * (int64_t)u, m->V + 3 * (int64_t)w);
+            if (l > lmax) lmax = l;
+            if (l < lmin) lmin = l;
+            double cs = edge_cos(m, 3 * g + c);
+            if (cs < cmin) cmin = cs;
+        }
+        int64_t o = ovl ? ovl[g] : 0;
+        osum += o;
+        if (o > omax) omax = o;
+    }
+    /* common neighbours: vertices other than a, b on faces of both stars */
+    int common = 0;
+    for (int64_t i = m->inc_off[a]; i < m->inc_off[a + 1]; i++) {
+        int32_t g = m->inc[i];
+        for (int c = 0; c < 3; c++) {
+            int32_t v = m->F[3 * (int64_t)g + c];
+            if (v == a || v == b) continue;
+            /* count v once: only from the first face of star(a) holding it */
+            int first = 1;
+            for (int64_t j = m->inc_off[a]; j < i && first; j++)
+                if (face_has(m, m->inc[j], v)) first = 0;
+            if (!first) continue;
+            int inb = 0;
+            for (int64_t j = m->inc_off[b]; j < m->inc_off[b + 1] && !inb; j++)
+                if (face_has(m, m->inc[j], v)) inb = 1;
+            common += inb;
+        }
+    }
+    f[0] = plog2(key_cost(m->key[h]));
+    f[1] = plog2(le);
+    f[2] = le / lmax;
+    f[3] = lmin / le;
+    f[4] = edge_cos(m, h);
+    f[5] = cmin;
+    f[6] = (double)(m->inc_off[a + 1] - m->inc_off[a]);
+    f[7] = (double)(m->inc_off[b + 1] - m->inc_off[b]);
+    f[8] = (double)common;
+    f[9] = (double)osum;
+    f[10] = (double)omax;
+    for (int k = 0; k < NFEAT; k++) x[k] = k < NF_USED ? quantize_feature(f[k], FEAT_SHIFT[k]) : 0.0f;
+}
+
+/* the network on one quantised feature vector: 32 -> 64 -> 64 -> 1, ReLU,
+ * each hidden activation scaled by 2^a and rounded to an integer in [0, 127].
+ * Weights lie on grids fine enough and sums are short enough that every
+ * float64 operation here is exact. */
+static double mlp_logit(const oracle_mlp *M, const float *x) {
+    double h1[64], h2[64];
+    for (int j = 0; j < 64; j++) {
+        double acc = M->b1[j];
+        for (int k = 0; k < 32; k++) acc += (double)M->w1[j][k] * (double)x[k];
+        if (acc < 0.0) acc = 0.0;
+        double q = rint(ldexp(acc, M->a1));
+        h1[j] = q > 127.0 ? 127.0 : q;
+    }
+    for (int j = 0; j < 64; j++) {
+        double acc = M->b2[j];
+        for (int k = 0; k < 64; k++) acc += (double)M->w2[j][k] * h1[k];
+        if (acc < 0.0) acc = 0.0;
+        double q = rint(ldexp(acc, M->a2));
+        h2[j] = q > 127.0 ? 127.0 : q;
+    }
+    double acc = M->b3;
+    for (int k = 0; k < 64; k++) acc += (double)M->w3[k] * h2[k];
+    return acc;
+}
+
+/* ovl of face t on the current mesh (t alive) */
+static int32_t overlap_count(const omesh *m, const ogrid *G, int64_t t, int64_t *stamp, int64_t stamp_id) {
+    double a[3], b[3];
+    face_box(m, t, a, b);
+    int i0 = cell_of(G, 0, a[0]), i1 = cell_of(G, 0, b[0]);
+    int j0 = cell_of(G, 1, a[1]), j1 = cell_of(G, 1, b[1]);
+    int k0 = cell_of(G, 2, a[2]), k1 = cell_of(G, 2, b[2]);
+    int g = G->g[0];
+    int32_t n = 0;
+    for (int i = i0; i <= i1; i++)
+        for (int j = j0; j <= j1; j++)
+            for (int k = k0; k <= k1; k++) {
+                int64_t c = ((int64_t)i * g + j) * g + k;
+                for (int64_t e = G->off[c]; e < G->off[c + 1]; e++) {
+                    int64_t u = G->items[e];
+                    if (u == t || stamp[u] == stamp_id) continue;
+                    stamp[u] = stamp_id;
+                    double c0[3], c1[3];
+                    face_box(m, u, c0, c1);
+                    if (!boxes_overlap(a, b, c0, c1)) continue;
+                    const int32_t *tu = m->F + 3 * u;
+                    if (face_has(m, (int32_t)t, tu[0]) || face_has(m, (int32_t)t, tu[1]) ||
+                        face_has(m, (int32_t)t, tu[2]))
+                        continue;
+                    n++;
+                }
+            }
+    return n;
+}
+
+/* ovl of every alive face */
+static void overlap_init(const omesh *m, int32_t *ovl) {
+    ogrid G;
+    grid_build(m, &G);
+    int64_t *stamp = xalloc(sizeof(int64_t) * (size_t)m->nf);
+    for (int64_t f = 0; f < m->nf; f++) stamp[f] = -1;
+    for (int64_t f = 0; f < m->nf; f++) ovl[f] = m->falive[f] ? overlap_count(m, &G, f, stamp, f) : 0;
+    free(stamp);
+    grid_free(&G);
+}
+
+/* ------------------------------------------------------------------------ */
 /* one round                                                                 */
 /* ------------------------------------------------------------------------ */
 
@@ -610,6 +832,8 @@ typedef struct {
     uint8_t *reason;   /* 0 committed, 1 link, 2 flip/degenerate, 3 intersection, 4 capped */
     double *vbar;      /* 3 per candidate */
     int64_t passing, chosen, changed, undo_iters, commits;
+    int64_t demoted;   /* learned mode: candidates set aside by the network */
+    int retry;         /* learned mode: nothing committed with set-aside candidates; rerun plain */
 } round_out;
 
 typedef struct {
@@ -640,8 +864,10 @@ static int64_t count_alive_faces(const omesh *m) {
 }
 
 /* one full round; returns 0 or a negative error */
+/* mlp (may be NULL): the learned proposal; ovl (may be NULL): per-face
+ * overlap counts, kept up to date when given */
 static int run_round(omesh *m, int64_t target_eff, const oracle_opts *opt, round_out *out,
-                     int stop_after_check) {
+                     int stop_after_check, const oracle_mlp *mlp, int32_t *ovl) {
     int err = build_adjacency(m);
     if (err) return err;
     compute_quadrics(m);
@@ -650,6 +876,20 @@ static int run_round(omesh *m, int64_t target_eff, const oracle_opts *opt, round
 
     int32_t *cand = xalloc(sizeof(int32_t) * (size_t)(3 * nf + 1));
     int64_t nc = select_edges(m, cand);
+    int64_t demoted = 0;
+    if (mlp) {
+        /* score every candidate first, then set the low ones aside */
+        uint8_t *low = xalloc((size_t)nc + 1);
+        float x[NFEAT];
+        for (int64_t c = 0; c < nc; c++) {
+            edge_features(m, ovl, cand[c], x);
+            low[c] = mlp_logit(mlp, x) < (double)mlp->threshold;
+        }
+        for (int64_t c = 0; c < nc; c++)
+            if (low[c]) { m->key[cand[c]] = KEY_MAX; demoted++; }
+        free(low);
+        if (demoted) nc = select_edges(m, cand);
+    }
     uint8_t *reason = xalloc((size_t)nc + 1);
     double *vbar = xalloc(sizeof(double) * 3 * (size_t)(nc + 1));
 
@@ -741,9 +981,17 @@ static int run_round(omesh *m, int64_t target_eff, const oracle_opts *opt, round
     int64_t *stamp = xalloc(sizeof(int64_t) * (size_t)nf);
     for (int64_t f = 0; f < nf; f++) stamp[f] = -1;
     int64_t stamp_id = 0;
+    int32_t *ovl_new = ovl ? xalloc(sizeof(int32_t) * (size_t)nf) : NULL;
     for (;;) {
         ogrid G;
         grid_build(m, &G);
+        if (ovl_new && iters == 0) {
+            /* overlap counts of the changed faces on the tentative mesh */
+            for (int64_t t = 0; t < nf; t++) {
+                if (!m->falive[t] || owner[t] < 0 || !applied[owner[t]]) continue;
+                ovl_new[t] = overlap_count(m, &G, t, stamp, stamp_id++);
+            }
+        }
         memset(mark, 0, (size_t)nc + 1);
         undo_ctx uc = {m, owner, applied, mark, 0};
         for (int64_t t = 0; t < nf; t++) {
@@ -780,7 +1028,14 @@ static int run_round(omesh *m, int64_t target_eff, const oracle_opts *opt, round
         int32_t a = Fpre[h], b = Fpre[3 * (h / 3) + (h % 3 + 1) % 3];
         m->valive[a < b ? b : a] = 0;
     }
-    if (!stop_after_check) {
+    if (ovl_new) {
+        for (int64_t t = 0; t < nf; t++)
+            if (m->falive[t] && owner[t] >= 0 && applied[owner[t]]) ovl[t] = ovl_new[t];
+        free(ovl_new);
+    }
+    out->demoted = demoted;
+    out->retry = mlp && demoted > 0 && commits == 0;
+    if (!stop_after_check && !out->retry) {
         uint8_t *nflags = xalloc((size_t)(3 * nf));
         for (int64_t c = 0; c < nc; c++) {
             if (reason[c] >= 1 && reason[c] <= 3) {
@@ -893,7 +1148,7 @@ int oracle_check(const double *V, int64_t nv, const int32_t *F, int64_t nf, cons
     if (flags) memcpy(m.flags, flags, (size_t)(3 * nf));
     oracle_opts o = {w_e, w_s, 4, -1};
     round_out r;
-    int err = run_round(&m, target - (target % 2), &o, &r, 1);
+    int err = run_round(&m, target - (target % 2), &o, &r, 1, NULL, NULL);
     if (!err) {
         *ncand = r.ncand;
         memcpy(cand, r.cand, sizeof(int32_t) * (size_t)r.ncand);
@@ -906,21 +1161,32 @@ int oracle_check(const double *V, int64_t nv, const int32_t *F, int64_t nf, cons
     return err;
 }
 
-/* The whole method: rounds until the face target, the tolerance or
- * max_rounds.  Output is the stable compaction of alive vertices and faces;
- * flags_out (3 * nf_out, may be NULL) are the invalid-edge flags in the output
- * numbering. */
-int oracle_run(const double *V, int64_t nv, const int32_t *F, int64_t nf,
-               const uint8_t *flags_in, int32_t streak_in, int64_t target, const oracle_opts *opt,
-               double *Vout, int64_t *nv_out, int32_t *Fout, int64_t *nf_out,
-               uint8_t *flags_out, int32_t *streak_out, oracle_stats *st,
-               oracle_round_log *log, int64_t log_cap) {
+/* training rows of the learned proposal: the features of each round's
+ * candidates and whether the candidate was committed (1) or rejected by a
+ * check (0); candidates left out by the face target give no row */
+typedef struct {
+    float *X;
+    uint8_t *y;
+    int64_t cap, n;
+} collect_buf;
+
+static int run_impl(const double *V, int64_t nv, const int32_t *F, int64_t nf,
+                    const uint8_t *flags_in, int32_t streak_in, int64_t target, const oracle_opts *opt,
+                    double *Vout, int64_t *nv_out, int32_t *Fout, int64_t *nf_out,
+                    uint8_t *flags_out, int32_t *streak_out, oracle_stats *st,
+                    oracle_round_log *log, int64_t log_cap, const oracle_mlp *mlp, collect_buf *col,
+                    int64_t *learned_info) {
     if (check_input(F, nf, nv) || target < 0) return -1;
     omesh m;
     mesh_init(&m, V, nv, F, nf);
     if (flags_in) memcpy(m.flags, flags_in, (size_t)(3 * nf));
     m.streak = streak_in;
     memset(st, 0, sizeof(*st));
+    int32_t *ovl = NULL;
+    if (mlp || col) {
+        ovl = xalloc(sizeof(int32_t) * (size_t)nf);
+        overlap_init(&m, ovl);
+    }
     int64_t teff = target - (target % 2);
     int err = 0;
     for (;;) {
@@ -931,8 +1197,40 @@ int oracle_run(const double *V, int64_t nv, const int32_t *F, int64_t nf,
         int64_t valive = 0;
         for (int64_t v = 0; v < m.nv; v++) valive += m.valive[v];
         round_out r;
-        err = run_round(&m, teff, opt, &r, 0);
-        if (err) break;
+        float *feat = NULL;
+        if (col) {
+            /* features of this round's candidates, taken before the round
+             * changes the mesh (the plain selection; col and mlp exclude
+             * each other) */
+            err = build_adjacency(&m);
+            if (err) break;
+            compute_quadrics(&m);
+            compute_keys(&m, opt->w_e, opt->w_s);
+            int32_t *c0 = xalloc(sizeof(int32_t) * (size_t)(3 * m.nf + 1));
+            int64_t n0 = select_edges(&m, c0);
+            feat = xalloc(sizeof(float) * NFEAT * (size_t)(n0 + 1));
+            for (int64_t c = 0; c < n0; c++) edge_features(&m, ovl, c0[c], feat + NFEAT * c);
+            free(c0);
+        }
+        err = run_round(&m, teff, opt, &r, 0, mlp, ovl);
+        if (err) { free(feat); break; }
+        if (learned_info) learned_info[0] += r.demoted;
+        if (r.retry) {
+            /* nothing committed with candidates set aside: the plain round */
+            free(r.cand); free(r.reason); free(r.vbar);
+            if (learned_info) learned_info[1]++;
+            err = run_round(&m, teff, opt, &r, 0, NULL, ovl);
+            if (err) break;
+        }
+        if (col) {
+            for (int64_t c = 0; c < r.ncand && col->n < col->cap; c++) {
+                if (r.reason[c] > 3) continue;
+                memcpy(col->X + NFEAT * col->n, feat + NFEAT * c, sizeof(float) * NFEAT);
+                col->y[col->n] = r.reason[c] == 0;
+                col->n++;
+            }
+            free(feat);
+        }
         int64_t rl = 0, rf = 0, ri = 0, cp = 0;
         for (int64_t c = 0; c < r.ncand; c++) {
             rl += r.reason[c] == 1;
@@ -978,9 +1276,73 @@ int oracle_run(const double *V, int64_t nv, const int32_t *F, int64_t nf,
         if (streak_out) *streak_out = m.streak;
         free(vmap);
     }
+    free(ovl);
     mesh_free(&m);
     return err;
 }
+
+/* The whole method: rounds until the face target, the tolerance or
+ * max_rounds.  Output is the stable compaction of alive vertices and faces;
+ * flags_out (3 * nf_out, may be NULL) are the invalid-edge flags in the output
+ * numbering. */
+int oracle_run(const double *V, int64_t nv, const int32_t *F, int64_t nf,
+               const uint8_t *flags_in, int32_t streak_in, int64_t target, const oracle_opts *opt,
+               double *Vout, int64_t *nv_out, int32_t *Fout, int64_t *nf_out,
+               uint8_t *flags_out, int32_t *streak_out, oracle_stats *st,
+               oracle_round_log *log, int64_t log_cap) {
+    return run_impl(V, nv, F, nf, flags_in, streak_in, target, opt, Vout, nv_out, Fout, nf_out, flags_out,
+                    streak_out, st, log, log_cap, NULL, NULL, NULL);
+}
+
+/* The method with the learned proposal (mlp); learned_info (2 entries, may
+ * be NULL) gets the candidates set aside and the rounds run again plain. */
+int oracle_run_learned(const double *V, int64_t nv, const int32_t *F, int64_t nf, int64_t target,
+                       const oracle_opts *opt, const oracle_mlp *mlp, double *Vout, int64_t *nv_out,
+                       int32_t *Fout, int64_t *nf_out, oracle_stats *st, int64_t *learned_info) {
+    if (learned_info) learned_info[0] = learned_info[1] = 0;
+    return run_impl(V, nv, F, nf, NULL, 0, target, opt, Vout, nv_out, Fout, nf_out, NULL, NULL, st, NULL, 0,
+                    mlp, NULL, learned_info);
+}
+
+/* The plain method, logging training rows (X: cap x 32 floats, y: cap). */
+int oracle_collect(const double *V, int64_t nv, const int32_t *F, int64_t nf, int64_t target,
+                   const oracle_opts *opt, float *X, uint8_t *y, int64_t cap, int64_t *n,
+                   double *Vout, int64_t *nv_out, int32_t *Fout, int64_t *nf_out, oracle_stats *st) {
+    collect_buf col = {X, y, cap, 0};
+    int err = run_impl(V, nv, F, nf, NULL, 0, target, opt, Vout, nv_out, Fout, nf_out, NULL, NULL, st, NULL, 0,
+                       NULL, &col, NULL);
+    *n = col.n;
+    return err;
+}
+
+/* features of the given edges (half-edge ids) of a mesh, with the overlap
+ * counts of the mesh itself (as at the start of a run) */
+int oracle_features(const double *V, int64_t nv, const int32_t *F, int64_t nf, const int32_t *edges,
+                    int64_t ne, double w_e, double w_s, float *X, int32_t *ovl_out) {
+    if (check_input(F, nf, nv)) return -1;
+    omesh m;
+    mesh_init(&m, V, nv, F, nf);
+    int err = build_adjacency(&m);
+    if (!err) {
+        compute_quadrics(&m);
+        compute_keys(&m, w_e, w_s);
+        int32_t *ovl = xalloc(sizeof(int32_t) * (size_t)nf);
+        overlap_init(&m, ovl);
+        for (int64_t i = 0; i < ne; i++) edge_features(&m, ovl, edges[i], X + NFEAT * i);
+        if (ovl_out) memcpy(ovl_out, ovl, sizeof(int32_t) * (size_t)nf);
+        free(ovl);
+    }
+    mesh_free(&m);
+    return err;
+}
+
+/* the network's logit for each of n quantised feature rows */
+int oracle_mlp_logits(const oracle_mlp *M, const float *X, int64_t n, double *out) {
+    for (int64_t i = 0; i < n; i++) out[i] = mlp_logit(M, X + NFEAT * i);
+    return 0;
+}
+
+int64_t oracle_sizeof_mlp(void) { return (int64_t)sizeof(oracle_mlp); }
 
 int oracle_tri_pair(const double *P9, const int32_t *ip, const double *Q9, const int32_t *iq) {
     const double *P[3] = {P9, P9 + 3, P9 + 6};
