@@ -95,6 +95,47 @@ def batched(native, torch, dev, steps, warmup, count, seq_sample):
     }
 
 
+def learned_vs_plain(native, torch, dev, Vd, Fd, target, steps):
+    """The learned proposal (the committed trained network) against the plain
+    method on the same mesh: throughput, rounds, one-sided Hausdorff distance
+    from the input vertices to the output surface; also on a thin-shell mesh
+    (two nested spheres), where the plain method's candidates get undone for
+    intersections."""
+    from paper_2509_05595_amd import learn, meshgen
+    if not os.path.exists(learn.MODEL_PATH):
+        return None
+    model = learn.load_model()
+    ctx = native.Context(dev)
+    out = {"model": os.path.relpath(learn.MODEL_PATH, os.path.dirname(os.path.abspath(__file__)))}
+    Vs, Fs = meshgen.nested_spheres(k=6, gap=0.002)
+    cases = {"headline": (Vd, Fd, target),
+             "thin_shell": (torch.from_numpy(Vs).to(dev), torch.from_numpy(Fs).to(dev), len(Fs) // 50)}
+    for name, (V, F, t) in cases.items():
+        row = {"faces": int(F.shape[0]), "target": int(t)}
+        for mode in ("plain", "learned"):
+            ctx.set_mlp(model if mode == "learned" else None)
+            ctx.set_options(native.default_options(learned=int(mode == "learned")))
+            res = ctx.simplify(V, F, t)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                res = ctx.simplify(V, F, t)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            Vo, Fo, st = res
+            row[mode] = {"faces_per_s": F.shape[0] / dt, "ms": dt * 1e3, "rounds": st["rounds"],
+                         "faces_out": int(Fo.shape[0]), "demoted": st["demoted"], "fallbacks": st["fallbacks"],
+                         "rej_isect": st["rej_isect"],
+                         "hausdorff": ctx.hausdorff(V, Vo.contiguous(), Fo.contiguous())}
+        row["speedup"] = row["learned"]["faces_per_s"] / row["plain"]["faces_per_s"]
+        row["hausdorff_ratio"] = row["learned"]["hausdorff"] / max(row["plain"]["hausdorff"], 1e-300)
+        out[name] = row
+        log(f"learned vs plain on {name}: {row['speedup']:.3f}x")
+    ctx.set_options(native.default_options())
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +149,7 @@ def main():
     ap.add_argument("--coop", type=int, default=0, help="lanes per query when few remain (0: library default, 1: off)")
     ap.add_argument("--coop-below", type=int, default=0, help="query count below which lanes share a query")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-versus-plain comparison")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     args = ap.parse_args()
@@ -185,6 +227,10 @@ def main():
     out["path_roofline"] = {"algorithmic_bytes_per_step": tot_bytes,
                             "achieved_GBs": tot_bytes / (ms_per_step / 1e3) / 1e9,
                             "frac": tot_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS}
+    if not args.no_learned:
+        lv = learned_vs_plain(native, torch, dev, Vd, Fd, target, 2)
+        if lv is not None:
+            out["learned_vs_plain"] = lv
     if not args.no_batch:
         ctx.close()
         out["batched"] = batched(native, torch, dev, args.batch_steps, 1, args.batch_count, 32)

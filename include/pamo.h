@@ -60,7 +60,7 @@ typedef struct {
                            the first round's order is carried through the compactions) */
   int32_t query_coop;   /* lanes sharing one query when few queries remain (2,4,8,16; 1 = never; default 8) */
   int32_t coop_below;   /* ... namely when a pass has fewer than about this many queries (default 131072) */
-  int32_t reserved[1];
+  int32_t learned;      /* 1: the learned proposal (needs pamo_set_mlp); 0: the plain method */
 } pamo_options;
 
 typedef struct {
@@ -75,6 +75,8 @@ typedef struct {
   int64_t undo_hist[5]; /* rounds needing 0, 1, 2, 3, >3 undo iterations (cf. Table 7) */
   int64_t deferred_pairs; /* pairs settled by the exact (expansion) predicate */
   int64_t status;       /* as the return value */
+  int64_t demoted;      /* learned proposal: candidates set aside by the network */
+  int64_t fallbacks;    /* learned proposal: rounds run again without it (nothing committed) */
 } pamo_stats;
 
 /* Fill *opt with the paper's defaults (w_e 0.001, w_s 0.005, tolerance 4). */
@@ -191,6 +193,94 @@ pamo_status pamo_self_intersections(pamo_ctx* ctx, const double* V, int64_t nv, 
  * Asynchronous. */
 pamo_status pamo_tri_pairs(pamo_ctx* ctx, const double* P, const int32_t* ip, const double* Q, const int32_t* iq,
                            int64_t n, uint8_t* out);
+
+/* ---- the learned proposal (an addition to the paper's method) ----
+ *
+ * Each round, a small network scores every selected candidate from 32
+ * features of its neighbourhood; candidates scored below a threshold are set
+ * aside for the round (their key becomes the largest) and the selection is
+ * redone, so a neighbour of a likely rejection can collapse instead.  Every
+ * collapse still passes every check of Sec. 5.1 and 5.2.  A round that sets
+ * candidates aside and commits nothing runs again without the network.
+ *
+ * Features of edge (a, b), each scaled by a fixed power of two and rounded to
+ * an integer in [-127, 127]; S = star(a) u star(b), spokes = edges of S's
+ * faces through a or b:
+ *   0 plog2(cost of Eq. 1) (x4)   1 plog2(length) (x8)   2 length / longest spoke (x128)
+ *   3 shortest spoke / length (x128)   4 cos between the normals of the edge's faces (x64)
+ *   5 smallest such cos over the spokes (x64)   6, 7 valence of a, b (x4)
+ *   8 common neighbours of a and b (x16)   9 sum over S of ovl (x1)   10 largest ovl over S (x4)
+ *   11..31 zero
+ * plog2(c) = e - 1 + (2 m - 1) for c = m 2^e, m in [0.5, 1) (exact at powers
+ * of two, linear between); ovl(f) = alive faces sharing no vertex with f whose
+ * float64 boxes meet f's (closed), counted on the input and, for each face a
+ * round changes, on that round's tentative mesh, kept when the collapse is
+ * committed.
+ *
+ * Network: 32 -> 64 -> 64 -> 1 with ReLU; each hidden activation h is
+ * replaced by min(127, rint(h 2^a)).  Weights of layer l are integers k,
+ * |k| <= 127, times 2^-e_l; biases integers times 2^-e_l with magnitude at
+ * most 2^22 2^-e_l; 0 <= e_l <= 15.  Under these grids every operation of the
+ * inference is exact in float32, so results do not depend on summation order. */
+typedef struct {
+  float w1[64][32]; /* w1[j][k]: feature k -> unit j */
+  float b1[64];
+  float w2[64][64];
+  float b2[64];
+  float w3[64];
+  float b3;
+  int32_t e1, e2, e3; /* weight grids 2^-e */
+  int32_t a1, a2;     /* activation shifts */
+  float threshold;    /* set aside when the logit is below */
+} pamo_mlp;
+
+/* Set the network of the learned proposal (host struct, copied); NULL
+ * removes it.  PAMO_ERR_ARG when a value is off its grid. */
+pamo_status pamo_set_mlp(pamo_ctx* ctx, const pamo_mlp* mlp);
+
+/* Features (as above) of the edges given by half-edge ids (device int32
+ * [ne]) of a mesh, with the overlap counts of the mesh itself.  X: device
+ * float [ne][32]; ovl: device int32 [nf] or NULL.  Synchronises the stream. */
+pamo_status pamo_features(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                          const int32_t* edges, int64_t ne, float* X, int32_t* ovl);
+
+/* The network's logit of each feature row: X device float [n][32] (integers
+ * in [-127, 127]), logits device float [n].  Asynchronous. */
+pamo_status pamo_mlp_logits(pamo_ctx* ctx, const float* X, int64_t n, float* logits);
+
+/* The plain method on one mesh, logging one training row per candidate that
+ * a check decided (committed: label 1; rejected by the link condition, a
+ * flipped or degenerate triangle, or an intersection: label 0), in round and
+ * candidate order: features X device float [cap][32], labels y device uint8
+ * [cap]; *rows (host) = rows written.  Synchronises the stream. */
+pamo_status pamo_collect(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                         int64_t target_faces, float* X, uint8_t* y, int64_t cap, int64_t* rows, pamo_stats* stats);
+
+/* Training of the network on feature rows X (device float [n][32]) and labels
+ * y (device uint8 [n]).  params: device float [6337], the float master
+ * weights in the order W1 (64 x 32, row = unit) | b1 | W2 (64 x 64) | b2 | W3 |
+ * b3; meta (host int32 [5]): e1, e2, e3, a1, a2.  The forward pass rounds the
+ * master weights to their grids; gradients pass straight through every
+ * rounding (zero where a value is clamped).  Loss: mean binary cross-entropy
+ * of the logit.
+ * pamo_mlp_grad: gradient (device float [6337]) and loss (host) over all n rows.
+ * pamo_mlp_train: `steps` Adam steps (beta 0.9, 0.999, eps 1e-8, rate lr) on
+ * batches of `batch` rows order[s * batch .. (s+1) * batch) (device int32
+ * [steps * batch]; entries outside [0, n) are left out of their batch); m, v
+ * device float [6337] Adam moments; t0 = steps taken before; loss device
+ * float [steps] or NULL.  Asynchronous. */
+pamo_status pamo_mlp_grad(pamo_ctx* ctx, const float* params, const int32_t* meta, const float* X, const uint8_t* y,
+                          int64_t n, float* grad, float* loss);
+pamo_status pamo_mlp_train(pamo_ctx* ctx, float* params, float* m, float* v, const int32_t* meta, const float* X,
+                           const uint8_t* y, int64_t n, const int32_t* order, int64_t steps, int64_t batch, float lr,
+                           int64_t t0, float* loss);
+
+/* One-sided Hausdorff distance from points P (device float64 [np][3]) to the
+ * surface (V, F): dist (device float64 [np], may be NULL) gets each point's
+ * distance to its closest triangle, *dmax (host) the largest.  Brute force
+ * over the triangles.  Synchronises the stream. */
+pamo_status pamo_hausdorff(pamo_ctx* ctx, const double* P, int64_t np, const double* V, int64_t nv, const int32_t* F,
+                           int64_t nf, double* dist, double* dmax);
 
 /* ---- measurement ---- */
 

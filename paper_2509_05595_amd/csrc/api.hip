@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "learn.hpp"
 #include "round.hpp"
 #include "exact_dev.hpp"
 
@@ -26,11 +27,11 @@ using namespace pamo;
 // minimum (every input element read once, every output written once).
 enum Phase {
   PH_QUADRICS, PH_COST, PH_SELECT, PH_LOCAL, PH_CAP, PH_BOXES, PH_APPLY, PH_BVH, PH_FACELIST, PH_QUERY,
-  PH_PAIRS, PH_RESOLVE, PH_UNDO, PH_COMMIT, PH_FLAGS, PH_COMPACT, PH_COUNT
+  PH_PAIRS, PH_RESOLVE, PH_UNDO, PH_COMMIT, PH_FLAGS, PH_COMPACT, PH_LEARN, PH_COUNT
 };
 static const char* const PH_NAME[PH_COUNT] = {
     "quadrics", "cost_keys", "select", "local_check", "cap", "face_boxes", "apply", "bvh_build",
-    "face_list", "query", "pairs", "resolve", "undo", "commit", "flags", "compact"};
+    "face_list", "query", "pairs", "resolve", "undo", "commit", "flags", "compact", "learn"};
 
 struct Prof {
   uint32_t mask = 0;
@@ -65,6 +66,7 @@ struct pamo_ctx {
   int* hbt = nullptr;   // pinned mirror of the per-mesh tallies of a batch
   size_t hbt_n = 0;
   Prof prof;
+  MlpDev* mlp = nullptr;  // the learned proposal's network (device), when set
 };
 
 namespace {
@@ -82,6 +84,8 @@ enum {
   C_HIST2 = 16,  // 8 entries: final reason histogram
   C_ERR = 24,    // error bits
   C_NORD = 25,   // length of the remapped leaf order
+  C_NDEMOTE = 26,  // candidates set aside by the network this round
+  C_NROWS = 27,    // training rows logged this round
   C_COUNT = 32
 };
 
@@ -219,6 +223,8 @@ struct RoundBufs {
   int2* defer;
   int defer_cap;
   int* morder;  // leaf order carried between rounds (see Driver)
+  int* ovl_new;  // learned proposal: overlap counts measured this round (null when not tracked)
+  float* X;      // learned proposal: features of this round's candidates (null when unused)
 };
 
 // one query pass (traversal + pair predicate + exact resolve); grows the
@@ -240,6 +246,7 @@ const int* query_pass(pamo_ctx* c, const Bvh& bvh, QueryMode mode, const int* ql
   const int coop = coop_lanes(c, nq_est);
   fill_i32(s, c->dcnt + C_NUNDO, 4, 0);  // undone, deferred, collected, intersecting
   for (;;) {
+    if (qa.ovl_cnt) fill_i32(s, qa.ovl_cnt, bvh.n, 0);  // counted afresh by every attempt
     {
       TIMED(PH_QUERY, bytes);
       launch_query(s, bvh, mode, qlist, nq_dev, bound, qa, packet, coop);
@@ -293,6 +300,8 @@ RoundBufs round_bufs(pamo_ctx* c, int64_t nv, int64_t nf) {
   b.defer_cap = (int)std::max<int64_t>(1 << 16, nf);
   b.defer = w.get<int2>("r.defer", b.defer_cap);
   b.morder = w.get<int>("r.morder", nf);
+  b.ovl_new = nullptr;
+  b.X = nullptr;
   return b;
 }
 
@@ -300,6 +309,20 @@ struct RoundResult {
   int ncand = 0, npass = 0, chosen = 0, undone = 0, commits = 0, iters = 0, deferred = 0;
   int hist[8] = {0};
   const int* leaf_order = nullptr;  // the BVH leaf order used this round (null: no BVH built)
+  int demoted = 0;     // learned proposal: candidates set aside
+  bool retry = false;  // learned proposal: set-aside round committed nothing; rerun it plain
+};
+
+// The learned proposal's share of a run: setting candidates aside with the
+// network, keeping the per-face overlap counts its features read, and logging
+// training rows (features and outcome of each candidate the checks decided).
+struct LearnRun {
+  bool learned = false;
+  bool track = false;
+  float* X = nullptr;  // logging: rows [cap][32] and labels [cap] (device)
+  uint8_t* y = nullptr;
+  int64_t cap = 0, n = 0;
+  int64_t demoted = 0, fallbacks = 0;
 };
 
 // Leaf order of the BVH carried across rounds: sorting by Morton code every
@@ -344,7 +367,8 @@ void cap_single(pamo_ctx* c, const RoundBufs& b, const int* ncand_dev, uint8_t* 
 // applied).  undone[c] != 0 marks collapses undone by the loop (reason not yet
 // set to 3).  `order`: BVH leaf order to reuse, or null to sort.
 void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand, const int* ncand_dev, int ncand,
-                    uint8_t* reason, double* vbar, RoundResult& R, const int* order, int nmesh = 1) {
+                    uint8_t* reason, double* vbar, RoundResult& R, const int* order, int nmesh = 1,
+                    int* ovl_new = nullptr) {
   hipStream_t s = c->stream;
   int* cnt = c->dcnt;
   const int* h;
@@ -384,7 +408,9 @@ void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand
   init_pair_buffer(c, qa, m.nf);
   const double qbytes = 64 * (nf - 1) + 17 * nf + 24 * nv;  // tree + faces + alive/owner + vertices
   const double pbytes = 17 * nf + 24 * nv;                   // pairs: faces, alive/owner, vertices (+ 8 per pair)
+  qa.ovl_cnt = ovl_new;  // overlap counts of the changed faces on the tentative mesh
   h = query_pass(c, bvh, QUERY_CHANGED, b.qlist, cnt + C_NQ, m.nf, 10ll * R.chosen, qa, qbytes, pbytes);
+  qa.ovl_cnt = nullptr;
   int newly = h[C_NUNDO];
   R.deferred += h[C_NDEFER];
   while (newly > 0) {
@@ -421,12 +447,15 @@ void add_stats(pamo_stats* st, const RoundResult& R) {
 
 // One full round on `cur`.  When collapses are committed, the compacted mesh
 // lands in `alt` and the two views are swapped.
-RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, int64_t teff, OrderState& os) {
+RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, int64_t teff, OrderState& os,
+                      LearnRun* L = nullptr) {
   hipStream_t s = c->stream;
   int* cnt = c->dcnt;
   RoundResult R;
   fill_i32(s, cnt, C_COUNT, 0);
   const double nf = cur.nf, nv = cur.nv;
+  const bool learned = L && L->learned;
+  const bool logging = L && L->X;
   {
     TIMED(PH_QUADRICS, 108 * nv + 24 * nf);
     launch_quadrics(s, cur, b.Q, cnt + C_ERR);
@@ -439,16 +468,35 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs
     TIMED(PH_SELECT, 20 * nv + 93 * nf);
     launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
   }
-  local_checks(c, cur, b, b.cand, cnt + C_NCAND, cur.nf / 2 + 1, b.reason, b.vbar);
+  const int bound = cur.nf / 2 + 1;
+  if (learned || logging) {
+    TIMED(PH_LEARN, 0);
+    launch_features(s, cur, b.key, b.cand, cnt + C_NCAND, bound, cur.ovl, b.X, cnt + C_ERR);
+    if (learned) {
+      launch_mlp(s, b.X, cnt + C_NCAND, bound, c->mlp, nullptr, b.cand, cur.twin, b.key, cnt + C_NDEMOTE);
+      launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);  // without the set-aside edges
+    }
+  }
+  local_checks(c, cur, b, b.cand, cnt + C_NCAND, bound, b.reason, b.vbar);
   const int* h = readback(c);
   check_err_bits(h[C_ERR]);
   R.ncand = h[C_NCAND];
   R.npass = h[C_HIST + 0];
+  R.demoted = h[C_NDEMOTE];
   prof_bytes(c, PH_LOCAL, 780.0 * R.ncand);
-  if (R.ncand == 0) return R;  // nothing selectable: a round without collapses
+  if (R.ncand == 0) {  // nothing selectable: a round without collapses
+    R.retry = learned && R.demoted > 0;
+    return R;
+  }
   const bool reuse = os.valid && os.age < os.resort;
   cap_single(c, b, cnt + C_NCAND, b.reason, teff, cur.nf, R);
-  check_and_undo(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr);
+  check_and_undo(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr, 1,
+                 L && L->track ? b.ovl_new : nullptr);
+  if (learned && R.demoted > 0 && R.commits == 0) {
+    // everything was undone, so the mesh is as the round found it
+    R.retry = true;
+    return R;
+  }
   if (R.leaf_order) os.age = reuse ? os.age + 1 : 1;
   fill_u8(s, b.valive, cur.nv, 1);
   if (R.chosen > 0) {
@@ -456,6 +504,12 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs
     launch_commit(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.undone, b.valive);
   }
   launch_reason_hist(s, cnt + C_NCAND, R.ncand, b.reason, cnt + C_HIST2);
+  if (L && L->track && R.chosen > 0) launch_ovl_commit(s, cur.nf, b.owner, b.falive, b.undone, b.ovl_new, cur.ovl);
+  if (logging && L->n < L->cap) {
+    TIMED(PH_LEARN, 0);
+    launch_log_rows(c->ws, s, cnt + C_NCAND, R.ncand, b.reason, b.X, L->X + L->n * LEARN_NFEAT, L->y + L->n,
+                    L->cap - L->n, cnt + C_NROWS);
+  }
   // invalid flags for the next round: this round's rejections, plus the old
   // flags when nothing was collapsed (Sec. 5.3)
   {
@@ -482,10 +536,28 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs
   h = readback(c);
   check_err_bits(h[C_ERR]);
   for (int i = 0; i < 8; i++) R.hist[i] = h[C_HIST2 + i];
+  if (logging) L->n += std::min<int64_t>(h[C_NROWS], L->cap - L->n);
   if (R.commits > 0) {
     alt.nf = h[C_NF];
     alt.nv = h[C_NV];
     std::swap(cur, alt);
+  }
+  return R;
+}
+
+// a learned round that set candidates aside and committed nothing runs again
+// without the network
+RoundResult run_round_learned(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, int64_t teff,
+                              OrderState& os, LearnRun* L) {
+  RoundResult R = run_round(c, cur, alt, b, teff, os, L);
+  if (!L) return R;
+  L->demoted += R.demoted;
+  if (R.retry) {
+    L->fallbacks++;
+    LearnRun plain = *L;
+    plain.learned = false;
+    R = run_round(c, cur, alt, b, teff, os, &plain);
+    L->n = plain.n;
   }
   return R;
 }
@@ -503,7 +575,7 @@ __global__ void k_check_index(const int* F, int64_t n3, int nv, int* err) {
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
 
 // all intersecting pairs of the mesh m; returns their number
-int64_t whole_mesh_pairs(pamo_ctx* c, MeshView m, int2* pairs, int64_t cap, int nmesh = 1) {
+int64_t whole_mesh_pairs(pamo_ctx* c, MeshView m, int2* pairs, int64_t cap, int nmesh = 1, int* ovl = nullptr) {
   hipStream_t s = c->stream;
   int* cnt = c->dcnt;
   float* box = c->ws.get<float>("w.box", 6 * (int64_t)m.nf);
@@ -526,6 +598,7 @@ int64_t whole_mesh_pairs(pamo_ctx* c, MeshView m, int2* pairs, int64_t cap, int 
   qa.npairs = cnt + C_NPAIRS;
   qa.pairs_cap = cap;
   qa.err = cnt + C_ERR;
+  qa.ovl_cnt = ovl;
   init_pair_buffer(c, qa, m.nf);
   const int* h = query_pass(c, bvh, QUERY_ALL_PAIRS, ql, cnt + C_NQ, m.nf, m.nf, qa, 0, 0);
   return h[C_NPAIRS];
@@ -596,9 +669,10 @@ struct Batch {
   int commits_m() const { return 2 * n; }
   int undo_m() const { return 3 * n; }
   int hist_m() const { return 4 * n; }
-  int f_off() const { return 12 * n; }
-  int v_off() const { return 13 * n + 1; }
-  int total() const { return 14 * n + 2; }
+  int demote_m() const { return 12 * n; }
+  int f_off() const { return 13 * n; }
+  int v_off() const { return 14 * n + 1; }
+  int total() const { return 15 * n + 2; }
   int* d(int o) const { return dev + o; }
 };
 
@@ -642,7 +716,7 @@ struct MeshRun {
 // One round over every mesh of the batch (the single-mesh round of run_round
 // with per-mesh targets, tallies, flag clearing and offsets).
 RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, const Batch& B,
-                            std::vector<MeshRun>& mr, OrderState& os) {
+                            std::vector<MeshRun>& mr, OrderState& os, bool learned = false, bool track = false) {
   hipStream_t s = c->stream;
   int* cnt = c->dcnt;
   const int n = B.n;
@@ -672,6 +746,13 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const Rou
     launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
   }
   const int bound = cur.nf / 2 + 1;
+  if (learned) {
+    TIMED(PH_LEARN, 0);
+    launch_features(s, cur, b.key, b.cand, cnt + C_NCAND, bound, cur.ovl, b.X, cnt + C_ERR);
+    launch_mlp(s, b.X, cnt + C_NCAND, bound, c->mlp, nullptr, b.cand, cur.twin, b.key, cnt + C_NDEMOTE, cur.fmesh,
+               B.d(B.demote_m()));
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
+  }
   local_checks(c, cur, b, b.cand, cnt + C_NCAND, bound, b.reason, b.vbar);
   launch_mesh_tally(s, b.cand, cnt + C_NCAND, bound, cur.fmesh, b.reason, nullptr, nullptr, B.d(B.ncand_m()),
                     B.d(B.npass_m()), nullptr, nullptr, nullptr);
@@ -694,7 +775,8 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const Rou
                      B.d(B.ncand_m()), n);
   }
   const bool reuse = os.valid && os.age < os.resort;
-  check_and_undo(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr, n);
+  check_and_undo(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr, n,
+                 track ? b.ovl_new : nullptr);
   if (R.leaf_order) os.age = reuse ? os.age + 1 : 1;
   fill_u8(s, b.valive, cur.nv, 1);
   if (R.chosen > 0) {
@@ -704,6 +786,9 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const Rou
   launch_reason_hist(s, cnt + C_NCAND, R.ncand, b.reason, cnt + C_HIST2);
   launch_mesh_tally(s, b.cand, cnt + C_NCAND, R.ncand, cur.fmesh, nullptr, b.reason, b.undone, nullptr, nullptr,
                     B.d(B.commits_m()), B.d(B.hist_m()), B.d(B.undo_m()));
+  if (track && R.chosen > 0) launch_ovl_commit(s, cur.nf, b.owner, b.falive, b.undone, b.ovl_new, cur.ovl);
+  if (learned)  // meshes whose round runs again keep their flags
+    launch_mark_retry(s, b.cand, cnt + C_NCAND, R.ncand, cur.fmesh, B.d(B.demote_m()), B.d(B.commits_m()), b.reason);
   {
     TIMED(PH_FLAGS, 3 * nf + 10.0 * R.ncand);
     if (R.commits > 0) launch_flags_clear_batch(s, cur, B.d(B.commits_m()));
@@ -735,6 +820,62 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const Rou
     std::swap(cur, alt);
   }
   return R;
+}
+
+// the whole method on one mesh (plain, learned, or plain with row logging)
+pamo_status simplify_run(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F, int64_t nf, int64_t target_faces,
+                         double* V_out, int64_t* nv_out, int32_t* F_out, int64_t* nf_out, pamo_stats* stats,
+                         LearnRun* L) {
+  check_sizes(nv, nf);
+  if (target_faces < 0) fail(PAMO_ERR_ARG, "negative target");
+  if (L->learned && !c->mlp) fail(PAMO_ERR_ARG, "the learned proposal needs a network (pamo_set_mlp)");
+  hipStream_t s = c->stream;
+  MeshView cur = mesh_bufs(c, "mA", nv, nf);
+  MeshView alt = mesh_bufs(c, "mB", nv, nf);
+  load_mesh(c, cur, V, F, nullptr);
+  if (c->opt.validate_input) {
+    int2* dummy = c->ws.get<int2>("w.pairs", 1);
+    if (whole_mesh_pairs(c, cur, dummy, 0) > 0) fail(PAMO_ERR_SELF_INTERSECTING, "the input intersects itself");
+  }
+  RoundBufs b = round_bufs(c, nv, nf);
+  if (L->track) {
+    cur.ovl = c->ws.get<int>("mA.ovl", nf);
+    alt.ovl = c->ws.get<int>("mB.ovl", nf);
+    b.ovl_new = c->ws.get<int>("r.ovl_new", nf);
+    b.X = c->ws.get<float>("r.X", (nf / 2 + 1) * (int64_t)LEARN_NFEAT);
+    int2* dummy = c->ws.get<int2>("w.pairs", 1);
+    whole_mesh_pairs(c, cur, dummy, 0, 1, cur.ovl);
+  }
+  pamo_stats st;
+  memset(&st, 0, sizeof(st));
+  int64_t teff = target_faces - target_faces % 2;
+  int streak = 0;
+  pamo_status status = PAMO_OK;
+  OrderState os;
+  os.resort = c->opt.resort_every > 0 ? c->opt.resort_every : PAMO_DEFAULT_RESORT;
+  for (;;) {
+    if (cur.nf <= teff) break;
+    if (streak >= c->opt.tolerance) {
+      status = PAMO_TARGET_UNREACHED;
+      break;
+    }
+    if (c->opt.max_rounds >= 0 && st.rounds >= c->opt.max_rounds) break;
+    RoundResult R = run_round_learned(c, cur, alt, b, teff, os, L);
+    add_stats(&st, R);
+    streak = R.commits == 0 ? streak + 1 : 0;
+  }
+  PAMO_HIP(hipMemcpyAsync(V_out, cur.V, 3 * (size_t)cur.nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  PAMO_HIP(hipMemcpyAsync(F_out, cur.F, 3 * (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+  PAMO_HIP(hipStreamSynchronize(s));
+  *nv_out = cur.nv;
+  *nf_out = cur.nf;
+  st.faces_out = cur.nf;
+  st.verts_out = cur.nv;
+  st.status = status;
+  st.demoted = L->demoted;
+  st.fallbacks = L->fallbacks;
+  if (stats) *stats = st;
+  return status;
 }
 
 }  // namespace
@@ -784,6 +925,7 @@ void pamo_destroy(pamo_ctx* c) {
   if (c->dcnt) (void)hipFree(c->dcnt);
   if (c->hcnt) (void)hipHostFree(c->hcnt);
   if (c->hbt) (void)hipHostFree(c->hbt);
+  if (c->mlp) (void)hipFree(c->mlp);
   delete c;
 }
 
@@ -923,45 +1065,28 @@ pamo_status pamo_simplify(pamo_ctx* c, const double* V, int64_t nv, const int32_
                           pamo_stats* stats) {
   return guarded(c, [&]() -> pamo_status {
     if (!V || !F || !V_out || !F_out || !nv_out || !nf_out) fail(PAMO_ERR_ARG, "null pointer");
-    check_sizes(nv, nf);
-    if (target_faces < 0) fail(PAMO_ERR_ARG, "negative target");
-    hipStream_t s = c->stream;
-    MeshView cur = mesh_bufs(c, "mA", nv, nf);
-    MeshView alt = mesh_bufs(c, "mB", nv, nf);
-    load_mesh(c, cur, V, F, nullptr);
-    if (c->opt.validate_input) {
-      int2* dummy = c->ws.get<int2>("w.pairs", 1);
-      if (whole_mesh_pairs(c, cur, dummy, 0) > 0) fail(PAMO_ERR_SELF_INTERSECTING, "the input intersects itself");
-    }
-    RoundBufs b = round_bufs(c, nv, nf);
-    pamo_stats st;
-    memset(&st, 0, sizeof(st));
-    int64_t teff = target_faces - target_faces % 2;
-    int streak = 0;
-    pamo_status status = PAMO_OK;
-    OrderState os;
-    os.resort = c->opt.resort_every > 0 ? c->opt.resort_every : PAMO_DEFAULT_RESORT;
-    for (;;) {
-      if (cur.nf <= teff) break;
-      if (streak >= c->opt.tolerance) {
-        status = PAMO_TARGET_UNREACHED;
-        break;
-      }
-      if (c->opt.max_rounds >= 0 && st.rounds >= c->opt.max_rounds) break;
-      RoundResult R = run_round(c, cur, alt, b, teff, os);
-      add_stats(&st, R);
-      streak = R.commits == 0 ? streak + 1 : 0;
-    }
-    PAMO_HIP(hipMemcpyAsync(V_out, cur.V, 3 * (size_t)cur.nv * sizeof(double), hipMemcpyDeviceToDevice, s));
-    PAMO_HIP(hipMemcpyAsync(F_out, cur.F, 3 * (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
-    PAMO_HIP(hipStreamSynchronize(s));
-    *nv_out = cur.nv;
-    *nf_out = cur.nf;
-    st.faces_out = cur.nf;
-    st.verts_out = cur.nv;
-    st.status = status;
-    if (stats) *stats = st;
-    return status;
+    LearnRun L;
+    L.learned = c->opt.learned != 0;
+    L.track = L.learned;
+    return simplify_run(c, V, nv, F, nf, target_faces, V_out, nv_out, F_out, nf_out, stats, &L);
+  });
+}
+
+pamo_status pamo_collect(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                         int64_t target_faces, float* X, uint8_t* y, int64_t cap, int64_t* rows, pamo_stats* stats) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!V || !F || !rows || cap < 0 || (cap > 0 && (!X || !y))) fail(PAMO_ERR_ARG, "bad arguments");
+    LearnRun L;
+    L.track = true;
+    L.X = cap > 0 ? X : nullptr;
+    L.y = y;
+    L.cap = cap;
+    double* Vo = c->ws.get<double>("col.V", 3 * nv);
+    int* Fo = c->ws.get<int>("col.F", 3 * nf);
+    int64_t nvo = 0, nfo = 0;
+    pamo_status st = simplify_run(c, V, nv, F, nf, target_faces, Vo, &nvo, Fo, &nfo, stats, &L);
+    *rows = L.n;
+    return st;
   });
 }
 
@@ -1009,6 +1134,16 @@ pamo_status pamo_simplify_batch(pamo_ctx* c, int32_t nmesh, const double* V, con
       if (whole_mesh_pairs(c, cur, dummy, 0, nmesh) > 0) fail(PAMO_ERR_SELF_INTERSECTING, "an input mesh intersects itself");
     }
     RoundBufs b = round_bufs(c, nv, nf);
+    const bool learned = c->opt.learned != 0;
+    if (learned && !c->mlp) fail(PAMO_ERR_ARG, "the learned proposal needs a network (pamo_set_mlp)");
+    if (learned) {
+      cur.ovl = c->ws.get<int>("mA.ovl", nf);
+      alt.ovl = c->ws.get<int>("mB.ovl", nf);
+      b.ovl_new = c->ws.get<int>("r.ovl_new", nf);
+      b.X = c->ws.get<float>("r.X", (nf / 2 + 1) * (int64_t)LEARN_NFEAT);
+      int2* dummy = c->ws.get<int2>("w.pairs", 1);
+      whole_mesh_pairs(c, cur, dummy, 0, nmesh, cur.ovl);
+    }
     std::vector<MeshRun> mr(nmesh);
     for (int m = 0; m < nmesh; m++) mr[m].teff = targets[m] - targets[m] % 2;
     int64_t deferred = 0;
@@ -1033,26 +1168,44 @@ pamo_status pamo_simplify_batch(pamo_ctx* c, int32_t nmesh, const double* V, con
         nactive++;
       }
       if (nactive == 0) break;
-      RoundResult R = run_round_batch(c, cur, alt, b, B, mr, os);
+      RoundResult R = run_round_batch(c, cur, alt, b, B, mr, os, learned, learned);
       deferred += R.deferred;
-      for (int m = 0; m < nmesh; m++) {
+      // per-mesh outcome of the round (tallies in the host mirror)
+      auto absorb = [&](int m) {
         MeshRun& r = mr[m];
-        if (!r.active) continue;
-        const bool had = R.ncand > 0;  // otherwise the tallies of the round were never filled
-        int ncm = had ? c->hbt[B.ncand_m() + m] : 0;
-        int cm = had ? c->hbt[B.commits_m() + m] : 0;
+        int ncm = c->hbt[B.ncand_m() + m];
+        int cm = c->hbt[B.commits_m() + m];
         const int* hm = c->hbt + B.hist_m() + 8 * m;
         r.st.rounds++;
         r.st.candidates += ncm;
         r.st.commits += cm;
-        if (had) {
-          r.st.rej_link += hm[1];
-          r.st.rej_flip += hm[2];
-          r.st.rej_isect += hm[3];
-          r.st.capped += hm[4];
-        }
-        r.st.undo_hist[std::min(had ? c->hbt[B.undo_m() + m] : 0, 4)]++;
+        r.st.rej_link += hm[1];
+        r.st.rej_flip += hm[2];
+        r.st.rej_isect += hm[3];
+        r.st.capped += hm[4];
+        r.st.undo_hist[std::min(c->hbt[B.undo_m() + m], 4)]++;
         r.streak = cm == 0 ? r.streak + 1 : 0;
+      };
+      std::vector<int> retry;
+      for (int m = 0; m < nmesh; m++) {
+        if (!mr[m].active) continue;
+        const int dm = c->hbt[B.demote_m() + m];
+        mr[m].st.demoted += dm;
+        if (learned && dm > 0 && c->hbt[B.commits_m() + m] == 0) {
+          retry.push_back(m);  // set candidates aside and committed nothing: run it again plain
+          continue;
+        }
+        absorb(m);
+      }
+      if (!retry.empty()) {
+        for (int m = 0; m < nmesh; m++) mr[m].active = false;
+        for (int m : retry) mr[m].active = true;
+        RoundResult R2 = run_round_batch(c, cur, alt, b, B, mr, os, false, learned);
+        deferred += R2.deferred;
+        for (int m : retry) {
+          mr[m].st.fallbacks++;
+          absorb(m);
+        }
       }
     }
     launch_batch_output(s, cur, B.d(B.f_off()), B.d(B.v_off()), B.d(B.f_off()), B.d(B.v_off()), nmesh, V_out, F_out);
@@ -1071,6 +1224,171 @@ pamo_status pamo_simplify_batch(pamo_ctx* c, int32_t nmesh, const double* V, con
       }
     }
     return any_unreached ? PAMO_TARGET_UNREACHED : PAMO_OK;
+  });
+}
+
+// ------------------------------------------------------------ learned proposal
+static bool on_grid(float w, int e, double kmax) {
+  double k = ldexp((double)w, e);
+  return k == rint(k) && fabs(k) <= kmax;
+}
+
+pamo_status pamo_set_mlp(pamo_ctx* c, const pamo_mlp* m) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!m) {
+      if (c->mlp) PAMO_HIP(hipFree(c->mlp));
+      c->mlp = nullptr;
+      return PAMO_OK;
+    }
+    const int e[3] = {m->e1, m->e2, m->e3};
+    for (int l = 0; l < 3; l++)
+      if (e[l] < 0 || e[l] > 15) fail(PAMO_ERR_ARG, "weight grid exponent outside [0, 15]");
+    if (m->a1 < -30 || m->a1 > 30 || m->a2 < -30 || m->a2 > 30) fail(PAMO_ERR_ARG, "activation shift outside [-30, 30]");
+    const double BMAX = 4194304.0;  // 2^22
+    for (int j = 0; j < 64; j++) {
+      for (int k = 0; k < 32; k++)
+        if (!on_grid(m->w1[j][k], e[0], 127)) fail(PAMO_ERR_ARG, "w1 off its grid");
+      for (int k = 0; k < 64; k++)
+        if (!on_grid(m->w2[j][k], e[1], 127)) fail(PAMO_ERR_ARG, "w2 off its grid");
+      if (!on_grid(m->w3[j], e[2], 127)) fail(PAMO_ERR_ARG, "w3 off its grid");
+      if (!on_grid(m->b1[j], e[0], BMAX) || !on_grid(m->b2[j], e[1], BMAX)) fail(PAMO_ERR_ARG, "bias off its grid");
+    }
+    if (!on_grid(m->b3, e[2], BMAX)) fail(PAMO_ERR_ARG, "bias off its grid");
+    if (!(m->threshold == m->threshold)) fail(PAMO_ERR_ARG, "threshold is NaN");
+    MlpDev h;
+    memset(&h, 0, sizeof(h));
+    // grid values have at most 7 significant bits: bfloat16 holds them
+    // exactly, as the upper half of their float32 bits
+    auto bf = [](float x) {
+      uint32_t u;
+      memcpy(&u, &x, 4);
+      return (uint16_t)(u >> 16);
+    };
+    uint16_t* w1 = reinterpret_cast<uint16_t*>(h.w1);
+    uint16_t* w2 = reinterpret_cast<uint16_t*>(h.w2);
+    for (int j = 0; j < 64; j++) {
+      for (int k = 0; k < 32; k++) w1[j * 32 + k] = bf(m->w1[j][k]);
+      for (int k = 0; k < 64; k++) w2[j * 64 + k] = bf(m->w2[j][k]);
+      h.w3[j] = m->w3[j];
+      h.b1[j] = m->b1[j];
+      h.b2[j] = m->b2[j];
+    }
+    h.b3 = m->b3;
+    h.a1 = m->a1;
+    h.a2 = m->a2;
+    h.threshold = m->threshold;
+    if (!c->mlp) PAMO_HIP(hipMalloc((void**)&c->mlp, sizeof(MlpDev)));
+    PAMO_HIP(hipMemcpyAsync(c->mlp, &h, sizeof(MlpDev), hipMemcpyHostToDevice, c->stream));
+    PAMO_HIP(hipStreamSynchronize(c->stream));
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_features(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                          const int32_t* edges, int64_t ne, float* X, int32_t* ovl) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!V || !F || ne < 0 || (ne > 0 && (!edges || !X))) fail(PAMO_ERR_ARG, "bad arguments");
+    check_sizes(nv, nf);
+    if (ne > 3 * nf) fail(PAMO_ERR_ARG, "more edges than half-edges");
+    hipStream_t s = c->stream;
+    MeshView A = mesh_bufs(c, "mA", nv, nf);
+    load_mesh(c, A, V, F, nullptr);
+    A.ovl = c->ws.get<int>("mA.ovl", nf);
+    int2* dummy = c->ws.get<int2>("w.pairs", 1);
+    whole_mesh_pairs(c, A, dummy, 0, 1, A.ovl);
+    RoundBufs b = round_bufs(c, nv, nf);
+    fill_i32(s, c->dcnt, C_COUNT, 0);
+    if (ne > 0) {
+      hipLaunchKernelGGL(k_check_index, dim3(nblk(ne)), dim3(256), 0, s, edges, ne, (int)(3 * nf), c->dcnt + C_ERR);
+      check_err_bits(readback(c)[C_ERR]);
+      launch_quadrics(s, A, b.Q, c->dcnt + C_ERR);
+      launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR);
+      fill_i32(s, c->dcnt + C_NCAND, 1, (int)ne);
+      launch_features(s, A, b.key, edges, c->dcnt + C_NCAND, (int)ne, A.ovl, X, c->dcnt + C_ERR);
+    }
+    if (ovl) PAMO_HIP(hipMemcpyAsync(ovl, A.ovl, (size_t)nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+    check_err_bits(readback(c)[C_ERR]);
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_mlp_logits(pamo_ctx* c, const float* X, int64_t n, float* logits) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!c->mlp) fail(PAMO_ERR_ARG, "no network set");
+    if (n < 0 || n > INT32_MAX || (n > 0 && (!X || !logits))) fail(PAMO_ERR_ARG, "bad arguments");
+    if (n == 0) return PAMO_OK;
+    int* nd = c->ws.get<int>("mlp.n", 1);
+    fill_i32(c->stream, nd, 1, (int)n);
+    launch_mlp(c->stream, X, nd, (int)n, c->mlp, logits, nullptr, nullptr, nullptr, nullptr);
+    return PAMO_OK;
+  });
+}
+
+static MlpMeta meta_of(const int32_t* m) {
+  if (!m) fail(PAMO_ERR_ARG, "null meta");
+  for (int l = 0; l < 3; l++)
+    if (m[l] < 0 || m[l] > 15) fail(PAMO_ERR_ARG, "weight grid exponent outside [0, 15]");
+  if (m[3] < -30 || m[3] > 30 || m[4] < -30 || m[4] > 30) fail(PAMO_ERR_ARG, "activation shift outside [-30, 30]");
+  return MlpMeta{m[0], m[1], m[2], m[3], m[4]};
+}
+
+pamo_status pamo_mlp_grad(pamo_ctx* c, const float* params, const int32_t* meta, const float* X, const uint8_t* y,
+                          int64_t n, float* grad, float* loss) {
+  return guarded(c, [&]() -> pamo_status {
+    MlpMeta md = meta_of(meta);
+    if (!params || !X || !y || !grad || n < 1 || n > (1 << 18)) fail(PAMO_ERR_ARG, "bad arguments (1 <= n <= 2^18)");
+    hipStream_t s = c->stream;
+    int nb = (int)n, blocks = train_blocks(nb);
+    float* part = c->ws.get<float>("tr.part", (int64_t)blocks * LEARN_NPARAM);
+    float* ploss = c->ws.get<float>("tr.ploss", blocks);
+    float* dloss = c->ws.get<float>("tr.loss", 1);
+    launch_train_grad(s, params, md, X, y, nullptr, 0, nb, n, part, ploss);
+    launch_train_reduce(s, part, ploss, nb, md, const_cast<float*>(params), grad, nullptr, nullptr, 0.0f, 0, dloss);
+    float l = 0;
+    PAMO_HIP(hipMemcpyAsync(&l, dloss, sizeof(float), hipMemcpyDeviceToHost, s));
+    PAMO_HIP(hipStreamSynchronize(s));
+    if (loss) *loss = l;
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_mlp_train(pamo_ctx* c, float* params, float* m, float* v, const int32_t* meta, const float* X,
+                           const uint8_t* y, int64_t n, const int32_t* order, int64_t steps, int64_t batch, float lr,
+                           int64_t t0, float* loss) {
+  return guarded(c, [&]() -> pamo_status {
+    MlpMeta md = meta_of(meta);
+    if (!params || !m || !v || !X || !y || !order || n < 1 || steps < 0 || batch < 1 || batch > (1 << 16) || t0 < 0)
+      fail(PAMO_ERR_ARG, "bad arguments (1 <= batch <= 2^16)");
+    hipStream_t s = c->stream;
+    int nb = (int)batch, blocks = train_blocks(nb);
+    float* part = c->ws.get<float>("tr.part", (int64_t)blocks * LEARN_NPARAM);
+    float* ploss = c->ws.get<float>("tr.ploss", blocks);
+    float* dloss = c->ws.get<float>("tr.loss", 1);
+    for (int64_t st = 0; st < steps; st++) {
+      launch_train_grad(s, params, md, X, y, order, st * batch, nb, n, part, ploss);
+      launch_train_reduce(s, part, ploss, nb, md, params, nullptr, m, v, lr, t0 + st + 1, loss ? loss + st : dloss);
+    }
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_hausdorff(pamo_ctx* c, const double* P, int64_t np, const double* V, int64_t nv, const int32_t* F,
+                           int64_t nf, double* dist, double* dmax) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!P || !V || !F || !dmax || np < 0 || np > INT32_MAX || nv < 1 || nf < 1 || nf > INT32_MAX / 3)
+      fail(PAMO_ERR_ARG, "bad arguments");
+    hipStream_t s = c->stream;
+    fill_i32(s, c->dcnt, C_COUNT, 0);
+    hipLaunchKernelGGL(k_check_index, dim3(nblk(3 * nf)), dim3(256), 0, s, F, 3 * nf, (int)nv, c->dcnt + C_ERR);
+    check_err_bits(readback(c)[C_ERR]);
+    uint64_t* bits = c->ws.get<uint64_t>("hd.max", 1);
+    fill_i32(s, reinterpret_cast<int32_t*>(bits), 2, 0);
+    if (np > 0) launch_point_surface(s, P, (int)np, V, F, (int)nf, dist, bits);
+    uint64_t hb = 0;
+    PAMO_HIP(hipMemcpyAsync(&hb, bits, sizeof(hb), hipMemcpyDeviceToHost, s));
+    PAMO_HIP(hipStreamSynchronize(s));
+    memcpy(dmax, &hb, sizeof(double));
+    return PAMO_OK;
   });
 }
 

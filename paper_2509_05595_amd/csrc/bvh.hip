@@ -174,6 +174,15 @@ __device__ __forceinline__ void load_tri(const double* __restrict__ V, const int
   T.hi[2] = fmax(fmax(T.p[0].z, T.p[1].z), T.p[2].z);
 }
 
+__device__ __forceinline__ bool share_vertex(const Tri& A, const Tri& B) {
+  bool r = false;
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) r |= A.id[i] == B.id[j];
+  return r;
+}
+
 __device__ __forceinline__ bool tri_box_overlap(const Tri& A, const Tri& B) {
 #pragma unroll
   for (int k = 0; k < 3; k++)
@@ -472,6 +481,9 @@ __global__ __launch_bounds__(256, 5) void k_pairs(QueryArgs a) {
     Tri T, U;
     load_tri(a.V, a.F, pr.x, T);
     load_tri(a.V, a.F, pr.y, U);
+    if (a.ovl_cnt && (!a.falive || a.falive[pr.y]) && (!a.fmesh || a.fmesh[pr.y] == a.fmesh[pr.x]) &&
+        !share_vertex(T, U) && tri_box_overlap(T, U))
+      atomicAdd(&a.ovl_cnt[pr.x], 1);
     if (!leaf_candidate<MODE>(a, pr.x, pr.y)) continue;
     if (!tri_box_overlap(T, U)) continue;
     int r = tri_pair<false>(T.p, T.id, U.p, U.id);

@@ -632,6 +632,7 @@ __global__ void k_compact_faces(MeshView src, MeshView dst, const uint8_t* __res
     dst.flags[3 * g + k] = src.flags[h];
   }
   if (src.fmesh) dst.fmesh[g] = src.fmesh[f];
+  if (src.ovl) dst.ovl[g] = src.ovl[f];
 }
 
 __global__ void k_compact_verts(MeshView src, MeshView dst, const uint8_t* __restrict__ valive,
@@ -658,6 +659,16 @@ __global__ void k_remap_order(const int* __restrict__ order, int n, const uint8_
 __global__ void k_flags_or(uint8_t* __restrict__ dst, const uint8_t* __restrict__ src, int64_t n) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) dst[i] |= src[i];
+}
+
+// faces changed by a committed collapse take the overlap count measured on
+// the round's tentative mesh
+__global__ void k_ovl_commit(int nf, const int* __restrict__ owner, const uint8_t* __restrict__ falive,
+                             const int* __restrict__ undone, const int* __restrict__ ovl_new, int* __restrict__ ovl) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf || !falive[f]) return;
+  int o = owner[f];
+  if (o >= 0 && undone[o] == 0) ovl[f] = ovl_new[f];
 }
 
 // state of a check/undo loop: every face alive and unowned, nothing undone
@@ -909,6 +920,12 @@ void launch_remap_order(Workspace& ws, hipStream_t s, const int* order, int nf_o
   uint8_t* pred = ws.get<uint8_t>("ord.pred", nf_old);
   hipLaunchKernelGGL(k_remap_order, dim3(nblk(nf_old)), dim3(256), 0, s, order, nf_old, falive, fmap, tmp, pred);
   compact_flags_map(ws, s, pred, nf_old, tmp, out, count);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_ovl_commit(hipStream_t s, int nf, const int* owner, const uint8_t* falive, const int* undone,
+                       const int* ovl_new, int* ovl) {
+  hipLaunchKernelGGL(k_ovl_commit, dim3(nblk(nf)), dim3(256), 0, s, nf, owner, falive, undone, ovl_new, ovl);
   PAMO_HIP(hipGetLastError());
 }
 

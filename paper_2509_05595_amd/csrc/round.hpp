@@ -23,6 +23,7 @@ struct MeshView {
   int nv, nf;
   int* fmesh = nullptr;  // batches only: mesh of each face / vertex (kept through compaction)
   int* vmesh = nullptr;
+  int* ovl = nullptr;    // learned proposal only: per-face overlap counts (kept through compaction)
 };
 
 // Batches keep their meshes apart in the BVH by shifting each mesh's boxes
@@ -48,6 +49,9 @@ void launch_local_check(hipStream_t s, MeshView m, const double* Q, double w_e, 
 void launch_cap(Workspace& ws, hipStream_t s, const int* ncand, int nc_host, const uint64_t* ckey, uint8_t* reason,
                 int64_t need);
 void launch_face_boxes(hipStream_t s, MeshView m, float* box);
+// ovl[f] = ovl_new[f] for the alive faces of committed collapses
+void launch_ovl_commit(hipStream_t s, int nf, const int* owner, const uint8_t* falive, const int* undone,
+                       const int* ovl_new, int* ovl);
 // falive[0..nf) = 1, owner[0..nf) = -1, undone[0..ncand) = 0
 void launch_check_reset(hipStream_t s, int nf, uint8_t* falive, int* owner, int ncand, int* undone);
 void launch_apply(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const uint8_t* reason,
@@ -137,6 +141,7 @@ struct QueryArgs {
   int* ncand;
   int cand_cap;
   const int* fmesh;       // batches: mesh of each face (query boxes are shifted like the tree's)
+  int* ovl_cnt;           // when set: per query face, the alive faces sharing no vertex whose boxes meet it
   int* err;
 };
 

@@ -20,7 +20,8 @@ ERRORS = {-1: "ARG", -2: "NONMANIFOLD", -3: "SELF_INTERSECTING", -4: "DEGENERATE
 
 EXPORTS = ["pamo_default_options", "pamo_create", "pamo_destroy", "pamo_set_options", "pamo_last_error",
            "pamo_workspace_bytes", "pamo_quadrics", "pamo_select", "pamo_check", "pamo_collapse",
-           "pamo_simplify", "pamo_simplify_batch", "pamo_self_intersections", "pamo_tri_pairs", "pamo_profile_enable",
+           "pamo_simplify", "pamo_simplify_batch", "pamo_set_mlp", "pamo_features", "pamo_mlp_logits",
+           "pamo_collect", "pamo_mlp_grad", "pamo_mlp_train", "pamo_hausdorff", "pamo_self_intersections", "pamo_tri_pairs", "pamo_profile_enable",
            "pamo_profile_phases", "pamo_profile_name", "pamo_profile_read", "pamo_profile_reset"]
 
 
@@ -28,19 +29,45 @@ class Options(C.Structure):
     _fields_ = [("w_e", C.c_double), ("w_s", C.c_double), ("tolerance", C.c_int32),
                 ("max_rounds", C.c_int32), ("validate_input", C.c_int32), ("query_packet", C.c_int32),
                 ("resort_every", C.c_int32), ("query_coop", C.c_int32), ("coop_below", C.c_int32),
-                ("reserved", C.c_int32 * 1)]
+                ("learned", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("rounds", C.c_int64), ("faces_out", C.c_int64), ("verts_out", C.c_int64),
                 ("candidates", C.c_int64), ("commits", C.c_int64), ("rej_link", C.c_int64),
                 ("rej_flip", C.c_int64), ("rej_isect", C.c_int64), ("capped", C.c_int64),
-                ("undo_hist", C.c_int64 * 5), ("deferred_pairs", C.c_int64), ("status", C.c_int64)]
+                ("undo_hist", C.c_int64 * 5), ("deferred_pairs", C.c_int64), ("status", C.c_int64),
+                ("demoted", C.c_int64), ("fallbacks", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "undo_hist"}
         d["undo_hist"] = list(self.undo_hist)
         return d
+
+
+NFEAT = 32
+NPARAM = 6337
+
+
+class MLP(C.Structure):
+    """pamo_mlp: the learned proposal's network (include/pamo.h)."""
+    _fields_ = [("w1", (C.c_float * 32) * 64), ("b1", C.c_float * 64), ("w2", (C.c_float * 64) * 64),
+                ("b2", C.c_float * 64), ("w3", C.c_float * 64), ("b3", C.c_float),
+                ("e1", C.c_int32), ("e2", C.c_int32), ("e3", C.c_int32), ("a1", C.c_int32), ("a2", C.c_int32),
+                ("threshold", C.c_float)]
+
+
+def mlp_struct(model: dict) -> MLP:
+    import numpy as np
+    m = MLP()
+    for k in ("w1", "b1", "w2", "b2", "w3"):
+        a = np.ascontiguousarray(model[k], dtype=np.float32)
+        C.memmove(C.addressof(getattr(m, k)), a.ctypes.data, a.nbytes)
+    m.b3 = float(model["b3"])
+    for k in ("e1", "e2", "e3", "a1", "a2"):
+        setattr(m, k, int(model[k]))
+    m.threshold = float(model["threshold"])
+    return m
 
 
 class PamoError(RuntimeError):
@@ -77,6 +104,13 @@ def lib():
         L.pamo_simplify.argtypes = [P, P, I64, P, I64, I64, P, C.POINTER(I64), P, C.POINTER(I64),
                                     C.POINTER(Stats)]
         L.pamo_simplify_batch.argtypes = [P, I32, P, P, P, P, P, P, P, P, P, P]
+        L.pamo_set_mlp.argtypes = [P, P]
+        L.pamo_features.argtypes = [P, P, I64, P, I64, P, I64, P, P]
+        L.pamo_mlp_logits.argtypes = [P, P, I64, P]
+        L.pamo_collect.argtypes = [P, P, I64, P, I64, I64, P, P, I64, C.POINTER(I64), C.POINTER(Stats)]
+        L.pamo_mlp_grad.argtypes = [P, P, P, P, P, I64, P, C.POINTER(C.c_float)]
+        L.pamo_mlp_train.argtypes = [P, P, P, P, P, P, P, I64, P, I64, I64, C.c_float, I64, P]
+        L.pamo_hausdorff.argtypes = [P, P, I64, P, I64, P, I64, P, C.POINTER(C.c_double)]
         L.pamo_self_intersections.argtypes = [P, P, I64, P, I64, P, I64, C.POINTER(I64)]
         L.pamo_tri_pairs.argtypes = [P, P, P, P, P, I64, P]
         L.pamo_profile_enable.argtypes = [P, C.c_uint32]
@@ -227,6 +261,71 @@ class Context:
                                               h(vo), _ptr(Fo), h(fo), st),
                     allow=(PAMO_OK, PAMO_TARGET_UNREACHED))
         return [(Vo[vo[m]:vo[m + 1]], Fo[fo[m]:fo[m + 1]], st[m].as_dict()) for m in range(n)]
+
+    # ---- learned proposal
+    def set_mlp(self, model):
+        """model: dict (w1, b1, w2, b2, w3, b3, e1, e2, e3, a1, a2, threshold) or None."""
+        if model is None:
+            self._check(lib().pamo_set_mlp(self._h, None))
+            return
+        m = mlp_struct(model)
+        self._check(lib().pamo_set_mlp(self._h, C.byref(m)))
+
+    def features(self, V, F, edges):
+        """(features float32 [n, 32], overlap counts int32 [nf]) of the given half-edges."""
+        V, F = self._mesh(V, F)
+        e = edges.to(self.device, torch.int32).contiguous()
+        X = torch.zeros((max(1, e.shape[0]), NFEAT), dtype=torch.float32, device=self.device)
+        ovl = torch.zeros(F.shape[0], dtype=torch.int32, device=self.device)
+        self._check(lib().pamo_features(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(e), e.shape[0],
+                                        _ptr(X), _ptr(ovl)))
+        return X[: e.shape[0]], ovl
+
+    def mlp_logits(self, X):
+        X = X.to(self.device, torch.float32).contiguous()
+        out = torch.empty(max(1, X.shape[0]), dtype=torch.float32, device=self.device)
+        self._check(lib().pamo_mlp_logits(self._h, _ptr(X), X.shape[0], _ptr(out)))
+        return out[: X.shape[0]]
+
+    def collect(self, V, F, target, cap):
+        """Plain run logging training rows: (X [n, 32], y [n], stats)."""
+        V, F = self._mesh(V, F)
+        X = torch.empty((max(1, cap), NFEAT), dtype=torch.float32, device=self.device)
+        y = torch.empty(max(1, cap), dtype=torch.uint8, device=self.device)
+        n, st = C.c_int64(0), Stats()
+        self._check(lib().pamo_collect(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], int(target), _ptr(X),
+                                       _ptr(y), int(cap), C.byref(n), C.byref(st)),
+                    allow=(PAMO_OK, PAMO_TARGET_UNREACHED))
+        return X[: n.value], y[: n.value], st.as_dict()
+
+    def mlp_grad(self, params, meta, X, y):
+        import numpy as np
+        md = np.ascontiguousarray(meta, dtype=np.int32)
+        g = torch.empty(NPARAM, dtype=torch.float32, device=self.device)
+        loss = C.c_float(0)
+        self._check(lib().pamo_mlp_grad(self._h, _ptr(params), md.ctypes.data_as(C.c_void_p), _ptr(X), _ptr(y),
+                                        X.shape[0], _ptr(g), C.byref(loss)))
+        return g, loss.value
+
+    def mlp_train(self, params, m, v, meta, X, y, order, steps, batch, lr, t0):
+        """Adam steps in place on params (and moments m, v); returns per-step losses."""
+        import numpy as np
+        md = np.ascontiguousarray(meta, dtype=np.int32)
+        loss = torch.empty(max(1, steps), dtype=torch.float32, device=self.device)
+        self._check(lib().pamo_mlp_train(self._h, _ptr(params), _ptr(m), _ptr(v), md.ctypes.data_as(C.c_void_p),
+                                         _ptr(X), _ptr(y), int(X.shape[0]), _ptr(order), int(steps), int(batch),
+                                         float(lr), int(t0), _ptr(loss)))
+        return loss[:steps]
+
+    def hausdorff(self, P, V, F, per_point=False):
+        """Largest distance from the points P to the surface (V, F) (and each point's)."""
+        V, F = self._mesh(V, F)
+        P = P.contiguous()
+        d = torch.empty(max(1, P.shape[0]), dtype=torch.float64, device=self.device) if per_point else None
+        dm = C.c_double(0)
+        self._check(lib().pamo_hausdorff(self._h, _ptr(P), P.shape[0], _ptr(V), V.shape[0], _ptr(F), F.shape[0],
+                                         _ptr(d), C.byref(dm)))
+        return (dm.value, d[: P.shape[0]]) if per_point else dm.value
 
     def self_intersections(self, V, F, cap=1 << 16):
         V, F = self._mesh(V, F)

@@ -1,0 +1,234 @@
+"""GPU parity of the learned proposal: features, overlap counts, the network's
+logits (all bit for bit), learned runs and logged training rows (bit for bit
+against the oracle), training gradients and Adam steps (against the float64
+reference, float32 rounding tolerance) and the Hausdorff distance."""
+import numpy as np
+import pytest
+
+import oracle.hausdorff as hd
+import oracle.mlp_train as mt
+import oracle.oracle as orc
+from paper_2509_05595_amd import meshgen as g
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_05595_amd import native
+    c = native.Context("cuda:0")
+    yield c
+    c.close()
+
+
+def dev(V, F):
+    return (torch.from_numpy(np.ascontiguousarray(V, dtype=np.float64)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(F, dtype=np.int32)).cuda())
+
+
+def same(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    if a.dtype == np.float64:
+        return np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    return np.array_equal(a, b)
+
+
+MESHES = {
+    "nested": lambda: g.nested_spheres(k=3, gap=0.01),
+    "noisy": lambda: g.bumpy_icosphere_gauss(k=3, seed=4),
+    "torus": lambda: g.bumpy_torus(32, 12, seed=2),
+    "crease": lambda: g.crease_sphere(3, 5),
+}
+
+
+def random_model(seed, threshold=0.0, e=(9, 9, 9), a=(-3, -3)):
+    rng = np.random.default_rng(seed)
+    f = np.float32
+    return {"w1": (rng.integers(-127, 128, (64, 32)) * 2.0 ** -e[0]).astype(f),
+            "b1": (rng.integers(-2000, 2000, 64) * 2.0 ** -e[0]).astype(f),
+            "w2": (rng.integers(-127, 128, (64, 64)) * 2.0 ** -e[1]).astype(f),
+            "b2": (rng.integers(-2000, 2000, 64) * 2.0 ** -e[1]).astype(f),
+            "w3": (rng.integers(-127, 128, 64) * 2.0 ** -e[2]).astype(f),
+            "b3": float(rng.integers(-2000, 2000)) * 2.0 ** -e[2],
+            "e1": e[0], "e2": e[1], "e3": e[2], "a1": a[0], "a2": a[1], "threshold": threshold}
+
+
+def crowding_model():
+    """sets aside candidates whose neighbourhood overlaps more than 4 faces"""
+    m = random_model(0, e=(0, 0, 0))  # unit weights: grid 2^0
+    for k in ("w1", "b1", "w2", "b2", "w3"):
+        m[k][:] = 0
+    m["w1"][0, 9] = 1.0
+    m["w2"][0, 0] = 1.0
+    m["w3"][0] = -1.0
+    m["b3"] = 4.0
+    m["a1"] = m["a2"] = 0
+    return m
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_features_and_overlap_counts_bitwise(ctx, name):
+    V, F = MESHES[name]()
+    cand = orc.select(V, F)
+    Xo, ovl_o = orc.features(V, F, cand)
+    Vd, Fd = dev(V, F)
+    X, ovl = ctx.features(Vd, Fd, torch.from_numpy(cand))
+    assert np.array_equal(ovl.cpu().numpy(), ovl_o)
+    assert np.array_equal(X.cpu().numpy(), Xo)
+
+
+def test_mlp_logits_bitwise(ctx):
+    rng = np.random.default_rng(5)
+    X = rng.integers(-127, 128, (1000, 32)).astype(np.float32)  # ragged: not a multiple of 16 rows
+    X[:, 11:] = 0
+    for seed, a in ((1, (-3, -3)), (2, (-5, -2)), (3, (0, -4))):
+        m = random_model(seed, a=a)
+        ctx.set_mlp(m)
+        got = ctx.mlp_logits(torch.from_numpy(X).cuda()).cpu().numpy()
+        want = orc.mlp_logits(m, X)
+        assert np.array_equal(got.astype(np.float64), want)
+    ctx.set_mlp(None)
+
+
+def test_set_mlp_rejects_values_off_their_grid(ctx):
+    from paper_2509_05595_amd import native
+    m = random_model(1)
+    m["w2"][3, 4] = np.float32(0.3)  # not a multiple of 2^-9
+    with pytest.raises(native.PamoError):
+        ctx.set_mlp(m)
+    m = random_model(1)
+    m["w1"][0, 0] = np.float32(200 * 2.0 ** -9)  # |k| > 127
+    with pytest.raises(native.PamoError):
+        ctx.set_mlp(m)
+
+
+@pytest.mark.parametrize("name,target,model", [("nested", 400, "crowding"), ("nested", 400, "random"),
+                                                ("noisy", 200, "random"), ("torus", 80, "crowding")])
+def test_learned_run_bitwise(ctx, name, target, model):
+    from paper_2509_05595_amd import native
+    V, F = MESHES[name]()
+    m = crowding_model() if model == "crowding" else random_model(7, threshold=-2.0)
+    ctx.set_mlp(m)
+    ctx.set_options(native.default_options(learned=1))
+    try:
+        Vo, Fo, st = ctx.simplify(*dev(V, F), target)
+    finally:
+        ctx.set_options(native.default_options())
+        ctx.set_mlp(None)
+    r = orc.run_learned(V, F, target, m)
+    assert same(Fo.cpu().numpy(), r["F"]) and same(Vo.cpu().numpy(), r["V"])
+    assert st["demoted"] == r["demoted"] and st["fallbacks"] == r["fallbacks"]
+    for k in ("rounds", "commits", "rej_link", "rej_flip", "rej_isect", "capped", "status"):
+        assert st[k] == r["stats"][k], k
+    assert st["undo_hist"] == r["stats"]["undo_hist"]
+
+
+def test_learned_run_needs_a_network(ctx):
+    from paper_2509_05595_amd import native
+    V, F = MESHES["noisy"]()
+    ctx.set_options(native.default_options(learned=1))
+    try:
+        with pytest.raises(native.PamoError):
+            ctx.simplify(*dev(V, F), 100)
+    finally:
+        ctx.set_options(native.default_options())
+
+
+@pytest.mark.parametrize("name,target", [("nested", 400), ("crease", 60)])
+def test_collected_rows_bitwise(ctx, name, target):
+    V, F = MESHES[name]()
+    Xo, yo, _ = orc.collect(V, F, target)
+    X, y, st = ctx.collect(*dev(V, F), target, cap=len(Xo) + 100)
+    assert np.array_equal(y.cpu().numpy(), yo)
+    assert np.array_equal(X.cpu().numpy(), Xo)
+    # a smaller cap keeps the first rows
+    X2, y2, _ = ctx.collect(*dev(V, F), target, cap=len(Xo) // 3)
+    assert np.array_equal(X2.cpu().numpy(), Xo[: len(Xo) // 3])
+
+
+META = {"e1": 9, "e2": 9, "e3": 9, "a1": -3, "a2": -3}
+
+
+def train_data(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.integers(-127, 128, (n, 32)).astype(np.float32)
+    X[:, 11:] = 0
+    y = (X[:, 0] + X[:, 4] > 0).astype(np.uint8)
+    return X, y
+
+
+def test_gradient_against_float64_reference(ctx):
+    rng = np.random.default_rng(8)
+    P = rng.normal(0, 0.05, mt.NPARAM).astype(np.float32)
+    meta = [META[k] for k in ("e1", "e2", "e3", "a1", "a2")]
+    for n in (1, 45, 1000):  # ragged last block of 32 rows
+        X, y = train_data(n, n)
+        g_gpu, l_gpu = ctx.mlp_grad(torch.from_numpy(P).cuda(), meta, torch.from_numpy(X).cuda(),
+                                    torch.from_numpy(y).cuda())
+        l_ref, g_ref = mt.loss_and_grad(P.astype(np.float64), META, X, y)
+        g_gpu = g_gpu.cpu().numpy()
+        assert abs(l_gpu - l_ref) <= 1e-5 * max(1.0, abs(l_ref))
+        scale = np.abs(g_ref).max()
+        assert np.abs(g_gpu - g_ref).max() <= 1e-5 * scale, np.abs(g_gpu - g_ref).max() / scale
+
+
+def test_adam_steps_against_float64_reference(ctx):
+    rng = np.random.default_rng(9)
+    P0 = rng.normal(0, 0.05, mt.NPARAM).astype(np.float32)
+    meta = [META[k] for k in ("e1", "e2", "e3", "a1", "a2")]
+    X, y = train_data(256, 3)
+    order = rng.permutation(256).astype(np.int32)[:192]  # 3 steps of 64
+    P = torch.from_numpy(P0.copy()).cuda()
+    m = torch.zeros(mt.NPARAM, device="cuda")
+    v = torch.zeros(mt.NPARAM, device="cuda")
+    losses = ctx.mlp_train(P, m, v, meta, torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(),
+                           torch.from_numpy(order).cuda(), steps=3, batch=64, lr=1e-3, t0=0).cpu().numpy()
+    Pr, mr, vr = P0.astype(np.float64), np.zeros(mt.NPARAM), np.zeros(mt.NPARAM)
+    for s in range(3):
+        idx = order[64 * s: 64 * (s + 1)]
+        l, gr = mt.loss_and_grad(Pr, META, X[idx], y[idx])
+        assert abs(losses[s] - l) <= 1e-5 * max(1.0, abs(l))
+        Pr, mr, vr = mt.adam(Pr, mr, vr, gr, s + 1, 1e-3)
+    # Adam normalises each step to about lr: a gradient within float32 noise of
+    # zero may take either sign, moving that parameter by up to 2 lr per step;
+    # every other parameter agrees to float32 rounding
+    diff = np.abs(P.cpu().numpy() - Pr)
+    assert np.quantile(diff, 0.99) <= 1e-6
+    assert diff.max() <= 6e-3 + 1e-6
+
+
+def test_hausdorff_against_reference(ctx):
+    V, F = g.bumpy_icosphere_gauss(k=3, seed=1)
+    r = orc.run(V, F, 64)
+    Vd, Fd = dev(r["V"], r["F"])
+    P = torch.from_numpy(V).cuda()
+    dmax, d = ctx.hausdorff(P, Vd, Fd, per_point=True)
+    d_ref = hd.distances(V, r["V"], r["F"])
+    assert np.allclose(d.cpu().numpy(), d_ref, rtol=1e-12, atol=1e-15)
+    assert np.isclose(dmax, d_ref.max(), rtol=1e-12)
+    assert ctx.hausdorff(Vd, Vd, Fd) == 0.0
+
+
+def test_learned_batch_matches_single_and_oracle(ctx):
+    from paper_2509_05595_amd import native
+    meshes = [MESHES["nested"](), MESHES["noisy"](), g.nested_spheres(k=2, gap=0.02), MESHES["torus"]()]
+    targets = [400, 200, 64, 80]
+    m = crowding_model()
+    ctx.set_mlp(m)
+    ctx.set_options(native.default_options(learned=1))
+    try:
+        dm = [dev(V, F) for V, F in meshes]
+        out = ctx.simplify_batch(dm, targets)
+        single = [ctx.simplify(Vd, Fd, t) for (Vd, Fd), t in zip(dm, targets)]
+    finally:
+        ctx.set_options(native.default_options())
+        ctx.set_mlp(None)
+    for i, ((V, F), t, (Vb, Fb, sb), (Vs, Fs, ss)) in enumerate(zip(meshes, targets, out, single)):
+        assert same(Fb.cpu().numpy(), Fs.cpu().numpy()) and same(Vb.cpu().numpy(), Vs.cpu().numpy()), i
+        for k in ("rounds", "commits", "rej_isect", "status", "demoted", "fallbacks", "undo_hist"):
+            assert sb[k] == ss[k], (i, k)
+        r = orc.run_learned(V, F, t, m)
+        assert same(Fb.cpu().numpy(), r["F"]) and same(Vb.cpu().numpy(), r["V"]), i

@@ -133,7 +133,7 @@ def test_learned_run_without_set_aside_equals_plain():
 def test_learned_run_valid_output():
     V, F = g.nested_spheres(k=3, gap=0.01)
     # a model that sets aside edges with many overlapping faces around them
-    m = random_model(np.random.default_rng(2), threshold=0.0)
+    m = random_model(np.random.default_rng(2), e=(0, 0, 0), threshold=0.0)
     m["w1"][:] = 0
     m["b1"][:] = 0
     m["w1"][0, 9] = 1.0  # unit 0 = sum of overlap counts
@@ -202,3 +202,28 @@ def test_adam_first_step_closed_form():
     g_ = rng.normal(0, 1, 50)
     P1, m, v = mt.adam(P, np.zeros(50), np.zeros(50), g_, 1, lr=0.01)
     assert np.allclose(P1, P - 0.01 * g_ / (np.abs(g_) + 1e-8))
+
+
+def test_point_triangle_distance_regions():
+    import oracle.hausdorff as hd
+    A, B, C = np.array([[0.0, 0, 0]]), np.array([[1.0, 0, 0]]), np.array([[0.0, 1, 0]])
+    cases = [([0.25, 0.25, 0.7], 0.7),                      # above the interior: the height
+             ([-1.0, -1.0, 0.0], np.sqrt(2.0)),             # beyond vertex A
+             ([0.5, -2.0, 1.0], np.sqrt(5.0)),              # beside edge AB
+             ([1.0, 1.0, 0.0], np.sqrt(0.5)),               # beside edge BC, in the plane
+             ([3.0, 0.0, 4.0], np.sqrt(4.0 + 16.0))]        # beyond vertex B
+    for p, d in cases:
+        assert np.isclose(hd.point_tris(np.array(p), A, B, C)[0], d, rtol=1e-14)
+
+
+def test_hausdorff_of_a_mesh_to_itself_and_a_scaled_copy():
+    import oracle.hausdorff as hd
+    V, F = g.icosphere(2)
+    assert hd.hausdorff(V, V, F) == 0.0
+    # a sphere scaled by 1.1 about its centre: every vertex of the big one is
+    # at least 0.1 r from the small mesh (which lies inside the unit sphere)
+    c = V.mean(axis=0)
+    big = c + 1.1 * (V - c)
+    r = np.linalg.norm(V - c, axis=1).max()
+    d = hd.hausdorff(big, V, F)
+    assert 0.1 * r - 1e-12 <= d <= 0.1 * r + 0.02 * r
