@@ -201,7 +201,10 @@ pamo_status pamo_tri_pairs(pamo_ctx* ctx, const double* P, const int32_t* ip, co
  * aside for the round (their key becomes the largest) and the selection is
  * redone, so a neighbour of a likely rejection can collapse instead.  Every
  * collapse still passes every check of Sec. 5.1 and 5.2.  A round that sets
- * candidates aside and commits nothing runs again without the network.
+ * candidates aside and commits nothing runs again without the network.  The
+ * network is consulted only in rounds that follow a round whose checks
+ * rejected at least one candidate (per mesh in a batch; the first round is
+ * plain): where nothing is rejected it has nothing to predict.
  *
  * Features of edge (a, b), each scaled by a fixed power of two and rounded to
  * an integer in [-127, 127]; S = star(a) u star(b), spokes = edges of S's

@@ -608,7 +608,9 @@ static void query_face(const omesh *m, const ogrid *G, int64_t t, int64_t *stamp
  * becomes the largest) and the selection is redone, so that a neighbour of a
  * likely rejection can be collapsed instead.  Every collapse still passes
  * every check; a round that sets candidates aside and then commits nothing is
- * run again without the network.
+ * run again without the network.  The network is consulted only in rounds
+ * that follow a round whose checks rejected at least one candidate (the first
+ * round is plain): where nothing gets rejected it has nothing to predict.
  *
  * Per-face state for the overlap feature: ovl[f] counts the alive faces that
  * share no vertex with f and whose float64 boxes meet f's box (closed).  It is
@@ -1189,6 +1191,7 @@ static int run_impl(const double *V, int64_t nv, const int32_t *F, int64_t nf,
     }
     int64_t teff = target - (target % 2);
     int err = 0;
+    int prev_rejected = 0; /* the network is consulted only after a round whose checks rejected something */
     for (;;) {
         int64_t falive = count_alive_faces(&m);
         if (falive <= teff) { st->status = 0; break; }
@@ -1212,7 +1215,7 @@ static int run_impl(const double *V, int64_t nv, const int32_t *F, int64_t nf,
             for (int64_t c = 0; c < n0; c++) edge_features(&m, ovl, c0[c], feat + NFEAT * c);
             free(c0);
         }
-        err = run_round(&m, teff, opt, &r, 0, mlp, ovl);
+        err = run_round(&m, teff, opt, &r, 0, prev_rejected ? mlp : NULL, ovl);
         if (err) { free(feat); break; }
         if (learned_info) learned_info[0] += r.demoted;
         if (r.retry) {
@@ -1238,6 +1241,7 @@ static int run_impl(const double *V, int64_t nv, const int32_t *F, int64_t nf,
             ri += r.reason[c] == 3;
             cp += r.reason[c] == 4;
         }
+        prev_rejected = rl + rf + ri > 0;
         if (log && st->rounds < log_cap) {
             oracle_round_log *L = log + st->rounds;
             L->faces = falive; L->verts = valive; L->edges = falive * 3 / 2;

@@ -318,6 +318,7 @@ struct RoundResult {
 // training rows (features and outcome of each candidate the checks decided).
 struct LearnRun {
   bool learned = false;
+  bool active = false;  // consult the network this round (the previous round's checks rejected something)
   bool track = false;
   float* X = nullptr;  // logging: rows [cap][32] and labels [cap] (device)
   uint8_t* y = nullptr;
@@ -454,7 +455,7 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs
   RoundResult R;
   fill_i32(s, cnt, C_COUNT, 0);
   const double nf = cur.nf, nv = cur.nv;
-  const bool learned = L && L->learned;
+  const bool learned = L && L->learned && L->active;
   const bool logging = L && L->X;
   {
     TIMED(PH_QUADRICS, 108 * nv + 24 * nf);
@@ -664,6 +665,7 @@ struct Batch {
   int* dev = nullptr;      // [T_COUNT]
   int* need = nullptr;     // [n] collapses still needed (0 for stopped meshes)
   uint8_t* done = nullptr; // [n]
+  uint8_t* use = nullptr;  // [n] consult the network for this mesh this round
   int ncand_m() const { return 0; }
   int npass_m() const { return n; }
   int commits_m() const { return 2 * n; }
@@ -682,7 +684,8 @@ Batch batch_bufs(pamo_ctx* c, int n) {
   B.dev = c->ws.get<int>("bt.dev", B.total());
   B.need = c->ws.get<int>("bt.need", n);
   B.done = c->ws.get<uint8_t>("bt.done", n);
-  size_t want = (size_t)B.total() + n + (n + 3) / 4;
+  B.use = c->ws.get<uint8_t>("bt.use", n);
+  size_t want = (size_t)B.total() + n + 2 * ((n + 3) / 4);
   if (c->hbt_n < want) {
     if (c->hbt) PAMO_HIP(hipHostFree(c->hbt));
     c->hbt = nullptr;
@@ -696,6 +699,7 @@ Batch batch_bufs(pamo_ctx* c, int n) {
 // host staging of the per-round uploads, behind the tally mirror
 int* host_need(pamo_ctx* c, const Batch& B) { return c->hbt + B.total(); }
 uint8_t* host_done(pamo_ctx* c, const Batch& B) { return (uint8_t*)(c->hbt + B.total() + B.n); }
+uint8_t* host_use(pamo_ctx* c, const Batch& B) { return (uint8_t*)(c->hbt + B.total() + B.n + (B.n + 3) / 4); }
 
 // counters and tallies in one synchronisation
 const int* readback_batch(pamo_ctx* c, const Batch& B) {
@@ -710,6 +714,7 @@ struct MeshRun {
   int64_t teff = 0;
   int streak = 0;
   bool active = false;
+  bool rejected = false;  // the mesh's previous round had check rejections
   pamo_stats st{};
 };
 
@@ -732,6 +737,16 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const Rou
   }
   PAMO_HIP(hipMemcpyAsync(B.need, hneed, n * sizeof(int), hipMemcpyHostToDevice, s));
   PAMO_HIP(hipMemcpyAsync(B.done, hdone, n, hipMemcpyHostToDevice, s));
+  if (learned) {
+    uint8_t* huse = host_use(c, B);
+    bool any = false;
+    for (int m = 0; m < n; m++) {
+      huse[m] = mr[m].active && mr[m].rejected;
+      any |= huse[m] != 0;
+    }
+    learned = any;
+    if (any) PAMO_HIP(hipMemcpyAsync(B.use, huse, n, hipMemcpyHostToDevice, s));
+  }
   const double nf = cur.nf, nv = cur.nv;
   {
     TIMED(PH_QUADRICS, 108 * nv + 24 * nf);
@@ -750,7 +765,7 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const Rou
     TIMED(PH_LEARN, 0);
     launch_features(s, cur, b.key, b.cand, cnt + C_NCAND, bound, cur.ovl, b.X, cnt + C_ERR);
     launch_mlp(s, b.X, cnt + C_NCAND, bound, c->mlp, nullptr, b.cand, cur.twin, b.key, cnt + C_NDEMOTE, cur.fmesh,
-               B.d(B.demote_m()));
+               B.d(B.demote_m()), B.use);
     launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
   }
   local_checks(c, cur, b, b.cand, cnt + C_NCAND, bound, b.reason, b.vbar);
@@ -863,6 +878,7 @@ pamo_status simplify_run(pamo_ctx* c, const double* V, int64_t nv, const int32_t
     RoundResult R = run_round_learned(c, cur, alt, b, teff, os, L);
     add_stats(&st, R);
     streak = R.commits == 0 ? streak + 1 : 0;
+    L->active = R.hist[1] + R.hist[2] + R.hist[3] > 0;  // the network has something to predict
   }
   PAMO_HIP(hipMemcpyAsync(V_out, cur.V, 3 * (size_t)cur.nv * sizeof(double), hipMemcpyDeviceToDevice, s));
   PAMO_HIP(hipMemcpyAsync(F_out, cur.F, 3 * (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
@@ -1185,6 +1201,7 @@ pamo_status pamo_simplify_batch(pamo_ctx* c, int32_t nmesh, const double* V, con
         r.st.capped += hm[4];
         r.st.undo_hist[std::min(c->hbt[B.undo_m() + m], 4)]++;
         r.streak = cm == 0 ? r.streak + 1 : 0;
+        r.rejected = hm[1] + hm[2] + hm[3] > 0;
       };
       std::vector<int> retry;
       for (int m = 0; m < nmesh; m++) {

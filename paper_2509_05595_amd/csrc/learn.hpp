@@ -30,10 +30,11 @@ void launch_features(hipStream_t s, MeshView m, const uint64_t* key, const int* 
                      const int* ovl, float* X, int* err);
 // logits of X[0..*n_dev) into out (may be null); with key non-null, rows under
 // the threshold set their edge cand[row] aside (largest key on both
-// half-edges) and count into *ndemote (and ndemote_m[mesh] when fmesh is set)
+// half-edges) and count into *ndemote (and ndemote_m[mesh] when fmesh is set;
+// then only meshes with use_m[mesh] set candidates aside)
 void launch_mlp(hipStream_t s, const float* X, const int* n_dev, int bound, const MlpDev* M, float* out,
                 const int* cand, const int* twin, uint64_t* key, int* ndemote, const int* fmesh = nullptr,
-                int* ndemote_m = nullptr);
+                int* ndemote_m = nullptr, const uint8_t* use_m = nullptr);
 // batches: reason 5 (no flag) for the candidates of meshes that set
 // candidates aside and committed nothing (their round runs again)
 void launch_mark_retry(hipStream_t s, const int* cand, const int* ncand, int bound, const int* fmesh,
