@@ -45,6 +45,28 @@ def cpu_baseline():
                       f"({len(r['F'])} faces), serial C oracle, {dt:.1f} s"}
 
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "query__noisy-icosphere-1310720f-to-1pct.md")
+
+
+def measured_traffic(phase):
+    """HBM bytes per launch of `phase` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counts), or None
+    when there is none or the kernel source changed since it was taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    val, ok = None, False
+    for line in open(TRAFFIC_PROFILE):
+        f = line.split()
+        if len(f) == 3 and f[0] == "traffic_bytes_per_launch" and f[1] == phase:
+            val = float(f[2])
+        if len(f) == 3 and f[0] == "source_sha256":
+            path = os.path.join(HERE, f[1])
+            ok = os.path.exists(path) and hashlib.sha256(open(path, "rb").read()).hexdigest() == f[2]
+    return val if ok else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -217,7 +239,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant),
             "launches": launches, "avg_launch_us": kms / launches * 1e3,
             "bytes_per_launch": kbytes / launches,
         },
