@@ -223,6 +223,9 @@ struct RoundBufs {
   int2* defer;
   int defer_cap;
   int* morder;  // leaf order carried between rounds (see Driver)
+  int* vstar;    // per-vertex star faces, star sizes and neighbour boxes (written by the quadrics kernel)
+  int* vdeg;
+  double* vbox;
   int* ovl_new;  // learned proposal: overlap counts measured this round (null when not tracked)
   float* X;      // learned proposal: features of this round's candidates (null when unused)
 };
@@ -300,6 +303,9 @@ RoundBufs round_bufs(pamo_ctx* c, int64_t nv, int64_t nf) {
   b.defer_cap = (int)std::max<int64_t>(1 << 16, nf);
   b.defer = w.get<int2>("r.defer", b.defer_cap);
   b.morder = w.get<int>("r.morder", nf);
+  b.vstar = w.get<int>("r.vstar", VSTAR * nv);
+  b.vdeg = w.get<int>("r.vdeg", nv);
+  b.vbox = w.get<double>("r.vbox", 6 * nv);
   b.ovl_new = nullptr;
   b.X = nullptr;
   return b;
@@ -346,9 +352,8 @@ void local_checks(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand, 
   {
     TIMED(PH_LOCAL, 0);  // bytes are added once the candidate count is known
     launch_local_check(s, m, b.Q, c->opt.w_e, c->opt.w_s, cand, ncand_dev, bound, b.key, reason, vbar, b.ckey,
-                       cnt + C_ERR);
+                       cnt + C_ERR, cnt + C_HIST);  // C_HIST zeroed with the round's counters
   }
-  launch_reason_hist(s, ncand_dev, bound, reason, cnt + C_HIST);  // C_HIST zeroed with the round's counters
 }
 
 // exact face target of a single mesh: keep the `need` smallest keys
@@ -373,13 +378,12 @@ void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand
   hipStream_t s = c->stream;
   int* cnt = c->dcnt;
   const int* h;
-  launch_check_reset(s, m.nf, b.falive, b.owner, ncand, b.undone);
-  if (R.chosen == 0) return;
   const double nf = m.nf, nv = m.nv;
   {
     TIMED(PH_BOXES, 36 * nf + 24 * nv);
-    launch_face_boxes(s, m, b.box);
+    launch_round_prep(s, m, R.chosen > 0 ? b.box : nullptr, b.falive, b.owner, ncand, b.undone, b.valive);
   }
+  if (R.chosen == 0) return;
   {
     TIMED(PH_APPLY, 900.0 * R.chosen);
     launch_apply(s, m, cand, ncand_dev, ncand, reason, vbar, b.oldpos, b.owner, b.falive, b.box);
@@ -457,6 +461,9 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs
   const double nf = cur.nf, nv = cur.nv;
   const bool learned = L && L->learned && L->active;
   const bool logging = L && L->X;
+  cur.vstar = b.vstar;
+  cur.vdeg = b.vdeg;
+  cur.vbox = b.vbox;
   {
     TIMED(PH_QUADRICS, 108 * nv + 24 * nf);
     launch_quadrics(s, cur, b.Q, cnt + C_ERR);
@@ -499,12 +506,10 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs
     return R;
   }
   if (R.leaf_order) os.age = reuse ? os.age + 1 : 1;
-  fill_u8(s, b.valive, cur.nv, 1);
   if (R.chosen > 0) {
     TIMED(PH_COMMIT, 100.0 * R.chosen);
     launch_commit(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.undone, b.valive);
   }
-  launch_reason_hist(s, cnt + C_NCAND, R.ncand, b.reason, cnt + C_HIST2);
   if (L && L->track && R.chosen > 0) launch_ovl_commit(s, cur.nf, b.owner, b.falive, b.undone, b.ovl_new, cur.ovl);
   if (logging && L->n < L->cap) {
     TIMED(PH_LEARN, 0);
@@ -516,7 +521,7 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs
   {
     TIMED(PH_FLAGS, 3 * nf + 10.0 * R.ncand);
     if (R.commits > 0) fill_u8(s, cur.flags, 3 * (int64_t)cur.nf, 0);
-    launch_flags(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason);
+    launch_flags(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, cnt + C_HIST2);
   }
   if (R.commits > 0) {
     TIMED(PH_COMPACT, 72 * nf + 66 * nv);
@@ -748,6 +753,9 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const Rou
     if (any) PAMO_HIP(hipMemcpyAsync(B.use, huse, n, hipMemcpyHostToDevice, s));
   }
   const double nf = cur.nf, nv = cur.nv;
+  cur.vstar = b.vstar;
+  cur.vdeg = b.vdeg;
+  cur.vbox = b.vbox;
   {
     TIMED(PH_QUADRICS, 108 * nv + 24 * nf);
     launch_quadrics(s, cur, b.Q, cnt + C_ERR);
@@ -793,12 +801,10 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const Rou
   check_and_undo(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr, n,
                  track ? b.ovl_new : nullptr);
   if (R.leaf_order) os.age = reuse ? os.age + 1 : 1;
-  fill_u8(s, b.valive, cur.nv, 1);
   if (R.chosen > 0) {
     TIMED(PH_COMMIT, 100.0 * R.chosen);
     launch_commit(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.undone, b.valive);
   }
-  launch_reason_hist(s, cnt + C_NCAND, R.ncand, b.reason, cnt + C_HIST2);
   launch_mesh_tally(s, b.cand, cnt + C_NCAND, R.ncand, cur.fmesh, nullptr, b.reason, b.undone, nullptr, nullptr,
                     B.d(B.commits_m()), B.d(B.hist_m()), B.d(B.undo_m()));
   if (track && R.chosen > 0) launch_ovl_commit(s, cur.nf, b.owner, b.falive, b.undone, b.ovl_new, cur.ovl);
@@ -807,7 +813,7 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const Rou
   {
     TIMED(PH_FLAGS, 3 * nf + 10.0 * R.ncand);
     if (R.commits > 0) launch_flags_clear_batch(s, cur, B.d(B.commits_m()));
-    launch_flags(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason);
+    launch_flags(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, cnt + C_HIST2);
   }
   if (R.commits > 0) {
     TIMED(PH_COMPACT, 72 * nf + 66 * nv);

@@ -237,7 +237,7 @@ PAMO_HD __forceinline__ int o2k(P3 a, P3 b, P3 c, int k) {
 }
 
 // exact: is the triangle collinear (zero in every axis projection)?
-PAMO_HD inline bool degenerate_exact(P3 a, P3 b, P3 c) {
+PAMO_HD inline __attribute__((noinline)) bool degenerate_exact(P3 a, P3 b, P3 c) {
   for (int k = 0; k < 3; k++)
     if (o2k<true>(a, b, c, k) != 0) return false;
   return true;

@@ -38,6 +38,17 @@ __device__ __forceinline__ bool walk_star(const int* __restrict__ twin, int h0, 
 
 __device__ __forceinline__ int dest(const int* __restrict__ F, int h) { return F[he_next(h)]; }
 
+// histogram of reasons 0..4 over the active lanes of a wave: one atomic per
+// value present
+__device__ __forceinline__ void wave_hist(int r, int* hist) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int v = 0; v <= 4; v++) {
+    unsigned long long b = __ballot(r == v);
+    if (b && lane == __ffsll((long long)b) - 1) atomicAdd(&hist[v], __popcll(b));
+  }
+}
+
 // pop the smallest entry of an ascending register list
 template <int CAP>
 __device__ __forceinline__ int pop_front(int* a) {
@@ -118,11 +129,13 @@ __global__ void k_check_vertices(const int* __restrict__ twin, const int* __rest
 __global__ __launch_bounds__(256) void k_quadrics(MeshView m, double* __restrict__ Q, int* err) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= m.nv) return;
-  constexpr int CAP = 16;
+  constexpr int CAP = VSTAR;
   int fl[CAP];
 #pragma unroll
   for (int i = 0; i < CAP; i++) fl[i] = INT32_MAX;
   int n = 0;
+  P3 lo{INFINITY, INFINITY, INFINITY}, hi{-INFINITY, -INFINITY, -INFINITY};
+  const bool stars = m.vstar != nullptr;
   bool ok = walk_star(m.twin, m.vh[v], [&](int h) {
     if (n < CAP) sorted_insert<CAP>(fl, h / 3);
     n++;
@@ -130,6 +143,12 @@ __global__ __launch_bounds__(256) void k_quadrics(MeshView m, double* __restrict
   if (!ok) {
     set_err(err, PAMO_EBIT_RING);
     return;
+  }
+  if (stars) {
+    int4* o = reinterpret_cast<int4*>(m.vstar + (int64_t)VSTAR * v);
+#pragma unroll
+    for (int i = 0; i < CAP / 4; i++) o[i] = make_int4(fl[4 * i], fl[4 * i + 1], fl[4 * i + 2], fl[4 * i + 3]);
+    m.vdeg[v] = n;
   }
   double q[10];
 #pragma unroll
@@ -149,17 +168,31 @@ __global__ __launch_bounds__(256) void k_quadrics(MeshView m, double* __restrict
     }
     last = f;
     double K[10];
-    face_quadric(ld3(m.V, m.F[3 * f]), ld3(m.V, m.F[3 * f + 1]), ld3(m.V, m.F[3 * f + 2]), K);
+    P3 p0 = ld3(m.V, m.F[3 * f]), p1 = ld3(m.V, m.F[3 * f + 1]), p2 = ld3(m.V, m.F[3 * f + 2]);
+    face_quadric(p0, p1, p2, K);
+    if (stars) {  // box of the closed 1-ring: every corner of the star
+      lo.x = fmin(lo.x, fmin(fmin(p0.x, p1.x), p2.x));
+      lo.y = fmin(lo.y, fmin(fmin(p0.y, p1.y), p2.y));
+      lo.z = fmin(lo.z, fmin(fmin(p0.z, p1.z), p2.z));
+      hi.x = fmax(hi.x, fmax(fmax(p0.x, p1.x), p2.x));
+      hi.y = fmax(hi.y, fmax(fmax(p0.y, p1.y), p2.y));
+      hi.z = fmax(hi.z, fmax(fmax(p0.z, p1.z), p2.z));
+    }
 #pragma unroll
     for (int i = 0; i < 10; i++) q[i] = q[i] + K[i];
   }
 #pragma unroll
   for (int i = 0; i < 10; i++) Q[10 * (int64_t)v + i] = q[i];
+  if (stars) {
+    double* bx = m.vbox + 6 * (int64_t)v;
+    bx[0] = lo.x; bx[1] = lo.y; bx[2] = lo.z;
+    bx[3] = hi.x; bx[4] = hi.y; bx[5] = hi.z;
+  }
 }
 
 // ------------------------------------------------------------ edge evaluation
 struct EdgeRing {
-  static constexpr int CAP = 32;
+  static constexpr int CAP = 16;  // longer rings (rare) take the rescanning path of ring_next
   int fl[CAP];  // faces of star(a) u star(b) without the two edge faces, ascending
   int n;
   P3 lo, hi;  // box of the closed 1-rings
@@ -172,6 +205,36 @@ __device__ __forceinline__ bool edge_ring(const MeshView& m, int h, EdgeRing& R)
 #pragma unroll
   for (int i = 0; i < EdgeRing::CAP; i++) R.fl[i] = INT32_MAX;
   R.n = 0;
+  if (m.vstar) {
+    // from the stars the quadrics kernel stored: the same faces and box
+    // without walking (the two edge faces are the only ones in both stars)
+    const int a = m.F[h], b = m.F[he_next(h)];
+    const int na = m.vdeg[a], nb = m.vdeg[b];
+    if (na <= VSTAR && nb <= VSTAR) {
+      const double* ba = m.vbox + 6 * (int64_t)a;
+      const double* bb = m.vbox + 6 * (int64_t)b;
+      R.lo = P3{fmin(ba[0], bb[0]), fmin(ba[1], bb[1]), fmin(ba[2], bb[2])};
+      R.hi = P3{fmax(ba[3], bb[3]), fmax(ba[4], bb[4]), fmax(ba[5], bb[5])};
+      const int4* sa = reinterpret_cast<const int4*>(m.vstar + (int64_t)VSTAR * a);
+      const int4* sb = reinterpret_cast<const int4*>(m.vstar + (int64_t)VSTAR * b);
+      auto take = [&](int f) {
+        if (f == INT32_MAX || f == f1 || f == f2) return;
+        if (R.n < EdgeRing::CAP) sorted_insert<EdgeRing::CAP>(R.fl, f);
+        R.n++;
+      };
+#pragma unroll
+      for (int i = 0; i < VSTAR / 4; i++) {
+        int4 x = sa[i];
+        take(x.x); take(x.y); take(x.z); take(x.w);
+      }
+#pragma unroll
+      for (int i = 0; i < VSTAR / 4; i++) {
+        int4 x = sb[i];
+        take(x.x); take(x.y); take(x.z); take(x.w);
+      }
+      return true;
+    }
+  }
   R.lo = P3{INFINITY, INFINITY, INFINITY};
   R.hi = P3{-INFINITY, -INFINITY, -INFINITY};
   auto visit = [&](int g) {
@@ -264,29 +327,49 @@ __device__ __forceinline__ double edge_cost(const MeshView& m, const double* __r
 }
 
 // ------------------------------------------------------------ cost + keys
+// One thread per edge: each wave gathers the representative half-edges
+// (h < twin h) of its 256 consecutive half-edges into an LDS queue and then
+// evaluates them with all 64 lanes busy (one thread per half-edge would leave
+// half the lanes idle).
+constexpr int CK_PER_WAVE = 256;
+
 __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
                                                    const uint8_t* __restrict__ demote,
                                                    const uint8_t* __restrict__ mesh_done, uint64_t* __restrict__ key,
                                                    int* err) {
-  int h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= 3 * m.nf) return;
-  int t = m.twin[h];
-  if (t < h) return;  // the smaller half-edge represents the edge
-  uint64_t k = PAMO_KEY_MAX;
-  bool skip = m.flags[h] || m.flags[t] || (demote && (demote[h] || demote[t])) ||
-              (mesh_done && mesh_done[m.fmesh[h / 3]]);
-  if (!skip) {
-    EdgeRing R;
-    if (!edge_ring(m, h, R)) {
-      set_err(err, PAMO_EBIT_RING);
-    } else {
-      P3 vbar;
-      double cost = edge_cost(m, Q, h, R, w_e, w_s, vbar);
-      k = make_key(cost, (uint32_t)h);
-    }
+  __shared__ int queue[4][CK_PER_WAVE];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nh = 3 * (int64_t)m.nf;
+  const int64_t base = ((int64_t)blockIdx.x * 4 + w) * CK_PER_WAVE;
+  int count = 0;
+#pragma unroll
+  for (int j = 0; j < CK_PER_WAVE / 64; j++) {
+    const int64_t h = base + 64 * j + lane;
+    const bool rep = h < nh && h < m.twin[h];
+    const unsigned long long b = __ballot(rep);
+    if (rep) queue[w][count + __popcll(b & ((1ull << lane) - 1))] = (int)h;
+    count += __popcll(b);
   }
-  key[h] = k;
-  key[t] = k;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  for (int i = lane; i < count; i += 64) {
+    const int h = queue[w][i];
+    const int t = m.twin[h];
+    uint64_t k = PAMO_KEY_MAX;
+    bool skip = m.flags[h] || m.flags[t] || (demote && (demote[h] || demote[t])) ||
+                (mesh_done && mesh_done[m.fmesh[h / 3]]);
+    if (!skip) {
+      EdgeRing R;
+      if (!edge_ring(m, h, R)) {
+        set_err(err, PAMO_EBIT_RING);
+      } else {
+        P3 vbar;
+        double cost = edge_cost(m, Q, h, R, w_e, w_s, vbar);
+        k = make_key(cost, (uint32_t)h);
+      }
+    }
+    key[h] = k;
+    key[t] = k;
+  }
 }
 
 // ------------------------------------------------------------ selection
@@ -371,7 +454,7 @@ __global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* _
                                                      double w_s, const int* __restrict__ cand,
                                                      const int* __restrict__ ncand, const uint64_t* __restrict__ key,
                                                      uint8_t* __restrict__ reason, double* __restrict__ vbar_out,
-                                                     uint64_t* __restrict__ ckey, int* err) {
+                                                     uint64_t* __restrict__ ckey, int* err, int* __restrict__ hist) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= *ncand) return;
   int h = cand[c];
@@ -418,6 +501,7 @@ __global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* _
   vbar_out[3 * (int64_t)c] = vbar.x;
   vbar_out[3 * (int64_t)c + 1] = vbar.y;
   vbar_out[3 * (int64_t)c + 2] = vbar.z;
+  wave_hist(rs, hist);
 }
 
 // candidates passing the local checks whose key exceeds the threshold are
@@ -589,7 +673,7 @@ __global__ __launch_bounds__(256) void k_commit(MeshView m, const int* __restric
 }
 
 __global__ void k_flags(MeshView m, const int* __restrict__ cand, const int* __restrict__ ncand,
-                        const uint8_t* __restrict__ reason) {
+                        const uint8_t* __restrict__ reason, int* __restrict__ hist) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= *ncand) return;
   uint8_t rs = reason[c];
@@ -598,6 +682,7 @@ __global__ void k_flags(MeshView m, const int* __restrict__ cand, const int* __r
     m.flags[h] = 1;
     m.flags[m.twin[h]] = 1;
   }
+  if (hist) wave_hist(rs, hist);
 }
 
 __global__ void k_reason_hist(const int* __restrict__ ncand, const uint8_t* __restrict__ reason, int* __restrict__ hist) {
@@ -669,6 +754,21 @@ __global__ void k_ovl_commit(int nf, const int* __restrict__ owner, const uint8_
   if (f >= nf || !falive[f]) return;
   int o = owner[f];
   if (o >= 0 && undone[o] == 0) ovl[f] = ovl_new[f];
+}
+
+// state of a round's check/undo loop: every face alive and unowned with its
+// box, nothing undone, every vertex alive
+__global__ void k_round_prep(MeshView m, float* __restrict__ box, uint8_t* __restrict__ falive,
+                             int* __restrict__ owner, int ncand, int* __restrict__ undone,
+                             uint8_t* __restrict__ valive) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m.nf) {
+    falive[i] = 1;
+    owner[i] = -1;
+    if (box) face_box_f32(m, i, box + 6 * (int64_t)i);
+  }
+  if (i < ncand) undone[i] = 0;
+  if (i < m.nv && valive) valive[i] = 1;
 }
 
 // state of a check/undo loop: every face alive and unowned, nothing undone
@@ -820,8 +920,8 @@ void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err) {
 
 void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
                       const uint8_t* mesh_done, uint64_t* key, int* err) {
-  hipLaunchKernelGGL(k_cost_keys, dim3(nblk(3 * (int64_t)m.nf)), dim3(256), 0, s, m, Q, w_e, w_s, demote, mesh_done,
-                     key, err);
+  hipLaunchKernelGGL(k_cost_keys, dim3(nblk(3 * (int64_t)m.nf, 4 * CK_PER_WAVE)), dim3(256), 0, s, m, Q, w_e, w_s,
+                     demote, mesh_done, key, err);
   PAMO_HIP(hipGetLastError());
 }
 
@@ -837,9 +937,9 @@ void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key
 
 void launch_local_check(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const int* cand,
                         const int* ncand, int cand_bound, const uint64_t* key, uint8_t* reason, double* vbar,
-                        uint64_t* ckey, int* err) {
+                        uint64_t* ckey, int* err, int* hist) {
   hipLaunchKernelGGL(k_local_check, dim3(nblk(cand_bound)), dim3(256), 0, s, m, Q, w_e, w_s, cand, ncand, key, reason,
-                     vbar, ckey, err);
+                     vbar, ckey, err, hist);
   PAMO_HIP(hipGetLastError());
 }
 
@@ -891,8 +991,8 @@ void launch_commit(hipStream_t s, MeshView m, const int* cand, const int* ncand,
 }
 
 void launch_flags(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound,
-                  const uint8_t* reason) {
-  hipLaunchKernelGGL(k_flags, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason);
+                  const uint8_t* reason, int* hist) {
+  hipLaunchKernelGGL(k_flags, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, hist);
   PAMO_HIP(hipGetLastError());
 }
 
@@ -926,6 +1026,14 @@ void launch_remap_order(Workspace& ws, hipStream_t s, const int* order, int nf_o
 void launch_ovl_commit(hipStream_t s, int nf, const int* owner, const uint8_t* falive, const int* undone,
                        const int* ovl_new, int* ovl) {
   hipLaunchKernelGGL(k_ovl_commit, dim3(nblk(nf)), dim3(256), 0, s, nf, owner, falive, undone, ovl_new, ovl);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_round_prep(hipStream_t s, MeshView m, float* box, uint8_t* falive, int* owner, int ncand, int* undone,
+                       uint8_t* valive) {
+  int n = m.nf > ncand ? m.nf : ncand;
+  n = n > m.nv ? n : m.nv;
+  hipLaunchKernelGGL(k_round_prep, dim3(nblk(n)), dim3(256), 0, s, m, box, falive, owner, ncand, undone, valive);
   PAMO_HIP(hipGetLastError());
 }
 

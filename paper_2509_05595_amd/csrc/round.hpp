@@ -24,7 +24,14 @@ struct MeshView {
   int* fmesh = nullptr;  // batches only: mesh of each face / vertex (kept through compaction)
   int* vmesh = nullptr;
   int* ovl = nullptr;    // learned proposal only: per-face overlap counts (kept through compaction)
+  // per-round vertex data written by the quadrics kernel when set (not carried
+  // through compaction): each vertex's star faces ascending (VSTAR per vertex,
+  // INT_MAX padding), its star size, and the box of its closed 1-ring (lo, hi)
+  int* vstar = nullptr;
+  int* vdeg = nullptr;
+  double* vbox = nullptr;
 };
+constexpr int VSTAR = 16;
 
 // Batches keep their meshes apart in the BVH by shifting each mesh's boxes
 // to its own cell of a 16 x 16 x 16 grid of pitch 2 (meshes live in [0,1]^3).
@@ -45,13 +52,18 @@ void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key
                    int* ncand);
 void launch_local_check(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const int* cand,
                         const int* ncand, int cand_bound, const uint64_t* key, uint8_t* reason, double* vbar,
-                        uint64_t* ckey, int* err);
+                        uint64_t* ckey, int* err, int* hist);
 void launch_cap(Workspace& ws, hipStream_t s, const int* ncand, int nc_host, const uint64_t* ckey, uint8_t* reason,
                 int64_t need);
 void launch_face_boxes(hipStream_t s, MeshView m, float* box);
 // ovl[f] = ovl_new[f] for the alive faces of committed collapses
 void launch_ovl_commit(hipStream_t s, int nf, const int* owner, const uint8_t* falive, const int* undone,
                        const int* ovl_new, int* ovl);
+// one launch for a round's check state: falive = 1, owner = -1 and (box not
+// null) the float32 box of every face, undone[0..ncand) = 0, valive (not
+// null) = 1
+void launch_round_prep(hipStream_t s, MeshView m, float* box, uint8_t* falive, int* owner, int ncand, int* undone,
+                       uint8_t* valive);
 // falive[0..nf) = 1, owner[0..nf) = -1, undone[0..ncand) = 0
 void launch_check_reset(hipStream_t s, int nf, uint8_t* falive, int* owner, int ncand, int* undone);
 void launch_apply(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const uint8_t* reason,
@@ -65,7 +77,9 @@ void launch_face_list(Workspace& ws, hipStream_t s, int nf, const int* owner, co
                       const int* undone, int iter, const int* order, int* list, int* count);
 void launch_commit(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, uint8_t* reason,
                    const int* undone, uint8_t* valive);
-void launch_flags(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const uint8_t* reason);
+// flags of rejected edges; hist (may be null) += histogram of the reasons
+void launch_flags(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const uint8_t* reason,
+                  int* hist = nullptr);
 void launch_flags_or(hipStream_t s, uint8_t* dst, const uint8_t* src, int64_t n);
 void launch_reason_hist(hipStream_t s, const int* ncand, int cand_bound, const uint8_t* reason, int* hist);
 void launch_compact(Workspace& ws, hipStream_t s, MeshView src, MeshView dst, const uint8_t* falive,
