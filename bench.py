@@ -16,7 +16,10 @@ Besides the throughput line the JSON carries
   batched       the batched form: 256 meshes (noisy geodesic spheres and
                 bumpy tori, face counts log-uniform in [5k, 200k]) each to 1%
                 in one pamo_simplify_batch call, beside the same meshes run
-                one pamo_simplify call at a time (a 32-mesh sample).
+                one pamo_simplify call at a time (a 32-mesh sample);
+  learned_vs_plain, sharp_feature_batch
+                the learned proposal against the plain method (headline mesh,
+                a thin shell; a 5.24M-face crease sphere batched with 32 tori).
 """
 from __future__ import annotations
 
@@ -158,6 +161,43 @@ def learned_vs_plain(native, torch, dev, Vd, Fd, target, steps):
     return out
 
 
+def sharp_feature(native, torch, dev, steps):
+    """Crease sphere (icosphere refined 9x, 5,242,880 faces, radius
+    1 + 0.03|sin 12 theta||sin 9 phi| + 0.002 N(0,1)) to 0.1%, in one batch with 32
+    bumpy tori of 20k-100k faces to 1%: plain and learned batched forms."""
+    from paper_2509_05595_amd import learn, meshgen
+    meshes = [meshgen.crease_sphere(9, 5)] + [meshgen.make_spec(sp) for sp in meshgen.tori_specs()]
+    targets = [len(meshes[0][1]) // 1000] + [len(F) // 100 for _, F in meshes[1:]]
+    dm = [(torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev)) for V, F in meshes]
+    nf_total = sum(len(F) for _, F in meshes)
+    log("sharp-feature batch generated")
+    ctx = native.Context(dev)
+    model = learn.load_model() if os.path.exists(learn.MODEL_PATH) else None
+    out = {"workload": f"crease sphere 5,242,880 faces -> 0.1% with 32 tori ({nf_total} faces in total), "
+                       f"one pamo_simplify_batch call"}
+    for mode in ("plain", "learned"):
+        if mode == "learned" and model is None:
+            continue
+        ctx.set_mlp(model if mode == "learned" else None)
+        ctx.set_options(native.default_options(learned=int(mode == "learned")))
+        res = ctx.simplify_batch(dm, targets)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = ctx.simplify_batch(dm, targets)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        Vo, Fo, st = res[0]
+        out[mode] = {"faces_per_s": nf_total / dt, "ms": dt * 1e3, "rounds": max(r[2]["rounds"] for r in res),
+                     "sphere_faces_out": int(Fo.shape[0]), "sphere_rejected": st["rej_link"] + st["rej_flip"] +
+                     st["rej_isect"], "demoted": sum(r[2]["demoted"] for r in res),
+                     "sphere_hausdorff": ctx.hausdorff(dm[0][0], Vo.contiguous(), Fo.contiguous())}
+        log(f"sharp-feature batch {mode}: {dt * 1e3:.1f} ms")
+    ctx.set_options(native.default_options())
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +212,7 @@ def main():
     ap.add_argument("--coop-below", type=int, default=0, help="query count below which lanes share a query")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-versus-plain comparison")
+    ap.add_argument("--no-sharp", action="store_true", help="skip the sharp-feature batch")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     args = ap.parse_args()
@@ -256,6 +297,8 @@ def main():
     if not args.no_batch:
         ctx.close()
         out["batched"] = batched(native, torch, dev, args.batch_steps, 1, args.batch_count, 32)
+    if not args.no_sharp:
+        out["sharp_feature_batch"] = sharp_feature(native, torch, dev, 1)
     if not args.no_cpu_baseline and args.gpus == 1:
         out["cpu_baseline"] = cpu_baseline()
         log("cpu baseline timed")

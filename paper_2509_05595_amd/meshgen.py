@@ -279,6 +279,19 @@ def batch_specs(count: int = 256, seed: int = 3, fmin: float = 5e3, fmax: float 
     return specs
 
 
+def tori_specs(count: int = 32, seed: int = 5, fmin: float = 2e4, fmax: float = 1e5):
+    """Bumpy tori of log-uniform face counts in [fmin, fmax] (the batch recipe's
+    tori)."""
+    rng = np.random.default_rng(seed)
+    fs = np.exp(rng.uniform(math.log(fmin), math.log(fmax), count))
+    out = []
+    for i, fi in enumerate(fs):
+        n = int(min(512, max(64, round(math.sqrt(fi * 1.0 / (2 * 0.35))))))
+        m = max(3, int(round(fi / (2 * n))))
+        out.append(("torus", (n, m), 2000 + i))
+    return out
+
+
 def make_spec(spec):
     kind, size, seed = spec
     if kind == "sphere":
