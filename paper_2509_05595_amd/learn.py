@@ -19,7 +19,7 @@ import time
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-MODEL_PATH = os.path.join(HERE, "models", "mlp_thin_shells.json")
+MODEL_PATH = os.path.join(HERE, "models", "mlp_v2.json")
 NPARAM = 6337
 O_W1, O_B1, O_W2, O_B2, O_W3, O_B3 = 0, 2048, 2112, 6208, 6272, 6336
 
@@ -27,7 +27,8 @@ O_W1, O_B1, O_W2, O_B2, O_W3, O_B3 = 0, 2048, 2112, 6208, 6272, 6336
 def training_meshes():
     """The meshes whose plain runs provide the rows: thin shells (two nested
     spheres close to each other, the case where collapses get undone for
-    intersections), plus the noisy spheres and tori of the benchmark recipes,
+    intersections), crease spheres simplified far (flipped triangles in the
+    late rounds), and the noisy spheres and tori of the benchmark recipes,
     where nearly every candidate passes.  Pairs (mesh, face target)."""
     from . import meshgen as g
     out = []
@@ -40,13 +41,18 @@ def training_meshes():
     for seed in (11, 12):
         V, F = g.bumpy_torus(128, 48, seed=seed)
         out.append(((V, F), len(F) // 100))
+    for seed in (11, 12):  # crease spheres: late, coarse rounds reject many collapses for flips
+        V, F = g.crease_sphere(8, seed)
+        out.append(((V, F), len(F) // 1000))
     return out
 
 
 def held_out_meshes():
-    """Thin shells not used for training (other resolution / gap)."""
+    """Meshes not used for training: a finer crease sphere, thin shells of
+    other resolution / gap."""
     from . import meshgen as g
-    return [(g.nested_spheres(k=5, gap=0.005), 0.02), (g.nested_spheres(k=6, gap=0.002), 0.02)]
+    return [(g.crease_sphere(9, 5), 0.001), (g.nested_spheres(k=5, gap=0.005), 0.02),
+            (g.nested_spheres(k=6, gap=0.002), 0.02)]
 
 
 def collect(ctx, meshes, cap_per_mesh=1 << 21):
@@ -88,7 +94,7 @@ def calibrate(P, X, e=(8, 8, 8)):
     return {"e1": e[0], "e2": e[1], "e3": e[2], "a1": a1, "a2": a2}
 
 
-def train(ctx, X, y, steps=3000, batch=4096, lr=1e-3, seed=4, log=None):
+def train(ctx, X, y, steps=4000, batch=4096, lr=1e-3, seed=4, log=None):
     """Train on device rows (X float32 [n, 32], y uint8 [n]); returns (params, meta, losses)."""
     import torch
     P0 = init_params(seed)
