@@ -22,7 +22,8 @@
  *       closed 1-rings, else the best of midpoint / endpoint / endpoint.
  *       (The paper does not say how it places the vertex.)
  *   R3  edge cost, Eq. 1: Q_ab + w_e l_ab + w_s sum(1 - C_ijk) over the
- *       triangles the collapse generates, w_e = 0.001, w_s = 0.005.
+ *       triangles the collapse generates (summed around the smaller endpoint
+ *       first, each star in ascending face slot), w_e = 0.001, w_s = 0.005.
  *   R4  64-bit key: float32 cost mapped to an order-preserving 32-bit code in
  *       the high half, unique edge id in the low half (Sec. 5.1, "Cost
  *       Propagation").  Flagged edges and NaN costs get the largest key.
@@ -302,12 +303,19 @@ static double edge_cost(const omesh *m, int32_t a, int32_t b, double w_e, double
     const double *ps = m->V + 3 * (int64_t)s, *pr = m->V + 3 * (int64_t)r;
     double dx = ps[0] - pr[0], dy = ps[1] - pr[1], dz = ps[2] - pr[2];
     double lab = sqrt(dx * dx + dy * dy + dz * dz);
+    /* The sum over the generated triangles has no order in the paper; it runs
+     * over the faces around s in ascending slot, then those around r.  The two
+     * faces holding both s and r are removed by the collapse and skipped, so
+     * every generated triangle is counted once. */
     double S = 0.0;
-    for (int i = 0; i < nring; i++) {
-        int32_t f = ring[i];
-        if (face_has(m, f, s) && face_has(m, f, r)) continue; /* removed by the collapse */
-        S = S + skinny_term(corner_after(m, f, 0, s, r, vbar), corner_after(m, f, 1, s, r, vbar),
-                            corner_after(m, f, 2, s, r, vbar));
+    for (int side = 0; side < 2; side++) {
+        int32_t v = side ? r : s;
+        for (int64_t i = m->inc_off[v]; i < m->inc_off[v + 1]; i++) {
+            int32_t f = m->inc[i];
+            if (face_has(m, f, s) && face_has(m, f, r)) continue;
+            S = S + skinny_term(corner_after(m, f, 0, s, r, vbar), corner_after(m, f, 1, s, r, vbar),
+                                corner_after(m, f, 2, s, r, vbar));
+        }
     }
     return quadric_eval(q, vbar) + w_e * lab + w_s * S;
 }

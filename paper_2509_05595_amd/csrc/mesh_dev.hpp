@@ -14,8 +14,9 @@
 //
 // Floating-point contract: every expression below is evaluated in float64 in
 // exactly the order written (the library is built with contraction off), and
-// sums over faces run in ascending face slot, so the results do not depend on
-// the thread that computes them.
+// sums over faces run in a fixed order (ascending face slot around one vertex;
+// around the smaller endpoint first for an edge), so the results do not depend
+// on the thread that computes them.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -27,6 +28,16 @@
 #define PAMO_SKINNY_K 3.4641016151377544  // 2 sqrt(3): 4 sqrt(3) A = (2 sqrt(3)) |n|
 
 namespace pamo {
+
+// The hardware deals the blocks of a launch to the 8 XCDs in turn (block b to
+// XCD b mod 8), and each XCD has its own L2.  This returns a logical block id
+// under which every XCD processes one contiguous eighth of the index range, so
+// that mesh neighbourhoods gathered by neighbouring elements stay in one L2.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int per = nb >> 3, rem = nb & 7, x = b & 7;
+  return x * per + (x < rem ? x : rem) + (b >> 3);
+}
 
 PAMO_HD __forceinline__ int he_next(int h) { return h - h % 3 + (h % 3 == 2 ? 0 : h % 3 + 1); }
 PAMO_HD __forceinline__ int he_prev(int h) { return h - h % 3 + (h % 3 == 0 ? 2 : h % 3 - 1); }

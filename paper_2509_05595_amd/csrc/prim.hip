@@ -53,23 +53,52 @@ __device__ __forceinline__ int block_sum(int x) {
   return t;
 }
 
+// Item loaders.  load16 reads the 16 consecutive items of one thread (i a
+// multiple of 16, zero past n) with vector loads where the run is aligned and
+// complete, so a thread has all of its items in flight at once.
 struct FlagLoad {
   const uint8_t* f;
   __device__ int load(int64_t i) const { return f[i] != 0; }
+  __device__ void load16(int64_t i, int64_t n, int* v) const {
+    if (i + 16 <= n && (reinterpret_cast<uintptr_t>(f + i) & 15) == 0) {
+      const uint4 x = *reinterpret_cast<const uint4*>(f + i);
+      const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int k = 0; k < 16; k++) v[k] = ((w[k >> 2] >> (8 * (k & 3))) & 0xffu) != 0;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; k++) v[k] = i + k < n ? load(i + k) : 0;
+    }
+  }
 };
 struct IntLoad {
   const int32_t* a;
   __device__ int load(int64_t i) const { return a[i]; }
+  __device__ void load16(int64_t i, int64_t n, int* v) const {
+    if (i + 16 <= n && (reinterpret_cast<uintptr_t>(a + i) & 15) == 0) {
+      const int4* p = reinterpret_cast<const int4*>(a + i);
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int4 x = p[q];
+        v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; k++) v[k] = i + k < n ? load(i + k) : 0;
+    }
+  }
 };
+static_assert(ITEMS == 16 && TOP_ITEMS == 16, "loaders read 16 items per thread");
 
+// tile sums; thread t of a tile holds items [16 t, 16 t + 16) of it
 template <class Op>
 __global__ __launch_bounds__(T) void k_tile_reduce(Op op, int64_t n, int32_t* tile_sum) {
-  int64_t base = (int64_t)blockIdx.x * TILE;
+  const int64_t base = (int64_t)blockIdx.x * TILE + (int64_t)threadIdx.x * ITEMS;
+  int v[ITEMS];
+  op.load16(base, n, v);
   int s = 0;
-  for (int i = threadIdx.x; i < TILE; i += T) {
-    int64_t g = base + i;
-    if (g < n) s += op.load(g);
-  }
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) s += v[i];
   s = block_sum<T>(s);
   if (threadIdx.x == 0) tile_sum[blockIdx.x] = s;
 }
@@ -116,18 +145,32 @@ struct ScanStore {
   __device__ void store(int64_t i, int prefix, int) const { out[i] = prefix; }
 };
 
+// Scan pass over tiles.  tile_off: exclusive offsets of the tiles (three-pass
+// form), or null, in which case each block adds up the sums of the tiles
+// before it itself (two-pass form, for up to LOCAL_TILES tiles); the last
+// block then writes the total.
+constexpr int64_t LOCAL_TILES = 1024;
+
 template <class Op, class St>
-__global__ __launch_bounds__(T) void k_tile_scan(Op op, St st, int64_t n, const int32_t* tile_off) {
-  int64_t base = (int64_t)blockIdx.x * TILE + (int64_t)threadIdx.x * ITEMS;
+__global__ __launch_bounds__(T) void k_tile_scan(Op op, St st, int64_t n, const int32_t* tile_off,
+                                                 const int32_t* tile_sum, int32_t* total) {
+  const int64_t base = (int64_t)blockIdx.x * TILE + (int64_t)threadIdx.x * ITEMS;
   int v[ITEMS];
+  op.load16(base, n, v);
   int s = 0;
 #pragma unroll
-  for (int i = 0; i < ITEMS; i++) {
-    v[i] = base + i < n ? op.load(base + i) : 0;
-    s += v[i];
+  for (int i = 0; i < ITEMS; i++) s += v[i];
+  int off;
+  if (tile_off) {
+    off = tile_off[blockIdx.x];
+  } else {
+    int pre = 0;
+    for (int t = threadIdx.x; t < (int)blockIdx.x; t += T) pre += tile_sum[t];
+    off = block_sum<T>(pre);
   }
   int tot;
-  int ex = block_excl_scan<T>(s, tot) + tile_off[blockIdx.x];
+  int ex = block_excl_scan<T>(s, tot) + off;
+  if (!tile_off && total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
 #pragma unroll
   for (int i = 0; i < ITEMS; i++) {
     if (base + i < n) st.store(base + i, ex, v[i]);
@@ -146,12 +189,10 @@ __global__ __launch_bounds__(TOP_T) void k_scan_single(Op op, St st, int64_t n, 
   for (int64_t base0 = 0; base0 < n; base0 += (int64_t)TOP_T * TOP_ITEMS) {
     int64_t base = base0 + (int64_t)threadIdx.x * TOP_ITEMS;
     int v[TOP_ITEMS];
+    op.load16(base, n, v);
     int s = 0;
 #pragma unroll
-    for (int i = 0; i < TOP_ITEMS; i++) {
-      v[i] = base + i < n ? op.load(base + i) : 0;
-      s += v[i];
-    }
+    for (int i = 0; i < TOP_ITEMS; i++) s += v[i];
     int tot;
     int ex = block_excl_scan<TOP_T>(s, tot) + carry;
 #pragma unroll
@@ -179,9 +220,14 @@ void run_scan(Workspace& ws, hipStream_t s, Op op, St st, int64_t n, int32_t* to
   }
   int32_t* tiles = ws.get<int32_t>("prim.tiles", ntiles);
   hipLaunchKernelGGL(k_tile_reduce<Op>, dim3((unsigned)ntiles), dim3(T), 0, s, op, n, tiles);
-  hipLaunchKernelGGL(k_top_scan, dim3(1), dim3(TOP_T), 0, s, tiles, (int)ntiles, total);
-  hipLaunchKernelGGL((k_tile_scan<Op, St>), dim3((unsigned)ntiles), dim3(T), 0, s, op, st, n,
-                     (const int32_t*)tiles);
+  if (ntiles <= LOCAL_TILES) {
+    hipLaunchKernelGGL((k_tile_scan<Op, St>), dim3((unsigned)ntiles), dim3(T), 0, s, op, st, n, nullptr,
+                       (const int32_t*)tiles, total);
+  } else {
+    hipLaunchKernelGGL(k_top_scan, dim3(1), dim3(TOP_T), 0, s, tiles, (int)ntiles, total);
+    hipLaunchKernelGGL((k_tile_scan<Op, St>), dim3((unsigned)ntiles), dim3(T), 0, s, op, st, n,
+                       (const int32_t*)tiles, nullptr, nullptr);
+  }
   PAMO_HIP(hipGetLastError());
 }
 

@@ -191,79 +191,79 @@ __global__ __launch_bounds__(256) void k_quadrics(MeshView m, double* __restrict
 }
 
 // ------------------------------------------------------------ edge evaluation
-struct EdgeRing {
-  static constexpr int CAP = 16;  // longer rings (rare) take the rescanning path of ring_next
-  int fl[CAP];  // faces of star(a) u star(b) without the two edge faces, ascending
-  int n;
-  P3 lo, hi;  // box of the closed 1-rings
+// Edge h with endpoints s < r, the half-edges leaving them, its two faces and
+// the box of every vertex of star(s) u star(r).  fast: both stars were stored
+// by the quadrics kernel of this round (at most VSTAR faces each), so neither
+// box nor ring needs a walk.
+struct EdgeStars {
+  int s, r, hs, hr, f1, f2, ns, nr;
+  bool fast;
+  P3 lo, hi;
 };
 
-// ring faces of edge h (a = F[h], b = F[next h]), ascending, and the box of
-// every vertex of star(a) u star(b)
-__device__ __forceinline__ bool edge_ring(const MeshView& m, int h, EdgeRing& R) {
-  int f1 = h / 3, f2 = m.twin[h] / 3;
-#pragma unroll
-  for (int i = 0; i < EdgeRing::CAP; i++) R.fl[i] = INT32_MAX;
-  R.n = 0;
+__device__ __forceinline__ bool edge_stars(const MeshView& m, int h, EdgeStars& E) {
+  const int t = m.twin[h];
+  const int a = m.F[h], b = m.F[he_next(h)];
+  E.s = a < b ? a : b;
+  E.r = a < b ? b : a;
+  E.hs = a < b ? h : t;
+  E.hr = a < b ? t : h;
+  E.f1 = h / 3;
+  E.f2 = t / 3;
+  E.fast = false;
+  E.ns = E.nr = 0;
   if (m.vstar) {
-    // from the stars the quadrics kernel stored: the same faces and box
-    // without walking (the two edge faces are the only ones in both stars)
-    const int a = m.F[h], b = m.F[he_next(h)];
-    const int na = m.vdeg[a], nb = m.vdeg[b];
-    if (na <= VSTAR && nb <= VSTAR) {
-      const double* ba = m.vbox + 6 * (int64_t)a;
-      const double* bb = m.vbox + 6 * (int64_t)b;
-      R.lo = P3{fmin(ba[0], bb[0]), fmin(ba[1], bb[1]), fmin(ba[2], bb[2])};
-      R.hi = P3{fmax(ba[3], bb[3]), fmax(ba[4], bb[4]), fmax(ba[5], bb[5])};
-      const int4* sa = reinterpret_cast<const int4*>(m.vstar + (int64_t)VSTAR * a);
-      const int4* sb = reinterpret_cast<const int4*>(m.vstar + (int64_t)VSTAR * b);
-      auto take = [&](int f) {
-        if (f == INT32_MAX || f == f1 || f == f2) return;
-        if (R.n < EdgeRing::CAP) sorted_insert<EdgeRing::CAP>(R.fl, f);
-        R.n++;
-      };
-#pragma unroll
-      for (int i = 0; i < VSTAR / 4; i++) {
-        int4 x = sa[i];
-        take(x.x); take(x.y); take(x.z); take(x.w);
-      }
-#pragma unroll
-      for (int i = 0; i < VSTAR / 4; i++) {
-        int4 x = sb[i];
-        take(x.x); take(x.y); take(x.z); take(x.w);
-      }
-      return true;
-    }
+    E.ns = m.vdeg[E.s];
+    E.nr = m.vdeg[E.r];
+    E.fast = E.ns <= VSTAR && E.nr <= VSTAR;
   }
-  R.lo = P3{INFINITY, INFINITY, INFINITY};
-  R.hi = P3{-INFINITY, -INFINITY, -INFINITY};
+  if (E.fast) {
+    const double* bs = m.vbox + 6 * (int64_t)E.s;
+    const double* br = m.vbox + 6 * (int64_t)E.r;
+    E.lo = P3{fmin(bs[0], br[0]), fmin(bs[1], br[1]), fmin(bs[2], br[2])};
+    E.hi = P3{fmax(bs[3], br[3]), fmax(bs[4], br[4]), fmax(bs[5], br[5])};
+    return true;
+  }
+  E.lo = P3{INFINITY, INFINITY, INFINITY};
+  E.hi = P3{-INFINITY, -INFINITY, -INFINITY};
   auto visit = [&](int g) {
-    int f = g / 3;
     P3 p = ld3(m.V, dest(m.F, g));
-    R.lo.x = fmin(R.lo.x, p.x); R.lo.y = fmin(R.lo.y, p.y); R.lo.z = fmin(R.lo.z, p.z);
-    R.hi.x = fmax(R.hi.x, p.x); R.hi.y = fmax(R.hi.y, p.y); R.hi.z = fmax(R.hi.z, p.z);
-    if (f == f1 || f == f2) return;
-    if (R.n < EdgeRing::CAP) sorted_insert<EdgeRing::CAP>(R.fl, f);
-    R.n++;
+    E.lo.x = fmin(E.lo.x, p.x); E.lo.y = fmin(E.lo.y, p.y); E.lo.z = fmin(E.lo.z, p.z);
+    E.hi.x = fmax(E.hi.x, p.x); E.hi.y = fmax(E.hi.y, p.y); E.hi.z = fmax(E.hi.z, p.z);
   };
-  bool ok = walk_star(m.twin, h, visit);
-  ok = ok && walk_star(m.twin, m.twin[h], visit);
-  return ok;
+  bool ok = walk_star(m.twin, E.hs, visit);
+  return ok && walk_star(m.twin, E.hr, visit);
 }
 
-// k-th step of an ascending walk over the ring faces: fast path pops the
-// register list, slow path (ring longer than the list) rescans the stars
-__device__ __forceinline__ int ring_next(const MeshView& m, int h, EdgeRing& R, int last) {
-  if (R.n <= EdgeRing::CAP) return pop_front<EdgeRing::CAP>(R.fl);
-  int f1 = h / 3, f2 = m.twin[h] / 3;
-  int best = INT32_MAX;
-  auto scan = [&](int g) {
-    int f = g / 3;
-    if (f != f1 && f != f2 && f > last && f < best) best = f;
-  };
-  walk_star(m.twin, h, scan);
-  walk_star(m.twin, m.twin[h], scan);
-  return best;
+// The faces of star(v) (v = E.s with hv = E.hs and n = E.ns, or the same for
+// r) other than the edge's two faces, in ascending face slot.  Fast path: the
+// stored sorted star, four slots per 16-byte load so the loads of four faces
+// are in flight together; otherwise repeated scans of the star for the next
+// larger slot.
+template <class Fn>
+__device__ __forceinline__ void star_ascending(const MeshView& m, const EdgeStars& E, int v, int hv, int n, Fn fn) {
+  if (E.fast) {
+    const int4* st = reinterpret_cast<const int4*>(m.vstar + (int64_t)VSTAR * v);
+    for (int j = 0; 4 * j < n; j++) {
+      const int4 x = st[j];
+      const int f4[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+        if (4 * j + k < n && f4[k] != E.f1 && f4[k] != E.f2) fn(f4[k]);
+    }
+    return;
+  }
+  int last = -1;
+  for (;;) {
+    int best = INT32_MAX;
+    walk_star(m.twin, hv, [&](int g) {
+      int f = g / 3;
+      if (f > last && f < best) best = f;
+    });
+    if (best == INT32_MAX) break;
+    last = best;
+    if (best != E.f1 && best != E.f2) fn(best);
+  }
 }
 
 // placement of the merged vertex (quadric minimiser by Cramer's rule when the
@@ -303,47 +303,92 @@ __device__ __forceinline__ P3 corner_after(const MeshView& m, int f, int c, int 
   return (v == s || v == r) ? vbar : ld3(m.V, v);
 }
 
-// cost (Eq. 1) and placement of edge h; R is consumed
-__device__ __forceinline__ double edge_cost(const MeshView& m, const double* __restrict__ Q, int h, EdgeRing& R,
+// S plus the skinny terms of the faces of the stored star of v (E.fast), in
+// slot order.  Four slots at a time, branch-free: every load of the four
+// faces (corner ids, then corner positions) is issued before any arithmetic,
+// slots past the star or holding the edge's faces read face f1 and add
+// nothing.  Same terms in the same order as star_ascending.
+__device__ __forceinline__ double skinny_sum_star(const MeshView& m, const EdgeStars& E, int v, int n, P3 vb,
+                                                  double S) {
+  const int4* st = reinterpret_cast<const int4*>(m.vstar + (int64_t)VSTAR * v);
+  for (int j = 0; 4 * j < n; j++) {
+    const int4 x = st[j];
+    const int f4[4] = {x.x, x.y, x.z, x.w};
+    bool use[4];
+    int c[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      use[k] = 4 * j + k < n && f4[k] != E.f1 && f4[k] != E.f2;
+      const int f = use[k] ? f4[k] : E.f1;
+#pragma unroll
+      for (int i = 0; i < 3; i++) c[k][i] = m.F[3 * (int64_t)f + i];
+    }
+    P3 p[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+#pragma unroll
+      for (int i = 0; i < 3; i++) {
+        const P3 q = ld3(m.V, c[k][i]);
+        p[k][i] = (c[k][i] == E.s || c[k][i] == E.r) ? vb : q;
+      }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const double t = skinny_term(p[k][0], p[k][1], p[k][2]);
+      S = use[k] ? S + t : S;
+    }
+  }
+  return S;
+}
+
+// cost (Eq. 1) and placement of edge E; the skinny terms are summed over the
+// faces around s, then those around r, each in ascending face slot
+__device__ __forceinline__ double edge_cost(const MeshView& m, const double* __restrict__ Q, const EdgeStars& E,
                                             double w_e, double w_s, P3& vbar) {
-  int a = m.F[h], b = m.F[he_next(h)];
-  int s = a < b ? a : b, r = a < b ? b : a;
+  const int s = E.s, r = E.r;
   double q[10];
 #pragma unroll
   for (int i = 0; i < 10; i++) q[i] = Q[10 * (int64_t)s + i] + Q[10 * (int64_t)r + i];
   P3 ps = ld3(m.V, s), pr = ld3(m.V, r);
-  vbar = placement(q, ps, pr, R.lo, R.hi);
+  vbar = placement(q, ps, pr, E.lo, E.hi);
   double dx = ps.x - pr.x, dy = ps.y - pr.y, dz = ps.z - pr.z;
   double lab = sqrt(dx * dx + dy * dy + dz * dz);
   double S = 0.0;
-  int last = -1;
-  for (int k = 0; k < R.n; k++) {
-    int f = ring_next(m, h, R, last);
-    last = f;
-    S = S + skinny_term(corner_after(m, f, 0, s, r, vbar), corner_after(m, f, 1, s, r, vbar),
-                        corner_after(m, f, 2, s, r, vbar));
+  const P3 vb = vbar;
+  if (E.fast) {
+    S = skinny_sum_star(m, E, s, E.ns, vb, S);
+    S = skinny_sum_star(m, E, r, E.nr, vb, S);
+  } else {
+    auto add = [&](int f) {
+      S = S + skinny_term(corner_after(m, f, 0, s, r, vb), corner_after(m, f, 1, s, r, vb),
+                          corner_after(m, f, 2, s, r, vb));
+    };
+    star_ascending(m, E, s, E.hs, E.ns, add);
+    star_ascending(m, E, r, E.hr, E.nr, add);
   }
   return quadric_eval(q, vbar) + w_e * lab + w_s * S;
 }
 
 // ------------------------------------------------------------ cost + keys
 // One thread per edge: each wave gathers the representative half-edges
-// (h < twin h) of its 256 consecutive half-edges into an LDS queue and then
-// evaluates them with all 64 lanes busy (one thread per half-edge would leave
-// half the lanes idle).
-constexpr int CK_PER_WAVE = 256;
+// (h < twin h) of its PW consecutive half-edges into an LDS queue and then
+// evaluates them with the lanes busy (one thread per half-edge would leave
+// half the lanes idle).  PW = 256 (two edges per lane) on large meshes; on
+// small ones PW = 64 (at most one edge per lane) puts four times as many waves
+// on the chip, since there the latency of one lane's loads sets the time.
+constexpr int64_t CK_SMALL_NH = 1 << 21;
 
+template <int PW>
 __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
                                                    const uint8_t* __restrict__ demote,
                                                    const uint8_t* __restrict__ mesh_done, uint64_t* __restrict__ key,
                                                    int* err) {
-  __shared__ int queue[4][CK_PER_WAVE];
+  __shared__ int queue[4][PW];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t nh = 3 * (int64_t)m.nf;
-  const int64_t base = ((int64_t)blockIdx.x * 4 + w) * CK_PER_WAVE;
+  const int64_t base = ((int64_t)xcd_block() * 4 + w) * PW;
   int count = 0;
 #pragma unroll
-  for (int j = 0; j < CK_PER_WAVE / 64; j++) {
+  for (int j = 0; j < PW / 64; j++) {
     const int64_t h = base + 64 * j + lane;
     const bool rep = h < nh && h < m.twin[h];
     const unsigned long long b = __ballot(rep);
@@ -358,12 +403,12 @@ __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __r
     bool skip = m.flags[h] || m.flags[t] || (demote && (demote[h] || demote[t])) ||
                 (mesh_done && mesh_done[m.fmesh[h / 3]]);
     if (!skip) {
-      EdgeRing R;
-      if (!edge_ring(m, h, R)) {
+      EdgeStars E;
+      if (!edge_stars(m, h, E)) {
         set_err(err, PAMO_EBIT_RING);
       } else {
         P3 vbar;
-        double cost = edge_cost(m, Q, h, R, w_e, w_s, vbar);
+        double cost = edge_cost(m, Q, E, w_e, w_s, vbar);
         k = make_key(cost, (uint32_t)h);
       }
     }
@@ -464,18 +509,13 @@ __global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* _
   if (!link_ok(m, h)) {
     rs = 1;
   } else {
-    EdgeRing R;
-    if (!edge_ring(m, h, R)) set_err(err, PAMO_EBIT_RING);
-    int nring = R.n;
-    (void)edge_cost(m, Q, h, R, w_e, w_s, vbar);
-    // the ring list was consumed; walk the stars again for the checks
-    int a = m.F[h], b = m.F[he_next(h)];
-    int s = a < b ? a : b, r = a < b ? b : a;
-    int f1 = h / 3, f2 = m.twin[h] / 3;
+    EdgeStars E;
+    if (!edge_stars(m, h, E)) set_err(err, PAMO_EBIT_RING);
+    (void)edge_cost(m, Q, E, w_e, w_s, vbar);
+    const int s = E.s, r = E.r;
     bool bad = false;
-    auto chk = [&](int g) {
-      int f = g / 3;
-      if (f == f1 || f == f2 || bad) return;
+    auto chk = [&](int f) {
+      if (bad) return;
       P3 o0 = ld3(m.V, m.F[3 * f]), o1 = ld3(m.V, m.F[3 * f + 1]), o2 = ld3(m.V, m.F[3 * f + 2]);
       P3 p0 = corner_after(m, f, 0, s, r, vbar), p1 = corner_after(m, f, 1, s, r, vbar),
          p2 = corner_after(m, f, 2, s, r, vbar);
@@ -492,9 +532,8 @@ __global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* _
       double dot = nox * nnx + noy * nny + noz * nnz;
       if (!(dot > 0.0)) bad = true;
     };
-    (void)nring;
-    walk_star(m.twin, h, chk);
-    walk_star(m.twin, m.twin[h], chk);
+    star_ascending(m, E, s, E.hs, E.ns, chk);
+    star_ascending(m, E, r, E.hr, E.nr, chk);
     if (bad) rs = 2;
   }
   reason[c] = rs;
@@ -920,8 +959,13 @@ void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err) {
 
 void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
                       const uint8_t* mesh_done, uint64_t* key, int* err) {
-  hipLaunchKernelGGL(k_cost_keys, dim3(nblk(3 * (int64_t)m.nf, 4 * CK_PER_WAVE)), dim3(256), 0, s, m, Q, w_e, w_s,
-                     demote, mesh_done, key, err);
+  const int64_t nh = 3 * (int64_t)m.nf;
+  if (nh <= CK_SMALL_NH)
+    hipLaunchKernelGGL(k_cost_keys<64>, dim3(nblk(nh, 4 * 64)), dim3(256), 0, s, m, Q, w_e, w_s, demote, mesh_done,
+                       key, err);
+  else
+    hipLaunchKernelGGL(k_cost_keys<256>, dim3(nblk(nh, 4 * 256)), dim3(256), 0, s, m, Q, w_e, w_s, demote, mesh_done,
+                       key, err);
   PAMO_HIP(hipGetLastError());
 }
 

@@ -90,3 +90,26 @@ def test_round0_full_size_elementwise(ctx, mesh):
     assert np.array_equal(F1.cpu().numpy(), r["F"])
     assert np.array_equal(V1.cpu().numpy().view(np.uint64), r["V"].view(np.uint64))
     assert np.array_equal(fl1.cpu().numpy(), r["flags"])
+
+
+def test_round0_beyond_two_pass_scan(ctx):
+    """Round 0 of a 1,568,000-face noisy geodesic sphere (4,704,000 half-edges,
+    more than 1,024 scan tiles of 4,096: the compactions take their three-pass
+    form) element by element against the oracle: candidates, reasons,
+    placements and the collapsed mesh."""
+    V, F = g.noisy_geodesic_sphere(280, 7)
+    assert 3 * len(F) > 1024 * 4096
+    Vd, Fd = torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda()
+    target = len(F) // 100
+    cand, _, n = ctx.select(Vd, Fd)
+    vbar, reason, iters = ctx.check(Vd, Fd, target, cand, n)
+    co, vo, ro, it_o = orc.check(V, F, target)
+    assert np.array_equal(cand.cpu().numpy(), co)
+    assert np.array_equal(reason.cpu().numpy(), ro)
+    assert np.array_equal(vbar.cpu().numpy().view(np.uint64), vo.view(np.uint64))
+    assert iters == it_o
+    V1, F1, fl1 = ctx.collapse(Vd, Fd, cand, n, vbar, reason)
+    r = orc.run(V, F, target, max_rounds=1)
+    assert np.array_equal(F1.cpu().numpy(), r["F"])
+    assert np.array_equal(V1.cpu().numpy().view(np.uint64), r["V"].view(np.uint64))
+    assert np.array_equal(fl1.cpu().numpy(), r["flags"])
