@@ -215,6 +215,8 @@ def main():
     ap.add_argument("--no-sharp", action="store_true", help="skip the sharp-feature batch")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB on the device three times (scale of the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the method shards by mesh "
@@ -222,6 +224,16 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        # a plain device copy of known size: FETCH_SIZE / WRITE_SIZE of this
+        # kernel against the 1 GiB it moves give the counters' scale
+        a = torch.ones(1 << 28, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {4 << 28} bytes three times")
+        return
     from paper_2509_05595_amd import meshgen, native
 
     V, F = meshgen.noisy_icosphere(args.refine, 2)

@@ -411,7 +411,7 @@ void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand
   qa.fmesh = m.fmesh;
   qa.err = cnt + C_ERR;
   init_pair_buffer(c, qa, m.nf);
-  const double qbytes = 64 * (nf - 1) + 17 * nf + 24 * nv;  // tree + faces + alive/owner + vertices
+  const double qbytes = 128.0 * bvh_nodes_written(m.nf) + 17 * nf + 24 * nv;  // tree + faces + alive/owner + vertices
   const double pbytes = 17 * nf + 24 * nv;                   // pairs: faces, alive/owner, vertices (+ 8 per pair)
   qa.ovl_cnt = ovl_new;  // overlap counts of the changed faces on the tentative mesh
   h = query_pass(c, bvh, QUERY_CHANGED, b.qlist, cnt + C_NQ, m.nf, 10ll * R.chosen, qa, qbytes, pbytes);

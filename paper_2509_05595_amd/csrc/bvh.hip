@@ -2,13 +2,13 @@
 // (the paper's intersection check, Sec. 5.2, uses a Karras-style LBVH).
 //
 // Build: 30-bit Morton code of each box centre -> stable radix sort -> a
-// balanced implicit binary tree over the sorted leaves (node k has children
-// 2k+1, 2k+2; leaf j sits below node (2^H - 1 + j - 1) / 2).  Boxes are
-// reduced level by level inside LDS, 11 levels per launch, so the build needs
-// no atomics and no device-scope fences: on a chip whose L2 is split over 8
-// XCDs those fences write back L2 and dominated the atomic bottom-up pass of a
-// Karras tree.  Depth is ceil(log2 n), which bounds the traversal stack.
-// Each node stores both child boxes (64 B, one load per visit).
+// balanced implicit 4-ary tree over the sorted leaves (node k has children
+// 4k+1 .. 4k+4).  Boxes are reduced level by level inside LDS, five levels
+// per launch, so the build needs no atomics and no device-scope fences: on a
+// chip whose L2 is split over 8 XCDs those fences write back L2 and dominated
+// the atomic bottom-up pass of a Karras tree.  A node holds the boxes of its
+// four children (128 B, fetched together): a query walks half as many levels
+// as in a binary tree.
 //
 // Query: one thread per query triangle walks the tree and only collects
 // candidate pairs (wave-aggregated appends); a second kernel evaluates the
@@ -21,11 +21,16 @@ namespace pamo {
 
 namespace {
 
-constexpr int LVL = 11;  // levels reduced per launch (2048 boxes in LDS)
+constexpr int LVL = 5;  // levels reduced per launch (4^5 = 1024 boxes in LDS)
 constexpr int LVL_T = 256;
-constexpr int STACK = 32;  // >= tree depth - 1; depth <= 30 for int32 face ids
+constexpr int STACK = 16;  // >= BVH_DMAX: one entry per level above the current node
+
+// level of internal node k: (4^l - 1)/3 <= k < (4^(l+1) - 1)/3, i.e. 4^l <= 3k+1
+__device__ __forceinline__ int node_level(int k) { return (31 - __clz(3 * k + 1)) >> 1; }
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
+// grids for xcd_item: a multiple of 8 blocks
+inline unsigned nblk8(int64_t n, int t = 256) { return (nblk(n, t) + 7u) & ~7u; }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t v) {
   uint32_t r = 0;
@@ -95,59 +100,63 @@ __device__ __forceinline__ Box unite(const Box& a, const Box& b) {
   return r;
 }
 
-__device__ __forceinline__ void write_node(BvhNode* nodes, int64_t k, const Box& L, const Box& R, int lf, int rf) {
-  BvhNode n;
-  n.a = make_float4(L.lo[0], L.lo[1], L.lo[2], L.hi[0]);
-  n.b = make_float4(L.hi[1], L.hi[2], R.lo[0], R.lo[1]);
-  n.c = make_float4(R.lo[2], R.hi[0], R.hi[1], R.hi[2]);
-  n.d = make_int4(lf, rf, 0, 0);
-  nodes[k] = n;
+__device__ __forceinline__ BvhNode make_node(const Box* c, int4 leaf) {
+  BvhNode nd;
+  nd.lx = make_float4(c[0].lo[0], c[1].lo[0], c[2].lo[0], c[3].lo[0]);
+  nd.ly = make_float4(c[0].lo[1], c[1].lo[1], c[2].lo[1], c[3].lo[1]);
+  nd.lz = make_float4(c[0].lo[2], c[1].lo[2], c[2].lo[2], c[3].lo[2]);
+  nd.hx = make_float4(c[0].hi[0], c[1].hi[0], c[2].hi[0], c[3].hi[0]);
+  nd.hy = make_float4(c[0].hi[1], c[1].hi[1], c[2].hi[1], c[3].hi[1]);
+  nd.hz = make_float4(c[0].hi[2], c[1].hi[2], c[2].hi[2], c[3].hi[2]);
+  nd.leaf = leaf;
+  nd.pad = make_int4(0, 0, 0, 0);
+  return nd;
 }
 
-// One launch reduces `lv` levels above level l0.  Block b owns the 2^lv boxes
-// [b 2^lv, (b+1) 2^lv) of level l0 (leaves when l0 == 0: box of face
-// sorted[j], empty beyond n), writes the node records of levels l0+1..l0+lv
-// and the box of its subtree root to top[b].
+// One launch reduces `lv` levels above height h0 (h0 = 0: the leaves).  Block
+// b owns the 4^lv boxes [b 4^lv, (b+1) 4^lv) of height h0 (leaves: box of face
+// sorted[j], empty beyond n; above: in[j], empty beyond cnt), writes the node
+// records of heights h0+1 .. h0+lv and the box of its subtree root to top[b].
 __global__ __launch_bounds__(LVL_T) void k_levels(const float* __restrict__ leafbox, const int* __restrict__ sorted,
-                                                  int n, const Box* __restrict__ in, Box* __restrict__ top, int l0,
-                                                  int lv, int H, BvhNode* __restrict__ nodes) {
-  __shared__ Box sb[1 << LVL];
-  __shared__ int sf[1 << LVL];
-  const int M = 1 << lv;
+                                                  int n, const Box* __restrict__ in, int cnt, Box* __restrict__ top,
+                                                  int h0, int lv, int D, BvhNode* __restrict__ nodes) {
+  __shared__ Box sb[1 << (2 * LVL)];
+  __shared__ int sf[1 << (2 * LVL)];
+  const int M = 1 << (2 * lv);
   const int64_t base = (int64_t)blockIdx.x * M;
   for (int i = threadIdx.x; i < M; i += LVL_T) {
     int64_t j = base + i;
     Box b = empty_box();
     int f = -1;
-    if (l0 == 0) {
+    if (h0 == 0) {
       if (j < n) {
         f = sorted[j];
         const float* p = leafbox + 6 * (int64_t)f;
         b = Box{{p[0], p[1], p[2]}, {p[3], p[4], p[5]}};
       }
-    } else {
+    } else if (j < cnt) {
       b = in[j];
     }
     sb[i] = b;
     sf[i] = f;
   }
   __syncthreads();
-  const int64_t N0 = (int64_t)1 << H;
   for (int k = 1; k <= lv; k++) {
-    int cnt = M >> k;
-    int level = l0 + k;
-    Box u[(1 << LVL) / 2 / LVL_T];
-    int nu = 0;
-    for (int t = threadIdx.x; t < cnt; t += LVL_T) {
-      Box L = sb[2 * t], R = sb[2 * t + 1];
-      int lf = level == 1 ? sf[2 * t] : -1, rf = level == 1 ? sf[2 * t + 1] : -1;
-      int64_t j = (base >> k) + t;
-      write_node(nodes, (N0 >> level) - 1 + j, L, R, lf, rf);
-      u[nu++] = unite(L, R);
+    const int cntk = M >> (2 * k);
+    const int level = D - (h0 + k);
+    const int64_t first = ((((int64_t)1) << (2 * level)) - 1) / 3;  // heap index of the level's first node
+    static_assert((1 << (2 * LVL)) / 4 <= LVL_T, "one node per thread and level");
+    Box u = empty_box();
+    const int t = threadIdx.x;
+    if (t < cntk) {
+      const Box c[4] = {sb[4 * t], sb[4 * t + 1], sb[4 * t + 2], sb[4 * t + 3]};
+      const int4 lf = h0 + k == 1 ? make_int4(sf[4 * t], sf[4 * t + 1], sf[4 * t + 2], sf[4 * t + 3])
+                                  : make_int4(-1, -1, -1, -1);
+      nodes[first + (base >> (2 * k)) + t] = make_node(c, lf);
+      u = unite(unite(c[0], c[1]), unite(c[2], c[3]));
     }
     __syncthreads();
-    nu = 0;
-    for (int t = threadIdx.x; t < cnt; t += LVL_T) sb[t] = u[nu++];
+    if (t < cntk) sb[t] = u;
     __syncthreads();
   }
   if (threadIdx.x == 0) top[blockIdx.x] = sb[0];
@@ -310,17 +319,30 @@ __device__ __forceinline__ void query_box(const QueryArgs& a, int t, float* tb) 
   }
 }
 
+// overlap mask of the four child boxes of nd with box b (bit c: child c)
+__device__ __forceinline__ int child_hits(const BvhNode& nd, const float* b) {
+  const float lx[4] = {nd.lx.x, nd.lx.y, nd.lx.z, nd.lx.w}, ly[4] = {nd.ly.x, nd.ly.y, nd.ly.z, nd.ly.w};
+  const float lz[4] = {nd.lz.x, nd.lz.y, nd.lz.z, nd.lz.w}, hx[4] = {nd.hx.x, nd.hx.y, nd.hx.z, nd.hx.w};
+  const float hy[4] = {nd.hy.x, nd.hy.y, nd.hy.z, nd.hy.w}, hz[4] = {nd.hz.x, nd.hz.y, nd.hz.z, nd.hz.w};
+  int m = 0;
+#pragma unroll
+  for (int c = 0; c < 4; c++)
+    m |= (lx[c] <= b[3] && b[0] <= hx[c] && ly[c] <= b[4] && b[1] <= hy[c] && lz[c] <= b[5] && b[2] <= hz[c]) << c;
+  return m;
+}
+
 // Wave-cooperative traversal in packets of G lanes.  The query list is in
 // Morton order, so the G queries of a packet are neighbours; each packet walks
-// the tree once (its lanes load the same node: one coalesced request), entering
-// a child when any of its lanes' own boxes meets it (the packet's union box is
-// a cheap uniform pre-test).  The 64/G packets of a wave advance in lockstep,
-// each with its own stack in LDS.  At a node whose children are leaves every
-// lane tests its own box; hits are staged per wave in LDS and flushed with one
+// the tree once (its lanes load the same node: one coalesced request),
+// entering a child when any of its lanes' own boxes meets it (the packet's
+// union box is a cheap uniform pre-test).  The stack holds one entry per level:
+// a node and the mask of its children still to visit, so it never exceeds the
+// depth.  At a node of the last internal level every lane tests its own box
+// against the four leaves; hits are staged per wave in LDS and flushed with one
 // atomic per ~200 pairs.  The traversal does no data-dependent loads besides
 // the nodes: the state filters run in the pair kernel.
 template <int MODE, int G>
-__global__ __launch_bounds__(64 * WPB) void k_collect(const BvhNode* __restrict__ nodes, int H, int n,
+__global__ __launch_bounds__(64 * WPB) void k_collect(const BvhNode* __restrict__ nodes, int D, int n,
                                                       const int* __restrict__ qlist, const int* __restrict__ nq,
                                                       QueryArgs a) {
   constexpr int NG = 64 / G;
@@ -330,10 +352,13 @@ __global__ __launch_bounds__(64 * WPB) void k_collect(const BvhNode* __restrict_
   const int lane = lane_id();
   const int grp = lane / G;
   const unsigned long long gmask = (G == 64 ? ~0ull : (((1ull << G) - 1) << (grp * G)));
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // XCD-contiguous ranges of the query list: it is in leaf (Morton) order, so
+  // each XCD walks one region of the tree and keeps its nodes in its own L2
   const int nqv = *nq;
-  if (blockIdx.x * blockDim.x + w * 64 >= nqv || n < 2) return;  // whole wave idle
-  const bool active = i < nqv;
+  int64_t end;
+  const int64_t i = xcd_item(nqv, blockDim.x, threadIdx.x, &end);
+  if (i - lane >= end || n < 2) return;  // whole wave idle
+  const bool active = i < end;
   const int t = active ? qlist[i] : -1;
   float tb[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
   if (active) query_box(a, t, tb);
@@ -345,67 +370,78 @@ __global__ __launch_bounds__(64 * WPB) void k_collect(const BvhNode* __restrict_
   }
   Stage st{sbuf[w], 0};
   int* stk = sstack[w][grp];
-  const int64_t leaf0 = ((int64_t)1 << H) - 1;  // heap index of the first leaf
   // a packet with no active lane has an empty union box: it is done at once
   bool done = !(ub[0] <= ub[3]);
   int sp = 0;
   int node = 0;
   while (__ballot(!done)) {
-    bool hl = false, hr = false;
-    int lf = 0, rf = 0;
+    int hit = 0;
+    int4 lf = make_int4(-1, -1, -1, -1);
     if (!done) {
       const BvhNode nd = nodes[node];
-      const bool uL = box_hit(ub, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y);
-      const bool uR = box_hit(ub, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w);
-      const bool oL = uL && box_hit(tb, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y);
-      const bool oR = uR && box_hit(tb, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w);
-      const int cl = 2 * node + 1;
       int next = -1;
-      if (cl >= leaf0) {  // both children are leaves
-        lf = nd.d.x;
-        rf = nd.d.y;
-        hl = oL && lf >= 0 && lf != t;
-        hr = oR && rf >= 0 && rf != t;
+      if (node_level(node) == D - 1) {  // the children are leaves
+        hit = child_hits(nd, tb);
+        lf = nd.leaf;
       } else {
-        const bool anyL = (__ballot(oL) & gmask) != 0, anyR = (__ballot(oR) & gmask) != 0;
-        if (anyL) {
-          next = cl;
-          if (anyR) stk[sp++] = cl + 1;  // depth <= H < STACK; every lane of the packet writes the same value
-        } else if (anyR) {
-          next = cl + 1;
+        int pm;
+        if (G == 1) {
+          pm = child_hits(nd, tb);
+        } else {
+          const int um = child_hits(nd, ub);  // uniform over the packet
+          const int own = um ? child_hits(nd, tb) : 0;
+          pm = 0;
+#pragma unroll
+          for (int c = 0; c < 4; c++) pm |= ((__ballot((own >> c) & 1) & gmask) != 0) << c;
+        }
+        if (pm) {
+          next = 4 * node + 1 + __builtin_ctz(pm);
+          pm &= pm - 1;
+          if (pm) stk[sp++] = (node << 4) | pm;  // one entry per level: sp < D <= STACK
         }
       }
       if (next < 0) {
-        if (sp == 0)
+        if (sp == 0) {
           done = true;
-        else
-          next = stk[--sp];
+        } else {  // next child of the deepest node with children left
+          const int e = stk[sp - 1];
+          const int k = e >> 4;
+          int msk = e & 15;
+          next = 4 * k + 1 + __builtin_ctz(msk);
+          msk &= msk - 1;
+          if (msk)
+            stk[sp - 1] = (k << 4) | msk;
+          else
+            sp--;
+        }
       }
       node = next;
     }
-    stage_append(st, hl, t, lf, a.cand, a.ncand, a.cand_cap);
-    stage_append(st, hr, t, rf, a.cand, a.ncand, a.cand_cap);
+    stage_append(st, (hit & 1) && lf.x >= 0 && lf.x != t, t, lf.x, a.cand, a.ncand, a.cand_cap);
+    stage_append(st, (hit & 2) && lf.y >= 0 && lf.y != t, t, lf.y, a.cand, a.ncand, a.cand_cap);
+    stage_append(st, (hit & 4) && lf.z >= 0 && lf.z != t, t, lf.z, a.cand, a.ncand, a.cand_cap);
+    stage_append(st, (hit & 8) && lf.w >= 0 && lf.w != t, t, lf.w, a.cand, a.ncand, a.cand_cap);
   }
   stage_flush(st, a.cand, a.ncand, a.cand_cap);
 }
 
 // Cooperative traversal: G lanes share ONE query.  The group keeps a stack of
 // pending nodes in LDS; each step its lanes pop up to G nodes (one each), load
-// them in parallel, test both children against the query box, push the
+// them in parallel, test the four children against the query box, push the
 // internal children that meet it and stage the leaf hits.  A query costs
 // about max(depth, visited nodes / G) dependent loads instead of one per
 // visited node, which matters when few queries are left (late rounds) and the
-// walk is bound by load latency rather than throughput.  Popping the top G
-// entries leaves at most G entries behind per level descended, so the stack
-// holds at most G (H + 2) entries.
-constexpr int COOP_HMAX = 24;
+// walk is bound by load latency rather than throughput.  A step pushes at
+// most 4 G entries and the next pops G of them, so at most 3 G entries are
+// left behind per level: the stack holds at most G (3 D + 4).
+constexpr int COOP_DMAX = 12;
 
 template <int MODE, int G>
-__global__ __launch_bounds__(64 * WPB) void k_collect_coop(const BvhNode* __restrict__ nodes, int H, int n,
+__global__ __launch_bounds__(64 * WPB) void k_collect_coop(const BvhNode* __restrict__ nodes, int D, int n,
                                                            const int* __restrict__ qlist, const int* __restrict__ nq,
                                                            QueryArgs a) {
   constexpr int NG = 64 / G;
-  constexpr int CST = G * (COOP_HMAX + 2);
+  constexpr int CST = G * (3 * COOP_DMAX + 4);
   __shared__ int2 sbuf[WPB][SEG];
   __shared__ int sstack[WPB][NG][CST];
   const int w = threadIdx.x >> 6;
@@ -413,17 +449,17 @@ __global__ __launch_bounds__(64 * WPB) void k_collect_coop(const BvhNode* __rest
   const int grp = lane / G, gl = lane % G;
   const unsigned long long gmask = (G == 64 ? ~0ull : (((1ull << G) - 1) << (grp * G)));
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const int wave_q0 = (blockIdx.x * WPB + w) * NG;
   const int nqv = *nq;
-  if (wave_q0 >= nqv || n < 2) return;  // whole wave idle
-  const int q = wave_q0 + grp;
-  const bool active = q < nqv;
+  int64_t end;  // XCD-contiguous ranges, as in k_collect
+  const int64_t wave_q0 = xcd_item(nqv, WPB * NG, w * NG, &end);
+  if (wave_q0 >= end || n < 2) return;  // whole wave idle
+  const int64_t q = wave_q0 + grp;
+  const bool active = q < end;
   const int t = active ? qlist[q] : -1;
   float tb[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
   if (active) query_box(a, t, tb);
   Stage st{sbuf[w], 0};
   int* stk = sstack[w][grp];
-  const int64_t leaf0 = ((int64_t)1 << H) - 1;
   if (active && gl == 0) stk[0] = 0;
   int sp = active ? 1 : 0;  // uniform over the group
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -432,38 +468,44 @@ __global__ __launch_bounds__(64 * WPB) void k_collect_coop(const BvhNode* __rest
     const int node = gl < take ? stk[sp - take + gl] : -1;
     sp -= take;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // pops read before pushes overwrite
-    bool hl = false, hr = false, pl = false, pr = false;
-    int lf = 0, rf = 0;
-    const int cl = 2 * node + 1;
+    int hit = 0, push = 0;
+    int4 lf = make_int4(-1, -1, -1, -1);
     if (node >= 0) {
       const BvhNode nd = nodes[node];
-      const bool oL = box_hit(tb, nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y);
-      const bool oR = box_hit(tb, nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w);
-      if (cl >= leaf0) {
-        lf = nd.d.x;
-        rf = nd.d.y;
-        hl = oL && lf >= 0 && lf != t;
-        hr = oR && rf >= 0 && rf != t;
+      const int m = child_hits(nd, tb);
+      if (node_level(node) == D - 1) {
+        hit = m;
+        lf = nd.leaf;
       } else {
-        pl = oL;
-        pr = oR;
+        push = m;
       }
     }
-    const unsigned long long bl = __ballot(pl) & gmask, br = __ballot(pr) & gmask;
-    int pos = sp + __popcll(bl & below) + __popcll(br & below);
-    if (pl) {
-      if (pos < CST) stk[pos] = cl;
-      pos++;
-    }
-    if (pr && pos < CST) stk[pos] = cl + 1;
-    sp += __popcll(bl) + __popcll(br);
-    if (sp > CST) {  // cannot happen for H <= COOP_HMAX; report instead of losing pairs
+    // group-wide offsets of this lane's pushes: lanes below it push first
+    const int np = __popc(push);
+    int before = 0;
+#pragma unroll
+    for (int c = 0; c < 4; c++) before += __popcll(__ballot((push >> c) & 1) & gmask & below);
+    int total = 0;
+#pragma unroll
+    for (int c = 0; c < 4; c++) total += __popcll(__ballot((push >> c) & 1) & gmask);
+    int pos = sp + before;
+#pragma unroll
+    for (int c = 0; c < 4; c++)
+      if ((push >> c) & 1) {
+        if (pos < CST) stk[pos] = 4 * node + 1 + c;
+        pos++;
+      }
+    (void)np;
+    sp += total;
+    if (sp > CST) {  // cannot happen for D <= COOP_DMAX; report instead of losing pairs
       if (gl == 0) atomicOr(a.err, PAMO_EBIT_STACK);
       sp = 0;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    stage_append(st, hl, t, lf, a.cand, a.ncand, a.cand_cap);
-    stage_append(st, hr, t, rf, a.cand, a.ncand, a.cand_cap);
+    stage_append(st, (hit & 1) && lf.x >= 0 && lf.x != t, t, lf.x, a.cand, a.ncand, a.cand_cap);
+    stage_append(st, (hit & 2) && lf.y >= 0 && lf.y != t, t, lf.y, a.cand, a.ncand, a.cand_cap);
+    stage_append(st, (hit & 4) && lf.z >= 0 && lf.z != t, t, lf.z, a.cand, a.ncand, a.cand_cap);
+    stage_append(st, (hit & 8) && lf.w >= 0 && lf.w != t, t, lf.w, a.cand, a.ncand, a.cand_cap);
   }
   stage_flush(st, a.cand, a.ncand, a.cand_cap);
 }
@@ -518,11 +560,11 @@ Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf, const int*
               int nmesh) {
   Bvh b;
   b.n = nf;
-  int H = 1;
-  while (((int64_t)1 << H) < nf) H++;
-  b.H = H;
-  int64_t N0 = (int64_t)1 << H;
-  b.nodes = ws.get<BvhNode>("bvh.nodes", N0 - 1);
+  int D = 1;
+  while (((int64_t)1 << (2 * D)) < nf) D++;
+  if (D > BVH_DMAX) throw std::runtime_error("mesh too large for the BVH (more than 4^14 faces)");
+  b.D = D;
+  b.nodes = ws.get<BvhNode>("bvh.nodes", ((((int64_t)1) << (2 * D)) - 1) / 3);
   b.sorted = nullptr;
   if (nf < 2) return b;
   const int* id = order;
@@ -542,19 +584,22 @@ Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf, const int*
     id = ids;
   }
   b.sorted = id;
-  Box* ta = ws.get<Box>("bvh.topA", (N0 >> LVL) + 1);
-  Box* tb = ws.get<Box>("bvh.topB", (N0 >> LVL) + 1);
-  int l0 = 0;
+  const int64_t top_cap = ((int64_t)nf + (1 << (2 * LVL)) - 1) >> (2 * LVL);
+  Box* ta = ws.get<Box>("bvh.topA", top_cap + 1);
+  Box* tb = ws.get<Box>("bvh.topB", top_cap + 1);
+  int h0 = 0;
+  int64_t cnt = nf;  // boxes of height h0 that may be non-empty
   const Box* in = nullptr;
   Box* out = ta;
-  while (l0 < H) {
-    int lv = H - l0 < LVL ? H - l0 : LVL;
-    int64_t blocks = N0 >> (l0 + lv);
-    hipLaunchKernelGGL(k_levels, dim3((unsigned)blocks), dim3(LVL_T), 0, s, box, id, nf, in, out, l0,
-                       lv, H, b.nodes);
+  while (h0 < D) {
+    const int lv = D - h0 < LVL ? D - h0 : LVL;
+    const int64_t blocks = (cnt + (1ll << (2 * lv)) - 1) >> (2 * lv);
+    hipLaunchKernelGGL(k_levels, dim3((unsigned)blocks), dim3(LVL_T), 0, s, box, id, nf, in, (int)cnt, out, h0, lv, D,
+                       b.nodes);
     in = out;
     out = out == ta ? tb : ta;
-    l0 += lv;
+    cnt = blocks;
+    h0 += lv;
   }
   PAMO_HIP(hipGetLastError());
   return b;
@@ -566,31 +611,31 @@ void launch_collect_g(hipStream_t s, const Bvh& bvh, QueryMode mode, const int* 
   dim3 t(64 * WPB);
   const BvhNode* nodes = bvh.nodes;
   if (mode == QUERY_CHANGED)
-    hipLaunchKernelGGL((k_collect<QUERY_CHANGED, G>), g, t, 0, s, nodes, bvh.H, bvh.n, qlist, nq, a);
+    hipLaunchKernelGGL((k_collect<QUERY_CHANGED, G>), g, t, 0, s, nodes, bvh.D, bvh.n, qlist, nq, a);
   else if (mode == QUERY_RESTORED)
-    hipLaunchKernelGGL((k_collect<QUERY_RESTORED, G>), g, t, 0, s, nodes, bvh.H, bvh.n, qlist, nq, a);
+    hipLaunchKernelGGL((k_collect<QUERY_RESTORED, G>), g, t, 0, s, nodes, bvh.D, bvh.n, qlist, nq, a);
   else
-    hipLaunchKernelGGL((k_collect<QUERY_ALL_PAIRS, G>), g, t, 0, s, nodes, bvh.H, bvh.n, qlist, nq, a);
+    hipLaunchKernelGGL((k_collect<QUERY_ALL_PAIRS, G>), g, t, 0, s, nodes, bvh.D, bvh.n, qlist, nq, a);
 }
 
 template <int G>
 void launch_coop_g(hipStream_t s, const Bvh& bvh, QueryMode mode, const int* qlist, const int* nq, int nq_bound,
                    const QueryArgs& a) {
-  dim3 g(nblk((int64_t)nq_bound * G, 64 * WPB)), t(64 * WPB);
+  dim3 g(nblk8((int64_t)nq_bound * G, 64 * WPB)), t(64 * WPB);
   const BvhNode* nodes = bvh.nodes;
   if (mode == QUERY_CHANGED)
-    hipLaunchKernelGGL((k_collect_coop<QUERY_CHANGED, G>), g, t, 0, s, nodes, bvh.H, bvh.n, qlist, nq, a);
+    hipLaunchKernelGGL((k_collect_coop<QUERY_CHANGED, G>), g, t, 0, s, nodes, bvh.D, bvh.n, qlist, nq, a);
   else if (mode == QUERY_RESTORED)
-    hipLaunchKernelGGL((k_collect_coop<QUERY_RESTORED, G>), g, t, 0, s, nodes, bvh.H, bvh.n, qlist, nq, a);
+    hipLaunchKernelGGL((k_collect_coop<QUERY_RESTORED, G>), g, t, 0, s, nodes, bvh.D, bvh.n, qlist, nq, a);
   else
-    hipLaunchKernelGGL((k_collect_coop<QUERY_ALL_PAIRS, G>), g, t, 0, s, nodes, bvh.H, bvh.n, qlist, nq, a);
+    hipLaunchKernelGGL((k_collect_coop<QUERY_ALL_PAIRS, G>), g, t, 0, s, nodes, bvh.D, bvh.n, qlist, nq, a);
 }
 
 void launch_query(hipStream_t s, const Bvh& bvh, QueryMode mode, const int* qlist, const int* nq, int nq_bound,
                   const QueryArgs& a, int packet, int coop) {
   if (nq_bound <= 0 || bvh.n < 2) return;
-  if (bvh.H - 1 > STACK) throw std::runtime_error("BVH deeper than the traversal stack");
-  if (coop > 1 && bvh.H <= COOP_HMAX) {
+  if (bvh.D > STACK) throw std::runtime_error("BVH deeper than the traversal stack");
+  if (coop > 1 && bvh.D <= COOP_DMAX) {
     switch (coop) {
       case 2: launch_coop_g<2>(s, bvh, mode, qlist, nq, nq_bound, a); break;
       case 4: launch_coop_g<4>(s, bvh, mode, qlist, nq, nq_bound, a); break;
@@ -600,7 +645,7 @@ void launch_query(hipStream_t s, const Bvh& bvh, QueryMode mode, const int* qlis
     PAMO_HIP(hipGetLastError());
     return;
   }
-  dim3 g(nblk(nq_bound, 64 * WPB));
+  dim3 g(nblk8(nq_bound, 64 * WPB));
   switch (packet) {
     case 2: launch_collect_g<2>(s, bvh, mode, qlist, nq, g, a); break;
     case 4: launch_collect_g<4>(s, bvh, mode, qlist, nq, g, a); break;

@@ -39,6 +39,18 @@ __device__ __forceinline__ int xcd_block() {
   return x * per + (x < rem ? x : rem) + (b >> 3);
 }
 
+// Item of this thread when n items (n known on the device only; the grid has
+// a multiple of 8 blocks of `per` items each, at least n items in total) are
+// split into 8 contiguous ranges, one per XCD: XCD x takes [x c, (x+1) c),
+// c = ceil(n / 8), in the order of its blocks.  Valid when the result < *end.
+__device__ __forceinline__ int64_t xcd_item(int64_t n, int per, int within, int64_t* end) {
+  const int b = blockIdx.x, x = b & 7;
+  const int64_t c = (n + 7) >> 3;
+  const int64_t e = (int64_t)(x + 1) * c;
+  *end = e < n ? e : n;
+  return (int64_t)x * c + (int64_t)(b >> 3) * per + within;
+}
+
 PAMO_HD __forceinline__ int he_next(int h) { return h - h % 3 + (h % 3 == 2 ? 0 : h % 3 + 1); }
 PAMO_HD __forceinline__ int he_prev(int h) { return h - h % 3 + (h % 3 == 0 ? 2 : h % 3 - 1); }
 

@@ -126,18 +126,21 @@ __global__ void k_check_vertices(const int* __restrict__ twin, const int* __rest
 }
 
 // ------------------------------------------------------------ quadrics
+// One thread per vertex: walk the star once (sorted half-edge list in
+// registers), then sum the face quadrics in ascending face slot, four faces
+// at a time with their loads issued together.
 __global__ __launch_bounds__(256) void k_quadrics(MeshView m, double* __restrict__ Q, int* err) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= m.nv) return;
   constexpr int CAP = VSTAR;
-  int fl[CAP];
+  int hl[CAP];
 #pragma unroll
-  for (int i = 0; i < CAP; i++) fl[i] = INT32_MAX;
+  for (int i = 0; i < CAP; i++) hl[i] = INT32_MAX;
   int n = 0;
   P3 lo{INFINITY, INFINITY, INFINITY}, hi{-INFINITY, -INFINITY, -INFINITY};
   const bool stars = m.vstar != nullptr;
   bool ok = walk_star(m.twin, m.vh[v], [&](int h) {
-    if (n < CAP) sorted_insert<CAP>(fl, h / 3);
+    if (n < CAP) sorted_insert<CAP>(hl, h);
     n++;
   });
   if (!ok) {
@@ -147,28 +150,14 @@ __global__ __launch_bounds__(256) void k_quadrics(MeshView m, double* __restrict
   if (stars) {
     int4* o = reinterpret_cast<int4*>(m.vstar + (int64_t)VSTAR * v);
 #pragma unroll
-    for (int i = 0; i < CAP / 4; i++) o[i] = make_int4(fl[4 * i], fl[4 * i + 1], fl[4 * i + 2], fl[4 * i + 3]);
+    for (int i = 0; i < CAP / 4; i++) o[i] = make_int4(hl[4 * i], hl[4 * i + 1], hl[4 * i + 2], hl[4 * i + 3]);
     m.vdeg[v] = n;
   }
   double q[10];
 #pragma unroll
   for (int i = 0; i < 10; i++) q[i] = 0.0;
-  int last = -1;
-  for (int k = 0; k < n; k++) {
-    int f;
-    if (n <= CAP) {
-      f = pop_front<CAP>(fl);
-    } else {
-      int best = INT32_MAX;
-      walk_star(m.twin, m.vh[v], [&](int h) {
-        int g = h / 3;
-        if (g > last && g < best) best = g;
-      });
-      f = best;
-    }
-    last = f;
+  auto add_face = [&](P3 p0, P3 p1, P3 p2) {
     double K[10];
-    P3 p0 = ld3(m.V, m.F[3 * f]), p1 = ld3(m.V, m.F[3 * f + 1]), p2 = ld3(m.V, m.F[3 * f + 2]);
     face_quadric(p0, p1, p2, K);
     if (stars) {  // box of the closed 1-ring: every corner of the star
       lo.x = fmin(lo.x, fmin(fmin(p0.x, p1.x), p2.x));
@@ -180,6 +169,42 @@ __global__ __launch_bounds__(256) void k_quadrics(MeshView m, double* __restrict
     }
 #pragma unroll
     for (int i = 0; i < 10; i++) q[i] = q[i] + K[i];
+  };
+  if (n <= CAP) {
+    const P3 pv = ld3(m.V, v);
+#pragma unroll
+    for (int j = 0; j < CAP / 4; j++) {
+      if (4 * j >= n) break;
+      P3 p[4][3];
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        // corner g % 3 of face g / 3 is v itself: only the other two are loaded
+        const int g = 4 * j + k < n ? hl[4 * j + k] : hl[0];
+        const int f = g / 3, ci = g - 3 * f;
+        int c[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) c[i] = m.F[3 * (int64_t)f + i];
+        const int c1 = ci == 2 ? 0 : ci + 1, c2 = ci == 0 ? 2 : ci - 1;
+        const P3 q1 = ld3(m.V, c1 == 0 ? c[0] : c1 == 1 ? c[1] : c[2]);
+        const P3 q2 = ld3(m.V, c2 == 0 ? c[0] : c2 == 1 ? c[1] : c[2]);
+#pragma unroll
+        for (int i = 0; i < 3; i++) p[k][i] = i == ci ? pv : i == c1 ? q1 : q2;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+        if (4 * j + k < n) add_face(p[k][0], p[k][1], p[k][2]);
+    }
+  } else {
+    int last = -1;
+    for (int k = 0; k < n; k++) {
+      int best = INT32_MAX;
+      walk_star(m.twin, m.vh[v], [&](int h) {
+        int g = h / 3;
+        if (g > last && g < best) best = g;
+      });
+      last = best;
+      add_face(ld3(m.V, m.F[3 * best]), ld3(m.V, m.F[3 * best + 1]), ld3(m.V, m.F[3 * best + 2]));
+    }
   }
 #pragma unroll
   for (int i = 0; i < 10; i++) Q[10 * (int64_t)v + i] = q[i];
@@ -235,24 +260,11 @@ __device__ __forceinline__ bool edge_stars(const MeshView& m, int h, EdgeStars& 
   return ok && walk_star(m.twin, E.hr, visit);
 }
 
-// The faces of star(v) (v = E.s with hv = E.hs and n = E.ns, or the same for
-// r) other than the edge's two faces, in ascending face slot.  Fast path: the
-// stored sorted star, four slots per 16-byte load so the loads of four faces
-// are in flight together; otherwise repeated scans of the star for the next
-// larger slot.
+// The faces of star(v) (v = E.s with hv = E.hs, or r with E.hr) other than
+// the edge's two faces, in ascending face slot, by repeated scans of the star
+// for the next larger slot (the path for stars that were not stored).
 template <class Fn>
-__device__ __forceinline__ void star_ascending(const MeshView& m, const EdgeStars& E, int v, int hv, int n, Fn fn) {
-  if (E.fast) {
-    const int4* st = reinterpret_cast<const int4*>(m.vstar + (int64_t)VSTAR * v);
-    for (int j = 0; 4 * j < n; j++) {
-      const int4 x = st[j];
-      const int f4[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-      for (int k = 0; k < 4; k++)
-        if (4 * j + k < n && f4[k] != E.f1 && f4[k] != E.f2) fn(f4[k]);
-    }
-    return;
-  }
+__device__ __forceinline__ void star_ascending(const MeshView& m, const EdgeStars& E, int hv, Fn fn) {
   int last = -1;
   for (;;) {
     int best = INT32_MAX;
@@ -303,6 +315,74 @@ __device__ __forceinline__ P3 corner_after(const MeshView& m, int f, int c, int 
   return (v == s || v == r) ? vbar : ld3(m.V, v);
 }
 
+// The stored star of v (n <= VSTAR half-edges leaving v, ascending) without
+// those in faces x1 and x2, four at a time: fn(g, use) gets four half-edges;
+// slots past the end carry `pad` (a half-edge that is safe to read through)
+// and use = false.  The excluded slots are located once in the star's 64-byte
+// line and skipped, so the chunks are full (a valence-6 star around an edge is
+// one chunk of four).  The callee issues its loads for all four before acting
+// on any, so a star costs a few load latencies instead of one per face of a
+// twin walk.
+template <class Fn>
+__device__ __forceinline__ void star_chunks(const MeshView& m, int v, int n, int x1, int x2, int pad, Fn fn) {
+  const int* st = m.vstar + (int64_t)VSTAR * v;
+  int q1 = VSTAR, q2 = VSTAR;  // physical slots of the excluded faces, ascending
+  int cnt = n;
+  if (x1 >= 0 || x2 >= 0) {
+    const int4* s4 = reinterpret_cast<const int4*>(st);
+#pragma unroll
+    for (int q = 0; q < VSTAR / 4; q++) {
+      const int4 x = s4[q];
+      const int gq[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        const int f = gq[k] / 3;
+        const bool ex = 4 * q + k < n && (f == x1 || f == x2);
+        q2 = ex && q1 < VSTAR && q2 == VSTAR ? 4 * q + k : q2;
+        q1 = ex && q1 == VSTAR ? 4 * q + k : q1;
+      }
+    }
+    cnt = n - (q1 < VSTAR) - (q2 < VSTAR);
+  }
+  for (int j = 0; 4 * j < cnt; j++) {
+    int g[4];
+    bool use[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int i = 4 * j + k;
+      int phys = i;
+      phys += phys >= q1;
+      phys += phys >= q2;
+      use[k] = i < cnt;
+      const int e = st[use[k] ? phys : 0];
+      g[k] = use[k] ? e : pad;
+    }
+    fn(g, use);
+  }
+}
+
+// The whole stored star of v in registers: g[i] for i < n, slot 0 beyond
+// (n >= 1), one 64-byte load.
+__device__ __forceinline__ void star_all(const MeshView& m, int v, int n, int* g) {
+  const int4* st = reinterpret_cast<const int4*>(m.vstar + (int64_t)VSTAR * v);
+  int raw[VSTAR];
+#pragma unroll
+  for (int q = 0; q < VSTAR / 4; q++) {
+    const int4 x = st[q];
+    raw[4 * q] = x.x; raw[4 * q + 1] = x.y; raw[4 * q + 2] = x.z; raw[4 * q + 3] = x.w;
+  }
+#pragma unroll
+  for (int i = 0; i < VSTAR; i++) g[i] = i < n ? raw[i] : raw[0];
+}
+
+// both stars of an edge stored (inside a round, before the tentative apply)
+__device__ __forceinline__ bool stars_stored(const MeshView& m, int s, int r, int& ns, int& nr) {
+  if (!m.vstar) return false;
+  ns = m.vdeg[s];
+  nr = m.vdeg[r];
+  return ns <= VSTAR && nr <= VSTAR;
+}
+
 // S plus the skinny terms of the faces of the stored star of v (E.fast), in
 // slot order.  Four slots at a time, branch-free: every load of the four
 // faces (corner ids, then corner positions) is issued before any arithmetic,
@@ -310,33 +390,28 @@ __device__ __forceinline__ P3 corner_after(const MeshView& m, int f, int c, int 
 // nothing.  Same terms in the same order as star_ascending.
 __device__ __forceinline__ double skinny_sum_star(const MeshView& m, const EdgeStars& E, int v, int n, P3 vb,
                                                   double S) {
-  const int4* st = reinterpret_cast<const int4*>(m.vstar + (int64_t)VSTAR * v);
-  for (int j = 0; 4 * j < n; j++) {
-    const int4 x = st[j];
-    const int f4[4] = {x.x, x.y, x.z, x.w};
-    bool use[4];
-    int c[4][3];
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-      use[k] = 4 * j + k < n && f4[k] != E.f1 && f4[k] != E.f2;
-      const int f = use[k] ? f4[k] : E.f1;
-#pragma unroll
-      for (int i = 0; i < 3; i++) c[k][i] = m.F[3 * (int64_t)f + i];
-    }
+  star_chunks(m, v, n, E.f1, E.f2, E.hs, [&](const int* g, const bool* use) {
+    // corner g % 3 of face g / 3 is v and moves to vb (no other corner is s
+    // or r); only the other two corners are loaded
     P3 p[4][3];
 #pragma unroll
-    for (int k = 0; k < 4; k++)
+    for (int k = 0; k < 4; k++) {
+      const int f = g[k] / 3, ci = g[k] - 3 * f;
+      int c[3];
 #pragma unroll
-      for (int i = 0; i < 3; i++) {
-        const P3 q = ld3(m.V, c[k][i]);
-        p[k][i] = (c[k][i] == E.s || c[k][i] == E.r) ? vb : q;
-      }
+      for (int i = 0; i < 3; i++) c[i] = m.F[3 * (int64_t)f + i];
+      const int c1 = ci == 2 ? 0 : ci + 1, c2 = ci == 0 ? 2 : ci - 1;
+      const P3 q1 = ld3(m.V, c1 == 0 ? c[0] : c1 == 1 ? c[1] : c[2]);
+      const P3 q2 = ld3(m.V, c2 == 0 ? c[0] : c2 == 1 ? c[1] : c[2]);
+#pragma unroll
+      for (int i = 0; i < 3; i++) p[k][i] = i == ci ? vb : i == c1 ? q1 : q2;
+    }
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       const double t = skinny_term(p[k][0], p[k][1], p[k][2]);
       S = use[k] ? S + t : S;
     }
-  }
+  });
   return S;
 }
 
@@ -362,8 +437,8 @@ __device__ __forceinline__ double edge_cost(const MeshView& m, const double* __r
       S = S + skinny_term(corner_after(m, f, 0, s, r, vb), corner_after(m, f, 1, s, r, vb),
                           corner_after(m, f, 2, s, r, vb));
     };
-    star_ascending(m, E, s, E.hs, E.ns, add);
-    star_ascending(m, E, r, E.hr, E.nr, add);
+    star_ascending(m, E, E.hs, add);
+    star_ascending(m, E, E.hr, add);
   }
   return quadric_eval(q, vbar) + w_e * lab + w_s * S;
 }
@@ -418,15 +493,27 @@ __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __r
 }
 
 // ------------------------------------------------------------ selection
+// vmin[v]: smallest key of the edges at v (each is one half-edge leaving v)
 __global__ __launch_bounds__(256) void k_vertex_min(MeshView m, const uint64_t* __restrict__ key,
                                                     uint64_t* __restrict__ vmin) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= m.nv) return;
   uint64_t best = PAMO_KEY_MAX;
-  walk_star(m.twin, m.vh[v], [&](int h) {
-    uint64_t k = key[h];
-    best = k < best ? k : best;
-  });
+  const int n = m.vstar ? m.vdeg[v] : VSTAR + 1;
+  if (n <= VSTAR) {
+    int g[VSTAR];
+    star_all(m, v, n, g);
+    uint64_t k[VSTAR];
+#pragma unroll
+    for (int i = 0; i < VSTAR; i++) k[i] = key[g[i]];
+#pragma unroll
+    for (int i = 0; i < VSTAR; i++) best = k[i] < best ? k[i] : best;  // slots past n repeat slot 0
+  } else {
+    walk_star(m.twin, m.vh[v], [&](int h) {
+      uint64_t k = key[h];
+      best = k < best ? k : best;
+    });
+  }
   vmin[v] = best;
 }
 
@@ -442,11 +529,30 @@ __global__ __launch_bounds__(256) void k_select(MeshView m, const uint64_t* __re
     int a = m.F[h], b = m.F[he_next(h)];
     if (vmin[a] == k && vmin[b] == k) {
       bool local_min = true;
-      auto nb = [&](int g) {
-        if (vmin[dest(m.F, g)] < k) local_min = false;
-      };
-      walk_star(m.twin, h, nb);
-      if (local_min) walk_star(m.twin, m.twin[h], nb);
+      int na = 0, nb = 0;
+      if (stars_stored(m, a, b, na, nb)) {
+        // N(v): the far ends of the half-edges leaving v
+        auto side = [&](int v, int n) {
+          int g[VSTAR];
+          star_all(m, v, n, g);
+          int w[VSTAR];
+#pragma unroll
+          for (int i = 0; i < VSTAR; i++) w[i] = m.F[he_next(g[i])];
+          uint64_t mw[VSTAR];
+#pragma unroll
+          for (int i = 0; i < VSTAR; i++) mw[i] = vmin[w[i]];
+#pragma unroll
+          for (int i = 0; i < VSTAR; i++) local_min = local_min && !(mw[i] < k);
+        };
+        side(a, na);
+        side(b, nb);
+      } else {
+        auto nbr = [&](int g) {
+          if (vmin[dest(m.F, g)] < k) local_min = false;
+        };
+        walk_star(m.twin, h, nbr);
+        if (local_min) walk_star(m.twin, m.twin[h], nbr);
+      }
       ok = local_min;
     }
   }
@@ -495,6 +601,29 @@ __device__ __forceinline__ bool link_ok(const MeshView& m, int h) {
   return common == 2 && !(vala == 3 && valb == 3);
 }
 
+// the same test from the stored stars: N(v) = far ends of the half-edges
+// leaving v, each neighbour once
+__device__ __forceinline__ bool link_ok_stars(const MeshView& m, int a, int na, int b, int nb) {
+  int ga[VSTAR], gb[VSTAR];
+  star_all(m, a, na, ga);
+  star_all(m, b, nb, gb);
+  int wa[VSTAR], wb[VSTAR];
+#pragma unroll
+  for (int i = 0; i < VSTAR; i++) {
+    wa[i] = m.F[he_next(ga[i])];
+    wb[i] = m.F[he_next(gb[i])];
+  }
+  int common = 0;
+#pragma unroll
+  for (int j = 0; j < VSTAR; j++) {
+    bool in = false;
+#pragma unroll
+    for (int i = 0; i < VSTAR; i++) in |= i < na && wa[i] == wb[j];
+    common += j < nb && in;
+  }
+  return common == 2 && !(na == 3 && nb == 3);
+}
+
 __global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* __restrict__ Q, double w_e,
                                                      double w_s, const int* __restrict__ cand,
                                                      const int* __restrict__ ncand, const uint64_t* __restrict__ key,
@@ -506,7 +635,10 @@ __global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* _
   ckey[c] = key[h];
   uint8_t rs = 0;
   P3 vbar{0, 0, 0};
-  if (!link_ok(m, h)) {
+  int na = 0, nb = 0;
+  const int a0 = m.F[h], b0 = m.F[he_next(h)];
+  const bool fast = stars_stored(m, a0, b0, na, nb);
+  if (!(fast ? link_ok_stars(m, a0, na, b0, nb) : link_ok(m, h))) {
     rs = 1;
   } else {
     EdgeStars E;
@@ -514,15 +646,10 @@ __global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* _
     (void)edge_cost(m, Q, E, w_e, w_s, vbar);
     const int s = E.s, r = E.r;
     bool bad = false;
-    auto chk = [&](int f) {
-      if (bad) return;
-      P3 o0 = ld3(m.V, m.F[3 * f]), o1 = ld3(m.V, m.F[3 * f + 1]), o2 = ld3(m.V, m.F[3 * f + 2]);
-      P3 p0 = corner_after(m, f, 0, s, r, vbar), p1 = corner_after(m, f, 1, s, r, vbar),
-         p2 = corner_after(m, f, 2, s, r, vbar);
-      if (degenerate(p0, p1, p2)) {
-        bad = true;
-        return;
-      }
+    // generated triangle (corners after the collapse) degenerate or with its
+    // normal turned by 90 degrees or more against the original
+    auto flipped = [&](P3 o0, P3 o1, P3 o2, P3 p0, P3 p1, P3 p2) {
+      if (degenerate(p0, p1, p2)) return true;
       double ax = o1.x - o0.x, ay = o1.y - o0.y, az = o1.z - o0.z;
       double bx = o2.x - o0.x, by = o2.y - o0.y, bz = o2.z - o0.z;
       double nox = ay * bz - az * by, noy = az * bx - ax * bz, noz = ax * by - ay * bx;
@@ -530,10 +657,49 @@ __global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* _
       double dx = p2.x - p0.x, dy = p2.y - p0.y, dz = p2.z - p0.z;
       double nnx = cy * dz - cz * dy, nny = cz * dx - cx * dz, nnz = cx * dy - cy * dx;
       double dot = nox * nnx + noy * nny + noz * nnz;
-      if (!(dot > 0.0)) bad = true;
+      return !(dot > 0.0);
     };
-    star_ascending(m, E, s, E.hs, E.ns, chk);
-    star_ascending(m, E, r, E.hr, E.nr, chk);
+    if (E.fast) {
+      // corner g % 3 of a star face is the star's vertex (position pc before,
+      // vbar after); no other corner is s or r; the other two are loaded
+      auto chunk = [&](const int* g, const bool* use, P3 pc) {
+        P3 o[4][3];
+        int ci[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          const int f = g[k] / 3;
+          ci[k] = g[k] - 3 * f;
+          int c[3];
+#pragma unroll
+          for (int i = 0; i < 3; i++) c[i] = m.F[3 * (int64_t)f + i];
+          const int c1 = ci[k] == 2 ? 0 : ci[k] + 1, c2 = ci[k] == 0 ? 2 : ci[k] - 1;
+          const P3 q1 = ld3(m.V, c1 == 0 ? c[0] : c1 == 1 ? c[1] : c[2]);
+          const P3 q2 = ld3(m.V, c2 == 0 ? c[0] : c2 == 1 ? c[1] : c[2]);
+#pragma unroll
+          for (int i = 0; i < 3; i++) o[k][i] = i == ci[k] ? pc : i == c1 ? q1 : q2;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          if (!use[k] || bad) continue;
+          P3 p[3];
+#pragma unroll
+          for (int i = 0; i < 3; i++) p[i] = i == ci[k] ? vbar : o[k][i];
+          bad = flipped(o[k][0], o[k][1], o[k][2], p[0], p[1], p[2]);
+        }
+      };
+      const P3 ps = ld3(m.V, s), pr = ld3(m.V, r);
+      star_chunks(m, s, E.ns, E.f1, E.f2, E.hs, [&](const int* g, const bool* use) { chunk(g, use, ps); });
+      star_chunks(m, r, E.nr, E.f1, E.f2, E.hs, [&](const int* g, const bool* use) { chunk(g, use, pr); });
+    } else {
+      auto chk = [&](int f) {
+        if (bad) return;
+        P3 o0 = ld3(m.V, m.F[3 * f]), o1 = ld3(m.V, m.F[3 * f + 1]), o2 = ld3(m.V, m.F[3 * f + 2]);
+        bad = flipped(o0, o1, o2, corner_after(m, f, 0, s, r, vbar), corner_after(m, f, 1, s, r, vbar),
+                      corner_after(m, f, 2, s, r, vbar));
+      };
+      star_ascending(m, E, E.hs, chk);
+      star_ascending(m, E, E.hr, chk);
+    }
     if (bad) rs = 2;
   }
   reason[c] = rs;
@@ -613,17 +779,71 @@ __global__ __launch_bounds__(256) void k_apply(MeshView m, const int* __restrict
   int s = a < b ? a : b, r = a < b ? b : a;
   int hr = a == r ? h : t;  // leaves r
   int f1 = h / 3, f2 = t / 3;
-  auto own = [&](int g) { owner[g / 3] = c; };
-  walk_star(m.twin, h, own);
-  walk_star(m.twin, t, own);
-  walk_star(m.twin, hr, [&](int g) {
-    int f = g / 3;
-    if (f != f1 && f != f2) m.F[g] = s;  // corner g % 3 of face f held r
-  });
+  int ns = 0, nr = 0;
+  const P3 vb{vbar[3 * (int64_t)c], vbar[3 * (int64_t)c + 1], vbar[3 * (int64_t)c + 2]};
+  const bool fast = stars_stored(m, s, r, ns, nr);
+  if (fast) {
+    // from the stored stars: ownership, relabelling r -> s and the grown
+    // boxes, four faces at a time (the corners read are the pre-apply ones,
+    // mapped r -> s and placed at vbar where they are s)
+    double ox = 0, oy = 0, oz = 0;
+    if (m.fmesh) mesh_shift(m.fmesh[f1], ox, oy, oz);
+    auto side = [&](const int* g, const bool* use, bool relabel) {
+      int f[4];
+#pragma unroll
+      for (int k = 0; k < 4; k++) f[k] = g[k] / 3;
+      // corner g % 3 of the face is s or r and moves to vbar; no other
+      // corner is s or r; the other two are loaded
+      P3 p[4][3];
+      float ob[4][6];
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        const int ci = g[k] - 3 * f[k];
+        int c[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) c[i] = m.F[3 * (int64_t)f[k] + i];
+        const int c1 = ci == 2 ? 0 : ci + 1, c2 = ci == 0 ? 2 : ci - 1;
+        const P3 q1 = ld3(m.V, c1 == 0 ? c[0] : c1 == 1 ? c[1] : c[2]);
+        const P3 q2 = ld3(m.V, c2 == 0 ? c[0] : c2 == 1 ? c[1] : c[2]);
+#pragma unroll
+        for (int i = 0; i < 3; i++) p[k][i] = i == ci ? vb : i == c1 ? q1 : q2;
+#pragma unroll
+        for (int i = 0; i < 6; i++) ob[k][i] = box[6 * (int64_t)f[k] + i];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        if (!use[k]) continue;
+        owner[f[k]] = c;
+        if (relabel) m.F[g[k]] = s;  // the corner of r in this face
+        float* bx = box + 6 * (int64_t)f[k];
+        bx[0] = fminf(ob[k][0], f_down(fmin(fmin(p[k][0].x, p[k][1].x), p[k][2].x) + ox));
+        bx[1] = fminf(ob[k][1], f_down(fmin(fmin(p[k][0].y, p[k][1].y), p[k][2].y) + oy));
+        bx[2] = fminf(ob[k][2], f_down(fmin(fmin(p[k][0].z, p[k][1].z), p[k][2].z) + oz));
+        bx[3] = fmaxf(ob[k][3], f_up(fmax(fmax(p[k][0].x, p[k][1].x), p[k][2].x) + ox));
+        bx[4] = fmaxf(ob[k][4], f_up(fmax(fmax(p[k][0].y, p[k][1].y), p[k][2].y) + oy));
+        bx[5] = fmaxf(ob[k][5], f_up(fmax(fmax(p[k][0].z, p[k][1].z), p[k][2].z) + oz));
+      }
+    };
+    star_chunks(m, s, ns, f1, f2, h, [&](const int* g, const bool* use) { side(g, use, false); });
+    star_chunks(m, r, nr, f1, f2, h, [&](const int* g, const bool* use) { side(g, use, true); });
+    owner[f1] = c;
+    owner[f2] = c;
+  } else {
+    auto own = [&](int g) { owner[g / 3] = c; };
+    walk_star(m.twin, h, own);
+    walk_star(m.twin, t, own);
+    walk_star(m.twin, hr, [&](int g) {
+      int f = g / 3;
+      if (f != f1 && f != f2) m.F[g] = s;  // corner g % 3 of face f held r
+    });
+  }
   for (int k = 0; k < 3; k++) oldpos[3 * (int64_t)c + k] = m.V[3 * (int64_t)s + k];
-  for (int k = 0; k < 3; k++) m.V[3 * (int64_t)s + k] = vbar[3 * (int64_t)c + k];
+  m.V[3 * (int64_t)s] = vb.x;
+  m.V[3 * (int64_t)s + 1] = vb.y;
+  m.V[3 * (int64_t)s + 2] = vb.z;
   falive[f1] = 0;
   falive[f2] = 0;
+  if (fast) return;
   // union boxes of the faces around s (now the merged vertex)
   int hs = a == s ? h : t;
   auto grow = [&](int g) {
@@ -653,10 +873,19 @@ __global__ __launch_bounds__(256) void k_undo(MeshView m, const int* __restrict_
   int s = a < b ? a : b, r = a < b ? b : a;
   int hr = a == r ? h : t;
   int f1 = h / 3, f2 = t / 3;
-  walk_star(m.twin, hr, [&](int g) {
-    int f = g / 3;
-    if (f != f1 && f != f2) m.F[g] = r;
-  });
+  int ns, nr;
+  if (stars_stored(m, s, r, ns, nr)) {
+    star_chunks(m, r, nr, f1, f2, h, [&](const int* g, const bool* use) {
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+        if (use[k]) m.F[g[k]] = r;
+    });
+  } else {
+    walk_star(m.twin, hr, [&](int g) {
+      int f = g / 3;
+      if (f != f1 && f != f2) m.F[g] = r;
+    });
+  }
   for (int k = 0; k < 3; k++) m.V[3 * (int64_t)s + k] = oldpos[3 * (int64_t)c + k];
   falive[f1] = 1;
   falive[f2] = 1;

@@ -25,8 +25,10 @@ struct MeshView {
   int* vmesh = nullptr;
   int* ovl = nullptr;    // learned proposal only: per-face overlap counts (kept through compaction)
   // per-round vertex data written by the quadrics kernel when set (not carried
-  // through compaction): each vertex's star faces ascending (VSTAR per vertex,
-  // INT_MAX padding), its star size, and the box of its closed 1-ring (lo, hi)
+  // through compaction): the half-edges leaving each vertex, ascending (so its
+  // star faces h / 3 are ascending too, and h % 3 is the vertex's corner in
+  // each; VSTAR per vertex, INT_MAX padding), its star size, and the box of
+  // its closed 1-ring (lo, hi)
   int* vstar = nullptr;
   int* vdeg = nullptr;
   double* vbox = nullptr;
@@ -86,18 +88,26 @@ void launch_compact(Workspace& ws, hipStream_t s, MeshView src, MeshView dst, co
                     const uint8_t* valive, int* nf_new, int* nv_new, int* err);
 
 // ------------------------------------------------------------ LBVH
+// 4-wide node: the boxes of its four children as structure of arrays (child
+// c: lo (lx[c], ly[c], lz[c]), hi (hx[c], hy[c], hz[c]); an absent child has
+// lo = +inf, hi = -inf and meets nothing).  128 bytes, two cache lines.
 struct __align__(16) BvhNode {
-  float4 a, b, c;  // left box (a.xyz, a.w b.xy) and right box (b.zw c.x, c.yzw): lo xyz, hi xyz
-  int4 d;          // when the children are leaves: their face ids (-1 = padding leaf)
+  float4 lx, ly, lz, hx, hy, hz;
+  int4 leaf;  // at the last internal level: face of each child leaf (-1 = none)
+  int4 pad;
 };
 
-// balanced implicit tree over 2^H Morton-sorted leaves: internal node k
-// (0 <= k < 2^H - 1) has children 2k+1 and 2k+2; heap index 2^H - 1 + j is leaf j
+// balanced implicit 4-ary tree over 4^D Morton-sorted leaf slots: internal
+// node k at level l (0 <= l < D, (4^l - 1)/3 <= k < (4^(l+1) - 1)/3) has
+// children 4k+1 .. 4k+4; slot j of the leaves is child j % 4 of the node at
+// position j / 4 of level D - 1.  Nodes whose leaves all lie past n are never
+// entered (their parents record them as empty) and are not written.
+constexpr int BVH_DMAX = 14;  // 4^14 leaf slots; stack entries pack a node index below 2^27
 struct Bvh {
   BvhNode* nodes;
   const int* sorted;  // faces in Morton order (leaf j holds sorted[j])
   int n;              // faces
-  int H;              // depth
+  int D;              // internal levels
 };
 
 // ------------------------------------------------------------ batches
@@ -128,6 +138,16 @@ void launch_batch_output(hipStream_t s, MeshView m, const int* f_off, const int*
 // instead of sorting by Morton code (any order gives a correct tree; a
 // near-Morton order gives a good one).
 // fmesh (batches, may be null): sort by (mesh, Morton code of the unshifted box)
+// node records the build writes for nf leaves (sum over heights h >= 1 of
+// ceil(nf / 4^h), 128 bytes each)
+inline int64_t bvh_nodes_written(int64_t nf) {
+  int64_t total = 0;
+  for (int64_t c = nf; c > 1;) {
+    c = (c + 3) / 4;
+    total += c;
+  }
+  return total;
+}
 Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf, const int* order, const int* fmesh = nullptr,
               int nmesh = 1);
 // new leaf order after a stable compaction: keep the alive faces of `order`
