@@ -86,6 +86,7 @@ enum {
   C_NORD = 25,   // length of the remapped leaf order
   C_NDEMOTE = 26,  // candidates set aside by the network this round
   C_NROWS = 27,    // training rows logged this round
+  C_GATE = 28,     // the round's check must be read back before it can end
   C_COUNT = 32
 };
 
@@ -222,7 +223,8 @@ struct RoundBufs {
   int* qlist;
   int2* defer;
   int defer_cap;
-  int* morder;  // leaf order carried between rounds (see Driver)
+  int* morder;   // leaf order carried between rounds (see Driver)
+  int* morder2;  // the next order while a round is not yet confirmed
   int* vstar;    // per-vertex star faces, star sizes and neighbour boxes (written by the quadrics kernel)
   int* vdeg;
   double* vbox;
@@ -239,30 +241,34 @@ int coop_lanes(const pamo_ctx* c, int64_t nq_est) {
   return c->opt.query_coop > 1 ? c->opt.query_coop : PAMO_DEFAULT_COOP;
 }
 
-// one query pass (traversal + pair predicate + exact resolve); grows the
-// candidate-pair buffer and repeats when it overflowed (marks are idempotent).
+// the kernels of one query pass: traversal, pair predicate, exact resolve.
 // nq_est: about how many queries the pass has (sizes grids, picks the walk)
-const int* query_pass(pamo_ctx* c, const Bvh& bvh, QueryMode mode, const int* qlist, int* nq_dev, int bound,
-                      int64_t nq_est, QueryArgs& qa, double bytes, double vbytes) {
+void query_launch(pamo_ctx* c, const Bvh& bvh, QueryMode mode, const int* qlist, int* nq_dev, int bound,
+                  int64_t nq_est, QueryArgs& qa, double bytes) {
   hipStream_t s = c->stream;
   const int packet = c->opt.query_packet > 0 ? c->opt.query_packet : PAMO_DEFAULT_PACKET;
   const int coop = coop_lanes(c, nq_est);
-  fill_i32(s, c->dcnt + C_NUNDO, 4, 0);  // undone, deferred, collected, intersecting
+  if (qa.ovl_cnt) fill_i32(s, qa.ovl_cnt, bvh.n, 0);  // counted afresh by every attempt
+  {
+    TIMED(PH_QUERY, bytes);
+    launch_query(s, bvh, mode, qlist, nq_dev, bound, qa, packet, coop);
+  }
+  {
+    TIMED(PH_PAIRS, 0);  // bytes added once the pair count is known
+    launch_pairs(s, mode, qa, 16 * nq_est);
+  }
+  {
+    TIMED(PH_RESOLVE, 0);
+    launch_resolve(s, mode, qa);
+  }
+}
+
+// given the counters h read back after a pass: when the candidate-pair buffer
+// overflowed, grow it and repeat the pass (marks are idempotent, and the
+// undone count stands), until one fits
+const int* query_settle(pamo_ctx* c, const Bvh& bvh, QueryMode mode, const int* qlist, int* nq_dev, int bound,
+                        int64_t nq_est, QueryArgs& qa, double bytes, double vbytes, const int* h) {
   for (;;) {
-    if (qa.ovl_cnt) fill_i32(s, qa.ovl_cnt, bvh.n, 0);  // counted afresh by every attempt
-    {
-      TIMED(PH_QUERY, bytes);
-      launch_query(s, bvh, mode, qlist, nq_dev, bound, qa, packet, coop);
-    }
-    {
-      TIMED(PH_PAIRS, 0);  // bytes added once the pair count is known
-      launch_pairs(s, mode, qa, 16 * nq_est);
-    }
-    {
-      TIMED(PH_RESOLVE, 0);
-      launch_resolve(s, mode, qa);
-    }
-    const int* h = readback(c);
     check_err_bits(h[C_ERR]);
     const int np = std::min(h[C_NCANDP], qa.cand_cap);
     prof_bytes(c, PH_PAIRS, 8.0 * np + vbytes);
@@ -271,8 +277,18 @@ const int* query_pass(pamo_ctx* c, const Bvh& bvh, QueryMode mode, const int* ql
     if (cap > INT32_MAX / 2) fail(PAMO_ERR_CAPACITY, "too many candidate pairs");
     qa.cand = c->ws.get<int2>("q.pairs", cap);
     qa.cand_cap = (int)cap;
-    fill_i32(s, c->dcnt + C_NDEFER, 3, 0);  // repeat: marks and the undone count stand
+    fill_i32(c->stream, c->dcnt + C_NDEFER, 3, 0);  // repeat: marks and the undone count stand
+    query_launch(c, bvh, mode, qlist, nq_dev, bound, nq_est, qa, bytes);
+    h = readback(c);
   }
+}
+
+// one whole query pass, read back
+const int* query_pass(pamo_ctx* c, const Bvh& bvh, QueryMode mode, const int* qlist, int* nq_dev, int bound,
+                      int64_t nq_est, QueryArgs& qa, double bytes, double vbytes) {
+  fill_i32(c->stream, c->dcnt + C_NUNDO, 4, 0);  // undone, deferred, collected, intersecting
+  query_launch(c, bvh, mode, qlist, nq_dev, bound, nq_est, qa, bytes);
+  return query_settle(c, bvh, mode, qlist, nq_dev, bound, nq_est, qa, bytes, vbytes, readback(c));
 }
 
 void init_pair_buffer(pamo_ctx* c, QueryArgs& qa, int64_t nf) {
@@ -303,6 +319,7 @@ RoundBufs round_bufs(pamo_ctx* c, int64_t nv, int64_t nf) {
   b.defer_cap = (int)std::max<int64_t>(1 << 16, nf);
   b.defer = w.get<int2>("r.defer", b.defer_cap);
   b.morder = w.get<int>("r.morder", nf);
+  b.morder2 = w.get<int>("r.morder2", nf);
   b.vstar = w.get<int>("r.vstar", VSTAR * nv);
   b.vdeg = w.get<int>("r.vdeg", nv);
   b.vbox = w.get<double>("r.vbox", 6 * nv);
@@ -340,6 +357,7 @@ struct OrderState {
   bool valid = false;
   int age = 0;
   int resort = 4;
+  int chosen_est = 0;  // collapses applied by the previous round (sizes the next query when not read back)
 };
 
 // Local checks of the candidates (link, degeneracy, flip) and the histogram
@@ -368,36 +386,43 @@ void cap_single(pamo_ctx* c, const RoundBufs& b, const int* ncand_dev, uint8_t* 
   }
 }
 
-// Tentative apply of the R.chosen collapses with reason 0 and the check/undo
-// fixed point on `m` (modified: undone collapses restored, applied ones left
-// applied).  undone[c] != 0 marks collapses undone by the loop (reason not yet
-// set to 3).  `order`: BVH leaf order to reuse, or null to sort.
-void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand, const int* ncand_dev, int ncand,
-                    uint8_t* reason, double* vbar, RoundResult& R, const int* order, int nmesh = 1,
-                    int* ovl_new = nullptr) {
+// A check/undo fixed point between the launch of its first query pass and
+// its resolution.
+struct CheckRun {
+  Bvh bvh{};
+  QueryArgs qa{};
+  double qbytes = 0, pbytes = 0;
+};
+
+// Tentative apply of the R.chosen collapses with reason 0 on `m`, the BVH,
+// the list of changed faces and the first query pass, all enqueued, nothing
+// read back.  Returns false when nothing was applied (no pass launched).
+// `order`: BVH leaf order to reuse, or null to sort.
+bool check_launch(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand, const int* ncand_dev, int ncand,
+                  uint8_t* reason, double* vbar, const RoundResult& R, const int* order, int nmesh, int* ovl_new,
+                  CheckRun& K) {
   hipStream_t s = c->stream;
   int* cnt = c->dcnt;
-  const int* h;
   const double nf = m.nf, nv = m.nv;
   {
     TIMED(PH_BOXES, 36 * nf + 24 * nv);
     launch_round_prep(s, m, R.chosen > 0 ? b.box : nullptr, b.falive, b.owner, ncand, b.undone, b.valive);
   }
-  if (R.chosen == 0) return;
+  if (R.chosen == 0) return false;
   {
     TIMED(PH_APPLY, 900.0 * R.chosen);
     launch_apply(s, m, cand, ncand_dev, ncand, reason, vbar, b.oldpos, b.owner, b.falive, b.box);
   }
-  Bvh bvh;
   {
-    TIMED(PH_BVH, 216 * nf);
-    bvh = build_bvh(c->ws, s, b.box, m.nf, order, m.fmesh, nmesh);
+    TIMED(PH_BVH, 24 * nf + 128.0 * bvh_nodes_written(m.nf));
+    K.bvh = build_bvh(c->ws, s, b.box, m.nf, order, m.fmesh, nmesh);
   }
   {
     TIMED(PH_FACELIST, 8 * nf);
-    launch_face_list(c->ws, s, m.nf, b.owner, b.falive, b.undone, 0, bvh.sorted, b.qlist, cnt + C_NQ);
+    launch_face_list(c->ws, s, m.nf, b.owner, b.falive, b.undone, 0, K.bvh.sorted, b.qlist, cnt + C_NQ);
   }
-  QueryArgs qa{};
+  QueryArgs& qa = K.qa;
+  qa = QueryArgs{};
   qa.V = m.V;
   qa.F = m.F;
   qa.falive = b.falive;
@@ -411,10 +436,25 @@ void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand
   qa.fmesh = m.fmesh;
   qa.err = cnt + C_ERR;
   init_pair_buffer(c, qa, m.nf);
-  const double qbytes = 128.0 * bvh_nodes_written(m.nf) + 17 * nf + 24 * nv;  // tree + faces + alive/owner + vertices
-  const double pbytes = 17 * nf + 24 * nv;                   // pairs: faces, alive/owner, vertices (+ 8 per pair)
-  qa.ovl_cnt = ovl_new;  // overlap counts of the changed faces on the tentative mesh
-  h = query_pass(c, bvh, QUERY_CHANGED, b.qlist, cnt + C_NQ, m.nf, 10ll * R.chosen, qa, qbytes, pbytes);
+  K.qbytes = 128.0 * bvh_nodes_written(m.nf) + 17 * nf + 24 * nv;  // tree + faces + alive/owner + vertices
+  K.pbytes = 17 * nf + 24 * nv;  // pairs: faces, alive/owner, vertices (+ 8 per pair)
+  qa.ovl_cnt = ovl_new;          // overlap counts of the changed faces on the tentative mesh
+  fill_i32(s, cnt + C_NUNDO, 4, 0);  // undone, deferred, collected, intersecting
+  query_launch(c, K.bvh, QUERY_CHANGED, b.qlist, cnt + C_NQ, m.nf, 10ll * R.chosen, qa, K.qbytes);
+  return true;
+}
+
+// The rest of the fixed point, given the counters h read back after the first
+// pass: a pass that overflowed is repeated, then every undone collapse is
+// restored and the faces it restored are checked again until nothing is
+// undone.  `m` is left with the surviving collapses applied.
+void check_resolve(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand, const int* ncand_dev, int ncand,
+                   RoundResult& R, CheckRun& K, const int* h) {
+  hipStream_t s = c->stream;
+  int* cnt = c->dcnt;
+  const double nf = m.nf;
+  QueryArgs& qa = K.qa;
+  h = query_settle(c, K.bvh, QUERY_CHANGED, b.qlist, cnt + C_NQ, m.nf, 10ll * R.chosen, qa, K.qbytes, K.pbytes, h);
   qa.ovl_cnt = nullptr;
   int newly = h[C_NUNDO];
   R.deferred += h[C_NDEFER];
@@ -427,15 +467,27 @@ void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand
     }
     {
       TIMED(PH_FACELIST, 8 * nf);
-      launch_face_list(c->ws, s, m.nf, b.owner, b.falive, b.undone, R.iters, bvh.sorted, b.qlist, cnt + C_NQ);
+      launch_face_list(c->ws, s, m.nf, b.owner, b.falive, b.undone, R.iters, K.bvh.sorted, b.qlist, cnt + C_NQ);
     }
     qa.iter = R.iters + 1;
-    h = query_pass(c, bvh, QUERY_RESTORED, b.qlist, cnt + C_NQ, m.nf, 10ll * newly, qa, qbytes, pbytes);
+    h = query_pass(c, K.bvh, QUERY_RESTORED, b.qlist, cnt + C_NQ, m.nf, 10ll * newly, qa, K.qbytes, K.pbytes);
     newly = h[C_NUNDO];
     R.deferred += h[C_NDEFER];
   }
   R.commits = R.chosen - R.undone;
-  R.leaf_order = bvh.sorted;
+  R.leaf_order = K.bvh.sorted;
+}
+
+// Tentative apply of the R.chosen collapses with reason 0 and the check/undo
+// fixed point on `m` (modified: undone collapses restored, applied ones left
+// applied).  undone[c] != 0 marks collapses undone by the loop (reason not yet
+// set to 3).  `order`: BVH leaf order to reuse, or null to sort.
+void check_and_undo(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand, const int* ncand_dev, int ncand,
+                    uint8_t* reason, double* vbar, RoundResult& R, const int* order, int nmesh = 1,
+                    int* ovl_new = nullptr) {
+  CheckRun K;
+  if (!check_launch(c, m, b, cand, ncand_dev, ncand, reason, vbar, R, order, nmesh, ovl_new, K)) return;
+  check_resolve(c, m, b, cand, ncand_dev, ncand, R, K, readback(c));
 }
 
 void add_stats(pamo_stats* st, const RoundResult& R) {
@@ -450,9 +502,65 @@ void add_stats(pamo_stats* st, const RoundResult& R) {
   st->deferred_pairs += R.deferred;
 }
 
+// The end of a round once the check is settled (or speculatively, gated):
+// commit the surviving collapses, next round's invalid flags (this round's
+// rejections, plus the old flags when nothing was collapsed, Sec. 5.3),
+// compaction into `alt`, and the BVH leaf order remapped into `order_out`.
+void round_tail(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, const RoundResult& R, LearnRun* L,
+                const int* gate, int* order_out) {
+  hipStream_t s = c->stream;
+  int* cnt = c->dcnt;
+  const double nf = cur.nf, nv = cur.nv;
+  const bool logging = L && L->X;
+  if (R.chosen > 0) {
+    TIMED(PH_COMMIT, 100.0 * R.chosen);
+    launch_commit(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.undone, b.valive, gate);
+  }
+  if (L && L->track && R.chosen > 0) launch_ovl_commit(s, cur.nf, b.owner, b.falive, b.undone, b.ovl_new, cur.ovl);
+  if (logging && L->n < L->cap) {
+    TIMED(PH_LEARN, 0);
+    launch_log_rows(c->ws, s, cnt + C_NCAND, R.ncand, b.reason, b.X, L->X + L->n * LEARN_NFEAT, L->y + L->n,
+                    L->cap - L->n, cnt + C_NROWS);
+  }
+  {
+    TIMED(PH_FLAGS, 3 * nf + 10.0 * R.ncand);
+    if (R.commits > 0) launch_clear_u8(s, cur.flags, 3 * (int64_t)cur.nf, gate);
+    launch_flags(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, cnt + C_HIST2, gate);
+  }
+  if (R.commits > 0) {
+    TIMED(PH_COMPACT, 72 * nf + 66 * nv);
+    launch_compact(c->ws, s, cur, alt, b.falive, b.valive, cnt + C_NF, cnt + C_NV, cnt + C_ERR, gate);
+  }
+  if (R.leaf_order) {
+    if (R.commits > 0) {
+      // the order buffer may be the one being remapped: go through a copy
+      int* tmp = c->ws.get<int>("ord.copy", cur.nf);
+      PAMO_HIP(hipMemcpyAsync(tmp, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+      launch_remap_order(c->ws, s, tmp, cur.nf, b.falive, c->ws.get<int>("cmp.fmap", cur.nf), order_out,
+                         cnt + C_NORD);
+    } else if (R.leaf_order != order_out) {
+      PAMO_HIP(hipMemcpyAsync(order_out, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+    }
+  }
+}
+
+// given the counters read back after round_tail: reasons, logged rows, and the
+// compacted mesh becomes current
+RoundResult round_end(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundResult& R, LearnRun* L, const int* h) {
+  check_err_bits(h[C_ERR]);
+  for (int i = 0; i < 8; i++) R.hist[i] = h[C_HIST2 + i];
+  if (L && L->X) L->n += std::min<int64_t>(h[C_NROWS], L->cap - L->n);
+  if (R.commits > 0) {
+    alt.nf = h[C_NF];
+    alt.nv = h[C_NV];
+    std::swap(cur, alt);
+  }
+  return R;
+}
+
 // One full round on `cur`.  When collapses are committed, the compacted mesh
 // lands in `alt` and the two views are swapped.
-RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, int64_t teff, OrderState& os,
+RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, int64_t teff, OrderState& os,
                       LearnRun* L = nullptr) {
   hipStream_t s = c->stream;
   int* cnt = c->dcnt;
@@ -486,74 +594,86 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs
     }
   }
   local_checks(c, cur, b, b.cand, cnt + C_NCAND, bound, b.reason, b.vbar);
-  const int* h = readback(c);
-  check_err_bits(h[C_ERR]);
-  R.ncand = h[C_NCAND];
-  R.npass = h[C_HIST + 0];
-  R.demoted = h[C_NDEMOTE];
-  prof_bytes(c, PH_LOCAL, 780.0 * R.ncand);
-  if (R.ncand == 0) {  // nothing selectable: a round without collapses
-    R.retry = learned && R.demoted > 0;
-    return R;
+  int* ovl_new = L && L->track ? b.ovl_new : nullptr;
+  const bool plain = !learned && !logging && !ovl_new;
+  // The exact-target cap cannot bind while nf >= 2 teff: selected edges have
+  // disjoint rings of at least four faces, so at most nf / 4 pass, and
+  // nf / 4 <= (nf - teff) / 2.  The plain method then goes on without reading
+  // the candidate counts back: grids take the bound, the device the counts.
+  const bool blind = plain && cur.nf >= 2 * teff;
+  const int* h = nullptr;
+  if (blind) {
+    R.ncand = bound;
+    // an estimate until the end of the round (it sizes the query grids): the
+    // previous round's count, or about one collapse per 32 faces at first
+    R.chosen = R.npass = std::max(1, os.chosen_est > 0 ? os.chosen_est : cur.nf / 32);
+  } else {
+    h = readback(c);
+    check_err_bits(h[C_ERR]);
+    R.ncand = h[C_NCAND];
+    R.npass = h[C_HIST + 0];
+    R.demoted = h[C_NDEMOTE];
+    prof_bytes(c, PH_LOCAL, 780.0 * R.ncand);
+    if (R.ncand == 0) {  // nothing selectable: a round without collapses
+      R.retry = learned && R.demoted > 0;
+      return R;
+    }
   }
   const bool reuse = os.valid && os.age < os.resort;
-  cap_single(c, b, cnt + C_NCAND, b.reason, teff, cur.nf, R);
-  check_and_undo(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr, 1,
-                 L && L->track ? b.ovl_new : nullptr);
+  if (!blind) cap_single(c, b, cnt + C_NCAND, b.reason, teff, cur.nf, R);
+  // Speculative end of round (plain method, something to apply): the round's
+  // tail is enqueued right behind the first query pass, its kernels gated on
+  // the device.  When that pass undid nothing, fitted its pair buffer and set
+  // no error bit, the round ends with this one read-back; otherwise the tail
+  // did nothing and the check is finished the usual way.
+  if (plain && R.chosen > 0) {
+    CheckRun K;
+    check_launch(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr, 1,
+                 nullptr, K);
+    launch_gate(s, cnt + C_NUNDO, cnt + C_NCANDP, K.qa.cand_cap, cnt + C_ERR, blind ? cnt + C_HIST : nullptr,
+                cnt + C_GATE);
+    R.commits = R.chosen;  // if nothing is undone
+    R.leaf_order = K.bvh.sorted;
+    round_tail(c, cur, alt, b, R, L, cnt + C_GATE, b.morder2);
+    h = readback(c);
+    if (blind) {
+      R.ncand = h[C_NCAND];
+      R.chosen = R.npass = h[C_HIST + 0];
+      prof_bytes(c, PH_LOCAL, 780.0 * R.ncand);
+    }
+    os.chosen_est = R.chosen;
+    if (!h[C_GATE]) {
+      prof_bytes(c, PH_PAIRS, 8.0 * h[C_NCANDP] + K.pbytes);
+      R.commits = R.chosen;
+      R.deferred += h[C_NDEFER];
+      os.age = reuse ? os.age + 1 : 1;
+      os.valid = true;
+      std::swap(b.morder, b.morder2);
+      return round_end(c, cur, alt, R, L, h);
+    }
+    R.commits = 0;
+    R.leaf_order = nullptr;
+    check_resolve(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, R, K, h);
+  } else {
+    check_and_undo(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr, 1,
+                   ovl_new);
+  }
   if (learned && R.demoted > 0 && R.commits == 0) {
     // everything was undone, so the mesh is as the round found it
     R.retry = true;
     return R;
   }
-  if (R.leaf_order) os.age = reuse ? os.age + 1 : 1;
-  if (R.chosen > 0) {
-    TIMED(PH_COMMIT, 100.0 * R.chosen);
-    launch_commit(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.undone, b.valive);
-  }
-  if (L && L->track && R.chosen > 0) launch_ovl_commit(s, cur.nf, b.owner, b.falive, b.undone, b.ovl_new, cur.ovl);
-  if (logging && L->n < L->cap) {
-    TIMED(PH_LEARN, 0);
-    launch_log_rows(c->ws, s, cnt + C_NCAND, R.ncand, b.reason, b.X, L->X + L->n * LEARN_NFEAT, L->y + L->n,
-                    L->cap - L->n, cnt + C_NROWS);
-  }
-  // invalid flags for the next round: this round's rejections, plus the old
-  // flags when nothing was collapsed (Sec. 5.3)
-  {
-    TIMED(PH_FLAGS, 3 * nf + 10.0 * R.ncand);
-    if (R.commits > 0) fill_u8(s, cur.flags, 3 * (int64_t)cur.nf, 0);
-    launch_flags(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, cnt + C_HIST2);
-  }
-  if (R.commits > 0) {
-    TIMED(PH_COMPACT, 72 * nf + 66 * nv);
-    launch_compact(c->ws, s, cur, alt, b.falive, b.valive, cnt + C_NF, cnt + C_NV, cnt + C_ERR);
-  }
   if (R.leaf_order) {
-    if (R.commits > 0) {
-      // the order buffer may be the one being remapped: go through a copy
-      int* tmp = c->ws.get<int>("ord.copy", cur.nf);
-      PAMO_HIP(hipMemcpyAsync(tmp, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
-      launch_remap_order(c->ws, s, tmp, cur.nf, b.falive, c->ws.get<int>("cmp.fmap", cur.nf), b.morder,
-                         cnt + C_NORD);
-    } else if (R.leaf_order != b.morder) {
-      PAMO_HIP(hipMemcpyAsync(b.morder, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
-    }
+    os.age = reuse ? os.age + 1 : 1;
     os.valid = true;
   }
-  h = readback(c);
-  check_err_bits(h[C_ERR]);
-  for (int i = 0; i < 8; i++) R.hist[i] = h[C_HIST2 + i];
-  if (logging) L->n += std::min<int64_t>(h[C_NROWS], L->cap - L->n);
-  if (R.commits > 0) {
-    alt.nf = h[C_NF];
-    alt.nv = h[C_NV];
-    std::swap(cur, alt);
-  }
-  return R;
+  round_tail(c, cur, alt, b, R, L, nullptr, b.morder);
+  return round_end(c, cur, alt, R, L, readback(c));
 }
 
 // a learned round that set candidates aside and committed nothing runs again
 // without the network
-RoundResult run_round_learned(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, int64_t teff,
+RoundResult run_round_learned(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, int64_t teff,
                               OrderState& os, LearnRun* L) {
   RoundResult R = run_round(c, cur, alt, b, teff, os, L);
   if (!L) return R;

@@ -914,7 +914,8 @@ __global__ void k_changed_faces(int nf, const int* __restrict__ owner, const uin
 // apexes, retire r.  Undone candidates get reason 3.
 __global__ __launch_bounds__(256) void k_commit(MeshView m, const int* __restrict__ cand, const int* __restrict__ ncand,
                                                 uint8_t* __restrict__ reason, const int* __restrict__ undone,
-                                                uint8_t* __restrict__ valive) {
+                                                uint8_t* __restrict__ valive, const int* __restrict__ gate) {
+  if (gate && *gate) return;
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= *ncand || reason[c] != 0) return;
   if (undone[c]) {
@@ -941,7 +942,8 @@ __global__ __launch_bounds__(256) void k_commit(MeshView m, const int* __restric
 }
 
 __global__ void k_flags(MeshView m, const int* __restrict__ cand, const int* __restrict__ ncand,
-                        const uint8_t* __restrict__ reason, int* __restrict__ hist) {
+                        const uint8_t* __restrict__ reason, int* __restrict__ hist, const int* __restrict__ gate) {
+  if (gate && *gate) return;
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= *ncand) return;
   uint8_t rs = reason[c];
@@ -965,7 +967,9 @@ __global__ void k_reason_hist(const int* __restrict__ ncand, const uint8_t* __re
 
 // ------------------------------------------------------------ compaction
 __global__ void k_compact_faces(MeshView src, MeshView dst, const uint8_t* __restrict__ falive,
-                                const int* __restrict__ fmap, const int* __restrict__ vmap, int* err) {
+                                const int* __restrict__ fmap, const int* __restrict__ vmap, int* err,
+                                const int* __restrict__ gate) {
+  if (gate && *gate) return;
   int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= src.nf || !falive[f]) return;
   int g = fmap[f];
@@ -989,7 +993,9 @@ __global__ void k_compact_faces(MeshView src, MeshView dst, const uint8_t* __res
 }
 
 __global__ void k_compact_verts(MeshView src, MeshView dst, const uint8_t* __restrict__ valive,
-                                const int* __restrict__ vmap, const int* __restrict__ fmap) {
+                                const int* __restrict__ vmap, const int* __restrict__ fmap,
+                                const int* __restrict__ gate) {
+  if (gate && *gate) return;
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= src.nv || !valive[v]) return;
   int w = vmap[v];
@@ -1007,6 +1013,20 @@ __global__ void k_remap_order(const int* __restrict__ order, int n, const uint8_
   bool keep = falive[f] != 0;
   tmp[j] = keep ? fmap[f] : -1;
   pred[j] = keep;
+}
+
+// the round's gate: set when the check pass must be read back before the
+// round can end (a collapse was undone, the pair buffer overflowed, an error)
+__global__ void k_gate(const int* __restrict__ nundo, const int* __restrict__ ncandp, int cap,
+                       const int* __restrict__ err, const int* __restrict__ npass, int* __restrict__ gate) {
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    *gate = (*nundo > 0 || *ncandp > cap || *err != 0 || (npass && *npass == 0)) ? 1 : 0;
+}
+
+__global__ void k_clear_u8(uint8_t* __restrict__ p, int64_t n, const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
 }
 
 __global__ void k_flags_or(uint8_t* __restrict__ dst, const uint8_t* __restrict__ src, int64_t n) {
@@ -1258,14 +1278,27 @@ void launch_face_list(Workspace& ws, hipStream_t s, int nf, const int* owner, co
 }
 
 void launch_commit(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, uint8_t* reason,
-                   const int* undone, uint8_t* valive) {
-  hipLaunchKernelGGL(k_commit, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, undone, valive);
+                   const int* undone, uint8_t* valive, const int* gate) {
+  hipLaunchKernelGGL(k_commit, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, undone, valive, gate);
   PAMO_HIP(hipGetLastError());
 }
 
 void launch_flags(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound,
-                  const uint8_t* reason, int* hist) {
-  hipLaunchKernelGGL(k_flags, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, hist);
+                  const uint8_t* reason, int* hist, const int* gate) {
+  hipLaunchKernelGGL(k_flags, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, hist, gate);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_gate(hipStream_t s, const int* nundo, const int* ncandp, int cap, const int* err, const int* npass,
+                 int* gate) {
+  hipLaunchKernelGGL(k_gate, dim3(1), dim3(64), 0, s, nundo, ncandp, cap, err, npass, gate);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_clear_u8(hipStream_t s, uint8_t* p, int64_t n, const int* gate) {
+  if (n <= 0) return;
+  int64_t b = (n + 255) / 256;
+  hipLaunchKernelGGL(k_clear_u8, dim3((unsigned)(b > 65536 ? 65536 : b)), dim3(256), 0, s, p, n, gate);
   PAMO_HIP(hipGetLastError());
 }
 
@@ -1275,15 +1308,15 @@ void launch_reason_hist(hipStream_t s, const int* ncand, int cand_bound, const u
 }
 
 void launch_compact(Workspace& ws, hipStream_t s, MeshView src, MeshView dst, const uint8_t* falive,
-                    const uint8_t* valive, int* nf_new, int* nv_new, int* err) {
+                    const uint8_t* valive, int* nf_new, int* nv_new, int* err, const int* gate) {
   int* fmap = ws.get<int>("cmp.fmap", src.nf);
   int* vmap = ws.get<int>("cmp.vmap", src.nv);
   rank_flags(ws, s, falive, src.nf, fmap, nf_new);
   rank_flags(ws, s, valive, src.nv, vmap, nv_new);
   hipLaunchKernelGGL(k_compact_faces, dim3(nblk(src.nf)), dim3(256), 0, s, src, dst, falive, (const int*)fmap,
-                     (const int*)vmap, err);
+                     (const int*)vmap, err, gate);
   hipLaunchKernelGGL(k_compact_verts, dim3(nblk(src.nv)), dim3(256), 0, s, src, dst, valive, (const int*)vmap,
-                     (const int*)fmap);
+                     (const int*)fmap, gate);
   PAMO_HIP(hipGetLastError());
 }
 
