@@ -574,15 +574,15 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
   cur.vbox = b.vbox;
   {
     TIMED(PH_QUADRICS, 108 * nv + 24 * nf);
-    launch_quadrics(s, cur, b.Q, cnt + C_ERR);
+    launch_quadrics(s, cur, b.Q, cnt + C_ERR, b.vmin);
   }
   {
     TIMED(PH_COST, 104 * nv + 51 * nf);
-    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, cnt + C_ERR);
+    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, cnt + C_ERR, b.vmin);
   }
   {
     TIMED(PH_SELECT, 20 * nv + 93 * nf);
-    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, true);
   }
   const int bound = cur.nf / 2 + 1;
   if (learned || logging) {
@@ -878,15 +878,15 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const Rou
   cur.vbox = b.vbox;
   {
     TIMED(PH_QUADRICS, 108 * nv + 24 * nf);
-    launch_quadrics(s, cur, b.Q, cnt + C_ERR);
+    launch_quadrics(s, cur, b.Q, cnt + C_ERR, b.vmin);
   }
   {
     TIMED(PH_COST, 104 * nv + 51 * nf);
-    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, B.done, b.key, cnt + C_ERR);
+    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, B.done, b.key, cnt + C_ERR, b.vmin);
   }
   {
     TIMED(PH_SELECT, 20 * nv + 93 * nf);
-    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, true);
   }
   const int bound = cur.nf / 2 + 1;
   if (learned) {

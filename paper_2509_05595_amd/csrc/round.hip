@@ -129,9 +129,11 @@ __global__ void k_check_vertices(const int* __restrict__ twin, const int* __rest
 // One thread per vertex: walk the star once (sorted half-edge list in
 // registers), then sum the face quadrics in ascending face slot, four faces
 // at a time with their loads issued together.
-__global__ __launch_bounds__(256) void k_quadrics(MeshView m, double* __restrict__ Q, int* err) {
+__global__ __launch_bounds__(256) void k_quadrics(MeshView m, double* __restrict__ Q, int* err,
+                                                  uint64_t* __restrict__ vmin) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= m.nv) return;
+  if (vmin) vmin[v] = PAMO_KEY_MAX;  // lowered by the cost kernel
   constexpr int CAP = VSTAR;
   int hl[CAP];
 #pragma unroll
@@ -456,7 +458,7 @@ template <int PW>
 __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
                                                    const uint8_t* __restrict__ demote,
                                                    const uint8_t* __restrict__ mesh_done, uint64_t* __restrict__ key,
-                                                   int* err) {
+                                                   int* err, uint64_t* __restrict__ vmin) {
   __shared__ int queue[4][PW];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t nh = 3 * (int64_t)m.nf;
@@ -485,6 +487,10 @@ __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __r
         P3 vbar;
         double cost = edge_cost(m, Q, E, w_e, w_s, vbar);
         k = make_key(cost, (uint32_t)h);
+        if (vmin && k != PAMO_KEY_MAX) {  // the vertex minima of the selection, in place of a gather pass
+          atomicMin(reinterpret_cast<unsigned long long*>(vmin + E.s), (unsigned long long)k);
+          atomicMin(reinterpret_cast<unsigned long long*>(vmin + E.r), (unsigned long long)k);
+        }
       }
     }
     key[h] = k;
@@ -501,13 +507,13 @@ __global__ __launch_bounds__(256) void k_vertex_min(MeshView m, const uint64_t* 
   uint64_t best = PAMO_KEY_MAX;
   const int n = m.vstar ? m.vdeg[v] : VSTAR + 1;
   if (n <= VSTAR) {
-    int g[VSTAR];
-    star_all(m, v, n, g);
-    uint64_t k[VSTAR];
+    star_chunks(m, v, n, -1, -1, 0, [&](const int* g, const bool* use) {
+      uint64_t k[4];
 #pragma unroll
-    for (int i = 0; i < VSTAR; i++) k[i] = key[g[i]];
+      for (int i = 0; i < 4; i++) k[i] = key[g[i]];
 #pragma unroll
-    for (int i = 0; i < VSTAR; i++) best = k[i] < best ? k[i] : best;  // slots past n repeat slot 0
+      for (int i = 0; i < 4; i++) best = use[i] && k[i] < best ? k[i] : best;
+    });
   } else {
     walk_star(m.twin, m.vh[v], [&](int h) {
       uint64_t k = key[h];
@@ -1201,28 +1207,28 @@ void launch_check_vertices(Workspace& ws, hipStream_t s, MeshView m, int* err) {
   PAMO_HIP(hipGetLastError());
 }
 
-void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err) {
-  hipLaunchKernelGGL(k_quadrics, dim3(nblk(m.nv)), dim3(256), 0, s, m, Q, err);
+void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err, uint64_t* vmin) {
+  hipLaunchKernelGGL(k_quadrics, dim3(nblk(m.nv)), dim3(256), 0, s, m, Q, err, vmin);
   PAMO_HIP(hipGetLastError());
 }
 
 void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
-                      const uint8_t* mesh_done, uint64_t* key, int* err) {
+                      const uint8_t* mesh_done, uint64_t* key, int* err, uint64_t* vmin) {
   const int64_t nh = 3 * (int64_t)m.nf;
   if (nh <= CK_SMALL_NH)
     hipLaunchKernelGGL(k_cost_keys<64>, dim3(nblk(nh, 4 * 64)), dim3(256), 0, s, m, Q, w_e, w_s, demote, mesh_done,
-                       key, err);
+                       key, err, vmin);
   else
     hipLaunchKernelGGL(k_cost_keys<256>, dim3(nblk(nh, 4 * 256)), dim3(256), 0, s, m, Q, w_e, w_s, demote, mesh_done,
-                       key, err);
+                       key, err, vmin);
   PAMO_HIP(hipGetLastError());
 }
 
 void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, int* cand,
-                   int* ncand) {
+                   int* ncand, bool vmin_ready) {
   int64_t nh = 3 * (int64_t)m.nf;
   uint8_t* sel = ws.get<uint8_t>("sel", nh);
-  hipLaunchKernelGGL(k_vertex_min, dim3(nblk(m.nv)), dim3(256), 0, s, m, key, vmin);
+  if (!vmin_ready) hipLaunchKernelGGL(k_vertex_min, dim3(nblk(m.nv)), dim3(256), 0, s, m, key, vmin);
   hipLaunchKernelGGL(k_select, dim3(nblk(nh)), dim3(256), 0, s, m, key, (const uint64_t*)vmin, sel);
   compact_flags(ws, s, sel, nh, cand, ncand);
   PAMO_HIP(hipGetLastError());

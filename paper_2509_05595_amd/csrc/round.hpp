@@ -46,12 +46,17 @@ constexpr int PAMO_MAX_MESHES = 4096;
 
 void launch_adjacency(Workspace& ws, hipStream_t s, MeshView m, int* err);
 void launch_check_vertices(Workspace& ws, hipStream_t s, MeshView m, int* err);
-void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err);
+// vmin (optional): set to the largest key for every vertex, to be lowered by the cost kernel
+void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err, uint64_t* vmin = nullptr);
 // mesh_done (batches, may be null): edges of finished meshes get no key
+// vmin (optional): every finite key is also folded into vmin of both endpoints
+// (atomic minimum; vmin set to the largest key beforehand)
 void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
-                      const uint8_t* mesh_done, uint64_t* key, int* err);
+                      const uint8_t* mesh_done, uint64_t* key, int* err, uint64_t* vmin = nullptr);
+// vmin_ready: vmin already holds the vertex minima of key (the cost kernel
+// folded them in), so only the selection and its compaction run
 void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, int* cand,
-                   int* ncand);
+                   int* ncand, bool vmin_ready = false);
 void launch_local_check(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const int* cand,
                         const int* ncand, int cand_bound, const uint64_t* key, uint8_t* reason, double* vbar,
                         uint64_t* ckey, int* err, int* hist);
