@@ -516,7 +516,8 @@ void round_tail(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, c
     TIMED(PH_COMMIT, 100.0 * R.chosen);
     launch_commit(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.undone, b.valive, gate);
   }
-  if (L && L->track && R.chosen > 0) launch_ovl_commit(s, cur.nf, b.owner, b.falive, b.undone, b.ovl_new, cur.ovl);
+  if (L && L->track && R.chosen > 0)
+    launch_ovl_commit(s, cur.nf, b.owner, b.falive, b.undone, b.ovl_new, cur.ovl, gate);
   if (logging && L->n < L->cap) {
     TIMED(PH_LEARN, 0);
     launch_log_rows(c->ws, s, cnt + C_NCAND, R.ncand, b.reason, b.X, L->X + L->n * LEARN_NFEAT, L->y + L->n,
@@ -595,7 +596,8 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
   }
   local_checks(c, cur, b, b.cand, cnt + C_NCAND, bound, b.reason, b.vbar);
   int* ovl_new = L && L->track ? b.ovl_new : nullptr;
-  const bool plain = !learned && !logging && !ovl_new;
+  // the network not consulted and no rows logged (overlap counts may be kept)
+  const bool plain = !learned && !logging;
   // The exact-target cap cannot bind while nf >= 2 teff: selected edges have
   // disjoint rings of at least four faces, so at most nf / 4 pass, and
   // nf / 4 <= (nf - teff) / 2.  The plain method then goes on without reading
@@ -621,15 +623,16 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
   }
   const bool reuse = os.valid && os.age < os.resort;
   if (!blind) cap_single(c, b, cnt + C_NCAND, b.reason, teff, cur.nf, R);
-  // Speculative end of round (plain method, something to apply): the round's
-  // tail is enqueued right behind the first query pass, its kernels gated on
-  // the device.  When that pass undid nothing, fitted its pair buffer and set
-  // no error bit, the round ends with this one read-back; otherwise the tail
-  // did nothing and the check is finished the usual way.
+  // Speculative end of round (network not consulted, nothing logged, something
+  // to apply): the round's tail is enqueued right behind the first query
+  // pass, its kernels gated on the device.  When that pass undid nothing,
+  // fitted its pair buffer and set no error bit, the round ends with this one
+  // read-back; otherwise the tail did nothing and the check is finished the
+  // usual way.
   if (plain && R.chosen > 0) {
     CheckRun K;
     check_launch(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr, 1,
-                 nullptr, K);
+                 ovl_new, K);
     launch_gate(s, cnt + C_NUNDO, cnt + C_NCANDP, K.qa.cand_cap, cnt + C_ERR, blind ? cnt + C_HIST : nullptr,
                 cnt + C_GATE);
     R.commits = R.chosen;  // if nothing is undone

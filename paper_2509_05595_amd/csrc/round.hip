@@ -1043,7 +1043,9 @@ __global__ void k_flags_or(uint8_t* __restrict__ dst, const uint8_t* __restrict_
 // faces changed by a committed collapse take the overlap count measured on
 // the round's tentative mesh
 __global__ void k_ovl_commit(int nf, const int* __restrict__ owner, const uint8_t* __restrict__ falive,
-                             const int* __restrict__ undone, const int* __restrict__ ovl_new, int* __restrict__ ovl) {
+                             const int* __restrict__ undone, const int* __restrict__ ovl_new, int* __restrict__ ovl,
+                             const int* __restrict__ gate) {
+  if (gate && *gate) return;
   int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nf || !falive[f]) return;
   int o = owner[f];
@@ -1336,8 +1338,8 @@ void launch_remap_order(Workspace& ws, hipStream_t s, const int* order, int nf_o
 }
 
 void launch_ovl_commit(hipStream_t s, int nf, const int* owner, const uint8_t* falive, const int* undone,
-                       const int* ovl_new, int* ovl) {
-  hipLaunchKernelGGL(k_ovl_commit, dim3(nblk(nf)), dim3(256), 0, s, nf, owner, falive, undone, ovl_new, ovl);
+                       const int* ovl_new, int* ovl, const int* gate) {
+  hipLaunchKernelGGL(k_ovl_commit, dim3(nblk(nf)), dim3(256), 0, s, nf, owner, falive, undone, ovl_new, ovl, gate);
   PAMO_HIP(hipGetLastError());
 }
 

@@ -65,7 +65,7 @@ void launch_cap(Workspace& ws, hipStream_t s, const int* ncand, int nc_host, con
 void launch_face_boxes(hipStream_t s, MeshView m, float* box);
 // ovl[f] = ovl_new[f] for the alive faces of committed collapses
 void launch_ovl_commit(hipStream_t s, int nf, const int* owner, const uint8_t* falive, const int* undone,
-                       const int* ovl_new, int* ovl);
+                       const int* ovl_new, int* ovl, const int* gate = nullptr);
 // one launch for a round's check state: falive = 1, owner = -1 and (box not
 // null) the float32 box of every face, undone[0..ncand) = 0, valive (not
 // null) = 1
