@@ -507,14 +507,15 @@ void add_stats(pamo_stats* st, const RoundResult& R) {
 // rejections, plus the old flags when nothing was collapsed, Sec. 5.3),
 // compaction into `alt`, and the BVH leaf order remapped into `order_out`.
 void round_tail(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, const RoundResult& R, LearnRun* L,
-                const int* gate, int* order_out) {
+                const GateIn& gin, int* order_out) {
+  const int* gate = gin.flag;
   hipStream_t s = c->stream;
   int* cnt = c->dcnt;
   const double nf = cur.nf, nv = cur.nv;
   const bool logging = L && L->X;
   if (R.chosen > 0) {
     TIMED(PH_COMMIT, 100.0 * R.chosen);
-    launch_commit(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.undone, b.valive, gate);
+    launch_commit(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.undone, b.valive, gin);  // evaluates the gate
   }
   if (L && L->track && R.chosen > 0)
     launch_ovl_commit(s, cur.nf, b.owner, b.falive, b.undone, b.ovl_new, cur.ovl, gate);
@@ -530,18 +531,18 @@ void round_tail(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, c
   }
   if (R.commits > 0) {
     TIMED(PH_COMPACT, 72 * nf + 66 * nv);
-    launch_compact(c->ws, s, cur, alt, b.falive, b.valive, cnt + C_NF, cnt + C_NV, cnt + C_ERR, gate);
-  }
-  if (R.leaf_order) {
-    if (R.commits > 0) {
-      // the order buffer may be the one being remapped: go through a copy
+    // the leaf order follows the compaction (through a copy when it would be
+    // remapped in place)
+    const int* src = R.leaf_order;
+    if (src && src == order_out) {
       int* tmp = c->ws.get<int>("ord.copy", cur.nf);
-      PAMO_HIP(hipMemcpyAsync(tmp, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
-      launch_remap_order(c->ws, s, tmp, cur.nf, b.falive, c->ws.get<int>("cmp.fmap", cur.nf), order_out,
-                         cnt + C_NORD);
-    } else if (R.leaf_order != order_out) {
-      PAMO_HIP(hipMemcpyAsync(order_out, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+      PAMO_HIP(hipMemcpyAsync(tmp, src, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+      src = tmp;
     }
+    launch_compact(c->ws, s, cur, alt, b.falive, b.valive, cnt + C_NF, cnt + C_NV, cnt + C_ERR, gate, src, order_out,
+                   cnt + C_NORD);
+  } else if (R.leaf_order && R.leaf_order != order_out) {
+    PAMO_HIP(hipMemcpyAsync(order_out, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
   }
 }
 
@@ -633,11 +634,16 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
     CheckRun K;
     check_launch(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr, 1,
                  ovl_new, K);
-    launch_gate(s, cnt + C_NUNDO, cnt + C_NCANDP, K.qa.cand_cap, cnt + C_ERR, blind ? cnt + C_HIST : nullptr,
-                cnt + C_GATE);
+    GateIn gin;
+    gin.nundo = cnt + C_NUNDO;
+    gin.ncandp = cnt + C_NCANDP;
+    gin.err = cnt + C_ERR;
+    gin.npass = blind ? cnt + C_HIST : nullptr;
+    gin.cap = K.qa.cand_cap;
+    gin.flag = cnt + C_GATE;
     R.commits = R.chosen;  // if nothing is undone
     R.leaf_order = K.bvh.sorted;
-    round_tail(c, cur, alt, b, R, L, cnt + C_GATE, b.morder2);
+    round_tail(c, cur, alt, b, R, L, gin, b.morder2);
     h = readback(c);
     if (blind) {
       R.ncand = h[C_NCAND];
@@ -670,7 +676,7 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
     os.age = reuse ? os.age + 1 : 1;
     os.valid = true;
   }
-  round_tail(c, cur, alt, b, R, L, nullptr, b.morder);
+  round_tail(c, cur, alt, b, R, L, GateIn{}, b.morder);
   return round_end(c, cur, alt, R, L, readback(c));
 }
 

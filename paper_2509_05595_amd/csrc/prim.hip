@@ -231,6 +231,100 @@ void run_scan(Workspace& ws, hipStream_t s, Op op, St st, int64_t n, int32_t* to
   PAMO_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------------------ segmented ranks
+// Up to three independent flag scans in one launch (or one pair): the
+// segments lie end to end, each padded to whole tiles, so that a tile belongs
+// to one segment and its offset is the sum of the segment's earlier tiles.
+// Segment k: item i is flagged when flag[k][i] (or flag[k][gather[k][i]] when
+// gather[k] is set) is nonzero; rank[k][i] gets its rank or -1, list[k][rank]
+// gets i (or gather[k][i]); total[k] the count.  Absent arrays are skipped.
+struct Seg3 {
+  const uint8_t* flag[3];
+  const int32_t* gather[3];
+  int32_t* rank[3];
+  int32_t* list[3];
+  int32_t* total[3];
+  int64_t n[3];
+  int64_t tile0[4];  // first tile of each segment; tile0[3]: all tiles
+};
+
+__device__ __forceinline__ int seg_of(const Seg3& g, int64_t tile) { return tile >= g.tile0[2] ? 2 : tile >= g.tile0[1]; }
+
+__device__ __forceinline__ void seg_load16(const Seg3& g, int k, int64_t i, int* v) {
+  const int64_t n = g.n[k];
+  if (g.gather[k]) {
+#pragma unroll
+    for (int j = 0; j < 16; j++) v[j] = i + j < n ? g.flag[k][g.gather[k][i + j]] != 0 : 0;
+  } else {
+    FlagLoad{g.flag[k]}.load16(i, n, v);
+  }
+}
+
+__device__ __forceinline__ void seg_store(const Seg3& g, int k, int64_t i, int prefix, int v) {
+  if (g.rank[k]) g.rank[k][i] = v ? prefix : -1;
+  if (v && g.list[k]) g.list[k][prefix] = g.gather[k] ? g.gather[k][i] : (int32_t)i;
+}
+
+__global__ __launch_bounds__(T) void k_seg_reduce(Seg3 g, int32_t* tile_sum) {
+  const int64_t b = blockIdx.x;
+  const int k = seg_of(g, b);
+  const int64_t base = (b - g.tile0[k]) * TILE + (int64_t)threadIdx.x * ITEMS;
+  int v[ITEMS];
+  seg_load16(g, k, base, v);
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) s += v[i];
+  s = block_sum<T>(s);
+  if (threadIdx.x == 0) tile_sum[b] = s;
+}
+
+__global__ __launch_bounds__(T) void k_seg_scan(Seg3 g, const int32_t* tile_sum) {
+  const int64_t b = blockIdx.x;
+  const int k = seg_of(g, b);
+  const int64_t base = (b - g.tile0[k]) * TILE + (int64_t)threadIdx.x * ITEMS;
+  int v[ITEMS];
+  seg_load16(g, k, base, v);
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) s += v[i];
+  int pre = 0;
+  for (int64_t t = g.tile0[k] + threadIdx.x; t < b; t += T) pre += tile_sum[t];
+  const int off = block_sum<T>(pre);
+  int tot;
+  int ex = block_excl_scan<T>(s, tot) + off;
+  if (g.total[k] && b == g.tile0[k + 1] - 1 && threadIdx.x == 0) *g.total[k] = off + tot;
+#pragma unroll
+  for (int i = 0; i < ITEMS; i++) {
+    if (base + i < g.n[k]) seg_store(g, k, base + i, ex, v[i]);
+    ex += v[i];
+  }
+}
+
+// small inputs: the segments one after the other in a single block
+__global__ __launch_bounds__(TOP_T) void k_seg_single(Seg3 g) {
+  for (int k = 0; k < 3; k++) {
+    if (!g.flag[k]) continue;
+    int carry = 0;
+    for (int64_t base0 = 0; base0 < g.n[k]; base0 += (int64_t)TOP_T * TOP_ITEMS) {
+      const int64_t base = base0 + (int64_t)threadIdx.x * TOP_ITEMS;
+      int v[TOP_ITEMS];
+      seg_load16(g, k, base, v);
+      int s = 0;
+#pragma unroll
+      for (int i = 0; i < TOP_ITEMS; i++) s += v[i];
+      int tot;
+      int ex = block_excl_scan<TOP_T>(s, tot) + carry;
+#pragma unroll
+      for (int i = 0; i < TOP_ITEMS; i++) {
+        if (base + i < g.n[k]) seg_store(g, k, base + i, ex, v[i]);
+        ex += v[i];
+      }
+      carry += tot;
+    }
+    if (threadIdx.x == 0 && g.total[k]) *g.total[k] = carry;
+  }
+}
+
 __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -358,6 +452,59 @@ void compact_flags_map(Workspace& ws, hipStream_t s, const uint8_t* flags, int64
                        int32_t* out, int32_t* count) {
   run_scan(ws, s, FlagLoad{flags}, CompactMapStore{out, map}, n, count);
 }
+void rank_segments(Workspace& ws, hipStream_t s, const FlagSegment* seg, int nseg) {
+  if (nseg < 1 || nseg > 3) throw std::runtime_error("rank_segments: 1 to 3 segments");
+  Seg3 g{};
+  int64_t tiles = 0, items = 0;
+  for (int k = 0; k < 3; k++) {
+    g.tile0[k] = tiles;
+    if (k < nseg && seg[k].n > 0) {
+      g.flag[k] = seg[k].flag;
+      g.gather[k] = seg[k].gather;
+      g.rank[k] = seg[k].rank;
+      g.list[k] = seg[k].list;
+      g.total[k] = seg[k].total;
+      g.n[k] = seg[k].n;
+      tiles += (seg[k].n + TILE - 1) / TILE;
+      items += seg[k].n;
+    } else if (k < nseg && seg[k].total) {
+      fill_i32(s, seg[k].total, 1, 0);
+    }
+  }
+  g.tile0[3] = tiles;
+  if (tiles == 0) return;
+  if (items <= SINGLE_MAX) {
+    hipLaunchKernelGGL(k_seg_single, dim3(1), dim3(TOP_T), 0, s, g);
+  } else if (tiles <= LOCAL_TILES) {
+    int32_t* ts = ws.get<int32_t>("prim.segtiles", tiles);
+    hipLaunchKernelGGL(k_seg_reduce, dim3((unsigned)tiles), dim3(T), 0, s, g, ts);
+    hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)tiles), dim3(T), 0, s, g, (const int32_t*)ts);
+  } else {  // large: one scan per segment
+    for (int k = 0; k < nseg; k++) {
+      if (seg[k].n <= 0) continue;
+      Seg3 one{};
+      one.flag[0] = g.flag[k];
+      one.gather[0] = g.gather[k];
+      one.rank[0] = g.rank[k];
+      one.list[0] = g.list[k];
+      one.total[0] = g.total[k];
+      one.n[0] = g.n[k];
+      const int64_t t = (g.n[k] + TILE - 1) / TILE;
+      one.tile0[1] = one.tile0[2] = one.tile0[3] = t;
+      if (t > LOCAL_TILES) {
+        // beyond the two-pass form: the plain three-pass scans
+        if (one.gather[0] || one.list[0]) throw std::runtime_error("rank_segments: list segment too large");
+        rank_flags(ws, s, one.flag[0], one.n[0], one.rank[0], one.total[0]);
+        continue;
+      }
+      int32_t* ts = ws.get<int32_t>("prim.segtiles", t);
+      hipLaunchKernelGGL(k_seg_reduce, dim3((unsigned)t), dim3(T), 0, s, one, ts);
+      hipLaunchKernelGGL(k_seg_scan, dim3((unsigned)t), dim3(T), 0, s, one, (const int32_t*)ts);
+    }
+  }
+  PAMO_HIP(hipGetLastError());
+}
+
 void rank_flags(Workspace& ws, hipStream_t s, const uint8_t* flags, int64_t n, int32_t* map, int32_t* count) {
   run_scan(ws, s, FlagLoad{flags}, RankStore{map}, n, count);
 }

@@ -920,8 +920,12 @@ __global__ void k_changed_faces(int nf, const int* __restrict__ owner, const uin
 // apexes, retire r.  Undone candidates get reason 3.
 __global__ __launch_bounds__(256) void k_commit(MeshView m, const int* __restrict__ cand, const int* __restrict__ ncand,
                                                 uint8_t* __restrict__ reason, const int* __restrict__ undone,
-                                                uint8_t* __restrict__ valive, const int* __restrict__ gate) {
-  if (gate && *gate) return;
+                                                uint8_t* __restrict__ valive, GateIn gin) {
+  if (gin.flag) {
+    const bool shut = *gin.nundo > 0 || *gin.ncandp > gin.cap || *gin.err != 0 || (gin.npass && *gin.npass == 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *gin.flag = shut ? 1 : 0;
+    if (shut) return;
+  }
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= *ncand || reason[c] != 0) return;
   if (undone[c]) {
@@ -972,9 +976,9 @@ __global__ void k_reason_hist(const int* __restrict__ ncand, const uint8_t* __re
 }
 
 // ------------------------------------------------------------ compaction
-__global__ void k_compact_faces(MeshView src, MeshView dst, const uint8_t* __restrict__ falive,
-                                const int* __restrict__ fmap, const int* __restrict__ vmap, int* err,
-                                const int* __restrict__ gate) {
+__device__ __forceinline__ void compact_face(MeshView src, MeshView dst, const uint8_t* __restrict__ falive,
+                                                     const int* __restrict__ fmap, const int* __restrict__ vmap,
+                                                     int* err, const int* __restrict__ gate) {
   if (gate && *gate) return;
   int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= src.nf || !falive[f]) return;
@@ -998,9 +1002,9 @@ __global__ void k_compact_faces(MeshView src, MeshView dst, const uint8_t* __res
   if (src.ovl) dst.ovl[g] = src.ovl[f];
 }
 
-__global__ void k_compact_verts(MeshView src, MeshView dst, const uint8_t* __restrict__ valive,
-                                const int* __restrict__ vmap, const int* __restrict__ fmap,
-                                const int* __restrict__ gate) {
+__device__ __forceinline__ void compact_vertex(MeshView src, MeshView dst, const uint8_t* __restrict__ valive,
+                                                     const int* __restrict__ vmap, const int* __restrict__ fmap,
+                                                     const int* __restrict__ gate) {
   if (gate && *gate) return;
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= src.nv || !valive[v]) return;
@@ -1011,6 +1015,20 @@ __global__ void k_compact_verts(MeshView src, MeshView dst, const uint8_t* __res
   if (src.vmesh) dst.vmesh[w] = src.vmesh[v];
 }
 
+// faces and vertices in one launch (thread i compacts face i and vertex i);
+// ord (optional): the surviving faces in leaf order, old ids -> new ids
+__global__ void k_compact(MeshView src, MeshView dst, const uint8_t* __restrict__ falive,
+                          const uint8_t* __restrict__ valive, const int* __restrict__ fmap,
+                          const int* __restrict__ vmap, int* err, const int* __restrict__ gate, int* __restrict__ ord,
+                          const int* __restrict__ nord) {
+  compact_face(src, dst, falive, fmap, vmap, err, gate);
+  compact_vertex(src, dst, valive, vmap, fmap, gate);
+  if (ord && !(gate && *gate)) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < *nord) ord[i] = fmap[ord[i]];
+  }
+}
+
 __global__ void k_remap_order(const int* __restrict__ order, int n, const uint8_t* __restrict__ falive,
                               const int* __restrict__ fmap, int* __restrict__ tmp, uint8_t* __restrict__ pred) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1019,14 +1037,6 @@ __global__ void k_remap_order(const int* __restrict__ order, int n, const uint8_
   bool keep = falive[f] != 0;
   tmp[j] = keep ? fmap[f] : -1;
   pred[j] = keep;
-}
-
-// the round's gate: set when the check pass must be read back before the
-// round can end (a collapse was undone, the pair buffer overflowed, an error)
-__global__ void k_gate(const int* __restrict__ nundo, const int* __restrict__ ncandp, int cap,
-                       const int* __restrict__ err, const int* __restrict__ npass, int* __restrict__ gate) {
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    *gate = (*nundo > 0 || *ncandp > cap || *err != 0 || (npass && *npass == 0)) ? 1 : 0;
 }
 
 __global__ void k_clear_u8(uint8_t* __restrict__ p, int64_t n, const int* __restrict__ gate) {
@@ -1286,20 +1296,14 @@ void launch_face_list(Workspace& ws, hipStream_t s, int nf, const int* owner, co
 }
 
 void launch_commit(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, uint8_t* reason,
-                   const int* undone, uint8_t* valive, const int* gate) {
-  hipLaunchKernelGGL(k_commit, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, undone, valive, gate);
+                   const int* undone, uint8_t* valive, GateIn gin) {
+  hipLaunchKernelGGL(k_commit, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, undone, valive, gin);
   PAMO_HIP(hipGetLastError());
 }
 
 void launch_flags(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound,
                   const uint8_t* reason, int* hist, const int* gate) {
   hipLaunchKernelGGL(k_flags, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, hist, gate);
-  PAMO_HIP(hipGetLastError());
-}
-
-void launch_gate(hipStream_t s, const int* nundo, const int* ncandp, int cap, const int* err, const int* npass,
-                 int* gate) {
-  hipLaunchKernelGGL(k_gate, dim3(1), dim3(64), 0, s, nundo, ncandp, cap, err, npass, gate);
   PAMO_HIP(hipGetLastError());
 }
 
@@ -1316,16 +1320,25 @@ void launch_reason_hist(hipStream_t s, const int* ncand, int cand_bound, const u
 }
 
 void launch_compact(Workspace& ws, hipStream_t s, MeshView src, MeshView dst, const uint8_t* falive,
-                    const uint8_t* valive, int* nf_new, int* nv_new, int* err, const int* gate) {
+                    const uint8_t* valive, int* nf_new, int* nv_new, int* err, const int* gate, const int* order,
+                    int* order_out, int* nord) {
   int* fmap = ws.get<int>("cmp.fmap", src.nf);
   int* vmap = ws.get<int>("cmp.vmap", src.nv);
-  rank_flags(ws, s, falive, src.nf, fmap, nf_new);
-  rank_flags(ws, s, valive, src.nv, vmap, nv_new);
-  hipLaunchKernelGGL(k_compact_faces, dim3(nblk(src.nf)), dim3(256), 0, s, src, dst, falive, (const int*)fmap,
-                     (const int*)vmap, err, gate);
-  hipLaunchKernelGGL(k_compact_verts, dim3(nblk(src.nv)), dim3(256), 0, s, src, dst, valive, (const int*)vmap,
-                     (const int*)fmap, gate);
+  // face ranks, vertex ranks and the surviving faces in leaf order in one
+  // scan (the order segment up to 1,024 tiles of 4,096; beyond, on its own)
+  const bool fuse = order && src.nf <= 1024ll * 4096;
+  FlagSegment sg[3];
+  sg[0].flag = falive; sg[0].n = src.nf; sg[0].rank = fmap; sg[0].total = nf_new;
+  sg[1].flag = valive; sg[1].n = src.nv; sg[1].rank = vmap; sg[1].total = nv_new;
+  if (fuse) {
+    sg[2].flag = falive; sg[2].gather = order; sg[2].n = src.nf; sg[2].list = order_out; sg[2].total = nord;
+  }
+  rank_segments(ws, s, sg, fuse ? 3 : 2);
+  hipLaunchKernelGGL(k_compact, dim3(nblk(src.nf > src.nv ? src.nf : src.nv)), dim3(256), 0, s, src, dst, falive,
+                     valive, (const int*)fmap, (const int*)vmap, err, gate, fuse ? order_out : nullptr,
+                     (const int*)nord);
   PAMO_HIP(hipGetLastError());
+  if (order && !fuse) launch_remap_order(ws, s, order, src.nf, falive, fmap, order_out, nord);
 }
 
 void launch_remap_order(Workspace& ws, hipStream_t s, const int* order, int nf_old, const uint8_t* falive,

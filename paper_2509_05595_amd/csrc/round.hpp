@@ -82,21 +82,32 @@ void launch_undo(hipStream_t s, MeshView m, const int* cand, const int* ncand, i
 // (in the order of `order` when given: a permutation of the faces)
 void launch_face_list(Workspace& ws, hipStream_t s, int nf, const int* owner, const uint8_t* falive,
                       const int* undone, int iter, const int* order, int* list, int* count);
+// Kernels given a gate do nothing when *gate != 0.  The gate is set when the
+// check pass must be read back before the round can end: a collapse was
+// undone, more candidate pairs than cap, an error bit, or (npass given) no
+// collapse passed the local checks.  The commit kernel evaluates it from these
+// counters (GateIn) and stores it for the kernels after it.
+struct GateIn {
+  const int* nundo = nullptr;
+  const int* ncandp = nullptr;
+  const int* err = nullptr;
+  const int* npass = nullptr;
+  int cap = 0;
+  int* flag = nullptr;  // null: no gate to evaluate
+};
+
 void launch_commit(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, uint8_t* reason,
-                   const int* undone, uint8_t* valive, const int* gate = nullptr);
+                   const int* undone, uint8_t* valive, GateIn gin = GateIn{});
 // flags of rejected edges; hist (may be null) += histogram of the reasons
 void launch_flags(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const uint8_t* reason,
                   int* hist = nullptr, const int* gate = nullptr);
 void launch_flags_or(hipStream_t s, uint8_t* dst, const uint8_t* src, int64_t n);
 void launch_reason_hist(hipStream_t s, const int* ncand, int cand_bound, const uint8_t* reason, int* hist);
+// order (optional): a leaf order of the source faces, whose surviving faces go
+// to order_out (new ids, the count to *nord); order_out must not be order
 void launch_compact(Workspace& ws, hipStream_t s, MeshView src, MeshView dst, const uint8_t* falive,
-                    const uint8_t* valive, int* nf_new, int* nv_new, int* err, const int* gate = nullptr);
-// Kernels given a gate do nothing when *gate != 0.  launch_gate sets *gate when
-// the check pass must be read back before the round can end (a collapse was
-// undone, more candidate pairs than cap, an error bit, or, when npass is
-// given, no collapse passed the local checks).
-void launch_gate(hipStream_t s, const int* nundo, const int* ncandp, int cap, const int* err, const int* npass,
-                 int* gate);
+                    const uint8_t* valive, int* nf_new, int* nv_new, int* err, const int* gate = nullptr,
+                    const int* order = nullptr, int* order_out = nullptr, int* nord = nullptr);
 void launch_clear_u8(hipStream_t s, uint8_t* p, int64_t n, const int* gate);
 
 // ------------------------------------------------------------ LBVH
