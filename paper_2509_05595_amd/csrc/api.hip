@@ -439,7 +439,8 @@ bool check_launch(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand, 
   K.qbytes = 128.0 * bvh_nodes_written(m.nf) + 17 * nf + 24 * nv;  // tree + faces + alive/owner + vertices
   K.pbytes = 17 * nf + 24 * nv;  // pairs: faces, alive/owner, vertices (+ 8 per pair)
   qa.ovl_cnt = ovl_new;          // overlap counts of the changed faces on the tentative mesh
-  fill_i32(s, cnt + C_NUNDO, 4, 0);  // undone, deferred, collected, intersecting
+  // the counters of the pass (undone, deferred, collected, intersecting) are
+  // still zero from the start of the round: every caller clears them there
   query_launch(c, K.bvh, QUERY_CHANGED, b.qlist, cnt + C_NQ, m.nf, 10ll * R.chosen, qa, K.qbytes);
   return true;
 }

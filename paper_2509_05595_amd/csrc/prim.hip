@@ -180,7 +180,8 @@ __global__ __launch_bounds__(T) void k_tile_scan(Op op, St st, int64_t n, const 
 
 // Small inputs: the whole scan in one block and one launch (a carry walks the
 // chunks of TOP_T * TOP_ITEMS items in order).  Late rounds run on small
-// meshes, where three launches per scan cost more than the work.
+// meshes, where three launches per scan cost more than the work (one block
+// over more than one chunk measured no faster than two launches).
 constexpr int64_t SINGLE_MAX = (int64_t)TOP_T * TOP_ITEMS;
 
 template <class Op, class St>
