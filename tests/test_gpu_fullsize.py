@@ -113,3 +113,26 @@ def test_round0_beyond_two_pass_scan(ctx):
     assert np.array_equal(F1.cpu().numpy(), r["F"])
     assert np.array_equal(V1.cpu().numpy().view(np.uint64), r["V"].view(np.uint64))
     assert np.array_equal(fl1.cpu().numpy(), r["flags"])
+
+
+def test_whole_mesh_check_on_interpenetrating_spheres(ctx):
+    """The whole-mesh exact check (the benchmark's pamo_self_intersections) on
+    two noisy geodesic spheres of 124,820 faces each, the second shifted by 0.6
+    of a radius so the two surfaces cross along a closed curve: the pair set
+    equals the oracle's (grid-based, exact predicate) element by element, and
+    each sphere alone reports none."""
+    V1, F1 = g.noisy_geodesic_sphere(79, 3)
+    V2, F2 = g.noisy_geodesic_sphere(79, 4)
+    V2 = V2 + np.array([0.3, 0.0, 0.0])
+    V = np.ascontiguousarray(np.concatenate([V1, V2]))
+    F = np.ascontiguousarray(np.concatenate([F1, F2 + len(V1)]).astype(np.int32))
+    want = orc.self_intersections(V, F, cap=1 << 20)
+    assert len(want) > 1000
+    pairs, n = ctx.self_intersections(torch.from_numpy(V).cuda(), torch.from_numpy(F).cuda(), cap=1 << 20)
+    assert n == len(want)
+    got = pairs.cpu().numpy()
+    key = lambda p: np.sort(np.minimum(p[:, 0], p[:, 1]).astype(np.int64) * (1 << 32) + np.maximum(p[:, 0], p[:, 1]))
+    assert np.array_equal(key(got), key(np.asarray(want)))
+    for Vs, Fs in ((V1, F1), (V2, F2)):
+        _, n1 = ctx.self_intersections(torch.from_numpy(np.ascontiguousarray(Vs)).cuda(), torch.from_numpy(Fs).cuda())
+        assert n1 == 0
