@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
 
 class Opts(C.Structure):
     _fields_ = [("w_e", C.c_double), ("w_s", C.c_double), ("tolerance", C.c_int32),
-                ("max_rounds", C.c_int32)]
+                ("max_rounds", C.c_int32), ("cost_target", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -189,8 +189,10 @@ def check(V, F, target, flags=None, w_e=W_E, w_s=W_S):
 
 
 def run(V, F, target, flags=None, streak=0, max_rounds=-1, w_e=W_E, w_s=W_S,
-        tolerance=TOLERANCE, log_rounds=0):
-    """Whole method.  Returns dict with V, F, flags, streak, stats, log."""
+        tolerance=TOLERANCE, log_rounds=0, cost_target=0.0):
+    """Whole method.  Returns dict with V, F, flags, streak, stats, log.
+    cost_target > 0: only edges costing at most this collapse, and a round that
+    selects nothing ends the run (the paper's target-cost termination)."""
     V, F = _mesh(V, F)
     Vo = np.zeros_like(V)
     Fo = np.zeros_like(F)
@@ -199,7 +201,7 @@ def run(V, F, target, flags=None, streak=0, max_rounds=-1, w_e=W_E, w_s=W_S,
     nfo = np.zeros(1, dtype=np.int64)
     so = np.zeros(1, dtype=np.int32)
     st = Stats()
-    opt = Opts(w_e, w_s, tolerance, max_rounds)
+    opt = Opts(w_e, w_s, tolerance, max_rounds, cost_target)
     LogArr = RoundLog * max(1, log_rounds)
     log = LogArr()
     rc = lib().oracle_run(_p(V), len(V), _p(F), len(F), _p(_flags(flags, len(F))), int(streak),

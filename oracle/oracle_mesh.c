@@ -57,6 +57,9 @@ typedef struct {
     double w_e, w_s;
     int32_t tolerance;
     int32_t max_rounds; /* < 0: no limit */
+    double cost_target; /* > 0: collapse only edges whose cost is at most this; the run
+                           also ends when a round selects no edge (the target-cost
+                           termination the paper offers besides the face count) */
 } oracle_opts;
 
 typedef struct {
@@ -335,8 +338,8 @@ static int edge_flagged(const omesh *m, int64_t h) {
 }
 
 /* keys at every half-edge that represents its edge (h < twin(h)); KEY_MAX
- * elsewhere */
-static void compute_keys(omesh *m, double w_e, double w_s) {
+ * elsewhere, and for edges costing more than cost_target when it is > 0 */
+static void compute_keys_capped(omesh *m, double w_e, double w_s, double cost_target) {
     free(m->key);
     m->key = xalloc(sizeof(uint64_t) * (size_t)(3 * m->nf));
     for (int64_t h = 0; h < 3 * m->nf; h++) {
@@ -346,9 +349,12 @@ static void compute_keys(omesh *m, double w_e, double w_s) {
         int32_t a = m->F[h], b = m->F[3 * (h / 3) + (h % 3 + 1) % 3];
         double vbar[3];
         double cost = edge_cost(m, a, b, w_e, w_s, vbar);
+        if (cost_target > 0 && cost > cost_target) continue;
         m->key[h] = make_key(cost, (uint32_t)h);
     }
 }
+
+static void compute_keys(omesh *m, double w_e, double w_s) { compute_keys_capped(m, w_e, w_s, 0.0); }
 
 /* R5/R6 in the push form of the paper: C_t = min over edges e whose 1-ring
  * contains t of C_e; e is chosen when C_t = C_e for every t of its 1-ring. */
@@ -881,7 +887,7 @@ static int run_round(omesh *m, int64_t target_eff, const oracle_opts *opt, round
     int err = build_adjacency(m);
     if (err) return err;
     compute_quadrics(m);
-    compute_keys(m, opt->w_e, opt->w_s);
+    compute_keys_capped(m, opt->w_e, opt->w_s, opt->cost_target);
     int64_t nf = m->nf, nv = m->nv;
 
     int32_t *cand = xalloc(sizeof(int32_t) * (size_t)(3 * nf + 1));
@@ -1156,7 +1162,7 @@ int oracle_check(const double *V, int64_t nv, const int32_t *F, int64_t nf, cons
     omesh m;
     mesh_init(&m, V, nv, F, nf);
     if (flags) memcpy(m.flags, flags, (size_t)(3 * nf));
-    oracle_opts o = {w_e, w_s, 4, -1};
+    oracle_opts o = {w_e, w_s, 4, -1, 0.0};
     round_out r;
     int err = run_round(&m, target - (target % 2), &o, &r, 1, NULL, NULL);
     if (!err) {
@@ -1216,7 +1222,7 @@ static int run_impl(const double *V, int64_t nv, const int32_t *F, int64_t nf,
             err = build_adjacency(&m);
             if (err) break;
             compute_quadrics(&m);
-            compute_keys(&m, opt->w_e, opt->w_s);
+            compute_keys_capped(&m, opt->w_e, opt->w_s, opt->cost_target);
             int32_t *c0 = xalloc(sizeof(int32_t) * (size_t)(3 * m.nf + 1));
             int64_t n0 = select_edges(&m, c0);
             feat = xalloc(sizeof(float) * NFEAT * (size_t)(n0 + 1));
@@ -1262,7 +1268,12 @@ static int run_impl(const double *V, int64_t nv, const int32_t *F, int64_t nf,
         st->candidates += r.ncand;
         st->rej_link += rl; st->rej_flip += rf; st->rej_isect += ri; st->capped += cp;
         st->undo_hist[r.undo_iters < 4 ? r.undo_iters : 4]++;
+        const int64_t selected = r.ncand;
         free(r.cand); free(r.reason); free(r.vbar);
+        /* with a cost target, a round that selects nothing ends the run: every
+         * edge is then flagged or costs more than the target, and the next
+         * round would be the same */
+        if (opt->cost_target > 0 && selected == 0) { st->status = 0; break; }
     }
     if (!err) {
         int32_t *vmap = xalloc(sizeof(int32_t) * (size_t)m.nv);

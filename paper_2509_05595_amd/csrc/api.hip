@@ -581,7 +581,8 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
   }
   {
     TIMED(PH_COST, 104 * nv + 51 * nf);
-    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, cnt + C_ERR, b.vmin);
+    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, cnt + C_ERR, b.vmin,
+                     c->opt.cost_target);
   }
   {
     TIMED(PH_SELECT, 20 * nv + 93 * nf);
@@ -848,6 +849,7 @@ const int* readback_batch(pamo_ctx* c, const Batch& B) {
 struct MeshRun {
   int64_t teff = 0;
   int streak = 0;
+  bool settled = false;  // cost target: a round selected nothing, the mesh is done
   bool active = false;
   bool rejected = false;  // the mesh's previous round had check rejections
   pamo_stats st{};
@@ -892,7 +894,8 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const Rou
   }
   {
     TIMED(PH_COST, 104 * nv + 51 * nf);
-    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, B.done, b.key, cnt + C_ERR, b.vmin);
+    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, B.done, b.key, cnt + C_ERR, b.vmin,
+                     c->opt.cost_target);
   }
   {
     TIMED(PH_SELECT, 20 * nv + 93 * nf);
@@ -1014,6 +1017,9 @@ pamo_status simplify_run(pamo_ctx* c, const double* V, int64_t nv, const int32_t
     RoundResult R = run_round_learned(c, cur, alt, b, teff, os, L);
     add_stats(&st, R);
     streak = R.commits == 0 ? streak + 1 : 0;
+    // with a cost target, a round that selects nothing ends the run: every
+    // edge is flagged or above the target, and the next round would be the same
+    if (c->opt.cost_target > 0 && R.ncand == 0) break;
     L->active = R.hist[1] + R.hist[2] + R.hist[3] > 0;  // the network has something to predict
   }
   PAMO_HIP(hipMemcpyAsync(V_out, cur.V, 3 * (size_t)cur.nv * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1120,7 +1126,8 @@ pamo_status pamo_select(pamo_ctx* c, const double* V, int64_t nv, const int32_t*
     RoundBufs b = round_bufs(c, nv, nf);
     uint64_t* key = keys ? keys : b.key;
     launch_quadrics(c->stream, A, b.Q, c->dcnt + C_ERR);
-    launch_cost_keys(c->stream, A, b.Q, c->opt.w_e, c->opt.w_s, demote, nullptr, key, c->dcnt + C_ERR);
+    launch_cost_keys(c->stream, A, b.Q, c->opt.w_e, c->opt.w_s, demote, nullptr, key, c->dcnt + C_ERR, nullptr,
+                     c->opt.cost_target);
     launch_select(c->ws, c->stream, A, key, b.vmin, cand, ncand);
     check_err_bits(readback(c)[C_ERR]);
     return PAMO_OK;
@@ -1144,7 +1151,8 @@ pamo_status pamo_check(pamo_ctx* c, const double* V, int64_t nv, const int32_t* 
     hipStream_t s = c->stream;
     fill_i32(s, c->dcnt, C_COUNT, 0);
     launch_quadrics(s, A, b.Q, c->dcnt + C_ERR);
-    launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR);
+    launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR, nullptr,
+                     c->opt.cost_target);
     int64_t teff = target_faces - target_faces % 2;
     if (A.nf <= teff) fail(PAMO_ERR_ARG, "the mesh is already at or below the target");
     RoundResult R;
@@ -1307,7 +1315,7 @@ pamo_status pamo_simplify_batch(pamo_ctx* c, int32_t nmesh, const double* V, con
       for (int m = 0; m < nmesh; m++) {
         MeshRun& r = mr[m];
         r.active = false;
-        if (r.st.status != PAMO_OK) continue;
+        if (r.st.status != PAMO_OK || r.settled) continue;
         int64_t nfm = c->hbt[B.f_off() + m + 1] - c->hbt[B.f_off() + m];
         if (nfm <= r.teff) continue;
         if (r.streak >= c->opt.tolerance) {
@@ -1338,6 +1346,7 @@ pamo_status pamo_simplify_batch(pamo_ctx* c, int32_t nmesh, const double* V, con
         r.st.undo_hist[std::min(c->hbt[B.undo_m() + m], 4)]++;
         r.streak = cm == 0 ? r.streak + 1 : 0;
         r.rejected = hm[1] + hm[2] + hm[3] > 0;
+        if (c->opt.cost_target > 0 && ncm == 0) r.settled = true;
       };
       std::vector<int> retry;
       for (int m = 0; m < nmesh; m++) {
@@ -1455,7 +1464,8 @@ pamo_status pamo_features(pamo_ctx* c, const double* V, int64_t nv, const int32_
       hipLaunchKernelGGL(k_check_index, dim3(nblk(ne)), dim3(256), 0, s, edges, ne, (int)(3 * nf), c->dcnt + C_ERR);
       check_err_bits(readback(c)[C_ERR]);
       launch_quadrics(s, A, b.Q, c->dcnt + C_ERR);
-      launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR);
+      launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR, nullptr,
+                     c->opt.cost_target);
       fill_i32(s, c->dcnt + C_NCAND, 1, (int)ne);
       launch_features(s, A, b.key, edges, c->dcnt + C_NCAND, (int)ne, A.ovl, X, c->dcnt + C_ERR);
     }

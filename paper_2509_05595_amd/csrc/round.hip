@@ -456,7 +456,7 @@ constexpr int64_t CK_SMALL_NH = 1 << 21;
 
 template <int PW>
 __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
-                                                   const uint8_t* __restrict__ demote,
+                                                   double cost_max, const uint8_t* __restrict__ demote,
                                                    const uint8_t* __restrict__ mesh_done, uint64_t* __restrict__ key,
                                                    int* err, uint64_t* __restrict__ vmin) {
   __shared__ int queue[4][PW];
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __r
       } else {
         P3 vbar;
         double cost = edge_cost(m, Q, E, w_e, w_s, vbar);
-        k = make_key(cost, (uint32_t)h);
+        k = cost > cost_max ? PAMO_KEY_MAX : make_key(cost, (uint32_t)h);  // above the cost target: never chosen
         if (vmin && k != PAMO_KEY_MAX) {  // the vertex minima of the selection, in place of a gather pass
           atomicMin(reinterpret_cast<unsigned long long*>(vmin + E.s), (unsigned long long)k);
           atomicMin(reinterpret_cast<unsigned long long*>(vmin + E.r), (unsigned long long)k);
@@ -1225,14 +1225,15 @@ void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err, uint64_t* v
 }
 
 void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
-                      const uint8_t* mesh_done, uint64_t* key, int* err, uint64_t* vmin) {
+                      const uint8_t* mesh_done, uint64_t* key, int* err, uint64_t* vmin, double cost_target) {
   const int64_t nh = 3 * (int64_t)m.nf;
+  const double cost_max = cost_target > 0 ? cost_target : INFINITY;
   if (nh <= CK_SMALL_NH)
-    hipLaunchKernelGGL(k_cost_keys<64>, dim3(nblk(nh, 4 * 64)), dim3(256), 0, s, m, Q, w_e, w_s, demote, mesh_done,
-                       key, err, vmin);
+    hipLaunchKernelGGL(k_cost_keys<64>, dim3(nblk(nh, 4 * 64)), dim3(256), 0, s, m, Q, w_e, w_s, cost_max, demote,
+                       mesh_done, key, err, vmin);
   else
-    hipLaunchKernelGGL(k_cost_keys<256>, dim3(nblk(nh, 4 * 256)), dim3(256), 0, s, m, Q, w_e, w_s, demote, mesh_done,
-                       key, err, vmin);
+    hipLaunchKernelGGL(k_cost_keys<256>, dim3(nblk(nh, 4 * 256)), dim3(256), 0, s, m, Q, w_e, w_s, cost_max, demote,
+                       mesh_done, key, err, vmin);
   PAMO_HIP(hipGetLastError());
 }
 

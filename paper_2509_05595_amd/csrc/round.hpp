@@ -51,8 +51,10 @@ void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err, uint64_t* v
 // mesh_done (batches, may be null): edges of finished meshes get no key
 // vmin (optional): every finite key is also folded into vmin of both endpoints
 // (atomic minimum; vmin set to the largest key beforehand)
+// cost_target > 0: edges costing more get the largest key (never chosen)
 void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
-                      const uint8_t* mesh_done, uint64_t* key, int* err, uint64_t* vmin = nullptr);
+                      const uint8_t* mesh_done, uint64_t* key, int* err, uint64_t* vmin = nullptr,
+                      double cost_target = 0.0);
 // vmin_ready: vmin already holds the vertex minima of key (the cost kernel
 // folded them in), so only the selection and its compaction run
 void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, int* cand,
