@@ -599,8 +599,8 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
   }
   local_checks(c, cur, b, b.cand, cnt + C_NCAND, bound, b.reason, b.vbar);
   int* ovl_new = L && L->track ? b.ovl_new : nullptr;
-  // the network not consulted and no rows logged (overlap counts may be kept)
-  const bool plain = !learned && !logging;
+  // no training rows logged (the network may be consulted, overlap counts kept)
+  const bool plain = !logging;
   // The exact-target cap cannot bind while nf >= 2 teff: selected edges have
   // disjoint rings of at least four faces, so at most nf / 4 pass, and
   // nf / 4 <= (nf - teff) / 2.  The plain method then goes on without reading
@@ -626,8 +626,8 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
   }
   const bool reuse = os.valid && os.age < os.resort;
   if (!blind) cap_single(c, b, cnt + C_NCAND, b.reason, teff, cur.nf, R);
-  // Speculative end of round (network not consulted, nothing logged, something
-  // to apply): the round's tail is enqueued right behind the first query
+  // Speculative end of round (no training rows logged, something to apply):
+  // the round's tail is enqueued right behind the first query
   // pass, its kernels gated on the device.  When that pass undid nothing,
   // fitted its pair buffer and set no error bit, the round ends with this one
   // read-back; otherwise the tail did nothing and the check is finished the
@@ -650,6 +650,7 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
     if (blind) {
       R.ncand = h[C_NCAND];
       R.chosen = R.npass = h[C_HIST + 0];
+      R.demoted = h[C_NDEMOTE];
       prof_bytes(c, PH_LOCAL, 780.0 * R.ncand);
     }
     os.chosen_est = R.chosen;
@@ -855,9 +856,49 @@ struct MeshRun {
   pamo_stats st{};
 };
 
+// The end of a batch round (gated like round_tail): commit, per-mesh tallies
+// of the outcome, overlap counts, flags (cleared only in meshes that
+// committed), compaction with the per-mesh offsets and the leaf order.
+void batch_tail(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, const Batch& B, const RoundResult& R,
+                bool track, bool learned, const GateIn& gin, int* order_out) {
+  hipStream_t s = c->stream;
+  int* cnt = c->dcnt;
+  const int n = B.n;
+  const double nf = cur.nf, nv = cur.nv;
+  const int* gate = gin.flag;
+  if (R.chosen > 0) {
+    TIMED(PH_COMMIT, 100.0 * R.chosen);
+    launch_commit(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.undone, b.valive, gin);  // evaluates the gate
+  }
+  launch_mesh_tally(s, b.cand, cnt + C_NCAND, R.ncand, cur.fmesh, nullptr, b.reason, b.undone, nullptr, nullptr,
+                    B.d(B.commits_m()), B.d(B.hist_m()), B.d(B.undo_m()), gate);
+  if (track && R.chosen > 0) launch_ovl_commit(s, cur.nf, b.owner, b.falive, b.undone, b.ovl_new, cur.ovl, gate);
+  if (learned)  // meshes whose round runs again keep their flags
+    launch_mark_retry(s, b.cand, cnt + C_NCAND, R.ncand, cur.fmesh, B.d(B.demote_m()), B.d(B.commits_m()), b.reason,
+                      gate);
+  {
+    TIMED(PH_FLAGS, 3 * nf + 10.0 * R.ncand);
+    if (R.commits > 0) launch_flags_clear_batch(s, cur, B.d(B.commits_m()), gate);
+    launch_flags(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, cnt + C_HIST2, gate);
+  }
+  if (R.commits > 0) {
+    TIMED(PH_COMPACT, 72 * nf + 66 * nv);
+    const int* src = R.leaf_order;
+    if (src && src == order_out) {  // remapping in place: go through a copy
+      int* tmp = c->ws.get<int>("ord.copy", cur.nf);
+      PAMO_HIP(hipMemcpyAsync(tmp, src, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+      src = tmp;
+    }
+    launch_compact(c->ws, s, cur, alt, b.falive, b.valive, cnt + C_NF, cnt + C_NV, cnt + C_ERR, gate, src, order_out,
+                   cnt + C_NORD, B.d(B.f_off()), B.d(B.v_off()), n);
+  } else if (R.leaf_order && R.leaf_order != order_out) {
+    PAMO_HIP(hipMemcpyAsync(order_out, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+  }
+}
+
 // One round over every mesh of the batch (the single-mesh round of run_round
 // with per-mesh targets, tallies, flag clearing and offsets).
-RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, const Batch& B,
+RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, const Batch& B,
                             std::vector<MeshRun>& mr, OrderState& os, bool learned = false, bool track = false) {
   hipStream_t s = c->stream;
   int* cnt = c->dcnt;
@@ -912,68 +953,84 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, const Rou
   local_checks(c, cur, b, b.cand, cnt + C_NCAND, bound, b.reason, b.vbar);
   launch_mesh_tally(s, b.cand, cnt + C_NCAND, bound, cur.fmesh, b.reason, nullptr, nullptr, B.d(B.ncand_m()),
                     B.d(B.npass_m()), nullptr, nullptr, nullptr);
-  const int* h = readback_batch(c, B);
-  check_err_bits(h[C_ERR]);
-  R.ncand = h[C_NCAND];
-  R.npass = h[C_HIST + 0];
-  prof_bytes(c, PH_LOCAL, 780.0 * R.ncand);
-  if (R.ncand == 0) return R;
-  bool capped = false;
-  R.chosen = 0;
-  for (int m = 0; m < n; m++) {
-    int np = c->hbt[B.npass_m() + m];
-    if (np > hneed[m]) capped = true;
-    R.chosen += std::min(np, hneed[m]);
+  // as in run_round: no mesh's exact-target cap can bind while every active
+  // mesh has nf_m >= 2 teff_m, so the plain batch then goes on without
+  // reading the candidate counts back
+  bool blind = true;
+  for (int m = 0; m < n && blind; m++) {
+    const int64_t nfm = c->hbt[B.f_off() + m + 1] - c->hbt[B.f_off() + m];
+    if (mr[m].active && nfm < 2 * mr[m].teff) blind = false;
   }
-  if (capped) {
-    TIMED(PH_CAP, 8 * 16.0 * R.ncand);
-    launch_cap_batch(c->ws, s, cnt + C_NCAND, R.ncand, b.cand, cur.fmesh, b.ckey, b.reason, B.need,
-                     B.d(B.ncand_m()), n);
+  const int* h = nullptr;
+  if (blind) {
+    R.ncand = bound;
+    R.chosen = R.npass = std::max(1, os.chosen_est > 0 ? os.chosen_est : cur.nf / 32);  // estimate (sizes grids)
+  } else {
+    h = readback_batch(c, B);
+    check_err_bits(h[C_ERR]);
+    R.ncand = h[C_NCAND];
+    R.npass = h[C_HIST + 0];
+    prof_bytes(c, PH_LOCAL, 780.0 * R.ncand);
+    if (R.ncand == 0) return R;
+    bool capped = false;
+    R.chosen = 0;
+    for (int m = 0; m < n; m++) {
+      int np = c->hbt[B.npass_m() + m];
+      if (np > hneed[m]) capped = true;
+      R.chosen += std::min(np, hneed[m]);
+    }
+    if (capped) {
+      TIMED(PH_CAP, 8 * 16.0 * R.ncand);
+      launch_cap_batch(c->ws, s, cnt + C_NCAND, R.ncand, b.cand, cur.fmesh, b.ckey, b.reason, B.need,
+                       B.d(B.ncand_m()), n);
+    }
   }
   const bool reuse = os.valid && os.age < os.resort;
-  check_and_undo(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr, n,
-                 track ? b.ovl_new : nullptr);
-  if (R.leaf_order) os.age = reuse ? os.age + 1 : 1;
+  int* ovl_new = track ? b.ovl_new : nullptr;
   if (R.chosen > 0) {
-    TIMED(PH_COMMIT, 100.0 * R.chosen);
-    launch_commit(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.undone, b.valive);
-  }
-  launch_mesh_tally(s, b.cand, cnt + C_NCAND, R.ncand, cur.fmesh, nullptr, b.reason, b.undone, nullptr, nullptr,
-                    B.d(B.commits_m()), B.d(B.hist_m()), B.d(B.undo_m()));
-  if (track && R.chosen > 0) launch_ovl_commit(s, cur.nf, b.owner, b.falive, b.undone, b.ovl_new, cur.ovl);
-  if (learned)  // meshes whose round runs again keep their flags
-    launch_mark_retry(s, b.cand, cnt + C_NCAND, R.ncand, cur.fmesh, B.d(B.demote_m()), B.d(B.commits_m()), b.reason);
-  {
-    TIMED(PH_FLAGS, 3 * nf + 10.0 * R.ncand);
-    if (R.commits > 0) launch_flags_clear_batch(s, cur, B.d(B.commits_m()));
-    launch_flags(s, cur, b.cand, cnt + C_NCAND, R.ncand, b.reason, cnt + C_HIST2);
-  }
-  if (R.commits > 0) {
-    TIMED(PH_COMPACT, 72 * nf + 66 * nv);
-    launch_compact(c->ws, s, cur, alt, b.falive, b.valive, cnt + C_NF, cnt + C_NV, cnt + C_ERR);
-    launch_batch_offsets(c->ws, s, b.falive, cur.nf, B.d(B.f_off()), n);
-    launch_batch_offsets(c->ws, s, b.valive, cur.nv, B.d(B.v_off()), n);
+    // speculative end of round, gated on the device (see run_round)
+    CheckRun K;
+    check_launch(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr, n,
+                 ovl_new, K);
+    GateIn gin;
+    gin.nundo = cnt + C_NUNDO;
+    gin.ncandp = cnt + C_NCANDP;
+    gin.err = cnt + C_ERR;
+    gin.npass = blind ? cnt + C_HIST : nullptr;
+    gin.cap = K.qa.cand_cap;
+    gin.flag = cnt + C_GATE;
+    R.commits = R.chosen;
+    R.leaf_order = K.bvh.sorted;
+    batch_tail(c, cur, alt, b, B, R, track, learned, gin, b.morder2);
+    h = readback_batch(c, B);
+    if (blind) {
+      R.ncand = h[C_NCAND];
+      R.chosen = R.npass = h[C_HIST + 0];
+      prof_bytes(c, PH_LOCAL, 780.0 * R.ncand);
+    }
+    os.chosen_est = R.chosen;
+    if (!h[C_GATE]) {
+      prof_bytes(c, PH_PAIRS, 8.0 * h[C_NCANDP] + K.pbytes);
+      R.commits = R.chosen;
+      R.deferred += h[C_NDEFER];
+      os.age = reuse ? os.age + 1 : 1;
+      os.valid = true;
+      std::swap(b.morder, b.morder2);
+      return round_end(c, cur, alt, R, nullptr, h);
+    }
+    R.commits = 0;
+    R.leaf_order = nullptr;
+    check_resolve(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, R, K, h);
+  } else {
+    check_and_undo(c, cur, b, b.cand, cnt + C_NCAND, R.ncand, b.reason, b.vbar, R, reuse ? b.morder : nullptr, n,
+                   ovl_new);
   }
   if (R.leaf_order) {
-    if (R.commits > 0) {
-      int* tmp = c->ws.get<int>("ord.copy", cur.nf);
-      PAMO_HIP(hipMemcpyAsync(tmp, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
-      launch_remap_order(c->ws, s, tmp, cur.nf, b.falive, c->ws.get<int>("cmp.fmap", cur.nf), b.morder,
-                         cnt + C_NORD);
-    } else if (R.leaf_order != b.morder) {
-      PAMO_HIP(hipMemcpyAsync(b.morder, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
-    }
+    os.age = reuse ? os.age + 1 : 1;
     os.valid = true;
   }
-  h = readback_batch(c, B);
-  check_err_bits(h[C_ERR]);
-  for (int i = 0; i < 8; i++) R.hist[i] = h[C_HIST2 + i];
-  if (R.commits > 0) {
-    alt.nf = h[C_NF];
-    alt.nv = h[C_NV];
-    std::swap(cur, alt);
-  }
-  return R;
+  batch_tail(c, cur, alt, b, B, R, track, learned, GateIn{}, b.morder);
+  return round_end(c, cur, alt, R, nullptr, readback_batch(c, B));
 }
 
 // the whole method on one mesh (plain, learned, or plain with row logging)

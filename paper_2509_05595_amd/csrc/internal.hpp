@@ -67,15 +67,17 @@ void compact_flags_map(Workspace& ws, hipStream_t s, const uint8_t* flags, int64
 void rank_flags(Workspace& ws, hipStream_t s, const uint8_t* flags, int64_t n, int32_t* map, int32_t* count);
 // Up to three independent flag scans in one launch pair.  Item i of a segment
 // is flagged when flag[i] (flag[gather[i]] with gather) is nonzero; rank[i]
-// (optional) gets its rank or -1, list[rank] (optional) gets i (gather[i]),
-// *total (optional) the count.  A segment with a list and more than 1,024
-// tiles of 4,096 items is refused.
+// (optional) gets its rank or -1, excl[i] (optional) the number of flagged
+// items before it, list[rank] (optional) gets i (gather[i]), *total
+// (optional) the count.  A segment with a list and more than 1,024 tiles of
+// 4,096 items is refused.
 struct FlagSegment {
   const uint8_t* flag = nullptr;
   const int32_t* gather = nullptr;
   int64_t n = 0;
   int32_t* rank = nullptr;
   int32_t* list = nullptr;
+  int32_t* excl = nullptr;
   int32_t* total = nullptr;
 };
 void rank_segments(Workspace& ws, hipStream_t s, const FlagSegment* seg, int nseg);

@@ -447,7 +447,9 @@ __global__ __launch_bounds__(256) void k_train_reduce(const float* __restrict__ 
 // sets no flag (5)
 __global__ void k_mark_retry(const int* __restrict__ cand, const int* __restrict__ ncand,
                              const int* __restrict__ fmesh, const int* __restrict__ demote_m,
-                             const int* __restrict__ commits_m, uint8_t* __restrict__ reason) {
+                             const int* __restrict__ commits_m, uint8_t* __restrict__ reason,
+                             const int* __restrict__ gate) {
+  if (gate && *gate) return;
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= *ncand) return;
   int m = fmesh[cand[c] / 3];
@@ -574,8 +576,9 @@ void launch_mlp(hipStream_t s, const float* X, const int* n_dev, int bound, cons
 }
 
 void launch_mark_retry(hipStream_t s, const int* cand, const int* ncand, int bound, const int* fmesh,
-                       const int* demote_m, const int* commits_m, uint8_t* reason) {
-  hipLaunchKernelGGL(k_mark_retry, dim3(nblk(bound)), dim3(256), 0, s, cand, ncand, fmesh, demote_m, commits_m, reason);
+                       const int* demote_m, const int* commits_m, uint8_t* reason, const int* gate) {
+  hipLaunchKernelGGL(k_mark_retry, dim3(nblk(bound)), dim3(256), 0, s, cand, ncand, fmesh, demote_m, commits_m, reason,
+                     gate);
   PAMO_HIP(hipGetLastError());
 }
 

@@ -38,7 +38,7 @@ void launch_mlp(hipStream_t s, const float* X, const int* n_dev, int bound, cons
 // batches: reason 5 (no flag) for the candidates of meshes that set
 // candidates aside and committed nothing (their round runs again)
 void launch_mark_retry(hipStream_t s, const int* cand, const int* ncand, int bound, const int* fmesh,
-                       const int* demote_m, const int* commits_m, uint8_t* reason);
+                       const int* demote_m, const int* commits_m, uint8_t* reason, const int* gate = nullptr);
 // one batch of nb samples (rows order[base + i], or base + i when order is
 // null; rows outside [0, nrows) are left out): per-block gradient sums into
 // part [blocks][LEARN_NPARAM] and losses

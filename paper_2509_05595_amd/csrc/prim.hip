@@ -244,6 +244,7 @@ struct Seg3 {
   const int32_t* gather[3];
   int32_t* rank[3];
   int32_t* list[3];
+  int32_t* excl[3];
   int32_t* total[3];
   int64_t n[3];
   int64_t tile0[4];  // first tile of each segment; tile0[3]: all tiles
@@ -262,6 +263,7 @@ __device__ __forceinline__ void seg_load16(const Seg3& g, int k, int64_t i, int*
 }
 
 __device__ __forceinline__ void seg_store(const Seg3& g, int k, int64_t i, int prefix, int v) {
+  if (g.excl[k]) g.excl[k][i] = prefix;
   if (g.rank[k]) g.rank[k][i] = v ? prefix : -1;
   if (v && g.list[k]) g.list[k][prefix] = g.gather[k] ? g.gather[k][i] : (int32_t)i;
 }
@@ -464,6 +466,7 @@ void rank_segments(Workspace& ws, hipStream_t s, const FlagSegment* seg, int nse
       g.gather[k] = seg[k].gather;
       g.rank[k] = seg[k].rank;
       g.list[k] = seg[k].list;
+      g.excl[k] = seg[k].excl;
       g.total[k] = seg[k].total;
       g.n[k] = seg[k].n;
       tiles += (seg[k].n + TILE - 1) / TILE;
@@ -488,6 +491,7 @@ void rank_segments(Workspace& ws, hipStream_t s, const FlagSegment* seg, int nse
       one.gather[0] = g.gather[k];
       one.rank[0] = g.rank[k];
       one.list[0] = g.list[k];
+      one.excl[0] = g.excl[k];
       one.total[0] = g.total[k];
       one.n[0] = g.n[k];
       const int64_t t = (g.n[k] + TILE - 1) / TILE;
@@ -495,7 +499,8 @@ void rank_segments(Workspace& ws, hipStream_t s, const FlagSegment* seg, int nse
       if (t > LOCAL_TILES) {
         // beyond the two-pass form: the plain three-pass scans
         if (one.gather[0] || one.list[0]) throw std::runtime_error("rank_segments: list segment too large");
-        rank_flags(ws, s, one.flag[0], one.n[0], one.rank[0], one.total[0]);
+        if (one.rank[0]) rank_flags(ws, s, one.flag[0], one.n[0], one.rank[0], one.total[0]);
+        if (one.excl[0]) run_flag_scan(ws, s, one.flag[0], one.n[0], one.excl[0], one.rank[0] ? nullptr : one.total[0]);
         continue;
       }
       int32_t* ts = ws.get<int32_t>("prim.segtiles", t);

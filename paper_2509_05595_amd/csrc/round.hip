@@ -1092,18 +1092,44 @@ __global__ void k_check_reset(int nf, uint8_t* __restrict__ falive, int* __restr
 __global__ void k_mesh_tally(const int* __restrict__ cand, const int* __restrict__ ncand, const int* __restrict__ fmesh,
                              const uint8_t* __restrict__ reason_local, const uint8_t* __restrict__ reason_final,
                              const int* __restrict__ undone, int* ncand_m, int* npass_m, int* commits_m, int* hist_m,
-                             int* undo_m) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= *ncand) return;
-  int m = fmesh[cand[c] / 3];
-  if (ncand_m) atomicAdd(&ncand_m[m], 1);
-  if (reason_local && npass_m && reason_local[c] == 0) atomicAdd(&npass_m[m], 1);
-  if (reason_final) {
-    uint8_t r = reason_final[c];
-    if (commits_m && r == 0) atomicAdd(&commits_m[m], 1);
-    if (hist_m) atomicAdd(&hist_m[8 * m + (r & 7)], 1);
+                             int* undo_m, const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  // Candidates are sorted by half-edge and meshes occupy contiguous face
+  // ranges, so the lanes of a wave nearly always share one mesh: the counts
+  // are reduced per (wave, mesh) and added with one atomic each (one atomic
+  // per candidate on the same few counters serialised the kernel).
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool valid = c < *ncand;
+  const int m = valid ? fmesh[cand[c] / 3] : -1;
+  const bool pass = valid && reason_local && reason_local[c] == 0;
+  const int r = valid && reason_final ? (reason_final[c] & 7) : -1;
+  if (valid && undo_m && undone && undone[c]) atomicMax(&undo_m[m], undone[c]);  // rare
+  unsigned long long left = __ballot(valid);
+  while (left) {
+    const int leader = __ffsll((long long)left) - 1;
+    const int mm = __shfl(m, leader, 64);
+    const unsigned long long same = __ballot(valid && m == mm);
+    const int nc = __popcll(same);
+    const int np = __popcll(__ballot(pass && m == mm));
+    int hv = 0;
+    if (hist_m || commits_m) {
+      // lane k (< 8) takes the count of reason k
+#pragma unroll
+      for (int k = 0; k < 8; k++) {
+        const int ck = __popcll(__ballot(r == k && m == mm));
+        hv = lane == k ? ck : hv;
+      }
+    }
+    if (lane == leader) {
+      if (ncand_m) atomicAdd(&ncand_m[mm], nc);
+      if (npass_m && np) atomicAdd(&npass_m[mm], np);
+    }
+    const int c0 = __shfl(hv, 0, 64);
+    if (lane == leader && commits_m && reason_final && c0) atomicAdd(&commits_m[mm], c0);
+    if (hist_m && reason_final && lane < 8 && hv) atomicAdd(&hist_m[8 * mm + lane], hv);
+    left &= ~same;
   }
-  if (undo_m && undone && undone[c]) atomicMax(&undo_m[m], undone[c]);
 }
 
 // candidates sorted by (mesh, key, index): rank inside the mesh's segment
@@ -1132,7 +1158,8 @@ __global__ void k_cap_batch_keys(const int* __restrict__ ncand, const int* __res
   idx[c] = c;
 }
 
-__global__ void k_flags_clear_batch(MeshView m, const int* __restrict__ commits_m) {
+__global__ void k_flags_clear_batch(MeshView m, const int* __restrict__ commits_m, const int* __restrict__ gate) {
+  if (gate && *gate) return;
   int h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= 3 * m.nf) return;
   if (commits_m[m.fmesh[h / 3]] > 0) m.flags[h] = 0;
@@ -1164,6 +1191,24 @@ __global__ void k_batch_ids(const int* __restrict__ f_off, const int* __restrict
     }
   }
   if (i < nv) vmesh[i] = seg_of(v_off, nmesh, i);
+}
+
+// per-mesh face and vertex offsets after a compaction, from the exclusive
+// prefix counts of the surviving faces and vertices (one launch for both)
+__global__ void k_batch_offsets2(const int* __restrict__ fexcl, const int* __restrict__ ftotal, int nf,
+                                 int* __restrict__ f_off, const int* __restrict__ vexcl,
+                                 const int* __restrict__ vtotal, int nv, int* __restrict__ v_off, int nmesh,
+                                 const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= nmesh) {
+    const int o = f_off[i];
+    f_off[i] = o >= nf ? *ftotal : fexcl[o];
+  } else if (i <= 2 * nmesh + 1) {
+    const int m = i - nmesh - 1;
+    const int o = v_off[m];
+    v_off[m] = o >= nv ? *vtotal : vexcl[o];
+  }
 }
 
 __global__ void k_batch_offsets(const int* __restrict__ excl, const int* __restrict__ total, int* __restrict__ off,
@@ -1322,15 +1367,20 @@ void launch_reason_hist(hipStream_t s, const int* ncand, int cand_bound, const u
 
 void launch_compact(Workspace& ws, hipStream_t s, MeshView src, MeshView dst, const uint8_t* falive,
                     const uint8_t* valive, int* nf_new, int* nv_new, int* err, const int* gate, const int* order,
-                    int* order_out, int* nord) {
+                    int* order_out, int* nord, int* f_off, int* v_off, int nmesh) {
   int* fmap = ws.get<int>("cmp.fmap", src.nf);
   int* vmap = ws.get<int>("cmp.vmap", src.nv);
   // face ranks, vertex ranks and the surviving faces in leaf order in one
-  // scan (the order segment up to 1,024 tiles of 4,096; beyond, on its own)
+  // scan (the order segment up to 1,024 tiles of 4,096; beyond, on its own);
+  // batches also take the exclusive counts for their per-mesh offsets
   const bool fuse = order && src.nf <= 1024ll * 4096;
   FlagSegment sg[3];
   sg[0].flag = falive; sg[0].n = src.nf; sg[0].rank = fmap; sg[0].total = nf_new;
   sg[1].flag = valive; sg[1].n = src.nv; sg[1].rank = vmap; sg[1].total = nv_new;
+  if (f_off) {
+    sg[0].excl = ws.get<int>("cmp.fexcl", src.nf);
+    sg[1].excl = ws.get<int>("cmp.vexcl", src.nv);
+  }
   if (fuse) {
     sg[2].flag = falive; sg[2].gather = order; sg[2].n = src.nf; sg[2].list = order_out; sg[2].total = nord;
   }
@@ -1338,6 +1388,10 @@ void launch_compact(Workspace& ws, hipStream_t s, MeshView src, MeshView dst, co
   hipLaunchKernelGGL(k_compact, dim3(nblk(src.nf > src.nv ? src.nf : src.nv)), dim3(256), 0, s, src, dst, falive,
                      valive, (const int*)fmap, (const int*)vmap, err, gate, fuse ? order_out : nullptr,
                      (const int*)nord);
+  if (f_off)
+    hipLaunchKernelGGL(k_batch_offsets2, dim3(nblk(2 * (int64_t)nmesh + 2)), dim3(256), 0, s, (const int*)sg[0].excl,
+                       (const int*)nf_new, src.nf, f_off, (const int*)sg[1].excl, (const int*)nv_new, src.nv, v_off,
+                       nmesh, gate);
   PAMO_HIP(hipGetLastError());
   if (order && !fuse) launch_remap_order(ws, s, order, src.nf, falive, fmap, order_out, nord);
 }
@@ -1373,9 +1427,9 @@ void launch_check_reset(hipStream_t s, int nf, uint8_t* falive, int* owner, int 
 
 void launch_mesh_tally(hipStream_t s, const int* cand, const int* ncand, int bound, const int* fmesh,
                        const uint8_t* reason_local, const uint8_t* reason_final, const int* undone, int* ncand_m,
-                       int* npass_m, int* commits_m, int* hist_m, int* undo_m) {
+                       int* npass_m, int* commits_m, int* hist_m, int* undo_m, const int* gate) {
   hipLaunchKernelGGL(k_mesh_tally, dim3(nblk(bound)), dim3(256), 0, s, cand, ncand, fmesh, reason_local, reason_final,
-                     undone, ncand_m, npass_m, commits_m, hist_m, undo_m);
+                     undone, ncand_m, npass_m, commits_m, hist_m, undo_m, gate);
   PAMO_HIP(hipGetLastError());
 }
 
@@ -1396,8 +1450,8 @@ void launch_cap_batch(Workspace& ws, hipStream_t s, const int* ncand, int nc_hos
   PAMO_HIP(hipGetLastError());
 }
 
-void launch_flags_clear_batch(hipStream_t s, MeshView m, const int* commits_m) {
-  hipLaunchKernelGGL(k_flags_clear_batch, dim3(nblk(3 * (int64_t)m.nf)), dim3(256), 0, s, m, commits_m);
+void launch_flags_clear_batch(hipStream_t s, MeshView m, const int* commits_m, const int* gate) {
+  hipLaunchKernelGGL(k_flags_clear_batch, dim3(nblk(3 * (int64_t)m.nf)), dim3(256), 0, s, m, commits_m, gate);
   PAMO_HIP(hipGetLastError());
 }
 

@@ -107,9 +107,11 @@ void launch_flags_or(hipStream_t s, uint8_t* dst, const uint8_t* src, int64_t n)
 void launch_reason_hist(hipStream_t s, const int* ncand, int cand_bound, const uint8_t* reason, int* hist);
 // order (optional): a leaf order of the source faces, whose surviving faces go
 // to order_out (new ids, the count to *nord); order_out must not be order
+// (f_off, v_off, nmesh): a batch's per-mesh offsets, updated to the compacted numbering
 void launch_compact(Workspace& ws, hipStream_t s, MeshView src, MeshView dst, const uint8_t* falive,
                     const uint8_t* valive, int* nf_new, int* nv_new, int* err, const int* gate = nullptr,
-                    const int* order = nullptr, int* order_out = nullptr, int* nord = nullptr);
+                    const int* order = nullptr, int* order_out = nullptr, int* nord = nullptr, int* f_off = nullptr,
+                    int* v_off = nullptr, int nmesh = 0);
 void launch_clear_u8(hipStream_t s, uint8_t* p, int64_t n, const int* gate);
 
 // ------------------------------------------------------------ LBVH
@@ -140,14 +142,14 @@ struct Bvh {
 // final reasons, deepest undo iteration (arrays of nmesh, cleared by caller)
 void launch_mesh_tally(hipStream_t s, const int* cand, const int* ncand, int bound, const int* fmesh,
                        const uint8_t* reason_local, const uint8_t* reason_final, const int* undone, int* ncand_m,
-                       int* npass_m, int* commits_m, int* hist_m, int* undo_m);
+                       int* npass_m, int* commits_m, int* hist_m, int* undo_m, const int* gate = nullptr);
 // exact-target cap per mesh: keep the need[m] smallest keys among the passing
 // candidates of mesh m
 void launch_cap_batch(Workspace& ws, hipStream_t s, const int* ncand, int nc_host, const int* cand,
                       const int* fmesh, const uint64_t* ckey, uint8_t* reason, const int* need_m,
                       const int* ncand_m, int nmesh);
 // clear the flags of meshes that committed a collapse this round
-void launch_flags_clear_batch(hipStream_t s, MeshView m, const int* commits_m);
+void launch_flags_clear_batch(hipStream_t s, MeshView m, const int* commits_m, const int* gate = nullptr);
 // F + v_off[mesh]: local to global vertex ids (local ids outside [0, nv of
 // the mesh) raise PAMO_EBIT_INDEX); fmesh/vmesh from the offsets (nmesh + 1 each)
 void launch_batch_ids(hipStream_t s, const int* f_off, const int* v_off, int nmesh, int nf, int nv, int* F,
