@@ -945,7 +945,7 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs
   const int bound = cur.nf / 2 + 1;
   if (learned) {
     TIMED(PH_LEARN, 0);
-    launch_features(s, cur, b.key, b.cand, cnt + C_NCAND, bound, cur.ovl, b.X, cnt + C_ERR);
+    launch_features(s, cur, b.key, b.cand, cnt + C_NCAND, bound, cur.ovl, b.X, cnt + C_ERR, cur.fmesh, B.use);
     launch_mlp(s, b.X, cnt + C_NCAND, bound, c->mlp, nullptr, b.cand, cur.twin, b.key, cnt + C_NDEMOTE, cur.fmesh,
                B.d(B.demote_m()), B.use);
     launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
@@ -1520,6 +1520,9 @@ pamo_status pamo_features(pamo_ctx* c, const double* V, int64_t nv, const int32_
     if (ne > 0) {
       hipLaunchKernelGGL(k_check_index, dim3(nblk(ne)), dim3(256), 0, s, edges, ne, (int)(3 * nf), c->dcnt + C_ERR);
       check_err_bits(readback(c)[C_ERR]);
+      A.vstar = b.vstar;  // the stored stars, as in a round
+      A.vdeg = b.vdeg;
+      A.vbox = b.vbox;
       launch_quadrics(s, A, b.Q, c->dcnt + C_ERR);
       launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR, nullptr,
                      c->opt.cost_target);

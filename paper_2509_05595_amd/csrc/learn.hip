@@ -69,6 +69,57 @@ __device__ __forceinline__ double key_cost(uint64_t key) {
 
 constexpr int WALK_GUARD = 1 << 12;
 
+// normal of a face given its corners starting at the corner of slot k
+// (p = the corner in slot k, q = next, r = previous), in slot order 0, 1, 2 so
+// that it matches face_normal bit for bit
+__device__ __forceinline__ P3 rotated_normal(P3 p, P3 q, P3 r, int k) {
+  const P3 p0 = k == 0 ? p : (k == 1 ? r : q);
+  const P3 p1 = k == 0 ? q : (k == 1 ? p : r);
+  const P3 p2 = k == 0 ? r : (k == 1 ? q : p);
+  double e1x = p1.x - p0.x, e1y = p1.y - p0.y, e1z = p1.z - p0.z;
+  double e2x = p2.x - p0.x, e2y = p2.y - p0.y, e2z = p2.z - p0.z;
+  return P3{e1y * e2z - e1z * e2y, e1z * e2x - e1x * e2z, e1x * e2y - e1y * e2x};
+}
+
+// The spokes and overlap counts of the faces of one stored star (n <= VSTAR
+// half-edges g leaving v; faces holding `skip` add no overlap count): every
+// edge (v, F[next g]) with the normals of its two faces g / 3 and twin[g] / 3.
+// Every edge holding a or b is the out-edge of one of the two stars, so the
+// spokes of both stars are exactly the spoke set of the walk below; lengths,
+// cosines and overlap maxima are order-free and the overlap sum is an integer
+// sum, so the features agree bit for bit.  Fills the star's targets in x[].
+template <class Spoke, class Ovl>
+__device__ __forceinline__ void stored_star(const MeshView& m, int v, int n, int skip, P3 pv, int* x, Spoke&& spoke,
+                                            Ovl&& face_ovl) {
+  const int* __restrict__ F = m.F;
+  const int4* st4 = reinterpret_cast<const int4*>(m.vstar + (int64_t)VSTAR * v);
+  int st[VSTAR];
+#pragma unroll
+  for (int q = 0; q < VSTAR / 4; q++) {
+    const int4 w = st4[q];
+    st[4 * q] = w.x;
+    st[4 * q + 1] = w.y;
+    st[4 * q + 2] = w.z;
+    st[4 * q + 3] = w.w;
+  }
+#pragma unroll
+  for (int i = 0; i < VSTAR; i++) {
+    x[i] = -1;
+    if (i < n) {
+      const int g = st[i];
+      const int xi = F[he_next(g)], yi = F[he_prev(g)];
+      const int t = m.twin[g];  // >= 0: the quadrics kernel stored the star by walking twins
+      const int zi = F[he_prev(t)];
+      const P3 px = ld3(m.V, xi), py = ld3(m.V, yi), pz = ld3(m.V, zi);
+      const P3 n0 = rotated_normal(pv, px, py, g % 3);
+      const P3 n1 = rotated_normal(px, pv, pz, t % 3);  // twin face: x -> v -> z
+      spoke(seg_len(pv, px), normal_cos(n0, n1));
+      if (xi != skip && yi != skip) face_ovl(g / 3);
+      x[i] = xi;
+    }
+  }
+}
+
 // Features of candidate edge h = (a, b); S = star(a) u star(b), spokes = the
 // edges of S's faces that contain a or b:
 //   0 plog2(cost)   1 plog2(length)   2 length / longest spoke   3 shortest spoke / length
@@ -76,16 +127,54 @@ constexpr int WALK_GUARD = 1 << 12;
 //   6 valence of a   7 valence of b   8 common neighbours   9 sum of ovl over S   10 largest ovl
 __global__ __launch_bounds__(256) void k_features(MeshView m, const uint64_t* __restrict__ key,
                                                   const int* __restrict__ cand, const int* __restrict__ ncand,
-                                                  const int* __restrict__ ovl, float* __restrict__ X, int* err) {
+                                                  const int* __restrict__ ovl, float* __restrict__ X, int* err,
+                                                  const int* __restrict__ fmesh, const uint8_t* __restrict__ use_m) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= *ncand) return;
   const int h = cand[c];
+  if (fmesh && use_m && !use_m[fmesh[h / 3]]) {  // its mesh does not consult the network this round
+    float4* x = reinterpret_cast<float4*>(X + (int64_t)c * LEARN_NFEAT);
+#pragma unroll
+    for (int k = 0; k < LEARN_NFEAT / 4; k++) x[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    return;
+  }
   const int* __restrict__ F = m.F;
   const int* __restrict__ tw = m.twin;
   const int a = F[h], b = F[he_next(h)];
   const double le = seg_len(ld3(m.V, a), ld3(m.V, b));
   double lmax = 0.0, lmin = INFINITY, cmin = INFINITY;
   int64_t osum = 0, omax = 0;
+  const int hb = tw[h];
+  int vala = 0, valb = 0, common = 0;
+  bool stored = false;
+  if (m.vstar) {
+    vala = m.vdeg[a];
+    valb = m.vdeg[b];
+    stored = vala <= VSTAR && valb <= VSTAR;
+  }
+  if (stored) {
+    auto spoke = [&](double l, double cs) {
+      lmax = l > lmax ? l : lmax;
+      lmin = l < lmin ? l : lmin;
+      cmin = cs < cmin ? cs : cmin;
+    };
+    auto face_ovl = [&](int f) {
+      int64_t o = ovl ? ovl[f] : 0;
+      osum += o;
+      omax = o > omax ? o : omax;
+    };
+    int xa[VSTAR], xb[VSTAR];
+    const P3 pa = ld3(m.V, a), pb = ld3(m.V, b);
+    stored_star(m, a, vala, -1, pa, xa, spoke, face_ovl);
+    stored_star(m, b, valb, a, pb, xb, spoke, face_ovl);
+#pragma unroll
+    for (int j = 0; j < VSTAR; j++) {
+      bool hit = false;
+#pragma unroll
+      for (int i = 0; i < VSTAR; i++) hit |= xa[i] == xb[j];
+      common += xb[j] >= 0 && xb[j] != a && hit;
+    }
+  } else {
   auto spoke = [&](int hh) {
     double l = seg_len(ld3(m.V, F[hh]), ld3(m.V, F[he_next(hh)]));
     lmax = l > lmax ? l : lmax;
@@ -99,7 +188,8 @@ __global__ __launch_bounds__(256) void k_features(MeshView m, const uint64_t* __
     omax = o > omax ? o : omax;
   };
   // star(a): every face once; all three edges of the two faces holding b
-  int vala = 0, g = h, guard = 0;
+  vala = 0;
+  int g = h, guard = 0;
   do {
     vala++;
     spoke(g);
@@ -110,8 +200,7 @@ __global__ __launch_bounds__(256) void k_features(MeshView m, const uint64_t* __
     g = tw[he_prev(g)];
   } while (g != h && g >= 0 && ++guard < WALK_GUARD);
   // star(b) without those two faces
-  int valb = 0;
-  const int hb = tw[h];
+  valb = 0;
   g = hb;
   guard = 0;
   do {
@@ -125,7 +214,6 @@ __global__ __launch_bounds__(256) void k_features(MeshView m, const uint64_t* __
     g = tw[he_prev(g)];
   } while (g != hb && g >= 0 && ++guard < WALK_GUARD);
   // common neighbours
-  int common = 0;
   g = hb;
   guard = 0;
   do {
@@ -143,6 +231,7 @@ __global__ __launch_bounds__(256) void k_features(MeshView m, const uint64_t* __
     g = tw[he_prev(g)];
   } while (g != hb && g >= 0 && ++guard < WALK_GUARD);
   if (guard >= WALK_GUARD || g < 0) atomicOr(err, PAMO_EBIT_RING);
+  }
   double f[LEARN_NF_USED];
   f[0] = plog2(key_cost(key[h]));
   f[1] = plog2(le);
@@ -558,8 +647,8 @@ __global__ __launch_bounds__(HT) void k_point_surface(const double* __restrict__
 
 // ============================================================ host wrappers
 void launch_features(hipStream_t s, MeshView m, const uint64_t* key, const int* cand, const int* ncand, int bound,
-                     const int* ovl, float* X, int* err) {
-  hipLaunchKernelGGL(k_features, dim3(nblk(bound)), dim3(256), 0, s, m, key, cand, ncand, ovl, X, err);
+                     const int* ovl, float* X, int* err, const int* fmesh, const uint8_t* use_m) {
+  hipLaunchKernelGGL(k_features, dim3(nblk(bound)), dim3(256), 0, s, m, key, cand, ncand, ovl, X, err, fmesh, use_m);
   PAMO_HIP(hipGetLastError());
 }
 

@@ -25,9 +25,11 @@ struct MlpMeta {
   int e1, e2, e3, a1, a2;
 };
 
-// features of cand[0..*ncand) (bound >= *ncand sizes the grid) into X [n][32]
+// features of cand[0..*ncand) (bound >= *ncand sizes the grid) into X [n][32];
+// with fmesh and use_m set, the rows of meshes with use_m[mesh] == 0 are zero
 void launch_features(hipStream_t s, MeshView m, const uint64_t* key, const int* cand, const int* ncand, int bound,
-                     const int* ovl, float* X, int* err);
+                     const int* ovl, float* X, int* err, const int* fmesh = nullptr,
+                     const uint8_t* use_m = nullptr);
 // logits of X[0..*n_dev) into out (may be null); with key non-null, rows under
 // the threshold set their edge cand[row] aside (largest key on both
 // half-edges) and count into *ndemote (and ndemote_m[mesh] when fmesh is set;

@@ -329,6 +329,20 @@ def csaszar_torus():
     return _pack(normalize_unit_cube(v), np.asarray(faces))
 
 
+def bipyramid(n: int = 24, seed: int = 3, jitter: float = 0.05):
+    """Two poles of valence n over a jittered ring of n vertices (valence 4):
+    a closed mesh whose pole edges have stars beyond a small fixed bound."""
+    rng = np.random.default_rng(seed)
+    t = 2 * np.pi * (np.arange(n) + jitter * rng.standard_normal(n)) / n
+    r = 1.0 + jitter * rng.standard_normal(n)
+    ring = np.stack([r * np.cos(t), r * np.sin(t), jitter * rng.standard_normal(n)], 1)
+    v = np.concatenate([ring, [[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]]])
+    i = np.arange(n)
+    top = np.stack([np.full(n, n), i, (i + 1) % n], 1)
+    bot = np.stack([np.full(n, n + 1), (i + 1) % n, i], 1)
+    return _pack(normalize_unit_cube(v), np.concatenate([top, bot]))
+
+
 def nested_spheres(k: int = 3, gap: float = 0.01, seed: int = 9, sigma: float = 0.002):
     """Two concentric bumpy icospheres (radii 1 and 1 - gap) as one closed
     two-component mesh.  Collapses on the outer sphere cut chords inward, so

@@ -80,6 +80,19 @@ def test_features_and_overlap_counts_bitwise(ctx, name):
     assert np.array_equal(X.cpu().numpy(), Xo)
 
 
+@pytest.mark.parametrize("n", [16, 17, 24])
+def test_features_of_every_edge_around_high_valence_poles(ctx, n):
+    # pole stars of 16 faces fit the stored stars, larger ones go to the walk
+    V, F = g.bipyramid(n)
+    # every edge once, by its half-edge of the lower id (the one carrying the key)
+    he = {(int(F[h // 3, h % 3]), int(F[h // 3, (h % 3 + 1) % 3])): h for h in range(3 * len(F))}
+    edges = np.array([h for (a, b), h in he.items() if h < he[(b, a)]], dtype=np.int32)
+    Xo, _ = orc.features(V, F, edges)
+    Vd, Fd = dev(V, F)
+    X, _ = ctx.features(Vd, Fd, torch.from_numpy(edges))
+    assert np.array_equal(X.cpu().numpy(), Xo)
+
+
 def test_mlp_logits_bitwise(ctx):
     rng = np.random.default_rng(5)
     X = rng.integers(-127, 128, (1000, 32)).astype(np.float32)  # ragged: not a multiple of 16 rows
