@@ -230,6 +230,7 @@ struct RoundBufs {
   double* vbox;
   int* ovl_new;  // learned proposal: overlap counts measured this round (null when not tracked)
   float* X;      // learned proposal: features of this round's candidates (null when unused)
+  int* dlist;    // learned proposal: the edges the network set aside this round
 };
 
 // one query pass (traversal + pair predicate + exact resolve); grows the
@@ -325,6 +326,7 @@ RoundBufs round_bufs(pamo_ctx* c, int64_t nv, int64_t nf) {
   b.vbox = w.get<double>("r.vbox", 6 * nv);
   b.ovl_new = nullptr;
   b.X = nullptr;
+  b.dlist = nullptr;
   return b;
 }
 
@@ -593,8 +595,10 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
     TIMED(PH_LEARN, 0);
     launch_features(s, cur, b.key, b.cand, cnt + C_NCAND, bound, cur.ovl, b.X, cnt + C_ERR);
     if (learned) {
-      launch_mlp(s, b.X, cnt + C_NCAND, bound, c->mlp, nullptr, b.cand, cur.twin, b.key, cnt + C_NDEMOTE);
-      launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);  // without the set-aside edges
+      launch_mlp(s, b.X, cnt + C_NCAND, bound, c->mlp, nullptr, b.cand, cur.twin, b.key, cnt + C_NDEMOTE, nullptr,
+                 nullptr, nullptr, b.dlist);
+      launch_reselect(c->ws, s, cur, b.key, b.vmin, b.dlist, cnt + C_NDEMOTE, bound, b.cand,
+                      cnt + C_NCAND);  // without the set-aside edges
     }
   }
   local_checks(c, cur, b, b.cand, cnt + C_NCAND, bound, b.reason, b.vbar);
@@ -947,8 +951,8 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs
     TIMED(PH_LEARN, 0);
     launch_features(s, cur, b.key, b.cand, cnt + C_NCAND, bound, cur.ovl, b.X, cnt + C_ERR, cur.fmesh, B.use);
     launch_mlp(s, b.X, cnt + C_NCAND, bound, c->mlp, nullptr, b.cand, cur.twin, b.key, cnt + C_NDEMOTE, cur.fmesh,
-               B.d(B.demote_m()), B.use);
-    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
+               B.d(B.demote_m()), B.use, b.dlist);
+    launch_reselect(c->ws, s, cur, b.key, b.vmin, b.dlist, cnt + C_NDEMOTE, bound, b.cand, cnt + C_NCAND);
   }
   local_checks(c, cur, b, b.cand, cnt + C_NCAND, bound, b.reason, b.vbar);
   launch_mesh_tally(s, b.cand, cnt + C_NCAND, bound, cur.fmesh, b.reason, nullptr, nullptr, B.d(B.ncand_m()),
@@ -1054,6 +1058,7 @@ pamo_status simplify_run(pamo_ctx* c, const double* V, int64_t nv, const int32_t
     alt.ovl = c->ws.get<int>("mB.ovl", nf);
     b.ovl_new = c->ws.get<int>("r.ovl_new", nf);
     b.X = c->ws.get<float>("r.X", (nf / 2 + 1) * (int64_t)LEARN_NFEAT);
+    b.dlist = c->ws.get<int>("r.dlist", nf / 2 + 1);
     int2* dummy = c->ws.get<int2>("w.pairs", 1);
     whole_mesh_pairs(c, cur, dummy, 0, 1, cur.ovl);
   }
@@ -1358,6 +1363,7 @@ pamo_status pamo_simplify_batch(pamo_ctx* c, int32_t nmesh, const double* V, con
       alt.ovl = c->ws.get<int>("mB.ovl", nf);
       b.ovl_new = c->ws.get<int>("r.ovl_new", nf);
       b.X = c->ws.get<float>("r.X", (nf / 2 + 1) * (int64_t)LEARN_NFEAT);
+      b.dlist = c->ws.get<int>("r.dlist", nf / 2 + 1);
       int2* dummy = c->ws.get<int2>("w.pairs", 1);
       whole_mesh_pairs(c, cur, dummy, 0, nmesh, cur.ovl);
     }

@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void k_mlp(const float* __restrict__ X, const 
                                              const int* __restrict__ cand, const int* __restrict__ twin,
                                              uint64_t* __restrict__ key, int* __restrict__ ndemote,
                                              const int* __restrict__ fmesh, int* __restrict__ ndemote_m,
-                                             const uint8_t* __restrict__ use_m) {
+                                             const uint8_t* __restrict__ use_m, int* __restrict__ dlist) {
   __shared__ __bf16 sh[4][16][64 + 8];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int row = l & 15, kg = l >> 4;
@@ -339,7 +339,8 @@ __global__ __launch_bounds__(256) void k_mlp(const float* __restrict__ X, const 
       if (key && z < thr && !(fmesh && use_m && !use_m[fmesh[h / 3]])) {
         key[h] = PAMO_KEY_MAX;
         key[twin[h]] = PAMO_KEY_MAX;
-        atomicAdd(ndemote, 1);
+        const int slot = atomicAdd(ndemote, 1);
+        if (dlist) dlist[slot] = h;
         if (fmesh) atomicAdd(&ndemote_m[fmesh[h / 3]], 1);
       }
     }
@@ -654,13 +655,13 @@ void launch_features(hipStream_t s, MeshView m, const uint64_t* key, const int* 
 
 void launch_mlp(hipStream_t s, const float* X, const int* n_dev, int bound, const MlpDev* M, float* out,
                 const int* cand, const int* twin, uint64_t* key, int* ndemote, const int* fmesh, int* ndemote_m,
-                const uint8_t* use_m) {
+                const uint8_t* use_m, int* dlist) {
   int64_t tiles = (bound + 15) / 16;
   int64_t blocks = (tiles + 3) / 4;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_mlp, dim3((unsigned)blocks), dim3(256), 0, s, X, n_dev, M, out, cand, twin, key, ndemote,
-                     fmesh, ndemote_m, use_m);
+                     fmesh, ndemote_m, use_m, dlist);
   PAMO_HIP(hipGetLastError());
 }
 

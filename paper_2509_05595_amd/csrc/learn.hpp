@@ -33,10 +33,11 @@ void launch_features(hipStream_t s, MeshView m, const uint64_t* key, const int* 
 // logits of X[0..*n_dev) into out (may be null); with key non-null, rows under
 // the threshold set their edge cand[row] aside (largest key on both
 // half-edges) and count into *ndemote (and ndemote_m[mesh] when fmesh is set;
-// then only meshes with use_m[mesh] set candidates aside)
+// then only meshes with use_m[mesh] set candidates aside); with dlist set,
+// the set-aside half-edges go to dlist[0..*ndemote) in no particular order
 void launch_mlp(hipStream_t s, const float* X, const int* n_dev, int bound, const MlpDev* M, float* out,
                 const int* cand, const int* twin, uint64_t* key, int* ndemote, const int* fmesh = nullptr,
-                int* ndemote_m = nullptr, const uint8_t* use_m = nullptr);
+                int* ndemote_m = nullptr, const uint8_t* use_m = nullptr, int* dlist = nullptr);
 // batches: reason 5 (no flag) for the candidates of meshes that set
 // candidates aside and committed nothing (their round runs again)
 void launch_mark_retry(hipStream_t s, const int* cand, const int* ncand, int bound, const int* fmesh,

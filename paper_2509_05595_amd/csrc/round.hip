@@ -525,10 +525,8 @@ __global__ __launch_bounds__(256) void k_vertex_min(MeshView m, const uint64_t* 
 
 // e = (a, b) is chosen iff its key is the minimum over the vertex minima of
 // {a, b} u N(a) u N(b), i.e. no edge sharing a ring triangle has a smaller key
-__global__ __launch_bounds__(256) void k_select(MeshView m, const uint64_t* __restrict__ key,
-                                                const uint64_t* __restrict__ vmin, uint8_t* __restrict__ sel) {
-  int h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= 3 * m.nf) return;
+__device__ __forceinline__ uint8_t select_edge(const MeshView& m, const uint64_t* __restrict__ key,
+                                               const uint64_t* __restrict__ vmin, int h) {
   uint8_t ok = 0;
   uint64_t k = key[h];
   if (k != PAMO_KEY_MAX && h < m.twin[h]) {
@@ -562,7 +560,106 @@ __global__ __launch_bounds__(256) void k_select(MeshView m, const uint64_t* __re
       ok = local_min;
     }
   }
-  sel[h] = ok;
+  return ok;
+}
+
+__global__ __launch_bounds__(256) void k_select(MeshView m, const uint64_t* __restrict__ key,
+                                                const uint64_t* __restrict__ vmin, uint8_t* __restrict__ sel) {
+  int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= 3 * m.nf) return;
+  sel[h] = select_edge(m, key, vmin, h);
+}
+
+// Re-selection after candidates were set aside (both half-edges of each got
+// the largest key).  A set-aside edge (a, b) changes only the vertex minima
+// of a and b, so a selection changes only for edges with an endpoint u in
+// {a, b} u N(a) u N(b), and such an edge can be chosen only if its key is
+// vmin[u]: each such u has one edge to evaluate again, the one holding its
+// minimum.  Every other edge keeps its flag of the selection before
+// (candidates' closed neighbourhoods hold no endpoint of another candidate,
+// so no two set-aside edges share a vertex either).  Work items run
+// grid-stride over the list of set-aside edges: two per edge for the minima,
+// 2 + 2 VSTAR per edge for the re-evaluation (its two ends, then the far end
+// of each stored half-edge leaving them; the ends of larger stars walk their
+// neighbours themselves).
+__global__ __launch_bounds__(256) void k_demoted_vmin(MeshView m, const uint64_t* __restrict__ key,
+                                                      const int* __restrict__ dlist, const int* __restrict__ nd,
+                                                      uint64_t* __restrict__ vmin, uint8_t* __restrict__ sel) {
+  const int64_t n = 2 * (int64_t)*nd;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int h = dlist[i >> 1];
+    const int v = (i & 1) ? m.F[he_next(h)] : m.F[h];
+    if (!(i & 1)) sel[h] = 0;
+    uint64_t best = PAMO_KEY_MAX;
+    const int deg = m.vdeg[v];
+    if (deg <= VSTAR) {
+      int g[VSTAR];
+      star_all(m, v, deg, g);
+      uint64_t k[VSTAR];
+#pragma unroll
+      for (int q = 0; q < VSTAR; q++) k[q] = key[g[q]];
+#pragma unroll
+      for (int q = 0; q < VSTAR; q++) best = k[q] < best ? k[q] : best;
+    } else {
+      walk_star(m.twin, m.vh[v], [&](int g) {
+        const uint64_t k = key[g];
+        best = k < best ? k : best;
+      });
+    }
+    vmin[v] = best;
+  }
+}
+
+constexpr int RESEL_ITEMS = 2 + 2 * VSTAR;
+
+// the edge (by its lower half-edge) holding the minimum vmin[u] of u's
+// star, or -1 when every edge at u has the largest key
+__device__ __forceinline__ int min_edge(const MeshView& m, const uint64_t* __restrict__ key,
+                                        const uint64_t* __restrict__ vmin, int u) {
+  const uint64_t want = vmin[u];
+  if (want == PAMO_KEY_MAX) return -1;
+  int found = -1;
+  const int deg = m.vdeg[u];
+  if (deg <= VSTAR) {
+    int g[VSTAR];
+    star_all(m, u, deg, g);
+    uint64_t k[VSTAR];
+#pragma unroll
+    for (int q = 0; q < VSTAR; q++) k[q] = key[g[q]];
+#pragma unroll
+    for (int q = 0; q < VSTAR; q++) found = k[q] == want ? g[q] : found;
+  } else {
+    walk_star(m.twin, m.vh[u], [&](int g) {
+      if (key[g] == want) found = g;
+    });
+  }
+  if (found < 0) return -1;
+  const int t = m.twin[found];
+  return t < found ? t : found;
+}
+
+__global__ __launch_bounds__(256) void k_reselect(MeshView m, const uint64_t* __restrict__ key,
+                                                  const int* __restrict__ dlist, const int* __restrict__ nd,
+                                                  const uint64_t* __restrict__ vmin, uint8_t* __restrict__ sel) {
+  const int64_t n = RESEL_ITEMS * (int64_t)*nd;
+  auto again = [&](int u) {
+    const int e = min_edge(m, key, vmin, u);
+    if (e >= 0) sel[e] = select_edge(m, key, vmin, e);
+  };
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int h = dlist[i / RESEL_ITEMS];
+    const int j = (int)(i % RESEL_ITEMS);
+    const int end = j < 2 ? j : (j - 2) / VSTAR;  // 0: a, 1: b
+    const int v = end ? m.F[he_next(h)] : m.F[h];
+    const int deg = m.vdeg[v];
+    if (j < 2) {
+      again(v);
+      if (deg > VSTAR) walk_star(m.twin, m.vh[v], [&](int g) { again(dest(m.F, g)); });
+    } else {
+      const int slot = (j - 2) % VSTAR;
+      if (deg <= VSTAR && slot < deg) again(dest(m.F, m.vstar[(int64_t)VSTAR * v + slot]));
+    }
+  }
 }
 
 // ------------------------------------------------------------ local checks
@@ -1288,6 +1385,18 @@ void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key
   uint8_t* sel = ws.get<uint8_t>("sel", nh);
   if (!vmin_ready) hipLaunchKernelGGL(k_vertex_min, dim3(nblk(m.nv)), dim3(256), 0, s, m, key, vmin);
   hipLaunchKernelGGL(k_select, dim3(nblk(nh)), dim3(256), 0, s, m, key, (const uint64_t*)vmin, sel);
+  compact_flags(ws, s, sel, nh, cand, ncand);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_reselect(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, const int* dlist,
+                     const int* nd, int bound, int* cand, int* ncand) {
+  int64_t nh = 3 * (int64_t)m.nf;
+  uint8_t* sel = ws.get<uint8_t>("sel", nh);  // the flags of the selection before
+  const unsigned g1 = std::min(nblk(2 * (int64_t)bound), 1024u);
+  const unsigned g2 = std::min(nblk(RESEL_ITEMS * (int64_t)bound), 2048u);
+  hipLaunchKernelGGL(k_demoted_vmin, dim3(g1), dim3(256), 0, s, m, key, dlist, nd, vmin, sel);
+  hipLaunchKernelGGL(k_reselect, dim3(g2), dim3(256), 0, s, m, key, dlist, nd, (const uint64_t*)vmin, sel);
   compact_flags(ws, s, sel, nh, cand, ncand);
   PAMO_HIP(hipGetLastError());
 }

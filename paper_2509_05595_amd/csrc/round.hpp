@@ -59,6 +59,12 @@ void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, do
 // folded them in), so only the selection and its compaction run
 void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, int* cand,
                    int* ncand, bool vmin_ready = false);
+// the selection again after the candidates dlist[0..*nd) (*nd <= bound) got
+// the largest key on both half-edges: into cand / ncand the same candidates as
+// a full launch_select, from the flags and vertex minima of the selection
+// before (m needs the stored stars of this round)
+void launch_reselect(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, const int* dlist,
+                     const int* nd, int bound, int* cand, int* ncand);
 void launch_local_check(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const int* cand,
                         const int* ncand, int cand_bound, const uint64_t* key, uint8_t* reason, double* vbar,
                         uint64_t* ckey, int* err, int* hist);
