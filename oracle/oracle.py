@@ -38,7 +38,7 @@ def build(force: bool = True) -> str:
 
 class Opts(C.Structure):
     _fields_ = [("w_e", C.c_double), ("w_s", C.c_double), ("tolerance", C.c_int32),
-                ("max_rounds", C.c_int32), ("cost_target", C.c_double)]
+                ("max_rounds", C.c_int32), ("cost_target", C.c_double), ("prefilter", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -90,7 +90,7 @@ def lib():
         L.oracle_quadrics.argtypes = [P, I64, P, I64, P]
         L.oracle_keys.argtypes = [P, I64, P, I64, P, C.c_double, C.c_double, P]
         L.oracle_select.argtypes = [P, I64, P, I64, P, C.c_double, C.c_double, P, P]
-        L.oracle_check.argtypes = [P, I64, P, I64, P, C.c_double, C.c_double, I64, P, P, P, P, P]
+        L.oracle_check.argtypes = [P, I64, P, I64, P, C.c_double, C.c_double, I64, C.c_int32, P, P, P, P, P]
         L.oracle_run.argtypes = [P, I64, P, I64, P, C.c_int32, I64, P, P, P, P, P, P, P, P, P, I64]
         L.oracle_tri_pair.argtypes = [P, P, P, P]
         L.oracle_degenerate.argtypes = [P]
@@ -170,8 +170,8 @@ def select(V, F, flags=None, w_e=W_E, w_s=W_S):
     return cand[: n[0]].copy()
 
 
-def check(V, F, target, flags=None, w_e=W_E, w_s=W_S):
-    """One round up to the end of the check/undo loop.
+def check(V, F, target, flags=None, w_e=W_E, w_s=W_S, prefilter=0):
+    """One round up to the end of the check/undo loop (prefilter: as in run).
     Returns (cand, vbar (n,3), reason (n,), undo_iterations)."""
     V, F = _mesh(V, F)
     cap = 3 * len(F) + 1
@@ -181,7 +181,7 @@ def check(V, F, target, flags=None, w_e=W_E, w_s=W_S):
     n = np.zeros(1, dtype=np.int64)
     it = np.zeros(1, dtype=np.int64)
     rc = lib().oracle_check(_p(V), len(V), _p(F), len(F), _p(_flags(flags, len(F))), w_e, w_s,
-                            int(target), _p(cand), _p(n), _p(vbar), _p(reason), _p(it))
+                            int(target), int(prefilter), _p(cand), _p(n), _p(vbar), _p(reason), _p(it))
     if rc:
         raise ValueError(f"oracle_check: {rc}")
     k = n[0]
@@ -189,10 +189,12 @@ def check(V, F, target, flags=None, w_e=W_E, w_s=W_S):
 
 
 def run(V, F, target, flags=None, streak=0, max_rounds=-1, w_e=W_E, w_s=W_S,
-        tolerance=TOLERANCE, log_rounds=0, cost_target=0.0):
+        tolerance=TOLERANCE, log_rounds=0, cost_target=0.0, prefilter=0):
     """Whole method.  Returns dict with V, F, flags, streak, stats, log.
     cost_target > 0: only edges costing at most this collapse, and a round that
-    selects nothing ends the run (the paper's target-cost termination)."""
+    selects nothing ends the run (the paper's target-cost termination).
+    prefilter: the link and flip checks run on every keyed edge before the
+    selection, and failing edges are not selectable that round."""
     V, F = _mesh(V, F)
     Vo = np.zeros_like(V)
     Fo = np.zeros_like(F)
@@ -201,7 +203,7 @@ def run(V, F, target, flags=None, streak=0, max_rounds=-1, w_e=W_E, w_s=W_S,
     nfo = np.zeros(1, dtype=np.int64)
     so = np.zeros(1, dtype=np.int32)
     st = Stats()
-    opt = Opts(w_e, w_s, tolerance, max_rounds, cost_target)
+    opt = Opts(w_e, w_s, tolerance, max_rounds, cost_target, int(prefilter))
     LogArr = RoundLog * max(1, log_rounds)
     log = LogArr()
     rc = lib().oracle_run(_p(V), len(V), _p(F), len(F), _p(_flags(flags, len(F))), int(streak),
@@ -315,7 +317,7 @@ def mlp_logits(model, X):
     return out
 
 
-def run_learned(V, F, target, model, max_rounds=-1, w_e=W_E, w_s=W_S, tolerance=TOLERANCE):
+def run_learned(V, F, target, model, max_rounds=-1, w_e=W_E, w_s=W_S, tolerance=TOLERANCE, prefilter=0):
     """The method with the learned proposal.  Returns dict with V, F, stats,
     demoted (candidates set aside) and fallbacks (rounds run again plain)."""
     V, F = _mesh(V, F)
@@ -323,7 +325,7 @@ def run_learned(V, F, target, model, max_rounds=-1, w_e=W_E, w_s=W_S, tolerance=
     nvo, nfo = np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64)
     info = np.zeros(2, dtype=np.int64)
     st = Stats()
-    opt = Opts(w_e, w_s, tolerance, max_rounds)
+    opt = Opts(w_e, w_s, tolerance, max_rounds, 0.0, int(prefilter))
     m = mlp_struct(model)
     rc = lib().oracle_run_learned(_p(V), len(V), _p(F), len(F), int(target), C.byref(opt), C.byref(m), _p(Vo),
                                   _p(nvo), _p(Fo), _p(nfo), C.byref(st), _p(info))

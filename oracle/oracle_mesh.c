@@ -60,6 +60,11 @@ typedef struct {
     double cost_target; /* > 0: collapse only edges whose cost is at most this; the run
                            also ends when a round selects no edge (the target-cost
                            termination the paper offers besides the face count) */
+    int32_t prefilter;  /* 1: the link and flip checks (R7) run on every keyed edge before
+                           the selection, and failing edges get no key this round, so
+                           they do not hold back their neighbourhood (the other order of
+                           selection and local checks; the paper applies the link
+                           condition during the collapse, Sec. 5.1) */
 } oracle_opts;
 
 typedef struct {
@@ -889,6 +894,18 @@ static int run_round(omesh *m, int64_t target_eff, const oracle_opts *opt, round
     compute_quadrics(m);
     compute_keys_capped(m, opt->w_e, opt->w_s, opt->cost_target);
     int64_t nf = m->nf, nv = m->nv;
+    if (opt->prefilter) {
+        /* R7 on every keyed edge, on the pre-round mesh: a failing edge is
+           not selectable this round (and is not flagged: it was never a
+           candidate) */
+        double vb[3];
+        for (int64_t h = 0; h < 3 * nf; h++) {
+            if (m->key[h] == KEY_MAX) continue;
+            int32_t a = m->F[h], b = m->F[3 * (h / 3) + (h % 3 + 1) % 3];
+            (void)edge_cost(m, a, b, opt->w_e, opt->w_s, vb);
+            if (local_check(m, a, b, vb) != 0) m->key[h] = KEY_MAX;
+        }
+    }
 
     int32_t *cand = xalloc(sizeof(int32_t) * (size_t)(3 * nf + 1));
     int64_t nc = select_edges(m, cand);
@@ -1156,13 +1173,13 @@ int oracle_select(const double *V, int64_t nv, const int32_t *F, int64_t nf, con
  * placements and their outcome (0 kept, 1 link, 2 flip/degenerate,
  * 3 intersection, 4 capped by the face target) */
 int oracle_check(const double *V, int64_t nv, const int32_t *F, int64_t nf, const uint8_t *flags,
-                 double w_e, double w_s, int64_t target, int32_t *cand, int64_t *ncand,
+                 double w_e, double w_s, int64_t target, int32_t prefilter, int32_t *cand, int64_t *ncand,
                  double *vbar, uint8_t *reason, int64_t *undo_iters) {
     if (check_input(F, nf, nv)) return -1;
     omesh m;
     mesh_init(&m, V, nv, F, nf);
     if (flags) memcpy(m.flags, flags, (size_t)(3 * nf));
-    oracle_opts o = {w_e, w_s, 4, -1, 0.0};
+    oracle_opts o = {w_e, w_s, 4, -1, 0.0, prefilter};
     round_out r;
     int err = run_round(&m, target - (target % 2), &o, &r, 1, NULL, NULL);
     if (!err) {
