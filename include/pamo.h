@@ -66,6 +66,12 @@ typedef struct {
                            most this are collapsed, and a round that selects no edge ends the run with
                            PAMO_OK (the face target still applies; pass 0 faces for cost alone).
                            <= 0: off (default) */
+  int32_t prefilter;    /* 1: the local checks (link condition, degenerate or flipped generated triangles;
+                           Sec. 5.1 applies the link condition during the collapse) run on every keyed edge
+                           before the selection, and an edge failing them gets no key that round, so it does
+                           not hold back its neighbourhood (the other order of selection and local checks);
+                           0: checks on the selected candidates only (default).  Applies to pamo_simplify
+                           and pamo_simplify_batch */
 } pamo_options;
 
 typedef struct {

@@ -588,7 +588,9 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
   }
   {
     TIMED(PH_SELECT, 20 * nv + 93 * nf);
-    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, true);
+    const bool pre = c->opt.prefilter != 0;
+    if (pre) launch_prefilter(s, cur, b.Q, c->opt.w_e, c->opt.w_s, b.key, cnt + C_ERR);
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, !pre);
   }
   const int bound = cur.nf / 2 + 1;
   if (learned || logging) {
@@ -944,7 +946,9 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs
   }
   {
     TIMED(PH_SELECT, 20 * nv + 93 * nf);
-    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, true);
+    const bool pre = c->opt.prefilter != 0;
+    if (pre) launch_prefilter(s, cur, b.Q, c->opt.w_e, c->opt.w_s, b.key, cnt + C_ERR);
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, !pre);
   }
   const int bound = cur.nf / 2 + 1;
   if (learned) {

@@ -727,17 +727,11 @@ __device__ __forceinline__ bool link_ok_stars(const MeshView& m, int a, int na, 
   return common == 2 && !(na == 3 && nb == 3);
 }
 
-__global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* __restrict__ Q, double w_e,
-                                                     double w_s, const int* __restrict__ cand,
-                                                     const int* __restrict__ ncand, const uint64_t* __restrict__ key,
-                                                     uint8_t* __restrict__ reason, double* __restrict__ vbar_out,
-                                                     uint64_t* __restrict__ ckey, int* err, int* __restrict__ hist) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= *ncand) return;
-  int h = cand[c];
-  ckey[c] = key[h];
+// R7 for the edge of h: 0 passes, 1 link condition, 2 a generated triangle
+// degenerate or flipped; vbar gets the placement (when the link holds)
+__device__ __forceinline__ uint8_t local_reason(const MeshView& m, const double* __restrict__ Q, double w_e,
+                                                double w_s, int h, P3& vbar, int* err) {
   uint8_t rs = 0;
-  P3 vbar{0, 0, 0};
   int na = 0, nb = 0;
   const int a0 = m.F[h], b0 = m.F[he_next(h)];
   const bool fast = stars_stored(m, a0, b0, na, nb);
@@ -805,11 +799,41 @@ __global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* _
     }
     if (bad) rs = 2;
   }
+  return rs;
+}
+
+__global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* __restrict__ Q, double w_e,
+                                                     double w_s, const int* __restrict__ cand,
+                                                     const int* __restrict__ ncand, const uint64_t* __restrict__ key,
+                                                     uint8_t* __restrict__ reason, double* __restrict__ vbar_out,
+                                                     uint64_t* __restrict__ ckey, int* err, int* __restrict__ hist) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= *ncand) return;
+  int h = cand[c];
+  ckey[c] = key[h];
+  P3 vbar{0, 0, 0};
+  const uint8_t rs = local_reason(m, Q, w_e, w_s, h, vbar, err);
   reason[c] = rs;
   vbar_out[3 * (int64_t)c] = vbar.x;
   vbar_out[3 * (int64_t)c + 1] = vbar.y;
   vbar_out[3 * (int64_t)c + 2] = vbar.z;
   wave_hist(rs, hist);
+}
+
+// Pre-filter: R7 on every keyed edge (by its lower half-edge) before the
+// selection; a failing edge gets the largest key on both half-edges, so it is
+// neither chosen nor holds back its neighbourhood this round
+__global__ __launch_bounds__(256) void k_prefilter(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
+                                                   uint64_t* __restrict__ key, int* err) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= 3 * m.nf) return;
+  const int t = m.twin[h];
+  if (!(h < t) || key[h] == PAMO_KEY_MAX) return;
+  P3 vbar{0, 0, 0};
+  if (local_reason(m, Q, w_e, w_s, h, vbar, err) != 0) {
+    key[h] = PAMO_KEY_MAX;
+    key[t] = PAMO_KEY_MAX;
+  }
 }
 
 // candidates passing the local checks whose key exceeds the threshold are
@@ -1398,6 +1422,11 @@ void launch_reselect(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* k
   hipLaunchKernelGGL(k_demoted_vmin, dim3(g1), dim3(256), 0, s, m, key, dlist, nd, vmin, sel);
   hipLaunchKernelGGL(k_reselect, dim3(g2), dim3(256), 0, s, m, key, dlist, nd, (const uint64_t*)vmin, sel);
   compact_flags(ws, s, sel, nh, cand, ncand);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_prefilter(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, uint64_t* key, int* err) {
+  hipLaunchKernelGGL(k_prefilter, dim3(nblk(3 * (int64_t)m.nf)), dim3(256), 0, s, m, Q, w_e, w_s, key, err);
   PAMO_HIP(hipGetLastError());
 }
 

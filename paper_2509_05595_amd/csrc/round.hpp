@@ -59,6 +59,10 @@ void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, do
 // folded them in), so only the selection and its compaction run
 void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, int* cand,
                    int* ncand, bool vmin_ready = false);
+// the link/flip pre-filter: every keyed edge failing the local checks (R7)
+// gets the largest key on both half-edges (m needs the stored stars of this
+// round; the vertex minima must be gathered again afterwards)
+void launch_prefilter(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, uint64_t* key, int* err);
 // the selection again after the candidates dlist[0..*nd) (*nd <= bound) got
 // the largest key on both half-edges: into cand / ncand the same candidates as
 // a full launch_select, from the flags and vertex minima of the selection
