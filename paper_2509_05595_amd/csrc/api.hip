@@ -584,13 +584,11 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
   {
     TIMED(PH_COST, 104 * nv + 51 * nf);
     launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, cnt + C_ERR, b.vmin,
-                     c->opt.cost_target);
+                     c->opt.cost_target, c->opt.prefilter != 0);
   }
   {
     TIMED(PH_SELECT, 20 * nv + 93 * nf);
-    const bool pre = c->opt.prefilter != 0;
-    if (pre) launch_prefilter(s, cur, b.Q, c->opt.w_e, c->opt.w_s, b.key, cnt + C_ERR);
-    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, !pre);
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, true);
   }
   const int bound = cur.nf / 2 + 1;
   if (learned || logging) {
@@ -942,13 +940,11 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs
   {
     TIMED(PH_COST, 104 * nv + 51 * nf);
     launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, B.done, b.key, cnt + C_ERR, b.vmin,
-                     c->opt.cost_target);
+                     c->opt.cost_target, c->opt.prefilter != 0);
   }
   {
     TIMED(PH_SELECT, 20 * nv + 93 * nf);
-    const bool pre = c->opt.prefilter != 0;
-    if (pre) launch_prefilter(s, cur, b.Q, c->opt.w_e, c->opt.w_s, b.key, cnt + C_ERR);
-    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, !pre);
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, true);
   }
   const int bound = cur.nf / 2 + 1;
   if (learned) {

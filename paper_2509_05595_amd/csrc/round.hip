@@ -445,6 +445,150 @@ __device__ __forceinline__ double edge_cost(const MeshView& m, const double* __r
   return quadric_eval(q, vbar) + w_e * lab + w_s * S;
 }
 
+// ------------------------------------------------------------ local checks
+__device__ __forceinline__ bool degenerate(P3 a, P3 b, P3 c) {
+  // certain nonzero in some projection -> not degenerate
+  for (int k = 0; k < 3; k++) {
+    int s = orient2d_filter(pu(a, k), pv(a, k), pu(b, k), pv(b, k), pu(c, k), pv(c, k));
+    if (s != UNK) return false;
+  }
+  return degenerate_exact(a, b, c);
+}
+
+// link condition Lk(a) n Lk(b) = Lk(ab) on a closed manifold: the only
+// common neighbours are the two apexes, and the edge is not inside a
+// tetrahedron component (both endpoints of valence 3)
+__device__ __forceinline__ bool link_ok(const MeshView& m, int h) {
+  constexpr int CAP = 16;
+  int na[CAP];
+#pragma unroll
+  for (int i = 0; i < CAP; i++) na[i] = -1;
+  int vala = 0;
+  walk_star(m.twin, h, [&](int g) {
+    int w = dest(m.F, g);
+#pragma unroll
+    for (int i = 0; i < CAP; i++)
+      if (i == vala) na[i] = w;
+    vala++;
+  });
+  int valb = 0, common = 0;
+  walk_star(m.twin, m.twin[h], [&](int g) {
+    int w = dest(m.F, g);
+    valb++;
+    bool in = false;
+    if (vala <= CAP) {
+#pragma unroll
+      for (int i = 0; i < CAP; i++) in |= na[i] == w;
+    } else {
+      walk_star(m.twin, h, [&](int g2) { in |= dest(m.F, g2) == w; });
+    }
+    common += in;
+  });
+  return common == 2 && !(vala == 3 && valb == 3);
+}
+
+// the same test from the stored stars: N(v) = far ends of the half-edges
+// leaving v, each neighbour once
+__device__ __forceinline__ bool link_ok_stars(const MeshView& m, int a, int na, int b, int nb) {
+  int ga[VSTAR], gb[VSTAR];
+  star_all(m, a, na, ga);
+  star_all(m, b, nb, gb);
+  int wa[VSTAR], wb[VSTAR];
+#pragma unroll
+  for (int i = 0; i < VSTAR; i++) {
+    wa[i] = m.F[he_next(ga[i])];
+    wb[i] = m.F[he_next(gb[i])];
+  }
+  int common = 0;
+#pragma unroll
+  for (int j = 0; j < VSTAR; j++) {
+    bool in = false;
+#pragma unroll
+    for (int i = 0; i < VSTAR; i++) in |= i < na && wa[i] == wb[j];
+    common += j < nb && in;
+  }
+  return common == 2 && !(na == 3 && nb == 3);
+}
+
+// the link condition for the edge of h, from the stored stars when they fit
+__device__ __forceinline__ bool link_holds(const MeshView& m, int h) {
+  int na = 0, nb = 0;
+  const int a0 = m.F[h], b0 = m.F[he_next(h)];
+  const bool fast = stars_stored(m, a0, b0, na, nb);
+  return fast ? link_ok_stars(m, a0, na, b0, nb) : link_ok(m, h);
+}
+
+// some generated triangle (corners after the collapse to vbar) degenerate or
+// with its normal turned by 90 degrees or more against the original
+__device__ __forceinline__ bool flipped_after(const MeshView& m, const EdgeStars& E, P3 vbar) {
+  const int s = E.s, r = E.r;
+  bool bad = false;
+  auto flipped = [&](P3 o0, P3 o1, P3 o2, P3 p0, P3 p1, P3 p2) {
+    if (degenerate(p0, p1, p2)) return true;
+    double ax = o1.x - o0.x, ay = o1.y - o0.y, az = o1.z - o0.z;
+    double bx = o2.x - o0.x, by = o2.y - o0.y, bz = o2.z - o0.z;
+    double nox = ay * bz - az * by, noy = az * bx - ax * bz, noz = ax * by - ay * bx;
+    double cx = p1.x - p0.x, cy = p1.y - p0.y, cz = p1.z - p0.z;
+    double dx = p2.x - p0.x, dy = p2.y - p0.y, dz = p2.z - p0.z;
+    double nnx = cy * dz - cz * dy, nny = cz * dx - cx * dz, nnz = cx * dy - cy * dx;
+    double dot = nox * nnx + noy * nny + noz * nnz;
+    return !(dot > 0.0);
+  };
+  if (E.fast) {
+    // corner g % 3 of a star face is the star's vertex (position pc before,
+    // vbar after); no other corner is s or r; the other two are loaded
+    auto chunk = [&](const int* g, const bool* use, P3 pc) {
+      P3 o[4][3];
+      int ci[4];
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        const int f = g[k] / 3;
+        ci[k] = g[k] - 3 * f;
+        int c[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) c[i] = m.F[3 * (int64_t)f + i];
+        const int c1 = ci[k] == 2 ? 0 : ci[k] + 1, c2 = ci[k] == 0 ? 2 : ci[k] - 1;
+        const P3 q1 = ld3(m.V, c1 == 0 ? c[0] : c1 == 1 ? c[1] : c[2]);
+        const P3 q2 = ld3(m.V, c2 == 0 ? c[0] : c2 == 1 ? c[1] : c[2]);
+#pragma unroll
+        for (int i = 0; i < 3; i++) o[k][i] = i == ci[k] ? pc : i == c1 ? q1 : q2;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        if (!use[k] || bad) continue;
+        P3 p[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) p[i] = i == ci[k] ? vbar : o[k][i];
+        bad = flipped(o[k][0], o[k][1], o[k][2], p[0], p[1], p[2]);
+      }
+    };
+    const P3 ps = ld3(m.V, s), pr = ld3(m.V, r);
+    star_chunks(m, s, E.ns, E.f1, E.f2, E.hs, [&](const int* g, const bool* use) { chunk(g, use, ps); });
+    star_chunks(m, r, E.nr, E.f1, E.f2, E.hs, [&](const int* g, const bool* use) { chunk(g, use, pr); });
+  } else {
+    auto chk = [&](int f) {
+      if (bad) return;
+      P3 o0 = ld3(m.V, m.F[3 * f]), o1 = ld3(m.V, m.F[3 * f + 1]), o2 = ld3(m.V, m.F[3 * f + 2]);
+      bad = flipped(o0, o1, o2, corner_after(m, f, 0, s, r, vbar), corner_after(m, f, 1, s, r, vbar),
+                    corner_after(m, f, 2, s, r, vbar));
+    };
+    star_ascending(m, E, E.hs, chk);
+    star_ascending(m, E, E.hr, chk);
+  }
+  return bad;
+}
+
+// R7 for the edge of h: 0 passes, 1 link condition, 2 a generated triangle
+// degenerate or flipped; vbar gets the placement (when the link holds)
+__device__ __forceinline__ uint8_t local_reason(const MeshView& m, const double* __restrict__ Q, double w_e,
+                                                double w_s, int h, P3& vbar, int* err) {
+  if (!link_holds(m, h)) return 1;
+  EdgeStars E;
+  if (!edge_stars(m, h, E)) set_err(err, PAMO_EBIT_RING);
+  (void)edge_cost(m, Q, E, w_e, w_s, vbar);
+  return flipped_after(m, E, vbar) ? 2 : 0;
+}
+
 // ------------------------------------------------------------ cost + keys
 // One thread per edge: each wave gathers the representative half-edges
 // (h < twin h) of its PW consecutive half-edges into an LDS queue and then
@@ -454,7 +598,9 @@ __device__ __forceinline__ double edge_cost(const MeshView& m, const double* __r
 // on the chip, since there the latency of one lane's loads sets the time.
 constexpr int64_t CK_SMALL_NH = 1 << 21;
 
-template <int PW>
+// PRE: the link/flip pre-filter, an edge failing the local checks of R7 gets
+// the largest key (from the placement just computed)
+template <int PW, bool PRE>
 __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
                                                    double cost_max, const uint8_t* __restrict__ demote,
                                                    const uint8_t* __restrict__ mesh_done, uint64_t* __restrict__ key,
@@ -487,6 +633,7 @@ __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __r
         P3 vbar;
         double cost = edge_cost(m, Q, E, w_e, w_s, vbar);
         k = cost > cost_max ? PAMO_KEY_MAX : make_key(cost, (uint32_t)h);  // above the cost target: never chosen
+        if (PRE && k != PAMO_KEY_MAX && (!link_holds(m, h) || flipped_after(m, E, vbar))) k = PAMO_KEY_MAX;
         if (vmin && k != PAMO_KEY_MAX) {  // the vertex minima of the selection, in place of a gather pass
           atomicMin(reinterpret_cast<unsigned long long*>(vmin + E.s), (unsigned long long)k);
           atomicMin(reinterpret_cast<unsigned long long*>(vmin + E.r), (unsigned long long)k);
@@ -662,146 +809,6 @@ __global__ __launch_bounds__(256) void k_reselect(MeshView m, const uint64_t* __
   }
 }
 
-// ------------------------------------------------------------ local checks
-__device__ __forceinline__ bool degenerate(P3 a, P3 b, P3 c) {
-  // certain nonzero in some projection -> not degenerate
-  for (int k = 0; k < 3; k++) {
-    int s = orient2d_filter(pu(a, k), pv(a, k), pu(b, k), pv(b, k), pu(c, k), pv(c, k));
-    if (s != UNK) return false;
-  }
-  return degenerate_exact(a, b, c);
-}
-
-// link condition Lk(a) n Lk(b) = Lk(ab) on a closed manifold: the only
-// common neighbours are the two apexes, and the edge is not inside a
-// tetrahedron component (both endpoints of valence 3)
-__device__ __forceinline__ bool link_ok(const MeshView& m, int h) {
-  constexpr int CAP = 16;
-  int na[CAP];
-#pragma unroll
-  for (int i = 0; i < CAP; i++) na[i] = -1;
-  int vala = 0;
-  walk_star(m.twin, h, [&](int g) {
-    int w = dest(m.F, g);
-#pragma unroll
-    for (int i = 0; i < CAP; i++)
-      if (i == vala) na[i] = w;
-    vala++;
-  });
-  int valb = 0, common = 0;
-  walk_star(m.twin, m.twin[h], [&](int g) {
-    int w = dest(m.F, g);
-    valb++;
-    bool in = false;
-    if (vala <= CAP) {
-#pragma unroll
-      for (int i = 0; i < CAP; i++) in |= na[i] == w;
-    } else {
-      walk_star(m.twin, h, [&](int g2) { in |= dest(m.F, g2) == w; });
-    }
-    common += in;
-  });
-  return common == 2 && !(vala == 3 && valb == 3);
-}
-
-// the same test from the stored stars: N(v) = far ends of the half-edges
-// leaving v, each neighbour once
-__device__ __forceinline__ bool link_ok_stars(const MeshView& m, int a, int na, int b, int nb) {
-  int ga[VSTAR], gb[VSTAR];
-  star_all(m, a, na, ga);
-  star_all(m, b, nb, gb);
-  int wa[VSTAR], wb[VSTAR];
-#pragma unroll
-  for (int i = 0; i < VSTAR; i++) {
-    wa[i] = m.F[he_next(ga[i])];
-    wb[i] = m.F[he_next(gb[i])];
-  }
-  int common = 0;
-#pragma unroll
-  for (int j = 0; j < VSTAR; j++) {
-    bool in = false;
-#pragma unroll
-    for (int i = 0; i < VSTAR; i++) in |= i < na && wa[i] == wb[j];
-    common += j < nb && in;
-  }
-  return common == 2 && !(na == 3 && nb == 3);
-}
-
-// R7 for the edge of h: 0 passes, 1 link condition, 2 a generated triangle
-// degenerate or flipped; vbar gets the placement (when the link holds)
-__device__ __forceinline__ uint8_t local_reason(const MeshView& m, const double* __restrict__ Q, double w_e,
-                                                double w_s, int h, P3& vbar, int* err) {
-  uint8_t rs = 0;
-  int na = 0, nb = 0;
-  const int a0 = m.F[h], b0 = m.F[he_next(h)];
-  const bool fast = stars_stored(m, a0, b0, na, nb);
-  if (!(fast ? link_ok_stars(m, a0, na, b0, nb) : link_ok(m, h))) {
-    rs = 1;
-  } else {
-    EdgeStars E;
-    if (!edge_stars(m, h, E)) set_err(err, PAMO_EBIT_RING);
-    (void)edge_cost(m, Q, E, w_e, w_s, vbar);
-    const int s = E.s, r = E.r;
-    bool bad = false;
-    // generated triangle (corners after the collapse) degenerate or with its
-    // normal turned by 90 degrees or more against the original
-    auto flipped = [&](P3 o0, P3 o1, P3 o2, P3 p0, P3 p1, P3 p2) {
-      if (degenerate(p0, p1, p2)) return true;
-      double ax = o1.x - o0.x, ay = o1.y - o0.y, az = o1.z - o0.z;
-      double bx = o2.x - o0.x, by = o2.y - o0.y, bz = o2.z - o0.z;
-      double nox = ay * bz - az * by, noy = az * bx - ax * bz, noz = ax * by - ay * bx;
-      double cx = p1.x - p0.x, cy = p1.y - p0.y, cz = p1.z - p0.z;
-      double dx = p2.x - p0.x, dy = p2.y - p0.y, dz = p2.z - p0.z;
-      double nnx = cy * dz - cz * dy, nny = cz * dx - cx * dz, nnz = cx * dy - cy * dx;
-      double dot = nox * nnx + noy * nny + noz * nnz;
-      return !(dot > 0.0);
-    };
-    if (E.fast) {
-      // corner g % 3 of a star face is the star's vertex (position pc before,
-      // vbar after); no other corner is s or r; the other two are loaded
-      auto chunk = [&](const int* g, const bool* use, P3 pc) {
-        P3 o[4][3];
-        int ci[4];
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-          const int f = g[k] / 3;
-          ci[k] = g[k] - 3 * f;
-          int c[3];
-#pragma unroll
-          for (int i = 0; i < 3; i++) c[i] = m.F[3 * (int64_t)f + i];
-          const int c1 = ci[k] == 2 ? 0 : ci[k] + 1, c2 = ci[k] == 0 ? 2 : ci[k] - 1;
-          const P3 q1 = ld3(m.V, c1 == 0 ? c[0] : c1 == 1 ? c[1] : c[2]);
-          const P3 q2 = ld3(m.V, c2 == 0 ? c[0] : c2 == 1 ? c[1] : c[2]);
-#pragma unroll
-          for (int i = 0; i < 3; i++) o[k][i] = i == ci[k] ? pc : i == c1 ? q1 : q2;
-        }
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-          if (!use[k] || bad) continue;
-          P3 p[3];
-#pragma unroll
-          for (int i = 0; i < 3; i++) p[i] = i == ci[k] ? vbar : o[k][i];
-          bad = flipped(o[k][0], o[k][1], o[k][2], p[0], p[1], p[2]);
-        }
-      };
-      const P3 ps = ld3(m.V, s), pr = ld3(m.V, r);
-      star_chunks(m, s, E.ns, E.f1, E.f2, E.hs, [&](const int* g, const bool* use) { chunk(g, use, ps); });
-      star_chunks(m, r, E.nr, E.f1, E.f2, E.hs, [&](const int* g, const bool* use) { chunk(g, use, pr); });
-    } else {
-      auto chk = [&](int f) {
-        if (bad) return;
-        P3 o0 = ld3(m.V, m.F[3 * f]), o1 = ld3(m.V, m.F[3 * f + 1]), o2 = ld3(m.V, m.F[3 * f + 2]);
-        bad = flipped(o0, o1, o2, corner_after(m, f, 0, s, r, vbar), corner_after(m, f, 1, s, r, vbar),
-                      corner_after(m, f, 2, s, r, vbar));
-      };
-      star_ascending(m, E, E.hs, chk);
-      star_ascending(m, E, E.hr, chk);
-    }
-    if (bad) rs = 2;
-  }
-  return rs;
-}
-
 __global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* __restrict__ Q, double w_e,
                                                      double w_s, const int* __restrict__ cand,
                                                      const int* __restrict__ ncand, const uint64_t* __restrict__ key,
@@ -818,22 +825,6 @@ __global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* _
   vbar_out[3 * (int64_t)c + 1] = vbar.y;
   vbar_out[3 * (int64_t)c + 2] = vbar.z;
   wave_hist(rs, hist);
-}
-
-// Pre-filter: R7 on every keyed edge (by its lower half-edge) before the
-// selection; a failing edge gets the largest key on both half-edges, so it is
-// neither chosen nor holds back its neighbourhood this round
-__global__ __launch_bounds__(256) void k_prefilter(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
-                                                   uint64_t* __restrict__ key, int* err) {
-  const int h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= 3 * m.nf) return;
-  const int t = m.twin[h];
-  if (!(h < t) || key[h] == PAMO_KEY_MAX) return;
-  P3 vbar{0, 0, 0};
-  if (local_reason(m, Q, w_e, w_s, h, vbar, err) != 0) {
-    key[h] = PAMO_KEY_MAX;
-    key[t] = PAMO_KEY_MAX;
-  }
 }
 
 // candidates passing the local checks whose key exceeds the threshold are
@@ -1391,15 +1382,18 @@ void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err, uint64_t* v
 }
 
 void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
-                      const uint8_t* mesh_done, uint64_t* key, int* err, uint64_t* vmin, double cost_target) {
+                      const uint8_t* mesh_done, uint64_t* key, int* err, uint64_t* vmin, double cost_target,
+                      bool prefilter) {
   const int64_t nh = 3 * (int64_t)m.nf;
   const double cost_max = cost_target > 0 ? cost_target : INFINITY;
+  auto go = [&](auto kern, int pw) {
+    hipLaunchKernelGGL(kern, dim3(nblk(nh, 4 * pw)), dim3(256), 0, s, m, Q, w_e, w_s, cost_max, demote, mesh_done,
+                       key, err, vmin);
+  };
   if (nh <= CK_SMALL_NH)
-    hipLaunchKernelGGL(k_cost_keys<64>, dim3(nblk(nh, 4 * 64)), dim3(256), 0, s, m, Q, w_e, w_s, cost_max, demote,
-                       mesh_done, key, err, vmin);
+    prefilter ? go(k_cost_keys<64, true>, 64) : go(k_cost_keys<64, false>, 64);
   else
-    hipLaunchKernelGGL(k_cost_keys<256>, dim3(nblk(nh, 4 * 256)), dim3(256), 0, s, m, Q, w_e, w_s, cost_max, demote,
-                       mesh_done, key, err, vmin);
+    prefilter ? go(k_cost_keys<256, true>, 256) : go(k_cost_keys<256, false>, 256);
   PAMO_HIP(hipGetLastError());
 }
 
@@ -1422,11 +1416,6 @@ void launch_reselect(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* k
   hipLaunchKernelGGL(k_demoted_vmin, dim3(g1), dim3(256), 0, s, m, key, dlist, nd, vmin, sel);
   hipLaunchKernelGGL(k_reselect, dim3(g2), dim3(256), 0, s, m, key, dlist, nd, (const uint64_t*)vmin, sel);
   compact_flags(ws, s, sel, nh, cand, ncand);
-  PAMO_HIP(hipGetLastError());
-}
-
-void launch_prefilter(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, uint64_t* key, int* err) {
-  hipLaunchKernelGGL(k_prefilter, dim3(nblk(3 * (int64_t)m.nf)), dim3(256), 0, s, m, Q, w_e, w_s, key, err);
   PAMO_HIP(hipGetLastError());
 }
 

@@ -51,18 +51,16 @@ void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err, uint64_t* v
 // mesh_done (batches, may be null): edges of finished meshes get no key
 // vmin (optional): every finite key is also folded into vmin of both endpoints
 // (atomic minimum; vmin set to the largest key beforehand)
-// cost_target > 0: edges costing more get the largest key (never chosen)
+// cost_target > 0: edges costing more get the largest key (never chosen);
+// prefilter: so do edges failing the local checks of R7 (link condition,
+// degenerate or flipped generated triangles; m needs this round's stars)
 void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
                       const uint8_t* mesh_done, uint64_t* key, int* err, uint64_t* vmin = nullptr,
-                      double cost_target = 0.0);
+                      double cost_target = 0.0, bool prefilter = false);
 // vmin_ready: vmin already holds the vertex minima of key (the cost kernel
 // folded them in), so only the selection and its compaction run
 void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, int* cand,
                    int* ncand, bool vmin_ready = false);
-// the link/flip pre-filter: every keyed edge failing the local checks (R7)
-// gets the largest key on both half-edges (m needs the stored stars of this
-// round; the vertex minima must be gathered again afterwards)
-void launch_prefilter(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, uint64_t* key, int* err);
 // the selection again after the candidates dlist[0..*nd) (*nd <= bound) got
 // the largest key on both half-edges: into cand / ncand the same candidates as
 // a full launch_select, from the flags and vertex minima of the selection

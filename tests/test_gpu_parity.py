@@ -116,6 +116,31 @@ def test_simplify_bitwise(ctx, name, target, we, ws):
     assert st["undo_hist"] == r["stats"]["undo_hist"]
 
 
+@pytest.mark.parametrize("target", [0, 1, 5, 318, 319, 320, 321, 10 ** 9])
+def test_targets_at_the_ends(ctx, target):
+    # 320 faces: down to a tetrahedron (the target unreachable below 4 faces),
+    # odd targets (T - T mod 2), one collapse, none, a target above the count
+    V, F = MESHES["ico2"]
+    Vo, Fo, st = ctx.simplify(dev(V, torch.float64), dev(F, torch.int32), target)
+    r = orc.run(V, F, target)
+    assert np.array_equal(host(Fo), r["F"])
+    assert np.array_equal(host(Vo).view(np.uint64), r["V"].view(np.uint64))
+    assert st["status"] == r["stats"]["status"] and st["rounds"] == r["stats"]["rounds"]
+    if target >= len(F):
+        assert st["rounds"] == 0 and np.array_equal(host(Fo), F)
+
+
+def test_batch_targets_at_the_ends(ctx):
+    V, F = MESHES["ico2"]
+    targets = [0, 319, 320, 10 ** 9, 5]
+    out = ctx.simplify_batch([(dev(V, torch.float64), dev(F, torch.int32))] * len(targets), targets)
+    for t, (Vo, Fo, st) in zip(targets, out):
+        r = orc.run(V, F, t)
+        assert np.array_equal(host(Fo), r["F"])
+        assert np.array_equal(host(Vo).view(np.uint64), r["V"].view(np.uint64))
+        assert st["status"] == r["stats"]["status"] and st["rounds"] == r["stats"]["rounds"]
+
+
 def test_tri_pairs_match_oracle(ctx):
     from test_oracle_predicates import _random_pair
     rng = np.random.default_rng(77)
