@@ -38,7 +38,8 @@ def build(force: bool = True) -> str:
 
 class Opts(C.Structure):
     _fields_ = [("w_e", C.c_double), ("w_s", C.c_double), ("tolerance", C.c_int32),
-                ("max_rounds", C.c_int32), ("cost_target", C.c_double), ("prefilter", C.c_int32)]
+                ("max_rounds", C.c_int32), ("cost_target", C.c_double), ("prefilter", C.c_int32),
+                ("key_mode", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -90,7 +91,7 @@ def lib():
         L.oracle_quadrics.argtypes = [P, I64, P, I64, P]
         L.oracle_keys.argtypes = [P, I64, P, I64, P, C.c_double, C.c_double, P]
         L.oracle_select.argtypes = [P, I64, P, I64, P, C.c_double, C.c_double, P, P]
-        L.oracle_check.argtypes = [P, I64, P, I64, P, C.c_double, C.c_double, I64, C.c_int32, P, P, P, P, P]
+        L.oracle_check.argtypes = [P, I64, P, I64, P, C.c_double, C.c_double, I64, C.c_int32, C.c_int32, P, P, P, P, P]
         L.oracle_run.argtypes = [P, I64, P, I64, P, C.c_int32, I64, P, P, P, P, P, P, P, P, P, I64]
         L.oracle_tri_pair.argtypes = [P, P, P, P]
         L.oracle_degenerate.argtypes = [P]
@@ -170,8 +171,8 @@ def select(V, F, flags=None, w_e=W_E, w_s=W_S):
     return cand[: n[0]].copy()
 
 
-def check(V, F, target, flags=None, w_e=W_E, w_s=W_S, prefilter=0):
-    """One round up to the end of the check/undo loop (prefilter: as in run).
+def check(V, F, target, flags=None, w_e=W_E, w_s=W_S, prefilter=0, key_mode=0):
+    """One round up to the end of the check/undo loop (prefilter, key_mode: as in run).
     Returns (cand, vbar (n,3), reason (n,), undo_iterations)."""
     V, F = _mesh(V, F)
     cap = 3 * len(F) + 1
@@ -181,7 +182,7 @@ def check(V, F, target, flags=None, w_e=W_E, w_s=W_S, prefilter=0):
     n = np.zeros(1, dtype=np.int64)
     it = np.zeros(1, dtype=np.int64)
     rc = lib().oracle_check(_p(V), len(V), _p(F), len(F), _p(_flags(flags, len(F))), w_e, w_s,
-                            int(target), int(prefilter), _p(cand), _p(n), _p(vbar), _p(reason), _p(it))
+                            int(target), int(prefilter), int(key_mode), _p(cand), _p(n), _p(vbar), _p(reason), _p(it))
     if rc:
         raise ValueError(f"oracle_check: {rc}")
     k = n[0]
@@ -189,12 +190,13 @@ def check(V, F, target, flags=None, w_e=W_E, w_s=W_S, prefilter=0):
 
 
 def run(V, F, target, flags=None, streak=0, max_rounds=-1, w_e=W_E, w_s=W_S,
-        tolerance=TOLERANCE, log_rounds=0, cost_target=0.0, prefilter=0):
+        tolerance=TOLERANCE, log_rounds=0, cost_target=0.0, prefilter=0, key_mode=0):
     """Whole method.  Returns dict with V, F, flags, streak, stats, log.
     cost_target > 0: only edges costing at most this collapse, and a round that
     selects nothing ends the run (the paper's target-cost termination).
     prefilter: the link and flip checks run on every keyed edge before the
-    selection, and failing edges are not selectable that round."""
+    selection, and failing edges are not selectable that round.
+    key_mode 1: keys ordered by the float64 cost, then the edge id."""
     V, F = _mesh(V, F)
     Vo = np.zeros_like(V)
     Fo = np.zeros_like(F)
@@ -203,7 +205,7 @@ def run(V, F, target, flags=None, streak=0, max_rounds=-1, w_e=W_E, w_s=W_S,
     nfo = np.zeros(1, dtype=np.int64)
     so = np.zeros(1, dtype=np.int32)
     st = Stats()
-    opt = Opts(w_e, w_s, tolerance, max_rounds, cost_target, int(prefilter))
+    opt = Opts(w_e, w_s, tolerance, max_rounds, cost_target, int(prefilter), int(key_mode))
     LogArr = RoundLog * max(1, log_rounds)
     log = LogArr()
     rc = lib().oracle_run(_p(V), len(V), _p(F), len(F), _p(_flags(flags, len(F))), int(streak),
@@ -317,7 +319,8 @@ def mlp_logits(model, X):
     return out
 
 
-def run_learned(V, F, target, model, max_rounds=-1, w_e=W_E, w_s=W_S, tolerance=TOLERANCE, prefilter=0):
+def run_learned(V, F, target, model, max_rounds=-1, w_e=W_E, w_s=W_S, tolerance=TOLERANCE, prefilter=0,
+                key_mode=0):
     """The method with the learned proposal.  Returns dict with V, F, stats,
     demoted (candidates set aside) and fallbacks (rounds run again plain)."""
     V, F = _mesh(V, F)
@@ -325,7 +328,7 @@ def run_learned(V, F, target, model, max_rounds=-1, w_e=W_E, w_s=W_S, tolerance=
     nvo, nfo = np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64)
     info = np.zeros(2, dtype=np.int64)
     st = Stats()
-    opt = Opts(w_e, w_s, tolerance, max_rounds, 0.0, int(prefilter))
+    opt = Opts(w_e, w_s, tolerance, max_rounds, 0.0, int(prefilter), int(key_mode))
     m = mlp_struct(model)
     rc = lib().oracle_run_learned(_p(V), len(V), _p(F), len(F), int(target), C.byref(opt), C.byref(m), _p(Vo),
                                   _p(nvo), _p(Fo), _p(nfo), C.byref(st), _p(info))
@@ -336,7 +339,7 @@ def run_learned(V, F, target, model, max_rounds=-1, w_e=W_E, w_s=W_S, tolerance=
             "fallbacks": int(info[1])}
 
 
-def collect(V, F, target, cap=1 << 20, w_e=W_E, w_s=W_S, tolerance=TOLERANCE):
+def collect(V, F, target, cap=1 << 20, w_e=W_E, w_s=W_S, tolerance=TOLERANCE, key_mode=0):
     """The plain method, logging (features, committed?) of every candidate the
     checks decided.  Returns (X (n, 32) float32, y (n,) uint8, run dict)."""
     V, F = _mesh(V, F)
@@ -346,7 +349,7 @@ def collect(V, F, target, cap=1 << 20, w_e=W_E, w_s=W_S, tolerance=TOLERANCE):
     Vo, Fo = np.zeros_like(V), np.zeros_like(F)
     nvo, nfo = np.zeros(1, dtype=np.int64), np.zeros(1, dtype=np.int64)
     st = Stats()
-    opt = Opts(w_e, w_s, tolerance, -1)
+    opt = Opts(w_e, w_s, tolerance, -1, 0.0, 0, int(key_mode))
     rc = lib().oracle_collect(_p(V), len(V), _p(F), len(F), int(target), C.byref(opt), _p(X), _p(y), cap, _p(n),
                               _p(Vo), _p(nvo), _p(Fo), _p(nfo), C.byref(st))
     if rc:

@@ -65,6 +65,10 @@ typedef struct {
                            they do not hold back their neighbourhood (the other order of
                            selection and local checks; the paper applies the link
                            condition during the collapse, Sec. 5.1) */
+    int32_t key_mode;   /* 0: R4's float32 key; 1: keys ordered by the float64 cost, then
+                           the edge id (the other reading of the cost-to-key conversion
+                           of Sec. 5.1, "Cost Propagation"); not with the learned proposal,
+                           whose features read the float32 cost from the key */
 } oracle_opts;
 
 typedef struct {
@@ -338,16 +342,38 @@ static uint64_t make_key(double cost, uint32_t edge_id) {
     return ((uint64_t)o << 32) | edge_id;
 }
 
+/* key_mode 1: a total order code of a float64 cost (zero of either sign as
+ * +0, so equal costs get equal codes) */
+static uint64_t ord64(double c) {
+    if (c == 0.0) c = 0.0;
+    uint64_t u;
+    memcpy(&u, &c, 8);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+static const uint64_t *g_codes; /* qsort helper (single-threaded oracle) */
+static int cmp_code_then_id(const void *x, const void *y) {
+    int64_t a = *(const int64_t *)x, b = *(const int64_t *)y;
+    if (g_codes[a] != g_codes[b]) return g_codes[a] < g_codes[b] ? -1 : 1;
+    return (a > b) - (a < b);
+}
+
 static int edge_flagged(const omesh *m, int64_t h) {
     return m->flags[h] || m->flags[m->twin[h]];
 }
 
 /* keys at every half-edge that represents its edge (h < twin(h)); KEY_MAX
- * elsewhere, and for edges costing more than cost_target when it is > 0 */
-static void compute_keys_capped(omesh *m, double w_e, double w_s, double cost_target) {
+ * elsewhere, and for edges costing more than cost_target when it is > 0.
+ * key_mode 1: keys are only ever compared, so each keyed edge takes as key its
+ * rank in the order of (float64 cost, edge id) */
+static void compute_keys_capped(omesh *m, double w_e, double w_s, double cost_target, int key_mode) {
     free(m->key);
-    m->key = xalloc(sizeof(uint64_t) * (size_t)(3 * m->nf));
-    for (int64_t h = 0; h < 3 * m->nf; h++) {
+    int64_t nh = 3 * m->nf;
+    m->key = xalloc(sizeof(uint64_t) * (size_t)nh);
+    uint64_t *code = key_mode ? xalloc(sizeof(uint64_t) * (size_t)nh) : NULL;
+    int64_t *keyed = key_mode ? xalloc(sizeof(int64_t) * (size_t)(nh + 1)) : NULL;
+    int64_t nk = 0;
+    for (int64_t h = 0; h < nh; h++) {
         m->key[h] = KEY_MAX;
         if (!m->falive[h / 3] || m->twin[h] < h) continue;
         if (edge_flagged(m, h)) continue;
@@ -355,11 +381,23 @@ static void compute_keys_capped(omesh *m, double w_e, double w_s, double cost_ta
         double vbar[3];
         double cost = edge_cost(m, a, b, w_e, w_s, vbar);
         if (cost_target > 0 && cost > cost_target) continue;
-        m->key[h] = make_key(cost, (uint32_t)h);
+        if (!key_mode) {
+            m->key[h] = make_key(cost, (uint32_t)h);
+        } else if (cost == cost) {
+            code[h] = ord64(cost);
+            keyed[nk++] = h;
+        }
+    }
+    if (key_mode) {
+        g_codes = code;
+        qsort(keyed, (size_t)nk, sizeof(int64_t), cmp_code_then_id);
+        for (int64_t i = 0; i < nk; i++) m->key[keyed[i]] = (uint64_t)i;
+        free(code);
+        free(keyed);
     }
 }
 
-static void compute_keys(omesh *m, double w_e, double w_s) { compute_keys_capped(m, w_e, w_s, 0.0); }
+static void compute_keys(omesh *m, double w_e, double w_s) { compute_keys_capped(m, w_e, w_s, 0.0, 0); }
 
 /* R5/R6 in the push form of the paper: C_t = min over edges e whose 1-ring
  * contains t of C_e; e is chosen when C_t = C_e for every t of its 1-ring. */
@@ -892,7 +930,7 @@ static int run_round(omesh *m, int64_t target_eff, const oracle_opts *opt, round
     int err = build_adjacency(m);
     if (err) return err;
     compute_quadrics(m);
-    compute_keys_capped(m, opt->w_e, opt->w_s, opt->cost_target);
+    compute_keys_capped(m, opt->w_e, opt->w_s, opt->cost_target, opt->key_mode);
     int64_t nf = m->nf, nv = m->nv;
     if (opt->prefilter) {
         /* R7 on every keyed edge, on the pre-round mesh: a failing edge is
@@ -1173,13 +1211,14 @@ int oracle_select(const double *V, int64_t nv, const int32_t *F, int64_t nf, con
  * placements and their outcome (0 kept, 1 link, 2 flip/degenerate,
  * 3 intersection, 4 capped by the face target) */
 int oracle_check(const double *V, int64_t nv, const int32_t *F, int64_t nf, const uint8_t *flags,
-                 double w_e, double w_s, int64_t target, int32_t prefilter, int32_t *cand, int64_t *ncand,
+                 double w_e, double w_s, int64_t target, int32_t prefilter, int32_t key_mode, int32_t *cand,
+                 int64_t *ncand,
                  double *vbar, uint8_t *reason, int64_t *undo_iters) {
     if (check_input(F, nf, nv)) return -1;
     omesh m;
     mesh_init(&m, V, nv, F, nf);
     if (flags) memcpy(m.flags, flags, (size_t)(3 * nf));
-    oracle_opts o = {w_e, w_s, 4, -1, 0.0, prefilter};
+    oracle_opts o = {w_e, w_s, 4, -1, 0.0, prefilter, key_mode};
     round_out r;
     int err = run_round(&m, target - (target % 2), &o, &r, 1, NULL, NULL);
     if (!err) {
@@ -1239,7 +1278,7 @@ static int run_impl(const double *V, int64_t nv, const int32_t *F, int64_t nf,
             err = build_adjacency(&m);
             if (err) break;
             compute_quadrics(&m);
-            compute_keys_capped(&m, opt->w_e, opt->w_s, opt->cost_target);
+            compute_keys_capped(&m, opt->w_e, opt->w_s, opt->cost_target, opt->key_mode);
             int32_t *c0 = xalloc(sizeof(int32_t) * (size_t)(3 * m.nf + 1));
             int64_t n0 = select_edges(&m, c0);
             feat = xalloc(sizeof(float) * NFEAT * (size_t)(n0 + 1));
@@ -1340,6 +1379,7 @@ int oracle_run_learned(const double *V, int64_t nv, const int32_t *F, int64_t nf
                        const oracle_opts *opt, const oracle_mlp *mlp, double *Vout, int64_t *nv_out,
                        int32_t *Fout, int64_t *nf_out, oracle_stats *st, int64_t *learned_info) {
     if (learned_info) learned_info[0] = learned_info[1] = 0;
+    if (opt->key_mode) return -1; /* the features read the float32 cost from the key */
     return run_impl(V, nv, F, nf, NULL, 0, target, opt, Vout, nv_out, Fout, nf_out, NULL, NULL, st, NULL, 0,
                     mlp, NULL, learned_info);
 }
@@ -1348,6 +1388,8 @@ int oracle_run_learned(const double *V, int64_t nv, const int32_t *F, int64_t nf
 int oracle_collect(const double *V, int64_t nv, const int32_t *F, int64_t nf, int64_t target,
                    const oracle_opts *opt, float *X, uint8_t *y, int64_t cap, int64_t *n,
                    double *Vout, int64_t *nv_out, int32_t *Fout, int64_t *nf_out, oracle_stats *st) {
+    /* logged rows come from the plain selection with R4's keys */
+    if (opt->key_mode || opt->prefilter) return -1;
     collect_buf col = {X, y, cap, 0};
     int err = run_impl(V, nv, F, nf, NULL, 0, target, opt, Vout, nv_out, Fout, nf_out, NULL, NULL, st, NULL, 0,
                        NULL, &col, NULL);
