@@ -70,8 +70,13 @@ typedef struct {
                            Sec. 5.1 applies the link condition during the collapse) run on every keyed edge
                            before the selection, and an edge failing them gets no key that round, so it does
                            not hold back its neighbourhood (the other order of selection and local checks);
-                           0: checks on the selected candidates only (default).  Applies to pamo_simplify
-                           and pamo_simplify_batch */
+                           0: checks on the selected candidates only (default).  Applies to pamo_simplify,
+                           pamo_simplify_batch and pamo_select; pamo_collect refuses it (PAMO_ERR_ARG) */
+  int32_t key_mode;     /* 0: the 64-bit key of Sec. 5.1 "Cost Propagation", float32 cost code above the edge
+                           id (default); 1: edges ordered by the float64 cost, then the edge id (the other
+                           reading of the paper's conversion of costs from floats): each keyed edge's key is
+                           its rank in that order above its id.  The learned proposal, pamo_features and
+                           pamo_collect read the float32 cost from the key and refuse it (PAMO_ERR_ARG) */
 } pamo_options;
 
 typedef struct {

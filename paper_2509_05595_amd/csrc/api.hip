@@ -584,11 +584,12 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
   {
     TIMED(PH_COST, 104 * nv + 51 * nf);
     launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, cnt + C_ERR, b.vmin,
-                     c->opt.cost_target, c->opt.prefilter != 0);
+                     c->opt.cost_target, c->opt.prefilter != 0, c->opt.key_mode != 0);
   }
   {
     TIMED(PH_SELECT, 20 * nv + 93 * nf);
-    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, true);
+    if (c->opt.key_mode) launch_rank_keys(c->ws, s, cur, b.key);
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, c->opt.key_mode == 0);
   }
   const int bound = cur.nf / 2 + 1;
   if (learned || logging) {
@@ -940,11 +941,12 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs
   {
     TIMED(PH_COST, 104 * nv + 51 * nf);
     launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, B.done, b.key, cnt + C_ERR, b.vmin,
-                     c->opt.cost_target, c->opt.prefilter != 0);
+                     c->opt.cost_target, c->opt.prefilter != 0, c->opt.key_mode != 0);
   }
   {
     TIMED(PH_SELECT, 20 * nv + 93 * nf);
-    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, true);
+    if (c->opt.key_mode) launch_rank_keys(c->ws, s, cur, b.key);
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, c->opt.key_mode == 0);
   }
   const int bound = cur.nf / 2 + 1;
   if (learned) {
@@ -1044,6 +1046,8 @@ pamo_status simplify_run(pamo_ctx* c, const double* V, int64_t nv, const int32_t
   check_sizes(nv, nf);
   if (target_faces < 0) fail(PAMO_ERR_ARG, "negative target");
   if (L->learned && !c->mlp) fail(PAMO_ERR_ARG, "the learned proposal needs a network (pamo_set_mlp)");
+  if (L->learned && c->opt.key_mode)
+    fail(PAMO_ERR_ARG, "the learned proposal's features read the float32 cost from the key (key_mode 0)");
   hipStream_t s = c->stream;
   MeshView cur = mesh_bufs(c, "mA", nv, nf);
   MeshView alt = mesh_bufs(c, "mB", nv, nf);
@@ -1189,7 +1193,8 @@ pamo_status pamo_select(pamo_ctx* c, const double* V, int64_t nv, const int32_t*
     uint64_t* key = keys ? keys : b.key;
     launch_quadrics(c->stream, A, b.Q, c->dcnt + C_ERR);
     launch_cost_keys(c->stream, A, b.Q, c->opt.w_e, c->opt.w_s, demote, nullptr, key, c->dcnt + C_ERR, nullptr,
-                     c->opt.cost_target);
+                     c->opt.cost_target, c->opt.prefilter != 0, c->opt.key_mode != 0);
+    if (c->opt.key_mode) launch_rank_keys(c->ws, c->stream, A, key);
     launch_select(c->ws, c->stream, A, key, b.vmin, cand, ncand);
     check_err_bits(readback(c)[C_ERR]);
     return PAMO_OK;
@@ -1214,7 +1219,8 @@ pamo_status pamo_check(pamo_ctx* c, const double* V, int64_t nv, const int32_t* 
     fill_i32(s, c->dcnt, C_COUNT, 0);
     launch_quadrics(s, A, b.Q, c->dcnt + C_ERR);
     launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR, nullptr,
-                     c->opt.cost_target);
+                     c->opt.cost_target, false, c->opt.key_mode != 0);
+    if (c->opt.key_mode) launch_rank_keys(c->ws, s, A, b.key);  // the cap orders by key
     int64_t teff = target_faces - target_faces % 2;
     if (A.nf <= teff) fail(PAMO_ERR_ARG, "the mesh is already at or below the target");
     RoundResult R;
@@ -1298,6 +1304,8 @@ pamo_status pamo_collect(pamo_ctx* c, const double* V, int64_t nv, const int32_t
                          int64_t target_faces, float* X, uint8_t* y, int64_t cap, int64_t* rows, pamo_stats* stats) {
   return guarded(c, [&]() -> pamo_status {
     if (!V || !F || !rows || cap < 0 || (cap > 0 && (!X || !y))) fail(PAMO_ERR_ARG, "bad arguments");
+    if (c->opt.key_mode || c->opt.prefilter)
+      fail(PAMO_ERR_ARG, "training rows come from the plain selection with float32 keys (key_mode 0, prefilter 0)");
     LearnRun L;
     L.track = true;
     L.X = cap > 0 ? X : nullptr;
@@ -1358,6 +1366,8 @@ pamo_status pamo_simplify_batch(pamo_ctx* c, int32_t nmesh, const double* V, con
     RoundBufs b = round_bufs(c, nv, nf);
     const bool learned = c->opt.learned != 0;
     if (learned && !c->mlp) fail(PAMO_ERR_ARG, "the learned proposal needs a network (pamo_set_mlp)");
+    if (learned && c->opt.key_mode)
+      fail(PAMO_ERR_ARG, "the learned proposal's features read the float32 cost from the key (key_mode 0)");
     if (learned) {
       cur.ovl = c->ws.get<int>("mA.ovl", nf);
       alt.ovl = c->ws.get<int>("mB.ovl", nf);
@@ -1515,6 +1525,7 @@ pamo_status pamo_features(pamo_ctx* c, const double* V, int64_t nv, const int32_
     if (!V || !F || ne < 0 || (ne > 0 && (!edges || !X))) fail(PAMO_ERR_ARG, "bad arguments");
     check_sizes(nv, nf);
     if (ne > 3 * nf) fail(PAMO_ERR_ARG, "more edges than half-edges");
+    if (c->opt.key_mode) fail(PAMO_ERR_ARG, "the features read the float32 cost from the key (key_mode 0)");
     hipStream_t s = c->stream;
     MeshView A = mesh_bufs(c, "mA", nv, nf);
     load_mesh(c, A, V, F, nullptr);

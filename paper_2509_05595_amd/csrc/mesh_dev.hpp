@@ -120,6 +120,17 @@ PAMO_HD __forceinline__ uint64_t make_key(double cost, uint32_t edge_id) {
   return ((uint64_t)o << 32) | (uint64_t)edge_id;
 }
 
+// The float64 key mode: a total-order code of the float64 cost (zero of
+// either sign as +0, NaN as the largest key); ranks in the order of (code,
+// edge id) then replace it (rank_keys).
+PAMO_HD __forceinline__ uint64_t cost_code64(double cost) {
+  if (cost != cost) return PAMO_KEY_MAX;
+  if (cost == 0.0) cost = 0.0;
+  uint64_t u;
+  __builtin_memcpy(&u, &cost, 8);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
 // Sorted insertion of x into a[0..CAP) kept ascending with INT_MAX padding.
 // Fully unrolled so the list stays in registers.
 template <int CAP>

@@ -599,12 +599,13 @@ __device__ __forceinline__ uint8_t local_reason(const MeshView& m, const double*
 constexpr int64_t CK_SMALL_NH = 1 << 21;
 
 // PRE: the link/flip pre-filter, an edge failing the local checks of R7 gets
-// the largest key (from the placement just computed)
+// the largest key (from the placement just computed).  lex: the key is the
+// float64 cost's order code (ranked afterwards; vmin is then null)
 template <int PW, bool PRE>
 __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
                                                    double cost_max, const uint8_t* __restrict__ demote,
                                                    const uint8_t* __restrict__ mesh_done, uint64_t* __restrict__ key,
-                                                   int* err, uint64_t* __restrict__ vmin) {
+                                                   int* err, uint64_t* __restrict__ vmin, bool lex) {
   __shared__ int queue[4][PW];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t nh = 3 * (int64_t)m.nf;
@@ -632,7 +633,9 @@ __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __r
       } else {
         P3 vbar;
         double cost = edge_cost(m, Q, E, w_e, w_s, vbar);
-        k = cost > cost_max ? PAMO_KEY_MAX : make_key(cost, (uint32_t)h);  // above the cost target: never chosen
+        k = cost > cost_max ? PAMO_KEY_MAX                                 // above the cost target: never chosen
+            : lex        ? cost_code64(cost)
+                         : make_key(cost, (uint32_t)h);
         if (PRE && k != PAMO_KEY_MAX && (!link_holds(m, h) || flipped_after(m, E, vbar))) k = PAMO_KEY_MAX;
         if (vmin && k != PAMO_KEY_MAX) {  // the vertex minima of the selection, in place of a gather pass
           atomicMin(reinterpret_cast<unsigned long long*>(vmin + E.s), (unsigned long long)k);
@@ -643,6 +646,37 @@ __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __r
     key[h] = k;
     key[t] = k;
   }
+}
+
+// float64 key mode: the edges (by their lower half-edge, ascending) and their
+// codes; a stable sort of the codes then gives each keyed edge its rank in the
+// order of (float64 cost, edge id), stored in the high half of its key (the
+// edge id below, so keys stay unique and the batch cap's high-half order holds)
+__global__ void k_edge_flags(int nh, const int* __restrict__ twin, uint8_t* __restrict__ flag) {
+  int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h < nh) flag[h] = h < twin[h];
+}
+
+__global__ void k_gather_codes(int ne, const int* __restrict__ count, int* __restrict__ edges,
+                               const uint64_t* __restrict__ key, uint64_t* __restrict__ codes) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ne) return;
+  if (i < *count) {
+    codes[i] = key[edges[i]];
+  } else {  // past the edges found (an open mesh has fewer): sorts last, ranks nothing
+    codes[i] = PAMO_KEY_MAX;
+    edges[i] = -1;
+  }
+}
+
+__global__ void k_assign_ranks(int ne, const int* __restrict__ edges, const uint64_t* __restrict__ codes,
+                               const int* __restrict__ twin, uint64_t* __restrict__ key) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ne || codes[i] == PAMO_KEY_MAX) return;
+  const int h = edges[i];
+  const uint64_t k = ((uint64_t)i << 32) | (uint32_t)h;
+  key[h] = k;
+  key[twin[h]] = k;
 }
 
 // ------------------------------------------------------------ selection
@@ -1383,17 +1417,35 @@ void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err, uint64_t* v
 
 void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
                       const uint8_t* mesh_done, uint64_t* key, int* err, uint64_t* vmin, double cost_target,
-                      bool prefilter) {
+                      bool prefilter, bool lex) {
   const int64_t nh = 3 * (int64_t)m.nf;
   const double cost_max = cost_target > 0 ? cost_target : INFINITY;
+  if (lex) vmin = nullptr;  // gathered after the ranks
   auto go = [&](auto kern, int pw) {
     hipLaunchKernelGGL(kern, dim3(nblk(nh, 4 * pw)), dim3(256), 0, s, m, Q, w_e, w_s, cost_max, demote, mesh_done,
-                       key, err, vmin);
+                       key, err, vmin, lex);
   };
   if (nh <= CK_SMALL_NH)
     prefilter ? go(k_cost_keys<64, true>, 64) : go(k_cost_keys<64, false>, 64);
   else
     prefilter ? go(k_cost_keys<256, true>, 256) : go(k_cost_keys<256, false>, 256);
+  PAMO_HIP(hipGetLastError());
+}
+
+void launch_rank_keys(Workspace& ws, hipStream_t s, MeshView m, uint64_t* key) {
+  const int64_t nh = 3 * (int64_t)m.nf;
+  const int64_t ne = nh / 2;  // every edge of a closed mesh has two half-edges
+  uint8_t* flag = ws.get<uint8_t>("rk.flag", nh);
+  int* edges = ws.get<int>("rk.edges", ne + 1);
+  int* count = ws.get<int>("rk.count", 1);
+  uint64_t* codes = ws.get<uint64_t>("rk.codes", ne + 1);
+  hipLaunchKernelGGL(k_edge_flags, dim3(nblk(nh)), dim3(256), 0, s, (int)nh, (const int*)m.twin, flag);
+  compact_flags(ws, s, flag, nh, edges, count);
+  hipLaunchKernelGGL(k_gather_codes, dim3(nblk(ne)), dim3(256), 0, s, (int)ne, (const int*)count, edges,
+                     (const uint64_t*)key, codes);
+  radix_sort_u64(ws, s, codes, edges, ne, 64);  // stable: equal codes keep ascending edge id
+  hipLaunchKernelGGL(k_assign_ranks, dim3(nblk(ne)), dim3(256), 0, s, (int)ne, (const int*)edges,
+                     (const uint64_t*)codes, (const int*)m.twin, key);
   PAMO_HIP(hipGetLastError());
 }
 

@@ -56,7 +56,11 @@ void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err, uint64_t* v
 // degenerate or flipped generated triangles; m needs this round's stars)
 void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
                       const uint8_t* mesh_done, uint64_t* key, int* err, uint64_t* vmin = nullptr,
-                      double cost_target = 0.0, bool prefilter = false);
+                      double cost_target = 0.0, bool prefilter = false, bool lex = false);
+// float64 key mode, after launch_cost_keys(lex): each keyed edge's key becomes
+// (rank in the order of (float64 cost, edge id)) << 32 | edge id; the vertex
+// minima must be gathered afterwards (launch_select without vmin_ready)
+void launch_rank_keys(Workspace& ws, hipStream_t s, MeshView m, uint64_t* key);
 // vmin_ready: vmin already holds the vertex minima of key (the cost kernel
 // folded them in), so only the selection and its compaction run
 void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, int* cand,

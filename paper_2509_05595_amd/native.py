@@ -29,7 +29,8 @@ class Options(C.Structure):
     _fields_ = [("w_e", C.c_double), ("w_s", C.c_double), ("tolerance", C.c_int32),
                 ("max_rounds", C.c_int32), ("validate_input", C.c_int32), ("query_packet", C.c_int32),
                 ("resort_every", C.c_int32), ("query_coop", C.c_int32), ("coop_below", C.c_int32),
-                ("learned", C.c_int32), ("cost_target", C.c_double), ("prefilter", C.c_int32)]
+                ("learned", C.c_int32), ("cost_target", C.c_double), ("prefilter", C.c_int32),
+                ("key_mode", C.c_int32)]
 
 
 class Stats(C.Structure):

@@ -37,6 +37,6 @@ def test_binding_covers_the_header():
     sys.path.insert(0, ROOT)
     from paper_2509_05595_amd import native
     assert set(declared()) <= set(native.EXPORTS)
-    assert ctypes.sizeof(native.Options) == 8 + 8 + 4 * 8 + 8 + 8  # prefilter + padding
+    assert ctypes.sizeof(native.Options) == 8 + 8 + 4 * 8 + 8 + 4 + 4  # ..., prefilter, key_mode
     assert ctypes.sizeof(native.Stats) == 8 * 18
     assert ctypes.sizeof(native.MLP) == 4 * (2048 + 64 + 4096 + 64 + 64 + 1 + 5 + 1)
