@@ -7,13 +7,14 @@ is the smallest distance from the centre to any triangle of the soup (no
 topology is assumed) when that distance is at most the band width, and +inf
 elsewhere (the paper only needs values inside the band, 3 / R by default).
 Every centre is compared with every triangle (brute force, float64 numpy,
-point-triangle distances from oracle.hausdorff); meant for small grids.
+point-triangle distances from oracle.hausdorff, edges for triangles of zero
+area); meant for small grids.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .hausdorff import point_tris
+from .hausdorff import _seg_dist, point_tris
 
 
 def centres(res: int) -> np.ndarray:
@@ -24,14 +25,26 @@ def centres(res: int) -> np.ndarray:
 
 
 def at(V, F, P, band: float) -> np.ndarray:
-    """the field at arbitrary points P (n, 3)"""
+    """the field at arbitrary points P (n, 3).  A triangle of (nearly) zero
+    area (|n|^2 <= 1e-20 |e0|^2 |e1|^2, n the cross product of two edges e0, e1)
+    counts as its three edges: there the projection onto its plane is not
+    defined."""
     V = np.asarray(V, dtype=np.float64)
     F = np.asarray(F)
     A, B, C = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
+    e0, e1 = B - A, C - A
+    n = np.cross(e0, e1)
+    flat = ~(np.einsum("ij,ij->i", n, n) > 1e-20 * np.einsum("ij,ij->i", e0, e0) * np.einsum("ij,ij->i", e1, e1))
     out = np.full(len(P), np.inf)
     for i, p in enumerate(np.asarray(P, dtype=np.float64)):
-        d = point_tris(p, A, B, C).min() if len(F) else np.inf
-        out[i] = d if d <= band else np.inf
+        if not len(F):
+            continue
+        d = point_tris(p, A, B, C)
+        if flat.any():
+            fa, fb, fc = A[flat], B[flat], C[flat]
+            d[flat] = np.minimum(np.minimum(_seg_dist(p, fa, fb), _seg_dist(p, fb, fc)), _seg_dist(p, fc, fa))
+        m = d.min()
+        out[i] = m if m <= band else np.inf
     return out
 
 

@@ -78,3 +78,17 @@ def test_soup_invariances():
     F2 = np.concatenate([F, [[len(V), len(V) + 1, len(V) + 2]]])
     U2 = udf.udf(V2, F2, res, band)
     assert np.all(U2 <= U) and np.any(U2 < U)
+
+
+def test_triangles_of_zero_area_count_as_their_edges():
+    # a repeated corner and three collinear corners: the distance to the
+    # segments they span (a point on the segment is at distance 0)
+    V = np.array([[0.3, 0.3, 0.3], [0.5, 0.5, 0.5], [0.7, 0.7, 0.7], [0.2, 0.6, 0.4]])
+    F = np.array([[0, 1, 2], [3, 3, 0]])
+    P = np.array([[0.475, 0.475, 0.475], [0.6, 0.6, 0.6], [0.25, 0.45, 0.35], [0.9, 0.9, 0.9]])
+    got = udf.at(V, F, P, 1.0)
+    seg = lambda p, a, b: np.linalg.norm(p - (a + np.clip(np.dot(p - a, b - a) / np.dot(b - a, b - a), 0, 1) * (b - a)))
+    for p, g_ in zip(P, got):
+        want = min(seg(p, V[0], V[2]), seg(p, V[3], V[0]))
+        assert abs(g_ - want) <= 1e-15
+    assert got[0] <= 1e-15 and got[1] <= 1e-15
