@@ -193,6 +193,22 @@ pamo_status pamo_simplify_batch(pamo_ctx* ctx, int32_t nmesh, const double* V, c
                                 const int32_t* F, const int64_t* f_off, const int64_t* targets, double* V_out,
                                 int64_t* v_out_off, int32_t* F_out, int64_t* f_out_off, pamo_stats* stats);
 
+/* ---- remeshing (the stage before the path), mesh-to-volume step ---- */
+
+/* The unsigned distance field of a triangle soup in a narrow band (Sec. 4.1,
+ * Mesh-to-Volume): at the centre ((i + 1/2) / res, (j + 1/2) / res,
+ * (k + 1/2) / res) of every voxel of a res^3 grid over [0,1]^3,
+ * udf[(i * res + j) * res + k] = the smallest float64 distance from the centre
+ * to any triangle of (V, F) when it is at most `band`, else +infinity (the
+ * paper keeps a band of 3 / res).  V: device float64 [nv][3], F: device int32
+ * [nf][3] (any soup: no manifoldness or orientation is assumed; nf may be 0);
+ * udf: device float64 [res^3], written whole.  res in [1, 2048], band > 0.
+ * Fails with PAMO_ERR_ARG on an index outside [0, nv) and PAMO_ERR_CAPACITY when
+ * one triangle's banded box covers more than 2^20 tiles of 4^3 voxels.
+ * Synchronises the stream. */
+pamo_status pamo_udf(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf, int32_t res,
+                     double band, double* udf);
+
 /* ---- utilities ---- */
 
 /* All pairs (t < u) of faces that intersect under the test of Sec. 5.2 /

@@ -17,6 +17,7 @@
 
 #include "internal.hpp"
 #include "learn.hpp"
+#include "remesh.hpp"
 #include "round.hpp"
 #include "exact_dev.hpp"
 
@@ -167,6 +168,7 @@ void check_err_bits(int e) {
   if (e & PAMO_EBIT_RING) fail(PAMO_ERR_NONMANIFOLD, "a vertex star is corrupt or too long");
   if (e & PAMO_EBIT_STACK) fail(PAMO_ERR_CAPACITY, "BVH traversal stack overflow");
   if (e & PAMO_EBIT_DEFER) fail(PAMO_ERR_CAPACITY, "too many pairs for the exact predicate");
+  if (e & PAMO_EBIT_TILES) fail(PAMO_ERR_CAPACITY, "a triangle's band reaches too many tiles of the grid");
   fail(PAMO_ERR_HIP, "unknown device error");
 }
 
@@ -1628,6 +1630,30 @@ pamo_status pamo_hausdorff(pamo_ctx* c, const double* P, int64_t np, const doubl
     PAMO_HIP(hipMemcpyAsync(&hb, bits, sizeof(hb), hipMemcpyDeviceToHost, s));
     PAMO_HIP(hipStreamSynchronize(s));
     memcpy(dmax, &hb, sizeof(double));
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_udf(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F, int64_t nf, int32_t res, double band,
+                     double* udf) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!udf || (nf > 0 && (!V || !F))) fail(PAMO_ERR_ARG, "null pointer");
+    if (nv < 0 || nf < 0 || nf > (int64_t)(INT32_MAX / 3) - 1 || (nf > 0 && nv < 1)) fail(PAMO_ERR_ARG, "bad sizes");
+    if (res < 1 || res > 2048) fail(PAMO_ERR_ARG, "grid resolution outside [1, 2048]");
+    if (!(band > 0.0) || !(band < INFINITY)) fail(PAMO_ERR_ARG, "band width must be positive and finite");
+    hipStream_t s = c->stream;
+    fill_i32(s, c->dcnt, C_COUNT, 0);
+    if (nf > 0) {
+      hipLaunchKernelGGL(k_check_index, dim3(nblk(3 * nf)), dim3(256), 0, s, F, 3 * nf, (int)nv, c->dcnt + C_ERR);
+      check_err_bits(readback(c)[C_ERR]);
+    }
+    udf_run(c->ws, s, V, F, (int)nf, res, band, udf, c->dcnt + C_ERR, [&](const unsigned long long* total) {
+      unsigned long long t = 0;
+      PAMO_HIP(hipMemcpyAsync(&t, total, sizeof(t), hipMemcpyDeviceToHost, s));
+      check_err_bits(readback(c)[C_ERR]);  // synchronises
+      return (int64_t)t;
+    });
+    PAMO_HIP(hipStreamSynchronize(s));
     return PAMO_OK;
   });
 }

@@ -131,6 +131,46 @@ PAMO_HD __forceinline__ uint64_t cost_code64(double cost) {
   return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
 }
 
+// squared distance from p to triangle abc (closest point by the region
+// tests of the Voronoi regions of the triangle's features; may be NaN for a
+// triangle of zero area)
+__device__ __forceinline__ double tri_dist2(P3 p, P3 a, P3 b, P3 c) {
+  double abx = b.x - a.x, aby = b.y - a.y, abz = b.z - a.z;
+  double acx = c.x - a.x, acy = c.y - a.y, acz = c.z - a.z;
+  double apx = p.x - a.x, apy = p.y - a.y, apz = p.z - a.z;
+  double d1 = abx * apx + aby * apy + abz * apz, d2 = acx * apx + acy * apy + acz * apz;
+  P3 q;
+  if (d1 <= 0.0 && d2 <= 0.0) {
+    q = a;
+  } else {
+    double bpx = p.x - b.x, bpy = p.y - b.y, bpz = p.z - b.z;
+    double d3 = abx * bpx + aby * bpy + abz * bpz, d4 = acx * bpx + acy * bpy + acz * bpz;
+    double cpx = p.x - c.x, cpy = p.y - c.y, cpz = p.z - c.z;
+    double d5 = abx * cpx + aby * cpy + abz * cpz, d6 = acx * cpx + acy * cpy + acz * cpz;
+    double vc = d1 * d4 - d3 * d2, vb = d5 * d2 - d1 * d6, va = d3 * d6 - d5 * d4;
+    if (d3 >= 0.0 && d4 <= d3) {
+      q = b;
+    } else if (d6 >= 0.0 && d5 <= d6) {
+      q = c;
+    } else if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+      double v = d1 / (d1 - d3);
+      q = P3{a.x + v * abx, a.y + v * aby, a.z + v * abz};
+    } else if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+      double v = d2 / (d2 - d6);
+      q = P3{a.x + v * acx, a.y + v * acy, a.z + v * acz};
+    } else if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {
+      double v = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+      q = P3{b.x + v * (c.x - b.x), b.y + v * (c.y - b.y), b.z + v * (c.z - b.z)};
+    } else {
+      double den = 1.0 / (va + vb + vc);
+      double v = vb * den, w = vc * den;
+      q = P3{a.x + abx * v + acx * w, a.y + aby * v + acy * w, a.z + abz * v + acz * w};
+    }
+  }
+  double dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+  return dx * dx + dy * dy + dz * dz;
+}
+
 // Sorted insertion of x into a[0..CAP) kept ascending with INT_MAX padding.
 // Fully unrolled so the list stays in registers.
 template <int CAP>

@@ -1,0 +1,22 @@
+// The remeshing stage's mesh-to-volume step (Sec. 4.1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <functional>
+
+#include "internal.hpp"
+
+namespace pamo {
+
+// Narrow-band unsigned distance field of the soup (V, F: nf triangles, device)
+// at the voxel centres ((i + 1/2) / res, ...) of a res^3 grid, udf[(i res + j)
+// res + k]: the smallest point-triangle distance when it is at most band,
+// else +inf.  read_total synchronises, reads the 64-bit pair count from the
+// device and checks the error bits (err: PAMO_EBIT_TILES when a triangle's
+// banded box covers too many tiles).
+void udf_run(Workspace& ws, hipStream_t s, const double* V, const int* F, int nf, int res, double band, double* udf,
+             int* err, const std::function<int64_t(const unsigned long long*)>& read_total);
+
+}  // namespace pamo

@@ -11,6 +11,7 @@
 #define PAMO_EBIT_RING 32        // a vertex star longer than the walk guard
 #define PAMO_EBIT_STACK 64       // BVH traversal stack overflow
 #define PAMO_EBIT_DEFER 128      // deferred exact-pair list overflow
+#define PAMO_EBIT_TILES 256      // a triangle of the distance field reaches too many tiles
 
 namespace pamo {
 

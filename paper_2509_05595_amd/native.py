@@ -21,7 +21,8 @@ ERRORS = {-1: "ARG", -2: "NONMANIFOLD", -3: "SELF_INTERSECTING", -4: "DEGENERATE
 EXPORTS = ["pamo_default_options", "pamo_create", "pamo_destroy", "pamo_set_options", "pamo_last_error",
            "pamo_workspace_bytes", "pamo_quadrics", "pamo_select", "pamo_check", "pamo_collapse",
            "pamo_simplify", "pamo_simplify_batch", "pamo_set_mlp", "pamo_features", "pamo_mlp_logits",
-           "pamo_collect", "pamo_mlp_grad", "pamo_mlp_train", "pamo_hausdorff", "pamo_self_intersections", "pamo_tri_pairs", "pamo_profile_enable",
+           "pamo_collect", "pamo_mlp_grad", "pamo_mlp_train", "pamo_hausdorff", "pamo_self_intersections", "pamo_tri_pairs",
+           "pamo_udf", "pamo_profile_enable",
            "pamo_profile_phases", "pamo_profile_name", "pamo_profile_read", "pamo_profile_reset"]
 
 
@@ -113,6 +114,7 @@ def lib():
         L.pamo_mlp_train.argtypes = [P, P, P, P, P, P, P, I64, P, I64, I64, C.c_float, I64, P]
         L.pamo_hausdorff.argtypes = [P, P, I64, P, I64, P, I64, P, C.POINTER(C.c_double)]
         L.pamo_self_intersections.argtypes = [P, P, I64, P, I64, P, I64, C.POINTER(I64)]
+        L.pamo_udf.argtypes = [P, P, I64, P, I64, C.c_int32, C.c_double, P]
         L.pamo_tri_pairs.argtypes = [P, P, P, P, P, I64, P]
         L.pamo_profile_enable.argtypes = [P, C.c_uint32]
         L.pamo_profile_phases.argtypes = []
@@ -335,6 +337,15 @@ class Context:
         self._check(lib().pamo_self_intersections(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(pairs),
                                                   cap, C.byref(n)))
         return pairs[: min(cap, n.value)], n.value
+
+    def udf(self, V, F, res, band=None):
+        """Narrow-band unsigned distance field (res, res, res) float64 at the voxel
+        centres of [0,1]^3 (+inf beyond the band, default 3 / res)."""
+        V, F = self._mesh(V, F)
+        band = 3.0 / res if band is None else float(band)
+        out = torch.empty((res, res, res), dtype=torch.float64, device=self.device)
+        self._check(lib().pamo_udf(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], int(res), band, _ptr(out)))
+        return out
 
     # ---- measurement
     @staticmethod
