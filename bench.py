@@ -193,6 +193,35 @@ def whole_mesh_check(native, torch, dev, reps=5):
                         f"{reps} calls including the count read-back", "rows": rows}
 
 
+def remesh_udf(native, torch, dev, reps=5):
+    """The remeshing stage's mesh-to-volume step (pamo_udf, Sec. 4.1): the
+    narrow-band unsigned distance field (band 3 / R) of noisy icospheres at the
+    voxel centres of R^3 grids.  The paper remeshes meshes of over 100k
+    vertices in about 3 ms on another GPU, this step and the surface
+    extraction together (context, not the target)."""
+    from paper_2509_05595_amd import meshgen
+    ctx = native.Context(dev)
+    rows = []
+    for k, res in ((7, 256), (7, 512), (8, 512)):
+        V, F = meshgen.noisy_icosphere(k, 2)
+        Vd, Fd = torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev)
+        U = ctx.udf(Vd, Fd, res)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            U = ctx.udf(Vd, Fd, res)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        ms = sorted(times)[len(times) // 2] * 1e3
+        rows.append({"faces": int(len(F)), "vertices": int(len(V)), "res": res, "ms": ms,
+                     "voxels_in_band": int(torch.isfinite(U).sum())})
+        log(f"distance field {len(F)} faces at {res}^3: {ms:.2f} ms")
+    ctx.close()
+    return {"workload": "noisy icospheres (seed 2), narrow-band unsigned distance field at voxel centres, band 3/R, "
+                        f"median of {reps} calls", "rows": rows}
+
+
 def sharp_feature(native, torch, dev, steps):
     """Crease sphere (icosphere refined 9x, 5,242,880 faces, radius
     1 + 0.03|sin 12 theta||sin 9 phi| + 0.002 N(0,1)) to 0.1%, in one batch with 32
@@ -248,6 +277,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-versus-plain comparison")
     ap.add_argument("--no-sharp", action="store_true", help="skip the sharp-feature batch")
     ap.add_argument("--no-check", action="store_true", help="skip the whole-mesh self-intersection check")
+    ap.add_argument("--no-udf", action="store_true", help="skip the remeshing distance-field measurement")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
@@ -348,6 +378,8 @@ def main():
         out["sharp_feature_batch"] = sharp_feature(native, torch, dev, 1)
     if not args.no_check:
         out["whole_mesh_check"] = whole_mesh_check(native, torch, dev)
+    if not args.no_udf:
+        out["remesh_udf"] = remesh_udf(native, torch, dev)
     if not args.no_cpu_baseline and args.gpus == 1:
         out["cpu_baseline"] = cpu_baseline()
         log("cpu baseline timed")
