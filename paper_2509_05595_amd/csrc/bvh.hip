@@ -119,7 +119,8 @@ __device__ __forceinline__ BvhNode make_node(const Box* c, int4 leaf) {
 // records of heights h0+1 .. h0+lv and the box of its subtree root to top[b].
 __global__ __launch_bounds__(LVL_T) void k_levels(const float* __restrict__ leafbox, const int* __restrict__ sorted,
                                                   int n, const Box* __restrict__ in, int cnt, Box* __restrict__ top,
-                                                  int h0, int lv, int D, BvhNode* __restrict__ nodes) {
+                                                  int h0, int lv, int D, BvhNode* __restrict__ nodes,
+                                                  const int* __restrict__ owner) {
   __shared__ Box sb[1 << (2 * LVL)];
   __shared__ int sf[1 << (2 * LVL)];
   const int M = 1 << (2 * lv);
@@ -133,6 +134,7 @@ __global__ __launch_bounds__(LVL_T) void k_levels(const float* __restrict__ leaf
         f = sorted[j];
         const float* p = leafbox + 6 * (int64_t)f;
         b = Box{{p[0], p[1], p[2]}, {p[3], p[4], p[5]}};
+        if (owner && owner[f] >= 0) f |= LEAF_CHANGED;  // a face the round changed
       }
     } else if (j < cnt) {
       b = in[j];
@@ -337,6 +339,18 @@ __device__ __forceinline__ int child_hits(const BvhNode& nd, const float* b) {
   return m;
 }
 
+// A leaf hit of query t (a changed face in the first pass): its face id, and
+// whether to stage it.  Two changed faces meet in both their queries; the
+// query of the smaller one takes the pair (unless every overlap of t is
+// counted for the learned proposal's overlap counts).
+template <int MODE>
+__device__ __forceinline__ bool leaf_take(const QueryArgs& a, int hit, int v, int t, int& u) {
+  u = v & LEAF_ID;
+  if (!hit || v < 0 || u == t) return false;
+  if (MODE == QUERY_CHANGED && !a.ovl_cnt && (v & LEAF_CHANGED) && u < t) return false;
+  return true;
+}
+
 // Wave-cooperative traversal in packets of G lanes.  The query list is in
 // Morton order, so the G queries of a packet are neighbours; each packet walks
 // the tree once (its lanes load the same node: one coalesced request),
@@ -346,7 +360,8 @@ __device__ __forceinline__ int child_hits(const BvhNode& nd, const float* b) {
 // depth.  At a node of the last internal level every lane tests its own box
 // against the four leaves; hits are staged per wave in LDS and flushed with one
 // atomic per ~200 pairs.  The traversal does no data-dependent loads besides
-// the nodes: the state filters run in the pair kernel.
+// the nodes: the state filters run in the pair kernel, except the one the
+// leaf records carry (leaf_take).
 template <int MODE, int G>
 __global__ __launch_bounds__(64 * WPB) void k_collect(const BvhNode* __restrict__ nodes, int D, int n,
                                                       const int* __restrict__ qlist, const int* __restrict__ nq,
@@ -423,10 +438,15 @@ __global__ __launch_bounds__(64 * WPB) void k_collect(const BvhNode* __restrict_
       }
       node = next;
     }
-    stage_append(st, (hit & 1) && lf.x >= 0 && lf.x != t, t, lf.x, a.cand, a.ncand, a.cand_cap);
-    stage_append(st, (hit & 2) && lf.y >= 0 && lf.y != t, t, lf.y, a.cand, a.ncand, a.cand_cap);
-    stage_append(st, (hit & 4) && lf.z >= 0 && lf.z != t, t, lf.z, a.cand, a.ncand, a.cand_cap);
-    stage_append(st, (hit & 8) && lf.w >= 0 && lf.w != t, t, lf.w, a.cand, a.ncand, a.cand_cap);
+    {
+      int u0, u1, u2, u3;
+      const bool k0 = leaf_take<MODE>(a, hit & 1, lf.x, t, u0), k1 = leaf_take<MODE>(a, hit & 2, lf.y, t, u1);
+      const bool k2 = leaf_take<MODE>(a, hit & 4, lf.z, t, u2), k3 = leaf_take<MODE>(a, hit & 8, lf.w, t, u3);
+      stage_append(st, k0, t, u0, a.cand, a.ncand, a.cand_cap);
+      stage_append(st, k1, t, u1, a.cand, a.ncand, a.cand_cap);
+      stage_append(st, k2, t, u2, a.cand, a.ncand, a.cand_cap);
+      stage_append(st, k3, t, u3, a.cand, a.ncand, a.cand_cap);
+    }
   }
   stage_flush(st, a.cand, a.ncand, a.cand_cap);
 }
@@ -508,10 +528,15 @@ __global__ __launch_bounds__(64 * WPB) void k_collect_coop(const BvhNode* __rest
       sp = 0;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    stage_append(st, (hit & 1) && lf.x >= 0 && lf.x != t, t, lf.x, a.cand, a.ncand, a.cand_cap);
-    stage_append(st, (hit & 2) && lf.y >= 0 && lf.y != t, t, lf.y, a.cand, a.ncand, a.cand_cap);
-    stage_append(st, (hit & 4) && lf.z >= 0 && lf.z != t, t, lf.z, a.cand, a.ncand, a.cand_cap);
-    stage_append(st, (hit & 8) && lf.w >= 0 && lf.w != t, t, lf.w, a.cand, a.ncand, a.cand_cap);
+    {
+      int u0, u1, u2, u3;
+      const bool k0 = leaf_take<MODE>(a, hit & 1, lf.x, t, u0), k1 = leaf_take<MODE>(a, hit & 2, lf.y, t, u1);
+      const bool k2 = leaf_take<MODE>(a, hit & 4, lf.z, t, u2), k3 = leaf_take<MODE>(a, hit & 8, lf.w, t, u3);
+      stage_append(st, k0, t, u0, a.cand, a.ncand, a.cand_cap);
+      stage_append(st, k1, t, u1, a.cand, a.ncand, a.cand_cap);
+      stage_append(st, k2, t, u2, a.cand, a.ncand, a.cand_cap);
+      stage_append(st, k3, t, u3, a.cand, a.ncand, a.cand_cap);
+    }
   }
   stage_flush(st, a.cand, a.ncand, a.cand_cap);
 }
@@ -563,7 +588,7 @@ __global__ __launch_bounds__(64) void k_resolve(QueryArgs a) {
 }  // namespace
 
 Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf, const int* order, const int* fmesh,
-              int nmesh) {
+              int nmesh, const int* owner) {
   Bvh b;
   b.n = nf;
   int D = 1;
@@ -601,7 +626,7 @@ Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf, const int*
     const int lv = D - h0 < LVL ? D - h0 : LVL;
     const int64_t blocks = (cnt + (1ll << (2 * lv)) - 1) >> (2 * lv);
     hipLaunchKernelGGL(k_levels, dim3((unsigned)blocks), dim3(LVL_T), 0, s, box, id, nf, in, (int)cnt, out, h0, lv, D,
-                       b.nodes);
+                       b.nodes, owner);
     in = out;
     out = out == ta ? tb : ta;
     cnt = blocks;
