@@ -419,7 +419,7 @@ bool check_launch(pamo_ctx* c, MeshView m, const RoundBufs& b, const int* cand, 
   }
   {
     TIMED(PH_BVH, 24 * nf + 128.0 * bvh_nodes_written(m.nf));
-    K.bvh = build_bvh(c->ws, s, b.box, m.nf, order, m.fmesh, nmesh, b.owner);
+    K.bvh = build_bvh(c->ws, s, b.box, m.nf, order, m.fmesh, nmesh, b.owner, b.falive);
   }
   {
     TIMED(PH_FACELIST, 8 * nf);

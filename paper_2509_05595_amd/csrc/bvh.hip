@@ -120,7 +120,7 @@ __device__ __forceinline__ BvhNode make_node(const Box* c, int4 leaf) {
 __global__ __launch_bounds__(LVL_T) void k_levels(const float* __restrict__ leafbox, const int* __restrict__ sorted,
                                                   int n, const Box* __restrict__ in, int cnt, Box* __restrict__ top,
                                                   int h0, int lv, int D, BvhNode* __restrict__ nodes,
-                                                  const int* __restrict__ owner) {
+                                                  const int* __restrict__ owner, const uint8_t* __restrict__ falive) {
   __shared__ Box sb[1 << (2 * LVL)];
   __shared__ int sf[1 << (2 * LVL)];
   const int M = 1 << (2 * lv);
@@ -134,7 +134,8 @@ __global__ __launch_bounds__(LVL_T) void k_levels(const float* __restrict__ leaf
         f = sorted[j];
         const float* p = leafbox + 6 * (int64_t)f;
         b = Box{{p[0], p[1], p[2]}, {p[3], p[4], p[5]}};
-        if (owner && owner[f] >= 0) f |= LEAF_CHANGED;  // a face the round changed
+        const bool chg = owner && owner[f] >= 0, dead = falive && !falive[f];
+        f |= (chg ? LEAF_CHANGED : 0) | (dead ? LEAF_DEAD : 0);
       }
     } else if (j < cnt) {
       b = in[j];
@@ -340,13 +341,16 @@ __device__ __forceinline__ int child_hits(const BvhNode& nd, const float* b) {
 }
 
 // A leaf hit of query t (a changed face in the first pass): its face id, and
-// whether to stage it.  Two changed faces meet in both their queries; the
-// query of the smaller one takes the pair (unless every overlap of t is
-// counted for the learned proposal's overlap counts).
+// whether to stage it.  In the first pass a deleted face meets nothing, and
+// two changed faces meet in both their queries: the query of the smaller one
+// takes the pair (unless every overlap of t is counted for the learned
+// proposal's overlap counts).  Later passes (faces restored) use the state
+// arrays in the pair kernel only.
 template <int MODE>
 __device__ __forceinline__ bool leaf_take(const QueryArgs& a, int hit, int v, int t, int& u) {
   u = v & LEAF_ID;
   if (!hit || v < 0 || u == t) return false;
+  if (MODE == QUERY_CHANGED && (v & LEAF_DEAD)) return false;
   if (MODE == QUERY_CHANGED && !a.ovl_cnt && (v & LEAF_CHANGED) && u < t) return false;
   return true;
 }
@@ -588,7 +592,7 @@ __global__ __launch_bounds__(64) void k_resolve(QueryArgs a) {
 }  // namespace
 
 Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf, const int* order, const int* fmesh,
-              int nmesh, const int* owner) {
+              int nmesh, const int* owner, const uint8_t* falive) {
   Bvh b;
   b.n = nf;
   int D = 1;
@@ -626,7 +630,7 @@ Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf, const int*
     const int lv = D - h0 < LVL ? D - h0 : LVL;
     const int64_t blocks = (cnt + (1ll << (2 * lv)) - 1) >> (2 * lv);
     hipLaunchKernelGGL(k_levels, dim3((unsigned)blocks), dim3(LVL_T), 0, s, box, id, nf, in, (int)cnt, out, h0, lv, D,
-                       b.nodes, owner);
+                       b.nodes, owner, falive);
     in = out;
     out = out == ta ? tb : ta;
     cnt = blocks;

@@ -142,8 +142,9 @@ struct __align__(16) BvhNode {
 // children 4k+1 .. 4k+4; slot j of the leaves is child j % 4 of the node at
 // position j / 4 of level D - 1.  Nodes whose leaves all lie past n are never
 // entered (their parents record them as empty) and are not written.
-constexpr int LEAF_CHANGED = 1 << 30;  // leaf record flag: the face was changed this round
-constexpr int LEAF_ID = LEAF_CHANGED - 1;
+constexpr int LEAF_CHANGED = 1 << 30;  // leaf record flags: the face was changed this round,
+constexpr int LEAF_DEAD = 1 << 29;     // the face was deleted by a tentative collapse
+constexpr int LEAF_ID = LEAF_DEAD - 1;
 constexpr int BVH_DMAX = 14;  // 4^14 leaf slots; stack entries pack a node index below 2^27
 struct Bvh {
   BvhNode* nodes;
@@ -190,10 +191,11 @@ inline int64_t bvh_nodes_written(int64_t nf) {
   }
   return total;
 }
-// owner (may be null): leaves of faces with owner[f] >= 0 carry LEAF_CHANGED
-// in their record (face id = record & LEAF_ID)
+// owner, falive (may be null): leaves of faces with owner[f] >= 0 carry
+// LEAF_CHANGED, those with falive[f] == 0 LEAF_DEAD in their record (face id =
+// record & LEAF_ID); the flags hold for the first check pass of the round
 Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf, const int* order, const int* fmesh = nullptr,
-              int nmesh = 1, const int* owner = nullptr);
+              int nmesh = 1, const int* owner = nullptr, const uint8_t* falive = nullptr);
 // new leaf order after a stable compaction: keep the alive faces of `order`
 // in sequence, renamed by fmap
 void launch_remap_order(Workspace& ws, hipStream_t s, const int* order, int nf_old, const uint8_t* falive,
