@@ -340,18 +340,21 @@ __device__ __forceinline__ int child_hits(const BvhNode& nd, const float* b) {
   return m;
 }
 
-// A leaf hit of query t (a changed face in the first pass): its face id, and
-// whether to stage it.  In the first pass a deleted face meets nothing, and
-// two changed faces meet in both their queries: the query of the smaller one
-// takes the pair (the pair kernel then counts the overlap for both faces when
-// the learned proposal's overlap counts are kept).  Later passes (faces
-// restored) use the state arrays in the pair kernel only.
+// A leaf hit of query t (a changed face in the first pass, any face in the
+// whole-mesh check): its face id, and whether to stage it.  In the first pass
+// a deleted face meets nothing, and two changed faces meet in both their
+// queries: the query of the smaller one takes the pair; in the whole-mesh
+// check every pair is met twice and the smaller face takes it.  The pair
+// kernel then counts the overlap for both faces when the learned proposal's
+// overlap counts are kept.  Later passes (faces restored) use the state
+// arrays in the pair kernel only.
 template <int MODE>
 __device__ __forceinline__ bool leaf_take(const QueryArgs& a, int hit, int v, int t, int& u) {
   u = v & LEAF_ID;
   if (!hit || v < 0 || u == t) return false;
   if (MODE == QUERY_CHANGED && (v & LEAF_DEAD)) return false;
   if (MODE == QUERY_CHANGED && (v & LEAF_CHANGED) && u < t) return false;
+  if (MODE == QUERY_ALL_PAIRS && u < t) return false;
   return true;
 }
 
@@ -561,9 +564,10 @@ __global__ __launch_bounds__(256, 5) void k_pairs(QueryArgs a) {
     if (a.ovl_cnt && (!a.falive || a.falive[pr.y]) && (!a.fmesh || a.fmesh[pr.y] == a.fmesh[pr.x]) &&
         !share_vertex(T, U) && tri_box_overlap(T, U)) {
       atomicAdd(&a.ovl_cnt[pr.x], 1);
-      // a changed partner's own query left this pair to the smaller face: it
-      // counts here too (the overlap test is symmetric)
-      if (MODE == QUERY_CHANGED && a.owner[pr.y] >= 0) atomicAdd(&a.ovl_cnt[pr.y], 1);
+      // a partner whose own query left this pair to the smaller face (a changed
+      // face; any face in the whole-mesh check) counts here too (the overlap
+      // test is symmetric)
+      if ((MODE == QUERY_CHANGED && a.owner[pr.y] >= 0) || MODE == QUERY_ALL_PAIRS) atomicAdd(&a.ovl_cnt[pr.y], 1);
     }
     if (!leaf_candidate<MODE>(a, pr.x, pr.y)) continue;
     if (!tri_box_overlap(T, U)) continue;
