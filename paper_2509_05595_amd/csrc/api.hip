@@ -1651,6 +1651,7 @@ pamo_status pamo_udf(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F,
       unsigned long long t = 0;
       PAMO_HIP(hipMemcpyAsync(&t, total, sizeof(t), hipMemcpyDeviceToHost, s));
       check_err_bits(readback(c)[C_ERR]);  // synchronises
+      if (t > (unsigned long long)INT32_MAX - 1) fail(PAMO_ERR_CAPACITY, "too many tile-triangle pairs for the grid");
       return (int64_t)t;
     });
     PAMO_HIP(hipStreamSynchronize(s));

@@ -12,8 +12,6 @@
 // minimum over all triangles whenever that minimum lies inside the band.
 #include <math.h>
 
-#include <stdexcept>
-
 #include "internal.hpp"
 #include "mesh_dev.hpp"
 #include "remesh.hpp"
@@ -199,8 +197,7 @@ void udf_run(Workspace& ws, hipStream_t s, const double* V, const int* F, int nf
   unsigned long long* total = ws.get<unsigned long long>("udf.total", 1);
   fill_i32(s, reinterpret_cast<int32_t*>(total), 2, 0);
   hipLaunchKernelGGL(k_udf_count, dim3(nblk(nf)), dim3(256), 0, s, g, V, F, nf, cnt, total, err);
-  const int64_t np = read_total(total);  // also checks the error bits
-  if (np > (int64_t)INT32_MAX - 1) throw std::runtime_error("udf: too many tile-triangle pairs");
+  const int64_t np = read_total(total);  // also checks the error bits and the int32 range
   if (np == 0) return;
   scan_exclusive(ws, s, cnt, off, nf, nullptr);
   uint32_t* tile = ws.get<uint32_t>("udf.tile", np);

@@ -14,8 +14,8 @@ namespace pamo {
 // at the voxel centres ((i + 1/2) / res, ...) of a res^3 grid, udf[(i res + j)
 // res + k]: the smallest point-triangle distance when it is at most band,
 // else +inf.  read_total synchronises, reads the 64-bit pair count from the
-// device and checks the error bits (err: PAMO_EBIT_TILES when a triangle's
-// banded box covers too many tiles).
+// device, checks the error bits (err: PAMO_EBIT_TILES when a triangle's
+// banded box covers too many tiles) and that the count fits int32.
 void udf_run(Workspace& ws, hipStream_t s, const double* V, const int* F, int nf, int res, double band, double* udf,
              int* err, const std::function<int64_t(const unsigned long long*)>& read_total);
 
