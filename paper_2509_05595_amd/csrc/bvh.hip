@@ -206,7 +206,7 @@ template <int MODE>
 __device__ __forceinline__ void mark(const QueryArgs& a, int t, int u) {
   if (MODE == QUERY_ALL_PAIRS) {
     int k = atomicAdd(a.npairs, 1);
-    if (k < a.pairs_cap) a.pairs[k] = make_int2(t, u);
+    if (k < a.pairs_cap) a.pairs[k] = t < u ? make_int2(t, u) : make_int2(u, t);
     return;
   }
   if (MODE == QUERY_CHANGED) {
@@ -223,7 +223,7 @@ __device__ __forceinline__ bool leaf_candidate(const QueryArgs& a, int t, int u)
   if (u == t) return false;
   if (a.falive && !a.falive[u]) return false;
   if (a.fmesh && a.fmesh[u] != a.fmesh[t]) return false;  // batches: meshes never meet
-  if (MODE == QUERY_ALL_PAIRS) return u > t;
+  if (MODE == QUERY_ALL_PAIRS) return true;  // staged once per pair (later_children)
   int ou = a.owner[u];
   if (MODE == QUERY_CHANGED) {
     // both changed: the query of the smaller face takes the pair
@@ -340,11 +340,27 @@ __device__ __forceinline__ int child_hits(const BvhNode& nd, const float* b) {
   return m;
 }
 
+// Whole-mesh check: the query list is the leaf order, so query i is leaf i.
+// Each pair is found by the query of its earlier leaf: the children of node
+// (level L, in-level index k) whose leaves all come at or before leaf i are
+// skipped (child c holds leaves [(4k + c) 4^(D-L-1), (4k + c + 1) 4^(D-L-1))).
+template <int MODE>
+__device__ __forceinline__ int later_children(int node, int D, int64_t i) {
+  if (MODE != QUERY_ALL_PAIRS) return 15;
+  const int L = node_level(node);
+  const int64_t k = node - ((((int64_t)1) << (2 * L)) - 1) / 3;
+  const int sh = 2 * (D - L - 1);
+  int m = 0;
+#pragma unroll
+  for (int c = 0; c < 4; c++) m |= (((4 * k + c + 1) << sh) > i + 1) << c;
+  return m;
+}
+
 // A leaf hit of query t (a changed face in the first pass, any face in the
 // whole-mesh check): its face id, and whether to stage it.  In the first pass
 // a deleted face meets nothing, and two changed faces meet in both their
 // queries: the query of the smaller one takes the pair; in the whole-mesh
-// check every pair is met twice and the smaller face takes it.  The pair
+// check the query of the earlier leaf takes it (later_children).  The pair
 // kernel then counts the overlap for both faces when the learned proposal's
 // overlap counts are kept.  Later passes (faces restored) use the state
 // arrays in the pair kernel only.
@@ -354,7 +370,6 @@ __device__ __forceinline__ bool leaf_take(const QueryArgs& a, int hit, int v, in
   if (!hit || v < 0 || u == t) return false;
   if (MODE == QUERY_CHANGED && (v & LEAF_DEAD)) return false;
   if (MODE == QUERY_CHANGED && (v & LEAF_CHANGED) && u < t) return false;
-  if (MODE == QUERY_ALL_PAIRS && u < t) return false;
   return true;
 }
 
@@ -408,16 +423,17 @@ __global__ __launch_bounds__(64 * WPB) void k_collect(const BvhNode* __restrict_
     if (!done) {
       const BvhNode nd = nodes[node];
       int next = -1;
+      const int later = later_children<MODE>(node, D, i);
       if (node_level(node) == D - 1) {  // the children are leaves
-        hit = child_hits(nd, tb);
+        hit = child_hits(nd, tb) & later;
         lf = nd.leaf;
       } else {
         int pm;
         if (G == 1) {
-          pm = child_hits(nd, tb);
+          pm = child_hits(nd, tb) & later;
         } else {
           const int um = child_hits(nd, ub);  // uniform over the packet
-          const int own = um ? child_hits(nd, tb) : 0;
+          const int own = um ? child_hits(nd, tb) & later : 0;
           pm = 0;
 #pragma unroll
           for (int c = 0; c < 4; c++) pm |= ((__ballot((own >> c) & 1) & gmask) != 0) << c;
@@ -505,7 +521,7 @@ __global__ __launch_bounds__(64 * WPB) void k_collect_coop(const BvhNode* __rest
     int4 lf = make_int4(-1, -1, -1, -1);
     if (node >= 0) {
       const BvhNode nd = nodes[node];
-      const int m = child_hits(nd, tb);
+      const int m = child_hits(nd, tb) & later_children<MODE>(node, D, q);
       if (node_level(node) == D - 1) {
         hit = m;
         lf = nd.leaf;
