@@ -278,6 +278,8 @@ def main():
     ap.add_argument("--no-sharp", action="store_true", help="skip the sharp-feature batch")
     ap.add_argument("--no-check", action="store_true", help="skip the whole-mesh self-intersection check")
     ap.add_argument("--no-udf", action="store_true", help="skip the remeshing distance-field measurement")
+    ap.add_argument("--only", choices=["check", "udf"], default=None,
+                    help="run only that section (whole-mesh check or distance field) and print its JSON")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
@@ -300,6 +302,12 @@ def main():
         log(f"copied {4 << 28} bytes three times")
         return
     from paper_2509_05595_amd import meshgen, native
+
+    if args.only:  # one section alone (for kernel profiles of its workload)
+        dev = torch.device("cuda:0")
+        res = whole_mesh_check(native, torch, dev) if args.only == "check" else remesh_udf(native, torch, dev)
+        print(json.dumps(res), flush=True)
+        return
 
     V, F = meshgen.noisy_icosphere(args.refine, 2)
     log("mesh generated")

@@ -142,12 +142,15 @@ __global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
 }
 
 // one wave per tile with pairs: each lane one voxel, the tile's triangles
-// staged 64 at a time
+// staged 64 at a time with their bounding spheres.  A triangle whose sphere
+// lies farther than the best distance so far (or than the band) by a margin
+// far above rounding cannot lower the minimum and is skipped, so the result
+// is the same as testing every triangle.
 __global__ __launch_bounds__(64) void k_udf_tiles(Grid g, const double* __restrict__ V, const int* __restrict__ F,
                                                   const uint32_t* __restrict__ tile, const int* __restrict__ tri,
                                                   int npairs, const int* __restrict__ runs,
                                                   const int* __restrict__ nruns, double* __restrict__ udf) {
-  __shared__ double tv[64][9];
+  __shared__ double tv[64][13];  // corners, centre, radius
   const int r = blockIdx.x;
   if (r >= *nruns) return;  // uniform over the block
   const int s = runs[r], e = r + 1 < *nruns ? runs[r + 1] : npairs;
@@ -156,21 +159,33 @@ __global__ __launch_bounds__(64) void k_udf_tiles(Grid g, const double* __restri
   const int l = threadIdx.x;
   const int i = UT * tx + l / (UT * UT), j = UT * ty + l / UT % UT, k = UT * tz + l % UT;
   const P3 p{centre(g, i), centre(g, j), centre(g, k)};
-  double best = INFINITY;
+  const double margin = 1e-9 * (g.band + 1.0);
+  double best = INFINITY;       // squared
+  double cut = g.band + margin;  // skip spheres beyond this distance
   for (int c0 = s; c0 < e; c0 += 64) {
     if (c0 + l < e) {
       P3 a, b, c;
       tri_corners(V, F, tri[c0 + l], a, b, c);
-      const double q[9] = {a.x, a.y, a.z, b.x, b.y, b.z, c.x, c.y, c.z};
+      const double cx = (a.x + b.x + c.x) / 3.0, cy = (a.y + b.y + c.y) / 3.0, cz = (a.z + b.z + c.z) / 3.0;
+      auto d2 = [&](P3 q) { return (q.x - cx) * (q.x - cx) + (q.y - cy) * (q.y - cy) + (q.z - cz) * (q.z - cz); };
+      const double rad = sqrt(fmax(d2(a), fmax(d2(b), d2(c))));
+      const double q[13] = {a.x, a.y, a.z, b.x, b.y, b.z, c.x, c.y, c.z, cx, cy, cz, rad};
 #pragma unroll
-      for (int m = 0; m < 9; m++) tv[l][m] = q[m];
+      for (int m = 0; m < 13; m++) tv[l][m] = q[m];
     }
     __syncthreads();
     const int n = e - c0 < 64 ? e - c0 : 64;
     for (int m = 0; m < n; m++) {
       const double* q = tv[m];
+      const double dx = p.x - q[9], dy = p.y - q[10], dz = p.z - q[11];
+      const double lim = q[12] + cut;
+      if (dx * dx + dy * dy + dz * dz > lim * lim) continue;
       const double d = soup_dist2(p, P3{q[0], q[1], q[2]}, P3{q[3], q[4], q[5]}, P3{q[6], q[7], q[8]});
-      best = d < best ? d : best;
+      if (d < best) {
+        best = d;
+        const double cd = sqrt(d) + margin;
+        cut = cd < cut ? cd : cut;
+      }
     }
     __syncthreads();
   }
