@@ -92,6 +92,32 @@ def test_round0_full_size_elementwise(ctx, mesh):
     assert np.array_equal(fl1.cpu().numpy(), r["flags"])
 
 
+@pytest.mark.parametrize("opt", [{"prefilter": 1}, {"key_mode": 1}, {"prefilter": 1, "key_mode": 1}])
+def test_rule_variants_full_size(ctx, mesh, opt):
+    """The pre-filter and the float64 key mode on the 1,310,720-face mesh: the
+    round-0 selection element by element against the oracle, and the whole run
+    to 1% checked by properties that hold at any size."""
+    from paper_2509_05595_amd import native
+    V, F, Vd, Fd = mesh
+    target = len(F) // 100
+    ctx.set_options(native.default_options(**opt))
+    try:
+        cand, _, _ = ctx.select(Vd, Fd)
+        Vo, Fo, st = ctx.simplify(Vd, Fd, target)
+    finally:
+        ctx.set_options(native.default_options())
+    co = orc.check(V, F, target, **opt)[0]
+    assert np.array_equal(np.sort(cand.cpu().numpy()), np.sort(co))
+    Fg = Fo.cpu().numpy()
+    assert st["status"] == 0 and len(Fg) == target - target % 2
+    assert euler(Fg) == 2
+    ctx.quadrics(Vo.contiguous(), Fo.contiguous())  # raises unless closed and manifold
+    _, n = ctx.self_intersections(Vo.contiguous(), Fo.contiguous())
+    assert n == 0
+    if opt.get("prefilter"):
+        assert st["rej_link"] == 0 and st["rej_flip"] == 0
+
+
 def test_round0_beyond_two_pass_scan(ctx):
     """Round 0 of a 1,568,000-face noisy geodesic sphere (4,704,000 half-edges,
     more than 1,024 scan tiles of 4,096: the compactions take their three-pass
