@@ -744,11 +744,19 @@ __device__ __forceinline__ uint8_t select_edge(const MeshView& m, const uint64_t
   return ok;
 }
 
+// A chosen edge holds the minimum key at both its ends, and a key carries its
+// edge's lower half-edge in its low 32 bits: so each vertex tests the one edge
+// its minimum names (from the edge's origin end only, once per edge), instead
+// of every half-edge testing itself.  sel must be zero on entry.
 __global__ __launch_bounds__(256) void k_select(MeshView m, const uint64_t* __restrict__ key,
                                                 const uint64_t* __restrict__ vmin, uint8_t* __restrict__ sel) {
-  int h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h >= 3 * m.nf) return;
-  sel[h] = select_edge(m, key, vmin, h);
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= m.nv) return;
+  const uint64_t k = vmin[v];
+  if (k == PAMO_KEY_MAX) return;
+  const int h = (int)(uint32_t)k;
+  if (m.F[h] != v) return;  // the other end tests it
+  if (select_edge(m, key, vmin, h)) sel[h] = 1;
 }
 
 // Re-selection after candidates were set aside (both half-edges of each got
@@ -1454,7 +1462,8 @@ void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key
   int64_t nh = 3 * (int64_t)m.nf;
   uint8_t* sel = ws.get<uint8_t>("sel", nh);
   if (!vmin_ready) hipLaunchKernelGGL(k_vertex_min, dim3(nblk(m.nv)), dim3(256), 0, s, m, key, vmin);
-  hipLaunchKernelGGL(k_select, dim3(nblk(nh)), dim3(256), 0, s, m, key, (const uint64_t*)vmin, sel);
+  fill_u8(s, sel, nh, 0);
+  hipLaunchKernelGGL(k_select, dim3(nblk(m.nv)), dim3(256), 0, s, m, key, (const uint64_t*)vmin, sel);
   compact_flags(ws, s, sel, nh, cand, ncand);
   PAMO_HIP(hipGetLastError());
 }
