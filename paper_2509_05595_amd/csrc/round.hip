@@ -763,9 +763,10 @@ __global__ __launch_bounds__(256) void k_select(MeshView m, const uint64_t* __re
 // the largest key).  A set-aside edge (a, b) changes only the vertex minima
 // of a and b, so a selection changes only for edges with an endpoint u in
 // {a, b} u N(a) u N(b), and such an edge can be chosen only if its key is
-// vmin[u]: each such u has one edge to evaluate again, the one holding its
-// minimum.  Every other edge keeps its flag of the selection before
-// (candidates' closed neighbourhoods hold no endpoint of another candidate,
+// vmin[u]: each such u has one edge to evaluate again, the one its minimum
+// names (a key carries its edge's lower half-edge in the low 32 bits).  Every
+// other edge keeps its flag of the selection before (candidates' closed
+// neighbourhoods hold no endpoint of another candidate,
 // so no two set-aside edges share a vertex either).  Work items run
 // grid-stride over the list of set-aside edges: two per edge for the minima,
 // 2 + 2 VSTAR per edge for the re-evaluation (its two ends, then the far end
@@ -801,39 +802,15 @@ __global__ __launch_bounds__(256) void k_demoted_vmin(MeshView m, const uint64_t
 
 constexpr int RESEL_ITEMS = 2 + 2 * VSTAR;
 
-// the edge (by its lower half-edge) holding the minimum vmin[u] of u's
-// star, or -1 when every edge at u has the largest key
-__device__ __forceinline__ int min_edge(const MeshView& m, const uint64_t* __restrict__ key,
-                                        const uint64_t* __restrict__ vmin, int u) {
-  const uint64_t want = vmin[u];
-  if (want == PAMO_KEY_MAX) return -1;
-  int found = -1;
-  const int deg = m.vdeg[u];
-  if (deg <= VSTAR) {
-    int g[VSTAR];
-    star_all(m, u, deg, g);
-    uint64_t k[VSTAR];
-#pragma unroll
-    for (int q = 0; q < VSTAR; q++) k[q] = key[g[q]];
-#pragma unroll
-    for (int q = 0; q < VSTAR; q++) found = k[q] == want ? g[q] : found;
-  } else {
-    walk_star(m.twin, m.vh[u], [&](int g) {
-      if (key[g] == want) found = g;
-    });
-  }
-  if (found < 0) return -1;
-  const int t = m.twin[found];
-  return t < found ? t : found;
-}
-
 __global__ __launch_bounds__(256) void k_reselect(MeshView m, const uint64_t* __restrict__ key,
                                                   const int* __restrict__ dlist, const int* __restrict__ nd,
                                                   const uint64_t* __restrict__ vmin, uint8_t* __restrict__ sel) {
   const int64_t n = RESEL_ITEMS * (int64_t)*nd;
-  auto again = [&](int u) {
-    const int e = min_edge(m, key, vmin, u);
-    if (e >= 0) sel[e] = select_edge(m, key, vmin, e);
+  auto again = [&](int u) {  // the edge holding u's minimum: the key's low 32 bits
+    const uint64_t k = vmin[u];
+    if (k == PAMO_KEY_MAX) return;
+    const int e = (int)(uint32_t)k;
+    sel[e] = select_edge(m, key, vmin, e);
   };
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int h = dlist[i / RESEL_ITEMS];
