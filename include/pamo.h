@@ -209,6 +209,27 @@ pamo_status pamo_simplify_batch(pamo_ctx* ctx, int32_t nmesh, const double* V, c
 pamo_status pamo_udf(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf, int32_t res,
                      double band, double* udf);
 
+/* ---- remeshing, volume-to-mesh step ---- */
+
+/* Dual Marching Cubes (Sec. 4.2, Volume-to-Mesh) on a res^3 grid of values
+ * S[(i * res + j) * res + k] (device float64) at the points ((i + 1/2) / res,
+ * (j + 1/2) / res, (k + 1/2) / res); a point is outside when S - iso >= 0.
+ * Per cube of 2^3 points: one vertex per surface patch, at the mean of the
+ * linear crossing points of its edges; patches come from face links, and an
+ * ambiguous face shared by two cubes that would otherwise give a non-manifold
+ * dual edge is resolved the other way in both (the paper's manifold fix).
+ * Per crossed grid edge with four neighbouring cubes: one quad, oriented with
+ * its normal towards the outside, split along its shorter diagonal into two
+ * triangles.  Vertices are numbered by cube (x outermost) then patch; faces by
+ * axis then grid point.  V_out: device float64 [vcap][3]; F_out: device int32
+ * [fcap][3]; *nv_out, *nf_out (host) get the sizes.  res in [2, 256]; values
+ * must be finite where a sign change occurs.  Fails with PAMO_ERR_CAPACITY,
+ * writing only the sizes, when the mesh does not fit.  This version uses the
+ * linear crossing and the plain quad split (no sigmoid interpolation or
+ * envelope division yet).  Synchronises the stream. */
+pamo_status pamo_dualmc(pamo_ctx* ctx, const double* S, int32_t res, double iso, double* V_out, int64_t vcap,
+                        int32_t* F_out, int64_t fcap, int64_t* nv_out, int64_t* nf_out);
+
 /* ---- utilities ---- */
 
 /* All pairs (t < u) of faces that intersect under the test of Sec. 5.2 /

@@ -1,0 +1,323 @@
+// The remeshing stage's volume-to-mesh step (Sec. 4.2): Dual Marching Cubes on
+// a grid of float64 values, with the manifold fix for ambiguous faces shared by
+// two cubes.
+//
+// Grid point (i, j, k) holds s = S[(i r + j) r + k] - iso and sits at
+// ((i + 1/2) / r, (j + 1/2) / r, (k + 1/2) / r); it is positive when s >= 0.
+// Cube (i, j, k) spans the points (i..i+1, j..j+1, k..k+1); corner c has bit 0
+// for +x, bit 1 for +y, bit 2 for +z.  Cube edge 4 a + u + 2 v runs along axis
+// a, u and v being its coordinates on the other two axes, lower axis first.
+//
+// Patches: per face, the crossed edges are joined where the surface crosses
+// the face: two crossed edges are joined to each other; on an ambiguous face
+// (four crossed edges) the two edges at each positive corner are joined, or,
+// when the face is flipped, the two at each negative corner.  The connected
+// sets of crossed edges are the cube's patches, numbered by their smallest
+// edge.  A face shared by two cubes is flipped (in both) when each cube,
+// unflipped, has one patch holding all four of its edges: that pair of
+// patches would otherwise be joined by four quads along one dual edge.
+//
+// Vertices: one per patch, the mean of its edges' linear crossing points
+// (summed in ascending edge order), numbered by cube (x outermost), then patch.
+// Quads: one per crossed grid edge whose four neighbouring cubes exist,
+// ordered by axis then grid point; its vertices go counter-clockwise round
+// the axis seen from the axis's positive side, reversed when the lower end is
+// positive, so the normal points to the positive side; each is split into
+// two triangles along its shorter diagonal (the one through its first vertex
+// on a tie).
+//
+// Kernels: one thread per cube (configuration, flips, patch count), a scan,
+// one thread per cube with patches (positions), one thread per grid edge
+// (crossing flag), a scan, one thread per crossing (two triangles).  The
+// patch structure of a cube is recomputed where needed from its 14-bit code
+// (configuration and flips) rather than stored.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.hpp"
+#include "remesh.hpp"
+
+namespace pamo {
+namespace {
+
+inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
+
+struct DGrid {
+  const double* S;
+  int r;
+  double iso;
+};
+
+__device__ __forceinline__ double gval(const DGrid& g, int i, int j, int k) {
+  return g.S[((int64_t)i * g.r + j) * g.r + k] - g.iso;
+}
+
+__device__ uint32_t cube_config(const DGrid& g, int i, int j, int k) {
+  uint32_t c = 0;
+  for (int b = 0; b < 8; b++)
+    if (gval(g, i + (b & 1), j + ((b >> 1) & 1), k + ((b >> 2) & 1)) >= 0.0) c |= 1u << b;
+  return c;
+}
+
+// the two axes other than a, lower first
+__device__ __forceinline__ int lo_axis(int a) { return a == 0 ? 1 : 0; }
+__device__ __forceinline__ int hi_axis(int a) { return a == 2 ? 1 : 2; }
+
+// id of the cube edge along axis a whose lower corner is c0
+__device__ __forceinline__ int edge_of(int a, int c0) {
+  return 4 * a + ((c0 >> lo_axis(a)) & 1) + 2 * ((c0 >> hi_axis(a)) & 1);
+}
+
+// lower corner of cube edge e
+__device__ __forceinline__ int edge_corner(int e) {
+  const int a = e >> 2;
+  return ((e & 1) << lo_axis(a)) | (((e >> 1) & 1) << hi_axis(a));
+}
+
+// corners of face (a, w) in cyclic order and the edge from corner t to t + 1
+__device__ __forceinline__ void face_ring(int a, int w, int c[4], int ed[4]) {
+  const int p = lo_axis(a), q = hi_axis(a);
+  c[0] = w << a;
+  c[1] = c[0] | (1 << p);
+  c[2] = c[1] | (1 << q);
+  c[3] = c[0] | (1 << q);
+  ed[0] = edge_of(p, c[0]);
+  ed[1] = edge_of(q, c[1]);
+  ed[2] = edge_of(p, c[3]);
+  ed[3] = edge_of(q, c[0]);
+}
+
+__device__ __forceinline__ int root(const int* par, int x) {
+  while (par[x] != x) x = par[x];
+  return x;
+}
+
+__device__ __forceinline__ void join(int* par, int x, int y) {
+  x = root(par, x);
+  y = root(par, y);
+  if (x != y) par[x > y ? x : y] = x < y ? x : y;
+}
+
+// patch of each cube edge (-1: not crossed); returns the number of patches
+__device__ int cube_patches(uint32_t cfg, uint32_t flips, int pid[12]) {
+  int par[12];
+  for (int e = 0; e < 12; e++) par[e] = e;
+  for (int f = 0; f < 6; f++) {
+    int c[4], ed[4];
+    face_ring(f >> 1, f & 1, c, ed);
+    int nx = 0, x0 = -1, x1 = -1;
+    for (int t = 0; t < 4; t++) {
+      if (((cfg >> c[t]) & 1) != ((cfg >> c[(t + 1) & 3]) & 1)) {
+        nx++;
+        if (x0 < 0)
+          x0 = ed[t];
+        else
+          x1 = ed[t];
+      }
+    }
+    if (nx == 2) {
+      join(par, x0, x1);
+    } else if (nx == 4) {
+      const uint32_t side = (flips >> f) & 1 ? 0u : 1u;
+      for (int t = 0; t < 4; t++)
+        if (((cfg >> c[t]) & 1) == side) join(par, ed[(t + 3) & 3], ed[t]);  // the edges meeting at corner t
+    }
+  }
+  int label[12];
+  for (int e = 0; e < 12; e++) label[e] = -1;
+  int n = 0;
+  for (int e = 0; e < 12; e++) {
+    const int c0 = edge_corner(e), c1 = c0 | (1 << (e >> 2));
+    if (((cfg >> c0) & 1) == ((cfg >> c1) & 1)) {
+      pid[e] = -1;
+      continue;
+    }
+    const int rt = root(par, e);
+    if (label[rt] < 0) label[rt] = n++;
+    pid[e] = label[rt];
+  }
+  return n;
+}
+
+// one unflipped patch holds all four edges of face f
+__device__ bool holds_face(uint32_t cfg, int f) {
+  int c[4], ed[4];
+  face_ring(f >> 1, f & 1, c, ed);
+  for (int t = 0; t < 4; t++)
+    if (((cfg >> c[t]) & 1) == ((cfg >> c[(t + 1) & 3]) & 1)) return false;
+  int pid[12];
+  cube_patches(cfg, 0, pid);
+  return pid[ed[0]] == pid[ed[1]] && pid[ed[0]] == pid[ed[2]] && pid[ed[0]] == pid[ed[3]];
+}
+
+__global__ void k_dmc_cubes(DGrid g, uint16_t* __restrict__ code, int32_t* __restrict__ cnt) {
+  const int m = g.r - 1;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * m * m) return;
+  const int k = (int)(idx % m), j = (int)(idx / m % m), i = (int)(idx / ((int64_t)m * m));
+  const uint32_t cfg = cube_config(g, i, j, k);
+  if (cfg == 0 || cfg == 255) {
+    code[idx] = (uint16_t)cfg;
+    cnt[idx] = 0;
+    return;
+  }
+  uint32_t flips = 0;
+  for (int f = 0; f < 6; f++) {
+    const int a = f >> 1, w = f & 1;
+    int n[3] = {i, j, k};
+    n[a] += w ? 1 : -1;
+    if (n[a] < 0 || n[a] > m - 1) continue;
+    if (holds_face(cfg, f) && holds_face(cube_config(g, n[0], n[1], n[2]), f ^ 1)) flips |= 1u << f;
+  }
+  int pid[12];
+  code[idx] = (uint16_t)(cfg | flips << 8);
+  cnt[idx] = cube_patches(cfg, flips, pid);
+}
+
+__global__ void k_dmc_verts(DGrid g, const uint16_t* __restrict__ code, const int32_t* __restrict__ cnt,
+                            const int32_t* __restrict__ vbase, double* __restrict__ V) {
+  const int m = g.r - 1;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * m * m || cnt[idx] == 0) return;
+  const int k = (int)(idx % m), j = (int)(idx / m % m), i = (int)(idx / ((int64_t)m * m));
+  const uint32_t cd = code[idx];
+  int pid[12];
+  const int np = cube_patches(cd & 255u, cd >> 8, pid);
+  if (np > 4) return;  // never: each patch is a cycle of at least three of the twelve edges
+  double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0}, sz[4] = {0, 0, 0, 0};
+  int ne[4] = {0, 0, 0, 0};
+  const double rr = (double)g.r;
+  for (int e = 0; e < 12; e++) {
+    const int p = pid[e];
+    if (p < 0) continue;
+    const int a = e >> 2, c0 = edge_corner(e);
+    const int i0 = i + (c0 & 1), j0 = j + ((c0 >> 1) & 1), k0 = k + ((c0 >> 2) & 1);
+    const double s0 = gval(g, i0, j0, k0);
+    const double s1 = gval(g, i0 + (a == 0), j0 + (a == 1), k0 + (a == 2));
+    const double t = s0 / (s0 - s1);
+    double q[3] = {(double)i0 + 0.5, (double)j0 + 0.5, (double)k0 + 0.5};
+    q[a] = q[a] + t;
+    sx[p] += q[0] / rr;
+    sy[p] += q[1] / rr;
+    sz[p] += q[2] / rr;
+    ne[p]++;
+  }
+  const int64_t b = vbase[idx];
+  for (int p = 0; p < np; p++) {
+    V[(b + p) * 3 + 0] = sx[p] / (double)ne[p];
+    V[(b + p) * 3 + 1] = sy[p] / (double)ne[p];
+    V[(b + p) * 3 + 2] = sz[p] / (double)ne[p];
+  }
+}
+
+// grid edge x = a r^3 + point: crossed, with all four neighbouring cubes
+__device__ __forceinline__ bool quad_edge(const DGrid& g, int64_t x, int& a, int gp[3]) {
+  const int r = g.r;
+  const int64_t n3 = (int64_t)r * r * r;
+  a = (int)(x / n3);
+  const int64_t p = x % n3;
+  gp[2] = (int)(p % r);
+  gp[1] = (int)(p / r % r);
+  gp[0] = (int)(p / ((int64_t)r * r));
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  if (gp[a] > r - 2 || gp[b] < 1 || gp[b] > r - 2 || gp[c] < 1 || gp[c] > r - 2) return false;
+  const bool p0 = gval(g, gp[0], gp[1], gp[2]) >= 0.0;
+  const bool p1 = gval(g, gp[0] + (a == 0), gp[1] + (a == 1), gp[2] + (a == 2)) >= 0.0;
+  return p0 != p1;
+}
+
+__global__ void k_dmc_qflags(DGrid g, int32_t* __restrict__ flag) {
+  const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (x >= 3 * (int64_t)g.r * g.r * g.r) return;
+  int a, gp[3];
+  flag[x] = quad_edge(g, x, a, gp) ? 1 : 0;
+}
+
+__device__ __forceinline__ double dist2(const double* x, const double* y) {
+  const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+  return dx * dx + dy * dy + dz * dz;
+}
+
+__global__ void k_dmc_quads(DGrid g, const uint16_t* __restrict__ code, const int32_t* __restrict__ vbase,
+                            const int32_t* __restrict__ qoff, const double* __restrict__ V, int32_t* __restrict__ F) {
+  const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (x >= 3 * (int64_t)g.r * g.r * g.r) return;
+  int a, gp[3];
+  if (!quad_edge(g, x, a, gp)) return;
+  const int m = g.r - 1;
+  const int b = (a + 1) % 3, c = (a + 2) % 3;
+  const int db[4] = {-1, 0, 0, -1}, dc[4] = {-1, -1, 0, 0};
+  int ring[4];
+  for (int t = 0; t < 4; t++) {
+    int cu[3] = {gp[0], gp[1], gp[2]};
+    cu[b] += db[t];
+    cu[c] += dc[t];
+    const int lb = -db[t], lc = -dc[t];  // the grid edge's place in the cube
+    const int u = b < c ? lb : lc, v = b < c ? lc : lb;
+    const int64_t ci = ((int64_t)cu[0] * m + cu[1]) * m + cu[2];
+    const uint32_t cd = code[ci];
+    int pid[12];
+    cube_patches(cd & 255u, cd >> 8, pid);
+    const int p = pid[4 * a + u + 2 * v];
+    if (p < 0) return;  // never: the cube's configuration comes from the same two values
+    ring[t] = vbase[ci] + p;
+  }
+  if (gval(g, gp[0], gp[1], gp[2]) >= 0.0) {
+    const int t1 = ring[1];
+    ring[1] = ring[3];
+    ring[3] = t1;
+  }
+  const int64_t o = (int64_t)qoff[x] * 6;
+  const double d02 = dist2(V + (int64_t)ring[0] * 3, V + (int64_t)ring[2] * 3);
+  const double d13 = dist2(V + (int64_t)ring[1] * 3, V + (int64_t)ring[3] * 3);
+  if (d02 <= d13) {
+    F[o + 0] = ring[0], F[o + 1] = ring[1], F[o + 2] = ring[2];
+    F[o + 3] = ring[0], F[o + 4] = ring[2], F[o + 5] = ring[3];
+  } else {
+    F[o + 0] = ring[0], F[o + 1] = ring[1], F[o + 2] = ring[3];
+    F[o + 3] = ring[1], F[o + 4] = ring[2], F[o + 5] = ring[3];
+  }
+}
+
+int32_t read_i32(hipStream_t s, const int32_t* p) {
+  int32_t h = 0;
+  PAMO_HIP(hipMemcpyAsync(&h, p, sizeof(h), hipMemcpyDeviceToHost, s));
+  PAMO_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+}  // namespace
+
+bool dualmc_run(Workspace& ws, hipStream_t s, const double* S, int res, double iso, double* V, int64_t vcap,
+                int32_t* F, int64_t fcap, int64_t* nv, int64_t* nf) {
+  *nv = *nf = 0;
+  if (res < 2) return true;
+  DGrid g{S, res, iso};
+  const int64_t ncube = (int64_t)(res - 1) * (res - 1) * (res - 1);
+  const int64_t nedge = 3 * (int64_t)res * res * res;
+  uint16_t* code = ws.get<uint16_t>("dmc.code", ncube);
+  int32_t* cnt = ws.get<int32_t>("dmc.cnt", ncube);
+  int32_t* vbase = ws.get<int32_t>("dmc.vbase", ncube);
+  int32_t* qflag = ws.get<int32_t>("dmc.qflag", nedge);
+  int32_t* qoff = ws.get<int32_t>("dmc.qoff", nedge);
+  int32_t* tot = ws.get<int32_t>("dmc.tot", 2);
+  hipLaunchKernelGGL(k_dmc_cubes, dim3(blocks(ncube)), dim3(256), 0, s, g, code, cnt);
+  scan_exclusive(ws, s, cnt, vbase, ncube, tot);
+  hipLaunchKernelGGL(k_dmc_qflags, dim3(blocks(nedge)), dim3(256), 0, s, g, qflag);
+  scan_exclusive(ws, s, qflag, qoff, nedge, tot + 1);
+  PAMO_HIP(hipGetLastError());
+  *nv = read_i32(s, tot);
+  *nf = 2 * (int64_t)read_i32(s, tot + 1);
+  if (*nv > vcap || *nf > fcap) return false;
+  if (*nv == 0) return true;
+  hipLaunchKernelGGL(k_dmc_verts, dim3(blocks(ncube)), dim3(256), 0, s, g, (const uint16_t*)code,
+                     (const int32_t*)cnt, (const int32_t*)vbase, V);
+  hipLaunchKernelGGL(k_dmc_quads, dim3(blocks(nedge)), dim3(256), 0, s, g, (const uint16_t*)code,
+                     (const int32_t*)vbase, (const int32_t*)qoff, (const double*)V, F);
+  PAMO_HIP(hipGetLastError());
+  return true;
+}
+
+}  // namespace pamo
