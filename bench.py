@@ -214,12 +214,25 @@ def remesh_udf(native, torch, dev, reps=5):
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
         ms = sorted(times)[len(times) // 2] * 1e3
-        rows.append({"faces": int(len(F)), "vertices": int(len(V)), "res": res, "ms": ms,
-                     "voxels_in_band": int(torch.isfinite(U).sum())})
+        row = {"faces": int(len(F)), "vertices": int(len(V)), "res": res, "ms": ms,
+               "voxels_in_band": int(torch.isfinite(U).sum())}
         log(f"distance field {len(F)} faces at {res}^3: {ms:.2f} ms")
+        if res <= 256:  # the surface extraction (pamo_dualmc) runs up to 256^3
+            Vo, Fo = ctx.dualmc(U, 0.9 / res)
+            nv, nf = len(Vo), len(Fo)
+            times = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                Vo, Fo = ctx.dualmc(U, 0.9 / res, vcap=nv, fcap=nf)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            row.update({"dualmc_ms": sorted(times)[len(times) // 2] * 1e3, "out_vertices": nv, "out_faces": nf})
+            log(f"dual marching cubes at {res}^3 -> {nf} faces: {row['dualmc_ms']:.2f} ms")
+        rows.append(row)
     ctx.close()
     return {"workload": "noisy icospheres (seed 2), narrow-band unsigned distance field at voxel centres, band 3/R, "
-                        f"median of {reps} calls", "rows": rows}
+                        "then Dual Marching Cubes of the field less 0.9/R (up to 256^3), "
+                        f"median of {reps} calls each", "rows": rows}
 
 
 def sharp_feature(native, torch, dev, steps):

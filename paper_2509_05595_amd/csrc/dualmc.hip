@@ -28,9 +28,9 @@
 //
 // Kernels: one thread per cube (configuration, flips, patch count), a scan,
 // one thread per cube with patches (positions), one thread per grid edge
-// (crossing flag), a scan, one thread per crossing (two triangles).  The
-// patch structure of a cube is recomputed where needed from its 14-bit code
-// (configuration and flips) rather than stored.
+// (crossing flag), a compaction, one thread per crossing (two triangles).
+// The patch structure of a cube is found once, by a small union-find, and
+// kept as two bits per edge.
 
 #include <hip/hip_runtime.h>
 
@@ -152,14 +152,17 @@ __device__ bool holds_face(uint32_t cfg, int f) {
   return pid[ed[0]] == pid[ed[1]] && pid[ed[0]] == pid[ed[2]] && pid[ed[0]] == pid[ed[3]];
 }
 
-__global__ void k_dmc_cubes(DGrid g, uint16_t* __restrict__ code, int32_t* __restrict__ cnt) {
+// per cube: the number of patches and, in pmap, the patch of each crossed
+// edge e in bits 2e..2e+1 (a cube has at most four patches: each is a cycle
+// of at least three of the twelve edges)
+__global__ void k_dmc_cubes(DGrid g, uint32_t* __restrict__ pmap, int32_t* __restrict__ cnt) {
   const int m = g.r - 1;
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= (int64_t)m * m * m) return;
   const int k = (int)(idx % m), j = (int)(idx / m % m), i = (int)(idx / ((int64_t)m * m));
   const uint32_t cfg = cube_config(g, i, j, k);
   if (cfg == 0 || cfg == 255) {
-    code[idx] = (uint16_t)cfg;
+    pmap[idx] = 0;
     cnt[idx] = 0;
     return;
   }
@@ -172,27 +175,29 @@ __global__ void k_dmc_cubes(DGrid g, uint16_t* __restrict__ code, int32_t* __res
     if (holds_face(cfg, f) && holds_face(cube_config(g, n[0], n[1], n[2]), f ^ 1)) flips |= 1u << f;
   }
   int pid[12];
-  code[idx] = (uint16_t)(cfg | flips << 8);
   cnt[idx] = cube_patches(cfg, flips, pid);
+  uint32_t pm = 0;
+  for (int e = 0; e < 12; e++)
+    if (pid[e] > 0) pm |= (uint32_t)pid[e] << (2 * e);
+  pmap[idx] = pm;
 }
 
-__global__ void k_dmc_verts(DGrid g, const uint16_t* __restrict__ code, const int32_t* __restrict__ cnt,
+__global__ void k_dmc_verts(DGrid g, const uint32_t* __restrict__ pmap, const int32_t* __restrict__ cnt,
                             const int32_t* __restrict__ vbase, double* __restrict__ V) {
   const int m = g.r - 1;
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)m * m * m || cnt[idx] == 0) return;
+  if (idx >= (int64_t)m * m * m) return;
+  const int np = cnt[idx];
+  if (np == 0) return;
   const int k = (int)(idx % m), j = (int)(idx / m % m), i = (int)(idx / ((int64_t)m * m));
-  const uint32_t cd = code[idx];
-  int pid[12];
-  const int np = cube_patches(cd & 255u, cd >> 8, pid);
-  if (np > 4) return;  // never: each patch is a cycle of at least three of the twelve edges
+  const uint32_t cfg = cube_config(g, i, j, k), pm = pmap[idx];
   double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0}, sz[4] = {0, 0, 0, 0};
   int ne[4] = {0, 0, 0, 0};
   const double rr = (double)g.r;
   for (int e = 0; e < 12; e++) {
-    const int p = pid[e];
-    if (p < 0) continue;
     const int a = e >> 2, c0 = edge_corner(e);
+    if (((cfg >> c0) & 1) == ((cfg >> (c0 | (1 << a))) & 1)) continue;
+    const int p = (pm >> (2 * e)) & 3;
     const int i0 = i + (c0 & 1), j0 = j + ((c0 >> 1) & 1), k0 = k + ((c0 >> 2) & 1);
     const double s0 = gval(g, i0, j0, k0);
     const double s1 = gval(g, i0 + (a == 0), j0 + (a == 1), k0 + (a == 2));
@@ -228,7 +233,7 @@ __device__ __forceinline__ bool quad_edge(const DGrid& g, int64_t x, int& a, int
   return p0 != p1;
 }
 
-__global__ void k_dmc_qflags(DGrid g, int32_t* __restrict__ flag) {
+__global__ void k_dmc_qflags(DGrid g, uint8_t* __restrict__ flag) {
   const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (x >= 3 * (int64_t)g.r * g.r * g.r) return;
   int a, gp[3];
@@ -240,12 +245,17 @@ __device__ __forceinline__ double dist2(const double* x, const double* y) {
   return dx * dx + dy * dy + dz * dz;
 }
 
-__global__ void k_dmc_quads(DGrid g, const uint16_t* __restrict__ code, const int32_t* __restrict__ vbase,
-                            const int32_t* __restrict__ qoff, const double* __restrict__ V, int32_t* __restrict__ F) {
-  const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (x >= 3 * (int64_t)g.r * g.r * g.r) return;
-  int a, gp[3];
-  if (!quad_edge(g, x, a, gp)) return;
+// one thread per crossed grid edge, from the ascending list of their ids
+__global__ void k_dmc_quads(DGrid g, const uint32_t* __restrict__ pmap, const int32_t* __restrict__ vbase,
+                            const int32_t* __restrict__ qlist, int nq, const double* __restrict__ V,
+                            int32_t* __restrict__ F) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const int64_t x = qlist[q];
+  const int r = g.r;
+  const int64_t n3 = (int64_t)r * r * r, pt = x % n3;
+  const int a = (int)(x / n3);
+  const int gp[3] = {(int)(pt / ((int64_t)r * r)), (int)(pt / r % r), (int)(pt % r)};
   const int m = g.r - 1;
   const int b = (a + 1) % 3, c = (a + 2) % 3;
   const int db[4] = {-1, 0, 0, -1}, dc[4] = {-1, -1, 0, 0};
@@ -257,19 +267,14 @@ __global__ void k_dmc_quads(DGrid g, const uint16_t* __restrict__ code, const in
     const int lb = -db[t], lc = -dc[t];  // the grid edge's place in the cube
     const int u = b < c ? lb : lc, v = b < c ? lc : lb;
     const int64_t ci = ((int64_t)cu[0] * m + cu[1]) * m + cu[2];
-    const uint32_t cd = code[ci];
-    int pid[12];
-    cube_patches(cd & 255u, cd >> 8, pid);
-    const int p = pid[4 * a + u + 2 * v];
-    if (p < 0) return;  // never: the cube's configuration comes from the same two values
-    ring[t] = vbase[ci] + p;
+    ring[t] = vbase[ci] + (int)((pmap[ci] >> (2 * (4 * a + u + 2 * v))) & 3);
   }
   if (gval(g, gp[0], gp[1], gp[2]) >= 0.0) {
     const int t1 = ring[1];
     ring[1] = ring[3];
     ring[3] = t1;
   }
-  const int64_t o = (int64_t)qoff[x] * 6;
+  const int64_t o = (int64_t)q * 6;
   const double d02 = dist2(V + (int64_t)ring[0] * 3, V + (int64_t)ring[2] * 3);
   const double d13 = dist2(V + (int64_t)ring[1] * 3, V + (int64_t)ring[3] * 3);
   if (d02 <= d13) {
@@ -297,25 +302,27 @@ bool dualmc_run(Workspace& ws, hipStream_t s, const double* S, int res, double i
   DGrid g{S, res, iso};
   const int64_t ncube = (int64_t)(res - 1) * (res - 1) * (res - 1);
   const int64_t nedge = 3 * (int64_t)res * res * res;
-  uint16_t* code = ws.get<uint16_t>("dmc.code", ncube);
+  uint32_t* pmap = ws.get<uint32_t>("dmc.pmap", ncube);
   int32_t* cnt = ws.get<int32_t>("dmc.cnt", ncube);
   int32_t* vbase = ws.get<int32_t>("dmc.vbase", ncube);
-  int32_t* qflag = ws.get<int32_t>("dmc.qflag", nedge);
-  int32_t* qoff = ws.get<int32_t>("dmc.qoff", nedge);
+  uint8_t* qflag = ws.get<uint8_t>("dmc.qflag", nedge);
+  int32_t* qlist = ws.get<int32_t>("dmc.qlist", nedge);
   int32_t* tot = ws.get<int32_t>("dmc.tot", 2);
-  hipLaunchKernelGGL(k_dmc_cubes, dim3(blocks(ncube)), dim3(256), 0, s, g, code, cnt);
+  hipLaunchKernelGGL(k_dmc_cubes, dim3(blocks(ncube)), dim3(256), 0, s, g, pmap, cnt);
   scan_exclusive(ws, s, cnt, vbase, ncube, tot);
   hipLaunchKernelGGL(k_dmc_qflags, dim3(blocks(nedge)), dim3(256), 0, s, g, qflag);
-  scan_exclusive(ws, s, qflag, qoff, nedge, tot + 1);
+  compact_flags(ws, s, qflag, nedge, qlist, tot + 1);
   PAMO_HIP(hipGetLastError());
   *nv = read_i32(s, tot);
   *nf = 2 * (int64_t)read_i32(s, tot + 1);
   if (*nv > vcap || *nf > fcap) return false;
   if (*nv == 0) return true;
-  hipLaunchKernelGGL(k_dmc_verts, dim3(blocks(ncube)), dim3(256), 0, s, g, (const uint16_t*)code,
+  hipLaunchKernelGGL(k_dmc_verts, dim3(blocks(ncube)), dim3(256), 0, s, g, (const uint32_t*)pmap,
                      (const int32_t*)cnt, (const int32_t*)vbase, V);
-  hipLaunchKernelGGL(k_dmc_quads, dim3(blocks(nedge)), dim3(256), 0, s, g, (const uint16_t*)code,
-                     (const int32_t*)vbase, (const int32_t*)qoff, (const double*)V, F);
+  const int nq = (int)(*nf / 2);
+  if (nq > 0)
+    hipLaunchKernelGGL(k_dmc_quads, dim3(blocks(nq)), dim3(256), 0, s, g, (const uint32_t*)pmap,
+                       (const int32_t*)vbase, (const int32_t*)qlist, nq, (const double*)V, F);
   PAMO_HIP(hipGetLastError());
   return true;
 }
