@@ -26,9 +26,11 @@
 // two triangles along its shorter diagonal (the one through its first vertex
 // on a tie).
 //
-// Kernels: one thread per cube (configuration, flips, patch count), a scan,
-// one thread per cube with patches (positions), one thread per grid edge
-// (crossing flag), a compaction, one thread per crossing (two triangles).
+// Kernels: one thread per grid point (sign byte), one per cube (configuration,
+// crossed or not), a compaction of the crossed cubes, one thread per crossed
+// cube (flips, patches), a scan of their patch counts, one per crossed cube
+// (positions), one per grid edge (crossed interior edge), a compaction, one
+// per crossing (two triangles).
 // The patch structure of a cube is found once, by a small union-find, and
 // kept as two bits per edge.
 
@@ -54,10 +56,16 @@ __device__ __forceinline__ double gval(const DGrid& g, int i, int j, int k) {
   return g.S[((int64_t)i * g.r + j) * g.r + k] - g.iso;
 }
 
-__device__ uint32_t cube_config(const DGrid& g, int i, int j, int k) {
+// the sign of every grid point (1: s >= 0), one byte each
+__global__ void k_dmc_sign(DGrid g, uint8_t* __restrict__ sg) {
+  const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (x < (int64_t)g.r * g.r * g.r) sg[x] = g.S[x] - g.iso >= 0.0 ? 1 : 0;
+}
+
+__device__ __forceinline__ uint32_t cube_config(const uint8_t* sg, int r, int i, int j, int k) {
   uint32_t c = 0;
   for (int b = 0; b < 8; b++)
-    if (gval(g, i + (b & 1), j + ((b >> 1) & 1), k + ((b >> 2) & 1)) >= 0.0) c |= 1u << b;
+    c |= (uint32_t)sg[((int64_t)(i + (b & 1)) * r + j + ((b >> 1) & 1)) * r + k + ((b >> 2) & 1)] << b;
   return c;
 }
 
@@ -152,45 +160,54 @@ __device__ bool holds_face(uint32_t cfg, int f) {
   return pid[ed[0]] == pid[ed[1]] && pid[ed[0]] == pid[ed[2]] && pid[ed[0]] == pid[ed[3]];
 }
 
-// per cube: the number of patches and, in pmap, the patch of each crossed
-// edge e in bits 2e..2e+1 (a cube has at most four patches: each is a cycle
-// of at least three of the twelve edges)
-__global__ void k_dmc_cubes(DGrid g, uint32_t* __restrict__ pmap, int32_t* __restrict__ cnt) {
-  const int m = g.r - 1;
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)m * m * m) return;
+// per cube: its configuration, and whether the surface crosses it
+__global__ void k_dmc_active(const uint8_t* __restrict__ sg, int r, uint8_t* __restrict__ cfgs,
+                             uint8_t* __restrict__ act) {
+  const int m = r - 1;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * m * m) return;
+  const int k = idx % m, j = idx / m % m, i = idx / (m * m);
+  const uint32_t cfg = cube_config(sg, r, i, j, k);
+  cfgs[idx] = (uint8_t)cfg;
+  act[idx] = cfg != 0 && cfg != 255;
+}
+
+// per crossed cube (ascending list): the number of patches and, in pmap, the
+// patch of each crossed edge e in bits 2e..2e+1 (a cube has at most four
+// patches: each is a cycle of at least three of the twelve edges)
+__global__ void k_dmc_cubes(const uint8_t* __restrict__ cfgs, int m, const int32_t* __restrict__ clist, int nc,
+                            uint32_t* __restrict__ pmap, int32_t* __restrict__ cntl) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc) return;
+  const int64_t idx = clist[q];
   const int k = (int)(idx % m), j = (int)(idx / m % m), i = (int)(idx / ((int64_t)m * m));
-  const uint32_t cfg = cube_config(g, i, j, k);
-  if (cfg == 0 || cfg == 255) {
-    pmap[idx] = 0;
-    cnt[idx] = 0;
-    return;
-  }
+  const uint32_t cfg = cfgs[idx];
   uint32_t flips = 0;
   for (int f = 0; f < 6; f++) {
     const int a = f >> 1, w = f & 1;
     int n[3] = {i, j, k};
     n[a] += w ? 1 : -1;
     if (n[a] < 0 || n[a] > m - 1) continue;
-    if (holds_face(cfg, f) && holds_face(cube_config(g, n[0], n[1], n[2]), f ^ 1)) flips |= 1u << f;
+    if (holds_face(cfg, f) && holds_face(cfgs[((int64_t)n[0] * m + n[1]) * m + n[2]], f ^ 1)) flips |= 1u << f;
   }
   int pid[12];
-  cnt[idx] = cube_patches(cfg, flips, pid);
+  cntl[q] = cube_patches(cfg, flips, pid);
   uint32_t pm = 0;
   for (int e = 0; e < 12; e++)
     if (pid[e] > 0) pm |= (uint32_t)pid[e] << (2 * e);
   pmap[idx] = pm;
 }
 
-__global__ void k_dmc_verts(DGrid g, const uint32_t* __restrict__ pmap, const int32_t* __restrict__ cnt,
-                            const int32_t* __restrict__ vbase, double* __restrict__ V) {
+__global__ void k_dmc_verts(DGrid g, const uint8_t* __restrict__ cfgs, const int32_t* __restrict__ clist, int nc,
+                            const uint32_t* __restrict__ pmap, const int32_t* __restrict__ cntl,
+                            const int32_t* __restrict__ vbl, int32_t* __restrict__ vbase, double* __restrict__ V) {
   const int m = g.r - 1;
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)m * m * m) return;
-  const int np = cnt[idx];
-  if (np == 0) return;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc) return;
+  const int64_t idx = clist[q];
+  const int np = cntl[q];
   const int k = (int)(idx % m), j = (int)(idx / m % m), i = (int)(idx / ((int64_t)m * m));
-  const uint32_t cfg = cube_config(g, i, j, k), pm = pmap[idx];
+  const uint32_t cfg = cfgs[idx], pm = pmap[idx];
   double sx[4] = {0, 0, 0, 0}, sy[4] = {0, 0, 0, 0}, sz[4] = {0, 0, 0, 0};
   int ne[4] = {0, 0, 0, 0};
   const double rr = (double)g.r;
@@ -209,7 +226,8 @@ __global__ void k_dmc_verts(DGrid g, const uint32_t* __restrict__ pmap, const in
     sz[p] += q[2] / rr;
     ne[p]++;
   }
-  const int64_t b = vbase[idx];
+  const int64_t b = vbl[q];
+  vbase[idx] = (int32_t)b;
   for (int p = 0; p < np; p++) {
     V[(b + p) * 3 + 0] = sx[p] / (double)ne[p];
     V[(b + p) * 3 + 1] = sy[p] / (double)ne[p];
@@ -217,27 +235,20 @@ __global__ void k_dmc_verts(DGrid g, const uint32_t* __restrict__ pmap, const in
   }
 }
 
-// grid edge x = a r^3 + point: crossed, with all four neighbouring cubes
-__device__ __forceinline__ bool quad_edge(const DGrid& g, int64_t x, int& a, int gp[3]) {
-  const int r = g.r;
-  const int64_t n3 = (int64_t)r * r * r;
-  a = (int)(x / n3);
-  const int64_t p = x % n3;
-  gp[2] = (int)(p % r);
-  gp[1] = (int)(p / r % r);
-  gp[0] = (int)(p / ((int64_t)r * r));
-  const int b = (a + 1) % 3, c = (a + 2) % 3;
-  if (gp[a] > r - 2 || gp[b] < 1 || gp[b] > r - 2 || gp[c] < 1 || gp[c] > r - 2) return false;
-  const bool p0 = gval(g, gp[0], gp[1], gp[2]) >= 0.0;
-  const bool p1 = gval(g, gp[0] + (a == 0), gp[1] + (a == 1), gp[2] + (a == 2)) >= 0.0;
-  return p0 != p1;
-}
-
-__global__ void k_dmc_qflags(DGrid g, uint8_t* __restrict__ flag) {
-  const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (x >= 3 * (int64_t)g.r * g.r * g.r) return;
-  int a, gp[3];
-  flag[x] = quad_edge(g, x, a, gp) ? 1 : 0;
+// one thread per grid point, its three edges towards +x, +y, +z (flag of the
+// edge along axis a at a r^3 + point); res <= 256 keeps the indices in int32
+__global__ void k_dmc_qflags(const uint8_t* __restrict__ sg, int r, uint8_t* __restrict__ flag) {
+  const int n3 = r * r * r;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n3) return;
+  const int gp[3] = {p / (r * r), p / r % r, p % r};
+  const int step[3] = {r * r, r, 1};
+  const uint8_t s0 = sg[p];
+  for (int a = 0; a < 3; a++) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    const bool in = gp[a] <= r - 2 && gp[b] >= 1 && gp[b] <= r - 2 && gp[c] >= 1 && gp[c] <= r - 2;
+    flag[a * n3 + p] = in && s0 != sg[p + step[a]] ? 1 : 0;
+  }
 }
 
 __device__ __forceinline__ double dist2(const double* x, const double* y) {
@@ -246,17 +257,17 @@ __device__ __forceinline__ double dist2(const double* x, const double* y) {
 }
 
 // one thread per crossed grid edge, from the ascending list of their ids
-__global__ void k_dmc_quads(DGrid g, const uint32_t* __restrict__ pmap, const int32_t* __restrict__ vbase,
+__global__ void k_dmc_quads(int r, const uint8_t* __restrict__ sg, const uint32_t* __restrict__ pmap,
+                            const int32_t* __restrict__ vbase,
                             const int32_t* __restrict__ qlist, int nq, const double* __restrict__ V,
                             int32_t* __restrict__ F) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
   const int64_t x = qlist[q];
-  const int r = g.r;
   const int64_t n3 = (int64_t)r * r * r, pt = x % n3;
   const int a = (int)(x / n3);
   const int gp[3] = {(int)(pt / ((int64_t)r * r)), (int)(pt / r % r), (int)(pt % r)};
-  const int m = g.r - 1;
+  const int m = r - 1;
   const int b = (a + 1) % 3, c = (a + 2) % 3;
   const int db[4] = {-1, 0, 0, -1}, dc[4] = {-1, -1, 0, 0};
   int ring[4];
@@ -269,7 +280,7 @@ __global__ void k_dmc_quads(DGrid g, const uint32_t* __restrict__ pmap, const in
     const int64_t ci = ((int64_t)cu[0] * m + cu[1]) * m + cu[2];
     ring[t] = vbase[ci] + (int)((pmap[ci] >> (2 * (4 * a + u + 2 * v))) & 3);
   }
-  if (gval(g, gp[0], gp[1], gp[2]) >= 0.0) {
+  if (sg[pt]) {
     const int t1 = ring[1];
     ring[1] = ring[3];
     ring[3] = t1;
@@ -300,29 +311,42 @@ bool dualmc_run(Workspace& ws, hipStream_t s, const double* S, int res, double i
   *nv = *nf = 0;
   if (res < 2) return true;
   DGrid g{S, res, iso};
-  const int64_t ncube = (int64_t)(res - 1) * (res - 1) * (res - 1);
-  const int64_t nedge = 3 * (int64_t)res * res * res;
-  uint32_t* pmap = ws.get<uint32_t>("dmc.pmap", ncube);
-  int32_t* cnt = ws.get<int32_t>("dmc.cnt", ncube);
-  int32_t* vbase = ws.get<int32_t>("dmc.vbase", ncube);
+  const int m = res - 1;
+  const int64_t npt = (int64_t)res * res * res, ncube = (int64_t)m * m * m, nedge = 3 * npt;
+  uint8_t* sg = ws.get<uint8_t>("dmc.sign", npt);
+  uint8_t* cfgs = ws.get<uint8_t>("dmc.cfg", ncube);
+  uint8_t* act = ws.get<uint8_t>("dmc.act", ncube);
+  int32_t* clist = ws.get<int32_t>("dmc.clist", ncube);
   uint8_t* qflag = ws.get<uint8_t>("dmc.qflag", nedge);
   int32_t* qlist = ws.get<int32_t>("dmc.qlist", nedge);
-  int32_t* tot = ws.get<int32_t>("dmc.tot", 2);
-  hipLaunchKernelGGL(k_dmc_cubes, dim3(blocks(ncube)), dim3(256), 0, s, g, pmap, cnt);
-  scan_exclusive(ws, s, cnt, vbase, ncube, tot);
-  hipLaunchKernelGGL(k_dmc_qflags, dim3(blocks(nedge)), dim3(256), 0, s, g, qflag);
+  int32_t* tot = ws.get<int32_t>("dmc.tot", 3);
+  hipLaunchKernelGGL(k_dmc_sign, dim3(blocks(npt)), dim3(256), 0, s, g, sg);
+  hipLaunchKernelGGL(k_dmc_active, dim3(blocks(ncube)), dim3(256), 0, s, (const uint8_t*)sg, res, cfgs, act);
+  compact_flags(ws, s, act, ncube, clist, tot);
+  hipLaunchKernelGGL(k_dmc_qflags, dim3(blocks(npt)), dim3(256), 0, s, (const uint8_t*)sg, res, qflag);
   compact_flags(ws, s, qflag, nedge, qlist, tot + 1);
   PAMO_HIP(hipGetLastError());
-  *nv = read_i32(s, tot);
-  *nf = 2 * (int64_t)read_i32(s, tot + 1);
+  int32_t h[3] = {0, 0, 0};
+  PAMO_HIP(hipMemcpyAsync(h, tot, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PAMO_HIP(hipStreamSynchronize(s));
+  const int nc = h[0], nq = h[1];
+  if (nc == 0) return nq == 0;  // a crossed grid edge lies in crossed cubes
+  uint32_t* pmap = ws.get<uint32_t>("dmc.pmap", ncube);
+  int32_t* vbase = ws.get<int32_t>("dmc.vbase", ncube);
+  int32_t* cntl = ws.get<int32_t>("dmc.cntl", nc);
+  int32_t* vbl = ws.get<int32_t>("dmc.vbl", nc);
+  hipLaunchKernelGGL(k_dmc_cubes, dim3(blocks(nc)), dim3(256), 0, s, (const uint8_t*)cfgs, m,
+                     (const int32_t*)clist, nc, pmap, cntl);
+  scan_exclusive(ws, s, cntl, vbl, nc, tot + 2);
+  PAMO_HIP(hipGetLastError());
+  *nv = read_i32(s, tot + 2);
+  *nf = 2 * (int64_t)nq;
   if (*nv > vcap || *nf > fcap) return false;
-  if (*nv == 0) return true;
-  hipLaunchKernelGGL(k_dmc_verts, dim3(blocks(ncube)), dim3(256), 0, s, g, (const uint32_t*)pmap,
-                     (const int32_t*)cnt, (const int32_t*)vbase, V);
-  const int nq = (int)(*nf / 2);
+  hipLaunchKernelGGL(k_dmc_verts, dim3(blocks(nc)), dim3(256), 0, s, g, (const uint8_t*)cfgs, (const int32_t*)clist,
+                     nc, (const uint32_t*)pmap, (const int32_t*)cntl, (const int32_t*)vbl, vbase, V);
   if (nq > 0)
-    hipLaunchKernelGGL(k_dmc_quads, dim3(blocks(nq)), dim3(256), 0, s, g, (const uint32_t*)pmap,
-                       (const int32_t*)vbase, (const int32_t*)qlist, nq, (const double*)V, F);
+    hipLaunchKernelGGL(k_dmc_quads, dim3(blocks(nq)), dim3(256), 0, s, res, (const uint8_t*)sg,
+                       (const uint32_t*)pmap, (const int32_t*)vbase, (const int32_t*)qlist, nq, (const double*)V, F);
   PAMO_HIP(hipGetLastError());
   return true;
 }
