@@ -222,7 +222,8 @@ pamo_status pamo_udf(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* 
  * its normal towards the outside, split along its shorter diagonal into two
  * triangles.  Vertices are numbered by cube (x outermost) then patch; faces by
  * axis then grid point.  V_out: device float64 [vcap][3]; F_out: device int32
- * [fcap][3]; *nv_out, *nf_out (host) get the sizes.  res in [2, 256]; values
+ * [fcap][3]; *nv_out, *nf_out (host) get the sizes.  res in [2, 512], at most
+ * 2^26 cubes crossed by the surface (else PAMO_ERR_HIP from the scan); values
  * must be finite where a sign change occurs.  Fails with PAMO_ERR_CAPACITY,
  * writing only the sizes, when the mesh does not fit.  This version uses the
  * linear crossing and the plain quad split (no sigmoid interpolation or

@@ -1663,7 +1663,7 @@ pamo_status pamo_dualmc(pamo_ctx* c, const double* S, int32_t res, double iso, d
                         int32_t* F_out, int64_t fcap, int64_t* nv_out, int64_t* nf_out) {
   return guarded(c, [&]() -> pamo_status {
     if (!S || !nv_out || !nf_out || (vcap > 0 && !V_out) || (fcap > 0 && !F_out)) fail(PAMO_ERR_ARG, "null pointer");
-    if (res < 2 || res > 256) fail(PAMO_ERR_ARG, "grid resolution outside [2, 256]");
+    if (res < 2 || res > 512) fail(PAMO_ERR_ARG, "grid resolution outside [2, 512]");
     if (vcap < 0 || fcap < 0 || !(iso == iso)) fail(PAMO_ERR_ARG, "bad sizes or iso value");
     if (!dualmc_run(c->ws, c->stream, S, res, iso, V_out, vcap, F_out, fcap, nv_out, nf_out))
       fail(PAMO_ERR_CAPACITY, "output capacity too small for the extracted mesh");

@@ -236,7 +236,7 @@ __global__ void k_dmc_verts(DGrid g, const uint8_t* __restrict__ cfgs, const int
 }
 
 // one thread per grid point, its three edges towards +x, +y, +z (flag of the
-// edge along axis a at a r^3 + point); res <= 256 keeps the indices in int32
+// edge along axis a at a r^3 + point); res <= 512 keeps the indices in int32
 __global__ void k_dmc_qflags(const uint8_t* __restrict__ sg, int r, uint8_t* __restrict__ flag) {
   const int n3 = r * r * r;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -297,11 +297,34 @@ __global__ void k_dmc_quads(int r, const uint8_t* __restrict__ sg, const uint32_
   }
 }
 
+__global__ void k_add_i32(int32_t* __restrict__ p, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] += v;
+}
+
 int32_t read_i32(hipStream_t s, const int32_t* p) {
   int32_t h = 0;
   PAMO_HIP(hipMemcpyAsync(&h, p, sizeof(h), hipMemcpyDeviceToHost, s));
   PAMO_HIP(hipStreamSynchronize(s));
   return h;
+}
+
+// ascending indices of the set flags of flags[0..n) into out; returns their
+// number.  The compaction takes at most 2^26 items a call, so longer inputs go
+// in chunks, each chunk's local indices then offset by its start.
+int32_t compact_long(Workspace& ws, hipStream_t s, const uint8_t* flags, int64_t n, int32_t* out, int32_t* tot) {
+  constexpr int64_t CHUNK = (int64_t)1 << 26;
+  int32_t count = 0;
+  for (int64_t off = 0; off < n; off += CHUNK) {
+    const int64_t len = n - off < CHUNK ? n - off : CHUNK;
+    compact_flags(ws, s, flags + off, len, out + count, tot);
+    const int32_t c = read_i32(s, tot);
+    if (off > 0 && c > 0)
+      hipLaunchKernelGGL(k_add_i32, dim3(blocks(c)), dim3(256), 0, s, out + count, c, (int32_t)off);
+    count += c;
+  }
+  PAMO_HIP(hipGetLastError());
+  return count;
 }
 
 }  // namespace
@@ -322,14 +345,21 @@ bool dualmc_run(Workspace& ws, hipStream_t s, const double* S, int res, double i
   int32_t* tot = ws.get<int32_t>("dmc.tot", 3);
   hipLaunchKernelGGL(k_dmc_sign, dim3(blocks(npt)), dim3(256), 0, s, g, sg);
   hipLaunchKernelGGL(k_dmc_active, dim3(blocks(ncube)), dim3(256), 0, s, (const uint8_t*)sg, res, cfgs, act);
-  compact_flags(ws, s, act, ncube, clist, tot);
   hipLaunchKernelGGL(k_dmc_qflags, dim3(blocks(npt)), dim3(256), 0, s, (const uint8_t*)sg, res, qflag);
-  compact_flags(ws, s, qflag, nedge, qlist, tot + 1);
   PAMO_HIP(hipGetLastError());
-  int32_t h[3] = {0, 0, 0};
-  PAMO_HIP(hipMemcpyAsync(h, tot, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  PAMO_HIP(hipStreamSynchronize(s));
-  const int nc = h[0], nq = h[1];
+  int nc, nq;
+  if (nedge <= ((int64_t)1 << 26)) {  // one compaction each, one read-back
+    compact_flags(ws, s, act, ncube, clist, tot);
+    compact_flags(ws, s, qflag, nedge, qlist, tot + 1);
+    int32_t h[2] = {0, 0};
+    PAMO_HIP(hipMemcpyAsync(h, tot, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PAMO_HIP(hipStreamSynchronize(s));
+    nc = h[0];
+    nq = h[1];
+  } else {
+    nc = compact_long(ws, s, act, ncube, clist, tot);
+    nq = compact_long(ws, s, qflag, nedge, qlist, tot + 1);
+  }
   if (nc == 0) return nq == 0;  // a crossed grid edge lies in crossed cubes
   uint32_t* pmap = ws.get<uint32_t>("dmc.pmap", ncube);
   int32_t* vbase = ws.get<int32_t>("dmc.vbase", ncube);

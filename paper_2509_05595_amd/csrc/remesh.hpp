@@ -23,7 +23,8 @@ void udf_run(Workspace& ws, hipStream_t s, const double* V, const int* F, int nf
 // S - iso, positive when >= 0) with linear crossings and the shared
 // ambiguous-face fix.  Writes *nv vertices to V (float64 [*nv][3]) and *nf
 // triangles to F (int32 [*nf][3]) when they fit vcap / fcap rows, else writes
-// nothing and returns false.  res <= 256.  Synchronises the stream.
+// nothing and returns false.  res <= 512, at most 2^26 crossed cubes (else the
+// scan throws).  Synchronises the stream.
 bool dualmc_run(Workspace& ws, hipStream_t s, const double* S, int res, double iso, double* V, int64_t vcap,
                 int32_t* F, int64_t fcap, int64_t* nv, int64_t* nf);
 

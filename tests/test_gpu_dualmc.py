@@ -2,8 +2,8 @@
 Marching Cubes of Sec. 4.2 with the shared-ambiguous-face fix) against the
 oracle.  Both sides run the same float64 operations in the same order on the
 same grid, so vertices, faces and their numbering must agree bit for bit.
-At 256^3 (beyond what the oracle finishes in seconds) the output is checked
-through properties that hold at any size."""
+At 256^3 and 512^3 (beyond what the oracle finishes in seconds) the output is
+checked through properties that hold at any size."""
 from collections import Counter
 
 import numpy as np
@@ -86,10 +86,15 @@ def test_degenerate_cases(ctx):
         run(ctx, sphere(16), vcap=3)
 
 
-def test_full_size_sphere(ctx):
-    # 256^3: properties of the output (closed, manifold, genus 0, on the sphere)
-    R, r = 256, 0.3
-    V, F = run(ctx, sphere(R, r))
+@pytest.mark.parametrize("R", [256, 512])
+def test_full_size_sphere(ctx, R):
+    # 256^3 and 512^3 (chunked compaction of the 402M grid edges): properties of
+    # the output (closed, manifold, genus 0, on the sphere)
+    r = 0.3
+    c = (np.arange(R, dtype=np.float64) + 0.5) / R - 0.5
+    S = np.sqrt(c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2) - r
+    V, F = run(ctx, S)
+    del S
     E = Counter()
     for a, b in ((0, 1), (1, 2), (2, 0)):
         for x, y in zip(F[:, a].tolist(), F[:, b].tolist()):
