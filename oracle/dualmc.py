@@ -23,7 +23,10 @@ patches, keeps the two cubes consistent, and merges no patch elsewhere, so
 one pass over the faces suffices.
 
 A patch's vertex is the mean of its edges' crossing points (each divided by
-R, summed in ascending edge id, then divided by their number).  Quads: every
+R, summed in ascending edge id, then divided by their number).  With beta > 0
+the crossing uses the smoothed fraction t' = 1 / (1 + exp(-beta (t - 1/2)))
+instead of t (Appendix 2.1, the paper takes beta = 5), which keeps vertices
+away from the cube corners; beta = 0 is the plain linear crossing.  Quads: every
 valid grid edge whose four surrounding cubes exist joins the vertices of the
 patches holding it in those cubes, ordered right-handed around the edge's
 axis and oriented so that the normal points from the negative end to the
@@ -94,8 +97,9 @@ def holds_face(config: int, f: int) -> bool:
     return any(all(e in p for e in FACES[f]) for p in patches(config))
 
 
-def dualmc(S):
+def dualmc(S, beta: float = 0.0):
     """S: (R, R, R) float64 grid values -> (V (n, 3) float64, F (m, 3) int32)"""
+    import math
     S = np.asarray(S, dtype=np.float64)
     R = S.shape[0]
     P = S >= 0
@@ -132,6 +136,8 @@ def dualmc(S):
                         g1 = (i + (c1 & 1), j + ((c1 >> 1) & 1), k + ((c1 >> 2) & 1))
                         s0, s1 = S[g0], S[g1]
                         t = s0 / (s0 - s1)
+                        if beta > 0:
+                            t = 1.0 / (1.0 + math.exp(-beta * (t - 0.5)))
                         q = [g0[0] + 0.5, g0[1] + 0.5, g0[2] + 0.5]
                         q[e // 4] = q[e // 4] + t
                         sx += q[0] / R

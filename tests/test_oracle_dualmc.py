@@ -128,3 +128,25 @@ def test_random_grids_are_closed_manifolds(seed):
     S[:, :, 0] = S[:, :, -1] = 1.0
     V, F = dm.dualmc(S)
     assert len(F) > 0 and _manifold(F)
+
+
+def test_smoothed_crossing_on_planes():
+    # Appendix 2.1: the crossing fraction t (the plane's place between two grid
+    # points, known from its position) becomes 1 / (1 + exp(-beta (t - 1/2)));
+    # a plane midway between grid points stays put, others move towards the middle
+    R, beta = 10, 5.0
+    for c, t in ((0.4, 0.5), (0.43, 0.8), (0.361, 0.11)):
+        S = ou.centres(R)[..., 2] - c  # z - c: crosses between points k and k + 1, k = 3
+        V, F = dm.dualmc(S, beta)
+        V0, F0 = dm.dualmc(S)
+        want = (3.5 + 1.0 / (1.0 + np.exp(-beta * (t - 0.5)))) / R
+        assert np.abs(V[:, 2] - want).max() < 1e-12
+        assert np.abs(V0[:, 2] - (3.5 + t) / R).max() < 1e-12
+        assert np.array_equal(V[:, :2], V0[:, :2])
+
+
+def test_smoothed_sphere_keeps_topology():
+    S = np.linalg.norm(ou.centres(16) - 0.5, axis=-1) - 0.3
+    V, F = dm.dualmc(S, 5.0)
+    assert _euler(V, F) == 2 and _manifold(F)
+    assert np.abs(np.linalg.norm(V - 0.5, axis=1) - 0.3).max() < 1.0 / 16
