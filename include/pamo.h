@@ -215,7 +215,9 @@ pamo_status pamo_udf(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* 
  * S[(i * res + j) * res + k] (device float64) at the points ((i + 1/2) / res,
  * (j + 1/2) / res, (k + 1/2) / res); a point is outside when S - iso >= 0.
  * Per cube of 2^3 points: one vertex per surface patch, at the mean of the
- * linear crossing points of its edges; patches come from face links, and an
+ * crossing points of its edges: at the fraction t = s0 / (s0 - s1) of an edge
+ * when beta = 0, at 1 / (1 + exp(-beta (t - 1/2))) when beta > 0 (Appendix
+ * 2.1's smoothing, beta = 5 in the paper); patches come from face links, and an
  * ambiguous face shared by two cubes that would otherwise give a non-manifold
  * dual edge is resolved the other way in both (the paper's manifold fix).
  * Per crossed grid edge with four neighbouring cubes: one quad, oriented with
@@ -225,11 +227,11 @@ pamo_status pamo_udf(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* 
  * [fcap][3]; *nv_out, *nf_out (host) get the sizes.  res in [2, 512], at most
  * 2^26 cubes crossed by the surface (else PAMO_ERR_HIP from the scan); values
  * must be finite where a sign change occurs.  Fails with PAMO_ERR_CAPACITY,
- * writing only the sizes, when the mesh does not fit.  This version uses the
- * linear crossing and the plain quad split (no sigmoid interpolation or
- * envelope division yet).  Synchronises the stream. */
-pamo_status pamo_dualmc(pamo_ctx* ctx, const double* S, int32_t res, double iso, double* V_out, int64_t vcap,
-                        int32_t* F_out, int64_t fcap, int64_t* nv_out, int64_t* nf_out);
+ * writing only the sizes, when the mesh does not fit, and PAMO_ERR_ARG for
+ * beta < 0 or not finite.  Quads use the plain shorter-diagonal split (the
+ * envelope division is not built).  Synchronises the stream. */
+pamo_status pamo_dualmc(pamo_ctx* ctx, const double* S, int32_t res, double iso, double beta, double* V_out,
+                        int64_t vcap, int32_t* F_out, int64_t fcap, int64_t* nv_out, int64_t* nf_out);
 
 /* ---- utilities ---- */
 

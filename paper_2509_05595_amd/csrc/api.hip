@@ -1659,13 +1659,14 @@ pamo_status pamo_udf(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F,
   });
 }
 
-pamo_status pamo_dualmc(pamo_ctx* c, const double* S, int32_t res, double iso, double* V_out, int64_t vcap,
-                        int32_t* F_out, int64_t fcap, int64_t* nv_out, int64_t* nf_out) {
+pamo_status pamo_dualmc(pamo_ctx* c, const double* S, int32_t res, double iso, double beta, double* V_out,
+                        int64_t vcap, int32_t* F_out, int64_t fcap, int64_t* nv_out, int64_t* nf_out) {
   return guarded(c, [&]() -> pamo_status {
     if (!S || !nv_out || !nf_out || (vcap > 0 && !V_out) || (fcap > 0 && !F_out)) fail(PAMO_ERR_ARG, "null pointer");
     if (res < 2 || res > 512) fail(PAMO_ERR_ARG, "grid resolution outside [2, 512]");
     if (vcap < 0 || fcap < 0 || !(iso == iso)) fail(PAMO_ERR_ARG, "bad sizes or iso value");
-    if (!dualmc_run(c->ws, c->stream, S, res, iso, V_out, vcap, F_out, fcap, nv_out, nf_out))
+    if (!(beta >= 0.0) || !(beta < INFINITY)) fail(PAMO_ERR_ARG, "beta must be finite and >= 0");
+    if (!dualmc_run(c->ws, c->stream, S, res, iso, beta, V_out, vcap, F_out, fcap, nv_out, nf_out))
       fail(PAMO_ERR_CAPACITY, "output capacity too small for the extracted mesh");
     PAMO_HIP(hipStreamSynchronize(c->stream));
     return PAMO_OK;

@@ -17,8 +17,10 @@
 // unflipped, has one patch holding all four of its edges: that pair of
 // patches would otherwise be joined by four quads along one dual edge.
 //
-// Vertices: one per patch, the mean of its edges' linear crossing points
-// (summed in ascending edge order), numbered by cube (x outermost), then patch.
+// Vertices: one per patch, the mean of its edges' crossing points (summed in
+// ascending edge order), numbered by cube (x outermost), then patch.  The
+// crossing sits at the fraction t = s0 / (s0 - s1) of the edge, or, with
+// beta > 0, at 1 / (1 + exp(-beta (t - 1/2))) (Appendix 2.1).
 // Quads: one per crossed grid edge whose four neighbouring cubes exist,
 // ordered by axis then grid point; its vertices go counter-clockwise round
 // the axis seen from the axis's positive side, reversed when the lower end is
@@ -50,6 +52,7 @@ struct DGrid {
   const double* S;
   int r;
   double iso;
+  double beta;  // > 0: smoothed crossing fraction
 };
 
 __device__ __forceinline__ double gval(const DGrid& g, int i, int j, int k) {
@@ -218,7 +221,8 @@ __global__ void k_dmc_verts(DGrid g, const uint8_t* __restrict__ cfgs, const int
     const int i0 = i + (c0 & 1), j0 = j + ((c0 >> 1) & 1), k0 = k + ((c0 >> 2) & 1);
     const double s0 = gval(g, i0, j0, k0);
     const double s1 = gval(g, i0 + (a == 0), j0 + (a == 1), k0 + (a == 2));
-    const double t = s0 / (s0 - s1);
+    double t = s0 / (s0 - s1);
+    if (g.beta > 0.0) t = 1.0 / (1.0 + exp(-g.beta * (t - 0.5)));
     double q[3] = {(double)i0 + 0.5, (double)j0 + 0.5, (double)k0 + 0.5};
     q[a] = q[a] + t;
     sx[p] += q[0] / rr;
@@ -329,11 +333,11 @@ int32_t compact_long(Workspace& ws, hipStream_t s, const uint8_t* flags, int64_t
 
 }  // namespace
 
-bool dualmc_run(Workspace& ws, hipStream_t s, const double* S, int res, double iso, double* V, int64_t vcap,
-                int32_t* F, int64_t fcap, int64_t* nv, int64_t* nf) {
+bool dualmc_run(Workspace& ws, hipStream_t s, const double* S, int res, double iso, double beta, double* V,
+                int64_t vcap, int32_t* F, int64_t fcap, int64_t* nv, int64_t* nf) {
   *nv = *nf = 0;
   if (res < 2) return true;
-  DGrid g{S, res, iso};
+  DGrid g{S, res, iso, beta};
   const int m = res - 1;
   const int64_t npt = (int64_t)res * res * res, ncube = (int64_t)m * m * m, nedge = 3 * npt;
   uint8_t* sg = ws.get<uint8_t>("dmc.sign", npt);

@@ -116,7 +116,8 @@ def lib():
         L.pamo_hausdorff.argtypes = [P, P, I64, P, I64, P, I64, P, C.POINTER(C.c_double)]
         L.pamo_self_intersections.argtypes = [P, P, I64, P, I64, P, I64, C.POINTER(I64)]
         L.pamo_udf.argtypes = [P, P, I64, P, I64, C.c_int32, C.c_double, P]
-        L.pamo_dualmc.argtypes = [P, P, C.c_int32, C.c_double, P, I64, P, I64, C.POINTER(I64), C.POINTER(I64)]
+        L.pamo_dualmc.argtypes = [P, P, C.c_int32, C.c_double, C.c_double, P, I64, P, I64, C.POINTER(I64),
+                                  C.POINTER(I64)]
         L.pamo_tri_pairs.argtypes = [P, P, P, P, P, I64, P]
         L.pamo_profile_enable.argtypes = [P, C.c_uint32]
         L.pamo_profile_phases.argtypes = []
@@ -349,20 +350,21 @@ class Context:
         self._check(lib().pamo_udf(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], int(res), band, _ptr(out)))
         return out
 
-    def dualmc(self, S, iso=0.0, vcap=None, fcap=None):
+    def dualmc(self, S, iso=0.0, vcap=None, fcap=None, beta=0.0):
         """Dual Marching Cubes of the (res, res, res) float64 grid S at level iso
-        -> (V (nv, 3) float64, F (nf, 3) int32) on the device."""
+        -> (V (nv, 3) float64, F (nf, 3) int32) on the device; beta > 0 smooths
+        the crossing fractions (the paper uses 5)."""
         assert S.dtype == torch.float64 and S.is_contiguous() and S.dim() == 3
         res = S.shape[0]
         nv, nf = C.c_int64(0), C.c_int64(0)
         if vcap is None or fcap is None:  # sizes first: a call with no room writes only them
-            self._check(lib().pamo_dualmc(self._h, _ptr(S), int(res), float(iso), None, 0, None, 0,
+            self._check(lib().pamo_dualmc(self._h, _ptr(S), int(res), float(iso), float(beta), None, 0, None, 0,
                                           C.byref(nv), C.byref(nf)), allow=(PAMO_OK, PAMO_ERR_CAPACITY))
             vcap = nv.value if vcap is None else int(vcap)
             fcap = nf.value if fcap is None else int(fcap)
         V = torch.empty((max(vcap, 1), 3), dtype=torch.float64, device=self.device)
         F = torch.empty((max(fcap, 1), 3), dtype=torch.int32, device=self.device)
-        self._check(lib().pamo_dualmc(self._h, _ptr(S), int(res), float(iso), _ptr(V), vcap, _ptr(F), fcap,
+        self._check(lib().pamo_dualmc(self._h, _ptr(S), int(res), float(iso), float(beta), _ptr(V), vcap, _ptr(F), fcap,
                                       C.byref(nv), C.byref(nf)))
         return V[:nv.value], F[:nf.value]
 

@@ -106,3 +106,43 @@ def test_full_size_sphere(ctx, R):
     a, b, c = V[F[:, 0]], V[F[:, 1]], V[F[:, 2]]
     vol = np.einsum("ij,ij->i", a - 0.5, np.cross(b - 0.5, c - 0.5)).sum() / 6
     assert abs(vol / (4 / 3 * np.pi * r ** 3) - 1) < 0.01
+
+
+# Smoothed crossings (Appendix 2.1, beta = 5): exp is evaluated by different
+# libraries on the two sides (each within about an ulp), so a crossing
+# fraction may differ by a few 1e-16; added to a grid coordinate below 512 it
+# can change that sum by one ulp (about 1e-13), which the division by R and the
+# mean bring below 1e-15 in a coordinate.  Faces must match exactly, except that
+# a quad whose two diagonals are equally long within rounding may be split the
+# other way on either side.
+VTOL = 1e-14
+
+
+def same_smoothed(ctx, S, iso=0.0, beta=5.0):
+    V, F = run(ctx, S, iso, beta=beta)
+    Vo, Fo = dm.dualmc(np.asarray(S, dtype=np.float64) - iso, beta)
+    assert V.shape == Vo.shape and F.shape == Fo.shape
+    assert np.abs(V - Vo).max() <= VTOL
+    for q in np.nonzero(np.any(F != Fo, axis=1))[0] // 2:
+        a, b = Fo[2 * q], Fo[2 * q + 1]
+        assert set(F[2 * q]) | set(F[2 * q + 1]) == set(a) | set(b)
+        diag = sorted(set(a) & set(b))
+        other = sorted((set(a) | set(b)) - set(diag))
+        d1 = np.sum((Vo[diag[0]] - Vo[diag[1]]) ** 2)
+        d2 = np.sum((Vo[other[0]] - Vo[other[1]]) ** 2)
+        assert abs(d1 - d2) <= 1e-12
+    return V, F
+
+
+def test_smoothed_crossings(ctx):
+    same_smoothed(ctx, sphere(20))
+    rng = np.random.default_rng(7)
+    same_smoothed(ctx, rng.standard_normal((11, 11, 11)), iso=0.1)
+    V, F = dm.dualmc(sphere(12))
+    Vg, Fg = run(ctx, sphere(12), beta=0.0)  # beta = 0: the linear crossing, bit for bit
+    assert np.array_equal(Vg.view(np.uint64), V.view(np.uint64)) and np.array_equal(Fg, F)
+
+
+def test_smoothed_rejects_bad_beta(ctx):
+    with pytest.raises(RuntimeError):
+        run(ctx, sphere(8), beta=-1.0)
