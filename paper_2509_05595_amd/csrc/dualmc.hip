@@ -28,13 +28,13 @@
 // two triangles along its shorter diagonal (the one through its first vertex
 // on a tie).
 //
-// Kernels: one thread per grid point (sign byte), one per cube (configuration,
-// crossed or not), a compaction of the crossed cubes, one thread per crossed
-// cube (flips, patches), a scan of their patch counts, one per crossed cube
-// (positions), one per grid edge (crossed interior edge), a compaction, one
-// per crossing (two triangles).
-// The patch structure of a cube is found once, by a small union-find, and
-// kept as two bits per edge.
+// Kernels: one thread per grid point (sign byte); one per cube (configuration,
+// crossed or not); one per grid point (its three edges: crossed and interior
+// or not); compactions of the crossed cubes and of the crossed edges; one
+// thread per crossed cube (flips, patches), a scan of their patch counts, one
+// per crossed cube (positions); one per crossed edge (two triangles).  The
+// patch structure of a cube is found once, by a small union-find, and kept as
+// two bits per edge.
 
 #include <hip/hip_runtime.h>
 
