@@ -23,17 +23,23 @@ W_S = 0.005
 TOLERANCE = 4  # Sec. 5.3
 
 
-def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (no GPU involved)."""
-    if not force and os.path.exists(LIB_PATH):
-        return LIB_PATH
-    srcs = [os.path.join(_HERE, s) for s in _SRC]
-    tmp = LIB_PATH + ".tmp"
+SOURCES = tuple(_SRC)
+
+
+def build(force: bool = True, src_dir: str = _HERE, out: str = None) -> str:
+    """Compile liboracle.so with gcc (no GPU involved).  src_dir / out: build
+    the sources of another directory into another file (the mutation tests
+    build planted variants this way)."""
+    out = out or LIB_PATH
+    if not force and os.path.exists(out):
+        return out
+    srcs = [os.path.join(src_dir, s) for s in _SRC]
+    tmp = out + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
            "-fPIC", "-shared", "-Wall", "-Wno-unused-function", "-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
 class Opts(C.Structure):

@@ -113,10 +113,13 @@ def _random_pair(rng, kind):
             return P, ip, Q, iq
 
 
-@pytest.mark.parametrize("kind", ["random", "coplanar", "sharp", "vertex", "edge",
-                                  "coplanar_vertex", "coplanar_edge"])
+PAIR_KINDS = ["random", "coplanar", "sharp", "vertex", "edge", "coplanar_vertex", "coplanar_edge"]
+
+
+@pytest.mark.parametrize("kind", PAIR_KINDS)
 def test_tri_pair_matches_exact_lp(kind):
-    rng = np.random.default_rng(hash(kind) % (2 ** 32))
+    # a fixed seed per kind, so a failing case replays
+    rng = np.random.default_rng(7100 + PAIR_KINDS.index(kind))
     pos = neg = 0
     for _ in range(300):
         P, ip, Q, iq = _random_pair(rng, kind)
