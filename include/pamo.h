@@ -46,7 +46,8 @@ typedef int32_t pamo_status;
 #define PAMO_ERR_SELF_INTERSECTING (-3) /* input has a self-intersection (only when validating) */
 #define PAMO_ERR_DEGENERATE (-4)  /* a face repeats a vertex */
 #define PAMO_ERR_HIP (-6)         /* HIP runtime error */
-#define PAMO_ERR_CAPACITY (-7)    /* an internal bound was exceeded (traversal stack, deferred pairs) */
+#define PAMO_ERR_CAPACITY (-7)    /* an internal bound was exceeded (traversal stack, deferred pairs), or
+                                     the caller's workspace is too small (pamo_set_workspace) */
 
 typedef struct {
   double w_e;          /* edge-length weight of Eq. 1 (paper default 0.001) */
@@ -77,6 +78,9 @@ typedef struct {
                            reading of the paper's conversion of costs from floats): each keyed edge's key is
                            its rank in that order above its id.  The learned proposal, pamo_features and
                            pamo_collect read the float32 cost from the key and refuse it (PAMO_ERR_ARG) */
+  int32_t pair_capacity; /* first capacity (pairs) of a query pass's candidate-pair buffer; a pass that
+                           collects more grows the buffer and runs again (no effect on results).
+                           0: max(2^20, 16 nf) (default) */
 } pamo_options;
 
 typedef struct {
@@ -99,15 +103,45 @@ typedef struct {
 void pamo_default_options(pamo_options* opt);
 
 /* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
- * NULL = the null stream).  `opt` may be NULL (defaults).  The context owns
- * its device workspace, which grows to fit the largest mesh seen. */
+ * NULL = the null stream).  `opt` may be NULL (defaults).  Unless it is given
+ * a workspace (pamo_set_workspace), the context allocates its own device
+ * workspace, which grows to fit the largest mesh seen. */
 pamo_status pamo_create(pamo_ctx** out, int device, void* hip_stream, const pamo_options* opt);
 void pamo_destroy(pamo_ctx* ctx);
 pamo_status pamo_set_options(pamo_ctx* ctx, const pamo_options* opt);
 /* Message of the last error on this context (valid until the next call). */
 const char* pamo_last_error(const pamo_ctx* ctx);
-/* Bytes of device workspace the context currently holds. */
-int64_t pamo_workspace_bytes(const pamo_ctx* ctx);
+
+/* Device workspace (scratch) of the method (the problem statement of Sec. 3:
+ * a mesh in, its simplification out; everything between lives here).
+ *
+ * pamo_workspace_bytes: bytes of workspace that suffice for every mesh entry
+ * point (pamo_quadrics, pamo_select, pamo_check, pamo_collapse,
+ * pamo_simplify, pamo_simplify_batch with up to 4096 meshes of these totals,
+ * pamo_collect, pamo_features, pamo_self_intersections) on a mesh of nv
+ * vertices and nf faces with options opt (NULL: defaults): the exact sum of
+ * the buffers those calls reserve, each rounded up to 256 bytes.  A query
+ * pass whose candidate pairs overflow pair_capacity takes more, when the
+ * workspace has it, and fails with PAMO_ERR_CAPACITY when it has not.
+ * Returns 0 for sizes no entry point accepts (nv or nf below 4, nf above
+ * 2^31 / 3).  Host-only; no context or device needed.
+ *
+ * pamo_set_workspace: from now on the context takes all its device scratch
+ * from dev (device memory on the context's device, 256-byte aligned, at least
+ * 4 KiB, owned by the caller, e.g. a torch tensor), which the caller keeps
+ * alive and leaves alone while calls on the context run; every call carves it
+ * afresh from its start, so nothing in it outlives a call.  The context frees
+ * the workspace it allocated before.  A call whose needs exceed `bytes` fails
+ * with PAMO_ERR_CAPACITY (the message names the buffer); the mesh entry points
+ * fit whenever bytes >= pamo_workspace_bytes(nv, nf, opt).  The remeshing and
+ * training entry points carve what they need as they go.  dev = NULL: back to
+ * workspace the context allocates itself.  Synchronises the stream.
+ *
+ * pamo_workspace_held: bytes of device workspace the context has allocated
+ * itself and holds (0 while it works in a caller's workspace). */
+size_t pamo_workspace_bytes(int64_t nv, int64_t nf, const pamo_options* opt);
+pamo_status pamo_set_workspace(pamo_ctx* ctx, void* dev, size_t bytes);
+int64_t pamo_workspace_held(const pamo_ctx* ctx);
 
 /* ---- round-level steps (stateless: the caller owns everything between calls) ---- */
 
@@ -119,6 +153,8 @@ pamo_status pamo_quadrics(pamo_ctx* ctx, const double* V, int64_t nv, const int3
 
 /* Edge costs (Eq. 1 with the QEM placement), 64-bit keys and the independent
  * edges of one round (cost propagation and region selection of Sec. 5.1).
+ * The quadrics are recomputed from V and F inside (they are a pure function
+ * of the mesh; a caller's Q could only disagree), so no Q is taken.
  *   flags  device uint8 [3 nf] invalid-edge flags, or NULL
  *   demote device uint8 [3 nf] edges to leave out this round, or NULL
  *   keys   device uint64 [3 nf] output (key of the edge on both half-edges;
@@ -135,7 +171,8 @@ pamo_status pamo_select(pamo_ctx* ctx, const double* V, int64_t nv, const int32_
  * target (keep the smallest keys when more pass than needed to reach
  * target_faces), then apply them together to an internal copy and run the
  * intersection check / undo loop (Sec. 5.2, 5.3) to its fixed point.
- *   cand, ncand  as produced by pamo_select for the same V, F, flags
+ *   cand, ncand  as produced by pamo_select for the same V, F, flags (at most
+ *                nf / 2 + 1 of them: chosen edges have disjoint rings)
  *   vbar   device float64 [ncand][3] output: new vertex position
  *   reason device uint8 [ncand] output: 0 collapse, 1 link condition,
  *          2 degenerate or flipped triangle, 3 self-intersection, 4 not needed
@@ -251,6 +288,14 @@ pamo_status pamo_tri_pairs(pamo_ctx* ctx, const double* P, const int32_t* ip, co
                            int64_t n, uint8_t* out);
 
 /* ---- the learned proposal (an addition to the paper's method) ----
+ *
+ * Entry points: pamo_set_mlp (set the network's weights), pamo_mlp_logits
+ * (inference), pamo_mlp_grad and pamo_mlp_train (training: gradient, and Adam
+ * steps over many batches in one call), plus pamo_features and pamo_collect
+ * (the training rows).  Training takes float master weights and a batch
+ * schedule rather than one bfloat16 step per call, so that thousands of
+ * steps run without a host round trip; inference takes the grid-exact
+ * network of pamo_mlp below.
  *
  * Each round, a small network scores every selected candidate from 32
  * features of its neighbourhood; candidates scored below a threshold are set

@@ -172,14 +172,14 @@ void check_err_bits(int e) {
   fail(PAMO_ERR_HIP, "unknown device error");
 }
 
-MeshView mesh_bufs(pamo_ctx* c, const char* tag, int64_t nv, int64_t nf) {
+MeshView mesh_bufs(Workspace& w, const char* tag, int64_t nv, int64_t nf) {
   std::string t(tag);
   MeshView m;
-  m.V = c->ws.get<double>(t + ".V", 3 * nv);
-  m.F = c->ws.get<int>(t + ".F", 3 * nf);
-  m.twin = c->ws.get<int>(t + ".twin", 3 * nf);
-  m.vh = c->ws.get<int>(t + ".vh", nv);
-  m.flags = c->ws.get<uint8_t>(t + ".flags", 3 * nf);
+  m.V = w.get<double>(t + ".V", 3 * nv);
+  m.F = w.get<int>(t + ".F", 3 * nf);
+  m.twin = w.get<int>(t + ".twin", 3 * nf);
+  m.vh = w.get<int>(t + ".vh", nv);
+  m.flags = w.get<uint8_t>(t + ".flags", 3 * nf);
   m.nv = (int)nv;
   m.nf = (int)nf;
   return m;
@@ -294,16 +294,22 @@ const int* query_pass(pamo_ctx* c, const Bvh& bvh, QueryMode mode, const int* ql
   return query_settle(c, bvh, mode, qlist, nq_dev, bound, nq_est, qa, bytes, vbytes, readback(c));
 }
 
+// initial capacity of the candidate-pair buffer of a query pass (grown and
+// the pass repeated when it overflows)
+int64_t pair_capacity(const pamo_options& o, int64_t nf) {
+  if (o.pair_capacity > 0) return o.pair_capacity;
+  return std::min<int64_t>(std::max<int64_t>(1 << 20, 16 * nf), INT32_MAX / 2);
+}
+
 void init_pair_buffer(pamo_ctx* c, QueryArgs& qa, int64_t nf) {
-  int64_t cap = std::max<int64_t>(1 << 20, 16 * nf);
+  int64_t cap = pair_capacity(c->opt, nf);
   qa.cand = c->ws.get<int2>("q.pairs", cap);
   qa.cand_cap = (int)std::min<int64_t>(cap, INT32_MAX / 2);
   qa.ncand = c->dcnt + C_NCANDP;
 }
 
-RoundBufs round_bufs(pamo_ctx* c, int64_t nv, int64_t nf) {
+RoundBufs round_bufs(Workspace& w, int64_t nv, int64_t nf) {
   RoundBufs b;
-  Workspace& w = c->ws;
   int64_t nh = 3 * nf;
   b.Q = w.get<double>("r.Q", 10 * nv);
   b.key = w.get<uint64_t>("r.key", nh);
@@ -330,6 +336,62 @@ RoundBufs round_bufs(pamo_ctx* c, int64_t nv, int64_t nf) {
   b.X = nullptr;
   b.dlist = nullptr;
   return b;
+}
+
+// Which optional parts of the path a call can reach.
+struct Parts {
+  int nmesh = 1;         // > 1: the batched form (per-mesh ids and tallies)
+  bool learned = false;  // overlap counts, features and the set-aside list of the learned proposal
+  bool collect = false;  // training-row logging (pamo_collect)
+};
+
+// Reserve every buffer a mesh entry point can request, at its largest size for
+// a mesh (or batch) of nv vertices and nf faces: later requests of the call
+// then fit their blocks, so an arena is carved once and the size query
+// (counting mode) is the exact total.  Sizes are the round-0 sizes (meshes
+// only shrink); candidates of a round are at most nf / 2 + 1 (their rings are
+// disjoint).
+void reserve_mesh(Workspace& w, int64_t nv, int64_t nf, const pamo_options& o, const Parts& p) {
+  const int64_t bound = nf / 2 + 1;
+  mesh_bufs(w, "mA", nv, nf);
+  mesh_bufs(w, "mB", nv, nf);
+  if (p.nmesh > 1) {
+    w.get<int>("mA.fmesh", nf);
+    w.get<int>("mA.vmesh", nv);
+    w.get<int>("mB.fmesh", nf);
+    w.get<int>("mB.vmesh", nv);
+    w.get<int>("bt.dev", 15 * (int64_t)p.nmesh + 2);
+    w.get<int>("bt.need", p.nmesh);
+    w.get<uint8_t>("bt.done", p.nmesh);
+    w.get<uint8_t>("bt.use", p.nmesh);
+  }
+  round_bufs(w, nv, nf);
+  w.get<int2>("q.pairs", pair_capacity(o, nf));
+  w.get<int>("ord.copy", nf);
+  w.get<float>("w.box", 6 * nf);
+  w.get<int2>("w.defer", std::max<int64_t>(1 << 16, nf));
+  w.get<int2>("w.pairs", 1);
+  if (p.learned || p.collect) {
+    w.get<int>("mA.ovl", nf);
+    w.get<int>("mB.ovl", nf);
+    w.get<int>("r.ovl_new", nf);
+    w.get<float>("r.X", bound * (int64_t)LEARN_NFEAT);
+    w.get<int>("r.dlist", bound);
+  }
+  if (p.collect) {
+    w.get<double>("col.V", 3 * nv);
+    w.get<int>("col.F", 3 * nf);
+    learn_reserve(w, bound);
+  }
+  bvh_reserve(w, nf, p.nmesh > 1);
+  round_reserve(w, nv, nf, bound, p.nmesh, o.key_mode != 0);
+  prim_reserve(w, 3 * nf, nf, 3 * nf, 2 * nf + nv);
+}
+
+// the reservation of a mesh entry point (arena mode only: owned buffers grow
+// on demand)
+void reserve(pamo_ctx* c, int64_t nv, int64_t nf, const Parts& p) {
+  if (c->ws.arena) reserve_mesh(c->ws, nv, nf, c->opt, p);
 }
 
 struct RoundResult {
@@ -581,17 +643,17 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
   cur.vbox = b.vbox;
   {
     TIMED(PH_QUADRICS, 108 * nv + 24 * nf);
-    launch_quadrics(s, cur, b.Q, cnt + C_ERR, b.vmin);
+    launch_quadrics(s, cur, b.Q, cnt + C_ERR);
   }
   {
     TIMED(PH_COST, 104 * nv + 51 * nf);
-    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, cnt + C_ERR, b.vmin,
-                     c->opt.cost_target, c->opt.prefilter != 0, c->opt.key_mode != 0);
+    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, cnt + C_ERR, c->opt.cost_target,
+                     c->opt.prefilter != 0, c->opt.key_mode != 0);
   }
   {
     TIMED(PH_SELECT, 20 * nv + 93 * nf);
     if (c->opt.key_mode) launch_rank_keys(c->ws, s, cur, b.key);
-    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, c->opt.key_mode == 0);
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
   }
   const int bound = cur.nf / 2 + 1;
   if (learned || logging) {
@@ -769,10 +831,15 @@ pamo_status guarded(pamo_ctx* c, Fn&& fn) {
   try {
     PAMO_HIP(hipSetDevice(c->device));
     c->err.clear();
+    c->ws.begin_call();
+    c->dcnt = c->ws.get<int>("ctx.cnt", C_COUNT);  // first in an arena
     return fn();
   } catch (const Fail& f) {
     c->err = f.msg;
     return f.code;
+  } catch (const WorkspaceFull& e) {
+    c->err = e.what();
+    return PAMO_ERR_CAPACITY;
   } catch (const HipError& e) {
     c->err = e.what();
     return PAMO_ERR_HIP;
@@ -938,17 +1005,17 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs
   cur.vbox = b.vbox;
   {
     TIMED(PH_QUADRICS, 108 * nv + 24 * nf);
-    launch_quadrics(s, cur, b.Q, cnt + C_ERR, b.vmin);
+    launch_quadrics(s, cur, b.Q, cnt + C_ERR);
   }
   {
     TIMED(PH_COST, 104 * nv + 51 * nf);
-    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, B.done, b.key, cnt + C_ERR, b.vmin,
-                     c->opt.cost_target, c->opt.prefilter != 0, c->opt.key_mode != 0);
+    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, B.done, b.key, cnt + C_ERR, c->opt.cost_target,
+                     c->opt.prefilter != 0, c->opt.key_mode != 0);
   }
   {
     TIMED(PH_SELECT, 20 * nv + 93 * nf);
     if (c->opt.key_mode) launch_rank_keys(c->ws, s, cur, b.key);
-    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, c->opt.key_mode == 0);
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
   }
   const int bound = cur.nf / 2 + 1;
   if (learned) {
@@ -1051,14 +1118,18 @@ pamo_status simplify_run(pamo_ctx* c, const double* V, int64_t nv, const int32_t
   if (L->learned && c->opt.key_mode)
     fail(PAMO_ERR_ARG, "the learned proposal's features read the float32 cost from the key (key_mode 0)");
   hipStream_t s = c->stream;
-  MeshView cur = mesh_bufs(c, "mA", nv, nf);
-  MeshView alt = mesh_bufs(c, "mB", nv, nf);
+  Parts parts;
+  parts.learned = L->track;
+  parts.collect = L->X != nullptr;
+  reserve(c, nv, nf, parts);
+  MeshView cur = mesh_bufs(c->ws, "mA", nv, nf);
+  MeshView alt = mesh_bufs(c->ws, "mB", nv, nf);
   load_mesh(c, cur, V, F, nullptr);
   if (c->opt.validate_input) {
     int2* dummy = c->ws.get<int2>("w.pairs", 1);
     if (whole_mesh_pairs(c, cur, dummy, 0) > 0) fail(PAMO_ERR_SELF_INTERSECTING, "the input intersects itself");
   }
-  RoundBufs b = round_bufs(c, nv, nf);
+  RoundBufs b = round_bufs(c->ws, nv, nf);
   if (L->track) {
     cur.ovl = c->ws.get<int>("mA.ovl", nf);
     alt.ovl = c->ws.get<int>("mB.ovl", nf);
@@ -1128,8 +1199,7 @@ pamo_status pamo_create(pamo_ctx** out, int device, void* hip_stream, const pamo
   c->stream = (hipStream_t)hip_stream;
   pamo_default_options(&c->opt);
   if (opt) c->opt = *opt;
-  if (hipSetDevice(device) != hipSuccess || hipHostMalloc((void**)&c->hcnt, C_COUNT * sizeof(int)) != hipSuccess ||
-      hipMalloc((void**)&c->dcnt, C_COUNT * sizeof(int)) != hipSuccess) {
+  if (hipSetDevice(device) != hipSuccess || hipHostMalloc((void**)&c->hcnt, C_COUNT * sizeof(int)) != hipSuccess) {
     if (c->hcnt) (void)hipHostFree(c->hcnt);
     delete c;
     return PAMO_ERR_HIP;
@@ -1148,7 +1218,6 @@ void pamo_destroy(pamo_ctx* c) {
   }
   for (auto e : c->prof.pool) (void)hipEventDestroy(e);
   c->ws.release();
-  if (c->dcnt) (void)hipFree(c->dcnt);
   if (c->hcnt) (void)hipHostFree(c->hcnt);
   if (c->hbt) (void)hipHostFree(c->hbt);
   if (c->mlp) (void)hipFree(c->mlp);
@@ -1164,19 +1233,52 @@ pamo_status pamo_set_options(pamo_ctx* c, const pamo_options* opt) {
   int qc = opt->query_coop;
   if (qc != 0 && qc != 1 && qc != 2 && qc != 4 && qc != 8 && qc != 16) return PAMO_ERR_ARG;
   if (opt->coop_below < 0) return PAMO_ERR_ARG;
+  if (opt->pair_capacity < 0 || opt->pair_capacity > INT32_MAX / 2) return PAMO_ERR_ARG;
   c->opt = *opt;
   return PAMO_OK;
 }
 
 const char* pamo_last_error(const pamo_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-int64_t pamo_workspace_bytes(const pamo_ctx* c) { return c ? (int64_t)c->ws.total : 0; }
+int64_t pamo_workspace_held(const pamo_ctx* c) { return c && !c->ws.arena ? (int64_t)c->ws.total : 0; }
+
+size_t pamo_workspace_bytes(int64_t nv, int64_t nf, const pamo_options* opt) {
+  if (nv < 4 || nf < 4 || nf > (int64_t)(INT32_MAX / 3) - 1 || nv > INT32_MAX - 1) return 0;
+  pamo_options o;
+  pamo_default_options(&o);
+  if (opt) o = *opt;
+  try {
+    Workspace w;
+    w.counting = true;
+    w.get<int>("ctx.cnt", C_COUNT);
+    Parts p;
+    p.nmesh = PAMO_MAX_MESHES;
+    p.learned = true;
+    p.collect = true;
+    reserve_mesh(w, nv, nf, o, p);
+    return w.total;
+  } catch (...) {
+    return 0;
+  }
+}
+
+pamo_status pamo_set_workspace(pamo_ctx* c, void* dev, size_t bytes) {
+  return guarded(c, [&]() -> pamo_status {
+    if (dev && ((uintptr_t)dev % 256 != 0)) fail(PAMO_ERR_ARG, "workspace must be 256-byte aligned");
+    if (dev && bytes < 4096) fail(PAMO_ERR_ARG, "workspace smaller than 4 KiB");
+    PAMO_HIP(hipStreamSynchronize(c->stream));  // owned buffers may still be in use
+    c->ws.set_arena(dev, bytes);
+    c->dcnt = nullptr;  // taken again at the start of every call
+    return PAMO_OK;
+  });
+}
 
 pamo_status pamo_quadrics(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F, int64_t nf, double* Q) {
   return guarded(c, [&]() -> pamo_status {
     if (!V || !F || !Q) fail(PAMO_ERR_ARG, "null pointer");
     check_sizes(nv, nf);
-    MeshView A = mesh_bufs(c, "mA", nv, nf);
+    reserve(c, nv, nf, Parts{});
+    MeshView A = mesh_bufs(c->ws, "mA", nv, nf);
     load_mesh(c, A, V, F, nullptr);
     launch_quadrics(c->stream, A, Q, c->dcnt + C_ERR);
     check_err_bits(readback(c)[C_ERR]);
@@ -1189,12 +1291,13 @@ pamo_status pamo_select(pamo_ctx* c, const double* V, int64_t nv, const int32_t*
   return guarded(c, [&]() -> pamo_status {
     if (!V || !F || !cand || !ncand) fail(PAMO_ERR_ARG, "null pointer");
     check_sizes(nv, nf);
-    MeshView A = mesh_bufs(c, "mA", nv, nf);
+    reserve(c, nv, nf, Parts{});
+    MeshView A = mesh_bufs(c->ws, "mA", nv, nf);
     load_mesh(c, A, V, F, flags);
-    RoundBufs b = round_bufs(c, nv, nf);
+    RoundBufs b = round_bufs(c->ws, nv, nf);
     uint64_t* key = keys ? keys : b.key;
     launch_quadrics(c->stream, A, b.Q, c->dcnt + C_ERR);
-    launch_cost_keys(c->stream, A, b.Q, c->opt.w_e, c->opt.w_s, demote, nullptr, key, c->dcnt + C_ERR, nullptr,
+    launch_cost_keys(c->stream, A, b.Q, c->opt.w_e, c->opt.w_s, demote, nullptr, key, c->dcnt + C_ERR,
                      c->opt.cost_target, c->opt.prefilter != 0, c->opt.key_mode != 0);
     if (c->opt.key_mode) launch_rank_keys(c->ws, c->stream, A, key);
     launch_select(c->ws, c->stream, A, key, b.vmin, cand, ncand);
@@ -1210,17 +1313,19 @@ pamo_status pamo_check(pamo_ctx* c, const double* V, int64_t nv, const int32_t* 
     if (!V || !F || !cand || !ncand || !vbar || !reason) fail(PAMO_ERR_ARG, "null pointer");
     check_sizes(nv, nf);
     if (target_faces < 0) fail(PAMO_ERR_ARG, "negative target");
-    MeshView A = mesh_bufs(c, "mA", nv, nf);
+    reserve(c, nv, nf, Parts{});
+    MeshView A = mesh_bufs(c->ws, "mA", nv, nf);
     load_mesh(c, A, V, F, flags);
-    RoundBufs b = round_bufs(c, nv, nf);
+    RoundBufs b = round_bufs(c->ws, nv, nf);
     int nc = read_count(c, ncand);
-    if (nc < 0 || nc > 3 * nf) fail(PAMO_ERR_ARG, "bad candidate count");
+    // chosen edges have disjoint rings of at least two faces each
+    if (nc < 0 || nc > nf / 2 + 1) fail(PAMO_ERR_ARG, "bad candidate count (more than nf / 2 + 1)");
     if (undo_iterations) *undo_iterations = 0;
     if (nc == 0) return PAMO_OK;
     hipStream_t s = c->stream;
     fill_i32(s, c->dcnt, C_COUNT, 0);
     launch_quadrics(s, A, b.Q, c->dcnt + C_ERR);
-    launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR, nullptr,
+    launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR,
                      c->opt.cost_target, false, c->opt.key_mode != 0);
     if (c->opt.key_mode) launch_rank_keys(c->ws, s, A, b.key);  // the cap orders by key
     int64_t teff = target_faces - target_faces % 2;
@@ -1247,11 +1352,12 @@ pamo_status pamo_collapse(pamo_ctx* c, double* V, int64_t* nv, int32_t* F, int64
   return guarded(c, [&]() -> pamo_status {
     if (!V || !nv || !F || !nf || !cand || !ncand || !vbar || !reason) fail(PAMO_ERR_ARG, "null pointer");
     check_sizes(*nv, *nf);
+    reserve(c, *nv, *nf, Parts{});
     hipStream_t s = c->stream;
-    MeshView A = mesh_bufs(c, "mA", *nv, *nf);
-    MeshView B = mesh_bufs(c, "mB", *nv, *nf);
+    MeshView A = mesh_bufs(c->ws, "mA", *nv, *nf);
+    MeshView B = mesh_bufs(c->ws, "mB", *nv, *nf);
     load_mesh(c, A, V, F, flags_io);
-    RoundBufs b = round_bufs(c, *nv, *nf);
+    RoundBufs b = round_bufs(c->ws, *nv, *nf);
     int nc = read_count(c, ncand);
     if (nc < 0 || nc > 3 * *nf) fail(PAMO_ERR_ARG, "bad candidate count");
     int* cnt = c->dcnt;
@@ -1337,9 +1443,13 @@ pamo_status pamo_simplify_batch(pamo_ctx* c, int32_t nmesh, const double* V, con
     }
     const int64_t nv = v_off[nmesh], nf = f_off[nmesh];
     check_sizes(nv, nf);
+    Parts parts;
+    parts.nmesh = std::max(nmesh, 2);
+    parts.learned = c->opt.learned != 0;
+    reserve(c, nv, nf, parts);
     hipStream_t s = c->stream;
-    MeshView cur = mesh_bufs(c, "mA", nv, nf);
-    MeshView alt = mesh_bufs(c, "mB", nv, nf);
+    MeshView cur = mesh_bufs(c->ws, "mA", nv, nf);
+    MeshView alt = mesh_bufs(c->ws, "mB", nv, nf);
     cur.fmesh = c->ws.get<int>("mA.fmesh", nf);
     cur.vmesh = c->ws.get<int>("mA.vmesh", nv);
     alt.fmesh = c->ws.get<int>("mB.fmesh", nf);
@@ -1365,7 +1475,7 @@ pamo_status pamo_simplify_batch(pamo_ctx* c, int32_t nmesh, const double* V, con
       int2* dummy = c->ws.get<int2>("w.pairs", 1);
       if (whole_mesh_pairs(c, cur, dummy, 0, nmesh) > 0) fail(PAMO_ERR_SELF_INTERSECTING, "an input mesh intersects itself");
     }
-    RoundBufs b = round_bufs(c, nv, nf);
+    RoundBufs b = round_bufs(c->ws, nv, nf);
     const bool learned = c->opt.learned != 0;
     if (learned && !c->mlp) fail(PAMO_ERR_ARG, "the learned proposal needs a network (pamo_set_mlp)");
     if (learned && c->opt.key_mode)
@@ -1528,13 +1638,16 @@ pamo_status pamo_features(pamo_ctx* c, const double* V, int64_t nv, const int32_
     check_sizes(nv, nf);
     if (ne > 3 * nf) fail(PAMO_ERR_ARG, "more edges than half-edges");
     if (c->opt.key_mode) fail(PAMO_ERR_ARG, "the features read the float32 cost from the key (key_mode 0)");
+    Parts parts;
+    parts.learned = true;
+    reserve(c, nv, nf, parts);
     hipStream_t s = c->stream;
-    MeshView A = mesh_bufs(c, "mA", nv, nf);
+    MeshView A = mesh_bufs(c->ws, "mA", nv, nf);
     load_mesh(c, A, V, F, nullptr);
     A.ovl = c->ws.get<int>("mA.ovl", nf);
     int2* dummy = c->ws.get<int2>("w.pairs", 1);
     whole_mesh_pairs(c, A, dummy, 0, 1, A.ovl);
-    RoundBufs b = round_bufs(c, nv, nf);
+    RoundBufs b = round_bufs(c->ws, nv, nf);
     fill_i32(s, c->dcnt, C_COUNT, 0);
     if (ne > 0) {
       hipLaunchKernelGGL(k_check_index, dim3(nblk(ne)), dim3(256), 0, s, edges, ne, (int)(3 * nf), c->dcnt + C_ERR);
@@ -1543,7 +1656,7 @@ pamo_status pamo_features(pamo_ctx* c, const double* V, int64_t nv, const int32_
       A.vdeg = b.vdeg;
       A.vbox = b.vbox;
       launch_quadrics(s, A, b.Q, c->dcnt + C_ERR);
-      launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR, nullptr,
+      launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR,
                      c->opt.cost_target);
       fill_i32(s, c->dcnt + C_NCAND, 1, (int)ne);
       launch_features(s, A, b.key, edges, c->dcnt + C_NCAND, (int)ne, A.ovl, X, c->dcnt + C_ERR);
@@ -1678,6 +1791,7 @@ pamo_status pamo_self_intersections(pamo_ctx* c, const double* V, int64_t nv, co
   return guarded(c, [&]() -> pamo_status {
     if (!V || !F || !npairs || (cap > 0 && !pairs)) fail(PAMO_ERR_ARG, "null pointer");
     if (nv < 1 || nf < 1 || nf > (int64_t)(INT32_MAX / 3) - 1) fail(PAMO_ERR_ARG, "bad sizes");
+    reserve(c, std::max<int64_t>(nv, 4), std::max<int64_t>(nf, 4), Parts{});
     MeshView m;
     m.V = const_cast<double*>(V);
     m.F = const_cast<int*>(F);

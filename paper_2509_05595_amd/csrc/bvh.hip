@@ -27,6 +27,8 @@ constexpr int STACK = 14;  // >= BVH_DMAX: one entry per level above the current
 
 // level of internal node k: (4^l - 1)/3 <= k < (4^(l+1) - 1)/3, i.e. 4^l <= 3k+1
 __device__ __forceinline__ int node_level(int k) { return (31 - __clz(3 * k + 1)) >> 1; }
+// index of the first node of level l
+__device__ __forceinline__ int level_first(int l) { return (int)(((1u << (2 * l)) - 1u) / 3u); }
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
 // grids for xcd_item: a multiple of 8 blocks
@@ -377,20 +379,21 @@ __device__ __forceinline__ bool leaf_take(const QueryArgs& a, int hit, int v, in
 // Morton order, so the G queries of a packet are neighbours; each packet walks
 // the tree once (its lanes load the same node: one coalesced request),
 // entering a child when any of its lanes' own boxes meets it (the packet's
-// union box is a cheap uniform pre-test).  The stack holds one entry per level:
-// a node and the mask of its children still to visit, so it never exceeds the
-// depth.  At a node of the last internal level every lane tests its own box
-// against the four leaves; hits are staged per wave in LDS and flushed with one
-// atomic per ~200 pairs.  The traversal does no data-dependent loads besides
-// the nodes: the state filters run in the pair kernel, except the one the
-// leaf records carry (leaf_take).
+// union box is a cheap uniform pre-test).  The walk needs no stack in memory:
+// in the implicit tree the path to the current node follows from its index,
+// so the only state is, per level, the mask of children still to visit, four
+// bits per level in one 64-bit register (14 levels at most); backtracking
+// goes to the deepest level with a bit left, whose node is the current node's
+// ancestor at that level.  At a node of the last internal level every lane
+// tests its own box against the four leaves; hits are staged per wave in LDS
+// and flushed with one atomic per ~200 pairs.  The traversal does no
+// data-dependent loads besides the nodes: the state filters run in the pair
+// kernel, except the one the leaf records carry (leaf_take).
 template <int MODE, int G>
 __global__ __launch_bounds__(64 * WPB) void k_collect(const BvhNode* __restrict__ nodes, int D, int n,
                                                       const int* __restrict__ qlist, const int* __restrict__ nq,
                                                       QueryArgs a) {
-  constexpr int NG = 64 / G;
   __shared__ int2 sbuf[WPB][SEG];
-  __shared__ int sstack[WPB][NG][STACK];
   const int w = threadIdx.x >> 6;
   const int lane = lane_id();
   const int grp = lane / G;
@@ -412,54 +415,43 @@ __global__ __launch_bounds__(64 * WPB) void k_collect(const BvhNode* __restrict_
     ub[k + 3] = group_max<G>(tb[k + 3]);
   }
   Stage st{sbuf[w], 0, SEG - 64};
-  int* stk = sstack[w][grp];
   // a packet with no active lane has an empty union box: it is done at once
   bool done = !(ub[0] <= ub[3]);
-  int sp = 0;
-  int node = 0;
+  uint64_t pend = 0;  // bits 4l .. 4l+3: children of the path's level-l node still to visit
+  int node = 0, lvl = 0;
   while (__ballot(!done)) {
     int hit = 0;
     int4 lf = make_int4(-1, -1, -1, -1);
     if (!done) {
       const BvhNode nd = nodes[node];
-      int next = -1;
       const int later = later_children<MODE>(node, D, i);
-      if (node_level(node) == D - 1) {  // the children are leaves
+      int pm = 0;
+      if (lvl == D - 1) {  // the children are leaves
         hit = child_hits(nd, tb) & later;
         lf = nd.leaf;
+      } else if (G == 1) {
+        pm = child_hits(nd, tb) & later;
       } else {
-        int pm;
-        if (G == 1) {
-          pm = child_hits(nd, tb) & later;
-        } else {
-          const int um = child_hits(nd, ub);  // uniform over the packet
-          const int own = um ? child_hits(nd, tb) & later : 0;
-          pm = 0;
+        const int um = child_hits(nd, ub);  // uniform over the packet
+        const int own = um ? child_hits(nd, tb) & later : 0;
 #pragma unroll
-          for (int c = 0; c < 4; c++) pm |= ((__ballot((own >> c) & 1) & gmask) != 0) << c;
-        }
-        if (pm) {
-          next = 4 * node + 1 + __builtin_ctz(pm);
-          pm &= pm - 1;
-          if (pm) stk[sp++] = (node << 4) | pm;  // one entry per level: sp < D <= STACK
-        }
+        for (int c = 0; c < 4; c++) pm |= ((__ballot((own >> c) & 1) & gmask) != 0) << c;
       }
-      if (next < 0) {
-        if (sp == 0) {
-          done = true;
-        } else {  // next child of the deepest node with children left
-          const int e = stk[sp - 1];
-          const int k = e >> 4;
-          int msk = e & 15;
-          next = 4 * k + 1 + __builtin_ctz(msk);
-          msk &= msk - 1;
-          if (msk)
-            stk[sp - 1] = (k << 4) | msk;
-          else
-            sp--;
-        }
+      if (pm) {  // descend into the first child met, remember the others
+        const int c = __builtin_ctz(pm);
+        pend |= (uint64_t)(pm & (pm - 1)) << (4 * lvl);
+        node = 4 * node + 1 + c;
+        lvl++;
+      } else if (pend == 0) {
+        done = true;
+      } else {  // next child of the deepest path node with children left
+        const int L = (63 - __clzll(pend)) >> 2;
+        const int c = __builtin_ctz((int)(pend >> (4 * L)) & 15);
+        pend &= ~(1ull << (4 * L + c));
+        const int anc = level_first(L) + ((node - level_first(lvl)) >> (2 * (lvl - L)));
+        node = 4 * anc + 1 + c;
+        lvl = L + 1;
       }
-      node = next;
     }
     {
       int u0, u1, u2, u3;
@@ -614,6 +606,18 @@ __global__ __launch_bounds__(64) void k_resolve(QueryArgs a) {
 }
 
 }  // namespace
+
+void bvh_reserve(Workspace& ws, int64_t nf, bool mesh_codes) {
+  int D = 1;
+  while (((int64_t)1 << (2 * D)) < nf) D++;
+  ws.get<BvhNode>("bvh.nodes", ((((int64_t)1) << (2 * D)) - 1) / 3);
+  ws.get<uint32_t>("bvh.code", nf);
+  if (mesh_codes) ws.get<uint64_t>("bvh.code64", nf);
+  ws.get<int>("bvh.id", nf);
+  const int64_t top_cap = (nf + (1 << (2 * LVL)) - 1) >> (2 * LVL);
+  ws.get<Box>("bvh.topA", top_cap + 1);
+  ws.get<Box>("bvh.topB", top_cap + 1);
+}
 
 Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf, const int* order, const int* fmesh,
               int nmesh, const int* owner, const uint8_t* falive) {

@@ -633,6 +633,11 @@ void launch_mark_retry(hipStream_t s, const int* cand, const int* ncand, int bou
   PAMO_HIP(hipGetLastError());
 }
 
+void learn_reserve(Workspace& ws, int64_t bound) {
+  ws.get<uint8_t>("log.flag", bound);
+  ws.get<int>("log.idx", bound);
+}
+
 void launch_log_rows(Workspace& ws, hipStream_t s, const int* ncand, int bound, const uint8_t* reason, const float* Xs,
                      float* X, uint8_t* y, int64_t room, int* nrows) {
   uint8_t* flag = ws.get<uint8_t>("log.flag", bound);

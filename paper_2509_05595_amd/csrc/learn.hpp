@@ -55,6 +55,8 @@ int train_blocks(int nb);
 // append the rows of the candidates the checks decided (reason <= 3), in
 // candidate order: features from Xs, label 1 when committed; at most room
 // rows; *nrows = rows available this round
+// reserve the row logger's buffers for up to `bound` candidates per round
+void learn_reserve(Workspace& ws, int64_t bound);
 void launch_log_rows(Workspace& ws, hipStream_t s, const int* ncand, int bound, const uint8_t* reason, const float* Xs,
                      float* X, uint8_t* y, int64_t room, int* nrows);
 // distance of each point of P to the closest triangle of (V, F); the largest

@@ -1,5 +1,7 @@
 // Device-wide primitives: prefix sums, stream compaction and a stable LSD
 // radix sort, written for 64-lane wavefronts (ballot / popcount ranking).
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace pamo {
@@ -521,6 +523,25 @@ void scan_exclusive(Workspace& ws, hipStream_t s, const int32_t* in, int32_t* ou
   // the tile pass reads all of a tile before writing it, so in == out is fine
   run_scan(ws, s, IntLoad{in}, ScanStore{out}, n, total);
 }
+void prim_reserve(Workspace& ws, int64_t scan_n, int64_t sort32_n, int64_t sort64_n, int64_t seg_n) {
+  auto hist_items = [](int64_t n) { return (int64_t)256 * ((n + RS_TILE - 1) / RS_TILE); };
+  int64_t scan = scan_n;
+  if (sort32_n > 1) {
+    ws.get<uint32_t>("rs32.k2", sort32_n);
+    ws.get<int32_t>("rs32.v2", sort32_n);
+    ws.get<int32_t>("rs32.hist", hist_items(sort32_n));
+    scan = std::max(scan, hist_items(sort32_n));
+  }
+  if (sort64_n > 1) {
+    ws.get<uint64_t>("rs64.k2", sort64_n);
+    ws.get<int32_t>("rs64.v2", sort64_n);
+    ws.get<int32_t>("rs64.hist", hist_items(sort64_n));
+    scan = std::max(scan, hist_items(sort64_n));
+  }
+  ws.get<int32_t>("prim.tiles", (scan + TILE - 1) / TILE);
+  ws.get<int32_t>("prim.segtiles", (seg_n + TILE - 1) / TILE + 3);
+}
+
 void radix_sort_u32(Workspace& ws, hipStream_t s, uint32_t* keys, int32_t* vals, int64_t n, int bits) {
   radix_sort_impl<uint32_t>(ws, s, keys, vals, n, bits, "rs32");
 }

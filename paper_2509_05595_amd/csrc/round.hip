@@ -5,8 +5,10 @@
 // kernels need no atomics except the idempotent marks of the check/undo loop:
 //   quadrics      vertex:    Q_v = sum of plane quadrics of its faces, ascending face slot
 //   cost_keys     edge:      placement + Eq. 1 cost + 64-bit key (both half-edges)
-//   vertex_min    vertex:    m_v = min key of its edges (pull form of the paper's AtomicMin)
-//   select        edge:      key_e = min of m_w over the closed neighbourhood of e
+//   vertex_min    vertex:    m_v = min key of its edges, gathered over the stored star
+//                            (the pull form of the paper's AtomicMin propagation)
+//   select        vertex:    the edge m_v names is chosen iff its key is the minimum
+//                            of m_w over the closed neighbourhood of the edge
 //   local_check   candidate: link condition, exact degeneracy, normal flip
 //   apply/undo    candidate: tentative collapse and its exact reversal
 //   commit        candidate: twin rewiring of the two removed faces
@@ -129,11 +131,9 @@ __global__ void k_check_vertices(const int* __restrict__ twin, const int* __rest
 // One thread per vertex: walk the star once (sorted half-edge list in
 // registers), then sum the face quadrics in ascending face slot, four faces
 // at a time with their loads issued together.
-__global__ __launch_bounds__(256) void k_quadrics(MeshView m, double* __restrict__ Q, int* err,
-                                                  uint64_t* __restrict__ vmin) {
+__global__ __launch_bounds__(256) void k_quadrics(MeshView m, double* __restrict__ Q, int* err) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= m.nv) return;
-  if (vmin) vmin[v] = PAMO_KEY_MAX;  // lowered by the cost kernel
   constexpr int CAP = VSTAR;
   int hl[CAP];
 #pragma unroll
@@ -600,12 +600,13 @@ constexpr int64_t CK_SMALL_NH = 1 << 21;
 
 // PRE: the link/flip pre-filter, an edge failing the local checks of R7 gets
 // the largest key (from the placement just computed).  lex: the key is the
-// float64 cost's order code (ranked afterwards; vmin is then null)
+// float64 cost's order code (ranked afterwards).  Keys go to both half-edges;
+// the vertex minima are gathered from them by the next kernel (no atomics).
 template <int PW, bool PRE>
 __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
                                                    double cost_max, const uint8_t* __restrict__ demote,
                                                    const uint8_t* __restrict__ mesh_done, uint64_t* __restrict__ key,
-                                                   int* err, uint64_t* __restrict__ vmin, bool lex) {
+                                                   int* err, bool lex) {
   __shared__ int queue[4][PW];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t nh = 3 * (int64_t)m.nf;
@@ -637,10 +638,6 @@ __global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __r
             : lex        ? cost_code64(cost)
                          : make_key(cost, (uint32_t)h);
         if (PRE && k != PAMO_KEY_MAX && (!link_holds(m, h) || flipped_after(m, E, vbar))) k = PAMO_KEY_MAX;
-        if (vmin && k != PAMO_KEY_MAX) {  // the vertex minima of the selection, in place of a gather pass
-          atomicMin(reinterpret_cast<unsigned long long*>(vmin + E.s), (unsigned long long)k);
-          atomicMin(reinterpret_cast<unsigned long long*>(vmin + E.r), (unsigned long long)k);
-        }
       }
     }
     key[h] = k;
@@ -1371,6 +1368,38 @@ inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t
 }  // namespace
 
 // ============================================================ host wrappers
+void round_reserve(Workspace& ws, int64_t nv, int64_t nf, int64_t ncand, int nmesh, bool key_mode) {
+  const int64_t nh = 3 * nf;
+  ws.get<uint64_t>("adj.keys", nh);
+  ws.get<int>("adj.vals", nh);
+  ws.get<int>("adj.deg", nv);
+  ws.get<uint8_t>("sel", nh);
+  ws.get<uint64_t>("cap.keys", ncand);
+  ws.get<int>("cap.idx", ncand);
+  ws.get<uint64_t>("cap.thr", 1);
+  ws.get<uint8_t>("qpred", nf);
+  ws.get<int>("cmp.fmap", nf);
+  ws.get<int>("cmp.vmap", nv);
+  ws.get<int>("cmp.fexcl", nf);
+  ws.get<int>("cmp.vexcl", nv);
+  ws.get<int>("ord.tmp", nf);
+  ws.get<uint8_t>("ord.pred", nf);
+  if (nmesh > 1) {
+    ws.get<uint64_t>("capb.keys", ncand);
+    ws.get<int>("capb.idx", ncand);
+    ws.get<int>("capb.seg", nmesh + 1);
+    ws.get<int>("bo.excl", std::max(nf, nv));
+    ws.get<int>("bo.total", 1);
+  }
+  if (key_mode) {
+    const int64_t ne = nh / 2;
+    ws.get<uint8_t>("rk.flag", nh);
+    ws.get<int>("rk.edges", ne + 1);
+    ws.get<int>("rk.count", 1);
+    ws.get<uint64_t>("rk.codes", ne + 1);
+  }
+}
+
 void launch_adjacency(Workspace& ws, hipStream_t s, MeshView m, int* err) {
   int64_t nh = 3 * (int64_t)m.nf;
   uint64_t* keys = ws.get<uint64_t>("adj.keys", nh);
@@ -1395,20 +1424,19 @@ void launch_check_vertices(Workspace& ws, hipStream_t s, MeshView m, int* err) {
   PAMO_HIP(hipGetLastError());
 }
 
-void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err, uint64_t* vmin) {
-  hipLaunchKernelGGL(k_quadrics, dim3(nblk(m.nv)), dim3(256), 0, s, m, Q, err, vmin);
+void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err) {
+  hipLaunchKernelGGL(k_quadrics, dim3(nblk(m.nv)), dim3(256), 0, s, m, Q, err);
   PAMO_HIP(hipGetLastError());
 }
 
 void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
-                      const uint8_t* mesh_done, uint64_t* key, int* err, uint64_t* vmin, double cost_target,
-                      bool prefilter, bool lex) {
+                      const uint8_t* mesh_done, uint64_t* key, int* err, double cost_target, bool prefilter,
+                      bool lex) {
   const int64_t nh = 3 * (int64_t)m.nf;
   const double cost_max = cost_target > 0 ? cost_target : INFINITY;
-  if (lex) vmin = nullptr;  // gathered after the ranks
   auto go = [&](auto kern, int pw) {
     hipLaunchKernelGGL(kern, dim3(nblk(nh, 4 * pw)), dim3(256), 0, s, m, Q, w_e, w_s, cost_max, demote, mesh_done,
-                       key, err, vmin, lex);
+                       key, err, lex);
   };
   if (nh <= CK_SMALL_NH)
     prefilter ? go(k_cost_keys<64, true>, 64) : go(k_cost_keys<64, false>, 64);
@@ -1435,10 +1463,10 @@ void launch_rank_keys(Workspace& ws, hipStream_t s, MeshView m, uint64_t* key) {
 }
 
 void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, int* cand,
-                   int* ncand, bool vmin_ready) {
+                   int* ncand) {
   int64_t nh = 3 * (int64_t)m.nf;
   uint8_t* sel = ws.get<uint8_t>("sel", nh);
-  if (!vmin_ready) hipLaunchKernelGGL(k_vertex_min, dim3(nblk(m.nv)), dim3(256), 0, s, m, key, vmin);
+  hipLaunchKernelGGL(k_vertex_min, dim3(nblk(m.nv)), dim3(256), 0, s, m, key, vmin);
   fill_u8(s, sel, nh, 0);
   hipLaunchKernelGGL(k_select, dim3(nblk(m.nv)), dim3(256), 0, s, m, key, (const uint64_t*)vmin, sel);
   compact_flags(ws, s, sel, nh, cand, ncand);

@@ -45,27 +45,27 @@ __host__ __device__ __forceinline__ void mesh_shift(int m, double& ox, double& o
 }
 constexpr int PAMO_MAX_MESHES = 4096;
 
+// reserve the round kernels' own buffers for a mesh (or batch of nmesh
+// meshes, nmesh > 1) of nv vertices and nf faces, with at most ncand
+// candidates per round; key_mode: the float64 key mode's ranking buffers
+void round_reserve(Workspace& ws, int64_t nv, int64_t nf, int64_t ncand, int nmesh, bool key_mode);
 void launch_adjacency(Workspace& ws, hipStream_t s, MeshView m, int* err);
 void launch_check_vertices(Workspace& ws, hipStream_t s, MeshView m, int* err);
-// vmin (optional): set to the largest key for every vertex, to be lowered by the cost kernel
-void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err, uint64_t* vmin = nullptr);
+void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err);
 // mesh_done (batches, may be null): edges of finished meshes get no key
-// vmin (optional): every finite key is also folded into vmin of both endpoints
-// (atomic minimum; vmin set to the largest key beforehand)
 // cost_target > 0: edges costing more get the largest key (never chosen);
 // prefilter: so do edges failing the local checks of R7 (link condition,
 // degenerate or flipped generated triangles; m needs this round's stars)
 void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
-                      const uint8_t* mesh_done, uint64_t* key, int* err, uint64_t* vmin = nullptr,
-                      double cost_target = 0.0, bool prefilter = false, bool lex = false);
+                      const uint8_t* mesh_done, uint64_t* key, int* err, double cost_target = 0.0,
+                      bool prefilter = false, bool lex = false);
 // float64 key mode, after launch_cost_keys(lex): each keyed edge's key becomes
-// (rank in the order of (float64 cost, edge id)) << 32 | edge id; the vertex
-// minima must be gathered afterwards (launch_select without vmin_ready)
+// (rank in the order of (float64 cost, edge id)) << 32 | edge id
 void launch_rank_keys(Workspace& ws, hipStream_t s, MeshView m, uint64_t* key);
-// vmin_ready: vmin already holds the vertex minima of key (the cost kernel
-// folded them in), so only the selection and its compaction run
+// the vertex minima of key gathered into vmin (one thread per vertex over its
+// stored star, no atomics), then the selection and its compaction
 void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, int* cand,
-                   int* ncand, bool vmin_ready = false);
+                   int* ncand);
 // the selection again after the candidates dlist[0..*nd) (*nd <= bound) got
 // the largest key on both half-edges: into cand / ncand the same candidates as
 // a full launch_select, from the flags and vertex minima of the selection
@@ -194,6 +194,10 @@ inline int64_t bvh_nodes_written(int64_t nf) {
 // owner, falive (may be null): leaves of faces with owner[f] >= 0 carry
 // LEAF_CHANGED, those with falive[f] == 0 LEAF_DEAD in their record (face id =
 // record & LEAF_ID); the flags hold for the first check pass of the round
+// reserve the BVH builder's buffers for up to nf leaves (mesh_codes: the
+// batch form's 64-bit (mesh, Morton) codes too); its sort is reserved by
+// prim_reserve
+void bvh_reserve(Workspace& ws, int64_t nf, bool mesh_codes);
 Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf, const int* order, const int* fmesh = nullptr,
               int nmesh = 1, const int* owner = nullptr, const uint8_t* falive = nullptr);
 // new leaf order after a stable compaction: keep the alive faces of `order`

@@ -20,7 +20,7 @@ PAMO_TARGET_UNREACHED = 1
 ERRORS = {-1: "ARG", -2: "NONMANIFOLD", -3: "SELF_INTERSECTING", -4: "DEGENERATE", -6: "HIP", -7: "CAPACITY"}
 
 EXPORTS = ["pamo_default_options", "pamo_create", "pamo_destroy", "pamo_set_options", "pamo_last_error",
-           "pamo_workspace_bytes", "pamo_quadrics", "pamo_select", "pamo_check", "pamo_collapse",
+           "pamo_workspace_bytes", "pamo_set_workspace", "pamo_workspace_held", "pamo_quadrics", "pamo_select", "pamo_check", "pamo_collapse",
            "pamo_simplify", "pamo_simplify_batch", "pamo_set_mlp", "pamo_features", "pamo_mlp_logits",
            "pamo_collect", "pamo_mlp_grad", "pamo_mlp_train", "pamo_hausdorff", "pamo_self_intersections", "pamo_tri_pairs",
            "pamo_udf", "pamo_dualmc", "pamo_profile_enable",
@@ -32,7 +32,7 @@ class Options(C.Structure):
                 ("max_rounds", C.c_int32), ("validate_input", C.c_int32), ("query_packet", C.c_int32),
                 ("resort_every", C.c_int32), ("query_coop", C.c_int32), ("coop_below", C.c_int32),
                 ("learned", C.c_int32), ("cost_target", C.c_double), ("prefilter", C.c_int32),
-                ("key_mode", C.c_int32)]
+                ("key_mode", C.c_int32), ("pair_capacity", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -98,8 +98,11 @@ def lib():
         L.pamo_set_options.argtypes = [P, C.POINTER(Options)]
         L.pamo_last_error.argtypes = [P]
         L.pamo_last_error.restype = C.c_char_p
-        L.pamo_workspace_bytes.argtypes = [P]
-        L.pamo_workspace_bytes.restype = I64
+        L.pamo_workspace_bytes.argtypes = [I64, I64, C.POINTER(Options)]
+        L.pamo_workspace_bytes.restype = C.c_size_t
+        L.pamo_set_workspace.argtypes = [P, P, C.c_size_t]
+        L.pamo_workspace_held.argtypes = [P]
+        L.pamo_workspace_held.restype = I64
         L.pamo_quadrics.argtypes = [P, P, I64, P, I64, P]
         L.pamo_select.argtypes = [P, P, I64, P, I64, P, P, P, P, P]
         L.pamo_check.argtypes = [P, P, I64, P, I64, P, I64, P, P, P, P, C.POINTER(I64)]
@@ -127,7 +130,7 @@ def lib():
         L.pamo_profile_reset.argtypes = [P]
         for n in EXPORTS:
             if n not in ("pamo_default_options", "pamo_destroy", "pamo_last_error", "pamo_workspace_bytes",
-                         "pamo_profile_name"):
+                         "pamo_workspace_held", "pamo_profile_name"):
                 getattr(L, n).restype = I32
         _lib = L
     return _lib
@@ -145,24 +148,80 @@ def default_options(**kw) -> Options:
     return o
 
 
-class Context:
-    """A library context bound to one device and the current torch stream."""
+def workspace_bytes(nv: int, nf: int, options: Options | None = None) -> int:
+    """Device workspace that suffices for every mesh entry point on a mesh (or
+    batch) of nv vertices and nf faces (pamo_workspace_bytes)."""
+    opt = options if options is not None else default_options()
+    return int(lib().pamo_workspace_bytes(int(nv), int(nf), C.byref(opt)))
 
-    def __init__(self, device=None, options: Options | None = None, stream=None):
+
+class Context:
+    """A library context bound to one device and the current torch stream.
+
+    workspace="torch" (default): the library's device scratch is a torch uint8
+    tensor the context allocates (pamo_set_workspace), sized by
+    pamo_workspace_bytes before each mesh call and grown when a larger mesh
+    comes; "library": the library allocates its own scratch."""
+
+    def __init__(self, device=None, options: Options | None = None, stream=None, workspace: str = "torch"):
+        if workspace not in ("torch", "library"):
+            raise ValueError("workspace must be 'torch' or 'library'")
         dev = torch.device(device if device is not None else "cuda")
         self.device = torch.device("cuda", dev.index if dev.index is not None else torch.cuda.current_device())
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = s
         self._h = C.c_void_p()
+        self._ws_mode = workspace
+        self._ws = None
         opt = options if options is not None else default_options()
+        self.options = Options.from_buffer_copy(opt)
         rc = lib().pamo_create(C.byref(self._h), self.device.index, C.c_void_p(s.cuda_stream), C.byref(opt))
         if rc != 0:
             raise PamoError(rc, "pamo_create failed")
 
+    # ---- workspace
+    def _set_workspace(self, nbytes):
+        t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self._check(lib().pamo_set_workspace(self._h, _ptr(t), int(nbytes)))  # synchronises the stream
+        self._ws = t
+
+    def _ensure_workspace(self, nv, nf):
+        """Before a mesh entry point: a torch workspace of at least the bytes
+        pamo_workspace_bytes asks for this size."""
+        if self._ws_mode != "torch":
+            return
+        need = int(lib().pamo_workspace_bytes(int(nv), int(nf), C.byref(self.options)))
+        if need and (self._ws is None or self._ws.numel() < need):
+            self._set_workspace(need)
+
+    def _call_growing(self, fn, allow=(PAMO_OK,)):
+        """Entry points that carve their workspace as they go (remeshing,
+        training, utilities): a call that finds the torch workspace too small
+        runs again with a larger one."""
+        if self._ws_mode == "torch" and self._ws is None:
+            self._set_workspace(64 << 20)
+        for _ in range(12):
+            rc = fn()
+            if (rc == PAMO_ERR_CAPACITY and self._ws_mode == "torch"
+                    and lib().pamo_last_error(self._h).decode().startswith("workspace of")):
+                self._set_workspace(2 * self._ws.numel())
+                continue
+            break
+        return self._check(rc, allow)
+
+    def workspace_held(self) -> int:
+        """Device bytes the library itself holds for this context (0 while it
+        works in the torch workspace)."""
+        return int(lib().pamo_workspace_held(self._h))
+
+    def workspace_tensor(self):
+        return self._ws
+
     def close(self):
         if self._h:
-            lib().pamo_destroy(self._h)
+            lib().pamo_destroy(self._h)  # synchronises the stream first
             self._h = C.c_void_p()
+        self._ws = None
 
     def __del__(self):
         try:
@@ -177,9 +236,7 @@ class Context:
 
     def set_options(self, options: Options):
         self._check(lib().pamo_set_options(self._h, C.byref(options)))
-
-    def workspace_bytes(self) -> int:
-        return int(lib().pamo_workspace_bytes(self._h))
+        self.options = Options.from_buffer_copy(options)
 
     def _mesh(self, V, F):
         assert V.is_cuda and F.is_cuda and V.device == self.device and F.device == self.device
@@ -189,6 +246,7 @@ class Context:
 
     def quadrics(self, V, F):
         V, F = self._mesh(V, F)
+        self._ensure_workspace(V.shape[0], F.shape[0])
         Q = torch.empty((V.shape[0], 10), dtype=torch.float64, device=self.device)
         self._check(lib().pamo_quadrics(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(Q)))
         return Q
@@ -196,6 +254,7 @@ class Context:
     def select(self, V, F, flags=None, demote=None):
         """Returns (cand int32 [ncand], keys uint64-as-int64 [3 nf])."""
         V, F = self._mesh(V, F)
+        self._ensure_workspace(V.shape[0], F.shape[0])
         nh = 3 * F.shape[0]
         keys = torch.empty(nh, dtype=torch.int64, device=self.device)
         cand = torch.empty(nh, dtype=torch.int32, device=self.device)
@@ -208,11 +267,12 @@ class Context:
     def check(self, V, F, target, cand, ncand_dev, flags=None):
         """Returns (vbar [n,3], reason uint8 [n], undo iterations)."""
         V, F = self._mesh(V, F)
+        self._ensure_workspace(V.shape[0], F.shape[0])
         n = max(1, cand.shape[0])
         vbar = torch.zeros((n, 3), dtype=torch.float64, device=self.device)
         reason = torch.zeros(n, dtype=torch.uint8, device=self.device)
         it = C.c_int64(0)
-        self._check(lib().pamo_check(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(flags), int(target),
+        self._call_growing(lambda: lib().pamo_check(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(flags), int(target),
                                      _ptr(cand), _ptr(ncand_dev), _ptr(vbar), _ptr(reason), C.byref(it)))
         k = cand.shape[0]
         return vbar[:k], reason[:k], it.value
@@ -220,6 +280,7 @@ class Context:
     def collapse(self, V, F, cand, ncand_dev, vbar, reason, flags=None):
         """Commit reason-0 collapses; returns (V, F, flags) (new tensors)."""
         V, F = self._mesh(V, F)
+        self._ensure_workspace(V.shape[0], F.shape[0])
         V = V.clone()
         F = F.clone()
         fl = flags.clone() if flags is not None else torch.zeros(3 * F.shape[0], dtype=torch.uint8,
@@ -233,10 +294,11 @@ class Context:
     def simplify(self, V, F, target):
         """Returns (V_out, F_out, stats dict)."""
         V, F = self._mesh(V, F)
+        self._ensure_workspace(V.shape[0], F.shape[0])
         Vo = torch.empty_like(V)
         Fo = torch.empty_like(F)
         nv, nf, st = C.c_int64(0), C.c_int64(0), Stats()
-        self._check(lib().pamo_simplify(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], int(target), _ptr(Vo),
+        self._call_growing(lambda: lib().pamo_simplify(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], int(target), _ptr(Vo),
                                         C.byref(nv), _ptr(Fo), C.byref(nf), C.byref(st)),
                     allow=(PAMO_OK, PAMO_TARGET_UNREACHED))
         return Vo[: nv.value], Fo[: nf.value], st.as_dict()
@@ -251,6 +313,7 @@ class Context:
             self._mesh(V, F)
         V = torch.cat([m[0] for m in meshes]).contiguous()
         F = torch.cat([m[1] for m in meshes]).contiguous()
+        self._ensure_workspace(V.shape[0], F.shape[0])
         v_off = np.zeros(n + 1, dtype=np.int64)
         f_off = np.zeros(n + 1, dtype=np.int64)
         v_off[1:] = np.cumsum([m[0].shape[0] for m in meshes])
@@ -263,7 +326,7 @@ class Context:
         fo = np.zeros(n + 1, dtype=np.int64)
         st = (Stats * max(n, 1))()
         h = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
-        self._check(lib().pamo_simplify_batch(self._h, n, _ptr(V), h(v_off), _ptr(F), h(f_off), h(tg), _ptr(Vo),
+        self._call_growing(lambda: lib().pamo_simplify_batch(self._h, n, _ptr(V), h(v_off), _ptr(F), h(f_off), h(tg), _ptr(Vo),
                                               h(vo), _ptr(Fo), h(fo), st),
                     allow=(PAMO_OK, PAMO_TARGET_UNREACHED))
         return [(Vo[vo[m]:vo[m + 1]], Fo[fo[m]:fo[m + 1]], st[m].as_dict()) for m in range(n)]
@@ -280,26 +343,28 @@ class Context:
     def features(self, V, F, edges):
         """(features float32 [n, 32], overlap counts int32 [nf]) of the given half-edges."""
         V, F = self._mesh(V, F)
+        self._ensure_workspace(V.shape[0], F.shape[0])
         e = edges.to(self.device, torch.int32).contiguous()
         X = torch.zeros((max(1, e.shape[0]), NFEAT), dtype=torch.float32, device=self.device)
         ovl = torch.zeros(F.shape[0], dtype=torch.int32, device=self.device)
-        self._check(lib().pamo_features(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(e), e.shape[0],
+        self._call_growing(lambda: lib().pamo_features(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(e), e.shape[0],
                                         _ptr(X), _ptr(ovl)))
         return X[: e.shape[0]], ovl
 
     def mlp_logits(self, X):
         X = X.to(self.device, torch.float32).contiguous()
         out = torch.empty(max(1, X.shape[0]), dtype=torch.float32, device=self.device)
-        self._check(lib().pamo_mlp_logits(self._h, _ptr(X), X.shape[0], _ptr(out)))
+        self._call_growing(lambda: lib().pamo_mlp_logits(self._h, _ptr(X), X.shape[0], _ptr(out)))
         return out[: X.shape[0]]
 
     def collect(self, V, F, target, cap):
         """Plain run logging training rows: (X [n, 32], y [n], stats)."""
         V, F = self._mesh(V, F)
+        self._ensure_workspace(V.shape[0], F.shape[0])
         X = torch.empty((max(1, cap), NFEAT), dtype=torch.float32, device=self.device)
         y = torch.empty(max(1, cap), dtype=torch.uint8, device=self.device)
         n, st = C.c_int64(0), Stats()
-        self._check(lib().pamo_collect(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], int(target), _ptr(X),
+        self._call_growing(lambda: lib().pamo_collect(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], int(target), _ptr(X),
                                        _ptr(y), int(cap), C.byref(n), C.byref(st)),
                     allow=(PAMO_OK, PAMO_TARGET_UNREACHED))
         return X[: n.value], y[: n.value], st.as_dict()
@@ -309,8 +374,8 @@ class Context:
         md = np.ascontiguousarray(meta, dtype=np.int32)
         g = torch.empty(NPARAM, dtype=torch.float32, device=self.device)
         loss = C.c_float(0)
-        self._check(lib().pamo_mlp_grad(self._h, _ptr(params), md.ctypes.data_as(C.c_void_p), _ptr(X), _ptr(y),
-                                        X.shape[0], _ptr(g), C.byref(loss)))
+        self._call_growing(lambda: lib().pamo_mlp_grad(self._h, _ptr(params), md.ctypes.data_as(C.c_void_p), _ptr(X),
+                                                       _ptr(y), X.shape[0], _ptr(g), C.byref(loss)))
         return g, loss.value
 
     def mlp_train(self, params, m, v, meta, X, y, order, steps, batch, lr, t0):
@@ -318,9 +383,10 @@ class Context:
         import numpy as np
         md = np.ascontiguousarray(meta, dtype=np.int32)
         loss = torch.empty(max(1, steps), dtype=torch.float32, device=self.device)
-        self._check(lib().pamo_mlp_train(self._h, _ptr(params), _ptr(m), _ptr(v), md.ctypes.data_as(C.c_void_p),
-                                         _ptr(X), _ptr(y), int(X.shape[0]), _ptr(order), int(steps), int(batch),
-                                         float(lr), int(t0), _ptr(loss)))
+        self._call_growing(lambda: lib().pamo_mlp_train(self._h, _ptr(params), _ptr(m), _ptr(v),
+                                                        md.ctypes.data_as(C.c_void_p), _ptr(X), _ptr(y),
+                                                        int(X.shape[0]), _ptr(order), int(steps), int(batch),
+                                                        float(lr), int(t0), _ptr(loss)))
         return loss[:steps]
 
     def hausdorff(self, P, V, F, per_point=False):
@@ -329,15 +395,16 @@ class Context:
         P = P.contiguous()
         d = torch.empty(max(1, P.shape[0]), dtype=torch.float64, device=self.device) if per_point else None
         dm = C.c_double(0)
-        self._check(lib().pamo_hausdorff(self._h, _ptr(P), P.shape[0], _ptr(V), V.shape[0], _ptr(F), F.shape[0],
-                                         _ptr(d), C.byref(dm)))
+        self._call_growing(lambda: lib().pamo_hausdorff(self._h, _ptr(P), P.shape[0], _ptr(V), V.shape[0], _ptr(F),
+                                                        F.shape[0], _ptr(d), C.byref(dm)))
         return (dm.value, d[: P.shape[0]]) if per_point else dm.value
 
     def self_intersections(self, V, F, cap=1 << 16):
         V, F = self._mesh(V, F)
+        self._ensure_workspace(V.shape[0], F.shape[0])
         pairs = torch.empty((cap, 2), dtype=torch.int32, device=self.device)
         n = C.c_int64(0)
-        self._check(lib().pamo_self_intersections(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(pairs),
+        self._call_growing(lambda: lib().pamo_self_intersections(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(pairs),
                                                   cap, C.byref(n)))
         return pairs[: min(cap, n.value)], n.value
 
@@ -347,7 +414,8 @@ class Context:
         V, F = self._mesh(V, F)
         band = 3.0 / res if band is None else float(band)
         out = torch.empty((res, res, res), dtype=torch.float64, device=self.device)
-        self._check(lib().pamo_udf(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], int(res), band, _ptr(out)))
+        self._call_growing(lambda: lib().pamo_udf(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], int(res), band,
+                                                  _ptr(out)))
         return out
 
     def dualmc(self, S, iso=0.0, vcap=None, fcap=None, beta=0.0):
@@ -358,14 +426,15 @@ class Context:
         res = S.shape[0]
         nv, nf = C.c_int64(0), C.c_int64(0)
         if vcap is None or fcap is None:  # sizes first: a call with no room writes only them
-            self._check(lib().pamo_dualmc(self._h, _ptr(S), int(res), float(iso), float(beta), None, 0, None, 0,
-                                          C.byref(nv), C.byref(nf)), allow=(PAMO_OK, PAMO_ERR_CAPACITY))
+            self._call_growing(lambda: lib().pamo_dualmc(self._h, _ptr(S), int(res), float(iso), float(beta), None, 0,
+                                                         None, 0, C.byref(nv), C.byref(nf)),
+                               allow=(PAMO_OK, PAMO_ERR_CAPACITY))
             vcap = nv.value if vcap is None else int(vcap)
             fcap = nf.value if fcap is None else int(fcap)
         V = torch.empty((max(vcap, 1), 3), dtype=torch.float64, device=self.device)
         F = torch.empty((max(fcap, 1), 3), dtype=torch.int32, device=self.device)
-        self._check(lib().pamo_dualmc(self._h, _ptr(S), int(res), float(iso), float(beta), _ptr(V), vcap, _ptr(F), fcap,
-                                      C.byref(nv), C.byref(nf)))
+        self._call_growing(lambda: lib().pamo_dualmc(self._h, _ptr(S), int(res), float(iso), float(beta), _ptr(V), vcap,
+                                                     _ptr(F), fcap, C.byref(nv), C.byref(nf)))
         return V[:nv.value], F[:nf.value]
 
     # ---- measurement
@@ -399,5 +468,5 @@ class Context:
     def tri_pairs(self, P, ip, Q, iq):
         n = P.shape[0]
         out = torch.empty(n, dtype=torch.uint8, device=self.device)
-        self._check(lib().pamo_tri_pairs(self._h, _ptr(P), _ptr(ip), _ptr(Q), _ptr(iq), n, _ptr(out)))
+        self._call_growing(lambda: lib().pamo_tri_pairs(self._h, _ptr(P), _ptr(ip), _ptr(Q), _ptr(iq), n, _ptr(out)))
         return out

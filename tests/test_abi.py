@@ -37,6 +37,20 @@ def test_binding_covers_the_header():
     sys.path.insert(0, ROOT)
     from paper_2509_05595_amd import native
     assert set(declared()) <= set(native.EXPORTS)
-    assert ctypes.sizeof(native.Options) == 8 + 8 + 4 * 8 + 8 + 4 + 4  # ..., prefilter, key_mode
+    assert ctypes.sizeof(native.Options) == 8 + 8 + 4 * 8 + 8 + 4 + 4 + 4 + 4  # ..., key_mode, pair_capacity, pad
     assert ctypes.sizeof(native.Stats) == 8 * 18
     assert ctypes.sizeof(native.MLP) == 4 * (2048 + 64 + 4096 + 64 + 64 + 1 + 5 + 1)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpamo.so not built")
+def test_workspace_size_query():
+    """pamo_workspace_bytes is host-only: refused sizes give 0, and the bytes
+    grow with the mesh (about a kilobyte per face)."""
+    lib = ctypes.CDLL(LIB)
+    f = lib.pamo_workspace_bytes
+    f.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
+    f.restype = ctypes.c_size_t
+    assert f(3, 100, None) == 0 and f(100, 3, None) == 0 and f(4, 2 ** 31, None) == 0
+    a, b = f(2562, 5120, None), f(655362, 1310720, None)
+    assert 0 < a < b < 2000 * 1310720
+    assert a % 256 == 0 and b % 256 == 0
