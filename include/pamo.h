@@ -201,6 +201,28 @@ pamo_status pamo_simplify(pamo_ctx* ctx, const double* V, int64_t nv, const int3
                           int64_t target_faces, double* V_out, int64_t* nv_out, int32_t* F_out, int64_t* nf_out,
                           pamo_stats* stats);
 
+/* pamo_simplify for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same method, arguments and results as pamo_simplify, but every buffer
+ * of the call lives in one static device array of PAMO_NOALLOC_SCRATCH_BYTES
+ * that each GPU the library runs on holds from the library's load until the
+ * process ends; the call allocates no device memory and no pinned host memory
+ * (no hipMalloc, hipFree or hipHostMalloc) and creates no HIP events (only
+ * the host bookkeeping of its buffer table uses the C++ heap); the context
+ * must have been created (pamo_create finds the array's device address).  A
+ * mesh whose buffers do not fit fails
+ * with PAMO_ERR_CAPACITY before any work (at the default options a closed
+ * mesh needs about 870 bytes per face, so meshes up to about 150,000 faces
+ * fit; pamo_workspace_bytes gives the size of a larger workspace for
+ * pamo_simplify).  Every call on a GPU shares that
+ * GPU's array and leaves its contents behind: calls that overlap on one GPU,
+ * from any context or thread, race and must not be made.  Synchronises the
+ * stream. */
+#define PAMO_NOALLOC_SCRATCH_BYTES (128u << 20)
+pamo_status pamo_simplify_noalloc(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                                  int64_t target_faces, double* V_out, int64_t* nv_out, int32_t* F_out,
+                                  int64_t* nf_out, pamo_stats* stats);
+
 /* The batched form: simplify nmesh independent meshes together.  The meshes
  * are concatenated into one set of arrays and every kernel launch of a round
  * covers all of them, so a batch of small meshes fills the GPU the way one

@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -68,6 +69,7 @@ struct pamo_ctx {
   size_t hbt_n = 0;
   Prof prof;
   MlpDev* mlp = nullptr;  // the learned proposal's network (device), when set
+  void* scratch = nullptr;  // device address of this device's static scratch (pamo_simplify_noalloc)
 };
 
 namespace {
@@ -97,6 +99,30 @@ struct Fail {
 };
 
 void fail(pamo_status code, const std::string& msg) { throw Fail{code, msg}; }
+
+// Scratch of pamo_simplify_noalloc: a file-scope device array that every GPU
+// the library runs on holds until the process ends.  In host code the array's
+// name is not a device address: each device's copy is found once, with that
+// device current, by hipGetSymbolAddress (scratch_address, from pamo_create),
+// and only that address is used afterwards.
+static __device__ __align__(256) unsigned char scratch[PAMO_NOALLOC_SCRATCH_BYTES];
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[SCRATCH_DEVICES] = {};
+
+// device address of `scratch` on `device`, which must be current
+void* scratch_address(int device) {
+  if (device < 0 || device >= SCRATCH_DEVICES) fail(PAMO_ERR_ARG, "device index outside [0, 64)");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    PAMO_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(PAMO_ERR_HIP, "no device address for the static scratch");
+    g_scratch_addr[device] = p;
+  }
+  return g_scratch_addr[device];
+}
 
 hipEvent_t ev_get(pamo_ctx* c) {
   if (!c->prof.pool.empty()) {
@@ -1204,6 +1230,13 @@ pamo_status pamo_create(pamo_ctx** out, int device, void* hip_stream, const pamo
     delete c;
     return PAMO_ERR_HIP;
   }
+  try {
+    c->scratch = scratch_address(device);  // once per device, with the device current
+  } catch (...) {
+    (void)hipHostFree(c->hcnt);
+    delete c;
+    return PAMO_ERR_HIP;
+  }
   *out = c;
   return PAMO_OK;
 }
@@ -1406,6 +1439,45 @@ pamo_status pamo_simplify(pamo_ctx* c, const double* V, int64_t nv, const int32_
     L.track = L.learned;
     return simplify_run(c, V, nv, F, nf, target_faces, V_out, nv_out, F_out, nf_out, stats, &L);
   });
+}
+
+pamo_status pamo_simplify_noalloc(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                                  int64_t target_faces, double* V_out, int64_t* nv_out, int32_t* F_out,
+                                  int64_t* nf_out, pamo_stats* stats) {
+  if (!c) return PAMO_ERR_ARG;
+  // For this call the context's workspace is the device's static scratch: the
+  // context's own buffers are set aside (a swap of host bookkeeping) and come
+  // back afterwards; phase timing (HIP events) is off.
+  Workspace arena;
+  arena.arena = static_cast<char*>(c->scratch);
+  arena.arena_bytes = c->scratch ? (size_t)PAMO_NOALLOC_SCRATCH_BYTES : 0;
+  std::swap(c->ws, arena);
+  int* const own_cnt = c->dcnt;
+  const uint32_t mask = c->prof.mask;
+  c->prof.mask = 0;
+  const pamo_status rc = guarded(c, [&]() -> pamo_status {
+    if (!c->scratch) fail(PAMO_ERR_HIP, "no static scratch on this device");
+    if (!V || !F || !V_out || !F_out || !nv_out || !nf_out) fail(PAMO_ERR_ARG, "null pointer");
+    check_sizes(nv, nf);
+    LearnRun L;
+    L.learned = c->opt.learned != 0;
+    L.track = L.learned;
+    Workspace count;  // what this call reserves, summed on the host
+    count.counting = true;
+    count.get<int>("ctx.cnt", C_COUNT);
+    Parts parts;
+    parts.learned = L.track;
+    reserve_mesh(count, nv, nf, c->opt, parts);
+    if (count.total > (size_t)PAMO_NOALLOC_SCRATCH_BYTES)
+      fail(PAMO_ERR_CAPACITY, "pamo_simplify_noalloc: the mesh needs " + std::to_string(count.total) +
+                                  " bytes of scratch, more than the " + std::to_string(PAMO_NOALLOC_SCRATCH_BYTES) +
+                                  " of the static scratch");
+    return simplify_run(c, V, nv, F, nf, target_faces, V_out, nv_out, F_out, nf_out, stats, &L);
+  });
+  std::swap(c->ws, arena);
+  c->dcnt = own_cnt;
+  c->prof.mask = mask;
+  return rc;
 }
 
 pamo_status pamo_collect(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F, int64_t nf,

@@ -21,7 +21,7 @@ ERRORS = {-1: "ARG", -2: "NONMANIFOLD", -3: "SELF_INTERSECTING", -4: "DEGENERATE
 
 EXPORTS = ["pamo_default_options", "pamo_create", "pamo_destroy", "pamo_set_options", "pamo_last_error",
            "pamo_workspace_bytes", "pamo_set_workspace", "pamo_workspace_held", "pamo_quadrics", "pamo_select", "pamo_check", "pamo_collapse",
-           "pamo_simplify", "pamo_simplify_batch", "pamo_set_mlp", "pamo_features", "pamo_mlp_logits",
+           "pamo_simplify", "pamo_simplify_noalloc", "pamo_simplify_batch", "pamo_set_mlp", "pamo_features", "pamo_mlp_logits",
            "pamo_collect", "pamo_mlp_grad", "pamo_mlp_train", "pamo_hausdorff", "pamo_self_intersections", "pamo_tri_pairs",
            "pamo_udf", "pamo_dualmc", "pamo_profile_enable",
            "pamo_profile_phases", "pamo_profile_name", "pamo_profile_read", "pamo_profile_reset"]
@@ -109,6 +109,8 @@ def lib():
         L.pamo_collapse.argtypes = [P, P, C.POINTER(I64), P, C.POINTER(I64), P, P, P, P, P]
         L.pamo_simplify.argtypes = [P, P, I64, P, I64, I64, P, C.POINTER(I64), P, C.POINTER(I64),
                                     C.POINTER(Stats)]
+        L.pamo_simplify_noalloc.argtypes = [P, P, I64, P, I64, I64, P, C.POINTER(I64), P, C.POINTER(I64),
+                                            C.POINTER(Stats)]
         L.pamo_simplify_batch.argtypes = [P, I32, P, P, P, P, P, P, P, P, P, P]
         L.pamo_set_mlp.argtypes = [P, P]
         L.pamo_features.argtypes = [P, P, I64, P, I64, P, I64, P, P]
