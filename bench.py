@@ -398,6 +398,12 @@ def main():
             "bytes_per_launch": kbytes / launches,
         },
         "phases_ms_per_step": {k: v[1] for k, v in sorted(breakdown.items(), key=lambda kv: -kv[1][1])},
+        # every phase of one profiled step: launches, HIP-event milliseconds, the
+        # algorithmic bytes of its launches and their rate against the HBM peak
+        "phases": {k: {"launches": v[0], "ms": v[1], "bytes": v[2],
+                       "GBs": v[2] / (v[1] / 1e3) / 1e9 if v[1] > 0 else None,
+                       "frac": v[2] / (v[1] / 1e3) / 1e9 / HBM_PEAK_GBS if v[1] > 0 else None}
+                   for k, v in sorted(breakdown.items(), key=lambda kv: -kv[1][1])},
     }
     tot_bytes = sum(v[2] for v in breakdown.values())
     out["path_roofline"] = {"algorithmic_bytes_per_step": tot_bytes,

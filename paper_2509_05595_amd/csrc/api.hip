@@ -668,16 +668,16 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
   cur.vdeg = b.vdeg;
   cur.vbox = b.vbox;
   {
-    TIMED(PH_QUADRICS, 108 * nv + 24 * nf);
+    TIMED(PH_QUADRICS, 224 * nv + 24 * nf);
     launch_quadrics(s, cur, b.Q, cnt + C_ERR);
   }
   {
-    TIMED(PH_COST, 104 * nv + 51 * nf);
+    TIMED(PH_COST, 220 * nv + 51 * nf);
     launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, cnt + C_ERR, c->opt.cost_target,
                      c->opt.prefilter != 0, c->opt.key_mode != 0);
   }
   {
-    TIMED(PH_SELECT, 20 * nv + 93 * nf);
+    TIMED(PH_SELECT, 84 * nv + 45 * nf);
     if (c->opt.key_mode) launch_rank_keys(c->ws, s, cur, b.key);
     launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
   }
@@ -1030,16 +1030,16 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs
   cur.vdeg = b.vdeg;
   cur.vbox = b.vbox;
   {
-    TIMED(PH_QUADRICS, 108 * nv + 24 * nf);
+    TIMED(PH_QUADRICS, 224 * nv + 24 * nf);
     launch_quadrics(s, cur, b.Q, cnt + C_ERR);
   }
   {
-    TIMED(PH_COST, 104 * nv + 51 * nf);
+    TIMED(PH_COST, 220 * nv + 51 * nf);
     launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, B.done, b.key, cnt + C_ERR, c->opt.cost_target,
                      c->opt.prefilter != 0, c->opt.key_mode != 0);
   }
   {
-    TIMED(PH_SELECT, 20 * nv + 93 * nf);
+    TIMED(PH_SELECT, 84 * nv + 45 * nf);
     if (c->opt.key_mode) launch_rank_keys(c->ws, s, cur, b.key);
     launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
   }
