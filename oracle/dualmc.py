@@ -30,9 +30,20 @@ away from the cube corners; beta = 0 is the plain linear crossing.  Quads: every
 valid grid edge whose four surrounding cubes exist joins the vertices of the
 patches holding it in those cubes, ordered right-handed around the edge's
 axis and oriented so that the normal points from the negative end to the
-positive one; a quad is split along its shorter diagonal (v0 v2 on a tie).
-Vertices are numbered by (cube, patch), cubes in index order i, then j, then
-k; quads by (axis, grid point) in the same order.
+positive one.
+
+Quad division by the envelope of the edge (Appendix 2.1): with p+ and p- the
+positive and negative ends of the grid edge and l, r the quad neighbours of
+vertex v (before and after it in the quad's order), v is concave when
+(v - p+) . ((l - p+) x (r - p+)) < 0 or (v - p-) . ((l - p-) x (r - p-)) > 0.
+A quad whose concave vertices lie on one diagonal only is split along that
+diagonal; one with concave vertices on both diagonals becomes four triangles
+around an extra vertex on the grid edge, at the edge's (smoothed) crossing
+point; one without concave vertices is split along the diagonal that gives
+the larger smallest angle (v0 v2 on a tie).  Vertices are numbered by (cube,
+patch), cubes in index order i, then j, then k, then the extra edge vertices
+in quad order; quads by (axis, grid point) in the same order, two or four
+triangles each.
 """
 from __future__ import annotations
 
@@ -97,8 +108,74 @@ def holds_face(config: int, f: int) -> bool:
     return any(all(e in p for e in FACES[f]) for p in patches(config))
 
 
-def dualmc(S, beta: float = 0.0):
-    """S: (R, R, R) float64 grid values -> (V (n, 3) float64, F (m, 3) int32)"""
+def _triple(v, l, r, p):
+    """(v - p) . ((l - p) x (r - p)), in this order of operations"""
+    ax, ay, az = l[0] - p[0], l[1] - p[1], l[2] - p[2]
+    bx, by, bz = r[0] - p[0], r[1] - p[1], r[2] - p[2]
+    cx = ay * bz - az * by
+    cy = az * bx - ax * bz
+    cz = ax * by - ay * bx
+    return (v[0] - p[0]) * cx + (v[1] - p[1]) * cy + (v[2] - p[2]) * cz
+
+
+def concave(v, l, r, ppos, pneg) -> bool:
+    """the concavity test of Appendix 2.1 for quad vertex v between l and r"""
+    return _triple(v, l, r, ppos) < 0.0 or _triple(v, l, r, pneg) > 0.0
+
+
+def _worst_cos(p, q, r):
+    """the largest cosine of the three angles of triangle pqr (its smallest
+    angle's cosine); 1 where an edge has zero length"""
+    import math
+    out = -2.0
+    for a, b, c in ((p, q, r), (q, r, p), (r, p, q)):
+        ux, uy, uz = b[0] - a[0], b[1] - a[1], b[2] - a[2]
+        wx, wy, wz = c[0] - a[0], c[1] - a[1], c[2] - a[2]
+        uu = ux * ux + uy * uy + uz * uz
+        ww = wx * wx + wy * wy + wz * wz
+        if uu == 0.0 or ww == 0.0:
+            cs = 1.0
+        else:
+            cs = (ux * wx + uy * wy + uz * wz) / (math.sqrt(uu) * math.sqrt(ww))
+        out = cs if cs > out else out
+    return out
+
+
+def divide_quad(q, ppos, pneg):
+    """the division of quad q (four positions, oriented) around the grid edge
+    with positive end ppos and negative end pneg: 'A' (along v0 v2), 'B' (along
+    v1 v3) or 'E' (four triangles around an extra vertex on the edge)"""
+    conc = [concave(q[i], q[(i + 3) % 4], q[(i + 1) % 4], ppos, pneg) for i in range(4)]
+    on_a, on_b = conc[0] or conc[2], conc[1] or conc[3]
+    if on_a and on_b:
+        return "E"
+    if on_a:
+        return "A"
+    if on_b:
+        return "B"
+    wa = max(_worst_cos(q[0], q[1], q[2]), _worst_cos(q[0], q[2], q[3]))
+    wb = max(_worst_cos(q[0], q[1], q[3]), _worst_cos(q[1], q[2], q[3]))
+    return "A" if wa <= wb else "B"
+
+
+def crossing(S, g0, g1, axis, beta):
+    """the surface's crossing point on the grid edge g0 -> g0 + axis (t from
+    the lower end g0, smoothed when beta > 0)"""
+    import math
+    R = S.shape[0]
+    s0, s1 = S[g0], S[g1]
+    t = s0 / (s0 - s1)
+    if beta > 0:
+        t = 1.0 / (1.0 + math.exp(-beta * (t - 0.5)))
+    q = [g0[0] + 0.5, g0[1] + 0.5, g0[2] + 0.5]
+    q[axis] = q[axis] + t
+    return (q[0] / R, q[1] / R, q[2] / R)
+
+
+def dualmc(S, beta: float = 0.0, info: dict | None = None):
+    """S: (R, R, R) float64 grid values -> (V (n, 3) float64, F (m, 3) int32);
+    info (optional) gets "patch_vertices", the number of vertices before the
+    extra edge vertices"""
     import math
     S = np.asarray(S, dtype=np.float64)
     R = S.shape[0]
@@ -153,6 +230,7 @@ def dualmc(S, beta: float = 0.0):
         raise AssertionError("a valid edge outside every patch")
 
     Fo = []
+    extra = []  # extra vertices on grid edges (four-triangle quads), in quad order
     for a in range(3):
         b, c = (a + 1) % 3, (a + 2) % 3  # right-handed around the axis
         for i in range(R):
@@ -177,13 +255,20 @@ def dualmc(S, beta: float = 0.0):
                     if p0:  # positive at the lower end: the normal points down the axis
                         ring = [ring[0], ring[3], ring[2], ring[1]]
                     q = [V[x] for x in ring]
-
-                    def dist2(x, y):
-                        dx, dy, dz = x[0] - y[0], x[1] - y[1], x[2] - y[2]
-                        return dx * dx + dy * dy + dz * dz
-                    d02, d13 = dist2(q[0], q[2]), dist2(q[1], q[3])
-                    if d02 <= d13:
+                    pt0 = tuple((g[x] + 0.5) / R for x in range(3))
+                    pt1 = tuple((g1[x] + 0.5) / R for x in range(3))
+                    kind = divide_quad(q, pt0 if p0 else pt1, pt1 if p0 else pt0)
+                    if kind == "A":
                         Fo += [(ring[0], ring[1], ring[2]), (ring[0], ring[2], ring[3])]
-                    else:
+                    elif kind == "B":
                         Fo += [(ring[0], ring[1], ring[3]), (ring[1], ring[2], ring[3])]
+                    else:
+                        ve = -1 - len(extra)  # numbered after every patch vertex
+                        extra.append(crossing(S, tuple(g), tuple(g1), a, beta))
+                        Fo += [(ring[i], ring[(i + 1) % 4], ve) for i in range(4)]
+    nv = len(V)
+    if info is not None:
+        info["patch_vertices"] = nv
+    V = V + extra
+    Fo = [tuple(x if x >= 0 else nv + (-1 - x) for x in t) for t in Fo]
     return np.array(V, dtype=np.float64).reshape(-1, 3), np.array(Fo, dtype=np.int32).reshape(-1, 3)

@@ -150,3 +150,158 @@ def test_smoothed_sphere_keeps_topology():
     V, F = dm.dualmc(S, 5.0)
     assert _euler(V, F) == 2 and _manifold(F)
     assert np.abs(np.linalg.norm(V - 0.5, axis=1) - 0.3).max() < 1.0 / 16
+
+
+# ---------------------------------------------------------------- envelope quad division (Appendix 2.1)
+def _reflex_2d(P, i):
+    """interior angle of vertex i of the counter-clockwise polygon P (2D) above 180 degrees"""
+    a, b, c = P[i - 1], P[i], P[(i + 1) % len(P)]
+    return (b[0] - a[0]) * (c[1] - b[1]) - (b[1] - a[1]) * (c[0] - b[0]) < 0
+
+
+def _star_quad(rng, reflex=None):
+    """a planar quad at z = 0 around the z axis, counter-clockwise seen from +z,
+    star-shaped from the axis (angles increasing), radius of vertex `reflex` shrunk"""
+    ang = np.sort(rng.uniform(0, 2 * np.pi, 4))
+    while np.max(np.diff(np.r_[ang, ang[0] + 2 * np.pi])) > 0.8 * np.pi:
+        ang = np.sort(rng.uniform(0, 2 * np.pi, 4))
+    rad = rng.uniform(0.5, 1.0, 4)
+    if reflex is not None:
+        rad[reflex] = rng.uniform(0.02, 0.15)
+    return [(float(r * np.cos(t)), float(r * np.sin(t)), 0.0) for r, t in zip(rad, ang)]
+
+
+def test_concavity_is_the_reflex_angle_of_planar_quads():
+    """For a quad in the plane across the edge (p+ above, p- below), the
+    triple-product test marks exactly the vertices whose interior angle
+    exceeds 180 degrees, found here from the plane polygon alone."""
+    rng = np.random.default_rng(21)
+    pp, pn = (0.0, 0.0, 1.0), (0.0, 0.0, -1.0)
+    seen = Counter()
+    for trial in range(400):
+        q = _star_quad(rng, reflex=trial % 5 if trial % 5 < 4 else None)
+        for i in range(4):
+            want = _reflex_2d([(x, y) for x, y, _ in q], i)
+            assert dm.concave(q[i], q[i - 1], q[(i + 1) % 4], pp, pn) == want
+            seen[want] += 1
+    assert seen[True] > 100 and seen[False] > 100
+
+
+def test_split_goes_through_the_concave_vertex():
+    """A planar quad with one reflex vertex is split along the diagonal through
+    it, and both triangles keep the quad's orientation (neither is inverted)."""
+    rng = np.random.default_rng(22)
+    pp, pn = (0.0, 0.0, 1.0), (0.0, 0.0, -1.0)
+    for trial in range(200):
+        i = trial % 4
+        q = _star_quad(rng, reflex=i)
+        if sum(_reflex_2d([(x, y) for x, y, _ in q], k) for k in range(4)) != 1:
+            continue
+        kind = dm.divide_quad(q, pp, pn)
+        assert kind == ("A" if i % 2 == 0 else "B")
+        tris = [(0, 1, 2), (0, 2, 3)] if kind == "A" else [(0, 1, 3), (1, 2, 3)]
+        for a, b, c in tris:
+            ux, uy = q[b][0] - q[a][0], q[b][1] - q[a][1]
+            wx, wy = q[c][0] - q[a][0], q[c][1] - q[a][1]
+            assert ux * wy - uy * wx > 0
+
+
+def test_convex_quads_take_the_larger_smallest_angle():
+    """Without concave vertices the split maximises the smallest angle of its
+    two triangles (brute force with arc cosines)."""
+    import math
+    rng = np.random.default_rng(23)
+
+    def min_angle(p, q, r):
+        out = 10.0
+        for a, b, c in ((p, q, r), (q, r, p), (r, p, q)):
+            u, w = np.subtract(b, a), np.subtract(c, a)
+            out = min(out, math.acos(max(-1.0, min(1.0, float(u @ w) / (np.linalg.norm(u) * np.linalg.norm(w))))))
+        return out
+    n = 0
+    for _ in range(300):
+        q = [(x, y, float(rng.uniform(-0.2, 0.2))) for x, y, _ in _star_quad(rng)]
+        pp, pn = (0.0, 0.0, 1.0), (0.0, 0.0, -1.0)
+        if any(dm.concave(q[i], q[i - 1], q[(i + 1) % 4], pp, pn) for i in range(4)):
+            continue
+        a = min(min_angle(q[0], q[1], q[2]), min_angle(q[0], q[2], q[3]))
+        b = min(min_angle(q[0], q[1], q[3]), min_angle(q[1], q[2], q[3]))
+        if abs(a - b) < 1e-9:
+            continue
+        assert dm.divide_quad(q, pp, pn) == ("A" if a > b else "B")
+        n += 1
+    assert n > 200
+
+
+def test_both_diagonals_concave_gives_four_triangles():
+    """A twisted quad going round the edge whose concave vertices (exact
+    rational triple products) lie on both diagonals becomes four triangles;
+    with the concave vertex on one diagonal only, that diagonal is taken."""
+    from fractions import Fraction as Fr
+
+    def triple_exact(v, l, r, p):
+        a = [Fr(l[k]) - Fr(p[k]) for k in range(3)]
+        b = [Fr(r[k]) - Fr(p[k]) for k in range(3)]
+        c = [a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]]
+        return sum((Fr(v[k]) - Fr(p[k])) * c[k] for k in range(3))
+
+    pp, pn = (0.0, 0.0, 2.0), (0.0, 0.0, -2.0)
+    q = [(3.0, 1.0, 1.0), (0.0, 3.0, -2.0), (-1.0, 1.0, 1.0), (-3.0, -2.0, 1.0)]
+    conc = [triple_exact(q[i], q[i - 1], q[(i + 1) % 4], pp) < 0 or triple_exact(q[i], q[i - 1], q[(i + 1) % 4], pn) > 0
+            for i in range(4)]
+    assert conc == [False, True, True, False]
+    assert [dm.concave(q[i], q[i - 1], q[(i + 1) % 4], pp, pn) for i in range(4)] == conc
+    assert dm.divide_quad(q, pp, pn) == "E"
+    flat = [(x, y, 0.0) for x, y, _ in q]  # planar: only the reflex vertex 2 is concave
+    assert [dm.concave(flat[i], flat[i - 1], flat[(i + 1) % 4], pp, pn) for i in range(4)] == [False, False, True, False]
+    assert dm.divide_quad(flat, pp, pn) == "A"
+
+
+def _rough_grid(seed, n=10):
+    rng = np.random.default_rng(seed)
+    S = rng.standard_normal((n, n, n)) * rng.uniform(0.2, 3) + rng.normal() * 0.3
+    S[0] = S[-1] = 1.0
+    S[:, 0] = S[:, -1] = 1.0
+    S[:, :, 0] = S[:, :, -1] = 1.0
+    return S
+
+
+@pytest.mark.parametrize("beta", [0.0, 5.0])
+def test_extra_vertices_sit_on_their_grid_edges(beta):
+    """Every vertex beyond the patch vertices belongs to a four-triangle quad:
+    it lies on a crossed grid edge at that edge's (smoothed) crossing, and its
+    four triangles form a closed fan around it."""
+    import math
+    found = 0
+    for seed in range(12):
+        S = _rough_grid(seed)
+        info = {}
+        V, F = dm.dualmc(S, beta, info)
+        R = S.shape[0]
+        for v in range(info["patch_vertices"], len(V)):
+            p = V[v] * R - 0.5
+            g = np.floor(p + 1e-12).astype(int)
+            a = int(np.argmax(np.abs(p - np.round(p))))  # the edge's axis: the non-integer coordinate
+            g0 = tuple(int(round(x)) if ax != a else int(g[a]) for ax, x in enumerate(p))
+            g1 = list(g0)
+            g1[a] += 1
+            s0, s1 = S[g0], S[tuple(g1)]
+            assert (s0 >= 0) != (s1 >= 0)
+            t = s0 / (s0 - s1)
+            if beta > 0:
+                t = 1.0 / (1.0 + math.exp(-beta * (t - 0.5)))
+            assert abs(p[a] - (g0[a] + t)) < 1e-12
+            ring = F[np.any(F == v, axis=1)]
+            others = [int(x) for t3 in ring for x in t3 if x != v]
+            assert all(c == 2 for c in Counter(others).values())
+            found += 1
+        assert _manifold(F) and orc.validate(V, F) == 0
+    assert found > 0
+
+
+def test_envelope_division_is_intersection_free_on_rough_grids():
+    for seed in range(8):
+        for beta in (0.0, 5.0):
+            V, F = dm.dualmc(_rough_grid(100 + seed), beta)
+            assert orc.validate(V, F) == 0
+            assert len(orc.self_intersections(V, F)) == 0
