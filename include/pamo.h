@@ -280,15 +280,21 @@ pamo_status pamo_udf(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* 
  * ambiguous face shared by two cubes that would otherwise give a non-manifold
  * dual edge is resolved the other way in both (the paper's manifold fix).
  * Per crossed grid edge with four neighbouring cubes: one quad, oriented with
- * its normal towards the outside, split along its shorter diagonal into two
- * triangles.  Vertices are numbered by cube (x outermost) then patch; faces by
- * axis then grid point.  V_out: device float64 [vcap][3]; F_out: device int32
- * [fcap][3]; *nv_out, *nf_out (host) get the sizes.  res in [2, 512], at most
- * 2^26 cubes crossed by the surface (else PAMO_ERR_HIP from the scan); values
- * must be finite where a sign change occurs.  Fails with PAMO_ERR_CAPACITY,
- * writing only the sizes, when the mesh does not fit, and PAMO_ERR_ARG for
- * beta < 0 or not finite.  Quads use the plain shorter-diagonal split (the
- * envelope division is not built).  Synchronises the stream. */
+ * its normal towards the outside, divided by the envelope of the grid edge
+ * (Appendix 2.1): with p+ and p- the edge's positive and negative ends and l,
+ * r a quad vertex v's neighbours, v is concave when
+ * (v - p+) . ((l - p+) x (r - p+)) < 0 or (v - p-) . ((l - p-) x (r - p-)) > 0;
+ * concave vertices on one diagonal only: two triangles split along it; on
+ * both: four triangles around an extra vertex at the edge's (smoothed)
+ * crossing point; none: the two triangles whose smallest angle is larger.
+ * Vertices are numbered by cube (x outermost) then patch, then the extra
+ * edge vertices in quad order; faces by axis then grid point, two or four per
+ * quad.  V_out: device float64 [vcap][3]; F_out: device int32 [fcap][3];
+ * *nv_out, *nf_out (host) get the sizes.  res in [2, 512], at most 2^26 cubes
+ * crossed by the surface and 2^26 quads (else PAMO_ERR_HIP); values must be
+ * finite where a sign change occurs.  Fails with PAMO_ERR_CAPACITY, writing
+ * only the sizes, when the mesh does not fit, and PAMO_ERR_ARG for beta < 0 or
+ * not finite.  Synchronises the stream. */
 pamo_status pamo_dualmc(pamo_ctx* ctx, const double* S, int32_t res, double iso, double beta, double* V_out,
                         int64_t vcap, int32_t* F_out, int64_t fcap, int64_t* nv_out, int64_t* nf_out);
 

@@ -175,7 +175,8 @@ def crossing(S, g0, g1, axis, beta):
 def dualmc(S, beta: float = 0.0, info: dict | None = None):
     """S: (R, R, R) float64 grid values -> (V (n, 3) float64, F (m, 3) int32);
     info (optional) gets "patch_vertices", the number of vertices before the
-    extra edge vertices"""
+    extra edge vertices, and "kinds", the division of every quad in order
+    ('A', 'B' or 'E')"""
     import math
     S = np.asarray(S, dtype=np.float64)
     R = S.shape[0]
@@ -231,6 +232,7 @@ def dualmc(S, beta: float = 0.0, info: dict | None = None):
 
     Fo = []
     extra = []  # extra vertices on grid edges (four-triangle quads), in quad order
+    kinds = []
     for a in range(3):
         b, c = (a + 1) % 3, (a + 2) % 3  # right-handed around the axis
         for i in range(R):
@@ -258,6 +260,7 @@ def dualmc(S, beta: float = 0.0, info: dict | None = None):
                     pt0 = tuple((g[x] + 0.5) / R for x in range(3))
                     pt1 = tuple((g1[x] + 0.5) / R for x in range(3))
                     kind = divide_quad(q, pt0 if p0 else pt1, pt1 if p0 else pt0)
+                    kinds.append(kind)
                     if kind == "A":
                         Fo += [(ring[0], ring[1], ring[2]), (ring[0], ring[2], ring[3])]
                     elif kind == "B":
@@ -269,6 +272,7 @@ def dualmc(S, beta: float = 0.0, info: dict | None = None):
     nv = len(V)
     if info is not None:
         info["patch_vertices"] = nv
+        info["kinds"] = kinds
     V = V + extra
     Fo = [tuple(x if x >= 0 else nv + (-1 - x) for x in t) for t in Fo]
     return np.array(V, dtype=np.float64).reshape(-1, 3), np.array(Fo, dtype=np.int32).reshape(-1, 3)

@@ -24,17 +24,26 @@
 // Quads: one per crossed grid edge whose four neighbouring cubes exist,
 // ordered by axis then grid point; its vertices go counter-clockwise round
 // the axis seen from the axis's positive side, reversed when the lower end is
-// positive, so the normal points to the positive side; each is split into
-// two triangles along its shorter diagonal (the one through its first vertex
-// on a tie).
+// positive, so the normal points to the positive side.
+//
+// Quad division by the envelope of the grid edge (Appendix 2.1): with p+ and
+// p- the edge's positive and negative ends and l, r the quad neighbours of
+// vertex v, v is concave when (v - p+) . ((l - p+) x (r - p+)) < 0 or
+// (v - p-) . ((l - p-) x (r - p-)) > 0.  Concave vertices on one diagonal
+// only: the split along it; on both: four triangles around an extra vertex at
+// the edge's crossing point (numbered after the patch vertices, in quad
+// order); none: the split whose smallest angle is larger (through the first
+// vertex on a tie).
 //
 // Kernels: one thread per grid point (sign byte); one per cube (configuration,
 // crossed or not); one per grid point (its three edges: crossed and interior
 // or not); compactions of the crossed cubes and of the crossed edges; one
 // thread per crossed cube (flips, patches), a scan of their patch counts, one
-// per crossed cube (positions); one per crossed edge (two triangles).  The
-// patch structure of a cube is found once, by a small union-find, and kept as
-// two bits per edge.
+// per crossed cube (positions, into scratch); one per crossed edge (its
+// division), a scan of the four-triangle quads; then the positions copied
+// out and one thread per crossed edge (extra vertex, triangles).  The patch
+// structure of a cube is found once, by a small union-find, and kept as two
+// bits per edge.
 
 #include <hip/hip_runtime.h>
 
@@ -255,26 +264,34 @@ __global__ void k_dmc_qflags(const uint8_t* __restrict__ sg, int r, uint8_t* __r
   }
 }
 
-__device__ __forceinline__ double dist2(const double* x, const double* y) {
-  const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
-  return dx * dx + dy * dy + dz * dz;
+// the crossing point of grid edge (i0, j0, k0) -> +axis a (fraction from the
+// lower end, smoothed when beta > 0), as for the patch vertices
+__device__ __forceinline__ void edge_crossing(const DGrid& g, int i0, int j0, int k0, int a, double* out) {
+  const double s0 = gval(g, i0, j0, k0);
+  const double s1 = gval(g, i0 + (a == 0), j0 + (a == 1), k0 + (a == 2));
+  double t = s0 / (s0 - s1);
+  if (g.beta > 0.0) t = 1.0 / (1.0 + exp(-g.beta * (t - 0.5)));
+  double q[3] = {(double)i0 + 0.5, (double)j0 + 0.5, (double)k0 + 0.5};
+  q[a] = q[a] + t;
+  const double rr = (double)g.r;
+  out[0] = q[0] / rr;
+  out[1] = q[1] / rr;
+  out[2] = q[2] / rr;
 }
 
-// one thread per crossed grid edge, from the ascending list of their ids
-__global__ void k_dmc_quads(int r, const uint8_t* __restrict__ sg, const uint32_t* __restrict__ pmap,
-                            const int32_t* __restrict__ vbase,
-                            const int32_t* __restrict__ qlist, int nq, const double* __restrict__ V,
-                            int32_t* __restrict__ F) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
-  const int64_t x = qlist[q];
+// the quad of crossed grid edge x (axis a = x / r^3): its four vertices in
+// order (normal towards the positive end), the grid point of its lower end
+__device__ __forceinline__ void quad_ring(int r, const uint8_t* __restrict__ sg, const uint32_t* __restrict__ pmap,
+                                          const int32_t* __restrict__ vbase, int64_t x, int ring[4], int gp[3],
+                                          int& a, bool& lower_pos) {
   const int64_t n3 = (int64_t)r * r * r, pt = x % n3;
-  const int a = (int)(x / n3);
-  const int gp[3] = {(int)(pt / ((int64_t)r * r)), (int)(pt / r % r), (int)(pt % r)};
+  a = (int)(x / n3);
+  gp[0] = (int)(pt / ((int64_t)r * r));
+  gp[1] = (int)(pt / r % r);
+  gp[2] = (int)(pt % r);
   const int m = r - 1;
   const int b = (a + 1) % 3, c = (a + 2) % 3;
   const int db[4] = {-1, 0, 0, -1}, dc[4] = {-1, -1, 0, 0};
-  int ring[4];
   for (int t = 0; t < 4; t++) {
     int cu[3] = {gp[0], gp[1], gp[2]};
     cu[b] += db[t];
@@ -284,20 +301,116 @@ __global__ void k_dmc_quads(int r, const uint8_t* __restrict__ sg, const uint32_
     const int64_t ci = ((int64_t)cu[0] * m + cu[1]) * m + cu[2];
     ring[t] = vbase[ci] + (int)((pmap[ci] >> (2 * (4 * a + u + 2 * v))) & 3);
   }
-  if (sg[pt]) {
+  lower_pos = sg[pt] != 0;
+  if (lower_pos) {
     const int t1 = ring[1];
     ring[1] = ring[3];
     ring[3] = t1;
   }
-  const int64_t o = (int64_t)q * 6;
-  const double d02 = dist2(V + (int64_t)ring[0] * 3, V + (int64_t)ring[2] * 3);
-  const double d13 = dist2(V + (int64_t)ring[1] * 3, V + (int64_t)ring[3] * 3);
-  if (d02 <= d13) {
+}
+
+// (v - p) . ((l - p) x (r - p)), in this order of operations
+__device__ __forceinline__ double triple(const double* v, const double* l, const double* r, const double* p) {
+  const double ax = l[0] - p[0], ay = l[1] - p[1], az = l[2] - p[2];
+  const double bx = r[0] - p[0], by = r[1] - p[1], bz = r[2] - p[2];
+  const double cx = ay * bz - az * by;
+  const double cy = az * bx - ax * bz;
+  const double cz = ax * by - ay * bx;
+  return (v[0] - p[0]) * cx + (v[1] - p[1]) * cy + (v[2] - p[2]) * cz;
+}
+
+// the largest cosine of the angles of triangle pqr (1 where an edge has zero length)
+__device__ __forceinline__ double worst_cos(const double* p, const double* q, const double* r) {
+  const double* A[3] = {p, q, r};
+  double out = -2.0;
+  for (int i = 0; i < 3; i++) {
+    const double* a = A[i];
+    const double* b = A[(i + 1) % 3];
+    const double* c = A[(i + 2) % 3];
+    const double ux = b[0] - a[0], uy = b[1] - a[1], uz = b[2] - a[2];
+    const double wx = c[0] - a[0], wy = c[1] - a[1], wz = c[2] - a[2];
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const double ww = wx * wx + wy * wy + wz * wz;
+    const double cs = uu == 0.0 || ww == 0.0 ? 1.0 : (ux * wx + uy * wy + uz * wz) / (sqrt(uu) * sqrt(ww));
+    out = cs > out ? cs : out;
+  }
+  return out;
+}
+
+// division of every crossed grid edge's quad: 0 along v0 v2, 1 along v1 v3,
+// 2 four triangles around an extra vertex on the edge (four[q] = 1)
+__global__ void k_dmc_qdiv(int r, const uint8_t* __restrict__ sg, const uint32_t* __restrict__ pmap,
+                           const int32_t* __restrict__ vbase, const int32_t* __restrict__ qlist, int nq,
+                           const double* __restrict__ V, uint8_t* __restrict__ kind, uint8_t* __restrict__ four) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  int ring[4], gp[3], a;
+  bool lower_pos;
+  quad_ring(r, sg, pmap, vbase, qlist[q], ring, gp, a, lower_pos);
+  double p[4][3];
+  for (int t = 0; t < 4; t++)
+    for (int k = 0; k < 3; k++) p[t][k] = V[(int64_t)ring[t] * 3 + k];
+  double e0[3], e1[3];
+  const double rr = (double)r;
+  for (int k = 0; k < 3; k++) {
+    e0[k] = ((double)gp[k] + 0.5) / rr;
+    e1[k] = ((double)(gp[k] + (k == a)) + 0.5) / rr;
+  }
+  const double* pp = lower_pos ? e0 : e1;
+  const double* pn = lower_pos ? e1 : e0;
+  bool conc[4];
+  for (int i = 0; i < 4; i++) {
+    const double* l = p[(i + 3) & 3];
+    const double* rt = p[(i + 1) & 3];
+    conc[i] = triple(p[i], l, rt, pp) < 0.0 || triple(p[i], l, rt, pn) > 0.0;
+  }
+  const bool on_a = conc[0] || conc[2], on_b = conc[1] || conc[3];
+  uint8_t k;
+  if (on_a && on_b) {
+    k = 2;
+  } else if (on_a) {
+    k = 0;
+  } else if (on_b) {
+    k = 1;
+  } else {
+    const double a1 = worst_cos(p[0], p[1], p[2]), a2 = worst_cos(p[0], p[2], p[3]);
+    const double b1 = worst_cos(p[0], p[1], p[3]), b2 = worst_cos(p[1], p[2], p[3]);
+    const double wa = a1 > a2 ? a1 : a2, wb = b1 > b2 ? b1 : b2;
+    k = wa <= wb ? 0 : 1;
+  }
+  kind[q] = k;
+  four[q] = k == 2;
+}
+
+// the triangles of every crossed grid edge's quad, from triangle 2 q + 2
+// rank[q] on (rank: four-triangle quads before it), and the extra vertex of a
+// four-triangle quad at nv_patch + rank[q]
+__global__ void k_dmc_quads(DGrid g, const uint8_t* __restrict__ sg, const uint32_t* __restrict__ pmap,
+                            const int32_t* __restrict__ vbase, const int32_t* __restrict__ qlist, int nq,
+                            const uint8_t* __restrict__ kind, const int32_t* __restrict__ rank, int nv_patch,
+                            double* __restrict__ V, int32_t* __restrict__ F) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  int ring[4], gp[3], a;
+  bool lower_pos;
+  quad_ring(g.r, sg, pmap, vbase, qlist[q], ring, gp, a, lower_pos);
+  const int rk = rank[q];
+  const int64_t o = ((int64_t)q + rk) * 6;
+  const uint8_t k = kind[q];
+  if (k == 0) {
     F[o + 0] = ring[0], F[o + 1] = ring[1], F[o + 2] = ring[2];
     F[o + 3] = ring[0], F[o + 4] = ring[2], F[o + 5] = ring[3];
-  } else {
+  } else if (k == 1) {
     F[o + 0] = ring[0], F[o + 1] = ring[1], F[o + 2] = ring[3];
     F[o + 3] = ring[1], F[o + 4] = ring[2], F[o + 5] = ring[3];
+  } else {
+    const int ve = nv_patch + rk;
+    edge_crossing(g, gp[0], gp[1], gp[2], a, V + (int64_t)ve * 3);
+    for (int t = 0; t < 4; t++) {
+      F[o + 3 * t + 0] = ring[t];
+      F[o + 3 * t + 1] = ring[(t + 1) & 3];
+      F[o + 3 * t + 2] = ve;
+    }
   }
 }
 
@@ -373,14 +486,33 @@ bool dualmc_run(Workspace& ws, hipStream_t s, const double* S, int res, double i
                      (const int32_t*)clist, nc, pmap, cntl);
   scan_exclusive(ws, s, cntl, vbl, nc, tot + 2);
   PAMO_HIP(hipGetLastError());
-  *nv = read_i32(s, tot + 2);
-  *nf = 2 * (int64_t)nq;
-  if (*nv > vcap || *nf > fcap) return false;
+  const int32_t nvp = read_i32(s, tot + 2);
+  // patch vertices into scratch first: the quads' division needs them, and
+  // the sizes (extra vertices, four-triangle quads) must be known before any
+  // output is written
+  double* vt = ws.get<double>("dmc.vtmp", 3 * (int64_t)nvp);
   hipLaunchKernelGGL(k_dmc_verts, dim3(blocks(nc)), dim3(256), 0, s, g, (const uint8_t*)cfgs, (const int32_t*)clist,
-                     nc, (const uint32_t*)pmap, (const int32_t*)cntl, (const int32_t*)vbl, vbase, V);
+                     nc, (const uint32_t*)pmap, (const int32_t*)cntl, (const int32_t*)vbl, vbase, vt);
+  int32_t n4 = 0;
+  uint8_t* kind = ws.get<uint8_t>("dmc.kind", nq);
+  int32_t* rank = ws.get<int32_t>("dmc.rank", nq);
+  if (nq > 0) {
+    if (nq > ((int64_t)1 << 26)) throw std::runtime_error("more than 2^26 quads");
+    uint8_t* four = ws.get<uint8_t>("dmc.four", nq);
+    hipLaunchKernelGGL(k_dmc_qdiv, dim3(blocks(nq)), dim3(256), 0, s, res, (const uint8_t*)sg, (const uint32_t*)pmap,
+                       (const int32_t*)vbase, (const int32_t*)qlist, nq, (const double*)vt, kind, four);
+    run_flag_scan(ws, s, four, nq, rank, tot + 2);
+    PAMO_HIP(hipGetLastError());
+    n4 = read_i32(s, tot + 2);
+  }
+  *nv = (int64_t)nvp + n4;
+  *nf = 2 * ((int64_t)nq + n4);
+  if (*nv > vcap || *nf > fcap) return false;
+  if (nvp > 0) PAMO_HIP(hipMemcpyAsync(V, vt, 3 * (size_t)nvp * sizeof(double), hipMemcpyDeviceToDevice, s));
   if (nq > 0)
-    hipLaunchKernelGGL(k_dmc_quads, dim3(blocks(nq)), dim3(256), 0, s, res, (const uint8_t*)sg,
-                       (const uint32_t*)pmap, (const int32_t*)vbase, (const int32_t*)qlist, nq, (const double*)V, F);
+    hipLaunchKernelGGL(k_dmc_quads, dim3(blocks(nq)), dim3(256), 0, s, g, (const uint8_t*)sg, (const uint32_t*)pmap,
+                       (const int32_t*)vbase, (const int32_t*)qlist, nq, (const uint8_t*)kind, (const int32_t*)rank,
+                       nvp, V, F);
   PAMO_HIP(hipGetLastError());
   return true;
 }
