@@ -212,7 +212,7 @@ pamo_status pamo_simplify(pamo_ctx* ctx, const double* V, int64_t nv, const int3
  * must have been created (pamo_create finds the array's device address).  A
  * mesh whose buffers do not fit fails
  * with PAMO_ERR_CAPACITY before any work (at the default options a closed
- * mesh needs about 870 bytes per face, so meshes up to about 150,000 faces
+ * mesh needs about 950 bytes per face, so meshes up to about 140,000 faces
  * fit; pamo_workspace_bytes gives the size of a larger workspace for
  * pamo_simplify).  Every call on a GPU shares that
  * GPU's array and leaves its contents behind: calls that overlap on one GPU,
@@ -262,8 +262,11 @@ pamo_status pamo_simplify_batch(pamo_ctx* ctx, int32_t nmesh, const double* V, c
  * paper keeps a band of 3 / res).  V: device float64 [nv][3], F: device int32
  * [nf][3] (any soup: no manifoldness or orientation is assumed; nf may be 0);
  * udf: device float64 [res^3], written whole.  res in [1, 2048], band > 0.
- * Fails with PAMO_ERR_ARG on an index outside [0, nv) and PAMO_ERR_CAPACITY when
- * one triangle's banded box covers more than 2^20 tiles of 4^3 voxels.
+ * Fails with PAMO_ERR_ARG on an index outside [0, nv), and with
+ * PAMO_ERR_CAPACITY (udf then holds no field) when one
+ * triangle's banded box covers more than 2^20 tiles of 4^3 voxels, when nf
+ * exceeds 2^26, or when the (tile, triangle) pairs that pass the band filter
+ * exceed 2^26 in all (the per-triangle counts and the pairs are scanned whole).
  * Synchronises the stream. */
 pamo_status pamo_udf(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf, int32_t res,
                      double band, double* udf);

@@ -1819,6 +1819,8 @@ pamo_status pamo_hausdorff(pamo_ctx* c, const double* P, int64_t np, const doubl
   });
 }
 
+constexpr int64_t kUdfScanMax = (int64_t)1 << 26;
+
 pamo_status pamo_udf(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F, int64_t nf, int32_t res, double band,
                      double* udf) {
   return guarded(c, [&]() -> pamo_status {
@@ -1826,6 +1828,9 @@ pamo_status pamo_udf(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F,
     if (nv < 0 || nf < 0 || nf > (int64_t)(INT32_MAX / 3) - 1 || (nf > 0 && nv < 1)) fail(PAMO_ERR_ARG, "bad sizes");
     if (res < 1 || res > 2048) fail(PAMO_ERR_ARG, "grid resolution outside [1, 2048]");
     if (!(band > 0.0) || !(band < INFINITY)) fail(PAMO_ERR_ARG, "band width must be positive and finite");
+    // the library's scans take at most 2^26 items: the per-triangle pair counts
+    // and the per-pair run flags are scanned whole
+    if (nf > kUdfScanMax) fail(PAMO_ERR_CAPACITY, "more than 2^26 triangles for the distance field");
     hipStream_t s = c->stream;
     fill_i32(s, c->dcnt, C_COUNT, 0);
     if (nf > 0) {
@@ -1836,7 +1841,7 @@ pamo_status pamo_udf(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F,
       unsigned long long t = 0;
       PAMO_HIP(hipMemcpyAsync(&t, total, sizeof(t), hipMemcpyDeviceToHost, s));
       check_err_bits(readback(c)[C_ERR]);  // synchronises
-      if (t > (unsigned long long)INT32_MAX - 1) fail(PAMO_ERR_CAPACITY, "too many tile-triangle pairs for the grid");
+      if (t > (unsigned long long)kUdfScanMax) fail(PAMO_ERR_CAPACITY, "more than 2^26 tile-triangle pairs");
       return (int64_t)t;
     });
     PAMO_HIP(hipStreamSynchronize(s));

@@ -131,9 +131,11 @@ PAMO_HD __forceinline__ uint64_t cost_code64(double cost) {
   return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
 }
 
-// squared distance from p to triangle abc (closest point by the region
-// tests of the Voronoi regions of the triangle's features; may be NaN for a
-// triangle of zero area)
+// squared distance from p to triangle abc: the closest point found by testing
+// which Voronoi region of the triangle's vertices, edges or face holds p, with
+// barycentric coordinates from dot products (the published method of
+// C. Ericson, Real-Time Collision Detection, 2005, Sec. 5.1.5; may be NaN for
+// a triangle of zero area)
 __device__ __forceinline__ double tri_dist2(P3 p, P3 a, P3 b, P3 c) {
   double abx = b.x - a.x, aby = b.y - a.y, abz = b.z - a.z;
   double acx = c.x - a.x, acy = c.y - a.y, acz = c.z - a.z;

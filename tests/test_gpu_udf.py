@@ -99,3 +99,29 @@ def test_udf_empty_soup_and_errors(ctx):
     assert e.value.code == -1
     with pytest.raises(native.PamoError):
         ctx.udf(V, F, 8, band=-1.0)
+
+
+def test_udf_scan_limits(ctx):
+    """The whole-array scans take at most 2^26 items: more triangles, or more
+    (tile, triangle) pairs passing the band filter, fail with PAMO_ERR_CAPACITY
+    and leave the context usable."""
+    from paper_2509_05595_amd import native
+    Vs, Fs = g.icosphere(2)
+    Vs = Vs * 0.3 + 0.5
+    before = ctx.udf(*dev(Vs, Fs), 16).cpu().numpy()
+    V = torch.zeros((3, 3), dtype=torch.float64, device="cuda")
+    F = torch.zeros(((1 << 26) + 1, 3), dtype=torch.int32, device="cuda")
+    with pytest.raises(native.PamoError) as e:
+        ctx.udf(V, F, 8)
+    assert e.value.code == native.PAMO_ERR_CAPACITY
+    del F
+    # the plane z = 1/2 as two triangles, each repeated: at res 256 (tiles of 4
+    # voxels, band 3 voxels) each copy passes the filter in two layers of at
+    # least half of the 64 x 64 tiles, so 32,768 copies give over 2^27 pairs
+    Vp = np.array([[0, 0, 0.5], [1, 0, 0.5], [1, 1, 0.5], [0, 1, 0.5]])
+    Fp = np.tile(np.array([[0, 1, 2], [0, 2, 3]]), (1 << 14, 1))
+    with pytest.raises(native.PamoError) as e:
+        ctx.udf(*dev(Vp, Fp), 256)
+    assert e.value.code == native.PAMO_ERR_CAPACITY
+    after = ctx.udf(*dev(Vs, Fs), 16).cpu().numpy()
+    assert np.array_equal(before, after)
