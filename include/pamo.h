@@ -301,6 +301,89 @@ pamo_status pamo_udf(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* 
 pamo_status pamo_dualmc(pamo_ctx* ctx, const double* S, int32_t res, double iso, double beta, double* V_out,
                         int64_t vcap, int32_t* F_out, int64_t fcap, int64_t* nv_out, int64_t* nf_out);
 
+/* ---- safe projection (the stage after the path), Sec. 6 ---- */
+
+/* Options of the safe projection; pamo_project_defaults gives the paper's
+ * values (Sec. 6.1, Sec. 6.2: k_dis 1e3, k_elas 1e-1, k_bend 1e-2, k_bar 1e2,
+ * dhat 1e-3, T = 50 iterations, targets refreshed every 10) and this
+ * library's choices where the paper gives none (CG tolerance 1e-8 relative
+ * to |grad B|, at most 1000 CG iterations; additive CCD keeps 0.1 of each
+ * pair's distance; at most 40 line-search halvings). */
+typedef struct {
+  double k_dis, k_elas, k_bend, k_bar;
+  double dhat;
+  double cg_tol;
+  double accd_s;
+  int32_t iterations;
+  int32_t refresh;
+  int32_t cg_max;
+  int32_t ls_max;
+} pamo_project_options;
+
+typedef struct {
+  int32_t iterations;  /* iterations run */
+  int32_t cg_iters;    /* CG iterations, summed */
+  int32_t halvings;    /* line-search halvings, summed */
+  int32_t stalled;     /* iterations whose line search found no decrease of B */
+  int64_t max_pt, max_ee;  /* most point-triangle / edge-edge contacts at an iteration's start */
+  double B_first, B_last;  /* B at the first iteration's start and at the end */
+} pamo_project_stats;
+
+void pamo_project_defaults(pamo_project_options* opt);
+
+/* Uniform samples on a triangle mesh (the m points of E_M2S, Sec. 6.1): from
+ * uniforms U (device float64 [m][3] in [0, 1)), sample s lies on the first
+ * triangle whose inclusive cumulative area exceeds U[s][0] times the total,
+ * at (1 - r) a + r (1 - U[s][2]) b + r U[s][2] c with r = sqrt(U[s][1])
+ * (uniform on the triangle).  Y: device float64 [m][3].  *area (host, may be
+ * NULL) gets the total area.  Synchronises the stream. */
+pamo_status pamo_sample_surface(pamo_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                                const double* U, int64_t m, double* Y, double* area);
+
+/* The closest-feature targets of App. 2.2 for the mesh (X, F) being projected
+ * towards (Vin, Fin): targets[i] (device float64 [nv][3]) the point of the
+ * input mesh closest to X[i]; tri[s] (device int32 [m]) the triangle of (X, F)
+ * closest to the sample Y[s] (device float64 [m][3]).  Ties go to the smallest
+ * triangle index whose squared distance is within a relative 1e-9 of the
+ * smallest.  Synchronises the stream. */
+pamo_status pamo_project_targets(pamo_ctx* ctx, const double* X, int64_t nv, const int32_t* F, int64_t nf,
+                                 const double* Vin, int64_t nv_in, const int32_t* Fin, int64_t nf_in, const double* Y,
+                                 int64_t m, double* targets, int32_t* tri);
+
+/* The pieces of one iteration of Alg. 2 at positions X (device [nv][3]) of the
+ * mesh F (device int32 [nf][3], closed and manifold) with rest shape X0, the
+ * given targets and tri (as pamo_project_targets writes them), samples Y and
+ * input area area_in (the weight A_in / m of E_M2S).  parts (host [6]): the
+ * unweighted terms E_S2M, E_M2S, E_elas, E_bend, the barrier sum, then B;
+ * contacts (host [2], may be NULL): point-triangle and edge-edge pairs closer
+ * than dhat.  Optional (NULL to skip), all device [nv][3]: grad = grad B; Hv =
+ * H v for the element-wise projected Hessian H; dir = the CG solution of
+ * H p = -grad B (with *cg_iters, host) and *step (host) the additive-CCD step
+ * bound along it.  Synchronises the stream. */
+pamo_status pamo_project_eval(pamo_ctx* ctx, const double* X0, const double* X, int64_t nv, const int32_t* F,
+                              int64_t nf, const double* targets, const double* Y, const int32_t* tri, int64_t m,
+                              double area_in, const pamo_project_options* opt, double* parts, int64_t* contacts,
+                              double* grad, const double* v, double* Hv, double* dir, int32_t* cg_iters, double* step);
+
+/* Safe projection (Sec. 6, Alg. 2; App. 2.2): moves the vertices of the
+ * simplified mesh (Vs, Fs: device, closed, manifold, free of
+ * self-intersections) towards the input mesh (Vin, Fin: device, any triangle
+ * mesh) by projected Newton on B = k_dis (E_S2M + E_M2S) + k_elas E_elas +
+ * k_bend E_bend + k_bar sum b(d): per iteration the element Hessians are
+ * projected to positive semi-definite, the direction comes from conjugate
+ * gradients, additive CCD bounds the step so that no pair of primitives meets
+ * along it, and the step is halved until B decreases.  Y: device float64
+ * [m][3], the samples of E_M2S on the input mesh (pamo_sample_surface).
+ * V_out: device float64 [nv][3] (may equal Vs).  log (host, may be NULL):
+ * [iterations][8] per iteration: B at its start, the CCD bound, the step
+ * taken (0 when none decreased B), halvings, CG iterations, point-triangle
+ * and edge-edge contacts, |grad B|.  Fails with PAMO_ERR_NONMANIFOLD when
+ * (Vs, Fs) is not a closed oriented manifold.  Synchronises the stream. */
+pamo_status pamo_safe_project(pamo_ctx* ctx, const double* Vs, int64_t nv, const int32_t* Fs, int64_t nf,
+                              const double* Vin, int64_t nv_in, const int32_t* Fin, int64_t nf_in, const double* Y,
+                              int64_t m, const pamo_project_options* opt, double* V_out, double* log,
+                              pamo_project_stats* stats);
+
 /* ---- utilities ---- */
 
 /* All pairs (t < u) of faces that intersect under the test of Sec. 5.2 /

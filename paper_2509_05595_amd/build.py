@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpamo.so")
-SOURCES = ["prim.hip", "round.hip", "bvh.hip", "learn.hip", "remesh.hip", "dualmc.hip", "api.hip"]
+SOURCES = ["prim.hip", "round.hip", "bvh.hip", "learn.hip", "remesh.hip", "dualmc.hip", "project.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

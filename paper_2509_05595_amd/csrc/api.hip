@@ -18,6 +18,7 @@
 
 #include "internal.hpp"
 #include "learn.hpp"
+#include "project.hpp"
 #include "remesh.hpp"
 #include "round.hpp"
 #include "exact_dev.hpp"
@@ -1859,6 +1860,140 @@ pamo_status pamo_dualmc(pamo_ctx* c, const double* S, int32_t res, double iso, d
     if (!dualmc_run(c->ws, c->stream, S, res, iso, beta, V_out, vcap, F_out, fcap, nv_out, nf_out))
       fail(PAMO_ERR_CAPACITY, "output capacity too small for the extracted mesh");
     PAMO_HIP(hipStreamSynchronize(c->stream));
+    return PAMO_OK;
+  });
+}
+
+void pamo_project_defaults(pamo_project_options* o) {
+  if (!o) return;
+  o->k_dis = 1e3;
+  o->k_elas = 1e-1;
+  o->k_bend = 1e-2;
+  o->k_bar = 1e2;
+  o->dhat = 1e-3;
+  o->cg_tol = 1e-8;
+  o->accd_s = 0.1;
+  o->iterations = 50;
+  o->refresh = 10;
+  o->cg_max = 1000;
+  o->ls_max = 40;
+}
+
+namespace {
+pamo_project_options project_options(const pamo_project_options* opt) {
+  pamo_project_options o;
+  pamo_project_defaults(&o);
+  if (opt) o = *opt;
+  auto fin = [](double x) { return x == x && x < INFINITY && x > -INFINITY; };
+  if (!fin(o.k_dis) || !fin(o.k_elas) || !fin(o.k_bend) || !fin(o.k_bar) || o.k_dis < 0 || o.k_elas < 0 ||
+      o.k_bend < 0 || o.k_bar < 0)
+    fail(PAMO_ERR_ARG, "energy weights must be finite and >= 0");
+  if (!fin(o.dhat) || !(o.dhat > 0)) fail(PAMO_ERR_ARG, "dhat must be positive");
+  if (!fin(o.cg_tol) || !(o.cg_tol > 0) || o.cg_max < 1) fail(PAMO_ERR_ARG, "bad CG options");
+  if (!(o.accd_s > 0 && o.accd_s < 1)) fail(PAMO_ERR_ARG, "accd_s must lie in (0, 1)");
+  if (o.iterations < 0 || o.refresh < 1 || o.ls_max < 1) fail(PAMO_ERR_ARG, "bad iteration options");
+  return o;
+}
+
+void check_faces(pamo_ctx* c, const int32_t* F, int64_t nf, int64_t nv) {
+  if (nf <= 0) return;
+  fill_i32(c->stream, c->dcnt, C_COUNT, 0);
+  hipLaunchKernelGGL(k_check_index, dim3(nblk(3 * nf)), dim3(256), 0, c->stream, F, 3 * nf, (int)nv, c->dcnt + C_ERR);
+  check_err_bits(readback(c)[C_ERR]);
+}
+
+void check_mesh_sizes(int64_t nv, int64_t nf, int64_t min_nf) {
+  if (nv < 1 || nf < min_nf || nf > (int64_t)(INT32_MAX / 9) || nv > (int64_t)(INT32_MAX / 9))
+    fail(PAMO_ERR_ARG, "bad sizes");
+}
+}  // namespace
+
+pamo_status pamo_sample_surface(pamo_ctx* c, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                                const double* U, int64_t m, double* Y, double* area) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!V || !F || (m > 0 && (!U || !Y))) fail(PAMO_ERR_ARG, "null pointer");
+    check_mesh_sizes(nv, nf, 1);
+    if (m < 0 || m > (int64_t)(INT32_MAX / 3)) fail(PAMO_ERR_ARG, "bad sample count");
+    check_faces(c, F, nf, nv);
+    const double a = project_sample(c->ws, c->stream, V, (int)nv, F, (int)nf, U, m, Y);
+    if (area) *area = a;
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_project_targets(pamo_ctx* c, const double* X, int64_t nv, const int32_t* F, int64_t nf,
+                                 const double* Vin, int64_t nv_in, const int32_t* Fin, int64_t nf_in, const double* Y,
+                                 int64_t m, double* targets, int32_t* tri) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!X || !F || !Vin || !Fin || !targets || (m > 0 && (!Y || !tri))) fail(PAMO_ERR_ARG, "null pointer");
+    check_mesh_sizes(nv, nf, 1);
+    check_mesh_sizes(nv_in, nf_in, 1);
+    if (m < 0 || m > (int64_t)(INT32_MAX / 3)) fail(PAMO_ERR_ARG, "bad sample count");
+    check_faces(c, F, nf, nv);
+    check_faces(c, Fin, nf_in, nv_in);
+    project_targets(c->ws, c->stream, X, (int)nv, F, (int)nf, Vin, (int)nv_in, Fin, (int)nf_in, Y, (int)m, targets,
+                    tri);
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_project_eval(pamo_ctx* c, const double* X0, const double* X, int64_t nv, const int32_t* F,
+                              int64_t nf, const double* targets, const double* Y, const int32_t* tri, int64_t m,
+                              double area_in, const pamo_project_options* opt, double* parts, int64_t* contacts,
+                              double* grad, const double* v, double* Hv, double* dir, int32_t* cg_iters, double* step) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!X0 || !X || !F || !targets || !parts || (m > 0 && (!Y || !tri)) || (Hv && !v) || (step && !dir))
+      fail(PAMO_ERR_ARG, "null pointer");
+    check_mesh_sizes(nv, nf, 4);
+    if (m < 0 || m > (int64_t)(INT32_MAX / 3)) fail(PAMO_ERR_ARG, "bad sample count");
+    if (!(area_in >= 0) || !(area_in < INFINITY)) fail(PAMO_ERR_ARG, "bad input area");
+    const pamo_project_options o = project_options(opt);
+    check_faces(c, F, nf, nv);
+    if (m > 0) {  // the samples' triangles must exist
+      fill_i32(c->stream, c->dcnt, C_COUNT, 0);
+      hipLaunchKernelGGL(k_check_index, dim3(nblk(m)), dim3(256), 0, c->stream, tri, m, (int)nf, c->dcnt + C_ERR);
+      check_err_bits(readback(c)[C_ERR]);
+    }
+    ProjectEvalOut out;
+    out.grad = grad;
+    out.v = v;
+    out.Hv = Hv;
+    out.dir = dir;
+    out.want_step = step != nullptr;
+    try {
+      project_eval(c->ws, c->stream, X0, X, (int)nv, F, (int)nf, targets, Y, tri, (int)m, area_in, o, out);
+    } catch (const ProjectMeshError& e) {
+      fail(PAMO_ERR_NONMANIFOLD, e.what());
+    }
+    for (int k = 0; k < 6; k++) parts[k] = out.parts[k];
+    if (contacts) {
+      contacts[0] = out.npt;
+      contacts[1] = out.nee;
+    }
+    if (cg_iters) *cg_iters = out.cg_iters;
+    if (step) *step = out.step;
+    return PAMO_OK;
+  });
+}
+
+pamo_status pamo_safe_project(pamo_ctx* c, const double* Vs, int64_t nv, const int32_t* Fs, int64_t nf,
+                              const double* Vin, int64_t nv_in, const int32_t* Fin, int64_t nf_in, const double* Y,
+                              int64_t m, const pamo_project_options* opt, double* V_out, double* log,
+                              pamo_project_stats* stats) {
+  return guarded(c, [&]() -> pamo_status {
+    if (!Vs || !Fs || !Vin || !Fin || !V_out || (m > 0 && !Y)) fail(PAMO_ERR_ARG, "null pointer");
+    check_mesh_sizes(nv, nf, 4);
+    check_mesh_sizes(nv_in, nf_in, 1);
+    if (m < 0 || m > (int64_t)(INT32_MAX / 3)) fail(PAMO_ERR_ARG, "bad sample count");
+    const pamo_project_options o = project_options(opt);
+    check_faces(c, Fs, nf, nv);
+    check_faces(c, Fin, nf_in, nv_in);
+    try {
+      project_run(c->ws, c->stream, Vs, (int)nv, Fs, (int)nf, Vin, (int)nv_in, Fin, (int)nf_in, Y, (int)m, o, V_out,
+                  log, stats);
+    } catch (const ProjectMeshError& e) {
+      fail(PAMO_ERR_NONMANIFOLD, e.what());
+    }
     return PAMO_OK;
   });
 }

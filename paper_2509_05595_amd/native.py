@@ -23,7 +23,8 @@ EXPORTS = ["pamo_default_options", "pamo_create", "pamo_destroy", "pamo_set_opti
            "pamo_workspace_bytes", "pamo_set_workspace", "pamo_workspace_held", "pamo_quadrics", "pamo_select", "pamo_check", "pamo_collapse",
            "pamo_simplify", "pamo_simplify_noalloc", "pamo_simplify_batch", "pamo_set_mlp", "pamo_features", "pamo_mlp_logits",
            "pamo_collect", "pamo_mlp_grad", "pamo_mlp_train", "pamo_hausdorff", "pamo_self_intersections", "pamo_tri_pairs",
-           "pamo_udf", "pamo_dualmc", "pamo_profile_enable",
+           "pamo_udf", "pamo_dualmc", "pamo_project_defaults", "pamo_sample_surface", "pamo_project_targets",
+           "pamo_project_eval", "pamo_safe_project", "pamo_profile_enable",
            "pamo_profile_phases", "pamo_profile_name", "pamo_profile_read", "pamo_profile_reset"]
 
 
@@ -33,6 +34,23 @@ class Options(C.Structure):
                 ("resort_every", C.c_int32), ("query_coop", C.c_int32), ("coop_below", C.c_int32),
                 ("learned", C.c_int32), ("cost_target", C.c_double), ("prefilter", C.c_int32),
                 ("key_mode", C.c_int32), ("pair_capacity", C.c_int32)]
+
+
+class ProjectOptions(C.Structure):
+    _fields_ = [("k_dis", C.c_double), ("k_elas", C.c_double), ("k_bend", C.c_double), ("k_bar", C.c_double),
+                ("dhat", C.c_double), ("cg_tol", C.c_double), ("accd_s", C.c_double), ("iterations", C.c_int32),
+                ("refresh", C.c_int32), ("cg_max", C.c_int32), ("ls_max", C.c_int32)]
+
+
+class ProjectStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("cg_iters", C.c_int32), ("halvings", C.c_int32), ("stalled", C.c_int32),
+                ("max_pt", C.c_int64), ("max_ee", C.c_int64), ("B_first", C.c_double), ("B_last", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+PROJECT_LOG = ("B", "alpha_ccd", "alpha", "halvings", "cg_iters", "n_pt", "n_ee", "grad_norm")
 
 
 class Stats(C.Structure):
@@ -124,6 +142,14 @@ def lib():
         L.pamo_dualmc.argtypes = [P, P, C.c_int32, C.c_double, C.c_double, P, I64, P, I64, C.POINTER(I64),
                                   C.POINTER(I64)]
         L.pamo_tri_pairs.argtypes = [P, P, P, P, P, I64, P]
+        L.pamo_project_defaults.argtypes = [C.POINTER(ProjectOptions)]
+        L.pamo_project_defaults.restype = None
+        L.pamo_sample_surface.argtypes = [P, P, I64, P, I64, P, I64, P, C.POINTER(C.c_double)]
+        L.pamo_project_targets.argtypes = [P, P, I64, P, I64, P, I64, P, I64, P, I64, P, P]
+        L.pamo_project_eval.argtypes = [P, P, P, I64, P, I64, P, P, P, I64, C.c_double, C.POINTER(ProjectOptions),
+                                        P, P, P, P, P, P, C.POINTER(I32), C.POINTER(C.c_double)]
+        L.pamo_safe_project.argtypes = [P, P, I64, P, I64, P, I64, P, I64, P, I64, C.POINTER(ProjectOptions), P, P,
+                                        C.POINTER(ProjectStats)]
         L.pamo_profile_enable.argtypes = [P, C.c_uint32]
         L.pamo_profile_phases.argtypes = []
         L.pamo_profile_name.argtypes = [I32]
@@ -132,7 +158,7 @@ def lib():
         L.pamo_profile_reset.argtypes = [P]
         for n in EXPORTS:
             if n not in ("pamo_default_options", "pamo_destroy", "pamo_last_error", "pamo_workspace_bytes",
-                         "pamo_workspace_held", "pamo_profile_name"):
+                         "pamo_workspace_held", "pamo_profile_name", "pamo_project_defaults"):
                 getattr(L, n).restype = I32
         _lib = L
     return _lib
@@ -145,6 +171,15 @@ def _ptr(t):
 def default_options(**kw) -> Options:
     o = Options()
     lib().pamo_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def project_options(**kw) -> ProjectOptions:
+    """pamo_project_options with the paper's defaults, fields overridden by kw"""
+    o = ProjectOptions()
+    lib().pamo_project_defaults(C.byref(o))
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -438,6 +473,73 @@ class Context:
         self._call_growing(lambda: lib().pamo_dualmc(self._h, _ptr(S), int(res), float(iso), float(beta), _ptr(V), vcap,
                                                      _ptr(F), fcap, C.byref(nv), C.byref(nf)))
         return V[:nv.value], F[:nf.value]
+
+    # ---- safe projection
+    def sample_surface(self, V, F, U):
+        """samples on (V, F) from uniforms U (m, 3) -> (Y (m, 3), total area)"""
+        V, F = self._mesh(V, F)
+        assert U.dtype == torch.float64 and U.is_contiguous() and U.device == self.device
+        Y = torch.empty((U.shape[0], 3), dtype=torch.float64, device=self.device)
+        area = C.c_double(0.0)
+        self._call_growing(lambda: lib().pamo_sample_surface(self._h, _ptr(V), V.shape[0], _ptr(F), F.shape[0],
+                                                             _ptr(U), U.shape[0], _ptr(Y), C.byref(area)))
+        return Y, area.value
+
+    def project_targets(self, X, F, Vin, Fin, Y):
+        """closest input-mesh point per vertex, closest triangle of (X, F) per sample"""
+        X, F = self._mesh(X, F)
+        Vin, Fin = self._mesh(Vin, Fin)
+        targets = torch.empty_like(X)
+        tri = torch.empty((Y.shape[0],), dtype=torch.int32, device=self.device)
+        self._call_growing(lambda: lib().pamo_project_targets(
+            self._h, _ptr(X), X.shape[0], _ptr(F), F.shape[0], _ptr(Vin), Vin.shape[0], _ptr(Fin), Fin.shape[0],
+            _ptr(Y), Y.shape[0], _ptr(targets), _ptr(tri)))
+        return targets, tri
+
+    def project_eval(self, X0, X, F, targets, Y, tri, area_in, options=None, grad=False, v=None, direction=False,
+                     step=False):
+        """the pieces of one iteration at X: dict with parts (s2m, m2s, elastic,
+        bend, barrier, B), contacts (pt, ee) and, when asked, grad, Hv,
+        direction, cg_iters, step"""
+        X, F = self._mesh(X, F)
+        opt = options if options is not None else project_options()
+        parts = (C.c_double * 6)()
+        cont = (C.c_int64 * 2)()
+        g = torch.empty_like(X) if grad else None
+        Hv = torch.empty_like(X) if v is not None else None
+        d = torch.empty_like(X) if (direction or step) else None
+        it = C.c_int32(0)
+        st = C.c_double(0.0)
+        self._call_growing(lambda: lib().pamo_project_eval(
+            self._h, _ptr(X0), _ptr(X), X.shape[0], _ptr(F), F.shape[0], _ptr(targets), _ptr(Y), _ptr(tri),
+            Y.shape[0], float(area_in), C.byref(opt), parts, cont, _ptr(g), _ptr(v), _ptr(Hv), _ptr(d),
+            C.byref(it), C.byref(st) if step else None))
+        out = {"parts": list(parts), "contacts": (cont[0], cont[1])}
+        if grad:
+            out["grad"] = g
+        if Hv is not None:
+            out["Hv"] = Hv
+        if d is not None:
+            out["direction"] = d
+            out["cg_iters"] = it.value
+        if step:
+            out["step"] = st.value
+        return out
+
+    def safe_project(self, Vs, Fs, Vin, Fin, Y, options=None, out=None):
+        """Alg. 2: -> (V_out, per-iteration log (iterations, 8) float64 on the
+        host, stats dict)"""
+        import numpy as np
+        Vs, Fs = self._mesh(Vs, Fs)
+        Vin, Fin = self._mesh(Vin, Fin)
+        opt = options if options is not None else project_options()
+        V_out = out if out is not None else torch.empty_like(Vs)
+        log = np.zeros((max(opt.iterations, 1), 8))
+        st = ProjectStats()
+        self._call_growing(lambda: lib().pamo_safe_project(
+            self._h, _ptr(Vs), Vs.shape[0], _ptr(Fs), Fs.shape[0], _ptr(Vin), Vin.shape[0], _ptr(Fin), Fin.shape[0],
+            _ptr(Y), Y.shape[0], C.byref(opt), _ptr(V_out), C.c_void_p(log.ctypes.data), C.byref(st)))
+        return V_out, log[:opt.iterations], st.as_dict()
 
     # ---- measurement
     @staticmethod
