@@ -253,6 +253,47 @@ def remesh_udf(native, torch, dev, reps=5):
                         f"median of {reps} calls each", "rows": rows}
 
 
+def safe_projection(native, torch, dev, Vd, Fd, Vs, Fs, reps=2, m=16384):
+    """The stage after the path (Sec. 6, Alg. 2): the headline's simplified
+    mesh projected back towards its input mesh with the paper's settings (m
+    samples, T = 50 iterations, targets refreshed every 10), median of reps
+    calls after one warm-up; the distance energy (both directions, targets
+    found afresh) before and after."""
+    import numpy as np
+    ctx = native.Context(dev)
+    U = torch.from_numpy(np.random.default_rng(7).random((m, 3))).to(dev)
+    Y, area = ctx.sample_surface(Vd, Fd, U)
+    opt = native.project_options()
+
+    def distance_energy(X):
+        tg, tri = ctx.project_targets(X, Fs, Vd, Fd, Y)
+        p = ctx.project_eval(Vs, X, Fs, tg, Y, tri, area, options=opt)["parts"]
+        return p[0] + p[1], p
+
+    before, parts0 = distance_energy(Vs)
+    Xo, lg, st = ctx.safe_project(Vs, Fs, Vd, Fd, Y, options=opt)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        Xo, lg, st = ctx.safe_project(Vs, Fs, Vd, Fd, Y, options=opt)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ms = sorted(times)[len(times) // 2] * 1e3
+    after, parts1 = distance_energy(Xo)
+    _, npairs = ctx.self_intersections(Xo, Fs)
+    ctx.close()
+    log(f"safe projection {int(Fs.shape[0])} faces towards {int(Fd.shape[0])}: {ms:.1f} ms, "
+        f"{st['cg_iters']} CG iterations, distance energy {before:.4g} -> {after:.4g}")
+    return {"workload": f"the headline's simplified mesh ({int(Fs.shape[0])} faces) projected towards its input "
+                        f"({int(Fd.shape[0])} faces), {m} samples, T = {opt.iterations}, refresh every "
+                        f"{opt.refresh}, paper weights; median of {reps} calls",
+            "ms": ms, "iterations_per_s": opt.iterations / (ms / 1e3), "stats": st,
+            "distance_energy_before": before, "distance_energy_after": after,
+            "parts_before": parts0, "parts_after": parts1, "intersecting_pairs_after": int(npairs),
+            "log_first": lg[0].tolist(), "log_last": lg[-1].tolist()}
+
+
 def sharp_feature(native, torch, dev, steps):
     """Crease sphere (icosphere refined 9x, 5,242,880 faces, radius
     1 + 0.03|sin 12 theta||sin 9 phi| + 0.002 N(0,1)) to 0.1%, in one batch with 32
@@ -309,7 +350,8 @@ def main():
     ap.add_argument("--no-sharp", action="store_true", help="skip the sharp-feature batch")
     ap.add_argument("--no-check", action="store_true", help="skip the whole-mesh self-intersection check")
     ap.add_argument("--no-udf", action="store_true", help="skip the remeshing distance-field measurement")
-    ap.add_argument("--only", choices=["check", "udf"], default=None,
+    ap.add_argument("--no-project", action="store_true", help="skip the safe-projection measurement")
+    ap.add_argument("--only", choices=["check", "udf", "project"], default=None,
                     help="run only that section (whole-mesh check or distance field) and print its JSON")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
@@ -334,10 +376,20 @@ def main():
         return
     from paper_2509_05595_amd import meshgen, native
 
-    if args.only:  # one section alone (for kernel profiles of its workload)
+    if args.only in ("check", "udf"):  # one section alone (for kernel profiles of its workload)
         dev = torch.device("cuda:0")
         res = whole_mesh_check(native, torch, dev) if args.only == "check" else remesh_udf(native, torch, dev)
         print(json.dumps(res), flush=True)
+        return
+    if args.only == "project":
+        dev = torch.device("cuda:0")
+        V, F = meshgen.noisy_icosphere(args.refine, 2)
+        Vd, Fd = torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev)
+        c = native.Context(dev)
+        Vs, Fs, _ = c.simplify(Vd, Fd, int(len(F) * args.target_frac))
+        c.close()
+        print(json.dumps(safe_projection(native, torch, dev, Vd, Fd, Vs.contiguous(), Fs.contiguous(), reps=1)),
+              flush=True)
         return
 
     V, F = meshgen.noisy_icosphere(args.refine, 2)
@@ -425,6 +477,8 @@ def main():
         out["whole_mesh_check"] = whole_mesh_check(native, torch, dev)
     if not args.no_udf:
         out["remesh_udf"] = remesh_udf(native, torch, dev)
+    if not args.no_project:
+        out["safe_projection"] = safe_projection(native, torch, dev, Vd, Fd, Vo.contiguous(), Fo.contiguous())
     if not args.no_cpu_baseline and args.gpus == 1:
         out["cpu_baseline"] = cpu_baseline(V, F, target)
         log("cpu baseline timed")

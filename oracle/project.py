@@ -26,7 +26,11 @@ What it computes (Sec. 6.1 energies, Sec. 6.2 with Alg. 2, App. 2.2):
   clamping its negative eigenvalues to zero, p from H p = -grad B by conjugate
   gradients with a 3x3 block-Jacobi preconditioner, the step bounded by
   additive CCD (Li et al. 2021) over the pairs whose swept boxes overlap, then
-  halved until B decreases.
+  halved until B decreases (at most ls_max halvings, and no further once the
+  step alpha |p| is shorter than LS_MIN_STEP); an iteration that finds no
+  decrease leaves X as it is, and so would every later iteration until the
+  targets are refreshed (the same X and targets give the same direction), so
+  those are skipped.
 
 Derivatives: every element energy is a torch function of the element's own
 coordinates; gradients and Hessians come from torch's automatic differentiation
@@ -49,6 +53,7 @@ TIE = 1e-9  # closest-triangle ties: the smallest index within this relative mar
 TIE_ABS = 1e-24
 PARALLEL = 1e-20  # two edges are parallel when |ea x eb|^2 <= PARALLEL |ea|^2 |eb|^2
 ACCD_MAX_STEPS = 1 << 20
+LS_MIN_STEP = 1e-14  # the line search stops once alpha |p| falls below this length
 
 
 @dataclass
@@ -723,20 +728,33 @@ def safe_project(X0, F, Vin, Fin, U, opt=None, iterations=None):
     o = pb.opt
     T = o.iterations if iterations is None else iterations
     X = pb.X0.copy()
+    stalled, B0 = False, math.nan
     for t in range(T):
         if t % o.refresh == 0:
             refresh_targets(pb, X, Vin, Fin)
+            stalled = False
+        if stalled:
+            pb.log.append({"B": B0, "alpha_ccd": 0.0, "alpha": 0.0, "halvings": 0, "cg_iters": 0,
+                           "grad_norm": 0.0, "skipped": True})
+            continue
         B0 = energy(pb, X)
         g, H, P, cg_it = newton_direction(pb, X)
         a_ccd = accd(pb, X, P)
         alpha = min(1.0, a_ccd)
+        pnorm = float(np.linalg.norm(P))
         moved, halvings = False, 0
         for halvings in range(o.ls_max):
+            if alpha * pnorm < LS_MIN_STEP:
+                break
             Xn = X + alpha * P
-            if energy(pb, Xn) < B0:
+            Bn = energy(pb, Xn)
+            if Bn < B0:
                 X, moved = Xn, True
                 break
             alpha *= 0.5
+        stalled = not moved
         pb.log.append({"B": B0, "alpha_ccd": a_ccd, "alpha": alpha if moved else 0.0, "halvings": halvings,
                        "cg_iters": cg_it, "grad_norm": float(np.linalg.norm(g))})
+        if moved:
+            B0 = Bn
     return X, pb

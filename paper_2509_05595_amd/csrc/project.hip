@@ -50,6 +50,7 @@ constexpr double TIE = 1e-9;  // closest-triangle ties: the smallest index withi
 constexpr double TIE_ABS = 1e-24;
 constexpr double PARALLEL = 1e-20;  // two edges are parallel when |ea x eb|^2 <= PARALLEL |ea|^2 |eb|^2
 constexpr int ACCD_MAX_STEPS = 1 << 20;
+constexpr double LS_MIN_STEP = 1e-14;  // the line search stops once alpha |p| falls below this length
 constexpr int WALK_STACK = 48;  // 3 (D - 1) + 4 entries at most for D <= 14 levels
 
 // ------------------------------------------------------------ hyper-dual numbers
@@ -384,72 +385,87 @@ __device__ __forceinline__ constexpr int ut(int i, int j) {
   return i <= j ? i * N - i * (i - 1) / 2 + (j - i) : j * N - j * (j - 1) / 2 + (i - j);
 }
 
+// Sixteen lanes per matrix: lane r holds row r of the matrix and row r of the
+// accumulated rotation Q (so Q J and the column half of J^T A J are local);
+// the row half exchanges rows p and q between their two lanes by shuffles.
+// The final PSD part sum_k max(lambda_k, 0) q_k q_k^T is written row by row.
+constexpr int PSD_G = 16;
 template <int N>
-__global__ __launch_bounds__(64) void k_elem_psd(double* __restrict__ H, int n) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  constexpr int NT = N * (N + 1) / 2;
-  double A[NT], Q[N][N];
+__global__ __launch_bounds__(256) void k_elem_psd(double* __restrict__ H, int n) {
+  static_assert(N <= PSD_G, "one lane per row");
+  const int lane = threadIdx.x & (PSD_G - 1);
+  const int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / PSD_G;
+  if (grp >= n) return;  // whole groups leave together
+  const int64_t e = grp;
+  const bool row = lane < N;
+  double a[N], q[N];
 #pragma unroll
-  for (int i = 0; i < N; i++)
-#pragma unroll
-    for (int j = i; j < N; j++)
-      A[ut<N>(i, j)] = 0.5 * (H[(int64_t)(i * N + j) * n + e] + H[(int64_t)(j * N + i) * n + e]);
-#pragma unroll
-  for (int i = 0; i < N; i++)
-#pragma unroll
-    for (int j = 0; j < N; j++) Q[i][j] = i == j ? 1.0 : 0.0;
+  for (int k = 0; k < N; k++) {
+    a[k] = row ? 0.5 * (H[(int64_t)(lane * N + k) * n + e] + H[(int64_t)(k * N + lane) * n + e]) : 0.0;
+    q[k] = (row && k == lane) ? 1.0 : 0.0;
+  }
   for (int sweep = 0; sweep < 30; sweep++) {
     double off = 0.0, all = 0.0;
 #pragma unroll
-    for (int i = 0; i < N; i++) {
-      all += A[ut<N>(i, i)] * A[ut<N>(i, i)];
-#pragma unroll
-      for (int j = i + 1; j < N; j++) off += A[ut<N>(i, j)] * A[ut<N>(i, j)];
+    for (int k = 0; k < N; k++) {
+      all += a[k] * a[k];
+      if (k != lane) off += a[k] * a[k];
     }
-    if (!(off > 1e-32 * (all + 2.0 * off))) break;
+#pragma unroll
+    for (int d = PSD_G / 2; d >= 1; d >>= 1) {
+      off += __shfl_xor(off, d, PSD_G);
+      all += __shfl_xor(all, d, PSD_G);
+    }
+    if (!(off > 1e-32 * all)) break;
 #pragma unroll
     for (int p = 0; p < N - 1; p++) {
 #pragma unroll
-      for (int q = p + 1; q < N; q++) {
-        const double apq = A[ut<N>(p, q)];
+      for (int qq = p + 1; qq < N; qq++) {
+        const double apq = __shfl(a[qq], p, PSD_G);
+        const double app = __shfl(a[p], p, PSD_G);
+        const double aqq = __shfl(a[qq], qq, PSD_G);
         if (apq != 0.0) {
-          const double th = (A[ut<N>(q, q)] - A[ut<N>(p, p)]) / (2.0 * apq);
+          const double th = (aqq - app) / (2.0 * apq);
           const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
           const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+          // columns p and qq of this lane's row (A J)
+          const double arp = a[p], arq = a[qq];
+          a[p] = c * arp - s * arq;
+          a[qq] = s * arp + c * arq;
+          // rows p and qq (J^T (A J)) from the partner's row
+          const int partner = lane == p ? qq : (lane == qq ? p : lane);
+          double o[N];
 #pragma unroll
-          for (int r = 0; r < N; r++) {
-            if (r == p || r == q) continue;
-            const double arp = A[ut<N>(r, p)], arq = A[ut<N>(r, q)];
-            A[ut<N>(r, p)] = c * arp - s * arq;
-            A[ut<N>(r, q)] = s * arp + c * arq;
-          }
-          A[ut<N>(p, p)] -= t * apq;
-          A[ut<N>(q, q)] += t * apq;
-          A[ut<N>(p, q)] = 0.0;
+          for (int k = 0; k < N; k++) o[k] = __shfl(a[k], partner, PSD_G);
+          if (lane == p) {
 #pragma unroll
-          for (int r = 0; r < N; r++) {
-            const double qrp = Q[r][p], qrq = Q[r][q];
-            Q[r][p] = c * qrp - s * qrq;
-            Q[r][q] = s * qrp + c * qrq;
+            for (int k = 0; k < N; k++) a[k] = c * a[k] - s * o[k];
+            a[p] = app - t * apq;
+            a[qq] = 0.0;
+          } else if (lane == qq) {
+#pragma unroll
+            for (int k = 0; k < N; k++) a[k] = s * o[k] + c * a[k];
+            a[qq] = aqq + t * apq;
+            a[p] = 0.0;
           }
+          // Q J on this lane's row of Q
+          const double qrp = q[p], qrq = q[qq];
+          q[p] = c * qrp - s * qrq;
+          q[qq] = s * qrp + c * qrq;
         }
       }
     }
   }
   double lam[N];
 #pragma unroll
-  for (int k = 0; k < N; k++) lam[k] = fmax(A[ut<N>(k, k)], 0.0);
+  for (int k = 0; k < N; k++) lam[k] = fmax(__shfl(a[k], k, PSD_G), 0.0);
 #pragma unroll
-  for (int i = 0; i < N; i++)
+  for (int j = 0; j < N; j++) {
+    double s = 0.0;
 #pragma unroll
-    for (int j = i; j < N; j++) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < N; k++) s += lam[k] * Q[i][k] * Q[j][k];
-      H[(int64_t)(i * N + j) * n + e] = s;
-      H[(int64_t)(j * N + i) * n + e] = s;
-    }
+    for (int k = 0; k < N; k++) s += lam[k] * q[k] * __shfl(q[k], j, PSD_G);
+    if (row) H[(int64_t)(lane * N + j) * n + e] = s;
+  }
 }
 
 template <int K>
@@ -460,48 +476,6 @@ __global__ __launch_bounds__(256) void k_elem_grad(Elems E, double* __restrict__
   for (int i = 0; i < KT<K>::N; i++) {
     const int64_t v = E.ids[KT<K>::NV * (int64_t)e + i / 3];
     unsafeAtomicAdd(&grad[3 * v + i % 3], E.g[(int64_t)i * E.n + e]);
-  }
-}
-
-// the element's 3x3 diagonal blocks into the per-vertex blocks (row-major)
-template <int K>
-__global__ __launch_bounds__(256) void k_elem_diag(Elems E, double* __restrict__ Dblk) {
-  constexpr int N = KT<K>::N;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E.n) return;
-#pragma unroll
-  for (int a = 0; a < KT<K>::NV; a++) {
-    const int64_t v = E.ids[KT<K>::NV * (int64_t)e + a];
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-      for (int c = 0; c < 3; c++)
-        unsafeAtomicAdd(&Dblk[9 * v + 3 * r + c], E.H[(int64_t)((3 * a + r) * N + 3 * a + c) * E.n + e]);
-  }
-}
-
-template <int K>
-__global__ __launch_bounds__(256) void k_elem_matvec(Elems E, const double* __restrict__ v, double* __restrict__ out,
-                                                     const int* __restrict__ done) {
-  constexpr int N = KT<K>::N, NV = KT<K>::NV;
-  if (done && *done) return;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= E.n) return;
-  int64_t id[NV];
-  double x[N];
-#pragma unroll
-  for (int a = 0; a < NV; a++) {
-    id[a] = E.ids[NV * (int64_t)e + a];
-    x[3 * a] = v[3 * id[a]];
-    x[3 * a + 1] = v[3 * id[a] + 1];
-    x[3 * a + 2] = v[3 * id[a] + 2];
-  }
-#pragma unroll
-  for (int i = 0; i < N; i++) {
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < N; j++) s += E.H[(int64_t)(i * N + j) * E.n + e] * x[j];
-    unsafeAtomicAdd(&out[3 * id[i / 3] + i % 3], s);
   }
 }
 
@@ -522,15 +496,6 @@ __global__ void k_s2m_init(const double* __restrict__ X, const double* __restric
   const double w = 2.0 * k * s0[i];
   for (int c = 0; c < 3; c++) grad[3 * i + c] = w * (X[3 * i + c] - tg[3 * i + c]);
   for (int c = 0; c < 9; c++) Dblk[9 * i + c] = (c % 4 == 0) ? w : 0.0;
-}
-
-__global__ void k_s2m_matvec(const double* __restrict__ s0, int nv, double k, const double* __restrict__ v,
-                             double* __restrict__ out, const int* __restrict__ done) {
-  if (done && *done) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nv) return;
-  const double w = 2.0 * k * s0[i];
-  for (int c = 0; c < 3; c++) out[3 * i + c] = w * v[3 * i + c];
 }
 
 // inverse of each 3x3 block (adjugate over determinant)
@@ -696,6 +661,204 @@ __global__ __launch_bounds__(SUM_T) void k_sum_final(const double* __restrict__ 
   if (threadIdx.x == 0) *out = s;
 }
 
+// ------------------------------------------------------------ fused launches
+// The element kinds of one evaluation in one launch: blocks [blk[k],
+// blk[k+1]) serve kind k (0 the vertex term, then K_M2S .. K_EE + 1).
+constexpr int NSEG = K_KINDS + 1;
+struct KindRanges {
+  Elems E[K_KINDS];
+  const double* s0;
+  const double* tg;
+  double* sval;  // vertex term values
+  int nv;
+  const int* cnt;  // device contact counts (point-face, edge-edge)
+  int blk[NSEG + 1];
+};
+__device__ __forceinline__ int kind_of_block(const KindRanges& a, int b, int* local) {
+  int k = 0;
+  while (k < NSEG - 1 && b >= a.blk[k + 1]) k++;
+  *local = (b - a.blk[k]) * 256 + (int)threadIdx.x;
+  return k;
+}
+template <int K>
+__device__ __forceinline__ void value_one(const Elems& E, int e, const double* __restrict__ X) {
+  double x[KT<K>::N];
+  elem_load<K>(E, X, e, x);
+  E.val[e] = elem_energy<K, double>(E, e, x, elem_code<K>(E, e, x));
+}
+// every element's unweighted energy; contacts up to their device counts
+__global__ __launch_bounds__(256) void k_values_all(KindRanges a, const double* __restrict__ X) {
+  int i;
+  const int k = kind_of_block(a, blockIdx.x, &i);
+  switch (k) {
+    case 0:
+      if (i < a.nv) {
+        const double dx = X[3 * i] - a.tg[3 * i], dy = X[3 * i + 1] - a.tg[3 * i + 1], dz = X[3 * i + 2] - a.tg[3 * i + 2];
+        a.sval[i] = a.s0[i] * (dx * dx + dy * dy + dz * dz);
+      }
+      break;
+    case 1 + K_M2S:
+      if (i < a.E[K_M2S].n) value_one<K_M2S>(a.E[K_M2S], i, X);
+      break;
+    case 1 + K_EL:
+      if (i < a.E[K_EL].n) value_one<K_EL>(a.E[K_EL], i, X);
+      break;
+    case 1 + K_BEND:
+      if (i < a.E[K_BEND].n) value_one<K_BEND>(a.E[K_BEND], i, X);
+      break;
+    case 1 + K_PT:
+      if (i < min(a.cnt[0], a.E[K_PT].n)) value_one<K_PT>(a.E[K_PT], i, X);
+      break;
+    default:
+      if (i < min(a.cnt[1], a.E[K_EE].n)) value_one<K_EE>(a.E[K_EE], i, X);
+      break;
+  }
+}
+// partial sums of NSEG value arrays (blockIdx.y the segment; counts from the
+// host, or for the contact segments from the device); every block writes
+// its partial, zero past the segment's end
+struct SegSums {
+  const double* v[NSEG];
+  int n[NSEG];
+  const int* cnt;
+  double* part;
+  int stride;
+};
+__global__ __launch_bounds__(SUM_T) void k_sum_seg(SegSums a) {
+  const int k = blockIdx.y;
+  int n = a.n[k];
+  if (k >= 1 + K_PT) n = min(n, a.cnt[k - 1 - K_PT]);
+  const int64_t base = (int64_t)blockIdx.x * SUM_T * SUM_ITEMS;
+  double s = 0.0;
+  if (base < n)
+    for (int j = 0; j < SUM_ITEMS; j++) {
+      const int64_t i = base + (int64_t)j * SUM_T + threadIdx.x;
+      if (i < n) s += a.v[k][i];
+    }
+  s = block_sum(s);
+  if (threadIdx.x == 0) a.part[(int64_t)k * a.stride + blockIdx.x] = s;
+}
+__global__ __launch_bounds__(SUM_T) void k_sum_seg_final(const double* __restrict__ part, int nb, int stride,
+                                                         double* __restrict__ sums) {
+  const double s = sum_parts(part + (int64_t)blockIdx.x * stride, nb);
+  if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+
+// ------------------------------------------------------------ block-sparse Hessian
+// After the element Hessians are projected, their 3x3 vertex blocks are
+// summed into one block-sparse matrix (rows by vertex, a 3x3 block per vertex
+// pair that shares an element): the products of the CG loop then read each
+// block once and need no atomics.  Entries: [0, nv) the vertex term's
+// diagonal blocks, then NV^2 blocks per element of each kind.
+struct EntryRanges {
+  Elems E[K_KINDS];
+  int64_t off[NSEG + 1];
+  const double* s0;
+  double k2;  // 2 k_dis
+  int nv;
+};
+__device__ __forceinline__ int entry_decode(const EntryRanges& r, int64_t id, int* e, int* a, int* b) {
+  if (id < r.off[1]) {
+    *e = (int)id;
+    *a = *b = 0;
+    return 0;
+  }
+  int k = 1;
+  while (k < NSEG && id >= r.off[k + 1]) k++;
+  const int nv = k == 1 + K_M2S || k == 1 + K_EL ? 3 : 4;
+  const int64_t loc = id - r.off[k];
+  *e = (int)(loc / (nv * nv));
+  const int ab = (int)(loc - (int64_t)*e * nv * nv);
+  *a = ab / nv;
+  *b = ab % nv;
+  return k;
+}
+__device__ __forceinline__ const Elems& kind_elems(const EntryRanges& r, int k) { return r.E[k - 1]; }
+
+__global__ void k_bsr_keys(EntryRanges r, int bits, uint64_t* __restrict__ keys, int* __restrict__ vals) {
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id >= r.off[NSEG]) return;
+  int e, a, b;
+  const int k = entry_decode(r, id, &e, &a, &b);
+  int64_t i, j;
+  if (k == 0) {
+    i = j = e;
+  } else {
+    const Elems& E = kind_elems(r, k);
+    const int nv = k == 1 + K_M2S || k == 1 + K_EL ? 3 : 4;
+    i = E.ids[nv * (int64_t)e + a];
+    j = E.ids[nv * (int64_t)e + b];
+  }
+  keys[id] = ((uint64_t)i << bits) | (uint64_t)j;
+  vals[id] = (int)id;
+}
+__global__ void k_bsr_flags(const uint64_t* __restrict__ keys, int64_t n, uint8_t* __restrict__ fl) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < n) fl[k] = k == 0 || keys[k] != keys[k - 1];
+}
+__global__ void k_bsr_starts(const uint8_t* __restrict__ fl, const int* __restrict__ excl, int64_t n,
+                             int* __restrict__ ustart) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < n && fl[k]) ustart[excl[k]] = (int)k;
+}
+// one thread per block: its column, its row's start, and the sum of its
+// entries' 3x3 blocks in sorted (key, entry) order
+__global__ void k_bsr_fill(EntryRanges r, const uint64_t* __restrict__ keys, const int* __restrict__ vals,
+                           const int* __restrict__ ustart, const int* __restrict__ nslot, int64_t n, int bits,
+                           int* __restrict__ rowptr, int* __restrict__ col, double* __restrict__ B) {
+  const int ns = *nslot;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ns) return;
+  const int64_t beg = ustart[k], end = k + 1 < ns ? ustart[k + 1] : n;
+  const uint64_t key = keys[beg];
+  const int i = (int)(key >> bits);
+  col[k] = (int)(key & ((1ull << bits) - 1));
+  if (k == 0 || (int)(keys[ustart[k - 1]] >> bits) != i) rowptr[i] = k;
+  if (k == ns - 1) rowptr[r.nv] = ns;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t p = beg; p < end; p++) {
+    int e, a, b;
+    const int kind = entry_decode(r, vals[p], &e, &a, &b);
+    if (kind == 0) {
+      const double w = r.k2 * r.s0[e];
+      acc[0] += w;
+      acc[4] += w;
+      acc[8] += w;
+      continue;
+    }
+    const Elems& E = kind_elems(r, kind);
+    const int N = kind == 1 + K_M2S || kind == 1 + K_EL ? 9 : 12;
+    for (int rr = 0; rr < 3; rr++)
+      for (int c = 0; c < 3; c++) acc[3 * rr + c] += E.H[(int64_t)((3 * a + rr) * N + 3 * b + c) * E.n + e];
+  }
+  for (int q = 0; q < 9; q++) B[9 * (int64_t)k + q] = acc[q];
+}
+// the diagonal block of each row into Dblk
+__global__ void k_bsr_diag(const int* __restrict__ rowptr, const int* __restrict__ col, const double* __restrict__ B,
+                           int nv, double* __restrict__ Dblk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  for (int k = rowptr[i]; k < rowptr[i + 1]; k++)
+    if (col[k] == i)
+      for (int q = 0; q < 9; q++) Dblk[9 * (int64_t)i + q] = B[9 * (int64_t)k + q];
+}
+// out = H v, one thread per output component
+__global__ __launch_bounds__(256) void k_bsr_spmv(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                  const double* __restrict__ B, int nv, const double* __restrict__ v,
+                                                  double* __restrict__ out, const int* __restrict__ done) {
+  if (done && *done) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * nv) return;
+  const int i = t / 3, r = t - 3 * i;
+  double s = 0.0;
+  for (int k = rowptr[i]; k < rowptr[i + 1]; k++) {
+    const int64_t j = col[k];
+    const double* b = B + 9 * (int64_t)k + 3 * r;
+    s += b[0] * v[3 * j] + b[1] * v[3 * j + 1] + b[2] * v[3 * j + 2];
+  }
+  out[t] = s;
+}
+
 // ------------------------------------------------------------ conjugate gradients
 struct CgState {
   double rz, rr, bb, alpha, beta, tol;
@@ -753,12 +916,14 @@ __global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ z, int
 }
 // x = 0, r = -g, z = D^-1 r, p = z
 __global__ void k_cg_init(const double* __restrict__ g, const double* __restrict__ Di, int nv, double* __restrict__ x,
-                          double* __restrict__ r, double* __restrict__ z, double* __restrict__ p) {
+                          double* __restrict__ r, double* __restrict__ z, double* __restrict__ p,
+                          double* __restrict__ Ap) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nv) return;
   double rv[3];
   for (int c = 0; c < 3; c++) {
     x[3 * i + c] = 0.0;
+    Ap[3 * i + c] = 0.0;
     rv[c] = -g[3 * i + c];
     r[3 * i + c] = rv[c];
   }
@@ -768,6 +933,94 @@ __global__ void k_cg_init(const double* __restrict__ g, const double* __restrict
     z[3 * i + c] = zc;
     p[3 * i + c] = zc;
   }
+}
+
+// The last block to finish reads every block's partial sum (written before a
+// device-scope fence and a ticket) and updates the scalars.
+__device__ __forceinline__ double load_l2(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ bool last_block(unsigned* ticket) {
+  __shared__ bool last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+  __syncthreads();
+  return last;
+}
+__device__ double sum_parts_l2(const double* __restrict__ part, int nb) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += SUM_T) s += load_l2(part + i);
+  return block_sum(s);
+}
+// p.Ap, then alpha = rz / p.Ap
+__global__ __launch_bounds__(SUM_T) void k_cg_pap(const double* __restrict__ p, const double* __restrict__ Ap,
+                                                  int64_t n, double* __restrict__ part, unsigned* ticket, CgState* st) {
+  if (st->done) return;
+  const int64_t base = (int64_t)blockIdx.x * SUM_T * SUM_ITEMS;
+  double s = 0.0;
+  for (int j = 0; j < SUM_ITEMS; j++) {
+    const int64_t i = base + (int64_t)j * SUM_T + threadIdx.x;
+    if (i < n) s += p[i] * Ap[i];
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (!last_block(ticket)) return;
+  const double pap = sum_parts_l2(part, gridDim.x);
+  if (threadIdx.x == 0) {
+    st->alpha = st->rz / pap;
+    *ticket = 0;
+  }
+}
+// x += alpha p, r -= alpha Ap, z = D^-1 r with the partial sums of r.z and r.r;
+// the last block: beta, the new r.z and r.r, the stopping test
+__global__ __launch_bounds__(SUM_T) void k_cg_step(double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ z, const double* __restrict__ p,
+                                                   const double* __restrict__ Ap, const double* __restrict__ Di,
+                                                   int nv, double* __restrict__ pz, double* __restrict__ pr,
+                                                   unsigned* ticket, CgState* st) {
+  if (st->done) return;
+  const double a = st->alpha;
+  double srz = 0.0, srr = 0.0;
+  const int i = blockIdx.x * SUM_T + threadIdx.x;
+  if (i < nv) {
+    double rv[3];
+    for (int c = 0; c < 3; c++) {
+      x[3 * i + c] += a * p[3 * i + c];
+      r[3 * i + c] -= a * Ap[3 * i + c];
+      rv[c] = r[3 * i + c];
+    }
+    const double* d = Di + 9 * (int64_t)i;
+    for (int c = 0; c < 3; c++) {
+      const double zc = d[3 * c] * rv[0] + d[3 * c + 1] * rv[1] + d[3 * c + 2] * rv[2];
+      z[3 * i + c] = zc;
+      srz += rv[c] * zc;
+      srr += rv[c] * rv[c];
+    }
+  }
+  srz = block_sum(srz);
+  srr = block_sum(srr);
+  if (threadIdx.x == 0) {
+    pz[blockIdx.x] = srz;
+    pr[blockIdx.x] = srr;
+  }
+  if (!last_block(ticket)) return;
+  const double rz = sum_parts_l2(pz, gridDim.x);
+  const double rr = sum_parts_l2(pr, gridDim.x);
+  if (threadIdx.x == 0) {
+    st->beta = rz / st->rz;
+    st->rz = rz;
+    st->rr = rr;
+    st->it += 1;
+    st->done = !(sqrt(rr) > st->tol * sqrt(st->bb)) || st->it >= st->max_it;
+    *ticket = 0;
+  }
+}
+// p = z + beta p
+__global__ void k_cg_next(double* __restrict__ p, const double* __restrict__ z, int64_t n, const CgState* st) {
+  if (st->done) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = z[i] + st->beta * p[i];
 }
 
 __global__ void k_axpy_pos(const double* __restrict__ X, const double* __restrict__ P, double a, int64_t n,
@@ -896,8 +1149,10 @@ struct WalkArgs {
   double pad, dhat2, s;
   int4* pt;
   int4* ee;
-  int* cnt;  // [0] point-face contacts, [1] edge-edge contacts, [2] stack overflow
+  int* cnt;  // [0] point-face contacts, [1] edge-edge contacts, [2] stack overflow, [3] face pairs
   int cap;
+  int2* fpair;  // face pairs whose boxes meet
+  int fcap;
   unsigned long long* step;  // bits of the smallest CCD step (non-negative doubles order like their bits)
 };
 
@@ -998,50 +1253,85 @@ __device__ void on_ee(const WalkArgs& a, const int* e1, const int* e2) {
   }
 }
 
-// the primitive pairs of faces t and u whose primitives the two faces own
-__device__ void face_pair(const WalkArgs& a, int t, int u) {
-  const int ft[3] = {a.F[3 * t], a.F[3 * t + 1], a.F[3 * t + 2]};
-  const int fu[3] = {a.F[3 * u], a.F[3 * u + 1], a.F[3 * u + 2]};
-  for (int c = 0; c < 3; c++) {
-    if (a.vown[ft[c]] == t) on_pt(a, ft[c], fu);
-    if (a.vown[fu[c]] == u) on_pt(a, fu[c], ft);
+// Slot s of face pair (t, u): 0-2 the vertex of corner s of t against face u,
+// 3-5 the vertex of corner s - 3 of u against face t, 6-14 edge (s - 6) / 3
+// of t against edge (s - 6) % 3 of u; a slot counts only when the faces own
+// its primitives, so every primitive pair is tested once.
+constexpr int PAIR_SLOTS = 15;
+__device__ void pair_slot(const WalkArgs& a, int t, int u, int slot) {
+  if (slot < 6) {
+    const int f = slot < 3 ? t : u, g = slot < 3 ? u : t;
+    const int v = a.F[3 * f + slot % 3];
+    if (a.vown[v] != f) return;
+    const int fg[3] = {a.F[3 * g], a.F[3 * g + 1], a.F[3 * g + 2]};
+    on_pt(a, v, fg);
+    return;
   }
-  for (int c = 0; c < 3; c++) {
-    if (!a.hown[3 * t + c]) continue;
-    const int e1[2] = {ft[c], ft[(c + 1) % 3]};
-    for (int d = 0; d < 3; d++) {
-      if (!a.hown[3 * u + d]) continue;
-      const int e2[2] = {fu[d], fu[(d + 1) % 3]};
-      on_ee(a, e1, e2);
-    }
+  const int c = (slot - 6) / 3, d = (slot - 6) % 3;
+  if (!a.hown[3 * t + c] || !a.hown[3 * u + d]) return;
+  const int e1[2] = {a.F[3 * t + c], a.F[3 * t + (c + 1) % 3]};
+  const int e2[2] = {a.F[3 * u + d], a.F[3 * u + (d + 1) % 3]};
+  on_ee(a, e1, e2);
+}
+
+// every (face pair, slot) of the collected pairs, over a grid of any size
+__global__ __launch_bounds__(256) void k_pair_slots(WalkArgs a) {
+  const int64_t n = (int64_t)min(a.cnt[3], a.fcap) * PAIR_SLOTS;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int f = (int)(i / PAIR_SLOTS), slot = (int)(i - (int64_t)f * PAIR_SLOTS);
+    const int2 pr = a.fpair[f];
+    pair_slot(a, pr.x, pr.y, slot);
   }
 }
 
-// one thread per face: every later face (larger id) whose box meets its box
-__global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.nf) return;
+__device__ __forceinline__ void emit_pair(const WalkArgs& a, int t, int u) {
+  const int k = atomicAdd(&a.cnt[3], 1);
+  if (k < a.fcap) a.fpair[k] = make_int2(t, u);
+}
+
+// One thread per leaf slot i (faces in Morton order, so a wave walks nearby
+// parts of the tree): every face in a later slot whose box meets this face's
+// box, each face pair once.  The walk keeps no stack in memory: per level, the
+// children still to visit are four bits of one 64-bit mask (levels below 14),
+// and backtracking goes to the deepest level with a bit left, whose node is
+// an ancestor of the current one (parent of node k is (k - 1) / 4).  Children
+// whose leaves all come at or before slot i are skipped: child c of node k at
+// level L holds slots [(4 k' + c) 4^(D-L-1), (4 k' + c + 1) 4^(D-L-1)), k' its
+// index within the level.
+__device__ __forceinline__ int later_mask(int node, int L, int D, int i) {
+  const int64_t k = node - ((((int64_t)1) << (2 * L)) - 1) / 3;
+  const int sh = 2 * (D - L - 1);
+  int m = 0;
+  for (int c = 0; c < 4; c++) m |= (((4 * k + c + 1) << sh) > (int64_t)i + 1) << c;
+  return m;
+}
+
+__global__ __launch_bounds__(256) void k_walk(WalkArgs a, const int* __restrict__ sorted) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.nf) return;
+  const int t = sorted[i];
   float b[6];
   for (int k = 0; k < 6; k++) b[k] = a.box[6 * (int64_t)t + k];
-  int stack[WALK_STACK];
-  int sp = 0;
-  stack[sp++] = 0;
-  while (sp > 0) {
-    const int ent = stack[--sp];
-    const int node = ent & ((1 << 27) - 1), L = ent >> 27;
+  int node = 0, L = 0;
+  uint64_t pend = 0;
+  for (;;) {
     const BvhNode nd = a.nodes[node];
-    const int m = child_hits(nd, b);
+    const int m = child_hits(nd, b) & later_mask(node, L, a.D, i);
     if (L == a.D - 1) {
       const int lf[4] = {nd.leaf.x, nd.leaf.y, nd.leaf.z, nd.leaf.w};
       for (int c = 0; c < 4; c++)
-        if (((m >> c) & 1) && lf[c] > t) face_pair(a, t, lf[c]);
+        if ((m >> c) & 1) emit_pair(a, t, lf[c]);
     } else {
-      for (int c = 0; c < 4; c++) {
-        if (!((m >> c) & 1)) continue;
-        if (sp < WALK_STACK) stack[sp++] = (4 * node + 1 + c) | ((L + 1) << 27);
-        else atomicOr(&a.cnt[2], 1);
-      }
+      pend |= (uint64_t)m << (4 * L);
     }
+    if (!pend) break;
+    const int Lp = (63 - __clzll((long long)pend)) >> 2;
+    const int c = __ffs((int)((pend >> (4 * Lp)) & 15)) - 1;
+    pend &= ~(1ull << (4 * Lp + c));
+    int anc = node;
+    for (int l = L; l > Lp; l--) anc = (anc - 1) >> 2;
+    node = 4 * anc + 1 + c;
+    L = Lp + 1;
   }
 }
 
@@ -1049,7 +1339,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a) {
 __global__ void k_walk_small(WalkArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0)
     for (int t = 0; t < a.nf; t++)
-      for (int u = t + 1; u < a.nf; u++) face_pair(a, t, u);
+      for (int u = t + 1; u < a.nf; u++) emit_pair(a, t, u);
 }
 
 // squared distance from q to a float box (a lower bound for its triangles)
@@ -1195,10 +1485,16 @@ struct Projection {
   int* m2s_ids;
   int4 *pt = nullptr, *ee = nullptr;
   int cap = 0, npt = 0, nee = 0;
+  int2* fpair = nullptr;
+  int fcap = 0;
   int* cnt;
   Elems E[K_KINDS];
   double *grad, *Dblk, *Dinv, *cx, *cr, *cz, *cp, *cAp, *part, *part2, *sums;
   CgState* cg;
+  int *rowptr = nullptr, *bcol = nullptr;
+  double* bval = nullptr;
+  double* evsum;
+  int* evcnt;
   unsigned long long* stepbits;
   int* err;
 
@@ -1265,6 +1561,8 @@ struct Projection {
     part2 = ws.get<double>("pj.part2", sum_blocks(3 * (int64_t)nv));
     sums = ws.get<double>("pj.sums", 8);
     cg = ws.get<CgState>("pj.cg", 1);
+    evsum = ws.get<double>("pj.evsum", 10);  // 8 sums, then the 4 counts
+    evcnt = reinterpret_cast<int*>(evsum + 8);
     stepbits = ws.get<unsigned long long>("pj.step", 1);
     // element sets that do not change
     E[K_M2S].ids = m2s_ids;
@@ -1287,6 +1585,7 @@ struct Projection {
     for (int k = 0; k < K_KINDS; k++)
       if (k < K_PT) E[k].val = ws.get<double>(vn[k], std::max(E[k].n, 1));
     grow_contacts(std::max(4096, 2 * nf));
+    grow_pairs(std::max(1 << 16, 32 * nf));
     check_launch();
   }
 
@@ -1330,30 +1629,17 @@ struct Projection {
     a.cnt = cnt;
     a.cap = cap;
     a.step = stepbits;
-    if (nf >= 2) hipLaunchKernelGGL(k_walk, dim3(nblk(nf)), dim3(256), 0, s, a);
+    a.fpair = fpair;
+    a.fcap = fcap;
+    if (nf >= 2) hipLaunchKernelGGL(k_walk, dim3(nblk(nf)), dim3(256), 0, s, a, b.sorted);
     else hipLaunchKernelGGL(k_walk_small, dim3(1), dim3(1), 0, s, a);
+    hipLaunchKernelGGL(k_pair_slots, dim3(1024), dim3(256), 0, s, a);
     check_launch();
   }
 
-  // contact pairs at X (point-face and edge-edge pairs closer than dhat)
-  void contacts(const double* X) {
-    for (;;) {
-      PAMO_HIP(hipMemsetAsync(cnt, 0, 4 * sizeof(int), s));
-      walk(X, nullptr, o.dhat);
-      int h[3];
-      read(s, h, cnt, 3);
-      if (h[2]) throw std::runtime_error("contact walk: traversal stack overflow");
-      if (h[0] <= cap && h[1] <= cap) {
-        npt = h[0];
-        nee = h[1];
-        break;
-      }
-      grow_contacts(std::max(h[0], h[1]) + std::max(h[0], h[1]) / 2);
-    }
-    E[K_PT].ids = (const int*)pt;
-    E[K_PT].n = npt;
-    E[K_EE].ids = (const int*)ee;
-    E[K_EE].n = nee;
+  void grow_pairs(int c) {
+    fcap = c;
+    fpair = ws.get<int2>("pj.fpair", fcap);
   }
 
   // the additive-CCD step along P from X (at most 1)
@@ -1362,48 +1648,92 @@ struct Projection {
     unsigned long long bits;
     __builtin_memcpy(&bits, &one, 8);
     PAMO_HIP(hipMemcpyAsync(stepbits, &bits, 8, hipMemcpyHostToDevice, s));
-    PAMO_HIP(hipMemsetAsync(cnt, 0, 4 * sizeof(int), s));
-    walk(X, P, 0.0);
-    int h[3];
-    read(s, h, cnt, 3);
-    if (h[2]) throw std::runtime_error("CCD walk: traversal stack overflow");
+    for (;;) {
+      PAMO_HIP(hipMemsetAsync(cnt, 0, 4 * sizeof(int), s));
+      walk(X, P, 0.0);
+      int h[4];
+      read(s, h, cnt, 4);
+      if (h[3] <= fcap) break;
+      grow_pairs(h[3] + h[3] / 2);
+      PAMO_HIP(hipMemcpyAsync(stepbits, &bits, 8, hipMemcpyHostToDevice, s));
+    }
     read(s, &bits, stepbits, 1);
     double t;
     __builtin_memcpy(&t, &bits, 8);
     return t;
   }
 
-  template <int K>
-  double sum_values(const double* X) {
-    Elems& e = E[K];
-    if (e.n == 0) return 0.0;
-    hipLaunchKernelGGL(k_elem_value<K>, dim3(nblk(e.n)), dim3(256), 0, s, e, X);
-    const unsigned nb = sum_blocks(e.n);
-    double* vp = ws.get<double>("pj.vpart", nb);
-    hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(SUM_T), 0, s, (const double*)e.val, (const double*)nullptr,
-                       (int64_t)e.n, vp, (const int*)nullptr);
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(SUM_T), 0, s, (const double*)vp, (int)nb, sums);
-    double v;
-    read(s, &v, sums, 1);
-    return v;
+  // the kinds' launch ranges (contacts sized by their capacity)
+  // the kinds' launch ranges, one thread per element (contacts sized by their
+  // capacity)
+  KindRanges ranges(bool contacts_by_cap) {
+    KindRanges r{};
+    for (int k = 0; k < K_KINDS; k++) r.E[k] = E[k];
+    if (contacts_by_cap) r.E[K_PT].n = r.E[K_EE].n = cap;
+    r.s0 = s0;
+    r.tg = targets;
+    r.sval = ws.get<double>("pj.s2mval", nv);
+    r.nv = nv;
+    r.cnt = cnt;
+    const int n[NSEG] = {nv, r.E[K_M2S].n, r.E[K_EL].n, r.E[K_BEND].n, r.E[K_PT].n, r.E[K_EE].n};
+    r.blk[0] = 0;
+    for (int k = 0; k < NSEG; k++) r.blk[k + 1] = r.blk[k] + (n[k] > 0 ? (int)nblk(n[k]) : 0);
+    return r;
   }
 
-  // the five terms (unweighted) and B at X; contacts are detected at X first
+  // the five terms (unweighted) and B at X; contacts are detected at X first.
+  // One read-back: the sums and the contact counts together.
   void energy(const double* X, double* parts) {
-    contacts(X);
-    double* sv = ws.get<double>("pj.s2mval", nv);
-    hipLaunchKernelGGL(k_s2m_value, dim3(nblk(nv)), dim3(256), 0, s, X, (const double*)targets, (const double*)s0, nv,
-                       sv);
-    const unsigned nb = sum_blocks(nv);
-    hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(SUM_T), 0, s, (const double*)sv, (const double*)nullptr,
-                       (int64_t)nv, part, (const int*)nullptr);
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(SUM_T), 0, s, (const double*)part, (int)nb, sums);
-    read(s, &parts[0], sums, 1);
-    parts[1] = area_in / (double)std::max(m, 1) * sum_values<K_M2S>(X);
-    parts[2] = sum_values<K_EL>(X);
-    parts[3] = sum_values<K_BEND>(X);
-    parts[4] = sum_values<K_PT>(X) + sum_values<K_EE>(X);
-    parts[5] = o.k_dis * (parts[0] + parts[1]) + o.k_elas * parts[2] + o.k_bend * parts[3] + o.k_bar * parts[4];
+    for (;;) {
+      PAMO_HIP(hipMemsetAsync(cnt, 0, 4 * sizeof(int), s));
+      walk(X, nullptr, o.dhat);
+      E[K_PT].ids = (const int*)pt;
+      E[K_EE].ids = (const int*)ee;
+      KindRanges r = ranges(true);
+      hipLaunchKernelGGL(k_values_all, dim3(r.blk[NSEG]), dim3(256), 0, s, r, X);
+      SegSums ss{};
+      const int n[NSEG] = {nv, E[K_M2S].n, E[K_EL].n, E[K_BEND].n, cap, cap};
+      const double* v[NSEG] = {r.sval, E[K_M2S].val, E[K_EL].val, E[K_BEND].val, E[K_PT].val, E[K_EE].val};
+      int most = 1;
+      for (int k = 0; k < NSEG; k++) {
+        ss.v[k] = v[k];
+        ss.n[k] = n[k];
+        most = std::max(most, n[k]);
+      }
+      const unsigned nb = sum_blocks(most);
+      ss.cnt = cnt;
+      ss.stride = (int)nb;
+      ss.part = ws.get<double>("pj.segpart", (int64_t)NSEG * nb);
+      hipLaunchKernelGGL(k_sum_seg, dim3(nb, NSEG), dim3(SUM_T), 0, s, ss);
+      hipLaunchKernelGGL(k_sum_seg_final, dim3(NSEG), dim3(SUM_T), 0, s, (const double*)ss.part, (int)nb, (int)nb,
+                         evsum);
+      PAMO_HIP(hipMemcpyAsync(evcnt, cnt, 4 * sizeof(int), hipMemcpyDeviceToDevice, s));
+      check_launch();
+      struct {
+        double sum[8];
+        int cnt[4];
+      } h;
+      read(s, reinterpret_cast<char*>(&h), reinterpret_cast<const char*>(evsum), sizeof(h));
+      if (h.cnt[3] > fcap) {
+        grow_pairs(h.cnt[3] + h.cnt[3] / 2);
+        continue;
+      }
+      if (h.cnt[0] > cap || h.cnt[1] > cap) {
+        grow_contacts(std::max(h.cnt[0], h.cnt[1]) + std::max(h.cnt[0], h.cnt[1]) / 2);
+        continue;
+      }
+      npt = h.cnt[0];
+      nee = h.cnt[1];
+      E[K_PT].n = npt;
+      E[K_EE].n = nee;
+      parts[0] = h.sum[0];
+      parts[1] = area_in / (double)std::max(m, 1) * h.sum[1 + K_M2S];
+      parts[2] = h.sum[1 + K_EL];
+      parts[3] = h.sum[1 + K_BEND];
+      parts[4] = h.sum[1 + K_PT] + h.sum[1 + K_EE];
+      parts[5] = o.k_dis * (parts[0] + parts[1]) + o.k_elas * parts[2] + o.k_bend * parts[3] + o.k_bar * parts[4];
+      return;
+    }
   }
 
   template <int K>
@@ -1414,9 +1744,8 @@ struct Projection {
     e.H = ws.get<double>(hn, (int64_t)N * N * e.n);
     e.g = ws.get<double>(gn, (int64_t)N * e.n);
     hipLaunchKernelGGL(k_elem_deriv<K>, dim3(nblk((int64_t)KT<K>::NP * e.n)), dim3(256), 0, s, e, X);
-    hipLaunchKernelGGL(k_elem_psd<N>, dim3(nblk(e.n, 64)), dim3(64), 0, s, e.H, e.n);
+    hipLaunchKernelGGL(k_elem_psd<N>, dim3(nblk((int64_t)PSD_G * e.n)), dim3(256), 0, s, e.H, e.n);
     hipLaunchKernelGGL(k_elem_grad<K>, dim3(nblk(e.n)), dim3(256), 0, s, e, grad);
-    hipLaunchKernelGGL(k_elem_diag<K>, dim3(nblk(e.n)), dim3(256), 0, s, e, Dblk);
     check_launch();
   }
 
@@ -1430,36 +1759,71 @@ struct Projection {
     derivs_of<K_BEND>(X, "pj.h2", "pj.g2");
     derivs_of<K_PT>(X, "pj.h3", "pj.g3");
     derivs_of<K_EE>(X, "pj.h4", "pj.g4");
+    assemble();
+    hipLaunchKernelGGL(k_bsr_diag, dim3(nblk(nv)), dim3(256), 0, s, (const int*)rowptr, (const int*)bcol,
+                       (const double*)bval, nv, Dblk);
     hipLaunchKernelGGL(k_block_inv, dim3(nblk(nv)), dim3(256), 0, s, (const double*)Dblk, nv, Dinv);
     check_launch();
   }
 
-  template <int K>
-  void matvec_of(const double* v, double* out, const int* done) {
-    const Elems& e = E[K];
-    if (e.n == 0) return;
-    hipLaunchKernelGGL(k_elem_matvec<K>, dim3(nblk(e.n)), dim3(256), 0, s, e, v, out, done);
-  }
-  void matvec(const double* v, double* out, const int* done) {
-    hipLaunchKernelGGL(k_s2m_matvec, dim3(nblk(nv)), dim3(256), 0, s, (const double*)s0, nv, o.k_dis, v, out, done);
-    matvec_of<K_M2S>(v, out, done);
-    matvec_of<K_EL>(v, out, done);
-    matvec_of<K_BEND>(v, out, done);
-    matvec_of<K_PT>(v, out, done);
-    matvec_of<K_EE>(v, out, done);
+  // the block-sparse Hessian from the projected element Hessians
+  void assemble() {
+    EntryRanges r{};
+    for (int k = 0; k < K_KINDS; k++) r.E[k] = E[k];
+    r.s0 = s0;
+    r.k2 = 2.0 * o.k_dis;
+    r.nv = nv;
+    const int64_t per[NSEG] = {(int64_t)nv, 9LL * E[K_M2S].n, 9LL * E[K_EL].n, 16LL * E[K_BEND].n,
+                               16LL * E[K_PT].n, 16LL * E[K_EE].n};
+    r.off[0] = 0;
+    for (int k = 0; k < NSEG; k++) r.off[k + 1] = r.off[k] + per[k];
+    const int64_t n = r.off[NSEG];
+    if (n > INT32_MAX) throw std::runtime_error("Hessian pattern too large");
+    int bits = 1;
+    while ((1 << bits) < nv) bits++;
+    uint64_t* keys = ws.get<uint64_t>("pj.bkeys", n);
+    int* vals = ws.get<int>("pj.bvals", n);
+    uint8_t* fl = ws.get<uint8_t>("pj.bflags", n);
+    int* excl = ws.get<int>("pj.bexcl", n);
+    int* ustart = ws.get<int>("pj.bstart", n);
+    int* nslot = ws.get<int>("pj.bnslot", 1);
+    rowptr = ws.get<int>("pj.browptr", (int64_t)nv + 1);
+    bcol = ws.get<int>("pj.bcol", n);
+    bval = ws.get<double>("pj.bval", 9 * n);
+    hipLaunchKernelGGL(k_bsr_keys, dim3(nblk(n)), dim3(256), 0, s, r, bits, keys, vals);
+    radix_sort_u64(ws, s, keys, vals, n, 2 * bits);
+    hipLaunchKernelGGL(k_bsr_flags, dim3(nblk(n)), dim3(256), 0, s, (const uint64_t*)keys, n, fl);
+    run_flag_scan(ws, s, fl, n, excl, nslot);
+    hipLaunchKernelGGL(k_bsr_starts, dim3(nblk(n)), dim3(256), 0, s, (const uint8_t*)fl, (const int*)excl, n, ustart);
+    hipLaunchKernelGGL(k_bsr_fill, dim3(nblk(n)), dim3(256), 0, s, r, (const uint64_t*)keys, (const int*)vals,
+                       (const int*)ustart, (const int*)nslot, n, bits, rowptr, bcol, bval);
     check_launch();
   }
 
-  // p from H p = -grad (after derivs); returns the CG iterations
+  // out = H v (after derivs)
+  void matvec(const double* v, double* out, const int* done) {
+    hipLaunchKernelGGL(k_bsr_spmv, dim3(nblk(3 * (int64_t)nv)), dim3(256), 0, s, (const int*)rowptr, (const int*)bcol,
+                       (const double*)bval, nv, v, out, done);
+    check_launch();
+  }
+
+  // p from H p = -grad (after derivs); returns the CG iterations.  Four
+  // launches per iteration; the host looks at the stopping flag every 8.
   int solve(double* dir) {
     const int64_t n3 = 3 * (int64_t)nv;
     const unsigned nb = sum_blocks(n3);
+    const unsigned nbv = nblk(nv, SUM_T);
+    double* pz = ws.get<double>("pj.cgpz", nbv);
+    double* pr = ws.get<double>("pj.cgpr", nbv);
+    double* pp = ws.get<double>("pj.cgpp", nb);
+    unsigned* ticket = ws.get<unsigned>("pj.ticket", 2);
+    PAMO_HIP(hipMemsetAsync(ticket, 0, 2 * sizeof(unsigned), s));
     CgState h{};
     h.tol = o.cg_tol;
     h.max_it = o.cg_max;
     PAMO_HIP(hipMemcpyAsync(cg, &h, sizeof(h), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_cg_init, dim3(nblk(nv)), dim3(256), 0, s, (const double*)grad, (const double*)Dinv, nv, cx, cr,
-                       cz, cp);
+                       cz, cp, cAp);
     hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(SUM_T), 0, s, (const double*)cr, (const double*)cr, n3, part,
                        (const int*)nullptr);
     hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(SUM_T), 0, s, (const double*)cr, (const double*)cz, n3, part2,
@@ -1469,17 +1833,12 @@ struct Projection {
     for (;;) {
       for (int k = 0; k < 8; k++) {
         matvec(cp, cAp, done);
-        hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(SUM_T), 0, s, (const double*)cp, (const double*)cAp, n3, part,
-                           done);
-        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(SUM_T), 0, s, (const double*)part, (int)nb, cg);
-        hipLaunchKernelGGL(k_cg_update, dim3(nblk(nv)), dim3(256), 0, s, cx, cr, cz, (const double*)cp,
-                           (const double*)cAp, (const double*)Dinv, nv, (const CgState*)cg);
-        hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(SUM_T), 0, s, (const double*)cr, (const double*)cz, n3, part2,
-                           done);
-        hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(SUM_T), 0, s, (const double*)cr, (const double*)cr, n3, part,
-                           done);
-        hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(SUM_T), 0, s, (const double*)part2, (const double*)part, (int)nb, cg);
-        hipLaunchKernelGGL(k_cg_p, dim3(nblk(n3)), dim3(256), 0, s, cp, (const double*)cz, n3, (const CgState*)cg);
+        hipLaunchKernelGGL(k_cg_pap, dim3(nb), dim3(SUM_T), 0, s, (const double*)cp, (const double*)cAp, n3, pp,
+                           ticket, cg);
+        hipLaunchKernelGGL(k_cg_step, dim3(nbv), dim3(SUM_T), 0, s, cx, cr, cz, (const double*)cp, (const double*)cAp,
+                           (const double*)Dinv, nv, pz, pr, ticket + 1, cg);
+        hipLaunchKernelGGL(k_cg_next, dim3(nblk(n3)), dim3(256), 0, s, cp, (const double*)cz, n3,
+                           (const CgState*)cg);
       }
       check_launch();
       read(s, &h, cg, 1);
@@ -1584,12 +1943,25 @@ void project_run(Workspace& ws, hipStream_t s, const double* X0, int nv, const i
   pamo_project_stats st{};
   double parts[6], trial[6];
   double B0 = 0.0;
-  bool have = false;  // contacts and B0 are those of X
+  bool have = false;     // contacts and B0 are those of X
+  bool stalled = false;  // this window's targets gave no decrease: X stays until the next refresh
   for (int t = 0; t < o.iterations; t++) {
-    if (o.refresh > 0 && t % o.refresh == 0) {
+    if (t % o.refresh == 0) {
       project_targets(ws, s, X, nv, F, nf, Vin, nvin, Fin, nfin, Y, m, P.targets, P.tri);
       P.use_targets(P.targets, P.tri);
       have = false;
+      stalled = false;
+    }
+    st.iterations++;
+    if (stalled) {
+      if (log) {
+        double* r = log + 8 * (int64_t)t;
+        for (int k = 0; k < 8; k++) r[k] = 0.0;
+        r[0] = B0;
+        r[5] = (double)P.npt;
+        r[6] = (double)P.nee;
+      }
+      continue;
     }
     if (!have) {
       P.energy(X, parts);
@@ -1599,14 +1971,17 @@ void project_run(Workspace& ws, hipStream_t s, const double* X0, int nv, const i
     st.max_pt = std::max<int64_t>(st.max_pt, P.npt);
     st.max_ee = std::max<int64_t>(st.max_ee, P.nee);
     const int64_t npt = P.npt, nee = P.nee;
+    const double Bstart = B0;
     P.derivs(X);
     const double gnorm = std::sqrt(dot_dev(ws, s, P.grad, P.grad, n3));
     const int it = P.solve(dir);
+    const double pnorm = std::sqrt(dot_dev(ws, s, dir, dir, n3));
     const double accd = P.ccd(X, dir);
     double alpha = std::min(1.0, accd);
     bool moved = false;
     int h = 0;
     for (h = 0; h < o.ls_max; h++) {
+      if (alpha * pnorm < LS_MIN_STEP) break;
       hipLaunchKernelGGL(k_axpy_pos, dim3(nblk(n3)), dim3(256), 0, s, (const double*)X, (const double*)dir, alpha, n3,
                          Xt);
       check_launch();
@@ -1619,15 +1994,15 @@ void project_run(Workspace& ws, hipStream_t s, const double* X0, int nv, const i
       }
       alpha *= 0.5;
     }
-    if (!moved) h = std::max(o.ls_max - 1, 0);
+    if (!moved && h >= o.ls_max) h = o.ls_max - 1;
     have = moved;
-    st.iterations++;
+    stalled = !moved;
     st.cg_iters += it;
     st.halvings += h;
     st.stalled += !moved;
     if (log) {
       double* r = log + 8 * (int64_t)t;
-      r[0] = parts[5];
+      r[0] = Bstart;
       r[1] = accd;
       r[2] = moved ? alpha : 0.0;
       r[3] = h;
@@ -1636,7 +2011,6 @@ void project_run(Workspace& ws, hipStream_t s, const double* X0, int nv, const i
       r[6] = (double)nee;
       r[7] = gnorm;
     }
-    parts[5] = B0;
   }
   st.B_last = B0;
   PAMO_HIP(hipStreamSynchronize(s));
