@@ -386,13 +386,21 @@ __device__ __forceinline__ constexpr int ut(int i, int j) {
 }
 
 // Sixteen lanes per matrix: lane r holds row r of the matrix and row r of the
-// accumulated rotation Q (so Q J and the column half of J^T A J are local);
-// the row half exchanges rows p and q between their two lanes by shuffles.
-// The final PSD part sum_k max(lambda_k, 0) q_k q_k^T is written row by row.
+// accumulated rotation Q.  Parallel cyclic Jacobi (round-robin ordering, as
+// in Golub and Van Loan, Sec. 8.5.5): a sweep is M - 1 steps (M = N rounded up
+// to even), each applying M / 2 rotations on disjoint index pairs at once, so
+// one exchange of rows between partner lanes serves them all; columns and Q
+// rotate locally.  Step st pairs M - 1 with st and st + k with st - k (mod
+// M - 1); an index >= N is a dummy whose pair does not rotate.  The final PSD
+// part sum_k max(lambda_k, 0) q_k q_k^T is written row by row.
 constexpr int PSD_G = 16;
+__host__ __device__ constexpr int rr_a(int M, int st, int k) { return k == 0 ? M - 1 : (st + k) % (M - 1); }
+__host__ __device__ constexpr int rr_b(int M, int st, int k) { return k == 0 ? st : (st - k + (M - 1)) % (M - 1); }
+
 template <int N>
 __global__ __launch_bounds__(256) void k_elem_psd(double* __restrict__ H, int n) {
   static_assert(N <= PSD_G, "one lane per row");
+  constexpr int M = N + (N & 1), R = M - 1;
   const int lane = threadIdx.x & (PSD_G - 1);
   const int64_t grp = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / PSD_G;
   if (grp >= n) return;  // whole groups leave together
@@ -418,40 +426,65 @@ __global__ __launch_bounds__(256) void k_elem_psd(double* __restrict__ H, int n)
     }
     if (!(off > 1e-32 * all)) break;
 #pragma unroll
-    for (int p = 0; p < N - 1; p++) {
+    for (int st = 0; st < R; st++) {
+      const int partner = lane == M - 1 ? st : (lane == st ? M - 1 : (lane < R ? (2 * st - lane + 2 * R) % R : lane));
+      const bool act = row && partner < N && partner != lane;
+      const bool isp = lane < partner;
+      double mydiag = 0.0, myoff = 0.0;
 #pragma unroll
-      for (int qq = p + 1; qq < N; qq++) {
-        const double apq = __shfl(a[qq], p, PSD_G);
-        const double app = __shfl(a[p], p, PSD_G);
-        const double aqq = __shfl(a[qq], qq, PSD_G);
-        if (apq != 0.0) {
-          const double th = (aqq - app) / (2.0 * apq);
-          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-          const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-          // columns p and qq of this lane's row (A J)
-          const double arp = a[p], arq = a[qq];
-          a[p] = c * arp - s * arq;
-          a[qq] = s * arp + c * arq;
-          // rows p and qq (J^T (A J)) from the partner's row
-          const int partner = lane == p ? qq : (lane == qq ? p : lane);
-          double o[N];
+      for (int k = 0; k < N; k++) {
+        mydiag = k == lane ? a[k] : mydiag;
+        myoff = k == partner ? a[k] : myoff;
+      }
+      const double pdiag = __shfl(mydiag, partner, PSD_G);
+      // the rotation of this lane's pair, computed on its smaller lane p
+      double c = 1.0, sn = 0.0, t = 0.0, app = mydiag, aqq = pdiag, apq = myoff;
+      if (act && isp && apq != 0.0) {
+        const double th = (aqq - app) / (2.0 * apq);
+        t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        c = 1.0 / sqrt(t * t + 1.0);
+        sn = t * c;
+      }
+      {
+        const double c2 = __shfl(c, partner, PSD_G), s2 = __shfl(sn, partner, PSD_G), t2 = __shfl(t, partner, PSD_G);
+        const double app2 = __shfl(app, partner, PSD_G), aqq2 = __shfl(aqq, partner, PSD_G);
+        const double apq2 = __shfl(apq, partner, PSD_G);
+        if (!isp) {
+          c = c2;
+          sn = s2;
+          t = t2;
+          app = app2;
+          aqq = aqq2;
+          apq = apq2;
+        }
+      }
+      // columns of every pair (A J) and rows of Q, with each pair's rotation
 #pragma unroll
-          for (int k = 0; k < N; k++) o[k] = __shfl(a[k], partner, PSD_G);
-          if (lane == p) {
+      for (int k = 0; k < M / 2; k++) {
+        const int pa = rr_a(M, st, k), pb = rr_b(M, st, k);
+        const int pp = pa < pb ? pa : pb, qq = pa < pb ? pb : pa;
+        if (qq >= N) continue;
+        const double ck = __shfl(c, pp, PSD_G), sk = __shfl(sn, pp, PSD_G);
+        const double arp = a[pp], arq = a[qq];
+        a[pp] = ck * arp - sk * arq;
+        a[qq] = sk * arp + ck * arq;
+        const double qrp = q[pp], qrq = q[qq];
+        q[pp] = ck * qrp - sk * qrq;
+        q[qq] = sk * qrp + ck * qrq;
+      }
+      // rows (J^T (A J)) from the partner's row
+      double o[N];
 #pragma unroll
-            for (int k = 0; k < N; k++) a[k] = c * a[k] - s * o[k];
-            a[p] = app - t * apq;
-            a[qq] = 0.0;
-          } else if (lane == qq) {
+      for (int k = 0; k < N; k++) o[k] = __shfl(a[k], partner, PSD_G);
+      if (act) {
+        if (isp) {
 #pragma unroll
-            for (int k = 0; k < N; k++) a[k] = s * o[k] + c * a[k];
-            a[qq] = aqq + t * apq;
-            a[p] = 0.0;
-          }
-          // Q J on this lane's row of Q
-          const double qrp = q[p], qrq = q[qq];
-          q[p] = c * qrp - s * qrq;
-          q[qq] = s * qrp + c * qrq;
+          for (int k = 0; k < N; k++)
+            a[k] = k == lane ? app - t * apq : (k == partner ? 0.0 : c * a[k] - sn * o[k]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < N; k++)
+            a[k] = k == lane ? aqq + t * apq : (k == partner ? 0.0 : sn * o[k] + c * a[k]);
         }
       }
     }
