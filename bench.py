@@ -297,9 +297,10 @@ def safe_projection(native, torch, dev, Vd, Fd, Vs, Fs, reps=2, m=16384):
 def sharp_feature(native, torch, dev, steps):
     """Crease sphere (icosphere refined 9x, 5,242,880 faces, radius
     1 + 0.03|sin 12 theta||sin 9 phi| + 0.002 N(0,1)) to 0.1%, in one batch with 32
-    bumpy tori of 20k-100k faces to 1%: plain and learned batched forms, and the
+    bumpy tori of 20k-100k faces to 1%: plain and learned batched forms, the
     plain form with the link/flip checks run on every edge before the selection
-    (the part of the learned form's gain that needs no network)."""
+    (the part of the learned form's gain that needs no network), and the
+    network on top of that pre-filter."""
     from paper_2509_05595_amd import learn, meshgen
     meshes = [meshgen.crease_sphere(9, 5)] + [meshgen.make_spec(sp) for sp in meshgen.tori_specs()]
     targets = [len(meshes[0][1]) // 1000] + [len(F) // 100 for _, F in meshes[1:]]
@@ -310,11 +311,12 @@ def sharp_feature(native, torch, dev, steps):
     model = learn.load_model() if os.path.exists(learn.MODEL_PATH) else None
     out = {"workload": f"crease sphere 5,242,880 faces -> 0.1% with 32 tori ({nf_total} faces in total), "
                        f"one pamo_simplify_batch call"}
-    for mode in ("plain", "learned", "prefilter"):
-        if mode == "learned" and model is None:
+    for mode in ("plain", "learned", "prefilter", "learned_prefilter"):
+        learned = mode in ("learned", "learned_prefilter")
+        if learned and model is None:
             continue
-        ctx.set_mlp(model if mode == "learned" else None)
-        ctx.set_options(native.default_options(learned=int(mode == "learned"), prefilter=int(mode == "prefilter")))
+        ctx.set_mlp(model if learned else None)
+        ctx.set_options(native.default_options(learned=int(learned), prefilter=int("prefilter" in mode)))
         res = ctx.simplify_batch(dm, targets)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -139,6 +139,27 @@ def test_learned_run_bitwise(ctx, name, target, model):
     assert st["undo_hist"] == r["stats"]["undo_hist"]
 
 
+@pytest.mark.parametrize("name,target", [("nested", 400), ("torus", 80)])
+def test_learned_with_prefilter_bitwise(ctx, name, target):
+    """The learned proposal on top of the link/flip pre-filter: the library and
+    the oracle end with the same mesh bit for bit."""
+    from paper_2509_05595_amd import native
+    V, F = MESHES[name]()
+    m = random_model(7, threshold=-2.0)
+    ctx.set_mlp(m)
+    ctx.set_options(native.default_options(learned=1, prefilter=1))
+    try:
+        Vo, Fo, st = ctx.simplify(*dev(V, F), target)
+    finally:
+        ctx.set_options(native.default_options())
+        ctx.set_mlp(None)
+    r = orc.run_learned(V, F, target, m, prefilter=1)
+    assert same(Fo.cpu().numpy(), r["F"]) and same(Vo.cpu().numpy(), r["V"])
+    assert st["demoted"] == r["demoted"] and st["fallbacks"] == r["fallbacks"]
+    for k in ("rounds", "commits", "rej_link", "rej_flip", "rej_isect", "capped", "status"):
+        assert st[k] == r["stats"][k], k
+
+
 def test_learned_run_needs_a_network(ctx):
     from paper_2509_05595_amd import native
     V, F = MESHES["noisy"]()
