@@ -306,7 +306,7 @@ pamo_status pamo_dualmc(pamo_ctx* ctx, const double* S, int32_t res, double iso,
 /* Options of the safe projection; pamo_project_defaults gives the paper's
  * values (Sec. 6.1, Sec. 6.2: k_dis 1e3, k_elas 1e-1, k_bend 1e-2, k_bar 1e2,
  * dhat 1e-3, T = 50 iterations, targets refreshed every 10) and this
- * library's choices where the paper gives none (CG tolerance 1e-8 relative
+ * library's choices where the paper gives none (CG tolerance 1e-4 relative
  * to |grad B|, at most 1000 CG iterations; additive CCD keeps 0.1 of each
  * pair's distance; at most 40 line-search halvings). */
 typedef struct {

@@ -65,7 +65,7 @@ class Options:
     dhat: float = 1e-3
     iterations: int = 50
     refresh: int = 10
-    cg_tol: float = 1e-8
+    cg_tol: float = 1e-4
     cg_max: int = 1000
     accd_s: float = 0.1
     ls_max: int = 40

@@ -1871,7 +1871,7 @@ void pamo_project_defaults(pamo_project_options* o) {
   o->k_bend = 1e-2;
   o->k_bar = 1e2;
   o->dhat = 1e-3;
-  o->cg_tol = 1e-8;
+  o->cg_tol = 1e-4;
   o->accd_s = 0.1;
   o->iterations = 50;
   o->refresh = 10;
