@@ -67,22 +67,23 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "query__noisy-icosphere-1310720f-to-1pct.md")
 
 
-def measured_traffic(phase):
-    """HBM bytes per launch of `phase` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counts), or None
-    when there is none or the kernel source changed since it was taken."""
+def measured_traffic():
+    """HBM bytes per launch of each phase from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE of the phase's own kernels, scaled by a
+    plain copy's counts); empty when there is none or a kernel source changed
+    since it was taken."""
     import hashlib
     if not os.path.exists(TRAFFIC_PROFILE):
-        return None
-    val, ok = None, False
+        return {}
+    vals, ok = {}, True
     for line in open(TRAFFIC_PROFILE):
         f = line.split()
-        if len(f) == 3 and f[0] == "traffic_bytes_per_launch" and f[1] == phase:
-            val = float(f[2])
+        if len(f) == 3 and f[0] == "traffic_bytes_per_launch":
+            vals[f[1]] = float(f[2])
         if len(f) == 3 and f[0] == "source_sha256":
             path = os.path.join(HERE, f[1])
-            ok = os.path.exists(path) and hashlib.sha256(open(path, "rb").read()).hexdigest() == f[2]
-    return val if ok else None
+            ok = ok and os.path.exists(path) and hashlib.sha256(open(path, "rb").read()).hexdigest() == f[2]
+    return vals if ok else {}
 
 
 def log(msg):
@@ -427,6 +428,7 @@ def main():
     ms_per_step = dt / args.steps * 1e3
     value = nf0 / (ms_per_step / 1e3)
     launches, kms, kbytes = prof[dominant]
+    traffic = measured_traffic()
     achieved = kbytes / (kms / 1e3) / 1e9
 
     out = {
@@ -450,7 +452,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic.get(dominant),
             "launches": launches, "avg_launch_us": kms / launches * 1e3,
             "bytes_per_launch": kbytes / launches,
         },
@@ -459,7 +461,11 @@ def main():
         # algorithmic bytes of its launches and their rate against the HBM peak
         "phases": {k: {"launches": v[0], "ms": v[1], "bytes": v[2],
                        "GBs": v[2] / (v[1] / 1e3) / 1e9 if v[1] > 0 else None,
-                       "frac": v[2] / (v[1] / 1e3) / 1e9 / HBM_PEAK_GBS if v[1] > 0 else None}
+                       "frac": v[2] / (v[1] / 1e3) / 1e9 / HBM_PEAK_GBS if v[1] > 0 else None,
+                       # counted HBM bytes per launch (rocprofv3 summary) and their rate
+                       "traffic": traffic.get(k),
+                       "traffic_frac": (traffic[k] * v[0] / (v[1] / 1e3) / 1e9 / HBM_PEAK_GBS
+                                        if k in traffic and v[1] > 0 else None)}
                    for k, v in sorted(breakdown.items(), key=lambda kv: -kv[1][1])},
     }
     tot_bytes = sum(v[2] for v in breakdown.values())

@@ -1397,24 +1397,29 @@ __device__ __forceinline__ double face_d2(const double* V, const int* F, int f, 
   return pt_dist2(q, ldX(V, F[3 * f]), ldX(V, F[3 * f + 1]), ldX(V, F[3 * f + 2]));
 }
 
-// Closest triangle of the tree's mesh to each query point: first the smallest
-// squared distance, then the smallest triangle index within the tie margin of
-// it; optionally the closest point on that triangle.
+// Closest triangle of the tree's mesh to each query point (queries taken in
+// the order `order` gives, Morton order of the points, so a wave walks nearby
+// parts of the tree): a best-first walk for the smallest squared distance,
+// then a walk for the smallest triangle index within the tie margin of it;
+// optionally the closest point on that triangle.
+__device__ __forceinline__ double tie_bound(double best) { return best * (1.0 + TIE) + TIE_ABS; }
+
 __global__ __launch_bounds__(256) void k_nearest(const BvhNode* __restrict__ nodes, int D, int ntree,
                                                  const double* __restrict__ V, const int* __restrict__ F,
-                                                 const double* __restrict__ Q, int nq, double* __restrict__ target,
-                                                 int* __restrict__ tri, int* __restrict__ err) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nq) return;
+                                                 const double* __restrict__ Q, const int* __restrict__ order, int nq,
+                                                 double* __restrict__ target, int* __restrict__ tri,
+                                                 int* __restrict__ err) {
+  const int qi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (qi >= nq) return;
+  const int i = order ? order[qi] : qi;
   const D3 q = ldX(Q, i);
   double best = INFINITY;
   int bestf = 0;
   if (ntree < 2) {
     for (int f = 0; f < ntree; f++) best = fmin(best, face_d2(V, F, f, q));
-    bestf = 0;
   } else {
     for (int pass = 0; pass < 2; pass++) {
-      const double bound0 = best * (1.0 + TIE) + TIE_ABS;
+      const double bound0 = tie_bound(best);
       int st[WALK_STACK];
       double sd[WALK_STACK];
       int sp = 0;
@@ -1423,9 +1428,8 @@ __global__ __launch_bounds__(256) void k_nearest(const BvhNode* __restrict__ nod
       while (sp > 0) {
         sp--;
         const int ent = st[sp];
-        const double nd2 = sd[sp];
         const double bound = pass == 0 ? best : bound0;
-        if (nd2 > bound) continue;
+        if (sd[sp] > bound) continue;
         const int node = ent & ((1 << 27) - 1), L = ent >> 27;
         const BvhNode nd = nodes[node];
         double cd[4];
@@ -1443,15 +1447,15 @@ __global__ __launch_bounds__(256) void k_nearest(const BvhNode* __restrict__ nod
           }
         } else {
           // push the far children first so the nearest is taken next
-          int order[4] = {0, 1, 2, 3};
+          int ord[4] = {0, 1, 2, 3};
           for (int x = 1; x < 4; x++)
-            for (int y = x; y > 0 && cd[order[y]] > cd[order[y - 1]]; y--) {
-              const int tmp = order[y];
-              order[y] = order[y - 1];
-              order[y - 1] = tmp;
+            for (int y = x; y > 0 && cd[ord[y]] > cd[ord[y - 1]]; y--) {
+              const int tmp = ord[y];
+              ord[y] = ord[y - 1];
+              ord[y - 1] = tmp;
             }
           for (int x = 0; x < 4; x++) {
-            const int c = order[x];
+            const int c = ord[x];
             if (cd[c] > bound) continue;
             if (sp < WALK_STACK) {
               st[sp] = (4 * node + 1 + c) | ((L + 1) << 27);
@@ -1488,6 +1492,28 @@ __global__ __launch_bounds__(256) void k_nearest(const BvhNode* __restrict__ nod
     target[3 * (int64_t)i + 1] = r.y;
     target[3 * (int64_t)i + 2] = r.z;
   }
+}
+
+// Morton codes of points (in [0,1]^3, 10 bits a coordinate) for the query order
+__device__ __forceinline__ uint32_t spread10(uint32_t x) {
+  x &= 1023;
+  x = (x | (x << 16)) & 0x030000FF;
+  x = (x | (x << 8)) & 0x0300F00F;
+  x = (x | (x << 4)) & 0x030C30C3;
+  x = (x | (x << 2)) & 0x09249249;
+  return x;
+}
+__global__ void k_point_codes(const double* __restrict__ P, int n, uint32_t* __restrict__ code, int* __restrict__ id) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t c3[3];
+  for (int k = 0; k < 3; k++) {
+    const double c = fmin(fmax(P[3 * (int64_t)i + k], 0.0), 1.0);
+    const int x = (int)(c * 1024.0);
+    c3[k] = (uint32_t)(x > 1023 ? 1023 : x);
+  }
+  code[i] = (spread10(c3[0]) << 2) | (spread10(c3[1]) << 1) | spread10(c3[2]);
+  id[i] = i;
 }
 
 // ------------------------------------------------------------ host side
@@ -1926,13 +1952,23 @@ void project_targets(Workspace& ws, hipStream_t s, const double* X, int nv, cons
   PAMO_HIP(hipMemsetAsync(err, 0, sizeof(int), s));
   float* box = ws.get<float>("pj.tbox", 6 * (int64_t)std::max(nfin, nf));
   hipLaunchKernelGGL(k_boxes, dim3(nblk(nfin)), dim3(256), 0, s, Vin, (const double*)nullptr, Fin, nfin, 0.0, box);
+  // query orders: the points sorted by Morton code
+  auto point_order = [&](const double* P, int n, const char* kn, const char* in) {
+    uint32_t* code = ws.get<uint32_t>(kn, std::max(n, 1));
+    int* id = ws.get<int>(in, std::max(n, 1));
+    hipLaunchKernelGGL(k_point_codes, dim3(nblk(n)), dim3(256), 0, s, P, n, code, id);
+    radix_sort_u32(ws, s, code, id, n, 30);
+    return (const int*)id;
+  };
+  const int* vorder = point_order(X, nv, "pj.vcode", "pj.vord");
+  const int* sorder = m > 0 ? point_order(Y, m, "pj.scode", "pj.sord") : nullptr;
   Bvh b = build_bvh(ws, s, box, nfin, nullptr);
-  hipLaunchKernelGGL(k_nearest, dim3(nblk(nv)), dim3(256), 0, s, (const BvhNode*)b.nodes, b.D, nfin, Vin, Fin, X, nv,
-                     targets, (int*)nullptr, err);
+  hipLaunchKernelGGL(k_nearest, dim3(nblk(nv)), dim3(256), 0, s, (const BvhNode*)b.nodes, b.D, nfin, Vin, Fin, X,
+                     vorder, nv, targets, (int*)nullptr, err);
   if (m > 0) {
     hipLaunchKernelGGL(k_boxes, dim3(nblk(nf)), dim3(256), 0, s, X, (const double*)nullptr, F, nf, 0.0, box);
     Bvh c = build_bvh(ws, s, box, nf, nullptr);
-    hipLaunchKernelGGL(k_nearest, dim3(nblk(m)), dim3(256), 0, s, (const BvhNode*)c.nodes, c.D, nf, X, F, Y, m,
+    hipLaunchKernelGGL(k_nearest, dim3(nblk(m)), dim3(256), 0, s, (const BvhNode*)c.nodes, c.D, nf, X, F, Y, sorder, m,
                        (double*)nullptr, tri, err);
   }
   check_launch();
