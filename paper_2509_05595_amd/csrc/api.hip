@@ -56,7 +56,7 @@ struct Prof {
 constexpr int PAMO_DEFAULT_PACKET = 1;
 constexpr int PAMO_DEFAULT_COOP = 8;
 constexpr int PAMO_DEFAULT_COOP_BELOW = 131072;
-constexpr int PAMO_DEFAULT_RESORT = 1 << 30;  // never: the first round's Morton order, carried along
+constexpr int PAMO_DEFAULT_RESORT = 1 << 30;  // never: the first round's Hilbert order, carried along
 
 struct pamo_ctx {
   int device = 0;
@@ -442,7 +442,7 @@ struct LearnRun {
   int64_t demoted = 0, fallbacks = 0;
 };
 
-// Leaf order of the BVH carried across rounds: sorting by Morton code every
+// Leaf order of the BVH carried across rounds: sorting by Hilbert index every
 // round is replaced by the previous order, stably remapped through the
 // compaction, with a fresh sort every `resort` rounds.  Any order gives a
 // correct tree; this only affects speed.
@@ -820,7 +820,7 @@ int64_t whole_mesh_pairs(pamo_ctx* c, MeshView m, int2* pairs, int64_t cap, int 
   fill_i32(s, cnt + C_NQ, 1, m.nf);
   launch_face_boxes(s, m, box);
   Bvh bvh = build_bvh(c->ws, s, box, m.nf, nullptr, m.fmesh, nmesh);
-  const int* ql = bvh.sorted;  // every face, in Morton order
+  const int* ql = bvh.sorted;  // every face, in Hilbert order
   QueryArgs qa{};
   qa.V = m.V;
   qa.F = m.F;

@@ -1322,7 +1322,7 @@ __device__ __forceinline__ void emit_pair(const WalkArgs& a, int t, int u) {
   if (k < a.fcap) a.fpair[k] = make_int2(t, u);
 }
 
-// One thread per leaf slot i (faces in Morton order, so a wave walks nearby
+// One thread per leaf slot i (faces in Hilbert order, so a wave walks nearby
 // parts of the tree): every face in a later slot whose box meets this face's
 // box, each face pair once.  The walk keeps no stack in memory: per level, the
 // children still to visit are four bits of one 64-bit mask (levels below 14),

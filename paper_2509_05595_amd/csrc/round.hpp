@@ -137,7 +137,7 @@ struct __align__(16) BvhNode {
   int4 pad;
 };
 
-// balanced implicit 4-ary tree over 4^D Morton-sorted leaf slots: internal
+// balanced implicit 4-ary tree over 4^D Hilbert-sorted leaf slots: internal
 // node k at level l (0 <= l < D, (4^l - 1)/3 <= k < (4^(l+1) - 1)/3) has
 // children 4k+1 .. 4k+4; slot j of the leaves is child j % 4 of the node at
 // position j / 4 of level D - 1.  Nodes whose leaves all lie past n are never
@@ -148,7 +148,7 @@ constexpr int LEAF_ID = LEAF_DEAD - 1;
 constexpr int BVH_DMAX = 14;  // 4^14 leaf slots; stack entries pack a node index below 2^27
 struct Bvh {
   BvhNode* nodes;
-  const int* sorted;  // faces in Morton order (leaf j holds sorted[j])
+  const int* sorted;  // faces in Hilbert order (leaf j holds sorted[j])
   int n;              // faces
   int D;              // internal levels
 };
@@ -178,9 +178,9 @@ void launch_batch_output(hipStream_t s, MeshView m, const int* f_off, const int*
 
 // build over the face boxes box[f] (6 floats, lo then hi), all nf faces.
 // `order` (may be null): a permutation of the faces to use as leaf order
-// instead of sorting by Morton code (any order gives a correct tree; a
-// near-Morton order gives a good one).
-// fmesh (batches, may be null): sort by (mesh, Morton code of the unshifted box)
+// instead of sorting by the Hilbert index of the box centres (any order gives
+// a correct tree; a near-Hilbert order gives a good one).
+// fmesh (batches, may be null): sort by (mesh, Hilbert index of the unshifted box)
 // node records the build writes for nf leaves (sum over heights h >= 1 of
 // ceil(nf / 4^h), 128 bytes each)
 inline int64_t bvh_nodes_written(int64_t nf) {
@@ -195,7 +195,7 @@ inline int64_t bvh_nodes_written(int64_t nf) {
 // LEAF_CHANGED, those with falive[f] == 0 LEAF_DEAD in their record (face id =
 // record & LEAF_ID); the flags hold for the first check pass of the round
 // reserve the BVH builder's buffers for up to nf leaves (mesh_codes: the
-// batch form's 64-bit (mesh, Morton) codes too); its sort is reserved by
+// batch form's 64-bit (mesh, Hilbert) codes too); its sort is reserved by
 // prim_reserve
 void bvh_reserve(Workspace& ws, int64_t nf, bool mesh_codes);
 Bvh build_bvh(Workspace& ws, hipStream_t s, const float* box, int nf, const int* order, const int* fmesh = nullptr,
