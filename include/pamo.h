@@ -60,7 +60,7 @@ typedef struct {
   int32_t resort_every; /* re-sort the BVH leaves by Morton code every this many rounds (default: never;
                            the first round's order is carried through the compactions) */
   int32_t query_coop;   /* lanes sharing one query when few queries remain (2,4,8,16; 1 = never; default 8) */
-  int32_t coop_below;   /* ... namely when a pass has fewer than about this many queries (default 131072) */
+  int32_t coop_below;   /* ... namely when a pass has fewer than about this many queries (default 65536) */
   int32_t learned;      /* 1: the learned proposal (needs pamo_set_mlp); 0: the plain method */
   double cost_target;   /* > 0: target-cost termination (the paper ends a run at a target edge cost or a
                            target face count, Sec. 5.1 "Edge Collapse"): only edges whose Eq. 1 cost is at

@@ -26,7 +26,7 @@ TABLE = os.path.join(HERE, "tuned.json")
 SPACE = {
     "query_packet": [1, 2, 8],
     "query_coop": [1, 4, 8, 16],
-    "coop_below": [32768, 131072, 524288],
+    "coop_below": [32768, 65536, 131072, 524288],
     "resort_every": [0, 8],
 }
 KNOBS = list(SPACE)
@@ -87,7 +87,7 @@ def tune_single(ctx_factory, V, F, target, reps=2):
         t = _time(lambda: ctx.simplify(V, F, target), reps)
         ctx.close()
         return t
-    start = {"query_packet": 1, "query_coop": 8, "coop_below": 131072, "resort_every": 0}
+    start = {"query_packet": 1, "query_coop": 8, "coop_below": 65536, "resort_every": 0}
     return coordinate_search(measure, start)
 
 
@@ -97,7 +97,7 @@ def tune_batch(ctx_factory, meshes, targets, reps=1):
         t = _time(lambda: ctx.simplify_batch(meshes, targets), reps)
         ctx.close()
         return t
-    start = {"query_packet": 1, "query_coop": 8, "coop_below": 131072, "resort_every": 0}
+    start = {"query_packet": 1, "query_coop": 8, "coop_below": 65536, "resort_every": 0}
     return coordinate_search(measure, start)
 
 

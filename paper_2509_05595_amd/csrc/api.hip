@@ -55,7 +55,7 @@ struct Prof {
 // workload; none of them changes a result)
 constexpr int PAMO_DEFAULT_PACKET = 1;
 constexpr int PAMO_DEFAULT_COOP = 8;
-constexpr int PAMO_DEFAULT_COOP_BELOW = 131072;
+constexpr int PAMO_DEFAULT_COOP_BELOW = 65536;
 constexpr int PAMO_DEFAULT_RESORT = 1 << 30;  // never: the first round's Hilbert order, carried along
 
 struct pamo_ctx {
