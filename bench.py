@@ -64,7 +64,7 @@ def cpu_baseline(V, F, target):
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "query__noisy-icosphere-1310720f-to-1pct.md")
+TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "simplify__noisy-icosphere-1310720f-to-1pct.md")
 
 
 def measured_traffic():
