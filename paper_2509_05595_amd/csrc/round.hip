@@ -328,35 +328,46 @@ __device__ __forceinline__ P3 corner_after(const MeshView& m, int f, int c, int 
 template <class Fn>
 __device__ __forceinline__ void star_chunks(const MeshView& m, int v, int n, int x1, int x2, int pad, Fn fn) {
   const int* st = m.vstar + (int64_t)VSTAR * v;
+  const int4* s4 = reinterpret_cast<const int4*>(st);
+  int raw[VSTAR];
+#pragma unroll
+  for (int q = 0; q < VSTAR / 4; q++) {
+    const int4 x = s4[q];
+    raw[4 * q] = x.x; raw[4 * q + 1] = x.y; raw[4 * q + 2] = x.z; raw[4 * q + 3] = x.w;
+  }
   int q1 = VSTAR, q2 = VSTAR;  // physical slots of the excluded faces, ascending
   int cnt = n;
   if (x1 >= 0 || x2 >= 0) {
-    const int4* s4 = reinterpret_cast<const int4*>(st);
 #pragma unroll
-    for (int q = 0; q < VSTAR / 4; q++) {
-      const int4 x = s4[q];
-      const int gq[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const int f = gq[k] / 3;
-        const bool ex = 4 * q + k < n && (f == x1 || f == x2);
-        q2 = ex && q1 < VSTAR && q2 == VSTAR ? 4 * q + k : q2;
-        q1 = ex && q1 == VSTAR ? 4 * q + k : q1;
-      }
+    for (int i = 0; i < VSTAR; i++) {
+      const int f = raw[i] / 3;
+      const bool ex = i < n && (f == x1 || f == x2);
+      q2 = ex && q1 < VSTAR && q2 == VSTAR ? i : q2;
+      q1 = ex && q1 == VSTAR ? i : q1;
     }
     cnt = n - (q1 < VSTAR) - (q2 < VSTAR);
   }
+  // the first two chunks from registers (logical slot i sits at physical slot
+  // i, i + 1 or i + 2, the excluded ones skipped); longer stars reload
+  int c8[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) c8[i] = i < q1 ? raw[i] : i + 1 < q2 ? raw[i + 1] : raw[i + 2];
   for (int j = 0; 4 * j < cnt; j++) {
     int g[4];
     bool use[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       const int i = 4 * j + k;
-      int phys = i;
-      phys += phys >= q1;
-      phys += phys >= q2;
       use[k] = i < cnt;
-      const int e = st[use[k] ? phys : 0];
+      int e;
+      if (j < 2) {
+        e = j == 0 ? c8[k] : c8[4 + k];
+      } else {
+        int phys = i;
+        phys += phys >= q1;
+        phys += phys >= q2;
+        e = st[use[k] ? phys : 0];
+      }
       g[k] = use[k] ? e : pad;
     }
     fn(g, use);
