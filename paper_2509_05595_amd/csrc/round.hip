@@ -456,6 +456,14 @@ __device__ __forceinline__ double edge_cost(const MeshView& m, const double* __r
   return quadric_eval(q, vbar) + w_e * lab + w_s * S;
 }
 
+// the placement of edge E alone (the same arithmetic as edge_cost)
+__device__ __forceinline__ P3 edge_placement(const MeshView& m, const double* __restrict__ Q, const EdgeStars& E) {
+  double q[10];
+#pragma unroll
+  for (int i = 0; i < 10; i++) q[i] = Q[10 * (int64_t)E.s + i] + Q[10 * (int64_t)E.r + i];
+  return placement(q, ld3(m.V, E.s), ld3(m.V, E.r), E.lo, E.hi);
+}
+
 // ------------------------------------------------------------ local checks
 __device__ __forceinline__ bool degenerate(P3 a, P3 b, P3 c) {
   // certain nonzero in some projection -> not degenerate
@@ -596,7 +604,7 @@ __device__ __forceinline__ uint8_t local_reason(const MeshView& m, const double*
   if (!link_holds(m, h)) return 1;
   EdgeStars E;
   if (!edge_stars(m, h, E)) set_err(err, PAMO_EBIT_RING);
-  (void)edge_cost(m, Q, E, w_e, w_s, vbar);
+  vbar = edge_placement(m, Q, E);  // the cost itself is not needed here
   return flipped_after(m, E, vbar) ? 2 : 0;
 }
 
