@@ -622,7 +622,7 @@ constexpr int64_t CK_SMALL_NH = 1 << 21;
 // float64 cost's order code (ranked afterwards).  Keys go to both half-edges;
 // the vertex minima are gathered from them by the next kernel (no atomics).
 template <int PW, bool PRE>
-__global__ __launch_bounds__(256) void k_cost_keys(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRE ? 2 : 1))) void k_cost_keys(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
                                                    double cost_max, const uint8_t* __restrict__ demote,
                                                    const uint8_t* __restrict__ mesh_done, uint64_t* __restrict__ key,
                                                    int* err, bool lex) {
