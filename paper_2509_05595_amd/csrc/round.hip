@@ -317,25 +317,21 @@ __device__ __forceinline__ P3 corner_after(const MeshView& m, int f, int c, int 
   return (v == s || v == r) ? vbar : ld3(m.V, v);
 }
 
-// The stored star of v (n <= VSTAR half-edges leaving v, ascending) without
-// those in faces x1 and x2, four at a time: fn(g, use) gets four half-edges;
-// slots past the end carry `pad` (a half-edge that is safe to read through)
-// and use = false.  The excluded slots are located once in the star's 64-byte
-// line and skipped, so the chunks are full (a valence-6 star around an edge is
-// one chunk of four).  The callee issues its loads for all four before acting
-// on any, so a star costs a few load latencies instead of one per face of a
-// twin walk.
-template <class Fn>
-__device__ __forceinline__ void star_chunks(const MeshView& m, int v, int n, int x1, int x2, int pad, Fn fn) {
-  const int* st = m.vstar + (int64_t)VSTAR * v;
-  const int4* s4 = reinterpret_cast<const int4*>(st);
+// The stored star of v (n <= VSTAR slots) without the slots of faces x1 and
+// x2: returns how many are left; c8 gets the first eight of them (logical
+// slot i sits at physical slot i, i + 1 or i + 2), q1 < q2 the excluded
+// physical slots (VSTAR when absent).  One 64-byte load.
+__device__ __forceinline__ int star_compact8(const MeshView& m, int v, int n, int x1, int x2, int* c8, int& q1,
+                                             int& q2) {
+  const int4* s4 = reinterpret_cast<const int4*>(m.vstar + (int64_t)VSTAR * v);
   int raw[VSTAR];
 #pragma unroll
   for (int q = 0; q < VSTAR / 4; q++) {
     const int4 x = s4[q];
     raw[4 * q] = x.x; raw[4 * q + 1] = x.y; raw[4 * q + 2] = x.z; raw[4 * q + 3] = x.w;
   }
-  int q1 = VSTAR, q2 = VSTAR;  // physical slots of the excluded faces, ascending
+  q1 = VSTAR;
+  q2 = VSTAR;
   int cnt = n;
   if (x1 >= 0 || x2 >= 0) {
 #pragma unroll
@@ -347,29 +343,47 @@ __device__ __forceinline__ void star_chunks(const MeshView& m, int v, int n, int
     }
     cnt = n - (q1 < VSTAR) - (q2 < VSTAR);
   }
-  // the first two chunks from registers (logical slot i sits at physical slot
-  // i, i + 1 or i + 2, the excluded ones skipped); longer stars reload
-  int c8[8];
 #pragma unroll
   for (int i = 0; i < 8; i++) c8[i] = i < q1 ? raw[i] : i + 1 < q2 ? raw[i + 1] : raw[i + 2];
+  return cnt;
+}
+
+// logical slot i (>= 8) of the star of v: a reload of the slot
+__device__ __forceinline__ int star_slot(const MeshView& m, int v, int i, int q1, int q2, bool use) {
+  int phys = i;
+  phys += phys >= q1;
+  phys += phys >= q2;
+  return m.vstar[(int64_t)VSTAR * v + (use ? phys : 0)];
+}
+
+// chunk j (four slots) of a compacted star
+__device__ __forceinline__ void star_chunk(const MeshView& m, int v, int j, int cnt, const int* c8, int q1, int q2,
+                                           int pad, int* g, bool* use) {
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int i = 4 * j + k;
+    use[k] = i < cnt;
+    const int e = j < 2 ? (j == 0 ? c8[k] : c8[4 + k]) : star_slot(m, v, i, q1, q2, use[k]);
+    g[k] = use[k] ? e : pad;
+  }
+}
+
+// The stored star of v (n <= VSTAR half-edges leaving v, ascending) without
+// those in faces x1 and x2, four at a time: fn(g, use) gets four half-edges;
+// slots past the end carry `pad` (a half-edge that is safe to read through)
+// and use = false.  The excluded slots are located once in the star's 64-byte
+// line and skipped, so the chunks are full (a valence-6 star around an edge is
+// one chunk of four); the first two chunks come from the registers holding
+// the line.  The callee issues its loads for all four before acting on any,
+// so a star costs a few load latencies instead of one per face of a twin walk.
+template <class Fn>
+__device__ __forceinline__ void star_chunks(const MeshView& m, int v, int n, int x1, int x2, int pad, Fn fn) {
+  int c8[8], q1, q2;
+  const int cnt = star_compact8(m, v, n, x1, x2, c8, q1, q2);
   for (int j = 0; 4 * j < cnt; j++) {
     int g[4];
     bool use[4];
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-      const int i = 4 * j + k;
-      use[k] = i < cnt;
-      int e;
-      if (j < 2) {
-        e = j == 0 ? c8[k] : c8[4 + k];
-      } else {
-        int phys = i;
-        phys += phys >= q1;
-        phys += phys >= q2;
-        e = st[use[k] ? phys : 0];
-      }
-      g[k] = use[k] ? e : pad;
-    }
+    star_chunk(m, v, j, cnt, c8, q1, q2, pad, g, use);
     fn(g, use);
   }
 }
@@ -507,26 +521,42 @@ __device__ __forceinline__ bool link_ok(const MeshView& m, int h) {
 }
 
 // the same test from the stored stars: N(v) = far ends of the half-edges
-// leaving v, each neighbour once
-__device__ __forceinline__ bool link_ok_stars(const MeshView& m, int a, int na, int b, int nb) {
+// leaving v, each neighbour once.  In two parts, so that a caller can issue
+// the loads and do other work before it needs the answer.
+struct LinkStars {
+  int na, nb;
+  int wa[VSTAR], wb[VSTAR];
+};
+
+__device__ __forceinline__ void link_stars_load(const MeshView& m, int a, int na, int b, int nb, LinkStars& L) {
   int ga[VSTAR], gb[VSTAR];
   star_all(m, a, na, ga);
   star_all(m, b, nb, gb);
-  int wa[VSTAR], wb[VSTAR];
+  L.na = na;
+  L.nb = nb;
 #pragma unroll
   for (int i = 0; i < VSTAR; i++) {
-    wa[i] = m.F[he_next(ga[i])];
-    wb[i] = m.F[he_next(gb[i])];
+    L.wa[i] = m.F[he_next(ga[i])];
+    L.wb[i] = m.F[he_next(gb[i])];
   }
+}
+
+__device__ __forceinline__ bool link_stars_holds(const LinkStars& L) {
   int common = 0;
 #pragma unroll
   for (int j = 0; j < VSTAR; j++) {
     bool in = false;
 #pragma unroll
-    for (int i = 0; i < VSTAR; i++) in |= i < na && wa[i] == wb[j];
-    common += j < nb && in;
+    for (int i = 0; i < VSTAR; i++) in |= i < L.na && L.wa[i] == L.wb[j];
+    common += j < L.nb && in;
   }
-  return common == 2 && !(na == 3 && nb == 3);
+  return common == 2 && !(L.na == 3 && L.nb == 3);
+}
+
+__device__ __forceinline__ bool link_ok_stars(const MeshView& m, int a, int na, int b, int nb) {
+  LinkStars L;
+  link_stars_load(m, a, na, b, nb, L);
+  return link_stars_holds(L);
 }
 
 // the link condition for the edge of h, from the stored stars when they fit
@@ -601,11 +631,24 @@ __device__ __forceinline__ bool flipped_after(const MeshView& m, const EdgeStars
 // degenerate or flipped; vbar gets the placement (when the link holds)
 __device__ __forceinline__ uint8_t local_reason(const MeshView& m, const double* __restrict__ Q, double w_e,
                                                 double w_s, int h, P3& vbar, int* err) {
-  if (!link_holds(m, h)) return 1;
   EdgeStars E;
-  if (!edge_stars(m, h, E)) set_err(err, PAMO_EBIT_RING);
-  vbar = edge_placement(m, Q, E);  // the cost itself is not needed here
-  return flipped_after(m, E, vbar) ? 2 : 0;
+  const bool ok = edge_stars(m, h, E);
+  const P3 vb = edge_placement(m, Q, E);  // the cost itself is not needed here
+  if (E.fast) {
+    // the link test's loads are in flight while the flip test runs; a
+    // candidate failing the link test keeps reason 1 and no placement
+    LinkStars L;
+    const bool a_is_s = m.F[h] == E.s;
+    link_stars_load(m, a_is_s ? E.s : E.r, a_is_s ? E.ns : E.nr, a_is_s ? E.r : E.s, a_is_s ? E.nr : E.ns, L);
+    const bool flipped = flipped_after(m, E, vb);
+    if (!link_stars_holds(L)) return 1;
+    vbar = vb;
+    return flipped ? 2 : 0;
+  }
+  if (!link_holds(m, h)) return 1;
+  if (!ok) set_err(err, PAMO_EBIT_RING);
+  vbar = vb;
+  return flipped_after(m, E, vb) ? 2 : 0;
 }
 
 // ------------------------------------------------------------ cost + keys
