@@ -905,47 +905,10 @@ __global__ void k_cg_start(const double* __restrict__ pr, const double* __restri
     st->rr = rr;
     st->bb = rr;
     st->rz = rz;
+    st->beta = 0.0;  // the first direction is z itself
     st->it = 0;
     st->done = !(sqrt(rr) > st->tol * sqrt(rr)) || st->max_it <= 0;
   }
-}
-__global__ void k_cg_alpha(const double* __restrict__ part, int nb, CgState* st) {
-  if (st->done) return;
-  const double pap = sum_parts(part, nb);
-  if (threadIdx.x == 0) st->alpha = st->rz / pap;
-}
-__global__ void k_cg_update(double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
-                            const double* __restrict__ p, const double* __restrict__ Ap, const double* __restrict__ Di,
-                            int nv, const CgState* st) {
-  if (st->done) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nv) return;
-  const double a = st->alpha;
-  double rv[3];
-  for (int c = 0; c < 3; c++) {
-    x[3 * i + c] += a * p[3 * i + c];
-    r[3 * i + c] -= a * Ap[3 * i + c];
-    rv[c] = r[3 * i + c];
-  }
-  const double* d = Di + 9 * (int64_t)i;
-  for (int c = 0; c < 3; c++) z[3 * i + c] = d[3 * c] * rv[0] + d[3 * c + 1] * rv[1] + d[3 * c + 2] * rv[2];
-}
-__global__ void k_cg_beta(const double* __restrict__ pz, const double* __restrict__ pr, int nb, CgState* st) {
-  if (st->done) return;
-  const double rz = sum_parts(pz, nb);
-  const double rr = sum_parts(pr, nb);
-  if (threadIdx.x == 0) {
-    st->beta = rz / st->rz;
-    st->rz = rz;
-    st->rr = rr;
-    st->it += 1;
-    st->done = !(sqrt(rr) > st->tol * sqrt(st->bb)) || st->it >= st->max_it;
-  }
-}
-__global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ z, int64_t n, const CgState* st) {
-  if (st->done) return;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) p[i] = z[i] + st->beta * p[i];
 }
 // x = 0, r = -g, z = D^-1 r, p = z
 __global__ void k_cg_init(const double* __restrict__ g, const double* __restrict__ Di, int nv, double* __restrict__ x,
@@ -985,25 +948,6 @@ __device__ double sum_parts_l2(const double* __restrict__ part, int nb) {
   double s = 0.0;
   for (int i = threadIdx.x; i < nb; i += SUM_T) s += load_l2(part + i);
   return block_sum(s);
-}
-// p.Ap, then alpha = rz / p.Ap
-__global__ __launch_bounds__(SUM_T) void k_cg_pap(const double* __restrict__ p, const double* __restrict__ Ap,
-                                                  int64_t n, double* __restrict__ part, unsigned* ticket, CgState* st) {
-  if (st->done) return;
-  const int64_t base = (int64_t)blockIdx.x * SUM_T * SUM_ITEMS;
-  double s = 0.0;
-  for (int j = 0; j < SUM_ITEMS; j++) {
-    const int64_t i = base + (int64_t)j * SUM_T + threadIdx.x;
-    if (i < n) s += p[i] * Ap[i];
-  }
-  s = block_sum(s);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
-  if (!last_block(ticket)) return;
-  const double pap = sum_parts_l2(part, gridDim.x);
-  if (threadIdx.x == 0) {
-    st->alpha = st->rz / pap;
-    *ticket = 0;
-  }
 }
 // x += alpha p, r -= alpha Ap, z = D^-1 r with the partial sums of r.z and r.r;
 // the last block: beta, the new r.z and r.r, the stopping test
@@ -1049,11 +993,44 @@ __global__ __launch_bounds__(SUM_T) void k_cg_step(double* __restrict__ x, doubl
     *ticket = 0;
   }
 }
-// p = z + beta p
-__global__ void k_cg_next(double* __restrict__ p, const double* __restrict__ z, int64_t n, const CgState* st) {
+// The direction and its product of one iteration in one launch: pn = z +
+// beta p (beta = 0 first, so pn = z), Apn = H pn (one thread per output
+// component, reading pn at the block's columns as z + beta p), the partial
+// sums of pn.Apn; the last block: alpha = rz / pn.Apn.  pn is a separate array
+// from p, since other blocks still read p while this one writes pn.
+__global__ __launch_bounds__(SUM_T) void k_cg_dir(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                  const double* __restrict__ B, int nv, const double* __restrict__ z,
+                                                  const double* __restrict__ p, double* __restrict__ pn,
+                                                  double* __restrict__ Ap, double* __restrict__ part, unsigned* ticket,
+                                                  CgState* st) {
   if (st->done) return;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) p[i] = z[i] + st->beta * p[i];
+  const double beta = st->beta;
+  const int t = blockIdx.x * SUM_T + threadIdx.x;
+  double dot = 0.0;
+  if (t < 3 * nv) {
+    const int i = t / 3, r = t - 3 * i;
+    double s = 0.0;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; k++) {
+      const int64_t j = col[k];
+      const double* b = B + 9 * (int64_t)k + 3 * r;
+      const double v0 = z[3 * j] + beta * p[3 * j];
+      const double v1 = z[3 * j + 1] + beta * p[3 * j + 1];
+      const double v2 = z[3 * j + 2] + beta * p[3 * j + 2];
+      s += b[0] * v0 + b[1] * v1 + b[2] * v2;
+    }
+    Ap[t] = s;
+    const double pt = z[t] + beta * p[t];
+    pn[t] = pt;
+    dot = pt * s;
+  }
+  dot = block_sum(dot);
+  if (threadIdx.x == 0) part[blockIdx.x] = dot;
+  if (!last_block(ticket)) return;
+  const double pap = sum_parts_l2(part, gridDim.x);
+  if (threadIdx.x == 0) {
+    st->alpha = st->rz / pap;
+    *ticket = 0;
+  }
 }
 
 __global__ void k_axpy_pos(const double* __restrict__ X, const double* __restrict__ P, double a, int64_t n,
@@ -1866,15 +1843,18 @@ struct Projection {
     check_launch();
   }
 
-  // p from H p = -grad (after derivs); returns the CG iterations.  Four
-  // launches per iteration; the host looks at the stopping flag every 8.
+  // p from H p = -grad (after derivs); returns the CG iterations.  Two
+  // launches per iteration (direction with its product, then the update);
+  // the host looks at the stopping flag every 8.
   int solve(double* dir) {
     const int64_t n3 = 3 * (int64_t)nv;
     const unsigned nb = sum_blocks(n3);
     const unsigned nbv = nblk(nv, SUM_T);
+    const unsigned nbd = nblk(n3, SUM_T);
     double* pz = ws.get<double>("pj.cgpz", nbv);
     double* pr = ws.get<double>("pj.cgpr", nbv);
-    double* pp = ws.get<double>("pj.cgpp", nb);
+    double* pp = ws.get<double>("pj.cgpp", nbd);
+    double* p2 = ws.get<double>("pj.cgp2", n3);  // the other direction buffer
     unsigned* ticket = ws.get<unsigned>("pj.ticket", 2);
     PAMO_HIP(hipMemsetAsync(ticket, 0, 2 * sizeof(unsigned), s));
     CgState h{};
@@ -1888,16 +1868,15 @@ struct Projection {
     hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(SUM_T), 0, s, (const double*)cr, (const double*)cz, n3, part2,
                        (const int*)nullptr);
     hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(SUM_T), 0, s, (const double*)part, (const double*)part2, (int)nb, cg);
-    const int* done = &cg->done;
+    double* pa = cp;  // this iteration's direction goes into pb
+    double* pb = p2;
     for (;;) {
       for (int k = 0; k < 8; k++) {
-        matvec(cp, cAp, done);
-        hipLaunchKernelGGL(k_cg_pap, dim3(nb), dim3(SUM_T), 0, s, (const double*)cp, (const double*)cAp, n3, pp,
-                           ticket, cg);
-        hipLaunchKernelGGL(k_cg_step, dim3(nbv), dim3(SUM_T), 0, s, cx, cr, cz, (const double*)cp, (const double*)cAp,
+        hipLaunchKernelGGL(k_cg_dir, dim3(nbd), dim3(SUM_T), 0, s, (const int*)rowptr, (const int*)bcol,
+                           (const double*)bval, nv, (const double*)cz, (const double*)pa, pb, cAp, pp, ticket, cg);
+        hipLaunchKernelGGL(k_cg_step, dim3(nbv), dim3(SUM_T), 0, s, cx, cr, cz, (const double*)pb, (const double*)cAp,
                            (const double*)Dinv, nv, pz, pr, ticket + 1, cg);
-        hipLaunchKernelGGL(k_cg_next, dim3(nblk(n3)), dim3(256), 0, s, cp, (const double*)cz, n3,
-                           (const CgState*)cg);
+        std::swap(pa, pb);
       }
       check_launch();
       read(s, &h, cg, 1);
