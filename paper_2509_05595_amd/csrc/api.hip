@@ -260,6 +260,7 @@ struct RoundBufs {
   int* ovl_new;  // learned proposal: overlap counts measured this round (null when not tracked)
   float* X;      // learned proposal: features of this round's candidates (null when unused)
   int* dlist;    // learned proposal: the edges the network set aside this round
+  bool sel_clear;  // the selection flags are zero (the last compaction cleared them)
 };
 
 // one query pass (traversal + pair predicate + exact resolve); grows the
@@ -362,6 +363,7 @@ RoundBufs round_bufs(Workspace& w, int64_t nv, int64_t nf) {
   b.ovl_new = nullptr;
   b.X = nullptr;
   b.dlist = nullptr;
+  b.sel_clear = false;
   return b;
 }
 
@@ -634,7 +636,7 @@ void round_tail(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, c
       src = tmp;
     }
     launch_compact(c->ws, s, cur, alt, b.falive, b.valive, cnt + C_NF, cnt + C_NV, cnt + C_ERR, gate, src, order_out,
-                   cnt + C_NORD);
+                   cnt + C_NORD, nullptr, nullptr, 0, c->ws.get<uint8_t>("sel", 3 * (int64_t)cur.nf));
   } else if (R.leaf_order && R.leaf_order != order_out) {
     PAMO_HIP(hipMemcpyAsync(order_out, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
   }
@@ -680,7 +682,8 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
   {
     TIMED(PH_SELECT, 84 * nv + 45 * nf);
     if (c->opt.key_mode) launch_rank_keys(c->ws, s, cur, b.key);
-    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, b.sel_clear);
+    b.sel_clear = false;
   }
   const int bound = cur.nf / 2 + 1;
   if (learned || logging) {
@@ -757,6 +760,7 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
       os.age = reuse ? os.age + 1 : 1;
       os.valid = true;
       std::swap(b.morder, b.morder2);
+      b.sel_clear = true;  // the speculative compaction ran
       return round_end(c, cur, alt, R, L, h);
     }
     R.commits = 0;
@@ -776,6 +780,7 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
     os.valid = true;
   }
   round_tail(c, cur, alt, b, R, L, GateIn{}, b.morder);
+  b.sel_clear = R.commits > 0;  // a compaction ran
   return round_end(c, cur, alt, R, L, readback(c));
 }
 
@@ -991,7 +996,7 @@ void batch_tail(pamo_ctx* c, MeshView& cur, MeshView& alt, const RoundBufs& b, c
       src = tmp;
     }
     launch_compact(c->ws, s, cur, alt, b.falive, b.valive, cnt + C_NF, cnt + C_NV, cnt + C_ERR, gate, src, order_out,
-                   cnt + C_NORD, B.d(B.f_off()), B.d(B.v_off()), n);
+                   cnt + C_NORD, B.d(B.f_off()), B.d(B.v_off()), n, c->ws.get<uint8_t>("sel", 3 * (int64_t)cur.nf));
   } else if (R.leaf_order && R.leaf_order != order_out) {
     PAMO_HIP(hipMemcpyAsync(order_out, R.leaf_order, (size_t)cur.nf * sizeof(int), hipMemcpyDeviceToDevice, s));
   }
@@ -1042,7 +1047,8 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs
   {
     TIMED(PH_SELECT, 84 * nv + 45 * nf);
     if (c->opt.key_mode) launch_rank_keys(c->ws, s, cur, b.key);
-    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND);
+    launch_select(c->ws, s, cur, b.key, b.vmin, b.cand, cnt + C_NCAND, b.sel_clear);
+    b.sel_clear = false;
   }
   const int bound = cur.nf / 2 + 1;
   if (learned) {
@@ -1118,6 +1124,7 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs
       os.age = reuse ? os.age + 1 : 1;
       os.valid = true;
       std::swap(b.morder, b.morder2);
+      b.sel_clear = true;  // the speculative compaction ran
       return round_end(c, cur, alt, R, nullptr, h);
     }
     R.commits = 0;
@@ -1132,6 +1139,7 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs
     os.valid = true;
   }
   batch_tail(c, cur, alt, b, B, R, track, learned, GateIn{}, b.morder);
+  b.sel_clear = R.commits > 0;  // a compaction ran
   return round_end(c, cur, alt, R, nullptr, readback_batch(c, B));
 }
 

@@ -1168,7 +1168,8 @@ __global__ void k_reason_hist(const int* __restrict__ ncand, const uint8_t* __re
 // ------------------------------------------------------------ compaction
 __device__ __forceinline__ void compact_face(MeshView src, MeshView dst, const uint8_t* __restrict__ falive,
                                                      const int* __restrict__ fmap, const int* __restrict__ vmap,
-                                                     int* err, const int* __restrict__ gate) {
+                                                     int* err, const int* __restrict__ gate,
+                                                     uint8_t* __restrict__ sel) {
   if (gate && *gate) return;
   int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= src.nf || !falive[f]) return;
@@ -1187,6 +1188,7 @@ __device__ __forceinline__ void compact_face(MeshView src, MeshView dst, const u
     dst.F[3 * g + k] = v;
     dst.twin[3 * g + k] = 3 * tf + (t >= 0 ? t % 3 : k);
     dst.flags[3 * g + k] = src.flags[h];
+    if (sel) sel[3 * g + k] = 0;  // the next round's selection flags start cleared
   }
   if (src.fmesh) dst.fmesh[g] = src.fmesh[f];
   if (src.ovl) dst.ovl[g] = src.ovl[f];
@@ -1210,8 +1212,8 @@ __device__ __forceinline__ void compact_vertex(MeshView src, MeshView dst, const
 __global__ void k_compact(MeshView src, MeshView dst, const uint8_t* __restrict__ falive,
                           const uint8_t* __restrict__ valive, const int* __restrict__ fmap,
                           const int* __restrict__ vmap, int* err, const int* __restrict__ gate, int* __restrict__ ord,
-                          const int* __restrict__ nord) {
-  compact_face(src, dst, falive, fmap, vmap, err, gate);
+                          const int* __restrict__ nord, uint8_t* __restrict__ sel) {
+  compact_face(src, dst, falive, fmap, vmap, err, gate, sel);
   compact_vertex(src, dst, valive, vmap, fmap, gate);
   if (ord && !(gate && *gate)) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1525,11 +1527,11 @@ void launch_rank_keys(Workspace& ws, hipStream_t s, MeshView m, uint64_t* key) {
 }
 
 void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, int* cand,
-                   int* ncand) {
+                   int* ncand, bool sel_clear) {
   int64_t nh = 3 * (int64_t)m.nf;
   uint8_t* sel = ws.get<uint8_t>("sel", nh);
   hipLaunchKernelGGL(k_vertex_min, dim3(nblk(m.nv)), dim3(256), 0, s, m, key, vmin);
-  fill_u8(s, sel, nh, 0);
+  if (!sel_clear) fill_u8(s, sel, nh, 0);
   hipLaunchKernelGGL(k_select, dim3(nblk(m.nv)), dim3(256), 0, s, m, key, (const uint64_t*)vmin, sel);
   compact_flags(ws, s, sel, nh, cand, ncand);
   PAMO_HIP(hipGetLastError());
@@ -1622,7 +1624,7 @@ void launch_reason_hist(hipStream_t s, const int* ncand, int cand_bound, const u
 
 void launch_compact(Workspace& ws, hipStream_t s, MeshView src, MeshView dst, const uint8_t* falive,
                     const uint8_t* valive, int* nf_new, int* nv_new, int* err, const int* gate, const int* order,
-                    int* order_out, int* nord, int* f_off, int* v_off, int nmesh) {
+                    int* order_out, int* nord, int* f_off, int* v_off, int nmesh, uint8_t* sel) {
   int* fmap = ws.get<int>("cmp.fmap", src.nf);
   int* vmap = ws.get<int>("cmp.vmap", src.nv);
   // face ranks, vertex ranks and the surviving faces in leaf order in one
@@ -1642,7 +1644,7 @@ void launch_compact(Workspace& ws, hipStream_t s, MeshView src, MeshView dst, co
   rank_segments(ws, s, sg, fuse ? 3 : 2);
   hipLaunchKernelGGL(k_compact, dim3(nblk(src.nf > src.nv ? src.nf : src.nv)), dim3(256), 0, s, src, dst, falive,
                      valive, (const int*)fmap, (const int*)vmap, err, gate, fuse ? order_out : nullptr,
-                     (const int*)nord);
+                     (const int*)nord, sel);
   if (f_off)
     hipLaunchKernelGGL(k_batch_offsets2, dim3(nblk(2 * (int64_t)nmesh + 2)), dim3(256), 0, s, (const int*)sg[0].excl,
                        (const int*)nf_new, src.nf, f_off, (const int*)sg[1].excl, (const int*)nv_new, src.nv, v_off,

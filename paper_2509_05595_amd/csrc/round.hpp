@@ -64,8 +64,10 @@ void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, do
 void launch_rank_keys(Workspace& ws, hipStream_t s, MeshView m, uint64_t* key);
 // the vertex minima of key gathered into vmin (one thread per vertex over its
 // stored star, no atomics), then the selection and its compaction
+// sel_clear: the selection flags ("sel", 3 nf bytes) are known to be zero
+// (a compaction given them cleared them), else they are cleared first
 void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key, uint64_t* vmin, int* cand,
-                   int* ncand);
+                   int* ncand, bool sel_clear = false);
 // the selection again after the candidates dlist[0..*nd) (*nd <= bound) got
 // the largest key on both half-edges: into cand / ncand the same candidates as
 // a full launch_select, from the flags and vertex minima of the selection
@@ -119,12 +121,14 @@ void launch_flags(hipStream_t s, MeshView m, const int* cand, const int* ncand, 
 void launch_flags_or(hipStream_t s, uint8_t* dst, const uint8_t* src, int64_t n);
 void launch_reason_hist(hipStream_t s, const int* ncand, int cand_bound, const uint8_t* reason, int* hist);
 // order (optional): a leaf order of the source faces, whose surviving faces go
-// to order_out (new ids, the count to *nord); order_out must not be order
+// to order_out (new ids, the count to *nord); order_out must not be order;
+// sel (optional): 3 bytes per surviving face set to zero (the next round's
+// selection flags)
 // (f_off, v_off, nmesh): a batch's per-mesh offsets, updated to the compacted numbering
 void launch_compact(Workspace& ws, hipStream_t s, MeshView src, MeshView dst, const uint8_t* falive,
                     const uint8_t* valive, int* nf_new, int* nv_new, int* err, const int* gate = nullptr,
                     const int* order = nullptr, int* order_out = nullptr, int* nord = nullptr, int* f_off = nullptr,
-                    int* v_off = nullptr, int nmesh = 0);
+                    int* v_off = nullptr, int nmesh = 0, uint8_t* sel = nullptr);
 void launch_clear_u8(hipStream_t s, uint8_t* p, int64_t n, const int* gate);
 
 // ------------------------------------------------------------ LBVH
