@@ -406,11 +406,16 @@ __global__ __launch_bounds__(256) void k_elem_psd(double* __restrict__ H, int n)
   if (grp >= n) return;  // whole groups leave together
   const int64_t e = grp;
   const bool row = lane < N;
-  double a[N], q[N];
+  // the lane's row of the accumulated rotations lives in LDS (column k of the
+  // block's rows at qs[k][threadIdx.x]: consecutive lanes, consecutive banks);
+  // in registers it would hold the kernel to one wave a SIMD
+  __shared__ double qs[N][256];
+  double* q = &qs[0][threadIdx.x];
+  double a[N];
 #pragma unroll
   for (int k = 0; k < N; k++) {
     a[k] = row ? 0.5 * (H[(int64_t)(lane * N + k) * n + e] + H[(int64_t)(k * N + lane) * n + e]) : 0.0;
-    q[k] = (row && k == lane) ? 1.0 : 0.0;
+    q[256 * k] = (row && k == lane) ? 1.0 : 0.0;
   }
   for (int sweep = 0; sweep < 30; sweep++) {
     double off = 0.0, all = 0.0;
@@ -468,9 +473,9 @@ __global__ __launch_bounds__(256) void k_elem_psd(double* __restrict__ H, int n)
         const double arp = a[pp], arq = a[qq];
         a[pp] = ck * arp - sk * arq;
         a[qq] = sk * arp + ck * arq;
-        const double qrp = q[pp], qrq = q[qq];
-        q[pp] = ck * qrp - sk * qrq;
-        q[qq] = sk * qrp + ck * qrq;
+        const double qrp = q[256 * pp], qrq = q[256 * qq];
+        q[256 * pp] = ck * qrp - sk * qrq;
+        q[256 * qq] = sk * qrp + ck * qrq;
       }
       // rows (J^T (A J)) from the partner's row
       double o[N];
@@ -489,14 +494,17 @@ __global__ __launch_bounds__(256) void k_elem_psd(double* __restrict__ H, int n)
       }
     }
   }
-  double lam[N];
+  double lam[N], qr[N];
 #pragma unroll
-  for (int k = 0; k < N; k++) lam[k] = fmax(__shfl(a[k], k, PSD_G), 0.0);
+  for (int k = 0; k < N; k++) {
+    lam[k] = fmax(__shfl(a[k], k, PSD_G), 0.0);
+    qr[k] = q[256 * k];
+  }
 #pragma unroll
   for (int j = 0; j < N; j++) {
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < N; k++) s += lam[k] * q[k] * __shfl(q[k], j, PSD_G);
+    for (int k = 0; k < N; k++) s += lam[k] * qr[k] * __shfl(qr[k], j, PSD_G);
     if (row) H[(int64_t)(lane * N + j) * n + e] = s;
   }
 }
