@@ -901,8 +901,10 @@ __global__ __launch_bounds__(256) void k_bsr_spmv(const int* __restrict__ rowptr
 }
 
 // ------------------------------------------------------------ conjugate gradients
+// rzs[i & 1]: r.z after i iterations (the two latest, so that a kernel can
+// write the new one while its other blocks still read the one before)
 struct CgState {
-  double rz, rr, bb, alpha, beta, tol;
+  double rzs[2], rr, bb, tol;
   int it, max_it, done, pad;
 };
 __global__ void k_cg_start(const double* __restrict__ pr, const double* __restrict__ pz, int nb, CgState* st) {
@@ -912,8 +914,7 @@ __global__ void k_cg_start(const double* __restrict__ pr, const double* __restri
   if (threadIdx.x == 0) {
     st->rr = rr;
     st->bb = rr;
-    st->rz = rz;
-    st->beta = 0.0;  // the first direction is z itself
+    st->rzs[0] = rz;
     st->it = 0;
     st->done = !(sqrt(rr) > st->tol * sqrt(rr)) || st->max_it <= 0;
   }
@@ -939,86 +940,63 @@ __global__ void k_cg_init(const double* __restrict__ g, const double* __restrict
   }
 }
 
-// The last block to finish reads every block's partial sum (written before a
-// device-scope fence and a ticket) and updates the scalars.
-__device__ __forceinline__ double load_l2(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Sums for the CG kernels, whose blocks are single waves (CG_T = 64): a small
+// system's few thousand rows then spread over many CUs, and a block's sum
+// needs no barrier.  The kernels of an iteration pass their dot products on as
+// per-block partial sums, and every block of the next kernel adds them up
+// itself, in the same order (so all get the same value): no block waits for
+// the others, and no device-scope fence is needed inside a kernel (on this
+// chip such a fence writes back and invalidates the L2).
+constexpr int CG_T = 64;
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
 }
-__device__ bool last_block(unsigned* ticket) {
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-  __syncthreads();
-  return last;
-}
-__device__ double sum_parts_l2(const double* __restrict__ part, int nb) {
+__device__ double sum_parts_wave(const double* __restrict__ part, int nb) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < nb; i += SUM_T) s += load_l2(part + i);
-  return block_sum(s);
+  for (int i = threadIdx.x; i < nb; i += CG_T) s += part[i];
+  return wave_sum(s);
 }
-// x += alpha p, r -= alpha Ap, z = D^-1 r with the partial sums of r.z and r.r;
-// the last block: beta, the new r.z and r.r, the stopping test
-__global__ __launch_bounds__(SUM_T) void k_cg_step(double* __restrict__ x, double* __restrict__ r,
-                                                   double* __restrict__ z, const double* __restrict__ p,
-                                                   const double* __restrict__ Ap, const double* __restrict__ Di,
-                                                   int nv, double* __restrict__ pz, double* __restrict__ pr,
-                                                   unsigned* ticket, CgState* st) {
+
+// Iteration i, first half: the stopping test on r after i iterations (i > 0:
+// its r.r and r.z from the step's partials), then the new direction pn = z +
+// beta p (beta = 0 at i = 0, so pn = z), Apn = H pn (one thread per output
+// component, reading pn at the block's columns as z + beta p) and the partial
+// sums of pn.Apn.  pn is a separate array from p, since other blocks still
+// read p while this one writes pn.
+__global__ __launch_bounds__(CG_T) void k_cg_dir(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                 const double* __restrict__ B, int nv, const double* __restrict__ z,
+                                                 const double* __restrict__ p, double* __restrict__ pn,
+                                                 double* __restrict__ Ap, double* __restrict__ part,
+                                                 const double* __restrict__ pz, const double* __restrict__ pr,
+                                                 int nbv, int i, CgState* st) {
   if (st->done) return;
-  const double a = st->alpha;
-  double srz = 0.0, srr = 0.0;
-  const int i = blockIdx.x * SUM_T + threadIdx.x;
-  if (i < nv) {
-    double rv[3];
-    for (int c = 0; c < 3; c++) {
-      x[3 * i + c] += a * p[3 * i + c];
-      r[3 * i + c] -= a * Ap[3 * i + c];
-      rv[c] = r[3 * i + c];
+  double beta = 0.0;
+  if (i > 0) {
+    const double rz = sum_parts_wave(pz, nbv);
+    const double rr = sum_parts_wave(pr, nbv);
+    const bool fin = !(sqrt(rr) > st->tol * sqrt(st->bb)) || i >= st->max_it;
+    if (fin) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rr = rr;
+        st->it = i;
+        st->done = 1;
+      }
+      return;
     }
-    const double* d = Di + 9 * (int64_t)i;
-    for (int c = 0; c < 3; c++) {
-      const double zc = d[3 * c] * rv[0] + d[3 * c + 1] * rv[1] + d[3 * c + 2] * rv[2];
-      z[3 * i + c] = zc;
-      srz += rv[c] * zc;
-      srr += rv[c] * rv[c];
+    beta = rz / st->rzs[(i - 1) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->rzs[i & 1] = rz;
+      st->rr = rr;
     }
   }
-  srz = block_sum(srz);
-  srr = block_sum(srr);
-  if (threadIdx.x == 0) {
-    pz[blockIdx.x] = srz;
-    pr[blockIdx.x] = srr;
-  }
-  if (!last_block(ticket)) return;
-  const double rz = sum_parts_l2(pz, gridDim.x);
-  const double rr = sum_parts_l2(pr, gridDim.x);
-  if (threadIdx.x == 0) {
-    st->beta = rz / st->rz;
-    st->rz = rz;
-    st->rr = rr;
-    st->it += 1;
-    st->done = !(sqrt(rr) > st->tol * sqrt(st->bb)) || st->it >= st->max_it;
-    *ticket = 0;
-  }
-}
-// The direction and its product of one iteration in one launch: pn = z +
-// beta p (beta = 0 first, so pn = z), Apn = H pn (one thread per output
-// component, reading pn at the block's columns as z + beta p), the partial
-// sums of pn.Apn; the last block: alpha = rz / pn.Apn.  pn is a separate array
-// from p, since other blocks still read p while this one writes pn.
-__global__ __launch_bounds__(SUM_T) void k_cg_dir(const int* __restrict__ rowptr, const int* __restrict__ col,
-                                                  const double* __restrict__ B, int nv, const double* __restrict__ z,
-                                                  const double* __restrict__ p, double* __restrict__ pn,
-                                                  double* __restrict__ Ap, double* __restrict__ part, unsigned* ticket,
-                                                  CgState* st) {
-  if (st->done) return;
-  const double beta = st->beta;
-  const int t = blockIdx.x * SUM_T + threadIdx.x;
+  const int t = blockIdx.x * CG_T + threadIdx.x;
   double dot = 0.0;
   if (t < 3 * nv) {
-    const int i = t / 3, r = t - 3 * i;
+    const int v = t / 3, r = t - 3 * v;
     double s = 0.0;
-    for (int k = rowptr[i]; k < rowptr[i + 1]; k++) {
+    for (int k = rowptr[v]; k < rowptr[v + 1]; k++) {
       const int64_t j = col[k];
       const double* b = B + 9 * (int64_t)k + 3 * r;
       const double v0 = z[3 * j] + beta * p[3 * j];
@@ -1031,13 +1009,43 @@ __global__ __launch_bounds__(SUM_T) void k_cg_dir(const int* __restrict__ rowptr
     pn[t] = pt;
     dot = pt * s;
   }
-  dot = block_sum(dot);
+  dot = wave_sum(dot);
   if (threadIdx.x == 0) part[blockIdx.x] = dot;
-  if (!last_block(ticket)) return;
-  const double pap = sum_parts_l2(part, gridDim.x);
+}
+
+// Iteration i, second half: alpha = (r.z) / (p.Ap) from the first half's
+// partials, x += alpha p, r -= alpha Ap, z = D^-1 r, and the partial sums of
+// r.z and r.r for the next iteration's first half.
+__global__ __launch_bounds__(CG_T) void k_cg_step(double* __restrict__ x, double* __restrict__ r,
+                                                  double* __restrict__ z, const double* __restrict__ p,
+                                                  const double* __restrict__ Ap, const double* __restrict__ Di,
+                                                  int nv, const double* __restrict__ part, int nbd,
+                                                  double* __restrict__ pz, double* __restrict__ pr, int i,
+                                                  const CgState* st) {
+  if (st->done) return;
+  const double a = st->rzs[i & 1] / sum_parts_wave(part, nbd);
+  double srz = 0.0, srr = 0.0;
+  const int v = blockIdx.x * CG_T + threadIdx.x;
+  if (v < nv) {
+    double rv[3];
+    for (int c = 0; c < 3; c++) {
+      x[3 * v + c] += a * p[3 * v + c];
+      r[3 * v + c] -= a * Ap[3 * v + c];
+      rv[c] = r[3 * v + c];
+    }
+    const double* d = Di + 9 * (int64_t)v;
+    for (int c = 0; c < 3; c++) {
+      const double zc = d[3 * c] * rv[0] + d[3 * c + 1] * rv[1] + d[3 * c + 2] * rv[2];
+      z[3 * v + c] = zc;
+      srz += rv[c] * zc;
+      srr += rv[c] * rv[c];
+    }
+  }
+  srz = wave_sum(srz);
+  srr = wave_sum(srr);
   if (threadIdx.x == 0) {
-    st->alpha = st->rz / pap;
-    *ticket = 0;
+    pz[blockIdx.x] = srz;
+    pr[blockIdx.x] = srr;
   }
 }
 
@@ -1857,14 +1865,12 @@ struct Projection {
   int solve(double* dir) {
     const int64_t n3 = 3 * (int64_t)nv;
     const unsigned nb = sum_blocks(n3);
-    const unsigned nbv = nblk(nv, SUM_T);
-    const unsigned nbd = nblk(n3, SUM_T);
+    const unsigned nbv = nblk(nv, CG_T);
+    const unsigned nbd = nblk(n3, CG_T);
     double* pz = ws.get<double>("pj.cgpz", nbv);
     double* pr = ws.get<double>("pj.cgpr", nbv);
     double* pp = ws.get<double>("pj.cgpp", nbd);
     double* p2 = ws.get<double>("pj.cgp2", n3);  // the other direction buffer
-    unsigned* ticket = ws.get<unsigned>("pj.ticket", 2);
-    PAMO_HIP(hipMemsetAsync(ticket, 0, 2 * sizeof(unsigned), s));
     CgState h{};
     h.tol = o.cg_tol;
     h.max_it = o.cg_max;
@@ -1878,12 +1884,13 @@ struct Projection {
     hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(SUM_T), 0, s, (const double*)part, (const double*)part2, (int)nb, cg);
     double* pa = cp;  // this iteration's direction goes into pb
     double* pb = p2;
-    for (;;) {
-      for (int k = 0; k < 8; k++) {
-        hipLaunchKernelGGL(k_cg_dir, dim3(nbd), dim3(SUM_T), 0, s, (const int*)rowptr, (const int*)bcol,
-                           (const double*)bval, nv, (const double*)cz, (const double*)pa, pb, cAp, pp, ticket, cg);
-        hipLaunchKernelGGL(k_cg_step, dim3(nbv), dim3(SUM_T), 0, s, cx, cr, cz, (const double*)pb, (const double*)cAp,
-                           (const double*)Dinv, nv, pz, pr, ticket + 1, cg);
+    for (int it = 0;;) {
+      for (int k = 0; k < 8; k++, it++) {
+        hipLaunchKernelGGL(k_cg_dir, dim3(nbd), dim3(CG_T), 0, s, (const int*)rowptr, (const int*)bcol,
+                           (const double*)bval, nv, (const double*)cz, (const double*)pa, pb, cAp, pp,
+                           (const double*)pz, (const double*)pr, (int)nbv, it, cg);
+        hipLaunchKernelGGL(k_cg_step, dim3(nbv), dim3(CG_T), 0, s, cx, cr, cz, (const double*)pb, (const double*)cAp,
+                           (const double*)Dinv, nv, (const double*)pp, (int)nbd, pz, pr, it, (const CgState*)cg);
         std::swap(pa, pb);
       }
       check_launch();
