@@ -1344,9 +1344,30 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a, const int* __restrict_
     const BvhNode nd = a.nodes[node];
     const int m = child_hits(nd, b) & later_mask(node, L, a.D, i);
     if (L == a.D - 1) {
+      // the leaf hits of every lane at this step go out with one atomic for
+      // the wave (a lane's count, at most 4, is summed over the lanes below it
+      // bit by bit from three ballots)
       const int lf[4] = {nd.leaf.x, nd.leaf.y, nd.leaf.z, nd.leaf.w};
+      const int mine = __popc(m);
+      const uint64_t below = (1ull << (threadIdx.x & 63)) - 1;
+      int pre = 0, tot = 0;
+#pragma unroll
+      for (int bit = 0; bit < 3; bit++) {
+        const uint64_t bb = __ballot((mine >> bit) & 1);
+        pre += __popcll(bb & below) << bit;
+        tot += __popcll(bb) << bit;
+      }
+      const uint64_t act = __ballot(1);
+      const int leader = __ffsll((long long)act) - 1;
+      int base = 0;
+      if ((threadIdx.x & 63) == leader && tot) base = atomicAdd(&a.cnt[3], tot);
+      base = __shfl(base, leader, 64);
+      int k = base + pre;
       for (int c = 0; c < 4; c++)
-        if ((m >> c) & 1) emit_pair(a, t, lf[c]);
+        if ((m >> c) & 1) {
+          if (k < a.fcap) a.fpair[k] = make_int2(t, lf[c]);
+          k++;
+        }
     } else {
       pend |= (uint64_t)m << (4 * L);
     }
