@@ -442,26 +442,17 @@ __global__ __launch_bounds__(256) void k_elem_psd(double* __restrict__ H, int n)
         myoff = k == partner ? a[k] : myoff;
       }
       const double pdiag = __shfl(mydiag, partner, PSD_G);
-      // the rotation of this lane's pair, computed on its smaller lane p
-      double c = 1.0, sn = 0.0, t = 0.0, app = mydiag, aqq = pdiag, apq = myoff;
-      if (act && isp && apq != 0.0) {
+      const double poff = __shfl(myoff, partner, PSD_G);
+      // the rotation of this lane's pair: both lanes compute it from the same
+      // three values (the off-diagonal entry as the smaller lane p holds it),
+      // so they get the same bits without sending the rotation across
+      const double app = isp ? mydiag : pdiag, aqq = isp ? pdiag : mydiag, apq = isp ? myoff : poff;
+      double c = 1.0, sn = 0.0, t = 0.0;
+      if (act && apq != 0.0) {
         const double th = (aqq - app) / (2.0 * apq);
         t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
         c = 1.0 / sqrt(t * t + 1.0);
         sn = t * c;
-      }
-      {
-        const double c2 = __shfl(c, partner, PSD_G), s2 = __shfl(sn, partner, PSD_G), t2 = __shfl(t, partner, PSD_G);
-        const double app2 = __shfl(app, partner, PSD_G), aqq2 = __shfl(aqq, partner, PSD_G);
-        const double apq2 = __shfl(apq, partner, PSD_G);
-        if (!isp) {
-          c = c2;
-          sn = s2;
-          t = t2;
-          app = app2;
-          aqq = aqq2;
-          apq = apq2;
-        }
       }
       // columns of every pair (A J) and rows of Q, with each pair's rotation
 #pragma unroll
