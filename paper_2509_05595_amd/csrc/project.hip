@@ -411,6 +411,12 @@ __global__ __launch_bounds__(256) void k_elem_psd(double* __restrict__ H, int n)
   // in registers it would hold the kernel to one wave a SIMD
   __shared__ double qs[N][256];
   double* q = &qs[0][threadIdx.x];
+  // the lane's row of A J for its partner to read, and the rotation of the
+  // lane's pair at its smaller lane, exchanged through LDS (fewer and wider
+  // operations than lane shuffles); the 16 lanes of a group are in one wave
+  __shared__ double rw[N][256];
+  __shared__ double csb[2][256];
+  const int gbase = threadIdx.x & ~(PSD_G - 1);
   double a[N];
 #pragma unroll
   for (int k = 0; k < N; k++) {
@@ -454,13 +460,19 @@ __global__ __launch_bounds__(256) void k_elem_psd(double* __restrict__ H, int n)
         c = 1.0 / sqrt(t * t + 1.0);
         sn = t * c;
       }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the last step's reads are done
+      if (act && isp) {
+        csb[0][threadIdx.x] = c;
+        csb[1][threadIdx.x] = sn;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       // columns of every pair (A J) and rows of Q, with each pair's rotation
 #pragma unroll
       for (int k = 0; k < M / 2; k++) {
         const int pa = rr_a(M, st, k), pb = rr_b(M, st, k);
         const int pp = pa < pb ? pa : pb, qq = pa < pb ? pb : pa;
         if (qq >= N) continue;
-        const double ck = __shfl(c, pp, PSD_G), sk = __shfl(sn, pp, PSD_G);
+        const double ck = csb[0][gbase + pp], sk = csb[1][gbase + pp];
         const double arp = a[pp], arq = a[qq];
         a[pp] = ck * arp - sk * arq;
         a[qq] = sk * arp + ck * arq;
@@ -469,9 +481,12 @@ __global__ __launch_bounds__(256) void k_elem_psd(double* __restrict__ H, int n)
         q[256 * qq] = sk * qrp + ck * qrq;
       }
       // rows (J^T (A J)) from the partner's row
+#pragma unroll
+      for (int k = 0; k < N; k++) rw[k][threadIdx.x] = a[k];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       double o[N];
 #pragma unroll
-      for (int k = 0; k < N; k++) o[k] = __shfl(a[k], partner, PSD_G);
+      for (int k = 0; k < N; k++) o[k] = rw[k][gbase + partner];
       if (act) {
         if (isp) {
 #pragma unroll
