@@ -1552,6 +1552,13 @@ struct Projection {
   hipStream_t s;
   pamo_project_options o;
   int nv, nf, ne = 0, m;
+  // a leaf order of the faces carried from walk to walk: the vertices move
+  // little between two walks, so the sorted order of an earlier walk still
+  // gives a tight tree (any order gives a correct one); sorted afresh every
+  // LEAF_RESORT walks
+  static constexpr int LEAF_RESORT = 16;
+  int* lord = nullptr;
+  int lord_age = LEAF_RESORT;
   const int* F;
   const double* X0;
   const double* Y;
@@ -1689,7 +1696,15 @@ struct Projection {
   void walk(const double* X, const double* P, double pad) {
     float* box = ws.get<float>("pj.box", 6 * (int64_t)nf);
     hipLaunchKernelGGL(k_boxes, dim3(nblk(nf)), dim3(256), 0, s, X, P, F, nf, pad, box);
-    Bvh b = build_bvh(ws, s, box, nf, nullptr);
+    const bool reuse = lord && lord_age < LEAF_RESORT;
+    Bvh b = build_bvh(ws, s, box, nf, reuse ? lord : nullptr);
+    if (reuse) {
+      lord_age++;
+    } else if (nf >= 2) {
+      lord = ws.get<int>("pj.lord", nf);
+      PAMO_HIP(hipMemcpyAsync(lord, b.sorted, (size_t)nf * sizeof(int), hipMemcpyDeviceToDevice, s));
+      lord_age = 1;
+    }
     WalkArgs a{};
     a.nodes = b.nodes;
     a.D = b.D;
