@@ -1725,7 +1725,7 @@ struct Projection {
     a.step = stepbits;
     a.fpair = fpair;
     a.fcap = fcap;
-    if (nf >= 2) hipLaunchKernelGGL(k_walk, dim3(nblk(nf)), dim3(256), 0, s, a, b.sorted);
+    if (nf >= 2) hipLaunchKernelGGL(k_walk, dim3(nblk(nf, 64)), dim3(64), 0, s, a, b.sorted);  // one-wave blocks
     else hipLaunchKernelGGL(k_walk_small, dim3(1), dim3(1), 0, s, a);
     hipLaunchKernelGGL(k_pair_slots, dim3(1024), dim3(256), 0, s, a);
     check_launch();
@@ -1999,12 +1999,13 @@ void project_targets(Workspace& ws, hipStream_t s, const double* X, int nv, cons
   const int* vorder = point_order(X, nv, "pj.vcode", "pj.vord");
   const int* sorder = m > 0 ? point_order(Y, m, "pj.scode", "pj.sord") : nullptr;
   Bvh b = build_bvh(ws, s, box, nfin, nullptr);
-  hipLaunchKernelGGL(k_nearest, dim3(nblk(nv)), dim3(256), 0, s, (const BvhNode*)b.nodes, b.D, nfin, Vin, Fin, X,
+  // one-wave blocks: a few thousand long walks spread over all the CUs
+  hipLaunchKernelGGL(k_nearest, dim3(nblk(nv, 64)), dim3(64), 0, s, (const BvhNode*)b.nodes, b.D, nfin, Vin, Fin, X,
                      vorder, nv, targets, (int*)nullptr, err);
   if (m > 0) {
     hipLaunchKernelGGL(k_boxes, dim3(nblk(nf)), dim3(256), 0, s, X, (const double*)nullptr, F, nf, 0.0, box);
     Bvh c = build_bvh(ws, s, box, nf, nullptr);
-    hipLaunchKernelGGL(k_nearest, dim3(nblk(m)), dim3(256), 0, s, (const BvhNode*)c.nodes, c.D, nf, X, F, Y, sorder, m,
+    hipLaunchKernelGGL(k_nearest, dim3(nblk(m, 64)), dim3(64), 0, s, (const BvhNode*)c.nodes, c.D, nf, X, F, Y, sorder, m,
                        (double*)nullptr, tri, err);
   }
   check_launch();
