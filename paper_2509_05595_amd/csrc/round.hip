@@ -892,8 +892,9 @@ __global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* _
                                                      const int* __restrict__ ncand, const uint64_t* __restrict__ key,
                                                      uint8_t* __restrict__ reason, double* __restrict__ vbar_out,
                                                      uint64_t* __restrict__ ckey, int* err, int* __restrict__ hist) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= *ncand) return;
+  int64_t ce;  // XCD-contiguous ranges of the candidate list
+  const int c = (int)xcd_item(*ncand, blockDim.x, threadIdx.x, &ce);
+  if (c >= ce) return;
   int h = cand[c];
   ckey[c] = key[h];
   P3 vbar{0, 0, 0};
@@ -967,8 +968,9 @@ __global__ __launch_bounds__(256) void k_apply(MeshView m, const int* __restrict
                                                const uint8_t* __restrict__ reason, const double* __restrict__ vbar,
                                                double* __restrict__ oldpos, int* __restrict__ owner,
                                                uint8_t* __restrict__ falive, float* __restrict__ box) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= *ncand || reason[c] != 0) return;
+  int64_t ce;  // XCD-contiguous ranges of the candidate list
+  const int c = (int)xcd_item(*ncand, blockDim.x, threadIdx.x, &ce);
+  if (c >= ce || reason[c] != 0) return;
   int h = cand[c];
   int t = m.twin[h];
   int a = m.F[h], b = m.F[he_next(h)];
@@ -1059,8 +1061,9 @@ __global__ __launch_bounds__(256) void k_apply(MeshView m, const int* __restrict
 __global__ __launch_bounds__(256) void k_undo(MeshView m, const int* __restrict__ cand, const int* __restrict__ ncand,
                                               const int* __restrict__ undone, int iter,
                                               const double* __restrict__ oldpos, uint8_t* __restrict__ falive) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= *ncand || undone[c] != iter) return;
+  int64_t ce;  // XCD-contiguous ranges of the candidate list
+  const int c = (int)xcd_item(*ncand, blockDim.x, threadIdx.x, &ce);
+  if (c >= ce || undone[c] != iter) return;
   int h = cand[c];
   int t = m.twin[h];
   int a = m.F[h], b = m.F[he_next(h)];
@@ -1116,8 +1119,9 @@ __global__ __launch_bounds__(256) void k_commit(MeshView m, const int* __restric
     if (blockIdx.x == 0 && threadIdx.x == 0) *gin.flag = shut ? 1 : 0;
     if (shut) return;
   }
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= *ncand || reason[c] != 0) return;
+  int64_t ce;  // XCD-contiguous ranges of the candidate list
+  const int c = (int)xcd_item(*ncand, blockDim.x, threadIdx.x, &ce);
+  if (c >= ce || reason[c] != 0) return;
   if (undone[c]) {
     reason[c] = 3;
     return;
@@ -1144,8 +1148,9 @@ __global__ __launch_bounds__(256) void k_commit(MeshView m, const int* __restric
 __global__ void k_flags(MeshView m, const int* __restrict__ cand, const int* __restrict__ ncand,
                         const uint8_t* __restrict__ reason, int* __restrict__ hist, const int* __restrict__ gate) {
   if (gate && *gate) return;
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= *ncand) return;
+  int64_t ce;  // XCD-contiguous ranges of the candidate list
+  const int c = (int)xcd_item(*ncand, blockDim.x, threadIdx.x, &ce);
+  if (c >= ce) return;
   uint8_t rs = reason[c];
   if (rs >= 1 && rs <= 3) {
     int h = cand[c];
@@ -1428,6 +1433,8 @@ __global__ void k_batch_output(MeshView mv, const int* __restrict__ f_off, const
 }
 
 inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
+// grids for xcd_item: a multiple of 8 blocks
+inline unsigned nblk8(int64_t n, int t = 256) { return (nblk(n, t) + 7u) & ~7u; }
 
 }  // namespace
 
@@ -1552,7 +1559,7 @@ void launch_reselect(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* k
 void launch_local_check(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const int* cand,
                         const int* ncand, int cand_bound, const uint64_t* key, uint8_t* reason, double* vbar,
                         uint64_t* ckey, int* err, int* hist) {
-  hipLaunchKernelGGL(k_local_check, dim3(nblk(cand_bound)), dim3(256), 0, s, m, Q, w_e, w_s, cand, ncand, key, reason,
+  hipLaunchKernelGGL(k_local_check, dim3(nblk8(cand_bound)), dim3(256), 0, s, m, Q, w_e, w_s, cand, ncand, key, reason,
                      vbar, ckey, err, hist);
   PAMO_HIP(hipGetLastError());
 }
@@ -1576,14 +1583,14 @@ void launch_face_boxes(hipStream_t s, MeshView m, float* box) {
 
 void launch_apply(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const uint8_t* reason,
                   const double* vbar, double* oldpos, int* owner, uint8_t* falive, float* box) {
-  hipLaunchKernelGGL(k_apply, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, vbar, oldpos, owner,
+  hipLaunchKernelGGL(k_apply, dim3(nblk8(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, vbar, oldpos, owner,
                      falive, box);
   PAMO_HIP(hipGetLastError());
 }
 
 void launch_undo(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const int* undone,
                  int iter, const double* oldpos, uint8_t* falive) {
-  hipLaunchKernelGGL(k_undo, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, undone, iter, oldpos, falive);
+  hipLaunchKernelGGL(k_undo, dim3(nblk8(cand_bound)), dim3(256), 0, s, m, cand, ncand, undone, iter, oldpos, falive);
   PAMO_HIP(hipGetLastError());
 }
 
@@ -1600,13 +1607,13 @@ void launch_face_list(Workspace& ws, hipStream_t s, int nf, const int* owner, co
 
 void launch_commit(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, uint8_t* reason,
                    const int* undone, uint8_t* valive, GateIn gin) {
-  hipLaunchKernelGGL(k_commit, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, undone, valive, gin);
+  hipLaunchKernelGGL(k_commit, dim3(nblk8(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, undone, valive, gin);
   PAMO_HIP(hipGetLastError());
 }
 
 void launch_flags(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound,
                   const uint8_t* reason, int* hist, const int* gate) {
-  hipLaunchKernelGGL(k_flags, dim3(nblk(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, hist, gate);
+  hipLaunchKernelGGL(k_flags, dim3(nblk8(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, hist, gate);
   PAMO_HIP(hipGetLastError());
 }
 
