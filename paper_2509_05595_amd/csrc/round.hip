@@ -569,20 +569,41 @@ __device__ __forceinline__ bool link_holds(const MeshView& m, int h) {
 
 // some generated triangle (corners after the collapse to vbar) degenerate or
 // with its normal turned by 90 degrees or more against the original
+// triangle o0 o1 o2 becomes p0 p1 p2: degenerate, or its normal turned by 90
+// degrees or more
+__device__ __forceinline__ bool turned(P3 o0, P3 o1, P3 o2, P3 p0, P3 p1, P3 p2) {
+  if (degenerate(p0, p1, p2)) return true;
+  double ax = o1.x - o0.x, ay = o1.y - o0.y, az = o1.z - o0.z;
+  double bx = o2.x - o0.x, by = o2.y - o0.y, bz = o2.z - o0.z;
+  double nox = ay * bz - az * by, noy = az * bx - ax * bz, noz = ax * by - ay * bx;
+  double cx = p1.x - p0.x, cy = p1.y - p0.y, cz = p1.z - p0.z;
+  double dx = p2.x - p0.x, dy = p2.y - p0.y, dz = p2.z - p0.z;
+  double nnx = cy * dz - cz * dy, nny = cz * dx - cx * dz, nnz = cx * dy - cy * dx;
+  double dot = nox * nnx + noy * nny + noz * nnz;
+  return !(dot > 0.0);
+}
+
+// the same test with the filters alone: 1 turned (or degenerate with its
+// normal not kept), 0 kept and certainly not degenerate, 2 undecided (every
+// projection of p0 p1 p2 within the filter's error bound of zero)
+__device__ __forceinline__ int turned_filter(P3 o0, P3 o1, P3 o2, P3 p0, P3 p1, P3 p2) {
+  double ax = o1.x - o0.x, ay = o1.y - o0.y, az = o1.z - o0.z;
+  double bx = o2.x - o0.x, by = o2.y - o0.y, bz = o2.z - o0.z;
+  double nox = ay * bz - az * by, noy = az * bx - ax * bz, noz = ax * by - ay * bx;
+  double cx = p1.x - p0.x, cy = p1.y - p0.y, cz = p1.z - p0.z;
+  double dx = p2.x - p0.x, dy = p2.y - p0.y, dz = p2.z - p0.z;
+  double nnx = cy * dz - cz * dy, nny = cz * dx - cx * dz, nnz = cx * dy - cy * dx;
+  double dot = nox * nnx + noy * nny + noz * nnz;
+  if (!(dot > 0.0)) return 1;
+  for (int k = 0; k < 3; k++)
+    if (orient2d_filter(pu(p0, k), pv(p0, k), pu(p1, k), pv(p1, k), pu(p2, k), pv(p2, k)) != UNK) return 0;
+  return 2;
+}
+
 __device__ __forceinline__ bool flipped_after(const MeshView& m, const EdgeStars& E, P3 vbar) {
   const int s = E.s, r = E.r;
   bool bad = false;
-  auto flipped = [&](P3 o0, P3 o1, P3 o2, P3 p0, P3 p1, P3 p2) {
-    if (degenerate(p0, p1, p2)) return true;
-    double ax = o1.x - o0.x, ay = o1.y - o0.y, az = o1.z - o0.z;
-    double bx = o2.x - o0.x, by = o2.y - o0.y, bz = o2.z - o0.z;
-    double nox = ay * bz - az * by, noy = az * bx - ax * bz, noz = ax * by - ay * bx;
-    double cx = p1.x - p0.x, cy = p1.y - p0.y, cz = p1.z - p0.z;
-    double dx = p2.x - p0.x, dy = p2.y - p0.y, dz = p2.z - p0.z;
-    double nnx = cy * dz - cz * dy, nny = cz * dx - cx * dz, nnz = cx * dy - cy * dx;
-    double dot = nox * nnx + noy * nny + noz * nnz;
-    return !(dot > 0.0);
-  };
+  auto flipped = [&](P3 o0, P3 o1, P3 o2, P3 p0, P3 p1, P3 p2) { return turned(o0, o1, o2, p0, p1, p2); };
   if (E.fast) {
     // corner g % 3 of a star face is the star's vertex (position pc before,
     // vbar after); no other corner is s or r; the other two are loaded
@@ -649,6 +670,85 @@ __device__ __forceinline__ uint8_t local_reason(const MeshView& m, const double*
   if (!ok) set_err(err, PAMO_EBIT_RING);
   vbar = vb;
   return flipped_after(m, E, vb) ? 2 : 0;
+}
+
+// The local checks of one candidate split over LC consecutive lanes (stored
+// stars only).  Every lane loads the edge, its stars and the placement (the
+// same addresses, merged by the memory pipeline); lane `part` then compares
+// one LC-th of b's neighbours against a's and tests two of every four faces
+// of one star (parts 0 and 1 the star of s, 2 and 3 that of r).  The group
+// sums the common neighbours and ORs the flip results: the same decisions as
+// local_reason, in a quarter of its dependent loads and arithmetic.  The
+// degeneracy test runs on its filters only; a candidate that needs the exact
+// test (or whose stars are not stored) gets REASON_LATE and is decided by
+// local_reason in a second kernel, which keeps the exact arithmetic's
+// registers and scratch out of this one.
+constexpr int LC = 4;
+constexpr uint8_t REASON_LATE = 5;
+
+// common neighbours of a and b over the slots j of b's star with j % LC == part
+__device__ __forceinline__ int link_common_part(const MeshView& m, int a, int na, int b, int nb, int part) {
+  int ga[VSTAR];
+  star_all(m, a, na, ga);
+  int wa[VSTAR], wb[VSTAR / LC];
+#pragma unroll
+  for (int i = 0; i < VSTAR; i++) wa[i] = m.F[he_next(ga[i])];
+#pragma unroll
+  for (int q = 0; q < VSTAR / LC; q++) {
+    const int j = LC * q + part;
+    wb[q] = m.F[he_next(m.vstar[(int64_t)VSTAR * b + (j < nb ? j : 0)])];
+  }
+  int common = 0;
+#pragma unroll
+  for (int q = 0; q < VSTAR / LC; q++) {
+    bool in = false;
+#pragma unroll
+    for (int i = 0; i < VSTAR; i++) in |= i < na && wa[i] == wb[q];
+    common += LC * q + part < nb && in;
+  }
+  return common;
+}
+
+// the flip test over faces 2 half, 2 half + 1 of every chunk of four of the
+// star of s (part < 2) or r, half = part & 1
+// (0 none turned, 1 some face turned, 2 none certainly turned, some undecided)
+__device__ __forceinline__ int flipped_part(const MeshView& m, const EdgeStars& E, P3 vbar, int part) {
+  const bool on_s = part < LC / 2;
+  const bool half = part & 1;
+  const int v = on_s ? E.s : E.r;
+  const P3 pc = ld3(m.V, v);
+  bool bad = false, und = false;
+  star_chunks(m, v, on_s ? E.ns : E.nr, E.f1, E.f2, E.hs, [&](const int* g, const bool* use) {
+    P3 o[2][3];
+    int ci[2];
+    bool u[2];
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const int gk = half ? g[2 + k] : g[k];
+      u[k] = half ? use[2 + k] : use[k];
+      const int f = gk / 3;
+      ci[k] = gk - 3 * f;
+      int c[3];
+#pragma unroll
+      for (int i = 0; i < 3; i++) c[i] = m.F[3 * (int64_t)f + i];
+      const int c1 = ci[k] == 2 ? 0 : ci[k] + 1, c2 = ci[k] == 0 ? 2 : ci[k] - 1;
+      const P3 q1 = ld3(m.V, c1 == 0 ? c[0] : c1 == 1 ? c[1] : c[2]);
+      const P3 q2 = ld3(m.V, c2 == 0 ? c[0] : c2 == 1 ? c[1] : c[2]);
+#pragma unroll
+      for (int i = 0; i < 3; i++) o[k][i] = i == ci[k] ? pc : i == c1 ? q1 : q2;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      if (!u[k] || bad) continue;
+      P3 p[3];
+#pragma unroll
+      for (int i = 0; i < 3; i++) p[i] = i == ci[k] ? vbar : o[k][i];
+      const int t = turned_filter(o[k][0], o[k][1], o[k][2], p[0], p[1], p[2]);
+      bad = t == 1;
+      und |= t == 2;
+    }
+  });
+  return bad ? 1 : und ? 2 : 0;
 }
 
 // ------------------------------------------------------------ cost + keys
@@ -892,17 +992,62 @@ __global__ __launch_bounds__(256) void k_local_check(MeshView m, const double* _
                                                      const int* __restrict__ ncand, const uint64_t* __restrict__ key,
                                                      uint8_t* __restrict__ reason, double* __restrict__ vbar_out,
                                                      uint64_t* __restrict__ ckey, int* err, int* __restrict__ hist) {
-  int64_t ce;  // XCD-contiguous ranges of the candidate list
+  int64_t ce;  // XCD-contiguous ranges of the candidate list, LC lanes per candidate
+  const int c = (int)xcd_item(*ncand, blockDim.x / LC, threadIdx.x / LC, &ce);
+  const int part = threadIdx.x % LC;
+  if (c >= ce) return;  // the whole group
+  const int h = cand[c];
+  P3 vbar{0, 0, 0};
+  uint8_t rs = 0;
+  EdgeStars E;
+  edge_stars(m, h, E);
+  if (E.fast) {  // uniform over the group
+    const P3 vb = edge_placement(m, Q, E);
+    const bool a_is_s = m.F[h] == E.s;
+    const int na = a_is_s ? E.ns : E.nr, nb = a_is_s ? E.nr : E.ns;
+    int common = link_common_part(m, a_is_s ? E.s : E.r, na, a_is_s ? E.r : E.s, nb, part);
+    const int fl = flipped_part(m, E, vb, part);
+    int bad = fl == 1, und = fl == 2;
+#pragma unroll
+    for (int o = 1; o < LC; o <<= 1) {
+      common += __shfl_xor(common, o);
+      bad |= __shfl_xor(bad, o);
+      und |= __shfl_xor(und, o);
+    }
+    // a candidate failing the link test keeps reason 1 and no placement
+    const bool link = common == 2 && !(na == 3 && nb == 3);
+    rs = !link ? 1 : bad ? 2 : und ? REASON_LATE : 0;
+    if (link) vbar = vb;
+  } else {
+    rs = REASON_LATE;
+  }
+  if (part == 0) {
+    ckey[c] = key[h];
+    reason[c] = rs;
+    vbar_out[3 * (int64_t)c] = vbar.x;
+    vbar_out[3 * (int64_t)c + 1] = vbar.y;
+    vbar_out[3 * (int64_t)c + 2] = vbar.z;
+  }
+  wave_hist(part == 0 ? rs : -1, hist);
+}
+
+// the candidates left to the exact tests (REASON_LATE), one lane each
+__global__ __launch_bounds__(256) void k_local_late(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
+                                                    const int* __restrict__ cand, const int* __restrict__ ncand,
+                                                    uint8_t* __restrict__ reason, double* __restrict__ vbar_out,
+                                                    int* err, int* __restrict__ hist) {
+  int64_t ce;
   const int c = (int)xcd_item(*ncand, blockDim.x, threadIdx.x, &ce);
   if (c >= ce) return;
-  int h = cand[c];
-  ckey[c] = key[h];
-  P3 vbar{0, 0, 0};
-  const uint8_t rs = local_reason(m, Q, w_e, w_s, h, vbar, err);
-  reason[c] = rs;
-  vbar_out[3 * (int64_t)c] = vbar.x;
-  vbar_out[3 * (int64_t)c + 1] = vbar.y;
-  vbar_out[3 * (int64_t)c + 2] = vbar.z;
+  int rs = -1;
+  if (reason[c] == REASON_LATE) {
+    P3 vbar{0, 0, 0};
+    rs = local_reason(m, Q, w_e, w_s, cand[c], vbar, err);
+    reason[c] = rs;
+    vbar_out[3 * (int64_t)c] = vbar.x;
+    vbar_out[3 * (int64_t)c + 1] = vbar.y;
+    vbar_out[3 * (int64_t)c + 2] = vbar.z;
+  }
   wave_hist(rs, hist);
 }
 
@@ -964,12 +1109,15 @@ __global__ __launch_bounds__(256) void k_face_boxes(MeshView m, float* __restric
 // the smaller id s and moves to vbar, corners of the larger id r are
 // relabelled s, the two faces of the edge die.  Faces of star(a) u star(b)
 // get owner = candidate; their boxes grow to cover the new geometry too.
+// Two lanes per candidate: with stored stars each takes one side of the edge.
+constexpr int AP = 2;
 __global__ __launch_bounds__(256) void k_apply(MeshView m, const int* __restrict__ cand, const int* __restrict__ ncand,
                                                const uint8_t* __restrict__ reason, const double* __restrict__ vbar,
                                                double* __restrict__ oldpos, int* __restrict__ owner,
                                                uint8_t* __restrict__ falive, float* __restrict__ box) {
-  int64_t ce;  // XCD-contiguous ranges of the candidate list
-  const int c = (int)xcd_item(*ncand, blockDim.x, threadIdx.x, &ce);
+  int64_t ce;  // XCD-contiguous ranges of the candidate list, AP lanes per candidate
+  const int c = (int)xcd_item(*ncand, blockDim.x / AP, threadIdx.x / AP, &ce);
+  const int part = threadIdx.x % AP;
   if (c >= ce || reason[c] != 0) return;
   int h = cand[c];
   int t = m.twin[h];
@@ -1022,10 +1170,15 @@ __global__ __launch_bounds__(256) void k_apply(MeshView m, const int* __restrict
         bx[5] = fmaxf(ob[k][5], f_up(fmax(fmax(p[k][0].z, p[k][1].z), p[k][2].z) + oz));
       }
     };
-    star_chunks(m, s, ns, f1, f2, h, [&](const int* g, const bool* use) { side(g, use, false); });
-    star_chunks(m, r, nr, f1, f2, h, [&](const int* g, const bool* use) { side(g, use, true); });
+    // lane 0 the faces around s, lane 1 those around r (relabelled): the two
+    // sets are disjoint, and neither reads a position the other writes
+    const bool on_r = part == 1;
+    star_chunks(m, on_r ? r : s, on_r ? nr : ns, f1, f2, h, [&](const int* g, const bool* use) { side(g, use, on_r); });
+    if (on_r) return;
     owner[f1] = c;
     owner[f2] = c;
+  } else if (part == 1) {
+    return;
   } else {
     auto own = [&](int g) { owner[g / 3] = c; };
     walk_star(m.twin, h, own);
@@ -1559,8 +1712,10 @@ void launch_reselect(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* k
 void launch_local_check(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const int* cand,
                         const int* ncand, int cand_bound, const uint64_t* key, uint8_t* reason, double* vbar,
                         uint64_t* ckey, int* err, int* hist) {
-  hipLaunchKernelGGL(k_local_check, dim3(nblk8(cand_bound)), dim3(256), 0, s, m, Q, w_e, w_s, cand, ncand, key, reason,
+  hipLaunchKernelGGL(k_local_check, dim3(nblk8((int64_t)cand_bound * LC)), dim3(256), 0, s, m, Q, w_e, w_s, cand, ncand, key, reason,
                      vbar, ckey, err, hist);
+  hipLaunchKernelGGL(k_local_late, dim3(nblk8(cand_bound)), dim3(256), 0, s, m, Q, w_e, w_s, cand, ncand, reason, vbar,
+                     err, hist);
   PAMO_HIP(hipGetLastError());
 }
 
@@ -1583,7 +1738,7 @@ void launch_face_boxes(hipStream_t s, MeshView m, float* box) {
 
 void launch_apply(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const uint8_t* reason,
                   const double* vbar, double* oldpos, int* owner, uint8_t* falive, float* box) {
-  hipLaunchKernelGGL(k_apply, dim3(nblk8(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, vbar, oldpos, owner,
+  hipLaunchKernelGGL(k_apply, dim3(nblk8((int64_t)cand_bound * AP)), dim3(256), 0, s, m, cand, ncand, reason, vbar, oldpos, owner,
                      falive, box);
   PAMO_HIP(hipGetLastError());
 }
