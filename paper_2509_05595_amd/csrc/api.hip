@@ -395,6 +395,10 @@ void reserve_mesh(Workspace& w, int64_t nv, int64_t nf, const pamo_options& o, c
     w.get<uint8_t>("bt.use", p.nmesh);
   }
   round_bufs(w, nv, nf);
+  if (o.prefilter) {  // the pre-filter's edges left to the exact flip test
+    w.get<int>("ck.late", 3 * nf / 2 + 1);
+    w.get<int>("ck.nlate", 1);
+  }
   w.get<int2>("q.pairs", pair_capacity(o, nf));
   w.get<int>("ord.copy", nf);
   w.get<float>("w.box", 6 * nf);
@@ -676,7 +680,7 @@ RoundResult run_round(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs& b, i
   }
   {
     TIMED(PH_COST, 220 * nv + 51 * nf);
-    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, cnt + C_ERR, c->opt.cost_target,
+    launch_cost_keys(c->ws, s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, cnt + C_ERR, c->opt.cost_target,
                      c->opt.prefilter != 0, c->opt.key_mode != 0);
   }
   {
@@ -1041,7 +1045,7 @@ RoundResult run_round_batch(pamo_ctx* c, MeshView& cur, MeshView& alt, RoundBufs
   }
   {
     TIMED(PH_COST, 220 * nv + 51 * nf);
-    launch_cost_keys(s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, B.done, b.key, cnt + C_ERR, c->opt.cost_target,
+    launch_cost_keys(c->ws, s, cur, b.Q, c->opt.w_e, c->opt.w_s, nullptr, B.done, b.key, cnt + C_ERR, c->opt.cost_target,
                      c->opt.prefilter != 0, c->opt.key_mode != 0);
   }
   {
@@ -1339,7 +1343,7 @@ pamo_status pamo_select(pamo_ctx* c, const double* V, int64_t nv, const int32_t*
     RoundBufs b = round_bufs(c->ws, nv, nf);
     uint64_t* key = keys ? keys : b.key;
     launch_quadrics(c->stream, A, b.Q, c->dcnt + C_ERR);
-    launch_cost_keys(c->stream, A, b.Q, c->opt.w_e, c->opt.w_s, demote, nullptr, key, c->dcnt + C_ERR,
+    launch_cost_keys(c->ws, c->stream, A, b.Q, c->opt.w_e, c->opt.w_s, demote, nullptr, key, c->dcnt + C_ERR,
                      c->opt.cost_target, c->opt.prefilter != 0, c->opt.key_mode != 0);
     if (c->opt.key_mode) launch_rank_keys(c->ws, c->stream, A, key);
     launch_select(c->ws, c->stream, A, key, b.vmin, cand, ncand);
@@ -1367,7 +1371,7 @@ pamo_status pamo_check(pamo_ctx* c, const double* V, int64_t nv, const int32_t* 
     hipStream_t s = c->stream;
     fill_i32(s, c->dcnt, C_COUNT, 0);
     launch_quadrics(s, A, b.Q, c->dcnt + C_ERR);
-    launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR,
+    launch_cost_keys(c->ws, s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR,
                      c->opt.cost_target, false, c->opt.key_mode != 0);
     if (c->opt.key_mode) launch_rank_keys(c->ws, s, A, b.key);  // the cap orders by key
     int64_t teff = target_faces - target_faces % 2;
@@ -1737,7 +1741,7 @@ pamo_status pamo_features(pamo_ctx* c, const double* V, int64_t nv, const int32_
       A.vdeg = b.vdeg;
       A.vbox = b.vbox;
       launch_quadrics(s, A, b.Q, c->dcnt + C_ERR);
-      launch_cost_keys(s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR,
+      launch_cost_keys(c->ws, s, A, b.Q, c->opt.w_e, c->opt.w_s, nullptr, nullptr, b.key, c->dcnt + C_ERR,
                      c->opt.cost_target);
       fill_i32(s, c->dcnt + C_NCAND, 1, (int)ne);
       launch_features(s, A, b.key, edges, c->dcnt + C_NCAND, (int)ne, A.ovl, X, c->dcnt + C_ERR);

@@ -600,47 +600,82 @@ __device__ __forceinline__ int turned_filter(P3 o0, P3 o1, P3 o2, P3 p0, P3 p1, 
   return 2;
 }
 
+// faces of a chunk of four of the stored star around a vertex at pc (corner
+// g % 3 of each is that vertex and moves to vbar; no other corner is s or r,
+// and the other two are loaded): all four when K = 4, else faces 2 hi and
+// 2 hi + 1.  Every load is issued before any test.  `bad` is set when a face
+// is turned; with EXACT the degeneracy test is exact, else its filters alone
+// decide and `und` is set for a face they leave undecided.
+template <int K, bool EXACT>
+__device__ __forceinline__ void flip_faces(const MeshView& m, const int* g, const bool* use, bool hi, P3 pc, P3 vbar,
+                                           bool& bad, bool& und) {
+  P3 o[K][3];
+  int ci[K];
+  bool u[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    int gk;
+    if constexpr (K == 4) {
+      gk = g[k];
+      u[k] = use[k];
+    } else {
+      gk = hi ? g[2 + k] : g[k];
+      u[k] = hi ? use[2 + k] : use[k];
+    }
+    const int f = gk / 3;
+    ci[k] = gk - 3 * f;
+    int c[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) c[i] = m.F[3 * (int64_t)f + i];
+    const int c1 = ci[k] == 2 ? 0 : ci[k] + 1, c2 = ci[k] == 0 ? 2 : ci[k] - 1;
+    const P3 q1 = ld3(m.V, c1 == 0 ? c[0] : c1 == 1 ? c[1] : c[2]);
+    const P3 q2 = ld3(m.V, c2 == 0 ? c[0] : c2 == 1 ? c[1] : c[2]);
+#pragma unroll
+    for (int i = 0; i < 3; i++) o[k][i] = i == ci[k] ? pc : i == c1 ? q1 : q2;
+  }
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    if (!u[k] || bad) continue;
+    P3 p[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) p[i] = i == ci[k] ? vbar : o[k][i];
+    if constexpr (EXACT) {
+      bad = turned(o[k][0], o[k][1], o[k][2], p[0], p[1], p[2]);
+    } else {
+      const int t = turned_filter(o[k][0], o[k][1], o[k][2], p[0], p[1], p[2]);
+      bad = t == 1;
+      und |= t == 2;
+    }
+  }
+}
+
+// the flip test over both stored stars on the filters alone: 0 no face
+// turned, 1 some face turned, 2 none certainly turned but some undecided
+__device__ __forceinline__ int flipped_filter(const MeshView& m, const EdgeStars& E, P3 vbar) {
+  bool bad = false, und = false;
+  const P3 ps = ld3(m.V, E.s), pr = ld3(m.V, E.r);
+  star_chunks(m, E.s, E.ns, E.f1, E.f2, E.hs,
+              [&](const int* g, const bool* use) { flip_faces<4, false>(m, g, use, false, ps, vbar, bad, und); });
+  star_chunks(m, E.r, E.nr, E.f1, E.f2, E.hs,
+              [&](const int* g, const bool* use) { flip_faces<4, false>(m, g, use, false, pr, vbar, bad, und); });
+  return bad ? 1 : und ? 2 : 0;
+}
+
 __device__ __forceinline__ bool flipped_after(const MeshView& m, const EdgeStars& E, P3 vbar) {
   const int s = E.s, r = E.r;
-  bool bad = false;
-  auto flipped = [&](P3 o0, P3 o1, P3 o2, P3 p0, P3 p1, P3 p2) { return turned(o0, o1, o2, p0, p1, p2); };
+  bool bad = false, und = false;
   if (E.fast) {
-    // corner g % 3 of a star face is the star's vertex (position pc before,
-    // vbar after); no other corner is s or r; the other two are loaded
-    auto chunk = [&](const int* g, const bool* use, P3 pc) {
-      P3 o[4][3];
-      int ci[4];
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const int f = g[k] / 3;
-        ci[k] = g[k] - 3 * f;
-        int c[3];
-#pragma unroll
-        for (int i = 0; i < 3; i++) c[i] = m.F[3 * (int64_t)f + i];
-        const int c1 = ci[k] == 2 ? 0 : ci[k] + 1, c2 = ci[k] == 0 ? 2 : ci[k] - 1;
-        const P3 q1 = ld3(m.V, c1 == 0 ? c[0] : c1 == 1 ? c[1] : c[2]);
-        const P3 q2 = ld3(m.V, c2 == 0 ? c[0] : c2 == 1 ? c[1] : c[2]);
-#pragma unroll
-        for (int i = 0; i < 3; i++) o[k][i] = i == ci[k] ? pc : i == c1 ? q1 : q2;
-      }
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        if (!use[k] || bad) continue;
-        P3 p[3];
-#pragma unroll
-        for (int i = 0; i < 3; i++) p[i] = i == ci[k] ? vbar : o[k][i];
-        bad = flipped(o[k][0], o[k][1], o[k][2], p[0], p[1], p[2]);
-      }
-    };
     const P3 ps = ld3(m.V, s), pr = ld3(m.V, r);
-    star_chunks(m, s, E.ns, E.f1, E.f2, E.hs, [&](const int* g, const bool* use) { chunk(g, use, ps); });
-    star_chunks(m, r, E.nr, E.f1, E.f2, E.hs, [&](const int* g, const bool* use) { chunk(g, use, pr); });
+    star_chunks(m, s, E.ns, E.f1, E.f2, E.hs,
+                [&](const int* g, const bool* use) { flip_faces<4, true>(m, g, use, false, ps, vbar, bad, und); });
+    star_chunks(m, r, E.nr, E.f1, E.f2, E.hs,
+                [&](const int* g, const bool* use) { flip_faces<4, true>(m, g, use, false, pr, vbar, bad, und); });
   } else {
     auto chk = [&](int f) {
       if (bad) return;
       P3 o0 = ld3(m.V, m.F[3 * f]), o1 = ld3(m.V, m.F[3 * f + 1]), o2 = ld3(m.V, m.F[3 * f + 2]);
-      bad = flipped(o0, o1, o2, corner_after(m, f, 0, s, r, vbar), corner_after(m, f, 1, s, r, vbar),
-                    corner_after(m, f, 2, s, r, vbar));
+      bad = turned(o0, o1, o2, corner_after(m, f, 0, s, r, vbar), corner_after(m, f, 1, s, r, vbar),
+                   corner_after(m, f, 2, s, r, vbar));
     };
     star_ascending(m, E, E.hs, chk);
     star_ascending(m, E, E.hr, chk);
@@ -718,36 +753,8 @@ __device__ __forceinline__ int flipped_part(const MeshView& m, const EdgeStars& 
   const int v = on_s ? E.s : E.r;
   const P3 pc = ld3(m.V, v);
   bool bad = false, und = false;
-  star_chunks(m, v, on_s ? E.ns : E.nr, E.f1, E.f2, E.hs, [&](const int* g, const bool* use) {
-    P3 o[2][3];
-    int ci[2];
-    bool u[2];
-#pragma unroll
-    for (int k = 0; k < 2; k++) {
-      const int gk = half ? g[2 + k] : g[k];
-      u[k] = half ? use[2 + k] : use[k];
-      const int f = gk / 3;
-      ci[k] = gk - 3 * f;
-      int c[3];
-#pragma unroll
-      for (int i = 0; i < 3; i++) c[i] = m.F[3 * (int64_t)f + i];
-      const int c1 = ci[k] == 2 ? 0 : ci[k] + 1, c2 = ci[k] == 0 ? 2 : ci[k] - 1;
-      const P3 q1 = ld3(m.V, c1 == 0 ? c[0] : c1 == 1 ? c[1] : c[2]);
-      const P3 q2 = ld3(m.V, c2 == 0 ? c[0] : c2 == 1 ? c[1] : c[2]);
-#pragma unroll
-      for (int i = 0; i < 3; i++) o[k][i] = i == ci[k] ? pc : i == c1 ? q1 : q2;
-    }
-#pragma unroll
-    for (int k = 0; k < 2; k++) {
-      if (!u[k] || bad) continue;
-      P3 p[3];
-#pragma unroll
-      for (int i = 0; i < 3; i++) p[i] = i == ci[k] ? vbar : o[k][i];
-      const int t = turned_filter(o[k][0], o[k][1], o[k][2], p[0], p[1], p[2]);
-      bad = t == 1;
-      und |= t == 2;
-    }
-  });
+  star_chunks(m, v, on_s ? E.ns : E.nr, E.f1, E.f2, E.hs,
+              [&](const int* g, const bool* use) { flip_faces<2, false>(m, g, use, half, pc, vbar, bad, und); });
   return bad ? 1 : und ? 2 : 0;
 }
 
@@ -768,7 +775,7 @@ template <int PW, bool PRE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRE ? 2 : 1))) void k_cost_keys(MeshView m, const double* __restrict__ Q, double w_e, double w_s,
                                                    double cost_max, const uint8_t* __restrict__ demote,
                                                    const uint8_t* __restrict__ mesh_done, uint64_t* __restrict__ key,
-                                                   int* err, bool lex) {
+                                                   int* err, bool lex, int* __restrict__ late, int* __restrict__ nlate) {
   __shared__ int queue[4][PW];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t nh = 3 * (int64_t)m.nf;
@@ -799,11 +806,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRE ? 2 : 1
         k = cost > cost_max ? PAMO_KEY_MAX                                 // above the cost target: never chosen
             : lex        ? cost_code64(cost)
                          : make_key(cost, (uint32_t)h);
-        if (PRE && k != PAMO_KEY_MAX && (!link_holds(m, h) || flipped_after(m, E, vbar))) k = PAMO_KEY_MAX;
+        if (PRE && k != PAMO_KEY_MAX) {
+          // the flip test on its filters; an edge they leave undecided (or
+          // whose stars are not stored) is listed for k_prefilter_late, which
+          // keeps the exact arithmetic's registers out of this kernel
+          const int fl = !link_holds(m, h) ? 1 : E.fast ? flipped_filter(m, E, vbar) : 2;
+          if (fl == 1) k = PAMO_KEY_MAX;
+          if (fl == 2) late[atomicAdd(nlate, 1)] = h;
+        }
       }
     }
     key[h] = k;
     key[t] = k;
+  }
+}
+
+// the listed edges of the pre-filter: the exact flip test, failing edges unkeyed
+__global__ __launch_bounds__(256) void k_prefilter_late(MeshView m, const double* __restrict__ Q,
+                                                        const int* __restrict__ late, const int* __restrict__ nlate,
+                                                        uint64_t* __restrict__ key) {
+  const int n = *nlate;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int h = late[i];
+    EdgeStars E;
+    edge_stars(m, h, E);
+    if (flipped_after(m, E, edge_placement(m, Q, E))) {
+      key[h] = PAMO_KEY_MAX;
+      key[m.twin[h]] = PAMO_KEY_MAX;
+    }
   }
 }
 
@@ -1653,19 +1683,28 @@ void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err) {
   PAMO_HIP(hipGetLastError());
 }
 
-void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
-                      const uint8_t* mesh_done, uint64_t* key, int* err, double cost_target, bool prefilter,
-                      bool lex) {
+void launch_cost_keys(Workspace& ws, hipStream_t s, MeshView m, const double* Q, double w_e, double w_s,
+                      const uint8_t* demote, const uint8_t* mesh_done, uint64_t* key, int* err, double cost_target,
+                      bool prefilter, bool lex) {
   const int64_t nh = 3 * (int64_t)m.nf;
   const double cost_max = cost_target > 0 ? cost_target : INFINITY;
+  int* late = nullptr;
+  int* nlate = nullptr;
+  if (prefilter) {  // at most one entry per edge
+    late = ws.get<int>("ck.late", nh / 2 + 1);
+    nlate = ws.get<int>("ck.nlate", 1);
+    fill_i32(s, nlate, 1, 0);
+  }
   auto go = [&](auto kern, int pw) {
     hipLaunchKernelGGL(kern, dim3(nblk(nh, 4 * pw)), dim3(256), 0, s, m, Q, w_e, w_s, cost_max, demote, mesh_done,
-                       key, err, lex);
+                       key, err, lex, late, nlate);
   };
   if (nh <= CK_SMALL_NH)
     prefilter ? go(k_cost_keys<64, true>, 64) : go(k_cost_keys<64, false>, 64);
   else
     prefilter ? go(k_cost_keys<256, true>, 256) : go(k_cost_keys<256, false>, 256);
+  if (prefilter)
+    hipLaunchKernelGGL(k_prefilter_late, dim3(16), dim3(256), 0, s, m, Q, (const int*)late, (const int*)nlate, key);
   PAMO_HIP(hipGetLastError());
 }
 

@@ -56,9 +56,9 @@ void launch_quadrics(hipStream_t s, MeshView m, double* Q, int* err);
 // cost_target > 0: edges costing more get the largest key (never chosen);
 // prefilter: so do edges failing the local checks of R7 (link condition,
 // degenerate or flipped generated triangles; m needs this round's stars)
-void launch_cost_keys(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const uint8_t* demote,
-                      const uint8_t* mesh_done, uint64_t* key, int* err, double cost_target = 0.0,
-                      bool prefilter = false, bool lex = false);
+void launch_cost_keys(Workspace& ws, hipStream_t s, MeshView m, const double* Q, double w_e, double w_s,
+                      const uint8_t* demote, const uint8_t* mesh_done, uint64_t* key, int* err,
+                      double cost_target = 0.0, bool prefilter = false, bool lex = false);
 // float64 key mode, after launch_cost_keys(lex): each keyed edge's key becomes
 // (rank in the order of (float64 cost, edge id)) << 32 | edge id
 void launch_rank_keys(Workspace& ws, hipStream_t s, MeshView m, uint64_t* key);
