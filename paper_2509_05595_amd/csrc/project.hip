@@ -153,7 +153,9 @@ __device__ int pt_feature(D3 p, D3 a, D3 b, D3 c) {
   return 0;
 }
 
-__device__ __constant__ int EE_OTHER[4][2] = {{2, 3}, {2, 3}, {0, 1}, {0, 1}};
+// end r of the segment that point p (0, 1 on the first, 2, 3 on the second)
+// is not on; with p and r known at compile time the points stay in registers
+__host__ __device__ constexpr int ee_other(int p, int r) { return p < 2 ? 2 + r : r; }
 
 // Closest features of segments P0P1 and P2P3: 0 inside both (not parallel):
 // line against line; 1 + p point p against the other segment's line; 5 + 2 p
@@ -172,8 +174,9 @@ __device__ int ee_feature(const D3* P) {
   }
   double best = INFINITY;
   int code = 0;
+#pragma unroll
   for (int p = 0; p < 4; p++) {
-    const D3 u = P[EE_OTHER[p][0]], v = P[EE_OTHER[p][1]];
+    const D3 u = P[ee_other(p, 0)], v = P[ee_other(p, 1)];
     const D3 ab = v - u, pu = P[p] - u;
     double t = dot(pu, ab) / fmax(dot(ab, ab), 1e-300);
     t = fmin(fmax(t, 0.0), 1.0);
@@ -224,15 +227,24 @@ __device__ T pt_d2(int code, V3<T> p, V3<T> a, V3<T> b, V3<T> c) {
     default: return d2_pp(p, c);
   }
 }
+// (one case per feature code, so that no point is indexed at run time)
 template <class T>
 __device__ T ee_d2(int code, const V3<T>* P) {
-  if (code == 0) return d2_ll(P[0], P[1], P[2], P[3]);
-  if (code <= 4) {
-    const int p = code - 1;
-    return d2_pl(P[p], P[EE_OTHER[p][0]], P[EE_OTHER[p][1]]);
+  switch (code) {
+    case 0: return d2_ll(P[0], P[1], P[2], P[3]);
+    case 1: return d2_pl(P[0], P[ee_other(0, 0)], P[ee_other(0, 1)]);
+    case 2: return d2_pl(P[1], P[ee_other(1, 0)], P[ee_other(1, 1)]);
+    case 3: return d2_pl(P[2], P[ee_other(2, 0)], P[ee_other(2, 1)]);
+    case 4: return d2_pl(P[3], P[ee_other(3, 0)], P[ee_other(3, 1)]);
+    case 5: return d2_pp(P[0], P[ee_other(0, 0)]);
+    case 6: return d2_pp(P[0], P[ee_other(0, 1)]);
+    case 7: return d2_pp(P[1], P[ee_other(1, 0)]);
+    case 8: return d2_pp(P[1], P[ee_other(1, 1)]);
+    case 9: return d2_pp(P[2], P[ee_other(2, 0)]);
+    case 10: return d2_pp(P[2], P[ee_other(2, 1)]);
+    case 11: return d2_pp(P[3], P[ee_other(3, 0)]);
+    default: return d2_pp(P[3], P[ee_other(3, 1)]);
   }
-  const int p = (code - 5) >> 1, r = (code - 5) & 1;
-  return d2_pp(P[p], P[EE_OTHER[p][r]]);
 }
 __device__ __forceinline__ double pt_dist2(D3 p, D3 a, D3 b, D3 c) { return pt_d2<double>(pt_feature(p, a, b, c), p, a, b, c); }
 __device__ __forceinline__ double ee_dist2(const D3* P) { return ee_d2<double>(ee_feature(P), P); }
