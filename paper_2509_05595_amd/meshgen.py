@@ -202,6 +202,38 @@ def torus(n: int, m: int, R: float = 1.0, r: float = 0.35):
     return v, f, nrm
 
 
+def grid_cube(n: int = 6):
+    """Unit cube with every side an n x n grid of squares, each split along the
+    same diagonal, outward: flat sides whose collapses can make exactly
+    collinear triangles (the degeneracy test's exact case)."""
+    keys, verts, faces = {}, [], []
+
+    def vid(p):
+        k = tuple(int(round(c * n)) for c in p)
+        if k not in keys:
+            keys[k] = len(verts)
+            verts.append([c / n for c in k])
+        return keys[k]
+
+    for axis in range(3):
+        for side in (0, 1):
+            u, w = (axis + 1) % 3, (axis + 2) % 3
+            for i in range(n):
+                for j in range(n):
+                    q = []
+                    for di, dj in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                        p = [0.0, 0.0, 0.0]
+                        p[axis], p[u], p[w] = float(side), (i + di) / n, (j + dj) / n
+                        q.append(vid(p))
+                    faces += [(q[0], q[1], q[2]), (q[0], q[2], q[3])]
+    v = np.asarray(verts, dtype=np.float64)
+    f = np.asarray(faces)
+    p0, p1, p2 = v[f[:, 0]], v[f[:, 1]], v[f[:, 2]]
+    out = np.einsum("ij,ij->i", np.cross(p1 - p0, p2 - p0), (p0 + p1 + p2) / 3 - 0.5) < 0
+    f[out] = f[out][:, [0, 2, 1]]
+    return _pack(v, f)
+
+
 def normalize_unit_cube(v: np.ndarray) -> np.ndarray:
     """Uniform scaling into [0,1]^3: subtract the bbox min, divide by the max extent."""
     lo = v.min(axis=0)

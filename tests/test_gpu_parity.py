@@ -41,6 +41,11 @@ def meshes():
         "torus": g.bumpy_torus(24, 10, seed=5),
         "nested": g.nested_spheres(k=3, gap=0.01),
         "crease": g.crease_sphere(3, 5),
+        # flat sides: with pure-QEM weights many collapses make exactly
+        # collinear triangles, which only the exact degeneracy test decides
+        "cube4": g.grid_cube(4),
+        # two poles of valence 24: stars beyond the stored slots
+        "bipyr": g.bipyramid(24),
     }
 
 
@@ -94,7 +99,8 @@ def test_check_round(ctx, name, target, we, ws):
 
 @pytest.mark.parametrize("name,target,we,ws", [
     ("ico2", 32, 0.001, 0.005), ("ico2", 101, 0.001, 0.005), ("small5120", 512, 0.001, 0.005),
-    ("torus", 48, 0.001, 0.005), ("nested", 128, 0.001, 0.005), ("crease", 16, 0.0, 0.0)])
+    ("torus", 48, 0.001, 0.005), ("nested", 128, 0.001, 0.005), ("crease", 16, 0.0, 0.0),
+    ("cube4", 12, 0.0, 0.0), ("bipyr", 8, 0.001, 0.005)])
 def test_simplify_bitwise(ctx, name, target, we, ws):
     from paper_2509_05595_amd import native
     V, F = MESHES[name]

@@ -37,7 +37,11 @@ CASES = [("crease_pure_qem", lambda: g.crease_sphere(3, 5), 16, (0.0, 0.0)),
          ("noisy_k4", lambda: g.bumpy_icosphere_gauss(k=4, seed=4), 51, None),
          ("thin_shell", lambda: g.nested_spheres(k=3, gap=0.01), 51, None),
          ("crease_k5", lambda: g.crease_sphere(5, 5), 20, None),
-         ("csaszar", g.csaszar_torus, 2, None)]
+         ("csaszar", g.csaszar_torus, 2, None),
+         # flat sides under pure-QEM weights (exactly collinear triangles
+         # for the exact degeneracy test); poles of valence 24
+         ("grid_cube_pure_qem", lambda: g.grid_cube(4), 12, (0.0, 0.0)),
+         ("bipyramid_24", lambda: g.bipyramid(24), 8, None)]
 
 
 def run_both(ctx, V, F, target, w):
