@@ -31,8 +31,7 @@ import time
 
 HBM_PEAK_GBS = 8000.0
 # single-kernel phases eligible as "the dominant kernel" of the roofline
-SINGLE_KERNEL = ["quadrics", "cost_keys", "local_check", "face_boxes", "apply", "query", "pairs", "resolve",
-                 "undo", "commit"]
+SINGLE_KERNEL = ["quadrics", "cost_keys", "face_boxes", "apply", "query", "pairs", "resolve", "undo", "commit"]
 
 
 def host_cpu():
