@@ -971,6 +971,8 @@ __device__ __forceinline__ double wave_sum(double x) {
   for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
   return x;
 }
+constexpr int CG_PRE = 8;  // blocks of a Hessian row loaded ahead in k_cg_dir
+
 __device__ double sum_parts_wave(const double* __restrict__ part, int nb) {
   double s = 0.0;
   for (int i = threadIdx.x; i < nb; i += CG_T) s += part[i];
@@ -989,6 +991,29 @@ __global__ __launch_bounds__(CG_T) void k_cg_dir(const int* __restrict__ rowptr,
                                                  double* __restrict__ Ap, double* __restrict__ part,
                                                  const double* __restrict__ pz, const double* __restrict__ pr,
                                                  int nbv, int i, CgState* st) {
+  // the row's first CG_PRE blocks and their columns of z and p do not depend
+  // on beta: their loads go out together with those of the scalars
+  const int t = blockIdx.x * CG_T + threadIdx.x;
+  const bool live = t < 3 * nv;
+  const int v = t / 3, r = t - 3 * v;
+  int k0 = 0, k1 = 0;
+  if (live) {
+    k0 = rowptr[v];
+    k1 = rowptr[v + 1];
+  }
+  double bq[CG_PRE][3], zq[CG_PRE][3], pq[CG_PRE][3];
+#pragma unroll
+  for (int q = 0; q < CG_PRE; q++) {
+    const int k = k0 + q < k1 ? k0 + q : k0;  // a valid slot when the row has one
+    const int64_t j = live && k0 < k1 ? col[k] : 0;
+    const double* b = B + 9 * (int64_t)(live && k0 < k1 ? k : 0) + 3 * r;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      bq[q][c] = live && k0 < k1 ? b[c] : 0.0;
+      zq[q][c] = z[3 * j + c];
+      pq[q][c] = p[3 * j + c];
+    }
+  }
   if (st->done) return;
   double beta = 0.0;
   if (i > 0) {
@@ -1009,12 +1034,19 @@ __global__ __launch_bounds__(CG_T) void k_cg_dir(const int* __restrict__ rowptr,
       st->rr = rr;
     }
   }
-  const int t = blockIdx.x * CG_T + threadIdx.x;
   double dot = 0.0;
-  if (t < 3 * nv) {
-    const int v = t / 3, r = t - 3 * v;
+  if (live) {
     double s = 0.0;
-    for (int k = rowptr[v]; k < rowptr[v + 1]; k++) {
+#pragma unroll
+    for (int q = 0; q < CG_PRE; q++) {
+      if (k0 + q < k1) {
+        const double v0 = zq[q][0] + beta * pq[q][0];
+        const double v1 = zq[q][1] + beta * pq[q][1];
+        const double v2 = zq[q][2] + beta * pq[q][2];
+        s += bq[q][0] * v0 + bq[q][1] * v1 + bq[q][2] * v2;
+      }
+    }
+    for (int k = k0 + CG_PRE; k < k1; k++) {
       const int64_t j = col[k];
       const double* b = B + 9 * (int64_t)k + 3 * r;
       const double v0 = z[3 * j] + beta * p[3 * j];
