@@ -1072,18 +1072,31 @@ __global__ __launch_bounds__(CG_T) void k_cg_step(double* __restrict__ x, double
                                                   int nv, const double* __restrict__ part, int nbd,
                                                   double* __restrict__ pz, double* __restrict__ pr, int i,
                                                   const CgState* st) {
+  // the vertex's own entries do not depend on alpha: loaded with the scalars
+  const int v = blockIdx.x * CG_T + threadIdx.x;
+  const bool live = v < nv;
+  double xv[3], rv[3], pv[3], av[3], d[9];
+  const int w = live ? v : 0;
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    xv[c] = x[3 * w + c];
+    rv[c] = r[3 * w + c];
+    pv[c] = p[3 * w + c];
+    av[c] = Ap[3 * w + c];
+  }
+#pragma unroll
+  for (int c = 0; c < 9; c++) d[c] = Di[9 * (int64_t)w + c];
   if (st->done) return;
   const double a = st->rzs[i & 1] / sum_parts_wave(part, nbd);
   double srz = 0.0, srr = 0.0;
-  const int v = blockIdx.x * CG_T + threadIdx.x;
-  if (v < nv) {
-    double rv[3];
+  if (live) {
+#pragma unroll
     for (int c = 0; c < 3; c++) {
-      x[3 * v + c] += a * p[3 * v + c];
-      r[3 * v + c] -= a * Ap[3 * v + c];
-      rv[c] = r[3 * v + c];
+      x[3 * v + c] = xv[c] + a * pv[c];
+      rv[c] = rv[c] - a * av[c];
+      r[3 * v + c] = rv[c];
     }
-    const double* d = Di + 9 * (int64_t)v;
+#pragma unroll
     for (int c = 0; c < 3; c++) {
       const double zc = d[3 * c] * rv[0] + d[3 * c + 1] * rv[1] + d[3 * c + 2] * rv[2];
       z[3 * v + c] = zc;
