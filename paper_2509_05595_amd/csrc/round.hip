@@ -567,8 +567,6 @@ __device__ __forceinline__ bool link_holds(const MeshView& m, int h) {
   return fast ? link_ok_stars(m, a0, na, b0, nb) : link_ok(m, h);
 }
 
-// some generated triangle (corners after the collapse to vbar) degenerate or
-// with its normal turned by 90 degrees or more against the original
 // triangle o0 o1 o2 becomes p0 p1 p2: degenerate, or its normal turned by 90
 // degrees or more
 __device__ __forceinline__ bool turned(P3 o0, P3 o1, P3 o2, P3 p0, P3 p1, P3 p2) {
@@ -661,6 +659,8 @@ __device__ __forceinline__ int flipped_filter(const MeshView& m, const EdgeStars
   return bad ? 1 : und ? 2 : 0;
 }
 
+// some generated triangle (corners after the collapse to vbar) degenerate or
+// with its normal turned by 90 degrees or more against the original
 __device__ __forceinline__ bool flipped_after(const MeshView& m, const EdgeStars& E, P3 vbar) {
   const int s = E.s, r = E.r;
   bool bad = false, und = false;
@@ -1203,7 +1203,8 @@ __global__ __launch_bounds__(256) void k_apply(MeshView m, const int* __restrict
     // lane 0 the faces around s, lane 1 those around r (relabelled): the two
     // sets are disjoint, and neither reads a position the other writes
     const bool on_r = part == 1;
-    star_chunks(m, on_r ? r : s, on_r ? nr : ns, f1, f2, h, [&](const int* g, const bool* use) { side(g, use, on_r); });
+    star_chunks(m, on_r ? r : s, on_r ? nr : ns, f1, f2, h,
+                [&](const int* g, const bool* use) { side(g, use, on_r); });
     if (on_r) return;
     owner[f1] = c;
     owner[f2] = c;
@@ -1751,8 +1752,8 @@ void launch_reselect(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* k
 void launch_local_check(hipStream_t s, MeshView m, const double* Q, double w_e, double w_s, const int* cand,
                         const int* ncand, int cand_bound, const uint64_t* key, uint8_t* reason, double* vbar,
                         uint64_t* ckey, int* err, int* hist) {
-  hipLaunchKernelGGL(k_local_check, dim3(nblk8((int64_t)cand_bound * LC)), dim3(256), 0, s, m, Q, w_e, w_s, cand, ncand, key, reason,
-                     vbar, ckey, err, hist);
+  hipLaunchKernelGGL(k_local_check, dim3(nblk8((int64_t)cand_bound * LC)), dim3(256), 0, s, m, Q, w_e, w_s, cand,
+                     ncand, key, reason, vbar, ckey, err, hist);
   hipLaunchKernelGGL(k_local_late, dim3(nblk8(cand_bound)), dim3(256), 0, s, m, Q, w_e, w_s, cand, ncand, reason, vbar,
                      err, hist);
   PAMO_HIP(hipGetLastError());
@@ -1777,8 +1778,8 @@ void launch_face_boxes(hipStream_t s, MeshView m, float* box) {
 
 void launch_apply(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const uint8_t* reason,
                   const double* vbar, double* oldpos, int* owner, uint8_t* falive, float* box) {
-  hipLaunchKernelGGL(k_apply, dim3(nblk8((int64_t)cand_bound * AP)), dim3(256), 0, s, m, cand, ncand, reason, vbar, oldpos, owner,
-                     falive, box);
+  hipLaunchKernelGGL(k_apply, dim3(nblk8((int64_t)cand_bound * AP)), dim3(256), 0, s, m, cand, ncand, reason, vbar,
+                     oldpos, owner, falive, box);
   PAMO_HIP(hipGetLastError());
 }
 
