@@ -756,7 +756,7 @@ void launch_query(hipStream_t s, const Bvh& bvh, QueryMode mode, const int* qlis
 
 void launch_pairs(hipStream_t s, QueryMode mode, const QueryArgs& a, int64_t pairs_est) {
   int64_t b = (pairs_est + 255) / 256;
-  dim3 g((unsigned)(b < 64 ? 64 : b > 2048 ? 2048 : b)), t(256);
+  dim3 g((unsigned)(b < 64 ? 64 : b > 8192 ? 8192 : b)), t(256);
   if (mode == QUERY_CHANGED)
     hipLaunchKernelGGL(k_pairs<QUERY_CHANGED>, g, t, 0, s, a);
   else if (mode == QUERY_RESTORED)
