@@ -1784,7 +1784,7 @@ struct Projection {
     a.fcap = fcap;
     if (nf >= 2) hipLaunchKernelGGL(k_walk, dim3(nblk(nf, 64)), dim3(64), 0, s, a, b.sorted);  // one-wave blocks
     else hipLaunchKernelGGL(k_walk_small, dim3(1), dim3(1), 0, s, a);
-    hipLaunchKernelGGL(k_pair_slots, dim3(1024), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_pair_slots, dim3(4096), dim3(256), 0, s, a);  // about one slot per thread
     check_launch();
   }
 
