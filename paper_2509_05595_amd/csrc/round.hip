@@ -1778,8 +1778,9 @@ void launch_face_boxes(hipStream_t s, MeshView m, float* box) {
 
 void launch_apply(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, const uint8_t* reason,
                   const double* vbar, double* oldpos, int* owner, uint8_t* falive, float* box) {
-  hipLaunchKernelGGL(k_apply, dim3(nblk8((int64_t)cand_bound * AP)), dim3(256), 0, s, m, cand, ncand, reason, vbar,
-                     oldpos, owner, falive, box);
+  // one-wave blocks: the candidates' serial gathers spread over more CUs
+  hipLaunchKernelGGL(k_apply, dim3(nblk8((int64_t)cand_bound * AP, 64)), dim3(64), 0, s, m, cand, ncand, reason,
+                     vbar, oldpos, owner, falive, box);
   PAMO_HIP(hipGetLastError());
 }
 
@@ -1802,7 +1803,8 @@ void launch_face_list(Workspace& ws, hipStream_t s, int nf, const int* owner, co
 
 void launch_commit(hipStream_t s, MeshView m, const int* cand, const int* ncand, int cand_bound, uint8_t* reason,
                    const int* undone, uint8_t* valive, GateIn gin) {
-  hipLaunchKernelGGL(k_commit, dim3(nblk8(cand_bound)), dim3(256), 0, s, m, cand, ncand, reason, undone, valive, gin);
+  hipLaunchKernelGGL(k_commit, dim3(nblk8(cand_bound, 64)), dim3(64), 0, s, m, cand, ncand, reason, undone, valive,
+                     gin);  // one-wave blocks, as k_apply
   PAMO_HIP(hipGetLastError());
 }
 
