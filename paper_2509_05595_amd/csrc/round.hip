@@ -598,28 +598,23 @@ __device__ __forceinline__ int turned_filter(P3 o0, P3 o1, P3 o2, P3 p0, P3 p1, 
   return 2;
 }
 
-// faces of a chunk of four of the stored star around a vertex at pc (corner
+// the four faces of a chunk of the stored star around a vertex at pc (corner
 // g % 3 of each is that vertex and moves to vbar; no other corner is s or r,
-// and the other two are loaded): all four when K = 4, else faces 2 hi and
-// 2 hi + 1.  Every load is issued before any test.  `bad` is set when a face
-// is turned; with EXACT the degeneracy test is exact, else its filters alone
-// decide and `und` is set for a face they leave undecided.
-template <int K, bool EXACT>
-__device__ __forceinline__ void flip_faces(const MeshView& m, const int* g, const bool* use, bool hi, P3 pc, P3 vbar,
+// and the other two are loaded).  Every load is issued before any test.
+// `bad` is set when a face is turned; with EXACT the degeneracy test is exact,
+// else its filters alone decide and `und` is set for a face they leave
+// undecided.
+template <bool EXACT>
+__device__ __forceinline__ void flip_faces(const MeshView& m, const int* g, const bool* use, P3 pc, P3 vbar,
                                            bool& bad, bool& und) {
+  constexpr int K = 4;
   P3 o[K][3];
   int ci[K];
   bool u[K];
 #pragma unroll
   for (int k = 0; k < K; k++) {
-    int gk;
-    if constexpr (K == 4) {
-      gk = g[k];
-      u[k] = use[k];
-    } else {
-      gk = hi ? g[2 + k] : g[k];
-      u[k] = hi ? use[2 + k] : use[k];
-    }
+    const int gk = g[k];
+    u[k] = use[k];
     const int f = gk / 3;
     ci[k] = gk - 3 * f;
     int c[3];
@@ -653,9 +648,9 @@ __device__ __forceinline__ int flipped_filter(const MeshView& m, const EdgeStars
   bool bad = false, und = false;
   const P3 ps = ld3(m.V, E.s), pr = ld3(m.V, E.r);
   star_chunks(m, E.s, E.ns, E.f1, E.f2, E.hs,
-              [&](const int* g, const bool* use) { flip_faces<4, false>(m, g, use, false, ps, vbar, bad, und); });
+              [&](const int* g, const bool* use) { flip_faces<false>(m, g, use, ps, vbar, bad, und); });
   star_chunks(m, E.r, E.nr, E.f1, E.f2, E.hs,
-              [&](const int* g, const bool* use) { flip_faces<4, false>(m, g, use, false, pr, vbar, bad, und); });
+              [&](const int* g, const bool* use) { flip_faces<false>(m, g, use, pr, vbar, bad, und); });
   return bad ? 1 : und ? 2 : 0;
 }
 
@@ -667,9 +662,9 @@ __device__ __forceinline__ bool flipped_after(const MeshView& m, const EdgeStars
   if (E.fast) {
     const P3 ps = ld3(m.V, s), pr = ld3(m.V, r);
     star_chunks(m, s, E.ns, E.f1, E.f2, E.hs,
-                [&](const int* g, const bool* use) { flip_faces<4, true>(m, g, use, false, ps, vbar, bad, und); });
+                [&](const int* g, const bool* use) { flip_faces<true>(m, g, use, ps, vbar, bad, und); });
     star_chunks(m, r, E.nr, E.f1, E.f2, E.hs,
-                [&](const int* g, const bool* use) { flip_faces<4, true>(m, g, use, false, pr, vbar, bad, und); });
+                [&](const int* g, const bool* use) { flip_faces<true>(m, g, use, pr, vbar, bad, und); });
   } else {
     auto chk = [&](int f) {
       if (bad) return;
@@ -707,18 +702,20 @@ __device__ __forceinline__ uint8_t local_reason(const MeshView& m, const double*
   return flipped_after(m, E, vb) ? 2 : 0;
 }
 
-// The local checks of one candidate split over LC consecutive lanes (stored
-// stars only).  Every lane loads the edge, its stars and the placement (the
-// same addresses, merged by the memory pipeline); lane `part` then compares
-// one LC-th of b's neighbours against a's and tests two of every four faces
-// of one star (parts 0 and 1 the star of s, 2 and 3 that of r).  The group
-// sums the common neighbours and ORs the flip results: the same decisions as
-// local_reason, in a quarter of its dependent loads and arithmetic.  The
+// The local checks of one candidate split over LC = 2 consecutive lanes
+// (stored stars only).  Both lanes load the edge, its stars and the placement
+// (the same addresses, merged by the memory pipeline); lane `part` then
+// compares half of b's neighbours against a's and tests the faces of one star
+// (lane 0 the star of s, lane 1 that of r).  The pair sums the common
+// neighbours and ORs the flip results: the same decisions as local_reason,
+// with its two stars' chains of loads side by side.  (Four lanes, two faces
+// of every chunk each, were no faster on single meshes and slower on
+// batches.)  The
 // degeneracy test runs on its filters only; a candidate that needs the exact
 // test (or whose stars are not stored) gets REASON_LATE and is decided by
 // local_reason in a second kernel, which keeps the exact arithmetic's
 // registers and scratch out of this one.
-constexpr int LC = 4;
+constexpr int LC = 2;
 constexpr uint8_t REASON_LATE = 5;
 
 // common neighbours of a and b over the slots j of b's star with j % LC == part
@@ -744,17 +741,16 @@ __device__ __forceinline__ int link_common_part(const MeshView& m, int a, int na
   return common;
 }
 
-// the flip test over faces 2 half, 2 half + 1 of every chunk of four of the
-// star of s (part < 2) or r, half = part & 1
-// (0 none turned, 1 some face turned, 2 none certainly turned, some undecided)
+// the flip test over the faces of the star of s (part 0) or r (part 1), on
+// the filters (0 none turned, 1 some face turned, 2 none certainly turned,
+// some undecided)
 __device__ __forceinline__ int flipped_part(const MeshView& m, const EdgeStars& E, P3 vbar, int part) {
-  const bool on_s = part < LC / 2;
-  const bool half = part & 1;
+  const bool on_s = part == 0;
   const int v = on_s ? E.s : E.r;
   const P3 pc = ld3(m.V, v);
   bool bad = false, und = false;
   star_chunks(m, v, on_s ? E.ns : E.nr, E.f1, E.f2, E.hs,
-              [&](const int* g, const bool* use) { flip_faces<2, false>(m, g, use, half, pc, vbar, bad, und); });
+              [&](const int* g, const bool* use) { flip_faces<false>(m, g, use, pc, vbar, bad, und); });
   return bad ? 1 : und ? 2 : 0;
 }
 
