@@ -933,15 +933,44 @@ __device__ __forceinline__ uint8_t select_edge(const MeshView& m, const uint64_t
 // edge's lower half-edge in its low 32 bits: so each vertex tests the one edge
 // its minimum names (from the edge's origin end only, once per edge), instead
 // of every half-edge testing itself.  sel must be zero on entry.
+constexpr int SELECT_PAIR_NV = 1 << 18;  // two lanes per vertex up to this many vertices
+
+// SL = 2: two lanes per vertex; with stored stars, lane 0 gathers the
+// neighbour minima around a, lane 1 those around b, and the pair ANDs the
+// answers (shorter chains on small meshes; on large ones the second lane's
+// loads cost more than they hide, and SL = 1 runs both sides on one lane).
+template <int SL>
 __global__ __launch_bounds__(256) void k_select(MeshView m, const uint64_t* __restrict__ key,
                                                 const uint64_t* __restrict__ vmin, uint8_t* __restrict__ sel) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= m.nv) return;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int v = (int)(t / SL), part = (int)(t % SL);
+  if (v >= m.nv) return;  // every lane of the vertex
   const uint64_t k = vmin[v];
   if (k == PAMO_KEY_MAX) return;
   const int h = (int)(uint32_t)k;
   if (m.F[h] != v) return;  // the other end tests it
-  if (select_edge(m, key, vmin, h)) sel[h] = 1;
+  if (key[h] != k || !(h < m.twin[h])) return;
+  const int a = v, b = m.F[he_next(h)];
+  if (vmin[b] != k) return;
+  int na = 0, nb = 0;
+  if (SL == 2 && stars_stored(m, a, b, na, nb)) {
+    const int u = part ? b : a, n = part ? nb : na;
+    int g[VSTAR];
+    star_all(m, u, n, g);
+    int w[VSTAR];
+#pragma unroll
+    for (int i = 0; i < VSTAR; i++) w[i] = m.F[he_next(g[i])];
+    uint64_t mw[VSTAR];
+#pragma unroll
+    for (int i = 0; i < VSTAR; i++) mw[i] = vmin[w[i]];
+    int low = 1;
+#pragma unroll
+    for (int i = 0; i < VSTAR; i++) low = low && !(mw[i] < k);
+    low &= __shfl_xor(low, 1);
+    if (part == 0 && low) sel[h] = 1;
+  } else if (part == 0 && select_edge(m, key, vmin, h)) {
+    sel[h] = 1;
+  }
 }
 
 // Re-selection after candidates were set aside (both half-edges of each got
@@ -1728,7 +1757,11 @@ void launch_select(Workspace& ws, hipStream_t s, MeshView m, const uint64_t* key
   uint8_t* sel = ws.get<uint8_t>("sel", nh);
   hipLaunchKernelGGL(k_vertex_min, dim3(nblk(m.nv)), dim3(256), 0, s, m, key, vmin);
   if (!sel_clear) fill_u8(s, sel, nh, 0);
-  hipLaunchKernelGGL(k_select, dim3(nblk(m.nv)), dim3(256), 0, s, m, key, (const uint64_t*)vmin, sel);
+  if (m.nv <= SELECT_PAIR_NV)
+    hipLaunchKernelGGL(k_select<2>, dim3(nblk(2 * (int64_t)m.nv)), dim3(256), 0, s, m, key, (const uint64_t*)vmin,
+                       sel);
+  else
+    hipLaunchKernelGGL(k_select<1>, dim3(nblk(m.nv)), dim3(256), 0, s, m, key, (const uint64_t*)vmin, sel);
   compact_flags(ws, s, sel, nh, cand, ncand);
   PAMO_HIP(hipGetLastError());
 }
